@@ -1,0 +1,341 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names what it pins.  None of them re-calls the oracle's own
+formula as the expected value: expected values come from closed forms
+(exponential integrals), 1-D quadrature of the radially symmetric problem,
+the FFT (a library convolution), Monte Carlo, hand-expanded loops, symmetry,
+scaling laws, or the constants the paper prints.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import exp1
+
+import gen
+from oracle import (absorbed_fraction, cube_self_coefficient, direct_sum_numpy, g_absorption,
+                    gas_constants, kernel_K, photoionization, rel_l2, source_mask, target_mask)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GC = gas_constants(gen.GAS_760)
+
+
+def _cube_grid(n, h):
+    half = n // 2
+    c = (np.arange(n) - half) * h
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def _A_closed(R, gc):
+    # absorbed fraction within R from the exponential integral: 1 - (E1(aR) - E1(bR)) / L
+    R = np.asarray(R, dtype=np.float64)
+    return 1.0 - (exp1(gc.a * R) - exp1(gc.b * R)) / gc.L
+
+
+# ---------------------------------------------------------------- constants (golden)
+
+def test_gas_constants_match_printed_parameters():
+    """Sec. 2.1 and Sec. 4.1 constants -> a, b, L, P (golden fixture with citations)."""
+    vals = {}
+    with open(os.path.join(HERE, "golden", "gas_parameters.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                k, v = line.split()[:2]
+                vals[k] = float(v)
+    gas = gen.GAS_760
+    assert gas["chi_min"] == vals["chi_min"] and gas["chi_max"] == vals["chi_max"]
+    assert gas["pq_torr"] == vals["pq_torr"] and gas["p_torr"] == vals["p_torr"]
+    assert gas["o2_fraction"] == vals["pO2_over_p"]
+    assert gas["xi_omega_over_alpha"] == pytest.approx(vals["xi"] * vals["omega_over_alpha"], rel=1e-15)
+    gc = gas_constants(gas)
+    pO2 = vals["pO2_over_p"] * vals["p_torr"]
+    assert gc.a == pytest.approx(vals["chi_min"] * pO2, rel=1e-15)
+    assert gc.b == pytest.approx(vals["chi_max"] * pO2, rel=1e-15)
+    assert gc.L == pytest.approx(math.log(vals["chi_max"] / vals["chi_min"]), rel=1e-15)
+    P = vals["pq_torr"] / (vals["p_torr"] + vals["pq_torr"]) * vals["xi"] * vals["omega_over_alpha"]
+    assert gc.P == pytest.approx(P, rel=1e-15)
+
+
+# ---------------------------------------------------------------- P1: normalisation
+
+@pytest.mark.parametrize("gas", [gen.GAS_760, gen.GAS_40])
+def test_p1_g_normalised(gas):
+    """Frullani: integral_0^inf g = 1, hence integral over R^3 of K = 1 (uniform medium gives S = P I)."""
+    gc = gas_constants(gas)
+    tot, _ = integrate.quad(lambda r: g_absorption(r, gc), 0, np.inf, limit=400, epsabs=0, epsrel=1e-12)
+    assert tot == pytest.approx(1.0, abs=1e-10)
+    tot3, _ = integrate.quad(lambda r: 4 * np.pi * r * r * kernel_K(r, gc), 0, np.inf, limit=400,
+                             epsabs=0, epsrel=1e-12)
+    assert tot3 == pytest.approx(1.0, abs=1e-10)
+
+
+@pytest.mark.parametrize("gas", [gen.GAS_760, gen.GAS_40])
+def test_p1_absorbed_fraction_closed_form(gas):
+    """A(R) by graded Gauss-Legendre equals the exponential-integral closed form."""
+    gc = gas_constants(gas)
+    R = np.array([1e-5, 1e-3, 0.01, 0.05, 0.1, 0.5, 3.0])
+    assert np.allclose(absorbed_fraction(R, gc), _A_closed(R, gc), rtol=1e-12, atol=1e-14)
+
+
+def test_kernel_forms_agree_and_g_limit():
+    """expm1 form of K equals the printed difference form of eq. (3); g(0+) = (b-a)/L."""
+    r = np.logspace(-4, 0.5, 200)
+    K_printed = g_absorption(r, GC) / (4 * np.pi * r ** 2)
+    assert np.allclose(kernel_K(r, GC), K_printed, rtol=1e-12)
+    assert g_absorption(1e-9, GC) == pytest.approx((GC.b - GC.a) / GC.L, rel=1e-6)
+
+
+# ---------------------------------------------------------------- c_self
+
+def test_cself_values_and_ball_bounds():
+    """Own-cell coefficient lies between the inscribed and circumscribed ball integrals, -> 1 for huge cells."""
+    for h in (0.2 / 24, 1.0 / 128, 2.0 / 256, 0.05):
+        c = cube_self_coefficient(h, GC)
+        assert _A_closed(h / 2, GC) < c < _A_closed(h * math.sqrt(3) / 2, GC)
+    assert cube_self_coefficient(10.0, GC) == pytest.approx(1.0, abs=1e-12)
+    # the C1 grid value (h = 1/120 cm) to the digits computed independently by Monte Carlo below
+    assert cube_self_coefficient(0.2 / 24, GC) == pytest.approx(0.26608, abs=1e-4)
+
+
+def test_cself_monte_carlo_over_directions():
+    """c_self = mean over directions of A(distance to the cube face), A from E1 (independent path)."""
+    rng = np.random.default_rng(7)
+    h = 0.2 / 24
+    u = rng.normal(size=(1_000_000, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    R = (h / 2) / np.abs(u).max(axis=1)
+    v = _A_closed(R, GC)
+    se = v.std() / math.sqrt(v.size)
+    assert abs(v.mean() - cube_self_coefficient(h, GC)) < 5 * se
+
+
+def test_cself_consistent_with_offdiagonal_quadrature():
+    """Uniform I on an odd n^3 grid of side D: centre value / (P I) -> c_self(D) as h -> 0.
+
+    The whole cube integral of K equals c_self of the big cube; the discrete sum (midpoint
+    off-diagonal + exact own cell) must converge to it.  Richardson over three grids.
+    """
+    D = 0.1
+    vals = []
+    for n in (21, 41, 81):
+        h = D / n
+        xyz = _cube_grid(n, h)
+        ctr = np.flatnonzero((np.abs(xyz) < 1e-12).all(axis=1))
+        r = photoionization(xyz, np.ones(len(xyz)), gen.GAS_760, h=h, targets=ctr)
+        vals.append(float(r.S_t[0]) / GC.P)
+    ref = cube_self_coefficient(D, GC)
+    errs = [abs(v / ref - 1) for v in vals]
+    assert errs[0] > errs[1] > errs[2]
+    # S(h) = S0 + c1 h + c2 h^2 through the three grids (h, h/2, h/4 ratios are 21:41:81 ~ 1:2:4)
+    hs = np.array([D / 21, D / 41, D / 81])
+    M = np.stack([np.ones(3), hs, hs ** 2], axis=1)
+    S0 = np.linalg.solve(M, np.array(vals))[0]
+    assert S0 == pytest.approx(ref, rel=2e-3)
+
+
+# ---------------------------------------------------------------- P2: uniform ball
+
+def test_p2_uniform_ball_centre():
+    """Centre of a uniform ball of radius R: S -> P I A(R) (A in closed form), first order in h."""
+    R = 0.05
+    vals, hs = [], []
+    for m in (16, 32, 48):
+        h = R / m
+        xyz = _cube_grid(2 * m + 1, h)
+        I = (np.linalg.norm(xyz, axis=1) <= R + 1e-12).astype(np.float64)
+        ctr = np.flatnonzero((np.abs(xyz) < 1e-12).all(axis=1))
+        r = photoionization(xyz, I, gen.GAS_760, h=h, targets=ctr)
+        vals.append(float(r.S_t[0]) / GC.P)
+        hs.append(h)
+    ref = float(_A_closed(R, GC))
+    errs = [abs(v / ref - 1) for v in vals]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1.2e-2
+    hs = np.array(hs)
+    M = np.stack([np.ones(3), hs, hs ** 2], axis=1)
+    S0 = np.linalg.solve(M, np.array(vals))[0]
+    assert S0 == pytest.approx(ref, rel=3e-3)
+
+
+# ---------------------------------------------------------------- P3: single point source
+
+def test_p3_single_point_source_is_the_kernel():
+    """One source with w I = 1: S_i = P K(r_i) off the source, P c_self I at it (spec check)."""
+    h = 0.01
+    xyz = _cube_grid(7, h) + 0.3
+    n = len(xyz)
+    j = 100
+    I = np.zeros(n)
+    I[j] = 1.0 / h ** 3
+    smask = np.zeros(n, dtype=bool)
+    smask[j] = True
+    r = photoionization(xyz, I, gen.GAS_760, h=h, smask=smask)
+    S = r.full(n)
+    d = np.linalg.norm(xyz - xyz[j], axis=1)
+    off = np.arange(n) != j
+    # eq. (3) exactly as printed, over 4 pi r^2
+    expect = GC.P * (np.exp(-GC.a * d[off]) - np.exp(-GC.b * d[off])) / (d[off] * GC.L) / (4 * np.pi * d[off] ** 2)
+    assert np.allclose(S[off], expect, rtol=1e-12)
+    assert S[j] == pytest.approx(GC.P * r.c_self * I[j], rel=1e-14)
+
+
+# ---------------------------------------------------------------- P4: Gaussian, 1-D radial quadrature
+
+def _radial_reference(R, sig, gc):
+    I = lambda r: np.exp(-r * r / sig / sig)
+    if R == 0:
+        return integrate.quad(lambda r: I(r) * g_absorption(max(r, 1e-300), gc) if r > 0
+                              else (gc.b - gc.a) / gc.L, 0, 8 * sig, limit=200, epsabs=0, epsrel=1e-13)[0]
+
+    def H(s):
+        # antiderivative of g(s)/s
+        return (-np.exp(-gc.a * s) / s + gc.a * exp1(gc.a * s) + np.exp(-gc.b * s) / s - gc.b * exp1(gc.b * s)) / gc.L
+    f = lambda r: I(r) * r * (H(R + r) - H(abs(R - r))) if r > 0 else 0.0
+    return integrate.quad(f, 0, 8 * sig, points=[R], limit=400, epsabs=0, epsrel=1e-12)[0] / (2 * R)
+
+
+def test_p4_radial_reference_values():
+    """The 1-D radial reduction at sigma = 0.015 cm, 760 Torr (values independent of the 3-D oracle)."""
+    sig = 0.015
+    got = [_radial_reference(R, sig, GC) for R in (0.0, 0.005, 0.015, 0.03)]
+    assert np.allclose(got, [0.4398535, 0.4007723, 0.1943183, 0.0250586], rtol=0, atol=2e-7)
+
+
+@pytest.mark.parametrize("R_over_sigma", [0, 1])
+def test_p4_gaussian_converges_to_radial_quadrature(R_over_sigma):
+    """3-D discrete sum of a Gaussian source -> 1-D radial value (first-order in h, Richardson)."""
+    sig = 0.015
+    vals, hs = [], []
+    for m in (4, 8, 16):
+        h = sig / m
+        half = int(math.ceil(6 * sig / h))
+        xyz = _cube_grid(2 * half + 1, h)
+        I = np.exp(-(xyz ** 2).sum(axis=1) / sig ** 2)
+        tgt_pt = np.array([R_over_sigma * sig, 0.0, 0.0])
+        tgt = np.flatnonzero((np.abs(xyz - tgt_pt) < 1e-12).all(axis=1))
+        r = photoionization(xyz, I, gen.GAS_760, h=h, targets=tgt)
+        vals.append(float(r.S_t[0]) / GC.P)
+        hs.append(h)
+    ref = _radial_reference(R_over_sigma * sig, sig, GC)
+    errs = [abs(v - ref) / ref for v in vals]
+    assert errs[0] > errs[1] > errs[2]
+    hs = np.array(hs)
+    M = np.stack([np.ones(3), hs, hs ** 2], axis=1)
+    S0 = np.linalg.solve(M, np.array(vals))[0]
+    assert S0 == pytest.approx(ref, rel=1e-3)
+
+
+# ---------------------------------------------------------------- P5: reciprocity
+
+def test_p5_reciprocity():
+    """With uniform weights the discrete operator is symmetric: <u, A v> = <A u, v>."""
+    h = 0.004
+    xyz = _cube_grid(8, h) + 0.1
+    rng = np.random.default_rng(3)
+    u, v = rng.uniform(size=len(xyz)), rng.uniform(size=len(xyz))
+    Au = photoionization(xyz, u, gen.GAS_760, h=h).full(len(xyz))
+    Av = photoionization(xyz, v, gen.GAS_760, h=h).full(len(xyz))
+    lhs, rhs = float(u @ Av), float(Au @ v)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+# ---------------------------------------------------------------- P6: brute force
+
+def _brute(xyz, I, h, gc, c_self):
+    out = []
+    for i in range(len(xyz)):
+        s = 0.0
+        for j in range(len(xyz)):
+            if i == j:
+                continue
+            r = math.dist(xyz[i], xyz[j])
+            s += h ** 3 * I[j] * (math.exp(-gc.a * r) - math.exp(-gc.b * r)) / (r * gc.L) / (4 * math.pi * r * r)
+        out.append(gc.P * (s + c_self * I[i]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_p6_brute_force_tiny_grids(n):
+    h = 0.01
+    xyz = _cube_grid(n, h) + 0.05
+    I = np.random.default_rng(n).uniform(0.5, 2.0, size=len(xyz))
+    r = photoionization(xyz, I, gen.GAS_760, h=h)
+    rn = photoionization(xyz, I, gen.GAS_760, h=h, use_numpy=True)
+    expect = _brute(xyz, I, h, GC, r.c_self)
+    assert np.allclose(r.full(len(xyz)), expect, rtol=1e-13)
+    assert np.allclose(rn.full(len(xyz)), expect, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- P7: FFT convolution
+
+def test_p7_fft_convolution_equals_direct_sum():
+    """On a uniform grid with every point a source and a target the sum is a discrete convolution."""
+    n, h = 14, 0.2 / 24
+    xyz, _ = gen.grid_points(n, 0.0, n * h)
+    I = np.random.default_rng(11).uniform(0, 1, size=n ** 3) ** 4 * 1e20
+    r = photoionization(xyz, I, gen.GAS_760, h=h)
+    # kernel table on the (2n)^3 periodic lattice: h^3 K(|d| h) off the origin, c_self at it
+    m = 2 * n
+    k = np.fft.fftfreq(m, d=1.0 / m)
+    DX, DY, DZ = np.meshgrid(k, k, k, indexing="ij")
+    dist = np.sqrt(DX ** 2 + DY ** 2 + DZ ** 2) * h
+    T = np.zeros_like(dist)
+    nz = dist > 0
+    T[nz] = h ** 3 * g_absorption(dist[nz], GC) / (4 * np.pi * dist[nz] ** 2)
+    T[~nz] = r.c_self
+    Ipad = np.zeros((m, m, m))
+    Ipad[:n, :n, :n] = I.reshape(n, n, n)
+    conv = np.fft.irfftn(np.fft.rfftn(T, axes=(0, 1, 2)) * np.fft.rfftn(Ipad, axes=(0, 1, 2)), s=(m, m, m), axes=(0, 1, 2))[:n, :n, :n].ravel()
+    assert rel_l2(r.full(n ** 3), GC.P * conv) < 1e-12
+
+
+# ---------------------------------------------------------------- P8: pressure similarity
+
+def test_p8_pressure_similarity():
+    """K(r; pO2) = pO2^3 K_1(pO2 r): x -> s x, w -> s^3 w, p -> p/s leaves the sum (S/P) unchanged."""
+    h = 0.005
+    xyz = _cube_grid(6, h) + 0.2
+    I = np.random.default_rng(5).uniform(0.1, 1.0, size=len(xyz))
+    s = 19.0
+    r1 = photoionization(xyz, I, gen.GAS_760, h=h)
+    gas2 = dict(gen.GAS_760, p_torr=760.0 / s)
+    r2 = photoionization(xyz * s, I, gas2, h=h * s)
+    gc2 = gas_constants(gas2)
+    assert r2.c_self == pytest.approx(r1.c_self, rel=1e-12)
+    assert np.allclose(r2.full(len(xyz)) / gc2.P, r1.full(len(xyz)) / GC.P, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- P9: linearity / positivity
+
+def test_p9_linearity_positivity_monotonicity():
+    h = 0.004
+    xyz = _cube_grid(7, h)
+    rng = np.random.default_rng(9)
+    I1, I2 = rng.uniform(size=len(xyz)), rng.uniform(size=len(xyz))
+    sm = np.ones(len(xyz), dtype=bool)
+    S1 = photoionization(xyz, I1, gen.GAS_760, h=h, smask=sm).full(len(xyz))
+    S2 = photoionization(xyz, I2, gen.GAS_760, h=h, smask=sm).full(len(xyz))
+    S12 = photoionization(xyz, 2.5 * I1 + 0.75 * I2, gen.GAS_760, h=h, smask=sm).full(len(xyz))
+    assert np.allclose(S12, 2.5 * S1 + 0.75 * S2, rtol=1e-13)
+    assert (S1 > 0).all()
+    I3 = I1.copy()
+    I3[50] += 1.0
+    S3 = photoionization(xyz, I3, gen.GAS_760, h=h, smask=sm).full(len(xyz))
+    assert (S3 > S1).all()
+
+
+# ---------------------------------------------------------------- selection
+
+def test_selection_rules():
+    """Eq. (18)/(22) (>=, relative to the global maximum) and the field rule of Sec. 5."""
+    I = np.array([1.0, 1e-4, 0.99e-4, 0.5, 0.0])
+    assert source_mask(I, 1e-4).tolist() == [True, True, False, True, False]
+    assert source_mask(I, 0.0).all()
+    E = np.array([5e6, 5.05e6, 5.0499e6, 1.5e7, 0.0])
+    # E_applied = 5e6, eps = 0.5 %: threshold = 5e6 + 0.005*(1.5e7 - 5e6) = 5.05e6
+    assert target_mask(E, -1.0, 5e6, 0.005).tolist() == [False, True, False, True, False]
+    assert target_mask(E, 3e6).tolist() == [True, True, True, True, False]
+    assert target_mask(None) is None
