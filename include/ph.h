@@ -1,0 +1,226 @@
+/*
+ * ph.h -- C ABI of the MI355X adaptive-FMM photoionization library (libph.so).
+ *
+ * The library evaluates the discrete Zheleznyak photoionization integral of
+ * Lin & Zhuang, "Adaptive Strategies to Fast Multipole Method in
+ * Photoionization Calculations" (arXiv 2112.10059):
+ *
+ *   S_ph(x_i) = P * sum_{j in S, j != i} w_j I_j K(|x_i - x_j|) + P [i in S] c_self I_i,   i in T
+ *
+ * with K(r) = g(r) / (4 pi r^2) and g of Sec. 2.1 eq. (3),
+ * P = p_q/(p+p_q) * xi*omega/alpha (eq. (2)), the quadrature form of
+ * Sec. 2.4 eq. (15), and the adaptive source set S (Sec. 3 eq. (18),
+ * Sec. 4.3 eq. (22)) and target set T (Sec. 3 strategy 2; field rule of
+ * Sec. 5).  The far field is approximated by a fast multipole method with
+ * artificial sources fitted at check points (Sec. 2.4 eq. (17) and the
+ * figure of artificial/check points), the near field of Sec. 2.4 eq. (16)
+ * is summed exactly.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns ph_status; nothing throws across the ABI.
+ *    A failed call leaves outputs unspecified and sets a thread-local detail
+ *    string readable with ph_last_error().
+ *  - "device" pointers are HIP device allocations on the GPU that was current
+ *    when the plan was created; "host" pointers are ordinary CPU memory.
+ *  - The caller owns every buffer it passes in; the plan owns its internal
+ *    device buffers (sorted points, tree, operators) and frees them in
+ *    ph_plan_destroy.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work of a call is enqueued on it; the call returns without
+ *    waiting unless stated otherwise.
+ *  - A plan is not safe for concurrent ph_evaluate calls (it owns one
+ *    per-call workspace).
+ */
+#ifndef PH_H_
+#define PH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ph_plan ph_plan; /* opaque */
+
+typedef enum {
+    PH_OK = 0,
+    PH_EINVAL = 1,        /* an argument failed host-side validation (no device work was done) */
+    PH_ENOMEM = 2,        /* device or host allocation failed, or the workspace cap was hit   */
+    PH_EDEVICE = 3,       /* a HIP runtime call failed                                        */
+    PH_ENUMERIC = 4,      /* a non-finite or negative source value was seen on the device     */
+    PH_EUNSUPPORTED = 5,  /* a valid request this build does not implement                    */
+    PH_EFALLBACK = 6      /* informational: the learned selector fell back to the threshold rule;
+                             the output is valid                                              */
+} ph_status;
+
+typedef enum {
+    PH_FP64 = 0,            /* every step in FP64                                              */
+    PH_FP32 = 1,            /* FP32 kernels, Kahan-compensated near field, FP64 final combine  */
+    PH_FP32_BF16SPLIT = 2   /* as PH_FP32 with M2L on split BF16 (hi/lo) operands              */
+} ph_precision;
+
+typedef enum {
+    PH_SEL_THRESHOLD = 0,   /* the source rule I >= src_rel * max I (Sec. 3 eq. (18))          */
+    PH_SEL_LEARNED = 1      /* learned per-leaf keep/drop on top of the threshold rule          */
+} ph_selector;
+
+typedef enum {
+    PH_METHOD_FMM = 0,      /* adaptive fast multipole evaluation                               */
+    PH_METHOD_DIRECT = 1    /* all-pairs direct sum over the selected sets (O(|S| |T|))         */
+} ph_method;
+
+/* Quadrature points (Sec. 2.4 eq. (15)).  Host pointers, read only during ph_plan_create. */
+typedef struct {
+    int64_t n;              /* number of points, >= 1                                          */
+    const double *xyz;      /* n x 3, cm, array of structures, caller order                    */
+    const double *w;        /* n quadrature volumes (cm^3); NULL => uniform grid, w = h^3      */
+    double h;               /* grid spacing (cm) for a uniform cell-centred grid, else 0       */
+    double self_coeff;      /* own-cell coefficient c_self; NaN => integral of K over the cube
+                               of side h (requires h > 0); 0 for point clouds                  */
+    double cube_lo[3];      /* lower corner of the octree root cube (cm)                        */
+    double cube_size;       /* edge of the root cube (cm); <= 0 => bounding cube of the points */
+} ph_points;
+
+/* Gas (Sec. 2.1 eqs. (2)-(3)).  pO2 = o2_fraction * p_torr. */
+typedef struct {
+    double p_torr;          /* gas pressure p (Torr), > 0                                       */
+    double o2_fraction;     /* pO2 / p, in (0, 1]                                              */
+    double pq_torr;         /* quenching pressure p_q (Torr), >= 0                             */
+    double xi_omega_over_alpha; /* xi * omega / alpha, >= 0                                    */
+    double chi_min;         /* cm^-1 Torr^-1, 0 < chi_min < chi_max                            */
+    double chi_max;
+} ph_gas;
+
+/* Adaptive selection (Sec. 3; Sec. 4.3 eq. (22); Sec. 5 field rule). */
+typedef struct {
+    double src_rel;         /* keep source j iff I_j >= src_rel * max_k I_k; 0 => every point  */
+    double e_abs;           /* keep target i iff |E_i| >= e_abs (V/m); < 0 => rule off         */
+    double e_applied;       /* keep target i iff |E_i| >= e_applied + e_rel (max|E| - e_applied) */
+    double e_rel;           /*   ... < 0 => rule off.  Both rules off => every point a target   */
+    double r_s;             /* third strategy of Sec. 3; must be 0 in this library              */
+} ph_thresholds;
+
+typedef struct {
+    ph_precision precision;
+    ph_selector selector;
+    ph_method method;
+    int order_q;            /* lattice points per box edge (2..8); 0 => 6 for FP64, 4 otherwise */
+    int leaf_capacity;      /* split a box while max(#sources, #targets) > this; 0 => 64         */
+    int max_depth;          /* 0 => depth of the tree over all points (bounded by 16)           */
+    double pinv_rel_cutoff; /* singular values below cutoff * sigma_max are dropped; 0 => default */
+    const float *selector_weights; /* host, PH_MLP_NPARAM floats (learned selector) or NULL     */
+    float selector_logit_threshold;/* keep a leaf iff logit >= threshold                       */
+    size_t workspace_cap_bytes;    /* 0 => unlimited                                           */
+} ph_options;
+
+#define PH_NPHASES 12
+typedef struct {
+    int64_t n_src;          /* selected sources                                                 */
+    int64_t n_tgt;          /* selected targets                                                 */
+    int64_t n_boxes;        /* boxes of the per-call tree                                       */
+    int64_t n_leaves;
+    int32_t levels;         /* deepest level + 1                                                */
+    int32_t fell_back;      /* 1 if the learned selector fell back                              */
+    int64_t n_src_dropped;  /* sources removed by the learned selector                          */
+    double t_ms[PH_NPHASES];/* per-phase device time (hipEvent), filled only when requested     */
+} ph_stats;
+
+/* Returns a static description of a status code. */
+const char *ph_status_string(ph_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *ph_last_error(void);
+
+/* Fills *opt with the defaults described above (FP32, threshold selector, FMM). */
+void ph_options_default(ph_options *opt);
+
+/*
+ * Builds a plan over a fixed point set: validates every argument on the host
+ * (no device call happens before validation passes), copies the points to the
+ * device, computes 63-bit Morton keys and radix-sorts them, and precomputes
+ * the per-level FMM operators in FP64 on the host.
+ * Errors: PH_EINVAL (bad argument), PH_ENOMEM, PH_EDEVICE, PH_EUNSUPPORTED.
+ * Synchronous.  *out is set only on success.
+ */
+ph_status ph_plan_create(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
+                         const ph_options *opt, ph_plan **out);
+
+/* Releases the plan and its device memory; NULL is allowed.  Synchronises the device. */
+void ph_plan_destroy(ph_plan *plan);
+
+/*
+ * One evaluation of S_ph (Sec. 2.4 eqs. (15)-(17) with the adaptive sets of Sec. 3).
+ *   I     device, n values in caller order: double for PH_FP64, float otherwise.
+ *         Must be finite and >= 0 (else PH_ENUMERIC is reported, see below).
+ *   absE  device, n floats |E| (V/m); may be NULL only if both field rules are off.
+ *   S_out device, n values, same type as I: S_ph at selected targets, 0 elsewhere.
+ *   stats host, nullable.  When non-NULL the call waits for the stream, fills
+ *         the counts and per-phase times, and reports PH_ENUMERIC if the device
+ *         flagged a bad source value.  When NULL the call is fully asynchronous
+ *         and a numeric fault is reported by the next ph_plan_check().
+ */
+ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
+                      void *stream, ph_stats *stats);
+
+/* Waits for the stream and reports PH_ENUMERIC if any earlier call saw a bad source value. */
+ph_status ph_plan_check(ph_plan *plan, void *stream);
+
+/* Number of points of the plan, or -1 for NULL. */
+int64_t ph_plan_size(const ph_plan *plan);
+
+/*
+ * Test/inspection access to plan-internal device arrays after the last
+ * ph_evaluate (or after ph_plan_create for the plan-time arrays).  Copies at
+ * most cap_bytes into the host buffer dst and stores the array length (in
+ * elements) in *n_out.  Synchronous.  what:
+ *   0 sorted Morton keys (uint64, n)      1 permutation sorted->caller (int32, n)
+ *   2 selected sources, sorted positions (int32, n_src)
+ *   3 selected targets, sorted positions (int32, n_tgt)
+ *   4 box table (int32, n_boxes x PH_BOX_FIELDS, fields below)
+ *   5 level offsets (int32, levels + 1)   6 own-cell coefficient (double, 1)
+ *   7 scale exponent e of the FP32 forms (int32, 1)
+ *   8 learned-selector leaf features (float, n_leaves x 8)
+ *   9 learned-selector leaf boxes (int32, n_leaves)
+ */
+#define PH_BOX_FIELDS 10  /* level, ax, ay, az, src_first, src_count, tgt_first, tgt_count, parent, flags */
+ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, int64_t *n_out);
+
+/*
+ * Learned leaf selector network: 8 inputs -> 64 -> 64 -> 1 logit, exact-erf
+ * GELU after each hidden layer.  Parameter vector layout (PH_MLP_NPARAM floats):
+ *   W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3[1]   (row-major, out x in)
+ * These calls carry the training loop; buffers are device, caller-owned, FP32.
+ */
+#define PH_MLP_NIN 8
+#define PH_MLP_NHID 64
+#define PH_MLP_NPARAM (64 * 8 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* logits[m] = net(X[m][8]); bf16 != 0 rounds weights and activations to BF16 (FP32 accumulate). */
+ph_status ph_mlp_forward(const float *params, const float *X, int64_t m, float *logits, int bf16,
+                         void *stream);
+
+/*
+ * Mean binary cross-entropy with logits over m rows, positive rows weighted by
+ * pos_weight, and its gradient: grad[PH_MLP_NPARAM] (overwritten) and loss[1].
+ */
+ph_status ph_mlp_backward(const float *params, const float *X, const float *y, float pos_weight,
+                          int64_t m, float *grad, float *loss, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on nparam values in place. */
+ph_status ph_adam_step(float *params, float *m1, float *m2, const float *grad, int64_t nparam,
+                       float lr, float beta1, float beta2, float eps, int64_t step, void *stream);
+
+/*
+ * Per-leaf selector features of the last ph_evaluate's source tree into feats
+ * (device, capacity cap_leaves x 8 floats); *n_leaves receives the count.
+ * Synchronous.  Feature definitions are listed in the selector documentation.
+ */
+ph_status ph_selector_features(ph_plan *plan, float *feats, int64_t cap_leaves, int64_t *n_leaves,
+                               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PH_H_ */

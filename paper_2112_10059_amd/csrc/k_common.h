@@ -1,0 +1,117 @@
+// Device helpers shared by the evaluation kernels: the absorption kernel and level bookkeeping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ph_internal.h"
+
+namespace ph {
+
+// K(r) = g(r) / (4 pi r^2), g of Sec. 2.1 eq. (3):
+//   K(r) = exp(-a r) (1 - exp(-(b - a) r)) / (4 pi L r^3),  a = chi_min pO2, b = chi_max pO2.
+template <class T>
+struct KParams {
+    T a, bma, inv4piL;   // a, b - a, 1 / (4 pi L)
+    T na_l2, nbma_l2;    // -a log2(e), -(b - a) log2(e) for the exp2 form
+};
+
+template <class T>
+inline KParams<T> make_kparams(const Gas &g)
+{
+    const double log2e = 1.4426950408889634;
+    KParams<T> k;
+    k.a = (T)g.a;
+    k.bma = (T)(g.b - g.a);
+    k.inv4piL = (T)(1.0 / (4.0 * M_PI * g.L));
+    k.na_l2 = (T)(-g.a * log2e);
+    k.nbma_l2 = (T)(-(g.b - g.a) * log2e);
+    return k;
+}
+
+// FP32: hardware rsqrt and exp2.  1 - exp(-t) loses relative accuracy for small t,
+// so below t = 1/4 it is summed as the alternating Taylor series (truncation < 4e-10).
+// NEAR selects that guarded form; far-field callers (t >= 1 by construction) may skip it.
+template <bool NEAR>
+__device__ __forceinline__ float kernel_eval(float r2, const KParams<float> &k)
+{
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    const float e1 = __builtin_amdgcn_exp2f(k.na_l2 * r);
+    float om = 1.0f - __builtin_amdgcn_exp2f(k.nbma_l2 * r);
+    if (NEAR) {
+        const float t = k.bma * r;
+        // t (1 - t/2 (1 - t/3 (1 - t/4 (1 - t/5 (1 - t/6 (1 - t/7))))))
+        float s = 1.0f - t * (1.0f / 7.0f);
+        s = 1.0f - t * (1.0f / 6.0f) * s;
+        s = 1.0f - t * (1.0f / 5.0f) * s;
+        s = 1.0f - t * (1.0f / 4.0f) * s;
+        s = 1.0f - t * (1.0f / 3.0f) * s;
+        s = 1.0f - t * 0.5f * s;
+        om = (t < 0.25f) ? t * s : om;
+    }
+    return e1 * om * (rinv * rinv * rinv) * k.inv4piL;
+}
+
+template <bool NEAR>
+__device__ __forceinline__ double kernel_eval(double r2, const KParams<double> &k)
+{
+    const double r = sqrt(r2);
+    return exp(-k.a * r) * (-expm1(-k.bma * r)) * k.inv4piL / (r2 * r);
+}
+
+template <class T>
+struct Vec4T;
+template <>
+struct Vec4T<float> {
+    using type = float4;
+};
+template <>
+struct Vec4T<double> {
+    using type = double4;
+};
+
+struct LevelTable {
+    int32_t base[kMaxDepth + 2];
+    int32_t cap[kMaxDepth + 2];
+    double hw[kMaxDepth + 2];
+    int32_t depth;
+};
+
+inline LevelTable make_level_table(const Plan &p)
+{
+    LevelTable t{};
+    for (int l = 0; l <= p.max_depth; ++l) {
+        t.base[l] = (int32_t)p.level_base[l];
+        t.cap[l] = (int32_t)p.level_cap[l];
+        t.hw[l] = p.hw[l];
+    }
+    t.base[p.max_depth + 1] = (int32_t)p.level_base[p.max_depth + 1];
+    t.depth = p.max_depth;
+    return t;
+}
+
+// Box b is live if it lies in its level's slot range below that level's count.
+__device__ __forceinline__ bool box_live(const LevelTable &lt, const CallScalars *sc, int32_t b, int &level)
+{
+    for (int l = 0; l <= lt.depth; ++l) {
+        const int32_t i = b - lt.base[l];
+        if (i >= 0 && i < lt.cap[l]) {
+            level = l;
+            return i < sc->lvl_count[l];
+        }
+    }
+    return false;
+}
+
+// Index of a well-separated offset t in [-3,3]^3 minus [-1,1]^3, in x-major order (0..315).
+__host__ __device__ __forceinline__ int m2l_slot(int dx, int dy, int dz)
+{
+    const int X = dx + 3, Y = dy + 3, Z = dz + 3;
+    const int full = X * 49 + Y * 7 + Z;
+    auto inner_before = [](int v) { return v < 2 ? 0 : (v > 4 ? 3 : v - 2); };
+    const bool xin = X >= 2 && X <= 4, yin = Y >= 2 && Y <= 4;
+    const int skipped = inner_before(X) * 9 + (xin ? (inner_before(Y) * 3 + (yin ? inner_before(Z) : 0)) : 0);
+    return full - skipped;
+}
+
+}  // namespace ph

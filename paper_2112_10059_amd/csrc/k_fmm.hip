@@ -1,0 +1,400 @@
+// Upward pass, translations, downward pass and leaf evaluation of the adaptive FMM.
+//
+// Sec. 2.4: near interactions (eq. (16), box B and its neighbours) are summed
+// exactly; far interactions go through artificial sources whose intensities
+// solve the check-point fit of eq. (17), recursively over the octree.
+// Representation per box of level l (half-width h_l, centre c):
+//   phi  (upward)   : intensities of artificial sources at c + h_l * lattice   (n_lam)
+//   u    (downward) : far-field values at the check points c + h_l * lattice   (n_lam)
+//   psi  (leaf)     : uc2e_l^T u, intensities of artificial sources at c + h_l * shell (n_sig)
+// Kernels:
+//   p2m     leaf sources -> check values on the shell -> phi = uc2e_l * check
+//   m2m     phi_parent = sum_c m2m_{l+1,c} phi_child_c
+//   down    u_B = l2l_{l,oct} u_parent + sum_{A in V(B)} m2l_{l,A-B} phi_A + sum_{X(B)} K(lattice, y) q
+//   leaf    targets of leaf B: K(x, shell) psi + sum_{W(B)} K(x, lattice_A) phi_A
+//           + sum_{U(B)} K(x, y) q (Kahan in FP32) + own-cell term, combined in FP64.
+#include <hip/hip_runtime.h>
+
+#include "k_common.h"
+
+namespace ph {
+
+namespace {
+
+template <class T>
+using V4 = typename Vec4T<T>::type;
+
+template <class T>
+struct FmmArgs {
+    BoxArrays bx;
+    Lists L;
+    LevelTable lt;
+    KParams<T> kp;
+    const CallScalars *sc;
+    const V4<T> *s_dat;
+    const V4<T> *t_dat;
+    const int32_t *t_pos;
+    const int32_t *perm;
+    const T *uc2e_rm;   // levels x n_lam x n_sig
+    const T *uc2e_cm;   // levels x n_sig x n_lam
+    const T *m2m;       // levels x 8 x n_lam^2 (column-major)
+    const T *l2l;
+    const T *m2l;       // levels x 316 x n_lam^2 (column-major)
+    const T *lat;       // n_lam x 3
+    const T *shell;     // n_sig x 3
+    T *phi;
+    T *u;
+    int n_lam, n_sig;
+    double lo0, lo1, lo2;
+    double P;
+};
+
+template <class T>
+__device__ __forceinline__ void box_centre(const FmmArgs<T> &a, int32_t b, double hw, T &cx, T &cy, T &cz)
+{
+    cx = (T)(a.lo0 + (2.0 * a.bx.ax[b] + 1.0) * hw);
+    cy = (T)(a.lo1 + (2.0 * a.bx.ay[b] + 1.0) * hw);
+    cz = (T)(a.lo2 + (2.0 * a.bx.az[b] + 1.0) * hw);
+}
+
+// ---------------------------------------------------------------- P2M
+
+template <class T>
+__global__ void p2m_kernel(FmmArgs<T> a, int level)
+{
+    const int32_t i = blockIdx.x;
+    if (i >= a.sc->lvl_count[level]) return;
+    const int32_t b = a.lt.base[level] + i;
+    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.s_cnt[b] == 0) return;
+    __shared__ V4<T> tile[128];
+    __shared__ T chk[kMaxShell];
+    const double hw = a.lt.hw[level];
+    T cx, cy, cz;
+    box_centre(a, b, hw, cx, cy, cz);
+    const T h = (T)hw;
+    const int32_t sf = a.bx.s_first[b], sn = a.bx.s_cnt[b];
+    T acc[4] = {0, 0, 0, 0};  // n_sig <= 4 * 128 check points per thread slot
+    for (int base = 0; base < sn; base += 128) {
+        const int m = min(128, sn - base);
+        __syncthreads();
+        if ((int)threadIdx.x < m) tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
+        __syncthreads();
+        for (int r = 0; r < 4; ++r) {
+            const int sg = threadIdx.x + r * 128;
+            if (sg >= a.n_sig) break;
+            const T px = cx + h * a.shell[3 * sg], py = cy + h * a.shell[3 * sg + 1], pz = cz + h * a.shell[3 * sg + 2];
+            T s = 0;
+            for (int j = 0; j < m; ++j) {
+                const V4<T> y = tile[j];
+                const T dx = px - y.x, dy = py - y.y, dz = pz - y.z;
+                s += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * y.w;
+            }
+            acc[r] += s;
+        }
+    }
+    for (int r = 0; r < 4; ++r) {
+        const int sg = threadIdx.x + r * 128;
+        if (sg < a.n_sig) chk[sg] = acc[r];
+    }
+    __syncthreads();
+    const T *U = a.uc2e_cm + (size_t)level * a.n_sig * a.n_lam;
+    for (int li = threadIdx.x; li < a.n_lam; li += blockDim.x) {
+        T s = 0;
+        for (int sg = 0; sg < a.n_sig; ++sg) s += U[(size_t)sg * a.n_lam + li] * chk[sg];
+        a.phi[(size_t)b * a.n_lam + li] = s;
+    }
+}
+
+// ---------------------------------------------------------------- M2M
+
+template <class T>
+__global__ void m2m_kernel(FmmArgs<T> a, int level)
+{
+    const int32_t i = blockIdx.x;
+    if (i >= a.sc->lvl_count[level]) return;
+    const int32_t b = a.lt.base[level] + i;
+    if ((a.bx.flags[b] & kBoxLeaf) || a.bx.s_cnt[b] == 0) return;
+    __shared__ T cphi[8 * kMaxLattice];
+    __shared__ int32_t chs[8];
+    if (threadIdx.x < 8) {
+        const int32_t c = a.bx.child[(size_t)b * 8 + threadIdx.x];
+        chs[threadIdx.x] = (c >= 0 && a.bx.s_cnt[c] > 0) ? c : -1;
+    }
+    __syncthreads();
+    for (int o = 0; o < 8; ++o) {
+        const int32_t c = chs[o];
+        for (int li = threadIdx.x; li < a.n_lam; li += blockDim.x)
+            cphi[o * a.n_lam + li] = c >= 0 ? a.phi[(size_t)c * a.n_lam + li] : T(0);
+    }
+    __syncthreads();
+    const size_t nn = (size_t)a.n_lam * a.n_lam;
+    for (int li = threadIdx.x; li < a.n_lam; li += blockDim.x) {
+        T s = 0;
+        for (int o = 0; o < 8; ++o) {
+            if (chs[o] < 0) continue;
+            const T *M = a.m2m + ((size_t)(level + 1) * 8 + o) * nn;
+            const T *x = cphi + o * a.n_lam;
+            for (int j = 0; j < a.n_lam; ++j) s += M[(size_t)j * a.n_lam + li] * x[j];
+        }
+        a.phi[(size_t)b * a.n_lam + li] = s;
+    }
+}
+
+// ---------------------------------------------------------------- downward: L2L + M2L + P2L
+
+template <class T>
+__global__ void down_kernel(FmmArgs<T> a, int level)
+{
+    const int32_t i = blockIdx.x;
+    if (i >= a.sc->lvl_count[level]) return;
+    const int32_t b = a.lt.base[level] + i;
+    if (a.bx.t_cnt[b] == 0) return;
+    __shared__ T vec[kMaxLattice];
+    __shared__ V4<T> tile[128];
+    const int nl = a.n_lam;
+    const size_t nn = (size_t)nl * nl;
+    // per-thread rows li = threadIdx.x + k * blockDim.x, at most 4 of them (n_lam <= 512 with 128+ threads)
+    T acc[4] = {0, 0, 0, 0};
+    const int32_t par = a.bx.parent[b];
+    if (level >= 3) {
+        for (int li = threadIdx.x; li < nl; li += blockDim.x) vec[li] = a.u[(size_t)par * nl + li];
+        __syncthreads();
+        const int oct = ((a.bx.ax[b] & 1) << 2) | ((a.bx.ay[b] & 1) << 1) | (a.bx.az[b] & 1);
+        const T *M = a.l2l + ((size_t)level * 8 + oct) * nn;
+        for (int k = 0; k < 4; ++k) {
+            const int li = threadIdx.x + k * blockDim.x;
+            if (li >= nl) break;
+            T s = 0;
+            for (int j = 0; j < nl; ++j) s += M[(size_t)j * nl + li] * vec[j];
+            acc[k] = s;
+        }
+    }
+    // V list: children of the parent's colleagues that are not adjacent to B
+    const int bx0 = a.bx.ax[b], by0 = a.bx.ay[b], bz0 = a.bx.az[b];
+    for (int d = 0; d < 27; ++d) {
+        const int32_t P = a.bx.coll[(size_t)par * 27 + d];
+        if (P < 0) continue;
+        for (int o = 0; o < 8; ++o) {
+            const int32_t A = a.bx.child[(size_t)P * 8 + o];
+            if (A < 0 || a.bx.s_cnt[A] == 0) continue;
+            const int dx = a.bx.ax[A] - bx0, dy = a.bx.ay[A] - by0, dz = a.bx.az[A] - bz0;
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+            __syncthreads();
+            for (int li = threadIdx.x; li < nl; li += blockDim.x) vec[li] = a.phi[(size_t)A * nl + li];
+            __syncthreads();
+            const T *M = a.m2l + ((size_t)level * kNumM2L + m2l_slot(dx, dy, dz)) * nn;
+            for (int k = 0; k < 4; ++k) {
+                const int li = threadIdx.x + k * blockDim.x;
+                if (li >= nl) break;
+                T s = 0;
+                for (int j = 0; j < nl; ++j) s += M[(size_t)j * nl + li] * vec[j];
+                acc[k] += s;
+            }
+        }
+    }
+    // X list: sources of coarser leaves straight onto the check points
+    const uint32_t x0 = a.L.x_off[b], x1 = a.L.x_off[b + 1];
+    if (x1 > x0) {
+        const double hw = a.lt.hw[level];
+        T cx, cy, cz;
+        box_centre(a, b, hw, cx, cy, cz);
+        const T h = (T)hw;
+        for (uint32_t e = x0; e < x1; ++e) {
+            const int32_t C = a.L.x[e];
+            const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
+            for (int base = 0; base < sn; base += 128) {
+                const int m = min(128, sn - base);
+                __syncthreads();
+                if ((int)threadIdx.x < m) tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
+                __syncthreads();
+                for (int k = 0; k < 4; ++k) {
+                    const int li = threadIdx.x + k * blockDim.x;
+                    if (li >= nl) break;
+                    const T px = cx + h * a.lat[3 * li], py = cy + h * a.lat[3 * li + 1], pz = cz + h * a.lat[3 * li + 2];
+                    T s = 0;
+                    for (int j = 0; j < m; ++j) {
+                        const V4<T> y = tile[j];
+                        const T ddx = px - y.x, ddy = py - y.y, ddz = pz - y.z;
+                        s += kernel_eval<true>(ddx * ddx + ddy * ddy + ddz * ddz, a.kp) * y.w;
+                    }
+                    acc[k] += s;
+                }
+            }
+        }
+    }
+    for (int k = 0; k < 4; ++k) {
+        const int li = threadIdx.x + k * blockDim.x;
+        if (li >= nl) break;
+        a.u[(size_t)b * nl + li] = acc[k];
+    }
+}
+
+// ---------------------------------------------------------------- leaf evaluation
+
+template <class T>
+struct Acc;
+template <>
+struct Acc<float> {
+    float s = 0.f, c = 0.f;  // Kahan sum and compensation
+    __device__ __forceinline__ void add(float v)
+    {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+template <>
+struct Acc<double> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(double v) { s += v; }
+    __device__ __forceinline__ double value() const { return s; }
+};
+
+template <class T, class TO>
+__global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
+{
+    const int32_t b = blockIdx.x;
+    int level;
+    if (!box_live(a.lt, a.sc, b, level)) return;
+    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.t_cnt[b] == 0) return;
+    __shared__ T uvec[kMaxLattice];
+    __shared__ T psi[kMaxShell];
+    __shared__ V4<T> tile[64];
+    const int nl = a.n_lam, ns = a.n_sig;
+    const bool has_far = level >= 2;
+    const double hw = a.lt.hw[level];
+    T cx, cy, cz;
+    box_centre(a, b, hw, cx, cy, cz);
+    const T h = (T)hw;
+    if (has_far) {
+        for (int li = threadIdx.x; li < nl; li += blockDim.x) uvec[li] = a.u[(size_t)b * nl + li];
+        __syncthreads();
+        const T *U = a.uc2e_rm + (size_t)level * nl * ns;
+        for (int sg = threadIdx.x; sg < ns; sg += blockDim.x) {
+            T s = 0;
+            for (int li = 0; li < nl; ++li) s += U[(size_t)li * ns + sg] * uvec[li];
+            psi[sg] = s;
+        }
+        __syncthreads();
+    }
+    const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+    const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
+    const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
+    const int scale_exp = a.sc->scale_exp;
+    for (int tb = 0; tb < tn; tb += blockDim.x) {
+        const int t = tb + threadIdx.x;
+        const bool act = t < tn;
+        V4<T> x;
+        if (act) x = a.t_dat[tf + t];
+        else x.x = x.y = x.z = x.w = T(0);
+        T far = 0;
+        if (has_far && act) {
+            for (int sg = 0; sg < ns; ++sg) {
+                const T dx = x.x - (cx + h * a.shell[3 * sg]);
+                const T dy = x.y - (cy + h * a.shell[3 * sg + 1]);
+                const T dz = x.z - (cz + h * a.shell[3 * sg + 2]);
+                far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * psi[sg];
+            }
+        }
+        // W list: artificial sources of smaller non-adjacent boxes
+        for (uint32_t e = w0; e < w1; ++e) {
+            const int32_t A = a.L.w[e];
+            const int la = a.bx.level[A];
+            const double hwa = a.lt.hw[la];
+            T ax, ay, az;
+            box_centre(a, A, hwa, ax, ay, az);
+            const T ha = (T)hwa;
+            __syncthreads();
+            for (int li = threadIdx.x; li < nl; li += blockDim.x) uvec[li] = a.phi[(size_t)A * nl + li];
+            __syncthreads();
+            if (act)
+                for (int li = 0; li < nl; ++li) {
+                    const T dx = x.x - (ax + ha * a.lat[3 * li]);
+                    const T dy = x.y - (ay + ha * a.lat[3 * li + 1]);
+                    const T dz = x.z - (az + ha * a.lat[3 * li + 2]);
+                    far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * uvec[li];
+                }
+        }
+        // U list: exact near field
+        Acc<T> near;
+        for (uint32_t e = u0; e < u1; ++e) {
+            const int32_t C = a.L.u[e];
+            const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
+            for (int base = 0; base < sn; base += 64) {
+                const int m = min(64, sn - base);
+                __syncthreads();
+                if ((int)threadIdx.x < m) tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
+                __syncthreads();
+                if (act)
+                    for (int j = 0; j < m; ++j) {
+                        const V4<T> y = tile[j];
+                        const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+                        const T r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 > T(0)) near.add(kernel_eval<true>(r2, a.kp) * y.w);
+                    }
+            }
+        }
+        if (act) {
+            const double tot = (double)far + near.value() + (double)x.w;
+            S_out[a.perm[a.t_pos[tf + t]]] = (TO)(a.P * ldexp(tot, scale_exp));
+        }
+    }
+}
+
+template <class T>
+FmmArgs<T> make_args(Plan &p)
+{
+    FmmArgs<T> a;
+    a.bx = p.box;
+    a.L = p.lists;
+    a.lt = make_level_table(p);
+    a.kp = make_kparams<T>(p.gas);
+    a.sc = p.d_sc;
+    a.s_dat = (const V4<T> *)p.d_s_dat;
+    a.t_dat = (const V4<T> *)p.d_t_dat;
+    a.t_pos = p.d_t_pos;
+    a.perm = p.d_perm;
+    a.uc2e_rm = (const T *)p.ops.uc2e_rm;
+    a.uc2e_cm = (const T *)p.ops.uc2e_cm;
+    a.m2m = (const T *)p.ops.m2m;
+    a.l2l = (const T *)p.ops.l2l;
+    a.m2l = (const T *)p.ops.m2l;
+    a.lat = (const T *)p.ops.lat_unit;
+    a.shell = (const T *)p.ops.shell_unit;
+    a.phi = (T *)p.d_phi;
+    a.u = (T *)p.d_u;
+    a.n_lam = p.n_lam;
+    a.n_sig = p.n_sig;
+    a.lo0 = p.cube_lo[0];
+    a.lo1 = p.cube_lo[1];
+    a.lo2 = p.cube_lo[2];
+    a.P = p.gas.P;
+    return a;
+}
+
+template <class T>
+void run_fmm_t(Plan &p, void *S_out, hipStream_t s)
+{
+    FmmArgs<T> a = make_args<T>(p);
+    const int D = p.max_depth;
+    const int down_threads = std::max(128, ((p.n_lam + 63) / 64) * 64);
+    for (int l = 2; l <= D; ++l)
+        p2m_kernel<T><<<(unsigned)p.level_cap[l], 128, 0, s>>>(a, l);
+    for (int l = D - 1; l >= 2; --l)
+        m2m_kernel<T><<<(unsigned)p.level_cap[l], down_threads, 0, s>>>(a, l);
+    for (int l = 2; l <= D; ++l)
+        down_kernel<T><<<(unsigned)p.level_cap[l], down_threads, 0, s>>>(a, l);
+    leaf_kernel<T, T><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out);
+}
+
+}  // namespace
+
+void run_fmm(Plan &p, void *S_out, hipStream_t s)
+{
+    if (p.precision == PH_FP64) run_fmm_t<double>(p, S_out, s);
+    else run_fmm_t<float>(p, S_out, s);
+}
+
+}  // namespace ph

@@ -1,0 +1,632 @@
+// C ABI entry points of libph: validation, plan construction, evaluation sequencing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "k_common.h"
+#include "ph_internal.h"
+
+namespace ph {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class T>
+void upload(Plan &p, void **dst, const std::vector<T> &src)
+{
+    *dst = dev_alloc(p, src.size() * sizeof(T));
+    PH_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <class T>
+std::vector<T> convert(const std::vector<double> &v)
+{
+    std::vector<T> out(v.size());
+    for (size_t i = 0; i < v.size(); ++i) out[i] = (T)v[i];
+    return out;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+// Validation happens entirely on the host, before any device call.
+void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr, const ph_options *opt)
+{
+    auto bad = [](const std::string &s) { throw Error{PH_EINVAL, s}; };
+    if (!pts || !gas || !thr || !opt) bad("null argument");
+    if (pts->n < 1) bad("points.n must be >= 1");
+    if (pts->n > (int64_t)1 << 30) bad("points.n exceeds 2^30");
+    if (!pts->xyz) bad("points.xyz is null");
+    for (int64_t i = 0; i < 3 * pts->n; ++i)
+        if (!finite(pts->xyz[i])) bad("points.xyz has a non-finite coordinate");
+    if (pts->w) {
+        for (int64_t i = 0; i < pts->n; ++i)
+            if (!finite(pts->w[i]) || pts->w[i] < 0) bad("points.w must be finite and >= 0");
+    } else if (!(pts->h > 0) || !finite(pts->h)) {
+        bad("points.h must be > 0 when points.w is null");
+    }
+    if (pts->h < 0 || !finite(pts->h)) bad("points.h must be finite and >= 0");
+    if (std::isnan(pts->self_coeff)) {
+        if (!(pts->h > 0)) bad("self_coeff NaN needs h > 0");
+    } else if (!finite(pts->self_coeff) || pts->self_coeff < 0) {
+        bad("points.self_coeff must be NaN or finite and >= 0");
+    }
+    if (pts->cube_size > 0) {
+        for (int d = 0; d < 3; ++d)
+            if (!finite(pts->cube_lo[d])) bad("points.cube_lo must be finite");
+        for (int64_t i = 0; i < pts->n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double x = pts->xyz[3 * i + d];
+                if (x < pts->cube_lo[d] || x > pts->cube_lo[d] + pts->cube_size)
+                    bad("a point lies outside the root cube");
+            }
+    } else if (!finite(pts->cube_size)) {
+        bad("points.cube_size must be finite");
+    }
+    if (!(gas->p_torr > 0) || !finite(gas->p_torr)) bad("gas.p_torr must be > 0");
+    if (!(gas->o2_fraction > 0) || !(gas->o2_fraction <= 1)) bad("gas.o2_fraction must be in (0, 1]");
+    if (!(gas->pq_torr >= 0) || !finite(gas->pq_torr)) bad("gas.pq_torr must be >= 0");
+    if (!(gas->xi_omega_over_alpha >= 0) || !finite(gas->xi_omega_over_alpha))
+        bad("gas.xi_omega_over_alpha must be >= 0");
+    if (!(gas->chi_min > 0) || !(gas->chi_max > gas->chi_min) || !finite(gas->chi_max))
+        bad("gas needs 0 < chi_min < chi_max");
+    if (!finite(thr->src_rel) || thr->src_rel < 0 || thr->src_rel > 1) bad("thresholds.src_rel must be in [0, 1]");
+    if (!finite(thr->e_abs)) bad("thresholds.e_abs must be finite");
+    if (!finite(thr->e_rel) || thr->e_rel > 1) bad("thresholds.e_rel must be <= 1 (negative = off)");
+    if (!finite(thr->e_applied) || thr->e_applied < 0) bad("thresholds.e_applied must be >= 0");
+    if (thr->r_s != 0.0) throw Error{PH_EUNSUPPORTED, "thresholds.r_s (third strategy) must be 0"};
+    if (opt->precision < PH_FP64 || opt->precision > PH_FP32_BF16SPLIT) bad("options.precision out of range");
+    if (opt->method < PH_METHOD_FMM || opt->method > PH_METHOD_DIRECT) bad("options.method out of range");
+    if (opt->selector < PH_SEL_THRESHOLD || opt->selector > PH_SEL_LEARNED) bad("options.selector out of range");
+    if (opt->order_q != 0 && (opt->order_q < 2 || opt->order_q > 8)) bad("options.order_q must be 0 or 2..8");
+    if (opt->leaf_capacity < 0 || opt->leaf_capacity > 4096) bad("options.leaf_capacity must be 0..4096");
+    if (opt->max_depth < 0 || opt->max_depth > kMaxDepth) bad("options.max_depth must be 0..16");
+    if (!(opt->pinv_rel_cutoff >= 0) || opt->pinv_rel_cutoff >= 1) bad("options.pinv_rel_cutoff must be in [0, 1)");
+    if (opt->selector == PH_SEL_LEARNED) {
+        if (!opt->selector_weights) bad("learned selector needs selector_weights");
+        for (int i = 0; i < PH_MLP_NPARAM; ++i)
+            if (!std::isfinite(opt->selector_weights[i])) bad("selector_weights has a non-finite value");
+        if (opt->method != PH_METHOD_FMM) bad("the learned selector needs the FMM method");
+    }
+}
+
+// Per-level box counts of the tree over all points (every point a source and a target).
+// Any per-call tree over a subset is contained in it, so these bound every call.
+void full_tree_levels(const std::vector<uint64_t> &keys, int leaf_cap, int depth_limit,
+                      std::vector<int64_t> &level_cap)
+{
+    struct Seg { int64_t b, e; };
+    std::vector<Seg> cur{{0, (int64_t)keys.size()}}, nxt;
+    level_cap.clear();
+    for (int l = 0; l <= depth_limit; ++l) {
+        level_cap.push_back((int64_t)cur.size());
+        if (l == depth_limit) break;
+        nxt.clear();
+        int shift = 3 * (kMortonBits - (l + 1));
+        for (const Seg &s : cur) {
+            if (s.e - s.b <= leaf_cap) continue;
+            int64_t i = s.b;
+            while (i < s.e) {
+                uint64_t pre = keys[i] >> shift;
+                int64_t j = std::upper_bound(keys.begin() + i, keys.begin() + s.e, ((pre + 1) << shift) - 1) -
+                            keys.begin();
+                nxt.push_back({i, j});
+                i = j;
+            }
+        }
+        if (nxt.empty()) break;
+        cur.swap(nxt);
+    }
+}
+
+void alloc_workspace(Plan &p)
+{
+    const int64_t n = p.n;
+    const size_t rs = p.precision == PH_FP64 ? sizeof(double) : sizeof(float);
+    p.d_sc = (CallScalars *)dev_alloc(p, sizeof(CallScalars));
+    p.d_flag = (uint64_t *)dev_alloc(p, (size_t)n * sizeof(uint64_t));
+    p.scan_tmp_bytes = std::max(scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4));
+    p.d_scan_tmp = dev_alloc(p, p.scan_tmp_bytes);
+    p.d_s_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    p.d_t_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    p.d_s_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
+    p.d_t_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
+    p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);
+    p.d_t_dat = dev_alloc(p, (size_t)n * 4 * rs);
+    const int64_t B = p.box_cap;
+    BoxArrays &b = p.box;
+    b.level = (int32_t *)dev_alloc(p, B * 4);
+    b.ax = (int32_t *)dev_alloc(p, B * 4);
+    b.ay = (int32_t *)dev_alloc(p, B * 4);
+    b.az = (int32_t *)dev_alloc(p, B * 4);
+    b.s_first = (int32_t *)dev_alloc(p, B * 4);
+    b.s_cnt = (int32_t *)dev_alloc(p, B * 4);
+    b.t_first = (int32_t *)dev_alloc(p, B * 4);
+    b.t_cnt = (int32_t *)dev_alloc(p, B * 4);
+    b.parent = (int32_t *)dev_alloc(p, B * 4);
+    b.flags = (int32_t *)dev_alloc(p, B * 4);
+    b.child = (int32_t *)dev_alloc(p, B * 8 * 4);
+    b.coll = (int32_t *)dev_alloc(p, B * 27 * 4);
+    b.child_tmp = (int4 *)dev_alloc(p, (size_t)p.widest_level * 8 * sizeof(int4));
+    b.child_cnt = (uint32_t *)dev_alloc(p, (size_t)(p.widest_level + 1) * 4);
+    Lists &L = p.lists;
+    L.u_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
+    L.w_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
+    L.x_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
+    L.u_cap = std::max<int64_t>(1024, 64 * B);
+    L.w_cap = std::max<int64_t>(1024, 32 * B);
+    L.x_cap = std::max<int64_t>(1024, 32 * B);
+    L.u = (int32_t *)dev_alloc(p, L.u_cap * 4);
+    L.w = (int32_t *)dev_alloc(p, L.w_cap * 4);
+    L.x = (int32_t *)dev_alloc(p, L.x_cap * 4);
+    if (p.method == PH_METHOD_FMM) {
+        p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
+        p.d_u = dev_alloc(p, (size_t)B * p.n_lam * rs);
+    }
+    p.d_srcbox_mark = (int32_t *)dev_alloc(p, B * 4);
+    p.d_feat = (float *)dev_alloc(p, (size_t)B * 8 * 4);
+    p.d_feat_box = (int32_t *)dev_alloc(p, B * 4);
+    p.d_logit = (float *)dev_alloc(p, B * 4);
+    p.d_sel_params = (float *)dev_alloc(p, PH_MLP_NPARAM * 4);
+    if (!p.sel_weights.empty())
+        PH_HIP(hipMemcpy(p.d_sel_params, p.sel_weights.data(), PH_MLP_NPARAM * 4, hipMemcpyHostToDevice));
+}
+
+void free_plan(Plan *p)
+{
+    if (!p) return;
+    // every pointer member that came from dev_alloc
+    void *ptrs[] = {p->d_key, p->d_perm, p->d_iperm, p->d_xyz, p->d_w, p->ops.uc2e_rm, p->ops.uc2e_cm,
+                    p->ops.m2m, p->ops.l2l, p->ops.m2l, p->ops.lat_unit, p->ops.shell_unit, p->ops.m2l_hi,
+                    p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_scan_tmp, p->d_s_pos, p->d_t_pos, p->d_s_key,
+                    p->d_t_key, p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
+                    p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
+                    p->box.child, p->box.coll, p->box.child_tmp, p->box.child_cnt, p->lists.u_off,
+                    p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->d_phi, p->d_u,
+                    p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params};
+    for (void *q : ptrs) dev_free(q);
+    if (p->events_ready)
+        for (auto &e : p->ev) (void)hipEventDestroy(e);
+    delete p;
+}
+
+ph_status fail(const Error &e)
+{
+    g_last_error = e.what;
+    return e.status;
+}
+
+}  // namespace
+
+void set_last_error(const std::string &s) { g_last_error = s; }
+
+void *dev_alloc(Plan &p, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (p.workspace_cap && p.bytes_allocated + bytes > p.workspace_cap)
+        throw Error{PH_ENOMEM, "workspace cap exceeded (" + std::to_string(p.bytes_allocated + bytes) + " bytes)"};
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) throw Error{PH_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    p.bytes_allocated += bytes;
+    return ptr;
+}
+
+void dev_free(void *ptr)
+{
+    if (ptr) (void)hipFree(ptr);
+}
+
+static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
+                        const ph_options *opt)
+{
+    p.n = pts->n;
+    PH_HIP(hipGetDevice(&p.device));
+    p.precision = opt->precision;
+    p.method = opt->method;
+    p.selector = opt->selector;
+    p.q = opt->order_q ? opt->order_q : (p.precision == PH_FP64 ? 6 : 4);
+    p.leaf_cap = opt->leaf_capacity ? opt->leaf_capacity : 64;
+    p.pinv_cut = opt->pinv_rel_cutoff > 0 ? opt->pinv_rel_cutoff : (p.precision == PH_FP64 ? 1e-15 : 1e-7);
+    p.thr = *thr;
+    p.workspace_cap = opt->workspace_cap_bytes;
+    p.h = pts->h;
+    const double pO2 = gas->o2_fraction * gas->p_torr;
+    p.gas.a = gas->chi_min * pO2;
+    p.gas.b = gas->chi_max * pO2;
+    p.gas.L = std::log(gas->chi_max / gas->chi_min);
+    p.gas.P = gas->pq_torr / (gas->p_torr + gas->pq_torr) * gas->xi_omega_over_alpha;
+    p.c_self = std::isnan(pts->self_coeff) ? cube_self_integral(p.gas, pts->h) : pts->self_coeff;
+    p.uniform_w = pts->w == nullptr;
+    p.w_uniform = p.uniform_w ? pts->h * pts->h * pts->h : 0.0;
+    if (opt->selector == PH_SEL_LEARNED) {
+        p.sel_weights.assign(opt->selector_weights, opt->selector_weights + PH_MLP_NPARAM);
+        p.sel_threshold = opt->selector_logit_threshold;
+    }
+    // root cube
+    if (pts->cube_size > 0) {
+        for (int d = 0; d < 3; ++d) p.cube_lo[d] = pts->cube_lo[d];
+        p.cube_size = pts->cube_size;
+    } else {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t i = 0; i < p.n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], pts->xyz[3 * i + d]);
+                hi[d] = std::max(hi[d], pts->xyz[3 * i + d]);
+            }
+        double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
+        if (!(ext > 0)) ext = 1.0;
+        ext *= 1.0 + 1e-9;
+        for (int d = 0; d < 3; ++d) p.cube_lo[d] = lo[d] - 1e-12 * ext;
+        p.cube_size = ext * (1.0 + 2e-12);
+    }
+    // points to the device, keys, sort
+    const int64_t n = p.n;
+    double *d_xyz_in = (double *)dev_alloc(p, (size_t)n * 3 * 8);
+    double *d_w_in = nullptr;
+    PH_HIP(hipMemcpy(d_xyz_in, pts->xyz, (size_t)n * 3 * 8, hipMemcpyHostToDevice));
+    if (pts->w) {
+        d_w_in = (double *)dev_alloc(p, (size_t)n * 8);
+        PH_HIP(hipMemcpy(d_w_in, pts->w, (size_t)n * 8, hipMemcpyHostToDevice));
+    }
+    p.d_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
+    p.d_perm = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    uint64_t *ktmp = (uint64_t *)dev_alloc(p, (size_t)n * 8);
+    int32_t *vtmp = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    size_t hb = radix_sort_tmp_bytes(n);
+    uint32_t *htmp = (uint32_t *)dev_alloc(p, hb);
+    hipStream_t s = nullptr;
+    launch_morton_keys(d_xyz_in, n, p.cube_lo[0], p.cube_lo[1], p.cube_lo[2], p.cube_size, p.d_key, p.d_perm, s);
+    radix_sort_pairs(p.d_key, p.d_perm, ktmp, vtmp, n, htmp, hb, 3 * kMortonBits, s);
+    p.d_xyz = (double *)dev_alloc(p, (size_t)n * 3 * 8);
+    p.d_iperm = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    if (d_w_in) p.d_w = (double *)dev_alloc(p, (size_t)n * 8);
+    launch_gather_sorted(d_xyz_in, d_w_in, p.d_perm, n, p.d_xyz, p.d_w, p.d_iperm, s);
+    PH_HIP(hipStreamSynchronize(s));
+    dev_free(ktmp);
+    dev_free(vtmp);
+    dev_free(htmp);
+    dev_free(d_xyz_in);
+    dev_free(d_w_in);
+    p.bytes_allocated -= (size_t)n * 8 + (size_t)n * 4 + hb + (size_t)n * 24 + (d_w_in ? (size_t)n * 8 : 0);
+    // tree bound from the tree over all points
+    std::vector<uint64_t> hkeys(n);
+    PH_HIP(hipMemcpy(hkeys.data(), p.d_key, (size_t)n * 8, hipMemcpyDeviceToHost));
+    int depth_limit = opt->max_depth ? opt->max_depth : kMaxDepth;
+    full_tree_levels(hkeys, p.leaf_cap, depth_limit, p.level_cap);
+    p.max_depth = (int)p.level_cap.size() - 1;
+    p.level_base.assign(p.level_cap.size() + 1, 0);
+    for (size_t l = 0; l < p.level_cap.size(); ++l) p.level_base[l + 1] = p.level_base[l] + p.level_cap[l];
+    p.box_cap = p.level_base.back();
+    p.widest_level = *std::max_element(p.level_cap.begin(), p.level_cap.end());
+    p.hw.resize(p.max_depth + 1);
+    for (int l = 0; l <= p.max_depth; ++l) p.hw[l] = p.cube_size / std::ldexp(1.0, l + 1);
+    // far-field operators
+    for (int t = 0; t < kNumM2L; ++t) {  // the device offset->slot map must match the host table
+        int dx, dy, dz;
+        m2l_offset(t, dx, dy, dz);
+        if (m2l_slot(dx, dy, dz) != t || m2l_index(dx, dy, dz) != t)
+            throw Error{PH_EDEVICE, "internal: translation slot table mismatch"};
+    }
+    if (p.method == PH_METHOD_FMM) {
+        HostOperators H;
+        build_operators(p.gas, p.q, p.cube_size, std::max(p.max_depth, 2), p.pinv_cut, H);
+        p.n_lam = H.n_lam;
+        p.n_sig = H.n_sig;
+        const int nl = p.n_lam, ns = p.n_sig, L = p.max_depth + 1;
+        std::vector<double> rm((size_t)L * nl * ns, 0.0), cm((size_t)L * nl * ns, 0.0);
+        std::vector<double> m2m((size_t)L * 8 * nl * nl, 0.0), l2l((size_t)L * 8 * nl * nl, 0.0);
+        std::vector<double> m2l((size_t)L * kNumM2L * nl * nl, 0.0);
+        for (int l = 2; l < L; ++l) {
+            const std::vector<double> &U = H.uc2e[l];
+            for (int i = 0; i < nl; ++i)
+                for (int k = 0; k < ns; ++k) {
+                    rm[(size_t)l * nl * ns + (size_t)i * ns + k] = U[(size_t)i * ns + k];
+                    cm[(size_t)l * nl * ns + (size_t)k * nl + i] = U[(size_t)i * ns + k];
+                }
+            if (l >= 3)
+                for (int c = 0; c < 8; ++c)
+                    for (int i = 0; i < nl; ++i)
+                        for (int j = 0; j < nl; ++j) {
+                            double v = H.m2m[l][(size_t)c * nl * nl + (size_t)i * nl + j];
+                            // column-major storage: (i, j) at j*nl + i
+                            m2m[((size_t)l * 8 + c) * nl * nl + (size_t)j * nl + i] = v;
+                            // l2l = m2m^T: (j, i) entry equals v
+                            l2l[((size_t)l * 8 + c) * nl * nl + (size_t)i * nl + j] = v;
+                        }
+            for (int t = 0; t < kNumM2L; ++t)
+                for (int i = 0; i < nl; ++i)
+                    for (int j = 0; j < nl; ++j)
+                        m2l[((size_t)l * kNumM2L + t) * nl * nl + (size_t)j * nl + i] =
+                            H.m2l[l][(size_t)t * nl * nl + (size_t)i * nl + j];
+        }
+        std::vector<double> shell = H.shell_unit, lat = H.lat_unit;
+        if (p.precision == PH_FP64) {
+            upload(p, &p.ops.uc2e_rm, rm);
+            upload(p, &p.ops.uc2e_cm, cm);
+            upload(p, &p.ops.m2m, m2m);
+            upload(p, &p.ops.l2l, l2l);
+            upload(p, &p.ops.m2l, m2l);
+            upload(p, &p.ops.lat_unit, lat);
+            upload(p, &p.ops.shell_unit, shell);
+        } else {
+            upload(p, &p.ops.uc2e_rm, convert<float>(rm));
+            upload(p, &p.ops.uc2e_cm, convert<float>(cm));
+            upload(p, &p.ops.m2m, convert<float>(m2m));
+            upload(p, &p.ops.l2l, convert<float>(l2l));
+            upload(p, &p.ops.m2l, convert<float>(m2l));
+            upload(p, &p.ops.lat_unit, convert<float>(lat));
+            upload(p, &p.ops.shell_unit, convert<float>(shell));
+        }
+    }
+    alloc_workspace(p);
+    for (auto &e : p.ev) PH_HIP(hipEventCreate(&e));
+    p.events_ready = true;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" {
+
+const char *ph_status_string(ph_status s)
+{
+    switch (s) {
+    case PH_OK: return "ok";
+    case PH_EINVAL: return "invalid argument";
+    case PH_ENOMEM: return "out of memory";
+    case PH_EDEVICE: return "device error";
+    case PH_ENUMERIC: return "non-finite or negative source value";
+    case PH_EUNSUPPORTED: return "unsupported";
+    case PH_EFALLBACK: return "learned selector fell back to the threshold rule";
+    }
+    return "unknown status";
+}
+
+const char *ph_last_error(void) { return g_last_error.c_str(); }
+
+void ph_options_default(ph_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = PH_FP32;
+    opt->selector = PH_SEL_THRESHOLD;
+    opt->method = PH_METHOD_FMM;
+    opt->selector_logit_threshold = 0.0f;
+}
+
+ph_status ph_plan_create(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
+                         const ph_options *opt, ph_plan **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(Error{PH_EINVAL, "out is null"});
+    Plan *p = nullptr;
+    try {
+        validate(pts, gas, thr, opt);
+        p = new Plan();
+        create_plan(*p, pts, gas, thr, opt);
+        *out = reinterpret_cast<ph_plan *>(p);
+        return PH_OK;
+    } catch (const Error &e) {
+        free_plan(p);
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        free_plan(p);
+        return fail(Error{PH_ENOMEM, "host allocation failed"});
+    }
+}
+
+void ph_plan_destroy(ph_plan *plan)
+{
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    free_plan(reinterpret_cast<Plan *>(plan));
+}
+
+int64_t ph_plan_size(const ph_plan *plan) { return plan ? reinterpret_cast<const Plan *>(plan)->n : -1; }
+
+static ph_status fetch_scalars(Plan &p, hipStream_t s)
+{
+    PH_HIP(hipMemcpyAsync(&p.h_sc, p.d_sc, sizeof(CallScalars), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (p.h_sc.err & 2) throw Error{PH_ENOMEM, "interaction list capacity exceeded"};
+    if (p.h_sc.err & 1) throw Error{PH_ENUMERIC, "I holds a non-finite or negative value"};
+    return PH_OK;
+}
+
+ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
+                      ph_stats *stats)
+{
+    g_last_error.clear();
+    if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (!I || !S_out) return fail(Error{PH_EINVAL, "I and S_out must be device pointers"});
+    const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
+    if (need_e && !absE) return fail(Error{PH_EINVAL, "absE is required when a field rule is on"});
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    try {
+        PH_HIP(hipSetDevice(p.device));
+        const bool timed = stats != nullptr;
+        int ph_i = 0;
+        auto mark = [&]() {
+            if (timed && ph_i <= PH_NPHASES) PH_HIP(hipEventRecord(p.ev[ph_i++], s));
+        };
+        mark();
+        launch_reset_scalars(p.d_sc, s);
+        launch_reduce_max(I, p.precision == PH_FP64, absE, p.thr.e_rel >= 0, p.n, p.d_sc, s);
+        launch_select_flags(p, I, absE, S_out, s);
+        exclusive_scan_u64(p.d_flag, p.n, p.d_scan_tmp, &p.d_sc->packed_total, s);
+        launch_compact(p, I, s);
+        mark();  // 1: selection + compaction
+        if (p.method == PH_METHOD_DIRECT) {
+            run_direct(p, S_out, s);
+            mark();
+        } else {
+            build_tree(p, s);
+            mark();  // 2: tree
+            if (p.selector == PH_SEL_LEARNED) {
+                selector_apply(p, s);
+                mark();  // 3: learned selector
+            }
+            build_lists(p, s);
+            mark();
+            run_fmm(p, S_out, s);
+            mark();
+        }
+        PH_HIP(hipGetLastError());
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            fetch_scalars(p, s);
+            stats->n_src = p.h_sc.n_src;
+            stats->n_tgt = p.h_sc.n_tgt;
+            int levels = 0;
+            int64_t nb = 0;
+            for (int l = 0; l <= p.max_depth; ++l) {
+                nb += p.h_sc.lvl_count[l];
+                if (p.h_sc.lvl_count[l] > 0) levels = l + 1;
+            }
+            stats->n_boxes = p.method == PH_METHOD_FMM ? nb : 0;
+            stats->levels = levels;
+            stats->n_src_dropped = p.h_sc.n_src_dropped;
+            for (int k = 0; k + 1 < ph_i && k < PH_NPHASES; ++k) {
+                float ms = 0;
+                PH_HIP(hipEventElapsedTime(&ms, p.ev[k], p.ev[k + 1]));
+                stats->t_ms[k] = ms;
+            }
+        }
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_plan_check(ph_plan *plan, void *stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    try {
+        PH_HIP(hipSetDevice(p.device));
+        return fetch_scalars(p, reinterpret_cast<hipStream_t>(stream));
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, int64_t *n_out)
+{
+    g_last_error.clear();
+    if (!plan || !n_out) return fail(Error{PH_EINVAL, "plan and n_out must be non-null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    try {
+        PH_HIP(hipSetDevice(p.device));
+        PH_HIP(hipDeviceSynchronize());
+        PH_HIP(hipMemcpy(&p.h_sc, p.d_sc, sizeof(CallScalars), hipMemcpyDeviceToHost));
+        auto copy = [&](const void *src, int64_t count, size_t elem) {
+            *n_out = count;
+            size_t bytes = std::min<size_t>((size_t)count * elem, cap_bytes > 0 ? (size_t)cap_bytes : 0);
+            if (bytes && dst) PH_HIP(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+        };
+        int64_t nb = 0;
+        for (int l = 0; l <= p.max_depth; ++l) nb += p.h_sc.lvl_count[l];
+        switch (what) {
+        case 0: copy(p.d_key, p.n, 8); break;
+        case 1: copy(p.d_perm, p.n, 4); break;
+        case 2: copy(p.d_s_pos, p.h_sc.n_src, 4); break;
+        case 3: copy(p.d_t_pos, p.h_sc.n_tgt, 4); break;
+        case 4: {
+            // assemble the box table level by level (levels are stored at fixed bases)
+            std::vector<int32_t> tab;
+            int32_t *fields[PH_BOX_FIELDS] = {p.box.level, p.box.ax, p.box.ay, p.box.az, p.box.s_first,
+                                              p.box.s_cnt, p.box.t_first, p.box.t_cnt, p.box.parent,
+                                              p.box.flags};
+            std::vector<int32_t> col;
+            tab.assign((size_t)nb * PH_BOX_FIELDS, 0);
+            int64_t row = 0;
+            for (int l = 0; l <= p.max_depth; ++l) {
+                int32_t c = p.h_sc.lvl_count[l], st = p.h_sc.lvl_start[l];
+                if (c <= 0) continue;
+                col.resize(c);
+                for (int f = 0; f < PH_BOX_FIELDS; ++f) {
+                    PH_HIP(hipMemcpy(col.data(), fields[f] + st, (size_t)c * 4, hipMemcpyDeviceToHost));
+                    for (int32_t k = 0; k < c; ++k) tab[(size_t)(row + k) * PH_BOX_FIELDS + f] = col[k];
+                }
+                row += c;
+            }
+            *n_out = nb;
+            size_t bytes = std::min<size_t>(tab.size() * 4, cap_bytes > 0 ? (size_t)cap_bytes : 0);
+            if (bytes && dst) std::memcpy(dst, tab.data(), bytes);
+            break;
+        }
+        case 5: {
+            std::vector<int32_t> v(p.max_depth + 2);
+            for (int l = 0; l <= p.max_depth + 1; ++l) v[l] = p.h_sc.lvl_start[l];
+            *n_out = (int64_t)v.size();
+            size_t bytes = std::min<size_t>(v.size() * 4, cap_bytes > 0 ? (size_t)cap_bytes : 0);
+            if (bytes && dst) std::memcpy(dst, v.data(), bytes);
+            break;
+        }
+        case 6:
+            *n_out = 1;
+            if (dst && cap_bytes >= 8) std::memcpy(dst, &p.c_self, 8);
+            break;
+        case 7:
+            *n_out = 1;
+            if (dst && cap_bytes >= 4) std::memcpy(dst, &p.h_sc.scale_exp, 4);
+            break;
+        default: throw Error{PH_EINVAL, "unknown debug array"};
+        }
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_mlp_forward(const float *params, const float *X, int64_t m, float *logits, int bf16, void *stream)
+{
+    g_last_error.clear();
+    if (!params || !X || !logits || m < 0) return fail(Error{PH_EINVAL, "bad mlp_forward arguments"});
+    try {
+        launch_mlp_forward(params, X, m, logits, bf16, reinterpret_cast<hipStream_t>(stream));
+        PH_HIP(hipGetLastError());
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_mlp_backward(const float *params, const float *X, const float *y, float pos_weight, int64_t m,
+                          float *grad, float *loss, void *stream)
+{
+    g_last_error.clear();
+    if (!params || !X || !y || !grad || !loss || m < 1 || !(pos_weight > 0))
+        return fail(Error{PH_EINVAL, "bad mlp_backward arguments"});
+    try {
+        launch_mlp_backward(params, X, y, pos_weight, m, grad, loss, reinterpret_cast<hipStream_t>(stream));
+        PH_HIP(hipGetLastError());
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_adam_step(float *params, float *m1, float *m2, const float *grad, int64_t nparam, float lr,
+                       float beta1, float beta2, float eps, int64_t step, void *stream)
+{
+    g_last_error.clear();
+    if (!params || !m1 || !m2 || !grad || nparam < 1 || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(Error{PH_EINVAL, "bad adam_step arguments"});
+    try {
+        launch_adam(params, m1, m2, grad, nparam, lr, beta1, beta2, eps, step, reinterpret_cast<hipStream_t>(stream));
+        PH_HIP(hipGetLastError());
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+}  // extern "C"

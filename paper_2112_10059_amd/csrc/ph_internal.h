@@ -1,0 +1,216 @@
+// Internal declarations of libph: the plan object, device buffers and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ph.h"
+
+namespace ph {
+
+// ------------------------------------------------------------------ errors
+
+struct Error {
+    ph_status status;
+    std::string what;
+};
+
+void set_last_error(const std::string &s);
+
+#define PH_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            throw ::ph::Error{PH_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)};   \
+    } while (0)
+
+// ------------------------------------------------------------------ constants
+
+constexpr int kMortonBits = 21;                 // bits per axis of the Morton key
+constexpr int kMaxDepth = 16;                   // deepest octree level supported
+constexpr int kNumM2L = 316;                    // 7^3 - 3^3 well-separated offsets
+constexpr int kMaxLattice = 512;                // q <= 8
+constexpr int kMaxShell = 6 * 8 * 8 + 2;        // shell of q+1 <= 9 points per edge
+
+// Box flag bits
+constexpr int kBoxLeaf = 1;
+
+// Device-resident per-call scalars (one struct, one allocation)
+struct CallScalars {
+    double imax;          // max of I over all points
+    double emax;          // max of |E| over all points
+    int32_t err;          // bit 0: bad source value seen
+    int32_t scale_exp;    // e with I scaled by 2^-e in the FP32 forms
+    int32_t n_src;
+    int32_t n_tgt;
+    int32_t lvl_count[kMaxDepth + 2];   // boxes per level
+    int32_t lvl_start[kMaxDepth + 3];   // first box of each level
+    int32_t n_u, n_w, n_x;              // list lengths
+    int32_t n_src_dropped;              // learned selector
+    int32_t pad;
+    uint64_t packed_total;              // selected (sources | targets << 32)
+};
+
+// Box table (structure of arrays, capacity box_cap)
+struct BoxArrays {
+    int32_t *level = nullptr;
+    int32_t *ax = nullptr, *ay = nullptr, *az = nullptr;
+    int32_t *s_first = nullptr, *s_cnt = nullptr, *t_first = nullptr, *t_cnt = nullptr;
+    int32_t *parent = nullptr;
+    int32_t *flags = nullptr;
+    int32_t *child = nullptr;       // box_cap x 8, -1 if absent
+    int32_t *coll = nullptr;        // box_cap x 27 colleagues, -1 if absent
+    int4 *child_tmp = nullptr;      // per-level scratch: (cap of widest level) x 8 child ranges
+    uint32_t *child_cnt = nullptr;  // per-level scratch: nonempty children per box (scan input)
+};
+
+// Interaction lists in CSR form over all boxes (offsets box_cap + 1)
+struct Lists {
+    uint32_t *u_off = nullptr, *w_off = nullptr, *x_off = nullptr;  // scanned counts
+    int32_t *u = nullptr, *w = nullptr, *x = nullptr;
+    int64_t u_cap = 0, w_cap = 0, x_cap = 0;
+};
+
+struct Gas {
+    double a, b, L, P;   // chi_min pO2, chi_max pO2, ln(chi_max/chi_min), prefactor
+};
+
+// Per-level FMM operators on the device; T is float or double.
+struct OperatorsDev {
+    void *uc2e_rm = nullptr;   // levels x n_lam x n_sig (row i = lattice index)
+    void *uc2e_cm = nullptr;   // levels x n_sig x n_lam (transposed copy)
+    void *m2m = nullptr;       // levels x 8 x n_lam x n_lam, column-major (entry (i,j) at j*n_lam+i)
+    void *l2l = nullptr;       // levels x 8 x n_lam x n_lam, column-major
+    void *m2l = nullptr;       // levels x 316 x n_lam x n_lam, column-major
+    void *lat_unit = nullptr;  // n_lam x 3 lattice nodes on [-1,1]^3 (T)
+    void *shell_unit = nullptr;// n_sig x 3 shell points (radius included) in units of the half-width
+    // BF16 split copies of m2l (hi, lo), row-major tiles for MFMA
+    void *m2l_hi = nullptr, *m2l_lo = nullptr;
+};
+
+struct Plan {
+    // configuration
+    int64_t n = 0;
+    int device = 0;
+    ph_precision precision = PH_FP32;
+    ph_method method = PH_METHOD_FMM;
+    ph_selector selector = PH_SEL_THRESHOLD;
+    int q = 4, n_lam = 64, n_sig = 98;
+    int leaf_cap = 64;
+    int max_depth = 0;       // deepest level any per-call tree may reach
+    double pinv_cut = 0;
+    double cube_lo[3] = {0, 0, 0};
+    double cube_size = 1;
+    double h = 0;
+    double c_self = 0;
+    Gas gas{};
+    ph_thresholds thr{};
+    bool uniform_w = true;
+    double w_uniform = 0;
+    // learned selector
+    std::vector<float> sel_weights;
+    float sel_threshold = 0.f;
+    bool sel_valid = false;
+
+    // plan-time device arrays
+    uint64_t *d_key = nullptr;      // sorted Morton keys (n)
+    int32_t *d_perm = nullptr;      // sorted -> caller index (n)
+    int32_t *d_iperm = nullptr;     // caller -> sorted index (n)
+    double *d_xyz = nullptr;        // sorted coordinates (n x 3)
+    double *d_w = nullptr;          // sorted weights (n), null on uniform grids
+    std::vector<int64_t> level_cap; // max boxes per level (from the tree over all points)
+    std::vector<int64_t> level_base;// first slot of each level in the box table
+    int64_t box_cap = 0;
+    int64_t widest_level = 0;
+    OperatorsDev ops;
+    std::vector<double> hw;         // half-width of boxes per level
+
+    // per-call workspace
+    CallScalars *d_sc = nullptr;
+    CallScalars h_sc{};             // host mirror of the last fetched scalars
+    uint64_t *d_flag = nullptr;     // n packed (src | tgt << 32) flags, scanned in place
+    void *d_scan_tmp = nullptr;     // scan partials
+    size_t scan_tmp_bytes = 0;
+    int32_t *d_s_pos = nullptr, *d_t_pos = nullptr;   // sorted positions of selected points
+    uint64_t *d_s_key = nullptr, *d_t_key = nullptr;  // their keys
+    void *d_s_dat = nullptr;        // sources: (x, y, z, q = w * I * 2^-e), float4 or double4
+    void *d_t_dat = nullptr;        // targets: (x, y, z, self = c_self * I * 2^-e or 0)
+    BoxArrays box;
+    Lists lists;
+    void *d_phi = nullptr;          // box_cap x n_lam upward densities
+    void *d_u = nullptr;            // box_cap x n_lam downward check potentials
+    int32_t *d_srcbox_mark = nullptr; // learned selector: per-box drop mark
+    float *d_feat = nullptr;        // learned selector features (box_cap x 8)
+    int32_t *d_feat_box = nullptr;  // box of each feature row
+    float *d_logit = nullptr;       // per-feature-row logits
+    float *d_sel_params = nullptr;  // device copy of the selector weights
+    hipEvent_t ev[PH_NPHASES + 1] = {};
+    bool events_ready = false;
+    size_t bytes_allocated = 0;
+    size_t workspace_cap = 0;
+};
+
+// ------------------------------------------------------------------ host-side helpers
+
+void *dev_alloc(Plan &p, size_t bytes);
+void dev_free(void *ptr);
+
+// Operators (ph_operators.cpp): FP64 on the host
+struct HostOperators {
+    int q = 0, n_lam = 0, n_sig = 0;
+    std::vector<double> lat_unit, shell_unit;            // n x 3
+    std::vector<std::vector<double>> uc2e;               // per level: n_lam x n_sig (row-major)
+    std::vector<std::vector<double>> m2m;                // per level: 8 x n_lam x n_lam (row-major)
+    std::vector<std::vector<double>> m2l;                // per level: 316 x n_lam x n_lam (row-major)
+};
+
+void build_operators(const Gas &gas, int q, double root_size, int max_depth, double cut,
+                     HostOperators &out);
+double cube_self_integral(const Gas &gas, double h);
+int m2l_index(int dx, int dy, int dz);  // -1 unless the offset is well separated
+void m2l_offset(int idx, int &dx, int &dy, int &dz);
+
+// ------------------------------------------------------------------ launchers (device code)
+
+// sort / scan (k_sort.hip)
+void launch_morton_keys(const double *xyz, int64_t n, double lo0, double lo1, double lo2,
+                        double size, uint64_t *keys, int32_t *idx, hipStream_t s);
+void radix_sort_pairs(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp, int64_t n,
+                      uint32_t *hist_tmp, size_t hist_bytes, int key_bits, hipStream_t s);
+size_t radix_sort_tmp_bytes(int64_t n);
+size_t scan_tmp_bytes(int64_t n, size_t elem);
+void exclusive_scan_u32(uint32_t *data, int64_t n, void *tmp, uint32_t *total, hipStream_t s);
+void exclusive_scan_u64(uint64_t *data, int64_t n, void *tmp, uint64_t *total, hipStream_t s);
+void launch_gather_sorted(const double *xyz, const double *w, const int32_t *perm, int64_t n,
+                          double *xyz_sorted, double *w_sorted, int32_t *iperm, hipStream_t s);
+
+// selection (k_select.hip)
+void launch_reset_scalars(CallScalars *sc, hipStream_t s);
+void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
+                       CallScalars *sc, hipStream_t s);
+void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s);
+void launch_compact(const Plan &p, const void *I, hipStream_t s);
+
+// tree (k_tree.hip)
+void build_tree(Plan &p, hipStream_t s);
+void build_lists(Plan &p, hipStream_t s);
+
+// fmm (k_fmm.hip)
+void run_fmm(Plan &p, void *S_out, hipStream_t s);
+
+// direct sum (k_direct.hip)
+void run_direct(Plan &p, void *S_out, hipStream_t s);
+
+// learned selector (k_mlp.hip)
+void selector_apply(Plan &p, hipStream_t s);
+void launch_mlp_forward(const float *params, const float *X, int64_t m, float *logits, int bf16,
+                        hipStream_t s);
+void launch_mlp_backward(const float *params, const float *X, const float *y, float pos_weight,
+                         int64_t m, float *grad, float *loss, hipStream_t s);
+void launch_adam(float *params, float *m1, float *m2, const float *grad, int64_t nparam, float lr,
+                 float b1, float b2, float eps, int64_t step, hipStream_t s);
+
+}  // namespace ph

@@ -1,0 +1,354 @@
+// Plan-time FP64 construction of the far-field operators (host side).
+//
+// The far field of eq. (16) is carried by artificial sources whose intensities
+// are fitted so that they reproduce the true field at check points
+// (Sec. 2.4 eq. (17) and the figure of artificial/check points), applied
+// recursively over the octree (Sec. 2.4, last paragraph).  For the
+// absorption kernel K(r) = g(r)/(4 pi r^2) of eq. (3) a single enclosing
+// surface of artificial sources does not converge (K is not harmonic, so
+// matching on one surface does not fix the field elsewhere).  The artificial
+// sources therefore sit on a q^3 Chebyshev lattice filling the box, and the
+// check points on the cube surface of half-width 3.5 h_l (q+1 points per
+// edge).  The downward (local) representation is the transpose: check points
+// on the lattice inside the box, artificial sources on the surface.
+//
+// Per level l (box half-width h_l):
+//   uc2e_l = pinv(K(shell_l, lattice_l))            n_lam x n_sig (truncated SVD)
+//   m2m_{l,c} = uc2e_{l-1} K(shell_{l-1}, lattice_l + off_c)   child c -> parent
+//   l2l_{l,c} = m2m_{l,c}^T                          parent check values -> child
+//   m2l_{l,t} = K(lattice_l, lattice_l + 2 h_l t)    316 well-separated offsets t
+#include <algorithm>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+#include "ph_internal.h"
+
+namespace ph {
+
+namespace {
+
+double kernel_fp64(double r, const Gas &g)
+{
+    return std::exp(-g.a * r) * (-std::expm1(-(g.b - g.a) * r)) / (4.0 * M_PI * g.L * r * r * r);
+}
+
+template <class F>
+void parallel_for(int n, F &&f)
+{
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 4 || nt == 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int i = (int)t; i < n; i += (int)nt) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+// One-sided Jacobi SVD of the m x n matrix A (column-major, m >= n).
+// On exit A holds U * diag(s); s the singular values; V (n x n, column-major).
+void jacobi_svd(int m, int n, std::vector<double> &A, std::vector<double> &s, std::vector<double> &V)
+{
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n - 1; ++p) {
+            double *ap = &A[(size_t)p * m];
+            for (int q = p + 1; q < n; ++q) {
+                double *aq = &A[(size_t)q * m];
+                double al = 0, be = 0, ga = 0;
+                for (int i = 0; i < m; ++i) {
+                    al += ap[i] * ap[i];
+                    be += aq[i] * aq[i];
+                    ga += ap[i] * aq[i];
+                }
+                if (ga == 0.0) continue;
+                double rel = std::fabs(ga) / std::sqrt(al * be);
+                if (!(rel > 1e-16)) continue;
+                off = std::max(off, rel);
+                double zeta = (be - al) / (2.0 * ga);
+                double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+                for (int i = 0; i < m; ++i) {
+                    double x = ap[i], y = aq[i];
+                    ap[i] = c * x - sn * y;
+                    aq[i] = sn * x + c * y;
+                }
+                double *vp = &V[(size_t)p * n], *vq = &V[(size_t)q * n];
+                for (int i = 0; i < n; ++i) {
+                    double x = vp[i], y = vq[i];
+                    vp[i] = c * x - sn * y;
+                    vq[i] = sn * x + c * y;
+                }
+            }
+        }
+        if (off < 1e-15) break;
+    }
+    s.resize(n);
+    for (int j = 0; j < n; ++j) {
+        double acc = 0;
+        for (int i = 0; i < m; ++i) acc += A[(size_t)j * m + i] * A[(size_t)j * m + i];
+        s[j] = std::sqrt(acc);
+    }
+}
+
+// Pseudo-inverse of the m x n row-major matrix M (m >= n) by truncated SVD:
+// returns the n x m row-major matrix V diag(1/s) U^T, dropping s < cut * s_max.
+std::vector<double> pinv_rowmajor(int m, int n, const std::vector<double> &M, double cut)
+{
+    std::vector<double> A((size_t)m * n);  // column-major copy
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) A[(size_t)j * m + i] = M[(size_t)i * n + j];
+    std::vector<double> s, V;
+    jacobi_svd(m, n, A, s, V);
+    double smax = 0;
+    for (double x : s) smax = std::max(smax, x);
+    std::vector<double> P((size_t)n * m, 0.0);
+    for (int k = 0; k < n; ++k) {
+        if (!(s[k] > cut * smax) || s[k] == 0.0) continue;
+        double inv2 = 1.0 / (s[k] * s[k]);  // A column k = U_k s_k  ->  U_k / s_k = A_k / s_k^2
+        const double *ak = &A[(size_t)k * m];
+        const double *vk = &V[(size_t)k * n];
+        for (int r = 0; r < n; ++r) {
+            double vr = vk[r] * inv2;
+            if (vr == 0.0) continue;
+            double *pr = &P[(size_t)r * m];
+            for (int c = 0; c < m; ++c) pr[c] += vr * ak[c];
+        }
+    }
+    return P;
+}
+
+void kernel_matrix(const std::vector<double> &X, const std::vector<double> &Y, int nx, int ny,
+                   double sx, double sy, const double *shift_y, const Gas &g, std::vector<double> &out)
+{
+    // out[i*ny + j] = K(|sx X_i - (sy Y_j + shift)|)
+    out.resize((size_t)nx * ny);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double d0 = sx * X[3 * i] - (sy * Y[3 * j] + shift_y[0]);
+            double d1 = sx * X[3 * i + 1] - (sy * Y[3 * j + 1] + shift_y[1]);
+            double d2 = sx * X[3 * i + 2] - (sy * Y[3 * j + 2] + shift_y[2]);
+            out[(size_t)i * ny + j] = kernel_fp64(std::sqrt(d0 * d0 + d1 * d1 + d2 * d2), g);
+        }
+}
+
+}  // namespace
+
+int m2l_index(int dx, int dy, int dz)
+{
+    if (dx < -3 || dx > 3 || dy < -3 || dy > 3 || dz < -3 || dz > 3) return -1;
+    if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) return -1;
+    int k = 0;
+    for (int x = -3; x <= 3; ++x)
+        for (int y = -3; y <= 3; ++y)
+            for (int z = -3; z <= 3; ++z) {
+                if (std::abs(x) <= 1 && std::abs(y) <= 1 && std::abs(z) <= 1) continue;
+                if (x == dx && y == dy && z == dz) return k;
+                ++k;
+            }
+    return -1;
+}
+
+void m2l_offset(int idx, int &dx, int &dy, int &dz)
+{
+    int k = 0;
+    for (int x = -3; x <= 3; ++x)
+        for (int y = -3; y <= 3; ++y)
+            for (int z = -3; z <= 3; ++z) {
+                if (std::abs(x) <= 1 && std::abs(y) <= 1 && std::abs(z) <= 1) continue;
+                if (k == idx) {
+                    dx = x;
+                    dy = y;
+                    dz = z;
+                    return;
+                }
+                ++k;
+            }
+    dx = dy = dz = 0;
+}
+
+void build_operators(const Gas &gas, int q, double root_size, int max_depth, double cut, HostOperators &out)
+{
+    const double kShellRadius = 3.5;
+    out.q = q;
+    out.n_lam = q * q * q;
+    // lattice: tensor Chebyshev nodes of the first kind on [-1,1]
+    std::vector<double> t(q);
+    for (int k = 0; k < q; ++k) t[k] = std::cos(M_PI * (k + 0.5) / q);
+    out.lat_unit.clear();
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j)
+            for (int k = 0; k < q; ++k) {
+                out.lat_unit.push_back(t[i]);
+                out.lat_unit.push_back(t[j]);
+                out.lat_unit.push_back(t[k]);
+            }
+    // shell: boundary points of the (q+1)^3 uniform grid on [-1,1]^3, times the shell radius
+    int e = q + 1;
+    out.shell_unit.clear();
+    for (int i = 0; i < e; ++i)
+        for (int j = 0; j < e; ++j)
+            for (int k = 0; k < e; ++k) {
+                if (i != 0 && i != e - 1 && j != 0 && j != e - 1 && k != 0 && k != e - 1) continue;
+                out.shell_unit.push_back(kShellRadius * (-1.0 + 2.0 * i / (e - 1)));
+                out.shell_unit.push_back(kShellRadius * (-1.0 + 2.0 * j / (e - 1)));
+                out.shell_unit.push_back(kShellRadius * (-1.0 + 2.0 * k / (e - 1)));
+            }
+    out.n_sig = (int)out.shell_unit.size() / 3;
+    const int nl = out.n_lam, ns = out.n_sig;
+    const int L = max_depth + 1;
+    out.uc2e.assign(L, {});
+    out.m2m.assign(L, {});
+    out.m2l.assign(L, {});
+    const double zero[3] = {0, 0, 0};
+    std::vector<double> hwl(L);
+    for (int l = 0; l < L; ++l) hwl[l] = root_size / std::ldexp(1.0, l + 1);
+    // check-to-equivalent pseudo-inverse per level
+    parallel_for(L, [&](int l) {
+        if (l < 2) return;
+        std::vector<double> Kmat;
+        kernel_matrix(out.shell_unit, out.lat_unit, ns, nl, hwl[l], hwl[l], zero, gas, Kmat);
+        out.uc2e[l] = pinv_rowmajor(ns, nl, Kmat, cut);
+    });
+    // child -> parent translations (child level l, parent level l-1 >= 2)
+    for (int l = 3; l < L; ++l) {
+        out.m2m[l].assign((size_t)8 * nl * nl, 0.0);
+        parallel_for(8, [&](int c) {
+            double off[3] = {(((c >> 2) & 1) ? 1.0 : -1.0) * hwl[l], (((c >> 1) & 1) ? 1.0 : -1.0) * hwl[l],
+                             ((c & 1) ? 1.0 : -1.0) * hwl[l]};
+            std::vector<double> Kmat;  // shell of the parent vs lattice of the child
+            kernel_matrix(out.shell_unit, out.lat_unit, ns, nl, hwl[l - 1], hwl[l], off, gas, Kmat);
+            const std::vector<double> &P = out.uc2e[l - 1];
+            double *dst = &out.m2m[l][(size_t)c * nl * nl];
+            for (int i = 0; i < nl; ++i)
+                for (int k = 0; k < ns; ++k) {
+                    double pik = P[(size_t)i * ns + k];
+                    const double *kr = &Kmat[(size_t)k * nl];
+                    for (int j = 0; j < nl; ++j) dst[(size_t)i * nl + j] += pik * kr[j];
+                }
+        });
+    }
+    // well-separated translations, pure kernel values between lattices
+    for (int l = 2; l < L; ++l) {
+        out.m2l[l].assign((size_t)kNumM2L * nl * nl, 0.0);
+        parallel_for(kNumM2L, [&](int k) {
+            int dx, dy, dz;
+            m2l_offset(k, dx, dy, dz);
+            double sh[3] = {2.0 * hwl[l] * dx, 2.0 * hwl[l] * dy, 2.0 * hwl[l] * dz};
+            std::vector<double> Kmat;
+            kernel_matrix(out.lat_unit, out.lat_unit, nl, nl, hwl[l], hwl[l], sh, gas, Kmat);
+            std::copy(Kmat.begin(), Kmat.end(), out.m2l[l].begin() + (size_t)k * nl * nl);
+        });
+    }
+}
+
+// ------------------------------------------------------------------ own-cell coefficient
+
+namespace {
+
+// Exponential integral E1(x), x > 0: power series below 1, continued fraction above.
+double expint_e1(double x)
+{
+    const double euler = 0.57721566490153286061;
+    if (x < 1.0) {
+        double term = 1.0, sum = 0.0;
+        for (int k = 1; k < 60; ++k) {
+            term *= -x / k;
+            double add = -term / k;  // (-1)^(k+1) x^k / (k k!)
+            sum += add;
+            if (std::fabs(add) < 1e-18 * std::fabs(sum)) break;
+        }
+        return -euler - std::log(x) + sum;
+    }
+    // modified Lentz evaluation of e^-x / (x + 1 - 1/(x + 3 - 4/(x + 5 - ...)))
+    const double tiny = 1e-300;
+    double b = x + 1.0, c = 1.0 / tiny, d = 1.0 / b, hcf = d;
+    for (int i = 1; i < 500; ++i) {
+        double an = -(double)i * i;
+        b += 2.0;
+        d = 1.0 / (an * d + b);
+        c = b + an / c;
+        double del = c * d;
+        hcf *= del;
+        if (std::fabs(del - 1.0) < 1e-16) break;
+    }
+    return hcf * std::exp(-x);
+}
+
+// Series part of E1 without the logarithm: sum_{k>=1} (-1)^(k+1) x^k/(k k!)
+double e1_series_tail(double x)
+{
+    double term = 1.0, sum = 0.0;
+    for (int k = 1; k < 80; ++k) {
+        term *= -x / k;
+        double add = -term / k;
+        sum += add;
+        if (std::fabs(add) < 1e-18 * std::fabs(sum)) break;
+    }
+    return sum;
+}
+
+// Fraction of photons absorbed within radius R: integral_0^R g = 1 - (E1(aR) - E1(bR)) / L
+double absorbed_within(double R, const Gas &g)
+{
+    double xa = g.a * R, xb = g.b * R;
+    if (xb < 1.0) {
+        // E1(xa) - E1(xb) = ln(b/a) + tail(xa) - tail(xb); ln(b/a) = L cancels the leading 1
+        return -(e1_series_tail(xa) - e1_series_tail(xb)) / g.L;
+    }
+    return 1.0 - (expint_e1(xa) - expint_e1(xb)) / g.L;
+}
+
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            double z1 = z;
+            z = z1 - p1 / pp;
+            if (std::fabs(z - z1) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+}  // namespace
+
+// c_self(h) = integral of K over the cube of side h centred at the evaluation point.
+// Over directions the radial integral gives A(R(direction))/(4 pi); the six faces give
+// (6/4pi) * integral over the face z = h/2 of A(rho) (h/2) / rho^3, computed on the
+// eighth of the face 0 <= v <= u <= h/2 (times 8) with a Gauss-Legendre product rule.
+double cube_self_integral(const Gas &gas, double h)
+{
+    std::vector<double> x, w;
+    gauss_legendre(48, x, w);
+    const double half = 0.5 * h;
+    double acc = 0.0;
+    for (int i = 0; i < 48; ++i) {
+        double u = 0.5 * half * (x[i] + 1.0), wu = 0.5 * half * w[i];
+        for (int j = 0; j < 48; ++j) {
+            double v = 0.5 * u * (x[j] + 1.0), wv = 0.5 * u * w[j];
+            double rho = std::sqrt(u * u + v * v + half * half);
+            acc += wu * wv * absorbed_within(rho, gas) * half / (rho * rho * rho);
+        }
+    }
+    return 6.0 / (4.0 * M_PI) * 8.0 * acc;
+}
+
+}  // namespace ph
