@@ -124,6 +124,9 @@ typedef struct {
     int32_t fell_back;      /* 1 if the learned selector fell back                              */
     int64_t n_src_dropped;  /* sources removed by the learned selector                          */
     double t_ms[PH_NPHASES];/* per-phase device time (hipEvent), filled only when requested     */
+    int64_t work[8];        /* algorithmic work: near pairs (P2P), local-to-target evaluations,
+                               W-list evaluations, P2M evaluations, X-list evaluations,
+                               M2L box pairs, M2M child translations, L2L translations         */
 } ph_stats;
 
 /* Returns a static description of a status code. */
@@ -162,6 +165,18 @@ void ph_plan_destroy(ph_plan *plan);
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);
+
+/*
+ * Per-phase device time.  ms_sum (host, PH_NPHASES doubles, nullable) receives the
+ * summed hipEvent time of every call recorded since the previous query, per phase:
+ *   0 selection + compaction   1 octree        2 learned selector   3 interaction lists
+ *   4 upward pass (P2M, M2M)   5 downward pass (M2L, L2L, P2L)
+ *   6 leaf evaluation (L2P, M2P, P2P, output) or the direct sum
+ * *n_calls (nullable) the number of calls.  The sums are then reset.  record = 1
+ * turns recording on for every later ph_evaluate (events on the caller's stream,
+ * no extra synchronisation), 0 turns it off, -1 leaves it unchanged.  Synchronous.
+ */
+ph_status ph_phase_times(ph_plan *plan, int record, double *ms_sum, int64_t *n_calls);
 
 /* Waits for the stream and reports PH_ENUMERIC if any earlier call saw a bad source value. */
 ph_status ph_plan_check(ph_plan *plan, void *stream);

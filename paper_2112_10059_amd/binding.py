@@ -57,12 +57,17 @@ class PhOptions(ctypes.Structure):
 class PhStats(ctypes.Structure):
     _fields_ = [("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("n_boxes", ctypes.c_int64),
                 ("n_leaves", ctypes.c_int64), ("levels", ctypes.c_int32), ("fell_back", ctypes.c_int32),
-                ("n_src_dropped", ctypes.c_int64), ("t_ms", ctypes.c_double * NPHASES)]
+                ("n_src_dropped", ctypes.c_int64), ("t_ms", ctypes.c_double * NPHASES),
+                ("work", ctypes.c_int64 * 8)]
+
+
+WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pairs", "m2m_children",
+        "l2l_boxes")
 
 
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
-            "ph_mlp_backward", "ph_adam_step", "ph_selector_features"]
+            "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times"]
 
 _lib = None
 
@@ -114,6 +119,8 @@ def load(path: Optional[str] = None):
     lib.ph_adam_step.restype = ctypes.c_int
     lib.ph_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_int64, vp]
+    lib.ph_phase_times.restype = ctypes.c_int
+    lib.ph_phase_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ph_selector_features.restype = ctypes.c_int
     lib.ph_selector_features.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), vp]
     _lib = lib
@@ -208,8 +215,17 @@ class Plan:
         if stats:
             return out, {"n_src": st.n_src, "n_tgt": st.n_tgt, "n_boxes": st.n_boxes, "levels": st.levels,
                          "fell_back": st.fell_back, "n_src_dropped": st.n_src_dropped,
-                         "t_ms": list(st.t_ms)}
+                         "t_ms": list(st.t_ms), "work": dict(zip(WORK, list(st.work)))}
         return out
+
+    PHASES = ("select", "tree", "selector", "lists", "upward", "downward", "leaf")
+
+    def phase_times(self, record: int = -1):
+        """Summed per-phase device ms since the last query, and the number of calls."""
+        sums = (ctypes.c_double * NPHASES)()
+        n = ctypes.c_int64()
+        _check(_lib.ph_phase_times(self._h, int(record), sums, ctypes.byref(n)))
+        return {name: sums[i] for i, name in enumerate(self.PHASES)}, n.value
 
     def check(self, stream=None):
         return _check(_lib.ph_plan_check(self._h, _stream_ptr(stream)))

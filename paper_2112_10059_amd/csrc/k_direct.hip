@@ -48,6 +48,10 @@ __global__ __launch_bounds__(256) void direct_kernel(const V4<T> *__restrict__ s
                 }
             }
     }
+    if (threadIdx.x == 0) {
+        const int32_t nt_here = min(256, nt - (int32_t)(blockIdx.x * blockDim.x));
+        atomicAdd(&const_cast<CallScalars *>(sc)->work[0], (unsigned long long)nt_here * ns);
+    }
     if (act) {
         const double tot = (double)s - (double)c + (double)x.w;
         S_out[perm[t_pos[t]]] = (TO)(P * ldexp(tot, sc->scale_exp));

@@ -44,6 +44,7 @@ struct FmmArgs {
     const T *shell;     // n_sig x 3
     T *phi;
     T *u;
+    unsigned long long *work;
     int n_lam, n_sig;
     double lo0, lo1, lo2;
     double P;
@@ -103,6 +104,7 @@ __global__ void p2m_kernel(FmmArgs<T> a, int level)
         for (int sg = 0; sg < a.n_sig; ++sg) s += U[(size_t)sg * a.n_lam + li] * chk[sg];
         a.phi[(size_t)b * a.n_lam + li] = s;
     }
+    if (threadIdx.x == 0) atomicAdd(&a.work[3], (unsigned long long)sn * a.n_sig);
 }
 
 // ---------------------------------------------------------------- M2M
@@ -138,6 +140,11 @@ __global__ void m2m_kernel(FmmArgs<T> a, int level)
         }
         a.phi[(size_t)b * a.n_lam + li] = s;
     }
+    if (threadIdx.x == 0) {
+        unsigned long long k = 0;
+        for (int o = 0; o < 8; ++o) k += chs[o] >= 0 ? 1 : 0;
+        atomicAdd(&a.work[6], k);
+    }
 }
 
 // ---------------------------------------------------------------- downward: L2L + M2L + P2L
@@ -155,6 +162,7 @@ __global__ void down_kernel(FmmArgs<T> a, int level)
     const size_t nn = (size_t)nl * nl;
     // per-thread rows li = threadIdx.x + k * blockDim.x, at most 4 of them (n_lam <= 512 with 128+ threads)
     T acc[4] = {0, 0, 0, 0};
+    unsigned long long n_m2l = 0, n_p2l = 0;
     const int32_t par = a.bx.parent[b];
     if (level >= 3) {
         for (int li = threadIdx.x; li < nl; li += blockDim.x) vec[li] = a.u[(size_t)par * nl + li];
@@ -183,6 +191,7 @@ __global__ void down_kernel(FmmArgs<T> a, int level)
             for (int li = threadIdx.x; li < nl; li += blockDim.x) vec[li] = a.phi[(size_t)A * nl + li];
             __syncthreads();
             const T *M = a.m2l + ((size_t)level * kNumM2L + m2l_slot(dx, dy, dz)) * nn;
+            ++n_m2l;
             for (int k = 0; k < 4; ++k) {
                 const int li = threadIdx.x + k * blockDim.x;
                 if (li >= nl) break;
@@ -202,6 +211,7 @@ __global__ void down_kernel(FmmArgs<T> a, int level)
         for (uint32_t e = x0; e < x1; ++e) {
             const int32_t C = a.L.x[e];
             const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
+            n_p2l += (unsigned long long)sn * nl;
             for (int base = 0; base < sn; base += 128) {
                 const int m = min(128, sn - base);
                 __syncthreads();
@@ -226,6 +236,11 @@ __global__ void down_kernel(FmmArgs<T> a, int level)
         const int li = threadIdx.x + k * blockDim.x;
         if (li >= nl) break;
         a.u[(size_t)b * nl + li] = acc[k];
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&a.work[5], n_m2l);
+        if (n_p2l) atomicAdd(&a.work[4], n_p2l);
+        if (level >= 3) atomicAdd(&a.work[7], 1ull);
     }
 }
 
@@ -283,6 +298,14 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
     const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
     const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
     const int scale_exp = a.sc->scale_exp;
+    if (threadIdx.x == 0) {
+        unsigned long long near_src = 0, w_eval = 0;
+        for (uint32_t e = u0; e < u1; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+        w_eval = (unsigned long long)(w1 - w0) * nl;
+        atomicAdd(&a.work[0], near_src * tn);
+        if (has_far) atomicAdd(&a.work[1], (unsigned long long)tn * ns);
+        if (w_eval) atomicAdd(&a.work[2], w_eval * tn);
+    }
     for (int tb = 0; tb < tn; tb += blockDim.x) {
         const int t = tb + threadIdx.x;
         const bool act = t < tn;
@@ -365,6 +388,7 @@ FmmArgs<T> make_args(Plan &p)
     a.shell = (const T *)p.ops.shell_unit;
     a.phi = (T *)p.d_phi;
     a.u = (T *)p.d_u;
+    a.work = p.d_sc->work;
     a.n_lam = p.n_lam;
     a.n_sig = p.n_sig;
     a.lo0 = p.cube_lo[0];
@@ -375,26 +399,51 @@ FmmArgs<T> make_args(Plan &p)
 }
 
 template <class T>
-void run_fmm_t(Plan &p, void *S_out, hipStream_t s)
+void fmm_upward_t(Plan &p, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int D = p.max_depth;
-    const int down_threads = std::max(128, ((p.n_lam + 63) / 64) * 64);
+    const int threads = std::max(128, ((p.n_lam + 63) / 64) * 64);
     for (int l = 2; l <= D; ++l)
         p2m_kernel<T><<<(unsigned)p.level_cap[l], 128, 0, s>>>(a, l);
     for (int l = D - 1; l >= 2; --l)
-        m2m_kernel<T><<<(unsigned)p.level_cap[l], down_threads, 0, s>>>(a, l);
-    for (int l = 2; l <= D; ++l)
-        down_kernel<T><<<(unsigned)p.level_cap[l], down_threads, 0, s>>>(a, l);
+        m2m_kernel<T><<<(unsigned)p.level_cap[l], threads, 0, s>>>(a, l);
+}
+
+template <class T>
+void fmm_downward_t(Plan &p, hipStream_t s)
+{
+    FmmArgs<T> a = make_args<T>(p);
+    const int threads = std::max(128, ((p.n_lam + 63) / 64) * 64);
+    for (int l = 2; l <= p.max_depth; ++l)
+        down_kernel<T><<<(unsigned)p.level_cap[l], threads, 0, s>>>(a, l);
+}
+
+template <class T>
+void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
+{
+    FmmArgs<T> a = make_args<T>(p);
     leaf_kernel<T, T><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out);
 }
 
 }  // namespace
 
-void run_fmm(Plan &p, void *S_out, hipStream_t s)
+void fmm_upward(Plan &p, hipStream_t s)
 {
-    if (p.precision == PH_FP64) run_fmm_t<double>(p, S_out, s);
-    else run_fmm_t<float>(p, S_out, s);
+    if (p.precision == PH_FP64) fmm_upward_t<double>(p, s);
+    else fmm_upward_t<float>(p, s);
+}
+
+void fmm_downward(Plan &p, hipStream_t s)
+{
+    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s);
+    else fmm_downward_t<float>(p, s);
+}
+
+void fmm_leaf(Plan &p, void *S_out, hipStream_t s)
+{
+    if (p.precision == PH_FP64) fmm_leaf_t<double>(p, S_out, s);
+    else fmm_leaf_t<float>(p, S_out, s);
 }
 
 }  // namespace ph

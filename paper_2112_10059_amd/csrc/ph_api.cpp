@@ -188,7 +188,8 @@ void free_plan(Plan *p)
                     p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
-        for (auto &e : p->ev) (void)hipEventDestroy(e);
+        for (auto &set : p->ring)
+            for (auto &e : set) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -362,7 +363,8 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         }
     }
     alloc_workspace(p);
-    for (auto &e : p.ev) PH_HIP(hipEventCreate(&e));
+    for (auto &set : p.ring)
+        for (auto &e : set) PH_HIP(hipEventCreate(&e));
     p.events_ready = true;
 }
 
@@ -437,6 +439,22 @@ static ph_status fetch_scalars(Plan &p, hipStream_t s)
     return PH_OK;
 }
 
+// Phase boundaries recorded per call (events 0..7): 0 start, 1 selection done,
+// 2 tree done, 3 learned selector done, 4 lists done, 5 upward done,
+// 6 downward done, 7 leaf evaluation (or direct sum) done.
+static void harvest_slot(Plan &p, int slot)
+{
+    if (!p.ring_used[slot]) return;
+    PH_HIP(hipEventSynchronize(p.ring[slot][Plan::kMarks - 1]));
+    for (int k = 0; k + 1 < Plan::kMarks; ++k) {
+        float ms = 0;
+        PH_HIP(hipEventElapsedTime(&ms, p.ring[slot][k], p.ring[slot][k + 1]));
+        p.phase_sum[k] += ms;
+    }
+    p.phase_calls += 1;
+    p.ring_used[slot] = false;
+}
+
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
                       ph_stats *stats)
 {
@@ -449,34 +467,42 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     try {
         PH_HIP(hipSetDevice(p.device));
-        const bool timed = stats != nullptr;
-        int ph_i = 0;
-        auto mark = [&]() {
-            if (timed && ph_i <= PH_NPHASES) PH_HIP(hipEventRecord(p.ev[ph_i++], s));
+        const bool timed = stats != nullptr || p.recording;
+        const int slot = p.ring_pos;
+        if (timed) {
+            harvest_slot(p, slot);  // a slot from kRing calls ago: long finished
+            p.ring_pos = (p.ring_pos + 1) % Plan::kRing;
+        }
+        auto mark = [&](int k) {
+            if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], s));
         };
-        mark();
+        mark(0);
         launch_reset_scalars(p.d_sc, s);
         launch_reduce_max(I, p.precision == PH_FP64, absE, p.thr.e_rel >= 0, p.n, p.d_sc, s);
         launch_select_flags(p, I, absE, S_out, s);
         exclusive_scan_u64(p.d_flag, p.n, p.d_scan_tmp, &p.d_sc->packed_total, s);
         launch_compact(p, I, s);
-        mark();  // 1: selection + compaction
+        mark(1);
         if (p.method == PH_METHOD_DIRECT) {
+            for (int k = 2; k <= 6; ++k) mark(k);
             run_direct(p, S_out, s);
-            mark();
+            mark(7);
         } else {
             build_tree(p, s);
-            mark();  // 2: tree
-            if (p.selector == PH_SEL_LEARNED) {
-                selector_apply(p, s);
-                mark();  // 3: learned selector
-            }
+            mark(2);
+            if (p.selector == PH_SEL_LEARNED) selector_apply(p, s);
+            mark(3);
             build_lists(p, s);
-            mark();
-            run_fmm(p, S_out, s);
-            mark();
+            mark(4);
+            fmm_upward(p, s);
+            mark(5);
+            fmm_downward(p, s);
+            mark(6);
+            fmm_leaf(p, S_out, s);
+            mark(7);
         }
         PH_HIP(hipGetLastError());
+        if (timed) p.ring_used[slot] = true;
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
             fetch_scalars(p, s);
@@ -491,12 +517,33 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             stats->n_boxes = p.method == PH_METHOD_FMM ? nb : 0;
             stats->levels = levels;
             stats->n_src_dropped = p.h_sc.n_src_dropped;
-            for (int k = 0; k + 1 < ph_i && k < PH_NPHASES; ++k) {
+            for (int k = 0; k < 8; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
+            for (int k = 0; k + 1 < Plan::kMarks; ++k) {
                 float ms = 0;
-                PH_HIP(hipEventElapsedTime(&ms, p.ev[k], p.ev[k + 1]));
+                PH_HIP(hipEventElapsedTime(&ms, p.ring[slot][k], p.ring[slot][k + 1]));
                 stats->t_ms[k] = ms;
             }
         }
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_phase_times(ph_plan *plan, int record, double *ms_sum, int64_t *n_calls)
+{
+    g_last_error.clear();
+    if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    try {
+        PH_HIP(hipSetDevice(p.device));
+        for (int k = 0; k < Plan::kRing; ++k) harvest_slot(p, k);
+        if (ms_sum)
+            for (int k = 0; k < PH_NPHASES; ++k) ms_sum[k] = k + 1 < Plan::kMarks ? p.phase_sum[k] : 0.0;
+        if (n_calls) *n_calls = p.phase_calls;
+        for (double &v : p.phase_sum) v = 0.0;
+        p.phase_calls = 0;
+        if (record >= 0) p.recording = record != 0;
         return PH_OK;
     } catch (const Error &e) {
         return fail(e);

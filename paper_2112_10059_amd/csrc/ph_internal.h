@@ -52,6 +52,9 @@ struct CallScalars {
     int32_t n_src_dropped;              // learned selector
     int32_t pad;
     uint64_t packed_total;              // selected (sources | targets << 32)
+    // algorithmic work of the call (integer counters, order independent)
+    unsigned long long work[8];         // p2p pairs, l2p evals, m2p evals, p2m evals,
+                                        // p2l evals, m2l pairs, m2m children, l2l boxes
 };
 
 // Box table (structure of arrays, capacity box_cap)
@@ -147,7 +150,15 @@ struct Plan {
     int32_t *d_feat_box = nullptr;  // box of each feature row
     float *d_logit = nullptr;       // per-feature-row logits
     float *d_sel_params = nullptr;  // device copy of the selector weights
-    hipEvent_t ev[PH_NPHASES + 1] = {};
+    // per-phase timing: a ring of event sets, one set per recorded call
+    static constexpr int kRing = 32;
+    static constexpr int kMarks = 8;          // boundaries of the 7 phases
+    hipEvent_t ring[kRing][kMarks] = {};
+    bool ring_used[kRing] = {};
+    int ring_pos = 0;
+    bool recording = false;
+    double phase_sum[PH_NPHASES] = {};
+    int64_t phase_calls = 0;
     bool events_ready = false;
     size_t bytes_allocated = 0;
     size_t workspace_cap = 0;
@@ -199,7 +210,9 @@ void build_tree(Plan &p, hipStream_t s);
 void build_lists(Plan &p, hipStream_t s);
 
 // fmm (k_fmm.hip)
-void run_fmm(Plan &p, void *S_out, hipStream_t s);
+void fmm_upward(Plan &p, hipStream_t s);
+void fmm_downward(Plan &p, hipStream_t s);
+void fmm_leaf(Plan &p, void *S_out, hipStream_t s);
 
 // direct sum (k_direct.hip)
 void run_direct(Plan &p, void *S_out, hipStream_t s);
