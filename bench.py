@@ -108,24 +108,7 @@ def main():
     log(f"fp32 adaptive: {ms:.4f} ms/step, {value:.4e} targets/s; phases {phases}")
 
     # roofline of the dominant phase
-    dom = max(phases, key=lambda k: phases[k])
-    w = st["work"]
-    if dom == "leaf":
-        evals = w["p2p_pairs"] + w["l2p_evals"] + w["m2p_evals"]
-        flops = FLOPS_PER_EVAL * evals
-        roof = {"bound": "alu", "kernel": "leaf_kernel (L2P + M2P + P2P + output)",
-                "achieved": flops / (phases[dom] * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
-    elif dom == "downward":
-        nl = st.get("n_lam", None)
-        flops = 2.0 * w["m2l_pairs"] * plan_n_lam(plan) ** 2 + FLOPS_PER_EVAL * w["p2l_evals"]
-        roof = {"bound": "alu", "kernel": "down_kernel (M2L + L2L + P2L)",
-                "achieved": flops / (phases[dom] * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "alu", "kernel": dom, "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
-    if roof["achieved"] is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["phase_ms"] = phases[dom]
-    roof["traffic"] = None
+    roof = roofline(phases, st, plan_n_lam(args), wl.n)
 
     # ---------------- parity on sampled targets + CPU oracle baseline
     from oracle import photoionization, rel_l2
@@ -198,7 +181,7 @@ def main():
                    "leaf_capacity": 64, "selector": "threshold", "plan_ms": plan_ms},
         "rel_l2_sampled": err,
         "phases_ms": phases,
-        "work": w,
+        "work": st["work"],
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_fp64_fmm": plain,
@@ -210,8 +193,48 @@ def plan_q(args):
     return args.order_q or 4
 
 
-def plan_n_lam(plan):
-    return (4 if True else 0) ** 3
+def plan_n_lam(args):
+    return plan_q(args) ** 3
+
+
+def phase_work(st, n_lam, n_points):
+    """Algorithmic FP operations and HBM bytes of each phase of one call (FP32 form)."""
+    w = st["work"]
+    n_src, n_tgt = st["n_src"], st["n_tgt"]
+    ev = FLOPS_PER_EVAL
+    return {
+        # reads I and |E| (4 B each) and the permutation (4 B) per point, writes the packed
+        # flags (8 B) and scans them (8 B read + 8 B write), writes 32 B per selected source
+        # and target (position + value) plus its key (8 B)
+        "select": {"flops": 0.0, "bytes": n_points * (4 + 4 + 4 + 8 + 16) + (n_src + n_tgt) * 40.0},
+        "upward": {"flops": ev * w["p2m_evals"] + 2.0 * w["grid_p2m_madds"] + 2.0 * n_lam * n_lam * w["m2m_children"],
+                   "bytes": n_src * 16.0},
+        "downward": {"flops": 2.0 * n_lam * n_lam * (w["m2l_pairs"] + w["l2l_boxes"]) + ev * w["p2l_evals"],
+                     "bytes": 0.0},
+        # leaf evaluation reads each target (16 B), its cell index and position (8 B) and the
+        # sorted->caller map (4 B), writes S (4 B); sources of the near field are re-read from L2
+        "leaf": {"flops": ev * (w["p2p_pairs"] + w["l2p_evals"] + w["m2p_evals"]) + 2.0 * w["grid_l2p_madds"],
+                 "bytes": n_tgt * (16.0 + 8.0 + 4.0 + 4.0)},
+    }
+
+
+def roofline(phases, st, n_lam, n_points):
+    dom = max(phases, key=lambda k: phases[k])
+    pw = phase_work(st, n_lam, n_points).get(dom, {"flops": 0.0, "bytes": 0.0})
+    sec = phases[dom] * 1e-3
+    tf = pw["flops"] / sec / 1e12
+    gb = pw["bytes"] / sec / 1e9
+    kernels = {"select": "select_flags + scan + compact", "tree": "split_count/split_emit/colleagues",
+               "lists": "list_count/list_fill", "upward": "p2m_kernel + m2m_kernel",
+               "downward": "down_kernel (L2L + M2L + P2L)", "leaf": "leaf_kernel (L2P + M2P + P2P + output)"}
+    if tf / PEAK_FP32_TFLOPS >= gb / PEAK_HBM_GBS:
+        r = {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        r = {"bound": "hbm", "achieved": gb, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r.update({"kernel": kernels.get(dom, dom), "phase": dom, "avg_ms": phases[dom],
+              "algorithmic_flops": pw["flops"], "algorithmic_bytes": pw["bytes"], "traffic": None})
+    return r
 
 
 if __name__ == "__main__":

@@ -124,9 +124,11 @@ typedef struct {
     int32_t fell_back;      /* 1 if the learned selector fell back                              */
     int64_t n_src_dropped;  /* sources removed by the learned selector                          */
     double t_ms[PH_NPHASES];/* per-phase device time (hipEvent), filled only when requested     */
-    int64_t work[8];        /* algorithmic work: near pairs (P2P), local-to-target evaluations,
-                               W-list evaluations, P2M evaluations, X-list evaluations,
-                               M2L box pairs, M2M child translations, L2L translations         */
+    int64_t work[12];       /* algorithmic work: [0] near pairs (P2P), [1] local-to-target kernel
+                               evaluations, [2] W-list evaluations, [3] P2M kernel evaluations,
+                               [4] X-list evaluations, [5] M2L box pairs, [6] M2M child
+                               translations, [7] L2L translations, [8] grid local-to-target
+                               multiply-adds, [9] grid P2M multiply-adds, [10-11] reserved      */
 } ph_stats;
 
 /* Returns a static description of a status code. */

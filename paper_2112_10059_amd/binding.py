@@ -58,11 +58,11 @@ class PhStats(ctypes.Structure):
     _fields_ = [("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("n_boxes", ctypes.c_int64),
                 ("n_leaves", ctypes.c_int64), ("levels", ctypes.c_int32), ("fell_back", ctypes.c_int32),
                 ("n_src_dropped", ctypes.c_int64), ("t_ms", ctypes.c_double * NPHASES),
-                ("work", ctypes.c_int64 * 8)]
+                ("work", ctypes.c_int64 * 12)]
 
 
 WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pairs", "m2m_children",
-        "l2l_boxes")
+        "l2l_boxes", "grid_l2p_madds", "grid_p2m_madds", "reserved10", "reserved11")
 
 
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",

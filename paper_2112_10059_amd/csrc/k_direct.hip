@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const V4<T> *__restrict__ s
                                                      const int32_t *__restrict__ t_pos,
                                                      const int32_t *__restrict__ perm,
                                                      const CallScalars *__restrict__ sc, KParams<T> kp, double P,
-                                                     TO *__restrict__ S_out)
+                                                     TO *__restrict__ S_out, unsigned long long *work)
 {
     __shared__ V4<T> tile[256];
     const int32_t ns = sc->n_src, nt = sc->n_tgt;
@@ -48,9 +48,9 @@ __global__ __launch_bounds__(256) void direct_kernel(const V4<T> *__restrict__ s
                 }
             }
     }
-    if (threadIdx.x == 0) {
+    if (work && threadIdx.x == 0) {
         const int32_t nt_here = min(256, nt - (int32_t)(blockIdx.x * blockDim.x));
-        atomicAdd(&const_cast<CallScalars *>(sc)->work[0], (unsigned long long)nt_here * ns);
+        atomicAdd(&work[0], (unsigned long long)nt_here * ns);
     }
     if (act) {
         const double tot = (double)s - (double)c + (double)x.w;
@@ -67,11 +67,13 @@ void run_direct(Plan &p, void *S_out, hipStream_t s)
     if (p.precision == PH_FP64)
         direct_kernel<double, double><<<g, 256, 0, s>>>((const double4 *)p.d_s_dat, (const double4 *)p.d_t_dat,
                                                         p.d_t_pos, p.d_perm, p.d_sc, make_kparams<double>(p.gas),
-                                                        p.gas.P, (double *)S_out);
+                                                        p.gas.P, (double *)S_out,
+                                                        p.count_work ? p.d_sc->work : nullptr);
     else
         direct_kernel<float, float><<<g, 256, 0, s>>>((const float4 *)p.d_s_dat, (const float4 *)p.d_t_dat, p.d_t_pos,
                                                       p.d_perm, p.d_sc, make_kparams<float>(p.gas), p.gas.P,
-                                                      (float *)S_out);
+                                                      (float *)S_out,
+                                                      p.count_work ? p.d_sc->work : nullptr);
 }
 
 }  // namespace ph

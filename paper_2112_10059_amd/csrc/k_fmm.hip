@@ -15,48 +15,11 @@
 //           + sum_{U(B)} K(x, y) q (Kahan in FP32) + own-cell term, combined in FP64.
 #include <hip/hip_runtime.h>
 
-#include "k_common.h"
+#include "k_fmm_args.h"
 
 namespace ph {
 
 namespace {
-
-template <class T>
-using V4 = typename Vec4T<T>::type;
-
-template <class T>
-struct FmmArgs {
-    BoxArrays bx;
-    Lists L;
-    LevelTable lt;
-    KParams<T> kp;
-    const CallScalars *sc;
-    const V4<T> *s_dat;
-    const V4<T> *t_dat;
-    const int32_t *t_pos;
-    const int32_t *perm;
-    const T *uc2e_rm;   // levels x n_lam x n_sig
-    const T *uc2e_cm;   // levels x n_sig x n_lam
-    const T *m2m;       // levels x 8 x n_lam^2 (column-major)
-    const T *l2l;
-    const T *m2l;       // levels x 316 x n_lam^2 (column-major)
-    const T *lat;       // n_lam x 3
-    const T *shell;     // n_sig x 3
-    T *phi;
-    T *u;
-    unsigned long long *work;
-    int n_lam, n_sig;
-    double lo0, lo1, lo2;
-    double P;
-};
-
-template <class T>
-__device__ __forceinline__ void box_centre(const FmmArgs<T> &a, int32_t b, double hw, T &cx, T &cy, T &cz)
-{
-    cx = (T)(a.lo0 + (2.0 * a.bx.ax[b] + 1.0) * hw);
-    cy = (T)(a.lo1 + (2.0 * a.bx.ay[b] + 1.0) * hw);
-    cz = (T)(a.lo2 + (2.0 * a.bx.az[b] + 1.0) * hw);
-}
 
 // ---------------------------------------------------------------- P2M
 
@@ -69,11 +32,40 @@ __global__ void p2m_kernel(FmmArgs<T> a, int level)
     if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.s_cnt[b] == 0) return;
     __shared__ V4<T> tile[128];
     __shared__ T chk[kMaxShell];
+    __shared__ int32_t rloc[128];
+    const int32_t sf = a.bx.s_first[b], sn = a.bx.s_cnt[b];
+    const int gm = a.grid_m[level];
+    if (gm > 0) {
+        // grid box: phi = G q over the box's cells (G = uc2e K(shell, cells))
+        const T *G = a.grid_gt + a.grid_off[level];
+        T accg[4] = {0, 0, 0, 0};
+        for (int base = 0; base < sn; base += 128) {
+            const int m = min(128, sn - base);
+            __syncthreads();
+            if ((int)threadIdx.x < m) {
+                tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
+                rloc[threadIdx.x] = local_cell(a, a.s_cell[sf + base + threadIdx.x], b, gm);
+            }
+            __syncthreads();
+            for (int k = 0; k < 4; ++k) {
+                const int li = threadIdx.x + k * blockDim.x;
+                if (li >= a.n_lam) break;
+                T sacc = 0;
+                for (int j = 0; j < m; ++j) sacc += G[(size_t)rloc[j] * a.n_lam + li] * tile[j].w;
+                accg[k] += sacc;
+            }
+        }
+        for (int k = 0; k < 4; ++k) {
+            const int li = threadIdx.x + k * blockDim.x;
+            if (li < a.n_lam) a.phi[(size_t)b * a.n_lam + li] = accg[k];
+        }
+        if (a.work && threadIdx.x == 0) atomicAdd(&a.work[9], (unsigned long long)sn * a.n_lam);
+        return;
+    }
     const double hw = a.lt.hw[level];
     T cx, cy, cz;
     box_centre(a, b, hw, cx, cy, cz);
     const T h = (T)hw;
-    const int32_t sf = a.bx.s_first[b], sn = a.bx.s_cnt[b];
     T acc[4] = {0, 0, 0, 0};  // n_sig <= 4 * 128 check points per thread slot
     for (int base = 0; base < sn; base += 128) {
         const int m = min(128, sn - base);
@@ -104,7 +96,7 @@ __global__ void p2m_kernel(FmmArgs<T> a, int level)
         for (int sg = 0; sg < a.n_sig; ++sg) s += U[(size_t)sg * a.n_lam + li] * chk[sg];
         a.phi[(size_t)b * a.n_lam + li] = s;
     }
-    if (threadIdx.x == 0) atomicAdd(&a.work[3], (unsigned long long)sn * a.n_sig);
+    if (a.work && threadIdx.x == 0) atomicAdd(&a.work[3], (unsigned long long)sn * a.n_sig);
 }
 
 // ---------------------------------------------------------------- M2M
@@ -140,107 +132,10 @@ __global__ void m2m_kernel(FmmArgs<T> a, int level)
         }
         a.phi[(size_t)b * a.n_lam + li] = s;
     }
-    if (threadIdx.x == 0) {
+    if (a.work && threadIdx.x == 0) {
         unsigned long long k = 0;
         for (int o = 0; o < 8; ++o) k += chs[o] >= 0 ? 1 : 0;
         atomicAdd(&a.work[6], k);
-    }
-}
-
-// ---------------------------------------------------------------- downward: L2L + M2L + P2L
-
-template <class T>
-__global__ void down_kernel(FmmArgs<T> a, int level)
-{
-    const int32_t i = blockIdx.x;
-    if (i >= a.sc->lvl_count[level]) return;
-    const int32_t b = a.lt.base[level] + i;
-    if (a.bx.t_cnt[b] == 0) return;
-    __shared__ T vec[kMaxLattice];
-    __shared__ V4<T> tile[128];
-    const int nl = a.n_lam;
-    const size_t nn = (size_t)nl * nl;
-    // per-thread rows li = threadIdx.x + k * blockDim.x, at most 4 of them (n_lam <= 512 with 128+ threads)
-    T acc[4] = {0, 0, 0, 0};
-    unsigned long long n_m2l = 0, n_p2l = 0;
-    const int32_t par = a.bx.parent[b];
-    if (level >= 3) {
-        for (int li = threadIdx.x; li < nl; li += blockDim.x) vec[li] = a.u[(size_t)par * nl + li];
-        __syncthreads();
-        const int oct = ((a.bx.ax[b] & 1) << 2) | ((a.bx.ay[b] & 1) << 1) | (a.bx.az[b] & 1);
-        const T *M = a.l2l + ((size_t)level * 8 + oct) * nn;
-        for (int k = 0; k < 4; ++k) {
-            const int li = threadIdx.x + k * blockDim.x;
-            if (li >= nl) break;
-            T s = 0;
-            for (int j = 0; j < nl; ++j) s += M[(size_t)j * nl + li] * vec[j];
-            acc[k] = s;
-        }
-    }
-    // V list: children of the parent's colleagues that are not adjacent to B
-    const int bx0 = a.bx.ax[b], by0 = a.bx.ay[b], bz0 = a.bx.az[b];
-    for (int d = 0; d < 27; ++d) {
-        const int32_t P = a.bx.coll[(size_t)par * 27 + d];
-        if (P < 0) continue;
-        for (int o = 0; o < 8; ++o) {
-            const int32_t A = a.bx.child[(size_t)P * 8 + o];
-            if (A < 0 || a.bx.s_cnt[A] == 0) continue;
-            const int dx = a.bx.ax[A] - bx0, dy = a.bx.ay[A] - by0, dz = a.bx.az[A] - bz0;
-            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
-            __syncthreads();
-            for (int li = threadIdx.x; li < nl; li += blockDim.x) vec[li] = a.phi[(size_t)A * nl + li];
-            __syncthreads();
-            const T *M = a.m2l + ((size_t)level * kNumM2L + m2l_slot(dx, dy, dz)) * nn;
-            ++n_m2l;
-            for (int k = 0; k < 4; ++k) {
-                const int li = threadIdx.x + k * blockDim.x;
-                if (li >= nl) break;
-                T s = 0;
-                for (int j = 0; j < nl; ++j) s += M[(size_t)j * nl + li] * vec[j];
-                acc[k] += s;
-            }
-        }
-    }
-    // X list: sources of coarser leaves straight onto the check points
-    const uint32_t x0 = a.L.x_off[b], x1 = a.L.x_off[b + 1];
-    if (x1 > x0) {
-        const double hw = a.lt.hw[level];
-        T cx, cy, cz;
-        box_centre(a, b, hw, cx, cy, cz);
-        const T h = (T)hw;
-        for (uint32_t e = x0; e < x1; ++e) {
-            const int32_t C = a.L.x[e];
-            const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
-            n_p2l += (unsigned long long)sn * nl;
-            for (int base = 0; base < sn; base += 128) {
-                const int m = min(128, sn - base);
-                __syncthreads();
-                if ((int)threadIdx.x < m) tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
-                __syncthreads();
-                for (int k = 0; k < 4; ++k) {
-                    const int li = threadIdx.x + k * blockDim.x;
-                    if (li >= nl) break;
-                    const T px = cx + h * a.lat[3 * li], py = cy + h * a.lat[3 * li + 1], pz = cz + h * a.lat[3 * li + 2];
-                    T s = 0;
-                    for (int j = 0; j < m; ++j) {
-                        const V4<T> y = tile[j];
-                        const T ddx = px - y.x, ddy = py - y.y, ddz = pz - y.z;
-                        s += kernel_eval<true>(ddx * ddx + ddy * ddy + ddz * ddz, a.kp) * y.w;
-                    }
-                    acc[k] += s;
-                }
-            }
-        }
-    }
-    for (int k = 0; k < 4; ++k) {
-        const int li = threadIdx.x + k * blockDim.x;
-        if (li >= nl) break;
-        a.u[(size_t)b * nl + li] = acc[k];
-    }
-    if (threadIdx.x == 0) {
-        atomicAdd(&a.work[5], n_m2l);
-        if (n_p2l) atomicAdd(&a.work[4], n_p2l);
-        if (level >= 3) atomicAdd(&a.work[7], 1ull);
     }
 }
 
@@ -275,10 +170,12 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
     if (!box_live(a.lt, a.sc, b, level)) return;
     if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.t_cnt[b] == 0) return;
     __shared__ T uvec[kMaxLattice];
-    __shared__ T psi[kMaxShell];
+    __shared__ T wphi[kMaxLattice];
+    __shared__ V4<T> shp[kMaxShell];  // shell point position and its intensity psi
     __shared__ V4<T> tile[64];
     const int nl = a.n_lam, ns = a.n_sig;
     const bool has_far = level >= 2;
+    const int gm = has_far ? a.grid_m[level] : 0;
     const double hw = a.lt.hw[level];
     T cx, cy, cz;
     box_centre(a, b, hw, cx, cy, cz);
@@ -286,24 +183,32 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
     if (has_far) {
         for (int li = threadIdx.x; li < nl; li += blockDim.x) uvec[li] = a.u[(size_t)b * nl + li];
         __syncthreads();
-        const T *U = a.uc2e_rm + (size_t)level * nl * ns;
-        for (int sg = threadIdx.x; sg < ns; sg += blockDim.x) {
-            T s = 0;
-            for (int li = 0; li < nl; ++li) s += U[(size_t)li * ns + sg] * uvec[li];
-            psi[sg] = s;
+        if (gm == 0) {
+            const T *U = a.uc2e_rm + (size_t)level * nl * ns;
+            for (int sg = threadIdx.x; sg < ns; sg += blockDim.x) {
+                T s = 0;
+                for (int li = 0; li < nl; ++li) s += U[(size_t)li * ns + sg] * uvec[li];
+                V4<T> q;
+                q.x = cx + h * a.shell[3 * sg];
+                q.y = cy + h * a.shell[3 * sg + 1];
+                q.z = cz + h * a.shell[3 * sg + 2];
+                q.w = s;
+                shp[sg] = q;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
     const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
     const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
     const int scale_exp = a.sc->scale_exp;
-    if (threadIdx.x == 0) {
+    if (a.work && threadIdx.x == 0) {
         unsigned long long near_src = 0, w_eval = 0;
         for (uint32_t e = u0; e < u1; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
         w_eval = (unsigned long long)(w1 - w0) * nl;
         atomicAdd(&a.work[0], near_src * tn);
-        if (has_far) atomicAdd(&a.work[1], (unsigned long long)tn * ns);
+        if (has_far && gm == 0) atomicAdd(&a.work[1], (unsigned long long)tn * ns);
+        if (has_far && gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
         if (w_eval) atomicAdd(&a.work[2], w_eval * tn);
     }
     for (int tb = 0; tb < tn; tb += blockDim.x) {
@@ -314,11 +219,17 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
         else x.x = x.y = x.z = x.w = T(0);
         T far = 0;
         if (has_far && act) {
-            for (int sg = 0; sg < ns; ++sg) {
-                const T dx = x.x - (cx + h * a.shell[3 * sg]);
-                const T dy = x.y - (cy + h * a.shell[3 * sg + 1]);
-                const T dz = x.z - (cz + h * a.shell[3 * sg + 2]);
-                far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * psi[sg];
+            if (gm > 0) {
+                const T *G = a.grid_g + a.grid_off[level];
+                const int R = gm * gm * gm;
+                const int r = local_cell(a, a.t_cell[tf + t], b, gm);
+                for (int li = 0; li < nl; ++li) far += G[(size_t)li * R + r] * uvec[li];
+            } else {
+                for (int sg = 0; sg < ns; ++sg) {
+                    const V4<T> q = shp[sg];
+                    const T dx = x.x - q.x, dy = x.y - q.y, dz = x.z - q.z;
+                    far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * q.w;
+                }
             }
         }
         // W list: artificial sources of smaller non-adjacent boxes
@@ -330,14 +241,14 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
             box_centre(a, A, hwa, ax, ay, az);
             const T ha = (T)hwa;
             __syncthreads();
-            for (int li = threadIdx.x; li < nl; li += blockDim.x) uvec[li] = a.phi[(size_t)A * nl + li];
+            for (int li = threadIdx.x; li < nl; li += blockDim.x) wphi[li] = a.phi[(size_t)A * nl + li];
             __syncthreads();
             if (act)
                 for (int li = 0; li < nl; ++li) {
                     const T dx = x.x - (ax + ha * a.lat[3 * li]);
                     const T dy = x.y - (ay + ha * a.lat[3 * li + 1]);
                     const T dz = x.z - (az + ha * a.lat[3 * li + 2]);
-                    far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * uvec[li];
+                    far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * wphi[li];
                 }
         }
         // U list: exact near field
@@ -367,38 +278,6 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
 }
 
 template <class T>
-FmmArgs<T> make_args(Plan &p)
-{
-    FmmArgs<T> a;
-    a.bx = p.box;
-    a.L = p.lists;
-    a.lt = make_level_table(p);
-    a.kp = make_kparams<T>(p.gas);
-    a.sc = p.d_sc;
-    a.s_dat = (const V4<T> *)p.d_s_dat;
-    a.t_dat = (const V4<T> *)p.d_t_dat;
-    a.t_pos = p.d_t_pos;
-    a.perm = p.d_perm;
-    a.uc2e_rm = (const T *)p.ops.uc2e_rm;
-    a.uc2e_cm = (const T *)p.ops.uc2e_cm;
-    a.m2m = (const T *)p.ops.m2m;
-    a.l2l = (const T *)p.ops.l2l;
-    a.m2l = (const T *)p.ops.m2l;
-    a.lat = (const T *)p.ops.lat_unit;
-    a.shell = (const T *)p.ops.shell_unit;
-    a.phi = (T *)p.d_phi;
-    a.u = (T *)p.d_u;
-    a.work = p.d_sc->work;
-    a.n_lam = p.n_lam;
-    a.n_sig = p.n_sig;
-    a.lo0 = p.cube_lo[0];
-    a.lo1 = p.cube_lo[1];
-    a.lo2 = p.cube_lo[2];
-    a.P = p.gas.P;
-    return a;
-}
-
-template <class T>
 void fmm_upward_t(Plan &p, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
@@ -408,15 +287,6 @@ void fmm_upward_t(Plan &p, hipStream_t s)
         p2m_kernel<T><<<(unsigned)p.level_cap[l], 128, 0, s>>>(a, l);
     for (int l = D - 1; l >= 2; --l)
         m2m_kernel<T><<<(unsigned)p.level_cap[l], threads, 0, s>>>(a, l);
-}
-
-template <class T>
-void fmm_downward_t(Plan &p, hipStream_t s)
-{
-    FmmArgs<T> a = make_args<T>(p);
-    const int threads = std::max(128, ((p.n_lam + 63) / 64) * 64);
-    for (int l = 2; l <= p.max_depth; ++l)
-        down_kernel<T><<<(unsigned)p.level_cap[l], threads, 0, s>>>(a, l);
 }
 
 template <class T>
@@ -432,12 +302,6 @@ void fmm_upward(Plan &p, hipStream_t s)
 {
     if (p.precision == PH_FP64) fmm_upward_t<double>(p, s);
     else fmm_upward_t<float>(p, s);
-}
-
-void fmm_downward(Plan &p, hipStream_t s)
-{
-    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s);
-    else fmm_downward_t<float>(p, s);
 }
 
 void fmm_leaf(Plan &p, void *S_out, hipStream_t s)

@@ -1,0 +1,103 @@
+// Argument block shared by the FMM kernels (upward pass, translations, leaf evaluation).
+#pragma once
+
+#include "k_common.h"
+
+namespace ph {
+
+template <class T>
+using V4 = typename Vec4T<T>::type;
+
+template <class T>
+struct FmmArgs {
+    BoxArrays bx;
+    Lists L;
+    LevelTable lt;
+    KParams<T> kp;
+    const CallScalars *sc;
+    const V4<T> *s_dat;
+    const V4<T> *t_dat;
+    const int32_t *t_pos;
+    const int32_t *perm;
+    const T *uc2e_rm;   // levels x n_lam x n_sig
+    const T *uc2e_cm;   // levels x n_sig x n_lam
+    const T *m2m;       // levels x 8 x n_lam^2 (column-major)
+    const T *l2l;
+    const T *m2l;       // levels x (316 n_lam) x k_pad (row-major GEMM operand)
+    const T *lat;       // n_lam x 3
+    const T *shell;     // n_sig x 3
+    T *phi;
+    T *u;
+    unsigned long long *work;
+    // uniform-grid lattice operators (grid_g [lambda][r], grid_gt [r][lambda] per level)
+    const T *grid_g;
+    const T *grid_gt;
+    const int32_t *s_cell;
+    const int32_t *t_cell;
+    int grid_m[kMaxDepth + 2];
+    int64_t grid_off[kMaxDepth + 2];
+    int n_lam, n_sig;
+    double lo0, lo1, lo2;
+    double P;
+};
+
+template <class T>
+__device__ __forceinline__ void box_centre(const FmmArgs<T> &a, int32_t b, double hw, T &cx, T &cy, T &cz)
+{
+    cx = (T)(a.lo0 + (2.0 * a.bx.ax[b] + 1.0) * hw);
+    cy = (T)(a.lo1 + (2.0 * a.bx.ay[b] + 1.0) * hw);
+    cz = (T)(a.lo2 + (2.0 * a.bx.az[b] + 1.0) * hw);
+}
+
+// cell index of a grid point inside its level-l box of m^3 cells
+template <class T>
+__device__ __forceinline__ int local_cell(const FmmArgs<T> &a, int32_t cell, int32_t b, int m)
+{
+    const int i = (cell & 1023) - a.bx.ax[b] * m;
+    const int j = ((cell >> 10) & 1023) - a.bx.ay[b] * m;
+    const int k = ((cell >> 20) & 1023) - a.bx.az[b] * m;
+    return (i * m + j) * m + k;
+}
+
+template <class T>
+inline FmmArgs<T> make_args(Plan &p)
+{
+    FmmArgs<T> a;
+    a.bx = p.box;
+    a.L = p.lists;
+    a.lt = make_level_table(p);
+    a.kp = make_kparams<T>(p.gas);
+    a.sc = p.d_sc;
+    a.s_dat = (const V4<T> *)p.d_s_dat;
+    a.t_dat = (const V4<T> *)p.d_t_dat;
+    a.t_pos = p.d_t_pos;
+    a.perm = p.d_perm;
+    a.uc2e_rm = (const T *)p.ops.uc2e_rm;
+    a.uc2e_cm = (const T *)p.ops.uc2e_cm;
+    a.m2m = (const T *)p.ops.m2m;
+    a.l2l = (const T *)p.ops.l2l;
+    a.m2l = (const T *)p.ops.m2l;
+    a.lat = (const T *)p.ops.lat_unit;
+    a.shell = (const T *)p.ops.shell_unit;
+    a.phi = (T *)p.d_phi;
+    a.u = (T *)p.d_u;
+    a.work = p.count_work ? p.d_sc->work : nullptr;
+    a.grid_g = (const T *)p.ops.grid_g;
+    a.grid_gt = (const T *)p.ops.grid_gt;
+    a.s_cell = p.d_s_cell;
+    a.t_cell = p.d_t_cell;
+    for (int l = 0; l < kMaxDepth + 2; ++l) {
+        a.grid_m[l] = p.grid_mode ? p.grid_m[l] : 0;
+        a.grid_off[l] = p.grid_off[l];
+    }
+    a.n_lam = p.n_lam;
+    a.n_sig = p.n_sig;
+    a.lo0 = p.cube_lo[0];
+    a.lo1 = p.cube_lo[1];
+    a.lo2 = p.cube_lo[2];
+    a.P = p.gas.P;
+    return a;
+}
+
+
+}  // namespace ph

@@ -26,10 +26,11 @@ __device__ __forceinline__ bool bad_value(T v)
     return !(v >= T(0)) || isinf(v);
 }
 
-// max over non-negative finite values via the ordered integer image of the bits
+// Maxima of I and |E|: each block reduces its grid-stride share into partial[],
+// one block then reduces the partials (no contended atomics).
 template <class T>
 __global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restrict__ E, int64_t n,
-                                  CallScalars *sc)
+                                  double *__restrict__ partial, CallScalars *sc)
 {
     __shared__ double smI[256];
     __shared__ float smE[256];
@@ -57,11 +58,32 @@ __global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restri
     }
     if (bad) atomicOr(&sc->err, 1);
     if (threadIdx.x == 0) {
-        // non-negative doubles order like their bit patterns as unsigned integers
-        atomicMax(reinterpret_cast<unsigned long long *>(&sc->imax),
-                  (unsigned long long)__double_as_longlong(smI[0]));
-        atomicMax(reinterpret_cast<unsigned long long *>(&sc->emax),
-                  (unsigned long long)__double_as_longlong((double)smE[0]));
+        partial[2 * blockIdx.x] = smI[0];
+        partial[2 * blockIdx.x + 1] = (double)smE[0];
+    }
+}
+
+__global__ void reduce_max_final_kernel(const double *__restrict__ partial, int nb, CallScalars *sc)
+{
+    __shared__ double a[256], b[256];
+    double mi = 0.0, me = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        mi = fmax(mi, partial[2 * i]);
+        me = fmax(me, partial[2 * i + 1]);
+    }
+    a[threadIdx.x] = mi;
+    b[threadIdx.x] = me;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            a[threadIdx.x] = fmax(a[threadIdx.x], a[threadIdx.x + o]);
+            b[threadIdx.x] = fmax(b[threadIdx.x], b[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sc->imax = a[0];
+        sc->emax = b[0];
     }
 }
 
@@ -112,7 +134,9 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
                                CallScalars *__restrict__ sc, const uint64_t *__restrict__ scanned,
                                int32_t *__restrict__ s_pos, int32_t *__restrict__ t_pos,
                                uint64_t *__restrict__ s_key, uint64_t *__restrict__ t_key,
-                               typename Vec4<T>::type *__restrict__ s_dat, typename Vec4<T>::type *__restrict__ t_dat)
+                               typename Vec4<T>::type *__restrict__ s_dat, typename Vec4<T>::type *__restrict__ t_dat,
+                               const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell,
+                               int32_t *__restrict__ t_cell)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double imax = sc->imax;
@@ -149,6 +173,7 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
         d.z = (T)z;
         d.w = (T)(wk * Iv);
         s_dat[sp_lo] = d;
+        if (cell) s_cell[sp_lo] = cell[k];
     }
     if (is_tgt) {
         t_pos[sp_hi] = (int32_t)k;
@@ -159,6 +184,7 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
         d.z = (T)z;
         d.w = is_src ? (T)(c_self * Iv) : T(0);
         t_dat[sp_hi] = d;
+        if (cell) t_cell[sp_hi] = cell[k];
     }
 }
 
@@ -167,13 +193,15 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
 void launch_reset_scalars(CallScalars *sc, hipStream_t s) { reset_scalars_kernel<<<1, 256, 0, s>>>(sc); }
 
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n, CallScalars *sc,
-                       hipStream_t s)
+                       void *tmp, hipStream_t s)
 {
-    int blocks = (int)std::min<int64_t>(2048, (n + 255) / 256);
+    int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    double *partial = reinterpret_cast<double *>(tmp);
     if (fp64)
-        reduce_max_kernel<double><<<blocks, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, n, sc);
+        reduce_max_kernel<double><<<blocks, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, n, partial, sc);
     else
-        reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, n, sc);
+        reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, n, partial, sc);
+    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, blocks, sc);
 }
 
 static SelectParams params_of(const Plan &p)
@@ -199,11 +227,13 @@ void launch_compact(const Plan &p, const void *I, hipStream_t s)
     if (p.precision == PH_FP64)
         compact_kernel<double, double><<<g, 256, 0, s>>>(
             (const double *)I, p.d_perm, p.d_key, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_flag,
-            p.d_s_pos, p.d_t_pos, p.d_s_key, p.d_t_key, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat);
+            p.d_s_pos, p.d_t_pos, p.d_s_key, p.d_t_key, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
+            p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
     else
         compact_kernel<float, float><<<g, 256, 0, s>>>(
             (const float *)I, p.d_perm, p.d_key, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_flag,
-            p.d_s_pos, p.d_t_pos, p.d_s_key, p.d_t_key, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat);
+            p.d_s_pos, p.d_t_pos, p.d_s_key, p.d_t_key, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
+            p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
 }
 
 }  // namespace ph

@@ -69,7 +69,10 @@ __global__ void init_root_kernel(BoxArrays bx, LevelInfo li, CallScalars *sc)
         bx.t_cnt[b] = sc->n_tgt;
         bx.parent[b] = -1;
         bx.flags[b] = 0;
+        bx.src_rank[b] = sc->n_src > 0 ? 0 : -1;
+        bx.src_box[b] = b;
         sc->lvl_count[0] = 1;
+        sc->lvl_src[0] = sc->n_src > 0 ? 1 : 0;
         for (int l = 0; l <= li.depth + 1 && l < kMaxDepth + 3; ++l) sc->lvl_start[l] = li.base[l];
     }
     if (threadIdx.x < 27) bx.coll[(size_t)li.base[0] * 27 + threadIdx.x] = (threadIdx.x == 13) ? li.base[0] : -1;
@@ -104,27 +107,35 @@ __global__ void split_count_kernel(BoxArrays bx, LevelInfo li, int level, int le
         sb[o] = lower_bound_prefix(s_key, sb[o - 1], sf + sn, shift, pre | (uint64_t)o);
         tb[o] = lower_bound_prefix(t_key, tb[o - 1], tf + tn, shift, pre | (uint64_t)o);
     }
-    uint32_t cnt = 0;
+    uint64_t cnt = 0, cnt_s = 0;
     for (int o = 0; o < 8; ++o) {
         int4 r = make_int4(sb[o], sb[o + 1] - sb[o], tb[o], tb[o + 1] - tb[o]);
         bx.child_tmp[(size_t)i * 8 + o] = r;
         cnt += (r.y + r.w) > 0 ? 1u : 0u;
+        cnt_s += r.y > 0 ? 1u : 0u;
     }
-    bx.child_cnt[i] = cnt;
+    bx.child_cnt[i] = cnt | (cnt_s << 32);
 }
 
-// child_cnt now holds exclusive offsets; lvl_count[level+1] the total.
-__global__ void split_emit_kernel(BoxArrays bx, LevelInfo li, int level, const CallScalars *__restrict__ sc)
+// child_cnt now holds packed exclusive offsets; lvl_count/lvl_src[level+1] the totals.
+__global__ void split_emit_kernel(BoxArrays bx, LevelInfo li, int level, CallScalars *__restrict__ sc)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= sc->lvl_count[level]) return;
+    if (i == 0) {
+        const uint64_t v = sc->lvl_pack[level + 1];
+        sc->lvl_count[level + 1] = (int32_t)(v & 0xffffffffu);
+        sc->lvl_src[level + 1] = (int32_t)(v >> 32);
+    }
     const int32_t b = li.base[level] + i;
     int32_t *ch = bx.child + (size_t)b * 8;
     if (bx.flags[b] & kBoxLeaf) {
         for (int o = 0; o < 8; ++o) ch[o] = -1;
         return;
     }
-    int32_t c = li.base[level + 1] + (int32_t)bx.child_cnt[i];
+    const uint64_t off = bx.child_cnt[i];
+    int32_t c = li.base[level + 1] + (int32_t)(off & 0xffffffffu);
+    int32_t rs = (int32_t)(off >> 32);  // next source rank at level + 1
     const int ax = bx.ax[b], ay = bx.ay[b], az = bx.az[b];
     for (int o = 0; o < 8; ++o) {
         int4 r = bx.child_tmp[(size_t)i * 8 + o];
@@ -143,6 +154,13 @@ __global__ void split_emit_kernel(BoxArrays bx, LevelInfo li, int level, const C
         bx.t_cnt[c] = r.w;
         bx.parent[c] = b;
         bx.flags[c] = 0;
+        if (r.y > 0) {
+            bx.src_rank[c] = rs;
+            bx.src_box[li.base[level + 1] + rs] = c;
+            ++rs;
+        } else {
+            bx.src_rank[c] = -1;
+        }
         ++c;
     }
 }
@@ -321,8 +339,7 @@ void build_tree(Plan &p, hipStream_t s)
         const int cap = (int)p.level_cap[l];
         const unsigned g = (unsigned)((cap + 255) / 256);
         split_count_kernel<<<g, 256, 0, s>>>(p.box, li, l, p.leaf_cap, 1, p.d_sc, p.d_s_key, p.d_t_key);
-        exclusive_scan_u32(p.box.child_cnt, cap, p.d_scan_tmp, reinterpret_cast<uint32_t *>(&p.d_sc->lvl_count[l + 1]),
-                           s);
+        exclusive_scan_u64(p.box.child_cnt, cap, p.d_scan_tmp, &p.d_sc->lvl_pack[l + 1], s);
         split_emit_kernel<<<g, 256, 0, s>>>(p.box, li, l, p.d_sc);
         const unsigned g1 = (unsigned)((p.level_cap[l + 1] + 255) / 256);
         colleagues_kernel<<<g1, 256, 0, s>>>(p.box, li, l + 1, p.d_sc);

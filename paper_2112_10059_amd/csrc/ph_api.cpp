@@ -1,6 +1,7 @@
 // C ABI entry points of libph: validation, plan construction, evaluation sequencing.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -127,7 +128,7 @@ void alloc_workspace(Plan &p)
     const size_t rs = p.precision == PH_FP64 ? sizeof(double) : sizeof(float);
     p.d_sc = (CallScalars *)dev_alloc(p, sizeof(CallScalars));
     p.d_flag = (uint64_t *)dev_alloc(p, (size_t)n * sizeof(uint64_t));
-    p.scan_tmp_bytes = std::max(scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4));
+    p.scan_tmp_bytes = std::max({scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4), (size_t)16384});
     p.d_scan_tmp = dev_alloc(p, p.scan_tmp_bytes);
     p.d_s_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
     p.d_t_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
@@ -135,6 +136,10 @@ void alloc_workspace(Plan &p)
     p.d_t_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
     p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);
     p.d_t_dat = dev_alloc(p, (size_t)n * 4 * rs);
+    if (p.grid_mode) {
+        p.d_s_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
+        p.d_t_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    }
     const int64_t B = p.box_cap;
     BoxArrays &b = p.box;
     b.level = (int32_t *)dev_alloc(p, B * 4);
@@ -150,7 +155,9 @@ void alloc_workspace(Plan &p)
     b.child = (int32_t *)dev_alloc(p, B * 8 * 4);
     b.coll = (int32_t *)dev_alloc(p, B * 27 * 4);
     b.child_tmp = (int4 *)dev_alloc(p, (size_t)p.widest_level * 8 * sizeof(int4));
-    b.child_cnt = (uint32_t *)dev_alloc(p, (size_t)(p.widest_level + 1) * 4);
+    b.child_cnt = (uint64_t *)dev_alloc(p, (size_t)(p.widest_level + 1) * 8);
+    b.src_rank = (int32_t *)dev_alloc(p, B * 4);
+    b.src_box = (int32_t *)dev_alloc(p, B * 4);
     Lists &L = p.lists;
     L.u_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
     L.w_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
@@ -164,6 +171,14 @@ void alloc_workspace(Plan &p)
     if (p.method == PH_METHOD_FMM) {
         p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
         p.d_u = dev_alloc(p, (size_t)B * p.n_lam * rs);
+        // translation products: at most 2 GiB, at least one tile of source boxes
+        const size_t col_bytes = (size_t)kNumM2L * p.n_lam * rs;
+        int64_t widest2 = 1;
+        for (int l = 2; l <= p.max_depth; ++l) widest2 = std::max<int64_t>(widest2, p.level_cap[l]);
+        size_t budget = 2ull << 30;
+        if (const char *env = std::getenv("PH_TRANSLATION_BUFFER_MB")) budget = (size_t)std::atoll(env) << 20;
+        p.y_cap_cols = (size_t)std::max<int64_t>(64, std::min<int64_t>(widest2, (int64_t)(budget / col_bytes)));
+        p.d_y = dev_alloc(p, p.y_cap_cols * col_bytes);
     }
     p.d_srcbox_mark = (int32_t *)dev_alloc(p, B * 4);
     p.d_feat = (float *)dev_alloc(p, (size_t)B * 8 * 4);
@@ -183,9 +198,11 @@ void free_plan(Plan *p)
                     p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_scan_tmp, p->d_s_pos, p->d_t_pos, p->d_s_key,
                     p->d_t_key, p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
                     p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
-                    p->box.child, p->box.coll, p->box.child_tmp, p->box.child_cnt, p->lists.u_off,
+                    p->box.child, p->box.coll, p->box.child_tmp, p->box.child_cnt, p->box.src_rank,
+                    p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->d_phi, p->d_u,
-                    p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params};
+                    p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params, p->d_cell,
+                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
         for (auto &set : p->ring)
@@ -292,6 +309,35 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     dev_free(d_xyz_in);
     dev_free(d_w_in);
     p.bytes_allocated -= (size_t)n * 8 + (size_t)n * 4 + hb + (size_t)n * 24 + (d_w_in ? (size_t)n * 8 : 0);
+    // uniform grid aligned with the root cube: every point at a cell centre
+    if (!pts->w && pts->h > 0) {
+        const double Nf = p.cube_size / pts->h;
+        const long N = std::lround(Nf);
+        bool ok = N >= 1 && N <= 1024 && std::fabs(Nf - (double)N) < 1e-9 * (double)N;
+        std::vector<int32_t> cell(ok ? n : 0);
+        for (int64_t i = 0; ok && i < n; ++i) {
+            int32_t c = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double f = (pts->xyz[3 * i + d] - p.cube_lo[d]) / pts->h - 0.5;
+                const long ci = std::lround(f);
+                if (std::fabs(f - (double)ci) > 1e-6 || ci < 0 || ci >= N) {
+                    ok = false;
+                    break;
+                }
+                c |= (int32_t)ci << (10 * d);
+            }
+            if (ok) cell[i] = c;
+        }
+        if (ok) {
+            std::vector<int32_t> perm(n), sorted(n);
+            PH_HIP(hipMemcpy(perm.data(), p.d_perm, (size_t)n * 4, hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < n; ++k) sorted[k] = cell[perm[k]];
+            p.d_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
+            PH_HIP(hipMemcpy(p.d_cell, sorted.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+            p.grid_mode = true;
+            p.grid_n = (int)N;
+        }
+    }
     // tree bound from the tree over all points
     std::vector<uint64_t> hkeys(n);
     PH_HIP(hipMemcpy(hkeys.data(), p.d_key, (size_t)n * 8, hipMemcpyDeviceToHost));
@@ -319,7 +365,9 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         const int nl = p.n_lam, ns = p.n_sig, L = p.max_depth + 1;
         std::vector<double> rm((size_t)L * nl * ns, 0.0), cm((size_t)L * nl * ns, 0.0);
         std::vector<double> m2m((size_t)L * 8 * nl * nl, 0.0), l2l((size_t)L * 8 * nl * nl, 0.0);
-        std::vector<double> m2l((size_t)L * kNumM2L * nl * nl, 0.0);
+        p.k_pad = ((nl + kGemmK - 1) / kGemmK) * kGemmK;
+        const int kp = p.k_pad;
+        std::vector<double> m2l((size_t)L * kNumM2L * nl * kp, 0.0);
         for (int l = 2; l < L; ++l) {
             const std::vector<double> &U = H.uc2e[l];
             for (int i = 0; i < nl; ++i)
@@ -337,13 +385,32 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
                             // l2l = m2m^T: (j, i) entry equals v
                             l2l[((size_t)l * 8 + c) * nl * nl + (size_t)i * nl + j] = v;
                         }
+            // stacked GEMM operand: row slot * nl + i, column j (zero padded to k_pad)
             for (int t = 0; t < kNumM2L; ++t)
                 for (int i = 0; i < nl; ++i)
                     for (int j = 0; j < nl; ++j)
-                        m2l[((size_t)l * kNumM2L + t) * nl * nl + (size_t)j * nl + i] =
+                        m2l[((size_t)l * kNumM2L * nl + (size_t)t * nl + i) * kp + j] =
                             H.m2l[l][(size_t)t * nl * nl + (size_t)i * nl + j];
         }
         std::vector<double> shell = H.shell_unit, lat = H.lat_unit;
+        // lattice operators of uniform-grid boxes
+        std::vector<double> gg, ggt;
+        if (p.grid_mode) {
+            for (int l = 2; l < L; ++l) {
+                const int m = (p.grid_n % (1 << l) == 0) ? (p.grid_n >> l) : 0;
+                if (m < 1 || m > kGridMaxCells) continue;
+                std::vector<double> G;
+                build_grid_operator(p.gas, H, l, p.hw[l], p.h, m, G);
+                const int R = m * m * m;
+                p.grid_m[l] = m;
+                p.grid_off[l] = (int64_t)gg.size();
+                gg.insert(gg.end(), G.begin(), G.end());
+                ggt.resize(gg.size());
+                for (int li = 0; li < nl; ++li)
+                    for (int r = 0; r < R; ++r) ggt[p.grid_off[l] + (size_t)r * nl + li] = G[(size_t)li * R + r];
+            }
+            if (gg.empty()) gg.push_back(0.0), ggt.push_back(0.0);
+        }
         if (p.precision == PH_FP64) {
             upload(p, &p.ops.uc2e_rm, rm);
             upload(p, &p.ops.uc2e_cm, cm);
@@ -352,6 +419,10 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
             upload(p, &p.ops.m2l, m2l);
             upload(p, &p.ops.lat_unit, lat);
             upload(p, &p.ops.shell_unit, shell);
+            if (p.grid_mode) {
+                upload(p, &p.ops.grid_g, gg);
+                upload(p, &p.ops.grid_gt, ggt);
+            }
         } else {
             upload(p, &p.ops.uc2e_rm, convert<float>(rm));
             upload(p, &p.ops.uc2e_cm, convert<float>(cm));
@@ -360,6 +431,10 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
             upload(p, &p.ops.m2l, convert<float>(m2l));
             upload(p, &p.ops.lat_unit, convert<float>(lat));
             upload(p, &p.ops.shell_unit, convert<float>(shell));
+            if (p.grid_mode) {
+                upload(p, &p.ops.grid_g, convert<float>(gg));
+                upload(p, &p.ops.grid_gt, convert<float>(ggt));
+            }
         }
     }
     alloc_workspace(p);
@@ -468,6 +543,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
     try {
         PH_HIP(hipSetDevice(p.device));
         const bool timed = stats != nullptr || p.recording;
+        p.count_work = stats != nullptr;
         const int slot = p.ring_pos;
         if (timed) {
             harvest_slot(p, slot);  // a slot from kRing calls ago: long finished
@@ -478,7 +554,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
         };
         mark(0);
         launch_reset_scalars(p.d_sc, s);
-        launch_reduce_max(I, p.precision == PH_FP64, absE, p.thr.e_rel >= 0, p.n, p.d_sc, s);
+        launch_reduce_max(I, p.precision == PH_FP64, absE, p.thr.e_rel >= 0, p.n, p.d_sc, p.d_scan_tmp, s);
         launch_select_flags(p, I, absE, S_out, s);
         exclusive_scan_u64(p.d_flag, p.n, p.d_scan_tmp, &p.d_sc->packed_total, s);
         launch_compact(p, I, s);
@@ -517,7 +593,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             stats->n_boxes = p.method == PH_METHOD_FMM ? nb : 0;
             stats->levels = levels;
             stats->n_src_dropped = p.h_sc.n_src_dropped;
-            for (int k = 0; k < 8; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
+            for (int k = 0; k < 12; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
             for (int k = 0; k + 1 < Plan::kMarks; ++k) {
                 float ms = 0;
                 PH_HIP(hipEventElapsedTime(&ms, p.ring[slot][k], p.ring[slot][k + 1]));

@@ -47,14 +47,17 @@ struct CallScalars {
     int32_t n_src;
     int32_t n_tgt;
     int32_t lvl_count[kMaxDepth + 2];   // boxes per level
+    int32_t lvl_src[kMaxDepth + 2];     // boxes with sources per level
     int32_t lvl_start[kMaxDepth + 3];   // first box of each level
     int32_t n_u, n_w, n_x;              // list lengths
     int32_t n_src_dropped;              // learned selector
     int32_t pad;
     uint64_t packed_total;              // selected (sources | targets << 32)
+    uint64_t lvl_pack[kMaxDepth + 2];   // packed per-level totals (boxes | source boxes << 32)
     // algorithmic work of the call (integer counters, order independent)
-    unsigned long long work[8];         // p2p pairs, l2p evals, m2p evals, p2m evals,
-                                        // p2l evals, m2l pairs, m2m children, l2l boxes
+    unsigned long long work[12];        // p2p pairs, l2p evals, m2p evals, p2m evals,
+                                        // p2l evals, m2l pairs, m2m children, l2l boxes,
+                                        // grid l2p multiply-adds, grid p2m multiply-adds
 };
 
 // Box table (structure of arrays, capacity box_cap)
@@ -67,7 +70,9 @@ struct BoxArrays {
     int32_t *child = nullptr;       // box_cap x 8, -1 if absent
     int32_t *coll = nullptr;        // box_cap x 27 colleagues, -1 if absent
     int4 *child_tmp = nullptr;      // per-level scratch: (cap of widest level) x 8 child ranges
-    uint32_t *child_cnt = nullptr;  // per-level scratch: nonempty children per box (scan input)
+    uint64_t *child_cnt = nullptr;  // per-level scratch: packed (children | children with sources << 32)
+    int32_t *src_rank = nullptr;    // rank of a box among its level's boxes with sources (-1 if none)
+    int32_t *src_box = nullptr;     // per-level slots: box of each source rank
 };
 
 // Interaction lists in CSR form over all boxes (offsets box_cap + 1)
@@ -87,12 +92,18 @@ struct OperatorsDev {
     void *uc2e_cm = nullptr;   // levels x n_sig x n_lam (transposed copy)
     void *m2m = nullptr;       // levels x 8 x n_lam x n_lam, column-major (entry (i,j) at j*n_lam+i)
     void *l2l = nullptr;       // levels x 8 x n_lam x n_lam, column-major
-    void *m2l = nullptr;       // levels x 316 x n_lam x n_lam, column-major
+    void *m2l = nullptr;       // levels x (316 n_lam) x k_pad, row m = slot n_lam + i, column k = j
     void *lat_unit = nullptr;  // n_lam x 3 lattice nodes on [-1,1]^3 (T)
     void *shell_unit = nullptr;// n_sig x 3 shell points (radius included) in units of the half-width
     // BF16 split copies of m2l (hi, lo), row-major tiles for MFMA
     void *m2l_hi = nullptr, *m2l_lo = nullptr;
+    // uniform-grid lattice operators per level (cells of a box at fixed offsets):
+    //   grid_g  [lambda][r] = (uc2e_l K(shell_l, cells_l))[lambda][r]   (L2P reads columns)
+    //   grid_gt [r][lambda] = same matrix transposed                      (P2M reads rows)
+    void *grid_g = nullptr, *grid_gt = nullptr;
 };
+
+constexpr int kGridMaxCells = 16;  // lattice operators for boxes of at most 16^3 cells
 
 struct Plan {
     // configuration
@@ -102,6 +113,9 @@ struct Plan {
     ph_method method = PH_METHOD_FMM;
     ph_selector selector = PH_SEL_THRESHOLD;
     int q = 4, n_lam = 64, n_sig = 98;
+    int k_pad = 64;          // n_lam rounded up to the GEMM K chunk
+    size_t y_cap_cols = 0;   // source boxes per translation chunk (Y buffer columns)
+    void *d_y = nullptr;     // translation products: y_cap_cols x (316 n_lam)
     int leaf_cap = 64;
     int max_depth = 0;       // deepest level any per-call tree may reach
     double pinv_cut = 0;
@@ -113,6 +127,12 @@ struct Plan {
     ph_thresholds thr{};
     bool uniform_w = true;
     double w_uniform = 0;
+    // uniform cell-centred grid aligned with the root cube: points carry integer cell indices
+    bool grid_mode = false;
+    int grid_n = 0;                          // cells per root-cube edge
+    int grid_m[kMaxDepth + 2] = {};          // cells per box edge at each level (0 = no operator)
+    int64_t grid_off[kMaxDepth + 2] = {};    // offset of each level's operator (elements)
+    int32_t *d_cell = nullptr;               // sorted packed cell index ix | iy << 10 | iz << 20
     // learned selector
     std::vector<float> sel_weights;
     float sel_threshold = 0.f;
@@ -141,6 +161,7 @@ struct Plan {
     uint64_t *d_s_key = nullptr, *d_t_key = nullptr;  // their keys
     void *d_s_dat = nullptr;        // sources: (x, y, z, q = w * I * 2^-e), float4 or double4
     void *d_t_dat = nullptr;        // targets: (x, y, z, self = c_self * I * 2^-e or 0)
+    int32_t *d_s_cell = nullptr, *d_t_cell = nullptr; // packed cell indices (grid mode)
     BoxArrays box;
     Lists lists;
     void *d_phi = nullptr;          // box_cap x n_lam upward densities
@@ -160,6 +181,7 @@ struct Plan {
     double phase_sum[PH_NPHASES] = {};
     int64_t phase_calls = 0;
     bool events_ready = false;
+    bool count_work = false;        // algorithmic work counters (only for calls that fetch stats)
     size_t bytes_allocated = 0;
     size_t workspace_cap = 0;
 };
@@ -181,6 +203,8 @@ struct HostOperators {
 void build_operators(const Gas &gas, int q, double root_size, int max_depth, double cut,
                      HostOperators &out);
 double cube_self_integral(const Gas &gas, double h);
+void build_grid_operator(const Gas &gas, const HostOperators &H, int level, double hw, double h, int m,
+                         std::vector<double> &G);
 int m2l_index(int dx, int dy, int dz);  // -1 unless the offset is well separated
 void m2l_offset(int idx, int &dx, int &dy, int &dz);
 
@@ -201,7 +225,7 @@ void launch_gather_sorted(const double *xyz, const double *w, const int32_t *per
 // selection (k_select.hip)
 void launch_reset_scalars(CallScalars *sc, hipStream_t s);
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
-                       CallScalars *sc, hipStream_t s);
+                       CallScalars *sc, void *tmp /* >= 16 KiB */, hipStream_t s);
 void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s);
 void launch_compact(const Plan &p, const void *I, hipStream_t s);
 
@@ -209,9 +233,10 @@ void launch_compact(const Plan &p, const void *I, hipStream_t s);
 void build_tree(Plan &p, hipStream_t s);
 void build_lists(Plan &p, hipStream_t s);
 
-// fmm (k_fmm.hip)
+// fmm (k_fmm.hip, k_m2l.hip)
 void fmm_upward(Plan &p, hipStream_t s);
 void fmm_downward(Plan &p, hipStream_t s);
+constexpr int kGemmK = 32;  // K chunk of the translation GEMM
 void fmm_leaf(Plan &p, void *S_out, hipStream_t s);
 
 // direct sum (k_direct.hip)

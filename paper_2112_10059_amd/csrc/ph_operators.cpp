@@ -248,6 +248,39 @@ void build_operators(const Gas &gas, int q, double root_size, int max_depth, dou
     }
 }
 
+// Lattice operator of a box of m^3 grid cells (uniform cell-centred grids):
+// G = uc2e_l K(shell_l, cells_l), n_lam x m^3, cell r = (i m + j) m + k at offset
+// ((i + 1/2) h - hw, (j + 1/2) h - hw, (k + 1/2) h - hw) from the box centre.
+// P2M of sources q on the cells is G q; the far field at the cells is G^T u, since
+// uc2e_l^T is the check-to-equivalent map of the downward pass and K is symmetric.
+void build_grid_operator(const Gas &gas, const HostOperators &H, int level, double hw, double h, int m,
+                         std::vector<double> &G)
+{
+    const int nl = H.n_lam, ns = H.n_sig, R = m * m * m;
+    std::vector<double> cells((size_t)R * 3);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            for (int k = 0; k < m; ++k) {
+                const int r = (i * m + j) * m + k;
+                cells[3 * r] = (i + 0.5) * h - hw;
+                cells[3 * r + 1] = (j + 0.5) * h - hw;
+                cells[3 * r + 2] = (k + 0.5) * h - hw;
+            }
+    const double zero[3] = {0, 0, 0};
+    std::vector<double> Kmat;  // n_sig x R
+    kernel_matrix(H.shell_unit, cells, ns, R, hw, 1.0, zero, gas, Kmat);
+    G.assign((size_t)nl * R, 0.0);
+    const std::vector<double> &U = H.uc2e[level];
+    parallel_for(nl, [&](int li) {
+        for (int sg = 0; sg < ns; ++sg) {
+            const double u = U[(size_t)li * ns + sg];
+            const double *kr = &Kmat[(size_t)sg * R];
+            double *g = &G[(size_t)li * R];
+            for (int r = 0; r < R; ++r) g[r] += u * kr[r];
+        }
+    });
+}
+
 // ------------------------------------------------------------------ own-cell coefficient
 
 namespace {

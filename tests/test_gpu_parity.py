@@ -162,3 +162,51 @@ def test_fmm_fp32_c2_small_adaptive(gpu_lib):
     _say(f"  rel-L2 = {err:.3e}")
     assert err <= 1e-3
     plan.close()
+
+
+def test_fmm_fp64_all_sources_c2_small(gpu_lib):
+    """Plain FP64 FMM (every point a source and a target) on a 32^3 streamer grid: <= 1e-6."""
+    import torch
+    wl = gen.config2(seed=1004, n_axis=32)
+    _say("fmm c2_32 fp64 all sources")
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, dict(src_rel=0.0), precision="fp64", leaf_capacity=64, **plan_kwargs(wl))
+    S = plan.evaluate(_tensor(wl.I, torch.float64)).cpu().numpy()
+    ref = photoionization(wl.xyz, wl.I, wl.gas, h=wl.h).full(wl.n)
+    err = rel_l2(S, ref)
+    _say(f"  rel-L2 = {err:.3e}")
+    assert err <= 1e-6
+    plan.close()
+
+
+def test_fmm_translation_chunks_match(gpu_lib, monkeypatch):
+    """A small translation buffer (many source-box chunks) gives the same field to rounding."""
+    import torch
+    wl = gen.config2(seed=1005, n_axis=48)
+    I32 = _tensor(wl.I.astype(np.float32), torch.float32)
+    E32 = _tensor(wl.E.astype(np.float32), torch.float32)
+    thr = dict(src_rel=1e-6, e_abs=3e6)
+    _say("fmm c2_48 fp32 one chunk vs many chunks")
+    p1 = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
+    S1 = p1.evaluate(I32, E32).double().cpu().numpy()
+    monkeypatch.setenv("PH_TRANSLATION_BUFFER_MB", "1")
+    p2 = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
+    S2 = p2.evaluate(I32, E32).double().cpu().numpy()
+    assert rel_l2(S2, S1) < 1e-6
+    r = photoionization(wl.xyz, wl.I.astype(np.float32).astype(np.float64), wl.gas, h=wl.h, src_rel=1e-6,
+                        E=wl.E.astype(np.float32).astype(np.float64), e_abs=3e6)
+    assert rel_l2(S2, r.full(wl.n)) <= 1e-3
+    p1.close()
+    p2.close()
+
+
+def test_repeat_calls_bitwise_identical(gpu_lib):
+    """No floating-point atomics: two identical calls give bitwise-identical output."""
+    import torch
+    wl = gen.config2(seed=1006, n_axis=48)
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, wl.thresholds, leaf_capacity=32, **plan_kwargs(wl))
+    I32 = _tensor(wl.I.astype(np.float32), torch.float32)
+    E32 = _tensor(wl.E.astype(np.float32), torch.float32)
+    a = plan.evaluate(I32, E32).cpu().numpy()
+    b = plan.evaluate(I32, E32).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    plan.close()
