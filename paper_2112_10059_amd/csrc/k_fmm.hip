@@ -162,8 +162,24 @@ struct Acc<double> {
     __device__ __forceinline__ double value() const { return s; }
 };
 
+// broadcast of lane j's value to the whole wave (scalar register)
+__device__ __forceinline__ float lane_bcast(float v, int j)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ __forceinline__ double lane_bcast(double v, int j)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), j);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), j);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Far field of every target leaf (lattice or shell L2P, W list) plus the own-cell term.
+// Leaves without near sources are finished here; the others leave their far field in
+// t_far for the near-field kernel.
 template <class T, class TO>
-__global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
+__global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far)
 {
     const int32_t b = blockIdx.x;
     int level;
@@ -251,29 +267,67 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out)
                     far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * wphi[li];
                 }
         }
-        // U list: exact near field
+        if (act) {
+            if (u1 > u0) {
+                t_far[tf + t] = far;
+            } else {
+                const double tot = (double)far + (double)x.w;
+                S_out[a.perm[a.t_pos[tf + t]]] = (TO)(a.P * ldexp(tot, scale_exp));
+            }
+        }
+    }
+}
+
+// Exact near field (Sec. 2.4 eq. (16)) of leaves with a U list: four waves per leaf,
+// wave w sums the U entries w, w+4, ...; each wave keeps a Kahan-compensated FP32 sum
+// (FP64 in the FP64 form); the partial sums, the far field and the own-cell term are
+// combined in FP64 in a fixed order.  Sources are broadcast lane by lane from registers.
+template <class T, class TO>
+__global__ __launch_bounds__(256) void near_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
+                                                   const T *__restrict__ t_far)
+{
+    const int32_t b = blockIdx.x;
+    int level;
+    if (!box_live(a.lt, a.sc, b, level)) return;
+    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.t_cnt[b] == 0) return;
+    const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
+    if (u1 == u0) return;
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+    const int scale_exp = a.sc->scale_exp;
+    for (int tb = 0; tb < tn; tb += 64) {
+        const int t = tb + lane;
+        const bool act = t < tn;
+        V4<T> x;
+        if (act) x = a.t_dat[tf + t];
+        else x.x = x.y = x.z = x.w = T(0);
         Acc<T> near;
-        for (uint32_t e = u0; e < u1; ++e) {
+        for (uint32_t e = u0 + w; e < u1; e += 4) {
             const int32_t C = a.L.u[e];
             const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
             for (int base = 0; base < sn; base += 64) {
                 const int m = min(64, sn - base);
-                __syncthreads();
-                if ((int)threadIdx.x < m) tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
-                __syncthreads();
-                if (act)
-                    for (int j = 0; j < m; ++j) {
-                        const V4<T> y = tile[j];
-                        const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
-                        const T r2 = dx * dx + dy * dy + dz * dz;
-                        if (r2 > T(0)) near.add(kernel_eval<true>(r2, a.kp) * y.w);
-                    }
+                V4<T> y;
+                if (lane < m) y = a.s_dat[sf + base + lane];
+                else y.x = y.y = y.z = y.w = T(0);
+                for (int j = 0; j < m; ++j) {
+                    const T yx = lane_bcast(y.x, j), yy = lane_bcast(y.y, j), yz = lane_bcast(y.z, j),
+                            yw = lane_bcast(y.w, j);
+                    const T dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    if (act && r2 > T(0)) near.add(kernel_eval<true>(r2, a.kp) * yw);
+                }
             }
         }
-        if (act) {
-            const double tot = (double)far + near.value() + (double)x.w;
+        part[w][lane] = near.value();
+        __syncthreads();
+        if (w == 0 && act) {
+            const double tot = (double)t_far[tf + t] + part[0][lane] + part[1][lane] + part[2][lane] +
+                               part[3][lane] + (double)x.w;
             S_out[a.perm[a.t_pos[tf + t]]] = (TO)(a.P * ldexp(tot, scale_exp));
         }
+        __syncthreads();
     }
 }
 
@@ -293,7 +347,8 @@ template <class T>
 void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
-    leaf_kernel<T, T><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out);
+    leaf_kernel<T, T><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far);
+    near_kernel<T, T><<<(unsigned)p.box_cap, 256, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
 }
 
 }  // namespace

@@ -3,9 +3,12 @@
 // Sec. 2.4: the octree is refined until every leaf holds at most a
 // prescribed number of points; near interactions N(B) are summed exactly and
 // far interactions F(B) go through the hierarchy.  Here a box is split while
-// max(#selected sources, #selected targets) > leaf capacity.  Since the
-// selected lists are sorted by Morton key, every box is a contiguous range of
-// each list and a child range is found by binary search on the next key digit.
+// max(#selected sources, #selected targets) > leaf capacity.  The plan holds
+// the tree over all points; since selected counts only shrink down the tree,
+// the per-call tree is that tree pruned: a box belongs to it iff it holds
+// selected points and its parent is split.  The selected lists are sorted by
+// Morton key, so a box's range in each list is read off the selection scan at
+// the ends of its range in the sorted point order.
 //
 // Lists (kernel-independent FMM of [ying2004], cited in Sec. 2.4):
 //   U(B), leaf B : source leaves adjacent to B (any level, B included)
@@ -29,169 +32,63 @@ struct LevelInfo {
     int32_t depth;  // deepest level
 };
 
-__device__ __forceinline__ uint64_t spread3(uint32_t v)
+// Per-call tree: the plan's tree over all points, pruned to the selected sets.
+// Box ranges come from the exclusive scan of the packed (source | target << 32)
+// selection indicators at the box's sorted-order range ends.
+__device__ __forceinline__ uint64_t scan_at(const uint64_t *__restrict__ scanned, int32_t k, int64_t n,
+                                            uint64_t total)
 {
-    uint64_t x = v & 0x1fffffu;
-    x = (x | (x << 32)) & 0x001f00000000ffffull;
-    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
-    x = (x | (x << 8)) & 0x100f00f00f00f00full;
-    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-    x = (x | (x << 2)) & 0x1249249249249249ull;
-    return x;
+    return k < n ? scanned[k] : total;
 }
 
-__device__ __forceinline__ uint64_t prefix_of(int ax, int ay, int az)
+__global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int leaf_cap, int max_depth,
+                                   const uint64_t *__restrict__ scanned, int64_t n, CallScalars *__restrict__ sc)
 {
-    return (spread3((uint32_t)ax) << 2) | (spread3((uint32_t)ay) << 1) | spread3((uint32_t)az);
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t total = sc->packed_total;
+    if (f == 0) {
+        for (int l = 0; l <= li.depth; ++l) sc->lvl_count[l] = li.cap[l];
+        for (int l = 0; l <= li.depth + 1; ++l) sc->lvl_start[l] = li.base[l];
+        bx.srcflag[nbox] = 0;
+    }
+    if (f >= nbox) return;
+    const int32_t st = bx.start[f], en = bx.end[f];
+    const uint64_t a = scan_at(scanned, st, n, total), b = scan_at(scanned, en, n, total);
+    const int32_t s0 = (int32_t)(a & 0xffffffffu), t0 = (int32_t)(a >> 32);
+    const int32_t sn = (int32_t)(b & 0xffffffffu) - s0, tn = (int32_t)(b >> 32) - t0;
+    const int32_t par = bx.parent[f];
+    bool exists = true;
+    if (par >= 0) {
+        const uint64_t pa = scan_at(scanned, bx.start[par], n, total), pb = scan_at(scanned, bx.end[par], n, total);
+        const int32_t psn = (int32_t)(pb & 0xffffffffu) - (int32_t)(pa & 0xffffffffu);
+        const int32_t ptn = (int32_t)(pb >> 32) - (int32_t)(pa >> 32);
+        exists = (sn + tn > 0) && (max(psn, ptn) > leaf_cap);
+    }
+    // split in the plan's tree iff it holds more than leaf_cap points above the depth limit
+    const bool split = exists && (en - st > leaf_cap) && (bx.level[f] < max_depth) && (max(sn, tn) > leaf_cap);
+    bx.s_first[f] = exists ? s0 : 0;
+    bx.s_cnt[f] = exists ? sn : 0;
+    bx.t_first[f] = exists ? t0 : 0;
+    bx.t_cnt[f] = exists ? tn : 0;
+    bx.flags[f] = exists ? (kBoxExists | (split ? 0 : kBoxLeaf)) : 0;
+    bx.srcflag[f] = (exists && sn > 0) ? 1u : 0u;
 }
 
-// first index in [lo, hi) with (key >> shift) >= target
-__device__ __forceinline__ int32_t lower_bound_prefix(const uint64_t *__restrict__ keys, int32_t lo, int32_t hi,
-                                                      int shift, uint64_t target)
+// srcflag holds its exclusive scan: rank of every box with sources within its level
+__global__ void tree_srcrank_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, CallScalars *__restrict__ sc)
 {
-    while (lo < hi) {
-        int32_t mid = lo + ((hi - lo) >> 1);
-        if ((keys[mid] >> shift) < target) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__global__ void init_root_kernel(BoxArrays bx, LevelInfo li, CallScalars *sc)
-{
-    if (threadIdx.x == 0) {
-        const int b = li.base[0];
-        bx.level[b] = 0;
-        bx.ax[b] = bx.ay[b] = bx.az[b] = 0;
-        bx.s_first[b] = 0;
-        bx.s_cnt[b] = sc->n_src;
-        bx.t_first[b] = 0;
-        bx.t_cnt[b] = sc->n_tgt;
-        bx.parent[b] = -1;
-        bx.flags[b] = 0;
-        bx.src_rank[b] = sc->n_src > 0 ? 0 : -1;
-        bx.src_box[b] = b;
-        sc->lvl_count[0] = 1;
-        sc->lvl_src[0] = sc->n_src > 0 ? 1 : 0;
-        for (int l = 0; l <= li.depth + 1 && l < kMaxDepth + 3; ++l) sc->lvl_start[l] = li.base[l];
-    }
-    if (threadIdx.x < 27) bx.coll[(size_t)li.base[0] * 27 + threadIdx.x] = (threadIdx.x == 13) ? li.base[0] : -1;
-}
-
-__global__ void split_count_kernel(BoxArrays bx, LevelInfo li, int level, int leaf_cap, int may_split,
-                                   const CallScalars *__restrict__ sc, const uint64_t *__restrict__ s_key,
-                                   const uint64_t *__restrict__ t_key)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= li.cap[level]) return;
-    if (i >= sc->lvl_count[level]) {
-        bx.child_cnt[i] = 0;
-        return;
-    }
-    const int32_t b = li.base[level] + i;
-    const int32_t sf = bx.s_first[b], sn = bx.s_cnt[b], tf = bx.t_first[b], tn = bx.t_cnt[b];
-    const bool split = may_split && (max(sn, tn) > leaf_cap);
-    bx.flags[b] = split ? 0 : kBoxLeaf;
-    if (!split) {
-        bx.child_cnt[i] = 0;
-        return;
-    }
-    const int shift = 3 * (kMortonBits - (level + 1));
-    const uint64_t pre = prefix_of(bx.ax[b], bx.ay[b], bx.az[b]) << 3;
-    int32_t sb[9], tb[9];
-    sb[0] = sf;
-    sb[8] = sf + sn;
-    tb[0] = tf;
-    tb[8] = tf + tn;
-    for (int o = 1; o < 8; ++o) {
-        sb[o] = lower_bound_prefix(s_key, sb[o - 1], sf + sn, shift, pre | (uint64_t)o);
-        tb[o] = lower_bound_prefix(t_key, tb[o - 1], tf + tn, shift, pre | (uint64_t)o);
-    }
-    uint64_t cnt = 0, cnt_s = 0;
-    for (int o = 0; o < 8; ++o) {
-        int4 r = make_int4(sb[o], sb[o + 1] - sb[o], tb[o], tb[o + 1] - tb[o]);
-        bx.child_tmp[(size_t)i * 8 + o] = r;
-        cnt += (r.y + r.w) > 0 ? 1u : 0u;
-        cnt_s += r.y > 0 ? 1u : 0u;
-    }
-    bx.child_cnt[i] = cnt | (cnt_s << 32);
-}
-
-// child_cnt now holds packed exclusive offsets; lvl_count/lvl_src[level+1] the totals.
-__global__ void split_emit_kernel(BoxArrays bx, LevelInfo li, int level, CallScalars *__restrict__ sc)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc->lvl_count[level]) return;
-    if (i == 0) {
-        const uint64_t v = sc->lvl_pack[level + 1];
-        sc->lvl_count[level + 1] = (int32_t)(v & 0xffffffffu);
-        sc->lvl_src[level + 1] = (int32_t)(v >> 32);
-    }
-    const int32_t b = li.base[level] + i;
-    int32_t *ch = bx.child + (size_t)b * 8;
-    if (bx.flags[b] & kBoxLeaf) {
-        for (int o = 0; o < 8; ++o) ch[o] = -1;
-        return;
-    }
-    const uint64_t off = bx.child_cnt[i];
-    int32_t c = li.base[level + 1] + (int32_t)(off & 0xffffffffu);
-    int32_t rs = (int32_t)(off >> 32);  // next source rank at level + 1
-    const int ax = bx.ax[b], ay = bx.ay[b], az = bx.az[b];
-    for (int o = 0; o < 8; ++o) {
-        int4 r = bx.child_tmp[(size_t)i * 8 + o];
-        if (r.y + r.w == 0) {
-            ch[o] = -1;
-            continue;
-        }
-        ch[o] = c;
-        bx.level[c] = level + 1;
-        bx.ax[c] = 2 * ax + ((o >> 2) & 1);
-        bx.ay[c] = 2 * ay + ((o >> 1) & 1);
-        bx.az[c] = 2 * az + (o & 1);
-        bx.s_first[c] = r.x;
-        bx.s_cnt[c] = r.y;
-        bx.t_first[c] = r.z;
-        bx.t_cnt[c] = r.w;
-        bx.parent[c] = b;
-        bx.flags[c] = 0;
-        if (r.y > 0) {
-            bx.src_rank[c] = rs;
-            bx.src_box[li.base[level + 1] + rs] = c;
-            ++rs;
-        } else {
-            bx.src_rank[c] = -1;
-        }
-        ++c;
-    }
-}
-
-__global__ void mark_last_level_kernel(BoxArrays bx, LevelInfo li, int level, const CallScalars *__restrict__ sc)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc->lvl_count[level]) return;
-    const int32_t b = li.base[level] + i;
-    bx.flags[b] = kBoxLeaf;
-    for (int o = 0; o < 8; ++o) bx.child[(size_t)b * 8 + o] = -1;
-}
-
-// Colleagues (the 27 same-level boxes around B, B included) from the parent's colleagues.
-__global__ void colleagues_kernel(BoxArrays bx, LevelInfo li, int level, const CallScalars *__restrict__ sc)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc->lvl_count[level]) return;
-    const int32_t b = li.base[level] + i;
-    const int ax = bx.ax[b], ay = bx.ay[b], az = bx.az[b];
-    const int32_t p = bx.parent[b];
-    const int lim = 1 << level;
-    for (int d = 0; d < 27; ++d) {
-        const int nx = ax + d / 9 - 1, ny = ay + (d / 3) % 3 - 1, nz = az + d % 3 - 1;
-        int32_t res = -1;
-        if (nx >= 0 && ny >= 0 && nz >= 0 && nx < lim && ny < lim && nz < lim) {
-            const int dpx = (nx >> 1) - (ax >> 1), dpy = (ny >> 1) - (ay >> 1), dpz = (nz >> 1) - (az >> 1);
-            const int32_t P = bx.coll[(size_t)p * 27 + (dpx + 1) * 9 + (dpy + 1) * 3 + (dpz + 1)];
-            if (P >= 0) res = bx.child[(size_t)P * 8 + (((nx & 1) << 2) | ((ny & 1) << 1) | (nz & 1))];
-        }
-        bx.coll[(size_t)b * 27 + d] = res;
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nbox) return;
+    const int l = bx.level[f];
+    const int32_t base = li.base[l];
+    if (f == base) sc->lvl_src[l] = (int32_t)(bx.srcflag[li.base[l + 1]] - bx.srcflag[base]);
+    const bool has = bx.srcflag[f + 1] != bx.srcflag[f];
+    if (has) {
+        const int32_t rank = (int32_t)(bx.srcflag[f] - bx.srcflag[base]);
+        bx.src_rank[f] = rank;
+        bx.src_box[base + rank] = f;
+    } else {
+        bx.src_rank[f] = -1;
     }
 }
 
@@ -334,18 +231,11 @@ LevelInfo level_info(const Plan &p)
 void build_tree(Plan &p, hipStream_t s)
 {
     LevelInfo li = level_info(p);
-    init_root_kernel<<<1, 64, 0, s>>>(p.box, li, p.d_sc);
-    for (int l = 0; l < p.max_depth; ++l) {
-        const int cap = (int)p.level_cap[l];
-        const unsigned g = (unsigned)((cap + 255) / 256);
-        split_count_kernel<<<g, 256, 0, s>>>(p.box, li, l, p.leaf_cap, 1, p.d_sc, p.d_s_key, p.d_t_key);
-        exclusive_scan_u64(p.box.child_cnt, cap, p.d_scan_tmp, &p.d_sc->lvl_pack[l + 1], s);
-        split_emit_kernel<<<g, 256, 0, s>>>(p.box, li, l, p.d_sc);
-        const unsigned g1 = (unsigned)((p.level_cap[l + 1] + 255) / 256);
-        colleagues_kernel<<<g1, 256, 0, s>>>(p.box, li, l + 1, p.d_sc);
-    }
-    const unsigned g = (unsigned)((p.level_cap[p.max_depth] + 255) / 256);
-    mark_last_level_kernel<<<g, 256, 0, s>>>(p.box, li, p.max_depth, p.d_sc);
+    const int32_t nbox = (int32_t)p.box_cap;
+    const unsigned g = (unsigned)((nbox + 255) / 256);
+    tree_status_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.leaf_cap, p.max_depth, p.d_flag, p.n, p.d_sc);
+    exclusive_scan_u32(p.box.srcflag, nbox + 1, p.d_scan_tmp, nullptr, s);
+    tree_srcrank_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.d_sc);
 }
 
 void build_lists(Plan &p, hipStream_t s)

@@ -93,32 +93,73 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
     }
 }
 
-// Per-level box counts of the tree over all points (every point a source and a target).
-// Any per-call tree over a subset is contained in it, so these bound every call.
-void full_tree_levels(const std::vector<uint64_t> &keys, int leaf_cap, int depth_limit,
-                      std::vector<int64_t> &level_cap)
+// The octree over all points (every point both a source and a target), split
+// while a box holds more than leaf_cap points.  Any per-call tree over selected
+// subsets is this tree pruned: a box survives iff it holds selected points and
+// its parent is split in the per-call tree (counts shrink monotonically down the
+// tree, so the parent's test implies every ancestor's).
+struct FullTree {
+    std::vector<int32_t> level, ax, ay, az, start, end, parent, child, coll;
+    std::vector<int64_t> level_cap;
+};
+
+void build_full_tree(const std::vector<uint64_t> &keys, int leaf_cap, int depth_limit, FullTree &T)
 {
-    struct Seg { int64_t b, e; };
-    std::vector<Seg> cur{{0, (int64_t)keys.size()}}, nxt;
-    level_cap.clear();
-    for (int l = 0; l <= depth_limit; ++l) {
-        level_cap.push_back((int64_t)cur.size());
-        if (l == depth_limit) break;
-        nxt.clear();
-        int shift = 3 * (kMortonBits - (l + 1));
-        for (const Seg &s : cur) {
-            if (s.e - s.b <= leaf_cap) continue;
-            int64_t i = s.b;
-            while (i < s.e) {
-                uint64_t pre = keys[i] >> shift;
-                int64_t j = std::upper_bound(keys.begin() + i, keys.begin() + s.e, ((pre + 1) << shift) - 1) -
-                            keys.begin();
-                nxt.push_back({i, j});
-                i = j;
+    const int64_t n = (int64_t)keys.size();
+    auto add = [&](int l, int x, int y, int z, int64_t b, int64_t e, int32_t par) {
+        T.level.push_back(l);
+        T.ax.push_back(x);
+        T.ay.push_back(y);
+        T.az.push_back(z);
+        T.start.push_back((int32_t)b);
+        T.end.push_back((int32_t)e);
+        T.parent.push_back(par);
+        for (int o = 0; o < 8; ++o) T.child.push_back(-1);
+        for (int d = 0; d < 27; ++d) T.coll.push_back(-1);
+    };
+    add(0, 0, 0, 0, 0, n, -1);
+    T.coll[13] = 0;
+    T.level_cap.assign(1, 1);
+    int64_t lb = 0, le = 1;  // boxes of the current level
+    for (int l = 0; l < depth_limit; ++l) {
+        const int shift = 3 * (kMortonBits - (l + 1));
+        const int64_t first_new = (int64_t)T.level.size();
+        for (int64_t f = lb; f < le; ++f) {
+            const int64_t b = T.start[f], e = T.end[f];
+            if (e - b <= leaf_cap) continue;
+            const uint64_t pre = ((uint64_t)0 + (keys[b] >> (shift + 3))) << 3;
+            for (int o = 0; o < 8; ++o) {
+                const uint64_t lo_key = (pre | (uint64_t)o) << shift;
+                const uint64_t hi_key = ((pre | (uint64_t)o) + 1) << shift;
+                const int64_t cb = std::lower_bound(keys.begin() + b, keys.begin() + e, lo_key) - keys.begin();
+                const int64_t ce = std::lower_bound(keys.begin() + b, keys.begin() + e, hi_key) - keys.begin();
+                if (ce == cb) continue;
+                T.child[(size_t)f * 8 + o] = (int32_t)T.level.size();
+                add(l + 1, 2 * T.ax[f] + ((o >> 2) & 1), 2 * T.ay[f] + ((o >> 1) & 1), 2 * T.az[f] + (o & 1), cb, ce,
+                    (int32_t)f);
             }
         }
-        if (nxt.empty()) break;
-        cur.swap(nxt);
+        const int64_t last_new = (int64_t)T.level.size();
+        if (last_new == first_new) break;
+        T.level_cap.push_back(last_new - first_new);
+        // colleagues of the new level from the parents' colleagues
+        const int lim = 1 << (l + 1);
+        for (int64_t f = first_new; f < last_new; ++f) {
+            const int x = T.ax[f], y = T.ay[f], z = T.az[f];
+            const int32_t par = T.parent[f];
+            for (int d = 0; d < 27; ++d) {
+                const int nx = x + d / 9 - 1, ny = y + (d / 3) % 3 - 1, nz = z + d % 3 - 1;
+                int32_t res = -1;
+                if (nx >= 0 && ny >= 0 && nz >= 0 && nx < lim && ny < lim && nz < lim) {
+                    const int dp = ((nx >> 1) - (x >> 1) + 1) * 9 + ((ny >> 1) - (y >> 1) + 1) * 3 + ((nz >> 1) - (z >> 1) + 1);
+                    const int32_t P = T.coll[(size_t)par * 27 + dp];
+                    if (P >= 0) res = T.child[(size_t)P * 8 + (((nx & 1) << 2) | ((ny & 1) << 1) | (nz & 1))];
+                }
+                T.coll[(size_t)f * 27 + d] = res;
+            }
+        }
+        lb = first_new;
+        le = last_new;
     }
 }
 
@@ -136,26 +177,19 @@ void alloc_workspace(Plan &p)
     p.d_t_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
     p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);
     p.d_t_dat = dev_alloc(p, (size_t)n * 4 * rs);
+    p.d_t_far = dev_alloc(p, (size_t)n * rs);
     if (p.grid_mode) {
         p.d_s_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
         p.d_t_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
     }
     const int64_t B = p.box_cap;
     BoxArrays &b = p.box;
-    b.level = (int32_t *)dev_alloc(p, B * 4);
-    b.ax = (int32_t *)dev_alloc(p, B * 4);
-    b.ay = (int32_t *)dev_alloc(p, B * 4);
-    b.az = (int32_t *)dev_alloc(p, B * 4);
     b.s_first = (int32_t *)dev_alloc(p, B * 4);
     b.s_cnt = (int32_t *)dev_alloc(p, B * 4);
     b.t_first = (int32_t *)dev_alloc(p, B * 4);
     b.t_cnt = (int32_t *)dev_alloc(p, B * 4);
-    b.parent = (int32_t *)dev_alloc(p, B * 4);
     b.flags = (int32_t *)dev_alloc(p, B * 4);
-    b.child = (int32_t *)dev_alloc(p, B * 8 * 4);
-    b.coll = (int32_t *)dev_alloc(p, B * 27 * 4);
-    b.child_tmp = (int4 *)dev_alloc(p, (size_t)p.widest_level * 8 * sizeof(int4));
-    b.child_cnt = (uint64_t *)dev_alloc(p, (size_t)(p.widest_level + 1) * 8);
+    b.srcflag = (uint32_t *)dev_alloc(p, (B + 1) * 4);
     b.src_rank = (int32_t *)dev_alloc(p, B * 4);
     b.src_box = (int32_t *)dev_alloc(p, B * 4);
     Lists &L = p.lists;
@@ -198,11 +232,11 @@ void free_plan(Plan *p)
                     p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_scan_tmp, p->d_s_pos, p->d_t_pos, p->d_s_key,
                     p->d_t_key, p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
                     p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
-                    p->box.child, p->box.coll, p->box.child_tmp, p->box.child_cnt, p->box.src_rank,
+                    p->box.child, p->box.coll, p->box.start, p->box.end, p->box.srcflag, p->box.src_rank,
                     p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->d_phi, p->d_u,
                     p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params, p->d_cell,
-                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt};
+                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_far};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
         for (auto &set : p->ring)
@@ -342,12 +376,30 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     std::vector<uint64_t> hkeys(n);
     PH_HIP(hipMemcpy(hkeys.data(), p.d_key, (size_t)n * 8, hipMemcpyDeviceToHost));
     int depth_limit = opt->max_depth ? opt->max_depth : kMaxDepth;
-    full_tree_levels(hkeys, p.leaf_cap, depth_limit, p.level_cap);
+    FullTree FT;
+    build_full_tree(hkeys, p.leaf_cap, depth_limit, FT);
+    p.level_cap = FT.level_cap;
     p.max_depth = (int)p.level_cap.size() - 1;
+    {
+        // the tree structure is fixed for the plan: upload it once
+        BoxArrays &bx = p.box;
+        auto up = [&](int32_t **dst, const std::vector<int32_t> &v) {
+            *dst = (int32_t *)dev_alloc(p, v.size() * 4);
+            PH_HIP(hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+        };
+        up(&bx.level, FT.level);
+        up(&bx.ax, FT.ax);
+        up(&bx.ay, FT.ay);
+        up(&bx.az, FT.az);
+        up(&bx.start, FT.start);
+        up(&bx.end, FT.end);
+        up(&bx.parent, FT.parent);
+        up(&bx.child, FT.child);
+        up(&bx.coll, FT.coll);
+    }
     p.level_base.assign(p.level_cap.size() + 1, 0);
     for (size_t l = 0; l < p.level_cap.size(); ++l) p.level_base[l + 1] = p.level_base[l] + p.level_cap[l];
     p.box_cap = p.level_base.back();
-    p.widest_level = *std::max_element(p.level_cap.begin(), p.level_cap.end());
     p.hw.resize(p.max_depth + 1);
     for (int l = 0; l <= p.max_depth; ++l) p.hw[l] = p.cube_size / std::ldexp(1.0, l + 1);
     // far-field operators
@@ -666,20 +718,18 @@ ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, 
             int32_t *fields[PH_BOX_FIELDS] = {p.box.level, p.box.ax, p.box.ay, p.box.az, p.box.s_first,
                                               p.box.s_cnt, p.box.t_first, p.box.t_cnt, p.box.parent,
                                               p.box.flags};
-            std::vector<int32_t> col;
-            tab.assign((size_t)nb * PH_BOX_FIELDS, 0);
+            // boxes of the per-call tree (the plan's tree pruned), level by level in Morton order
+            std::vector<std::vector<int32_t>> cols(PH_BOX_FIELDS, std::vector<int32_t>(nb));
+            for (int f = 0; f < PH_BOX_FIELDS; ++f)
+                PH_HIP(hipMemcpy(cols[f].data(), fields[f], (size_t)nb * 4, hipMemcpyDeviceToHost));
             int64_t row = 0;
-            for (int l = 0; l <= p.max_depth; ++l) {
-                int32_t c = p.h_sc.lvl_count[l], st = p.h_sc.lvl_start[l];
-                if (c <= 0) continue;
-                col.resize(c);
-                for (int f = 0; f < PH_BOX_FIELDS; ++f) {
-                    PH_HIP(hipMemcpy(col.data(), fields[f] + st, (size_t)c * 4, hipMemcpyDeviceToHost));
-                    for (int32_t k = 0; k < c; ++k) tab[(size_t)(row + k) * PH_BOX_FIELDS + f] = col[k];
-                }
-                row += c;
+            tab.reserve((size_t)nb * PH_BOX_FIELDS);
+            for (int64_t k = 0; k < nb; ++k) {
+                if (!(cols[9][k] & kBoxExists)) continue;
+                for (int f = 0; f < PH_BOX_FIELDS; ++f) tab.push_back(cols[f][k]);
+                ++row;
             }
-            *n_out = nb;
+            *n_out = row;
             size_t bytes = std::min<size_t>(tab.size() * 4, cap_bytes > 0 ? (size_t)cap_bytes : 0);
             if (bytes && dst) std::memcpy(dst, tab.data(), bytes);
             break;

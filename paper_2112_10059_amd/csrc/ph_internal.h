@@ -35,8 +35,9 @@ constexpr int kNumM2L = 316;                    // 7^3 - 3^3 well-separated offs
 constexpr int kMaxLattice = 512;                // q <= 8
 constexpr int kMaxShell = 6 * 8 * 8 + 2;        // shell of q+1 <= 9 points per edge
 
-// Box flag bits
-constexpr int kBoxLeaf = 1;
+// Box flag bits (per call)
+constexpr int kBoxLeaf = 1;    // a leaf of the per-call tree
+constexpr int kBoxExists = 2;  // the box belongs to the per-call tree
 
 // Device-resident per-call scalars (one struct, one allocation)
 struct CallScalars {
@@ -60,17 +61,20 @@ struct CallScalars {
                                         // grid l2p multiply-adds, grid p2m multiply-adds
 };
 
-// Box table (structure of arrays, capacity box_cap)
+// Box table (structure of arrays, capacity box_cap).  Structure fields come from the
+// plan's tree over all points; per-call fields mark the pruned per-call tree.
 struct BoxArrays {
+    // plan time
     int32_t *level = nullptr;
     int32_t *ax = nullptr, *ay = nullptr, *az = nullptr;
-    int32_t *s_first = nullptr, *s_cnt = nullptr, *t_first = nullptr, *t_cnt = nullptr;
+    int32_t *start = nullptr, *end = nullptr;  // range of the box in the sorted point order
     int32_t *parent = nullptr;
-    int32_t *flags = nullptr;
     int32_t *child = nullptr;       // box_cap x 8, -1 if absent
     int32_t *coll = nullptr;        // box_cap x 27 colleagues, -1 if absent
-    int4 *child_tmp = nullptr;      // per-level scratch: (cap of widest level) x 8 child ranges
-    uint64_t *child_cnt = nullptr;  // per-level scratch: packed (children | children with sources << 32)
+    // per call (boxes outside the per-call tree have zero counts and no flags)
+    int32_t *s_first = nullptr, *s_cnt = nullptr, *t_first = nullptr, *t_cnt = nullptr;
+    int32_t *flags = nullptr;
+    uint32_t *srcflag = nullptr;    // scan scratch: box holds selected sources (box_cap + 1)
     int32_t *src_rank = nullptr;    // rank of a box among its level's boxes with sources (-1 if none)
     int32_t *src_box = nullptr;     // per-level slots: box of each source rank
 };
@@ -147,7 +151,6 @@ struct Plan {
     std::vector<int64_t> level_cap; // max boxes per level (from the tree over all points)
     std::vector<int64_t> level_base;// first slot of each level in the box table
     int64_t box_cap = 0;
-    int64_t widest_level = 0;
     OperatorsDev ops;
     std::vector<double> hw;         // half-width of boxes per level
 
@@ -162,6 +165,7 @@ struct Plan {
     void *d_s_dat = nullptr;        // sources: (x, y, z, q = w * I * 2^-e), float4 or double4
     void *d_t_dat = nullptr;        // targets: (x, y, z, self = c_self * I * 2^-e or 0)
     int32_t *d_s_cell = nullptr, *d_t_cell = nullptr; // packed cell indices (grid mode)
+    void *d_t_far = nullptr;        // far field of targets whose leaf has near sources
     BoxArrays box;
     Lists lists;
     void *d_phi = nullptr;          // box_cap x n_lam upward densities
