@@ -26,10 +26,9 @@ namespace {
 template <class T>
 __global__ void p2m_kernel(FmmArgs<T> a, int level)
 {
-    const int32_t i = blockIdx.x;
-    if (i >= a.sc->lvl_count[level]) return;
-    const int32_t b = a.lt.base[level] + i;
-    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.s_cnt[b] == 0) return;
+  for (int32_t rk = blockIdx.x; rk < a.sc->lvl_src[level]; rk += gridDim.x) {
+    const int32_t b = a.bx.src_box[a.lt.base[level] + rk];
+    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.s_cnt[b] == 0) continue;
     __shared__ V4<T> tile[128];
     __shared__ T chk[kMaxShell];
     __shared__ int32_t rloc[128];
@@ -60,7 +59,7 @@ __global__ void p2m_kernel(FmmArgs<T> a, int level)
             if (li < a.n_lam) a.phi[(size_t)b * a.n_lam + li] = accg[k];
         }
         if (a.work && threadIdx.x == 0) atomicAdd(&a.work[9], (unsigned long long)sn * a.n_lam);
-        return;
+        continue;
     }
     const double hw = a.lt.hw[level];
     T cx, cy, cz;
@@ -97,46 +96,7 @@ __global__ void p2m_kernel(FmmArgs<T> a, int level)
         a.phi[(size_t)b * a.n_lam + li] = s;
     }
     if (a.work && threadIdx.x == 0) atomicAdd(&a.work[3], (unsigned long long)sn * a.n_sig);
-}
-
-// ---------------------------------------------------------------- M2M
-
-template <class T>
-__global__ void m2m_kernel(FmmArgs<T> a, int level)
-{
-    const int32_t i = blockIdx.x;
-    if (i >= a.sc->lvl_count[level]) return;
-    const int32_t b = a.lt.base[level] + i;
-    if ((a.bx.flags[b] & kBoxLeaf) || a.bx.s_cnt[b] == 0) return;
-    __shared__ T cphi[8 * kMaxLattice];
-    __shared__ int32_t chs[8];
-    if (threadIdx.x < 8) {
-        const int32_t c = a.bx.child[(size_t)b * 8 + threadIdx.x];
-        chs[threadIdx.x] = (c >= 0 && a.bx.s_cnt[c] > 0) ? c : -1;
-    }
-    __syncthreads();
-    for (int o = 0; o < 8; ++o) {
-        const int32_t c = chs[o];
-        for (int li = threadIdx.x; li < a.n_lam; li += blockDim.x)
-            cphi[o * a.n_lam + li] = c >= 0 ? a.phi[(size_t)c * a.n_lam + li] : T(0);
-    }
-    __syncthreads();
-    const size_t nn = (size_t)a.n_lam * a.n_lam;
-    for (int li = threadIdx.x; li < a.n_lam; li += blockDim.x) {
-        T s = 0;
-        for (int o = 0; o < 8; ++o) {
-            if (chs[o] < 0) continue;
-            const T *M = a.m2m + ((size_t)(level + 1) * 8 + o) * nn;
-            const T *x = cphi + o * a.n_lam;
-            for (int j = 0; j < a.n_lam; ++j) s += M[(size_t)j * a.n_lam + li] * x[j];
-        }
-        a.phi[(size_t)b * a.n_lam + li] = s;
-    }
-    if (a.work && threadIdx.x == 0) {
-        unsigned long long k = 0;
-        for (int o = 0; o < 8; ++o) k += chs[o] >= 0 ? 1 : 0;
-        atomicAdd(&a.work[6], k);
-    }
+  }
 }
 
 // ---------------------------------------------------------------- leaf evaluation
@@ -178,8 +138,8 @@ __device__ __forceinline__ double lane_bcast(double v, int j)
 // Far field of every target leaf (lattice or shell L2P, W list) plus the own-cell term.
 // Leaves without near sources are finished here; the others leave their far field in
 // t_far for the near-field kernel.
-template <class T, class TO>
-__global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far)
+template <class T, class TO, bool GRIDF>
+__global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far, int role)
 {
     const int32_t b = blockIdx.x;
     int level;
@@ -187,11 +147,13 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict_
     if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.t_cnt[b] == 0) return;
     __shared__ T uvec[kMaxLattice];
     __shared__ T wphi[kMaxLattice];
-    __shared__ V4<T> shp[kMaxShell];  // shell point position and its intensity psi
-    __shared__ V4<T> tile[64];
+    __shared__ V4<T> shp[GRIDF ? 1 : kMaxShell];  // shell point position and its intensity psi
     const int nl = a.n_lam, ns = a.n_sig;
     const bool has_far = level >= 2;
     const int gm = has_far ? a.grid_m[level] : 0;
+    // role 1: boxes with a lattice operator (or no far field); role 2: the others; role 0: all
+    if (role == 1 && has_far && gm == 0) return;
+    if (role == 2 && !(has_far && gm == 0)) return;
     const double hw = a.lt.hw[level];
     T cx, cy, cz;
     box_centre(a, b, hw, cx, cy, cz);
@@ -199,7 +161,7 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict_
     if (has_far) {
         for (int li = threadIdx.x; li < nl; li += blockDim.x) uvec[li] = a.u[(size_t)b * nl + li];
         __syncthreads();
-        if (gm == 0) {
+        if (!GRIDF && gm == 0) {
             const T *U = a.uc2e_rm + (size_t)level * nl * ns;
             for (int sg = threadIdx.x; sg < ns; sg += blockDim.x) {
                 T s = 0;
@@ -235,14 +197,14 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict_
         else x.x = x.y = x.z = x.w = T(0);
         T far = 0;
         if (has_far && act) {
-            if (gm > 0) {
+            if (GRIDF || gm > 0) {
                 const T *G = a.grid_g + a.grid_off[level];
                 const int R = gm * gm * gm;
                 const int r = local_cell(a, a.t_cell[tf + t], b, gm);
                 for (int li = 0; li < nl; ++li) far += G[(size_t)li * R + r] * uvec[li];
-            } else {
+            } else if (!GRIDF) {
                 for (int sg = 0; sg < ns; ++sg) {
-                    const V4<T> q = shp[sg];
+                    const V4<T> q = shp[GRIDF ? 0 : sg];
                     const T dx = x.x - q.x, dy = x.y - q.y, dz = x.z - q.z;
                     far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * q.w;
                 }
@@ -282,7 +244,7 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict_
 // wave w sums the U entries w, w+4, ...; each wave keeps a Kahan-compensated FP32 sum
 // (FP64 in the FP64 form); the partial sums, the far field and the own-cell term are
 // combined in FP64 in a fixed order.  Sources are broadcast lane by lane from registers.
-template <class T, class TO>
+template <class T, class TO, bool GUARD>
 __global__ __launch_bounds__(256) void near_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
                                                    const T *__restrict__ t_far)
 {
@@ -316,7 +278,7 @@ __global__ __launch_bounds__(256) void near_kernel(FmmArgs<T> a, TO *__restrict_
                             yw = lane_bcast(y.w, j);
                     const T dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
                     const T r2 = dx * dx + dy * dy + dz * dz;
-                    if (act && r2 > T(0)) near.add(kernel_eval<true>(r2, a.kp) * yw);
+                    if (act && r2 > T(0)) near.add(kernel_eval<GUARD>(r2, a.kp) * yw);
                 }
             }
         }
@@ -338,17 +300,26 @@ void fmm_upward_t(Plan &p, hipStream_t s)
     const int D = p.max_depth;
     const int threads = std::max(128, ((p.n_lam + 63) / 64) * 64);
     for (int l = 2; l <= D; ++l)
-        p2m_kernel<T><<<(unsigned)p.level_cap[l], 128, 0, s>>>(a, l);
-    for (int l = D - 1; l >= 2; --l)
-        m2m_kernel<T><<<(unsigned)p.level_cap[l], threads, 0, s>>>(a, l);
+        p2m_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 4096), 128, 0, s>>>(a, l);
+    for (int l = D - 1; l >= 2; --l) fmm_m2m_level(p, l, s);
 }
 
 template <class T>
 void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
-    leaf_kernel<T, T><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far);
-    near_kernel<T, T><<<(unsigned)p.box_cap, 256, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
+    bool shell_levels = !p.grid_mode;
+    for (int l = 2; l <= p.max_depth; ++l) shell_levels = shell_levels || p.grid_m[l] == 0;
+    if (p.grid_mode) {
+        leaf_kernel<T, T, true><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far, 1);
+        if (shell_levels) leaf_kernel<T, T, false><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far, 2);
+    } else {
+        leaf_kernel<T, T, false><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far, 0);
+    }
+    if (p.near_guard)
+        near_kernel<T, T, true><<<(unsigned)p.box_cap, 256, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
+    else
+        near_kernel<T, T, false><<<(unsigned)p.box_cap, 256, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
 }
 
 }  // namespace

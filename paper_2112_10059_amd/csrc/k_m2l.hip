@@ -1,5 +1,5 @@
-// Downward pass: well-separated translations (M2L) as one MFMA GEMM per level,
-// then a per-box gather that adds the parent's field (L2L) and coarse-leaf sources (P2L).
+// Translation operators on the matrix cores: M2M (upward), L2L and M2L (downward) as
+// stacked-operator GEMMs per level, then a per-box gather in a fixed order.
 //
 // For every well-separated offset t (316 per level) the translation is a dense
 // n_lam x n_lam kernel matrix between lattices, K(c_B + h Lambda_i, c_A + h Lambda_j)
@@ -51,91 +51,104 @@ constexpr int kTile = 64;     // tile of source boxes (rows of Y) and of stacked
 constexpr int kTK = kGemmK;   // K chunk staged in LDS
 constexpr int kPad = 4;       // LDS row padding (bank spread)
 
-// Y[col][m] = sum_k phi_{src_box(r0 + col)}[k] * M_all[m][k],  m < M = 316 n_lam
-template <class T>
-__global__ __launch_bounds__(256) void m2l_gemm_kernel(const T *__restrict__ M_all, int k_pad, int M, int nl,
-                                                       const T *__restrict__ phi, const int32_t *__restrict__ src_box,
-                                                       const CallScalars *__restrict__ sc, int level, int32_t lvl_base,
-                                                       int32_t r0, int32_t ccap, T *__restrict__ Y)
+enum { kModeM2L = 0, kModeL2L = 1, kModeM2M = 2 };
+
+// Translation GEMM on the matrix cores, out^T = X^T Op^T with Op (M x kp, row-major) a
+// stacked translation operator and X (kp x ncols) the gathered columns
+//   X[:, n] = vec of the n-th listed box of the level (rank r0 + n), out[n][m] row per box:
+//   M2L: phi of the boxes with sources, Op = 316 stacked offsets   -> Y
+//   L2L: u of the split boxes with targets, Op = 8 stacked octants -> Z (parent to child c)
+//   M2M: phi of the boxes with sources, Op = 8 stacked octants     -> Z (child c to parent)
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op, int kp, int M, int nl,
+                                                    const T *__restrict__ vec, const int32_t *__restrict__ list,
+                                                    const int32_t *__restrict__ count, int32_t lvl_base, int32_t r0,
+                                                    int32_t ccap, const int32_t *__restrict__ child,
+                                                    const int32_t *__restrict__ s_cnt, const int32_t *__restrict__ flags,
+                                                    T *__restrict__ out)
 {
-    __shared__ T As[kTK][kTile + kPad];  // phi^T tile, k-major
-    __shared__ T Bs[kTK][kTile + kPad];  // M_all^T tile, k-major
-    const int32_t ns = sc->lvl_src[level];
-    const int32_t ncols = min(ccap, ns - r0);
+    __shared__ T As[kTK][kTile + kPad];  // X^T tile, k-major
+    __shared__ T Bs[kTK][kTile + kPad];  // Op^T tile, k-major
+    __shared__ int32_t boxes[kTile];
+    const int32_t ncols = min(ccap, *count - r0);
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wn = w >> 1, wm = w & 1;
     using acc_t = typename Mfma<T>::acc_t;
-    // blockIdx.y strides over the tiles of source boxes (a bounded grid for any count)
+    // blockIdx.y strides over the tiles of columns (a bounded grid for any count)
     for (int n0 = blockIdx.y * kTile; n0 < ncols; n0 += gridDim.y * kTile) {
-    acc_t acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    for (int k0 = 0; k0 < k_pad; k0 += kTK) {
         __syncthreads();
-        for (int e = t; e < kTK * kTile; e += 256) {
-            const int n = e / kTK, k = e % kTK;
-            const int gn = n0 + n, gk = k0 + k;
-            T v = T(0);
-            if (gn < ncols && gk < nl) v = phi[(size_t)src_box[lvl_base + r0 + gn] * nl + gk];
-            As[k][n] = v;
-            const int gm = m0 + n;
-            Bs[k][n] = gm < M ? M_all[(size_t)gm * k_pad + gk] : T(0);
-        }
-        __syncthreads();
+        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[lvl_base + r0 + n0 + t] : -1;
+        acc_t acc[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int k0 = 0; k0 < kp; k0 += kTK) {
+            __syncthreads();
+            for (int e = t; e < kTK * kTile; e += 256) {
+                const int n = e / kTK, k = e % kTK;
+                const int gk = k0 + k;
+                const int32_t bx = boxes[n];
+                T v = T(0);
+                if (bx >= 0 && gk < nl) v = vec[(size_t)bx * nl + gk];
+                As[k][n] = v;
+                const int gm = m0 + n;
+                Bs[k][n] = gm < M ? Op[(size_t)gm * kp + gk] : T(0);
+            }
+            __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < kTK; ks += 4) {
-            const int kk = ks + (lane >> 4);
-            T a[2], b[2];
-            for (int i = 0; i < 2; ++i) a[i] = As[kk][wn * 32 + i * 16 + (lane & 15)];
-            for (int j = 0; j < 2; ++j) b[j] = Bs[kk][wm * 32 + j * 16 + (lane & 15)];
-            for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
-        }
-    }
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
-            const int gm = m0 + wm * 32 + j * 16 + (lane & 15);
-            for (int r = 0; r < 4; ++r) {
-                const int gn = n0 + wn * 32 + i * 16 + Mfma<T>::row(lane, r);
-                if (gn < ncols && gm < M) Y[(size_t)gn * M + gm] = acc[i][j][r];
+            for (int ks = 0; ks < kTK; ks += 4) {
+                const int kk = ks + (lane >> 4);
+                T a[2], b[2];
+                for (int i = 0; i < 2; ++i) a[i] = As[kk][wn * 32 + i * 16 + (lane & 15)];
+                for (int j = 0; j < 2; ++j) b[j] = Bs[kk][wm * 32 + j * 16 + (lane & 15)];
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
             }
         }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                const int gm = m0 + wm * 32 + j * 16 + (lane & 15);
+                for (int r = 0; r < 4; ++r) {
+                    const int nl_ = wn * 32 + i * 16 + Mfma<T>::row(lane, r);
+                    const int gn = n0 + nl_;
+                    if (gn >= ncols || gm >= M) continue;
+                    out[(size_t)gn * M + gm] = acc[i][j][r];
+                }
+            }
     }
 }
 
-// u_B = [first chunk: l2l u_parent + X-list sources] + sum over V(B) in this chunk of Y
+// One wave per target box B (four per workgroup):
+//   u_B = [first chunk: Z(parent, octant of B) + X-list sources of B] + sum over V(B) in this chunk of Y.
+// V(B) = children of the parent's colleagues not adjacent to B: each lane resolves one of the
+// 216 candidates, a ballot marks those with sources in this chunk, and the wave walks the
+// set bits in candidate order, broadcasting rank and offset slot from the owning lane.
 template <class T>
-__global__ void down_gather_kernel(FmmArgs<T> a, int level, const T *__restrict__ Y, int M, int32_t r0,
-                                   int32_t ccap, int first)
+__global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int level, const T *__restrict__ Y, int M,
+                                                          int32_t r0, int32_t ccap, int first,
+                                                          const T *__restrict__ Z)
 {
-    const int32_t i = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= a.sc->lvl_count[level]) return;
     const int32_t b = a.lt.base[level] + i;
     if (a.bx.t_cnt[b] == 0) return;
     const int32_t ns = a.sc->lvl_src[level];
     const int32_t ncols = min(ccap, ns - r0);
     if (!first && ncols <= 0) return;
-    __shared__ T vec[kMaxLattice];
-    __shared__ V4<T> tile[128];
-    __shared__ int32_t cand[216];
     const int nl = a.n_lam;
-    const size_t nn = (size_t)nl * nl;
-    T acc[4] = {0, 0, 0, 0};
-    unsigned long long n_m2l = 0, n_p2l = 0;
     const int32_t par = a.bx.parent[b];
+    T acc[kMaxLattice / 64];
+    const int nk = (nl + 63) / 64;
+    for (int k = 0; k < kMaxLattice / 64; ++k) acc[k] = T(0);
+    unsigned long long n_m2l = 0, n_p2l = 0;
     if (first) {
         if (level >= 3) {
-            for (int li = threadIdx.x; li < nl; li += blockDim.x) vec[li] = a.u[(size_t)par * nl + li];
-            __syncthreads();
             const int oct = ((a.bx.ax[b] & 1) << 2) | ((a.bx.ay[b] & 1) << 1) | (a.bx.az[b] & 1);
-            const T *Ml = a.l2l + ((size_t)level * 8 + oct) * nn;
-            for (int k = 0; k < 4; ++k) {
-                const int li = threadIdx.x + k * blockDim.x;
-                if (li >= nl) break;
-                T s = 0;
-                for (int j = 0; j < nl; ++j) s += Ml[(size_t)j * nl + li] * vec[j];
-                acc[k] = s;
+            const T *z = Z + ((size_t)a.bx.tpar_rank[par] * 8 + oct) * nl;
+            for (int k = 0; k < nk; ++k) {
+                const int li = lane + 64 * k;
+                if (li < nl) acc[k] = z[li];
             }
         }
         // X list: sources of coarser leaves straight onto the check points
@@ -149,63 +162,58 @@ __global__ void down_gather_kernel(FmmArgs<T> a, int level, const T *__restrict_
                 const int32_t C = a.L.x[e];
                 const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
                 n_p2l += (unsigned long long)sn * nl;
-                for (int base = 0; base < sn; base += 128) {
-                    const int m = min(128, sn - base);
-                    __syncthreads();
-                    for (int q = threadIdx.x; q < m; q += blockDim.x) tile[q] = a.s_dat[sf + base + q];
-                    __syncthreads();
-                    for (int k = 0; k < 4; ++k) {
-                        const int li = threadIdx.x + k * blockDim.x;
+                for (int j = 0; j < sn; ++j) {
+                    const V4<T> y = a.s_dat[sf + j];
+                    for (int k = 0; k < nk; ++k) {
+                        const int li = lane + 64 * k;
                         if (li >= nl) break;
-                        const T px = cx + h * a.lat[3 * li], py = cy + h * a.lat[3 * li + 1],
-                                pz = cz + h * a.lat[3 * li + 2];
-                        T s = 0;
-                        for (int j = 0; j < m; ++j) {
-                            const V4<T> y = tile[j];
-                            const T ddx = px - y.x, ddy = py - y.y, ddz = pz - y.z;
-                            s += kernel_eval<true>(ddx * ddx + ddy * ddy + ddz * ddz, a.kp) * y.w;
-                        }
-                        acc[k] += s;
+                        const T ddx = cx + h * a.lat[3 * li] - y.x, ddy = cy + h * a.lat[3 * li + 1] - y.y,
+                                ddz = cz + h * a.lat[3 * li + 2] - y.z;
+                        acc[k] += kernel_eval<true>(ddx * ddx + ddy * ddy + ddz * ddz, a.kp) * y.w;
                     }
                 }
             }
         }
     } else {
-        for (int k = 0; k < 4; ++k) {
-            const int li = threadIdx.x + k * blockDim.x;
+        for (int k = 0; k < nk; ++k) {
+            const int li = lane + 64 * k;
             if (li < nl) acc[k] = a.u[(size_t)b * nl + li];
         }
     }
-    // V list, resolved in parallel: candidate c = (parent colleague c/8, child octant c%8)
     const int bx0 = a.bx.ax[b], by0 = a.bx.ay[b], bz0 = a.bx.az[b];
-    for (int c = threadIdx.x; c < 216; c += blockDim.x) {
-        const int32_t P = a.bx.coll[(size_t)par * 27 + (c >> 3)];
-        const int32_t A = P >= 0 ? a.bx.child[(size_t)P * 8 + (c & 7)] : -1;
-        int32_t code = -1;
-        if (A >= 0) {
-            const int32_t rk = a.bx.src_rank[A] - r0;
-            const int dx = a.bx.ax[A] - bx0, dy = a.bx.ay[A] - by0, dz = a.bx.az[A] - bz0;
-            const bool far = !(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1);
-            if (far && a.bx.src_rank[A] >= 0 && rk >= 0 && rk < ncols) code = rk * kNumM2L + m2l_slot(dx, dy, dz);
+    for (int c0 = 0; c0 < 216; c0 += 64) {
+        const int c = c0 + lane;
+        int32_t code = -1;  // rank * 316 + slot
+        if (c < 216) {
+            const int32_t Q = a.bx.coll[(size_t)par * 27 + (c >> 3)];
+            const int32_t A = Q >= 0 ? a.bx.child[(size_t)Q * 8 + (c & 7)] : -1;
+            if (A >= 0) {
+                const int32_t rk = a.bx.src_rank[A] - r0;
+                if (a.bx.src_rank[A] >= 0 && rk >= 0 && rk < ncols) {
+                    const int dx = a.bx.ax[A] - bx0, dy = a.bx.ay[A] - by0, dz = a.bx.az[A] - bz0;
+                    if (!(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1))
+                        code = rk * kNumM2L + m2l_slot(dx, dy, dz);
+                }
+            }
         }
-        cand[c] = code;
-    }
-    __syncthreads();
-    for (int c = 0; c < 216; ++c) {
-        const int32_t code = cand[c];
-        if (code < 0) continue;
-        ++n_m2l;
-        const T *y = Y + (size_t)(code / kNumM2L) * M + (size_t)(code % kNumM2L) * nl;
-        for (int k = 0; k < 4; ++k) {
-            const int li = threadIdx.x + k * blockDim.x;
-            if (li < nl) acc[k] += y[li];
+        uint64_t mask = __ballot(code >= 0);
+        while (mask) {
+            const int src_lane = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            const int32_t cd = __builtin_amdgcn_readlane(code, src_lane);
+            ++n_m2l;
+            const T *y = Y + (size_t)(cd / kNumM2L) * M + (size_t)(cd % kNumM2L) * nl;
+            for (int k = 0; k < nk; ++k) {
+                const int li = lane + 64 * k;
+                if (li < nl) acc[k] += y[li];
+            }
         }
     }
-    for (int k = 0; k < 4; ++k) {
-        const int li = threadIdx.x + k * blockDim.x;
+    for (int k = 0; k < nk; ++k) {
+        const int li = lane + 64 * k;
         if (li < nl) a.u[(size_t)b * nl + li] = acc[k];
     }
-    if (a.work && threadIdx.x == 0) {
+    if (a.work && lane == 0) {
         if (n_m2l) atomicAdd(&a.work[5], n_m2l);
         if (n_p2l) atomicAdd(&a.work[4], n_p2l);
         if (first && level >= 3) atomicAdd(&a.work[7], 1ull);
@@ -218,21 +226,76 @@ void fmm_downward_t(Plan &p, hipStream_t s)
     FmmArgs<T> a = make_args<T>(p);
     const int nl = p.n_lam;
     const int M = kNumM2L * nl;
-    const int threads = nl <= 64 ? 64 : (nl <= 128 ? 128 : 256);
     for (int l = 2; l <= p.max_depth; ++l) {
         const int64_t cap = p.level_cap[l];
+        if (l >= 3) {
+            // Z = L2L_all (8 n_lam x n_lam) applied to every split box with targets at level l - 1
+            const int Mz = 8 * nl;
+            const int64_t pcap = p.level_cap[l - 1];
+            dim3 gz((Mz + kTile - 1) / kTile, (unsigned)std::min<int64_t>(1024, (pcap + kTile - 1) / kTile));
+            const T *Lop = (const T *)p.ops.l2l + (size_t)l * Mz * p.k_pad;
+            tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(Lop, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box,
+                                                         &p.d_sc->lvl_tpar[l - 1], (int32_t)p.level_base[l - 1], 0,
+                                                         (int32_t)pcap, nullptr, nullptr, nullptr, (T *)p.d_z);
+        }
         const int64_t ccap = std::min<int64_t>((int64_t)p.y_cap_cols, cap);
         const int nchunk = (int)((cap + ccap - 1) / ccap);
         const T *Ml = (const T *)p.ops.m2l + (size_t)l * M * p.k_pad;
         for (int c = 0; c < nchunk; ++c) {
             const int32_t r0 = (int32_t)(c * ccap);
-            dim3 g((M + kTile - 1) / kTile, (unsigned)std::min<int64_t>(32, (ccap + kTile - 1) / kTile));
-            m2l_gemm_kernel<T><<<g, 256, 0, s>>>(Ml, p.k_pad, M, nl, (const T *)p.d_phi, p.box.src_box, p.d_sc, l,
-                                                 (int32_t)p.level_base[l], r0, (int32_t)ccap, (T *)p.d_y);
-            down_gather_kernel<T><<<(unsigned)cap, threads, 0, s>>>(a, l, (const T *)p.d_y, M, r0, (int32_t)ccap,
-                                                                     c == 0 ? 1 : 0);
+            dim3 g((M + kTile - 1) / kTile, (unsigned)std::min<int64_t>(256, (ccap + kTile - 1) / kTile));
+            tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>(Ml, p.k_pad, M, nl, (const T *)p.d_phi, p.box.src_box,
+                                                        &p.d_sc->lvl_src[l], (int32_t)p.level_base[l], r0,
+                                                        (int32_t)ccap, nullptr, nullptr, nullptr, (T *)p.d_y);
+            down_gather_kernel<T><<<(unsigned)((cap + 3) / 4), 256, 0, s>>>(a, l, (const T *)p.d_y, M, r0,
+                                                                             (int32_t)ccap, c == 0 ? 1 : 0,
+                                                                             (const T *)p.d_z);
         }
     }
+}
+
+// phi_P = sum over children c with sources of W[child c][c n_lam + i], in octant order
+template <class T>
+__global__ void m2m_gather_kernel(FmmArgs<T> a, int level, const T *__restrict__ W)
+{
+    const int nl = a.n_lam;
+    for (int32_t rk = blockIdx.x; rk < a.sc->lvl_src[level]; rk += gridDim.x) {
+        const int32_t P = a.bx.src_box[a.lt.base[level] + rk];
+        if (a.bx.flags[P] & kBoxLeaf) continue;
+        T acc[4] = {0, 0, 0, 0};
+        for (int o = 0; o < 8; ++o) {
+            const int32_t C = a.bx.child[(size_t)P * 8 + o];
+            if (C < 0 || a.bx.src_rank[C] < 0) continue;
+            const T *w = W + ((size_t)a.bx.src_rank[C] * 8 + o) * nl;
+            for (int k = 0; k < 4; ++k) {
+                const int li = threadIdx.x + k * blockDim.x;
+                if (li < nl) acc[k] += w[li];
+            }
+        }
+        for (int k = 0; k < 4; ++k) {
+            const int li = threadIdx.x + k * blockDim.x;
+            if (li < nl) a.phi[(size_t)P * nl + li] = acc[k];
+        }
+    }
+}
+
+template <class T>
+void m2m_level_t(Plan &p, int l, hipStream_t s)
+{
+    // W = M2M_all (8 n_lam x n_lam) applied to every box with sources at level l + 1,
+    // then each non-leaf box with sources at level l sums its children's columns
+    FmmArgs<T> a = make_args<T>(p);
+    const int nl = p.n_lam;
+    const int Mw = 8 * nl;
+    const int64_t ccap = p.level_cap[l + 1];
+    dim3 g((Mw + kTile - 1) / kTile, (unsigned)std::min<int64_t>(1024, (ccap + kTile - 1) / kTile));
+    const T *Op = (const T *)p.ops.m2m + (size_t)(l + 1) * Mw * p.k_pad;
+    tgemm_kernel<T, kModeM2M><<<g, 256, 0, s>>>(Op, p.k_pad, Mw, nl, (const T *)p.d_phi, p.box.src_box,
+                                                &p.d_sc->lvl_src[l + 1], (int32_t)p.level_base[l + 1], 0,
+                                                (int32_t)ccap, nullptr, nullptr, nullptr, (T *)p.d_z);
+    const int threads = nl <= 64 ? 64 : (nl <= 128 ? 128 : 256);
+    m2m_gather_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 8192), threads, 0, s>>>(a, l,
+                                                                                              (const T *)p.d_z);
 }
 
 }  // namespace
@@ -241,6 +304,12 @@ void fmm_downward(Plan &p, hipStream_t s)
 {
     if (p.precision == PH_FP64) fmm_downward_t<double>(p, s);
     else fmm_downward_t<float>(p, s);
+}
+
+void fmm_m2m_level(Plan &p, int l, hipStream_t s)
+{
+    if (p.precision == PH_FP64) m2m_level_t<double>(p, l, s);
+    else m2m_level_t<float>(p, l, s);
 }
 
 }  // namespace ph

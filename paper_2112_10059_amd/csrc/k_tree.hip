@@ -44,14 +44,15 @@ __device__ __forceinline__ uint64_t scan_at(const uint64_t *__restrict__ scanned
 __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int leaf_cap, int max_depth,
                                    const uint64_t *__restrict__ scanned, int64_t n, CallScalars *__restrict__ sc)
 {
-    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t f0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t f = f0 < nbox ? f0 : nbox - 1;  // whole waves reach the reduction below
+    const bool mine = f0 < nbox;
     const uint64_t total = sc->packed_total;
     if (f == 0) {
         for (int l = 0; l <= li.depth; ++l) sc->lvl_count[l] = li.cap[l];
         for (int l = 0; l <= li.depth + 1; ++l) sc->lvl_start[l] = li.base[l];
         bx.srcflag[nbox] = 0;
     }
-    if (f >= nbox) return;
     const int32_t st = bx.start[f], en = bx.end[f];
     const uint64_t a = scan_at(scanned, st, n, total), b = scan_at(scanned, en, n, total);
     const int32_t s0 = (int32_t)(a & 0xffffffffu), t0 = (int32_t)(a >> 32);
@@ -66,29 +67,48 @@ __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int
     }
     // split in the plan's tree iff it holds more than leaf_cap points above the depth limit
     const bool split = exists && (en - st > leaf_cap) && (bx.level[f] < max_depth) && (max(sn, tn) > leaf_cap);
-    bx.s_first[f] = exists ? s0 : 0;
-    bx.s_cnt[f] = exists ? sn : 0;
-    bx.t_first[f] = exists ? t0 : 0;
-    bx.t_cnt[f] = exists ? tn : 0;
-    bx.flags[f] = exists ? (kBoxExists | (split ? 0 : kBoxLeaf)) : 0;
-    bx.srcflag[f] = (exists && sn > 0) ? 1u : 0u;
+    if (mine) {
+        bx.s_first[f] = exists ? s0 : 0;
+        bx.s_cnt[f] = exists ? sn : 0;
+        bx.t_first[f] = exists ? t0 : 0;
+        bx.t_cnt[f] = exists ? tn : 0;
+        bx.flags[f] = exists ? (kBoxExists | (split ? 0 : kBoxLeaf)) : 0;
+        // low word: box with sources; high word: split box with targets (parent of target boxes)
+        bx.srcflag[f] = (uint64_t)((exists && sn > 0) ? 1u : 0u) | ((uint64_t)((split && tn > 0) ? 1u : 0u) << 32);
+    }
+    // lowest level holding a leaf with sources, as max of (depth + 1 - level), one atomic per wave
+    int v = (mine && exists && !split && sn > 0) ? (li.depth + 1 - bx.level[f]) : 0;
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(&sc->min_leafsrc_level, v);
 }
 
-// srcflag holds its exclusive scan: rank of every box with sources within its level
+// srcflag holds its exclusive scan: per level, the rank of every box with sources and of
+// every split box with targets (the parents whose local fields the next level needs)
 __global__ void tree_srcrank_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, CallScalars *__restrict__ sc)
 {
     const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nbox) return;
     const int l = bx.level[f];
     const int32_t base = li.base[l];
-    if (f == base) sc->lvl_src[l] = (int32_t)(bx.srcflag[li.base[l + 1]] - bx.srcflag[base]);
-    const bool has = bx.srcflag[f + 1] != bx.srcflag[f];
-    if (has) {
-        const int32_t rank = (int32_t)(bx.srcflag[f] - bx.srcflag[base]);
+    const uint64_t here = bx.srcflag[f], next = bx.srcflag[f + 1], first = bx.srcflag[base];
+    if (f == base) {
+        const uint64_t end = bx.srcflag[li.base[l + 1]];
+        sc->lvl_src[l] = (int32_t)((end & 0xffffffffu) - (first & 0xffffffffu));
+        sc->lvl_tpar[l] = (int32_t)((end >> 32) - (first >> 32));
+    }
+    if ((next & 0xffffffffu) != (here & 0xffffffffu)) {
+        const int32_t rank = (int32_t)((here & 0xffffffffu) - (first & 0xffffffffu));
         bx.src_rank[f] = rank;
         bx.src_box[base + rank] = f;
     } else {
         bx.src_rank[f] = -1;
+    }
+    if ((next >> 32) != (here >> 32)) {
+        const int32_t rank = (int32_t)((here >> 32) - (first >> 32));
+        bx.tpar_rank[f] = rank;
+        bx.tpar_box[base + rank] = f;
+    } else {
+        bx.tpar_rank[f] = -1;
     }
 }
 
@@ -122,7 +142,7 @@ __device__ __forceinline__ int32_t box_of_thread(const LevelInfo &li, const Call
 enum { kListU = 0, kListW = 1, kListX = 2 };
 
 template <class F>
-__device__ void enumerate_lists(const BoxArrays &bx, int32_t b, F &&emit)
+__device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_level, F &&emit)
 {
     if (bx.t_cnt[b] == 0) return;
     const bool leaf = bx.flags[b] & kBoxLeaf;
@@ -153,7 +173,8 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, F &&emit)
             }
         }
     }
-    // coarser leaves around the ancestors
+    // coarser leaves around the ancestors (none if every leaf with sources is this deep)
+    if (bx.level[b] <= min_leaf_level) return;
     const int32_t par = bx.parent[b];
     for (int32_t A = par; A >= 0; A = bx.parent[A]) {
         for (int d = 0; d < 27; ++d) {
@@ -176,8 +197,9 @@ __global__ void list_count_kernel(BoxArrays bx, LevelInfo li, const CallScalars 
     if (gid >= nbox) return;
     const int32_t b = box_of_thread(li, sc, gid);
     uint32_t nu = 0, nw = 0, nx = 0;
+    const int mll = li.depth + 1 - sc->min_leafsrc_level;
     if (b >= 0)
-        enumerate_lists(bx, b, [&](int kind, int32_t) {
+        enumerate_lists(bx, b, mll, [&](int kind, int32_t) {
             if (kind == kListU) ++nu;
             else if (kind == kListW) ++nw;
             else ++nx;
@@ -195,7 +217,8 @@ __global__ void list_fill_kernel(BoxArrays bx, LevelInfo li, CallScalars *__rest
     if (b < 0) return;
     uint32_t pu = L.u_off[gid], pw = L.w_off[gid], px = L.x_off[gid];
     bool over = false;
-    enumerate_lists(bx, b, [&](int kind, int32_t C) {
+    const int mll = li.depth + 1 - sc->min_leafsrc_level;
+    enumerate_lists(bx, b, mll, [&](int kind, int32_t C) {
         if (kind == kListU) {
             if (pu < (uint32_t)L.u_cap) L.u[pu] = C;
             else over = true;
@@ -234,7 +257,7 @@ void build_tree(Plan &p, hipStream_t s)
     const int32_t nbox = (int32_t)p.box_cap;
     const unsigned g = (unsigned)((nbox + 255) / 256);
     tree_status_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.leaf_cap, p.max_depth, p.d_flag, p.n, p.d_sc);
-    exclusive_scan_u32(p.box.srcflag, nbox + 1, p.d_scan_tmp, nullptr, s);
+    exclusive_scan_u64(p.box.srcflag, nbox + 1, p.d_scan_tmp, nullptr, s);
     tree_srcrank_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.d_sc);
 }
 

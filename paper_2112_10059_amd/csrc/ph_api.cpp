@@ -189,7 +189,9 @@ void alloc_workspace(Plan &p)
     b.t_first = (int32_t *)dev_alloc(p, B * 4);
     b.t_cnt = (int32_t *)dev_alloc(p, B * 4);
     b.flags = (int32_t *)dev_alloc(p, B * 4);
-    b.srcflag = (uint32_t *)dev_alloc(p, (B + 1) * 4);
+    b.srcflag = (uint64_t *)dev_alloc(p, (B + 1) * 8);
+    b.tpar_rank = (int32_t *)dev_alloc(p, B * 4);
+    b.tpar_box = (int32_t *)dev_alloc(p, B * 4);
     b.src_rank = (int32_t *)dev_alloc(p, B * 4);
     b.src_box = (int32_t *)dev_alloc(p, B * 4);
     Lists &L = p.lists;
@@ -213,6 +215,10 @@ void alloc_workspace(Plan &p)
         if (const char *env = std::getenv("PH_TRANSLATION_BUFFER_MB")) budget = (size_t)std::atoll(env) << 20;
         p.y_cap_cols = (size_t)std::max<int64_t>(64, std::min<int64_t>(widest2, (int64_t)(budget / col_bytes)));
         p.d_y = dev_alloc(p, p.y_cap_cols * col_bytes);
+        int64_t widest_par = 1;
+        for (int l = 2; l <= p.max_depth; ++l) widest_par = std::max<int64_t>(widest_par, p.level_cap[l]);
+        p.z_cap_cols = (size_t)widest_par;
+        p.d_z = dev_alloc(p, p.z_cap_cols * 8 * p.n_lam * rs);
     }
     p.d_srcbox_mark = (int32_t *)dev_alloc(p, B * 4);
     p.d_feat = (float *)dev_alloc(p, (size_t)B * 8 * 4);
@@ -232,7 +238,7 @@ void free_plan(Plan *p)
                     p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_scan_tmp, p->d_s_pos, p->d_t_pos, p->d_s_key,
                     p->d_t_key, p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
                     p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
-                    p->box.child, p->box.coll, p->box.start, p->box.end, p->box.srcflag, p->box.src_rank,
+                    p->box.child, p->box.coll, p->box.start, p->box.end, p->box.srcflag, p->box.src_rank, p->box.tpar_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->d_phi, p->d_u,
                     p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params, p->d_cell,
@@ -372,6 +378,8 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
             p.grid_n = (int)N;
         }
     }
+    // on a grid the closest distinct pair is h apart: the guarded form is needed only if (b - a) h < 1/4
+    p.near_guard = !(p.grid_mode && (p.gas.b - p.gas.a) * p.h >= 0.25);
     // tree bound from the tree over all points
     std::vector<uint64_t> hkeys(n);
     PH_HIP(hipMemcpy(hkeys.data(), p.d_key, (size_t)n * 8, hipMemcpyDeviceToHost));
@@ -416,7 +424,11 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         p.n_sig = H.n_sig;
         const int nl = p.n_lam, ns = p.n_sig, L = p.max_depth + 1;
         std::vector<double> rm((size_t)L * nl * ns, 0.0), cm((size_t)L * nl * ns, 0.0);
-        std::vector<double> m2m((size_t)L * 8 * nl * nl, 0.0), l2l((size_t)L * 8 * nl * nl, 0.0);
+        p.k_pad8 = ((8 * nl + kGemmK - 1) / kGemmK) * kGemmK;
+        const int kp8 = p.k_pad8;
+        const int kpl = ((nl + kGemmK - 1) / kGemmK) * kGemmK;
+        std::vector<double> m2m((size_t)L * 8 * nl * kpl, 0.0), l2l((size_t)L * 8 * nl * kpl, 0.0);
+        (void)kp8;
         p.k_pad = ((nl + kGemmK - 1) / kGemmK) * kGemmK;
         const int kp = p.k_pad;
         std::vector<double> m2l((size_t)L * kNumM2L * nl * kp, 0.0);
@@ -431,11 +443,12 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
                 for (int c = 0; c < 8; ++c)
                     for (int i = 0; i < nl; ++i)
                         for (int j = 0; j < nl; ++j) {
-                            double v = H.m2m[l][(size_t)c * nl * nl + (size_t)i * nl + j];
-                            // column-major storage: (i, j) at j*nl + i
-                            m2m[((size_t)l * 8 + c) * nl * nl + (size_t)j * nl + i] = v;
-                            // l2l = m2m^T: (j, i) entry equals v
-                            l2l[((size_t)l * 8 + c) * nl * nl + (size_t)i * nl + j] = v;
+                            const double v = H.m2m[l][(size_t)c * nl * nl + (size_t)i * nl + j];
+                            // M2M stacked operand: row c nl + i (parent lattice, as seen from octant c),
+                            // column j (child lattice)
+                            m2m[((size_t)l * 8 * nl + (size_t)c * nl + i) * kpl + j] = v;
+                            // L2L = M2M^T: row c nl + j (child c check point), column i (parent)
+                            l2l[((size_t)l * 8 * nl + (size_t)c * nl + j) * kpl + i] = v;
                         }
             // stacked GEMM operand: row slot * nl + i, column j (zero padded to k_pad)
             for (int t = 0; t < kNumM2L; ++t)

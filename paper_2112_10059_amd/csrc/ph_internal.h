@@ -49,10 +49,11 @@ struct CallScalars {
     int32_t n_tgt;
     int32_t lvl_count[kMaxDepth + 2];   // boxes per level
     int32_t lvl_src[kMaxDepth + 2];     // boxes with sources per level
+    int32_t lvl_tpar[kMaxDepth + 2];    // split boxes with targets per level
     int32_t lvl_start[kMaxDepth + 3];   // first box of each level
     int32_t n_u, n_w, n_x;              // list lengths
     int32_t n_src_dropped;              // learned selector
-    int32_t pad;
+    int32_t min_leafsrc_level;          // lowest level holding a leaf with sources
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t lvl_pack[kMaxDepth + 2];   // packed per-level totals (boxes | source boxes << 32)
     // algorithmic work of the call (integer counters, order independent)
@@ -74,9 +75,11 @@ struct BoxArrays {
     // per call (boxes outside the per-call tree have zero counts and no flags)
     int32_t *s_first = nullptr, *s_cnt = nullptr, *t_first = nullptr, *t_cnt = nullptr;
     int32_t *flags = nullptr;
-    uint32_t *srcflag = nullptr;    // scan scratch: box holds selected sources (box_cap + 1)
+    uint64_t *srcflag = nullptr;    // scan scratch: (has sources | split with targets << 32) (box_cap + 1)
     int32_t *src_rank = nullptr;    // rank of a box among its level's boxes with sources (-1 if none)
     int32_t *src_box = nullptr;     // per-level slots: box of each source rank
+    int32_t *tpar_rank = nullptr;   // rank among the level's split boxes with targets (-1 if none)
+    int32_t *tpar_box = nullptr;    // per-level slots: box of each such rank
 };
 
 // Interaction lists in CSR form over all boxes (offsets box_cap + 1)
@@ -94,8 +97,8 @@ struct Gas {
 struct OperatorsDev {
     void *uc2e_rm = nullptr;   // levels x n_lam x n_sig (row i = lattice index)
     void *uc2e_cm = nullptr;   // levels x n_sig x n_lam (transposed copy)
-    void *m2m = nullptr;       // levels x 8 x n_lam x n_lam, column-major (entry (i,j) at j*n_lam+i)
-    void *l2l = nullptr;       // levels x 8 x n_lam x n_lam, column-major
+    void *m2m = nullptr;       // per child level: (8 n_lam) x k_pad, row c n_lam + i, column j (M2M_c[i][j])
+    void *l2l = nullptr;       // per child level: (8 n_lam) x k_pad, row c n_lam + i, column j (L2L_c[i][j])
     void *m2l = nullptr;       // levels x (316 n_lam) x k_pad, row m = slot n_lam + i, column k = j
     void *lat_unit = nullptr;  // n_lam x 3 lattice nodes on [-1,1]^3 (T)
     void *shell_unit = nullptr;// n_sig x 3 shell points (radius included) in units of the half-width
@@ -118,6 +121,9 @@ struct Plan {
     ph_selector selector = PH_SEL_THRESHOLD;
     int q = 4, n_lam = 64, n_sig = 98;
     int k_pad = 64;          // n_lam rounded up to the GEMM K chunk
+    int k_pad8 = 512;        // 8 n_lam rounded up to the GEMM K chunk
+    size_t z_cap_cols = 0;   // target parents per level (Z buffer columns)
+    void *d_z = nullptr;     // parent-to-child (and child-to-parent) translations: z_cap_cols x (8 n_lam)
     size_t y_cap_cols = 0;   // source boxes per translation chunk (Y buffer columns)
     void *d_y = nullptr;     // translation products: y_cap_cols x (316 n_lam)
     int leaf_cap = 64;
@@ -186,6 +192,7 @@ struct Plan {
     int64_t phase_calls = 0;
     bool events_ready = false;
     bool count_work = false;        // algorithmic work counters (only for calls that fetch stats)
+    bool near_guard = true;         // near pairs may have (b - a) r < 1/4: small-argument series needed
     size_t bytes_allocated = 0;
     size_t workspace_cap = 0;
 };
@@ -240,6 +247,7 @@ void build_lists(Plan &p, hipStream_t s);
 // fmm (k_fmm.hip, k_m2l.hip)
 void fmm_upward(Plan &p, hipStream_t s);
 void fmm_downward(Plan &p, hipStream_t s);
+void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
 void fmm_leaf(Plan &p, void *S_out, hipStream_t s);
 
