@@ -110,7 +110,9 @@ typedef struct {
     int max_depth;          /* 0 => depth of the tree over all points (bounded by 16)           */
     double pinv_rel_cutoff; /* singular values below cutoff * sigma_max are dropped; 0 => default */
     const float *selector_weights; /* host, PH_MLP_NPARAM floats (learned selector) or NULL     */
-    float selector_logit_threshold;/* keep a leaf iff logit >= threshold                       */
+    float selector_logit_threshold;/* keep a source leaf iff its logit >= threshold           */
+    double selector_fallback_rel;  /* source rule I >= rel * max I used when the learned
+                                      selector falls back; 0 => 1e-4                         */
     size_t workspace_cap_bytes;    /* 0 => unlimited                                           */
 } ph_options;
 
@@ -229,12 +231,30 @@ ph_status ph_adam_step(float *params, float *m1, float *m2, const float *grad, i
                        float lr, float beta1, float beta2, float eps, int64_t step, void *stream);
 
 /*
- * Per-leaf selector features of the last ph_evaluate's source tree into feats
- * (device, capacity cap_leaves x 8 floats); *n_leaves receives the count.
- * Synchronous.  Feature definitions are listed in the selector documentation.
+ * Learned selector rows: the source leaves (leaves holding selected sources) of the
+ * last ph_evaluate's tree, in box order.  Eight features per leaf b (E_max = max |E|,
+ * I_max = max I over all points, w_ref = h^3 on grids else cube volume / n):
+ *   0 log10(max_b I / I_max)              1 log10(sum_b w I / (I_max w_ref))
+ *   2 log2(side_b / w_ref^(1/3))          3 log10(1 + |centre_b - x_Emax| / side_b)
+ *   4 max |E| / E_max over b's points     5 mean |E| / E_max    6 std |E| / E_max
+ *   7 max |E| / E_max over the 27 boxes around b (features 3-7 are 0 without |E|)
+ * I and absE must be the arrays of that evaluation.  feats: device, cap_leaves x 8
+ * floats; *n_leaves receives the row count (rows beyond cap_leaves are not written).
+ * Synchronous.  Threshold-selector plans give the rows a learned plan would decide on.
  */
-ph_status ph_selector_features(ph_plan *plan, float *feats, int64_t cap_leaves, int64_t *n_leaves,
-                               void *stream);
+ph_status ph_selector_features(ph_plan *plan, const void *I, const float *absE, float *feats,
+                               int64_t cap_leaves, int64_t *n_leaves, void *stream);
+
+/*
+ * Training labels: for every row of the last ph_selector_features call, the Euclidean
+ * norm over the given targets of that leaf's exact field sum_{j in leaf} w_j I_j K(|x - y_j|)
+ * (own-cell term included), in units of P * 2^e (e the scale exponent of ph_debug_fetch 7),
+ * i.e. comparable with S_out / (P 2^e) at the same targets.
+ * targets: device, n_targets caller-order point indices.  contrib: device, one float per
+ * row (cap_rows of them).  Synchronous.
+ */
+ph_status ph_selector_contrib(ph_plan *plan, const int32_t *targets, int64_t n_targets, float *contrib,
+                              int64_t cap_rows, void *stream);
 
 #ifdef __cplusplus
 }

@@ -51,7 +51,8 @@ class PhOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("selector", ctypes.c_int), ("method", ctypes.c_int),
                 ("order_q", ctypes.c_int), ("leaf_capacity", ctypes.c_int), ("max_depth", ctypes.c_int),
                 ("pinv_rel_cutoff", ctypes.c_double), ("selector_weights", ctypes.POINTER(ctypes.c_float)),
-                ("selector_logit_threshold", ctypes.c_float), ("workspace_cap_bytes", ctypes.c_size_t)]
+                ("selector_logit_threshold", ctypes.c_float), ("selector_fallback_rel", ctypes.c_double),
+                ("workspace_cap_bytes", ctypes.c_size_t)]
 
 
 class PhStats(ctypes.Structure):
@@ -67,7 +68,7 @@ WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pa
 
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
-            "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times"]
+            "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_contrib"]
 
 _lib = None
 
@@ -122,7 +123,9 @@ def load(path: Optional[str] = None):
     lib.ph_phase_times.restype = ctypes.c_int
     lib.ph_phase_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ph_selector_features.restype = ctypes.c_int
-    lib.ph_selector_features.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), vp]
+    lib.ph_selector_features.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), vp]
+    lib.ph_selector_contrib.restype = ctypes.c_int
+    lib.ph_selector_contrib.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
     _lib = lib
     return lib
 
@@ -161,7 +164,7 @@ class Plan:
                  cube_lo=None, cube_size: float = 0.0, precision: str = "fp32", method: str = "fmm",
                  selector: str = "threshold", order_q: int = 0, leaf_capacity: int = 0, max_depth: int = 0,
                  pinv_rel_cutoff: float = 0.0, selector_weights=None, selector_logit_threshold: float = 0.0,
-                 workspace_cap: int = 0):
+                 selector_fallback_rel: float = 0.0, workspace_cap: int = 0):
         lib = load()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.n = int(self._xyz.shape[0])
@@ -189,6 +192,7 @@ class Plan:
             self._selw = np.ascontiguousarray(selector_weights, dtype=np.float32)
             opt.selector_weights = self._selw.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         opt.selector_logit_threshold = float(selector_logit_threshold)
+        opt.selector_fallback_rel = float(selector_fallback_rel)
         opt.workspace_cap_bytes = int(workspace_cap)
         self.precision = precision
         self.thresholds = dict(thresholds)
@@ -279,11 +283,22 @@ def adam_step(params, m1, m2, grad, lr, beta1, beta2, eps, step, stream=None):
                                float(beta1), float(beta2), float(eps), int(step), _stream_ptr(stream)))
 
 
-def selector_features(plan: Plan, stream=None):
+def selector_features(plan: Plan, I, E=None, stream=None):
+    """Features (rows x 8, device) of the source leaves of the plan's last evaluation."""
     import torch
-    cap = plan.n
-    feats = torch.empty((max(cap // 8, 1024), 8), dtype=torch.float32, device="cuda")
     n = ctypes.c_int64()
-    _check(load().ph_selector_features(plan._h, _dptr(feats), feats.shape[0], ctypes.byref(n),
+    _check(load().ph_selector_features(plan._h, _dptr(I), _dptr(E), None, 0, ctypes.byref(n),
                                        _stream_ptr(stream)))
+    feats = torch.empty((max(n.value, 1), 8), dtype=torch.float32, device=I.device)
+    _check(load().ph_selector_features(plan._h, _dptr(I), _dptr(E), _dptr(feats), feats.shape[0],
+                                       ctypes.byref(n), _stream_ptr(stream)))
     return feats[: n.value]
+
+
+def selector_contrib(plan: Plan, targets, rows: int, stream=None):
+    """Per-row field norms at the caller-order target indices (int32 device tensor)."""
+    import torch
+    out = torch.empty(max(rows, 1), dtype=torch.float32, device=targets.device)
+    _check(load().ph_selector_contrib(plan._h, _dptr(targets), targets.numel(), _dptr(out), out.numel(),
+                                      _stream_ptr(stream)))
+    return out[:rows]

@@ -89,20 +89,28 @@ __global__ void reduce_max_final_kernel(const double *__restrict__ partial, int 
 
 struct SelectParams {
     double src_rel, e_abs, e_applied, e_rel;
+    double fallback_rel;          // source rule used when the learned selector falls back
 };
 
+// drop: per sorted point, 1 if a learned decision removed its source leaf (null: none).
+// When the selector has fallen back (sc->fallback) the source rule is fallback_rel instead.
 template <class T>
 __global__ void select_flags_kernel(const T *__restrict__ I, const float *__restrict__ E,
                                     const int32_t *__restrict__ perm, int64_t n, SelectParams sp,
-                                    const CallScalars *__restrict__ sc, uint64_t *__restrict__ flag,
-                                    T *__restrict__ S_out)
+                                    CallScalars *__restrict__ sc, uint64_t *__restrict__ flag,
+                                    T *__restrict__ S_out, const uint8_t *__restrict__ drop)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int32_t o = perm[k];
-    const double thr_s = sp.src_rel * sc->imax;
     const double v = (double)I[o];
-    const bool src = (sp.src_rel <= 0.0) || (v >= thr_s);
+    bool src;
+    if (drop && sc->fallback) {
+        src = (sp.fallback_rel <= 0.0) || (v >= sp.fallback_rel * sc->imax);
+    } else {
+        src = (sp.src_rel <= 0.0) || (v >= sp.src_rel * sc->imax);
+        if (drop) src = src && !drop[k];
+    }
     bool tgt = true;
     if (E) {
         const double e = (double)E[o];
@@ -111,6 +119,8 @@ __global__ void select_flags_kernel(const T *__restrict__ I, const float *__rest
     }
     flag[k] = (uint64_t)(src ? 1u : 0u) | ((uint64_t)(tgt ? 1u : 0u) << 32);
     if (!tgt) S_out[o] = T(0);
+    // position of the largest |E| (smallest sorted index among ties): max of n - k
+    if (E && !drop && (double)E[o] == sc->emax) atomicMax(&sc->emax_pos_rev, (int32_t)(n - k));
 }
 
 template <class T>
@@ -206,19 +216,20 @@ void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, in
 
 static SelectParams params_of(const Plan &p)
 {
-    return SelectParams{p.thr.src_rel, p.thr.e_abs, p.thr.e_applied, p.thr.e_rel};
+    return SelectParams{p.thr.src_rel, p.thr.e_abs, p.thr.e_applied, p.thr.e_rel, p.fallback_rel};
 }
 
-void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s)
+void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s,
+                         const uint8_t *drop)
 {
     const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
     unsigned g = (unsigned)((p.n + 255) / 256);
     if (p.precision == PH_FP64)
         select_flags_kernel<double><<<g, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, p.d_perm, p.n,
-                                                      params_of(p), p.d_sc, p.d_flag, (double *)S_out);
+                                                      params_of(p), p.d_sc, p.d_flag, (double *)S_out, drop);
     else
         select_flags_kernel<float><<<g, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, p.d_perm, p.n,
-                                                     params_of(p), p.d_sc, p.d_flag, (float *)S_out);
+                                                     params_of(p), p.d_sc, p.d_flag, (float *)S_out, drop);
 }
 
 void launch_compact(const Plan &p, const void *I, hipStream_t s)

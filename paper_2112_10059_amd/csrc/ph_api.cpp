@@ -90,6 +90,9 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
         for (int i = 0; i < PH_MLP_NPARAM; ++i)
             if (!std::isfinite(opt->selector_weights[i])) bad("selector_weights has a non-finite value");
         if (opt->method != PH_METHOD_FMM) bad("the learned selector needs the FMM method");
+        if (!std::isfinite(opt->selector_logit_threshold)) bad("selector_logit_threshold must be finite");
+        if (!(opt->selector_fallback_rel >= 0) || opt->selector_fallback_rel > 1)
+            bad("selector_fallback_rel must be in [0, 1]");
     }
 }
 
@@ -225,6 +228,8 @@ void alloc_workspace(Plan &p)
     p.d_feat_box = (int32_t *)dev_alloc(p, B * 4);
     p.d_logit = (float *)dev_alloc(p, B * 4);
     p.d_sel_params = (float *)dev_alloc(p, PH_MLP_NPARAM * 4);
+    p.d_drop = (uint8_t *)dev_alloc(p, (size_t)n);
+    p.d_leafflag = (uint32_t *)dev_alloc(p, (B + 1) * 4);
     if (!p.sel_weights.empty())
         PH_HIP(hipMemcpy(p.d_sel_params, p.sel_weights.data(), PH_MLP_NPARAM * 4, hipMemcpyHostToDevice));
 }
@@ -241,7 +246,8 @@ void free_plan(Plan *p)
                     p->box.child, p->box.coll, p->box.start, p->box.end, p->box.srcflag, p->box.src_rank, p->box.tpar_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->d_phi, p->d_u,
-                    p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params, p->d_cell,
+                    p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
+                    p->d_cell,
                     p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_far};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
@@ -302,6 +308,7 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     if (opt->selector == PH_SEL_LEARNED) {
         p.sel_weights.assign(opt->selector_weights, opt->selector_weights + PH_MLP_NPARAM);
         p.sel_threshold = opt->selector_logit_threshold;
+        p.fallback_rel = opt->selector_fallback_rel > 0 ? opt->selector_fallback_rel : 1e-4;
     }
     // root cube
     if (pts->cube_size > 0) {
@@ -619,7 +626,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
         };
         mark(0);
         launch_reset_scalars(p.d_sc, s);
-        launch_reduce_max(I, p.precision == PH_FP64, absE, p.thr.e_rel >= 0, p.n, p.d_sc, p.d_scan_tmp, s);
+        launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_scan_tmp, s);
         launch_select_flags(p, I, absE, S_out, s);
         exclusive_scan_u64(p.d_flag, p.n, p.d_scan_tmp, &p.d_sc->packed_total, s);
         launch_compact(p, I, s);
@@ -631,7 +638,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
         } else {
             build_tree(p, s);
             mark(2);
-            if (p.selector == PH_SEL_LEARNED) selector_apply(p, s);
+            if (p.selector == PH_SEL_LEARNED) selector_apply(p, I, absE, S_out, s);
             mark(3);
             build_lists(p, s);
             mark(4);
@@ -657,7 +664,9 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             }
             stats->n_boxes = p.method == PH_METHOD_FMM ? nb : 0;
             stats->levels = levels;
-            stats->n_src_dropped = p.h_sc.n_src_dropped;
+            stats->n_src_dropped = p.selector == PH_SEL_LEARNED ? (int64_t)p.h_sc.n_src_base - p.h_sc.n_src : 0;
+            stats->fell_back = p.h_sc.fallback;
+            stats->n_leaves = p.h_sc.n_srcleaf;
             for (int k = 0; k < 12; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
             for (int k = 0; k + 1 < Plan::kMarks; ++k) {
                 float ms = 0;
@@ -665,6 +674,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
                 stats->t_ms[k] = ms;
             }
         }
+        if (stats && stats->fell_back) return PH_EFALLBACK;
         return PH_OK;
     } catch (const Error &e) {
         return fail(e);

@@ -54,6 +54,10 @@ struct CallScalars {
     int32_t n_u, n_w, n_x;              // list lengths
     int32_t n_src_dropped;              // learned selector
     int32_t min_leafsrc_level;          // lowest level holding a leaf with sources
+    int32_t emax_pos_rev;               // n - (sorted position of the largest |E|)
+    int32_t fallback;                   // learned selector fell back to the threshold rule
+    int32_t n_srcleaf;                  // source leaves (rows of the selector features)
+    int32_t n_src_base;                 // sources before the learned decisions
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t lvl_pack[kMaxDepth + 2];   // packed per-level totals (boxes | source boxes << 32)
     // algorithmic work of the call (integer counters, order independent)
@@ -146,7 +150,9 @@ struct Plan {
     // learned selector
     std::vector<float> sel_weights;
     float sel_threshold = 0.f;
-    bool sel_valid = false;
+    double fallback_rel = 1e-4;     // threshold rule of the learned selector's fallback
+    uint8_t *d_drop = nullptr;      // per sorted point: source removed by the learned selector
+    uint32_t *d_leafflag = nullptr; // scan scratch over boxes (source leaves)
 
     // plan-time device arrays
     uint64_t *d_key = nullptr;      // sorted Morton keys (n)
@@ -237,7 +243,8 @@ void launch_gather_sorted(const double *xyz, const double *w, const int32_t *per
 void launch_reset_scalars(CallScalars *sc, hipStream_t s);
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
                        CallScalars *sc, void *tmp /* >= 16 KiB */, hipStream_t s);
-void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s);
+void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s,
+                         const uint8_t *drop = nullptr);
 void launch_compact(const Plan &p, const void *I, hipStream_t s);
 
 // tree (k_tree.hip)
@@ -255,7 +262,8 @@ void fmm_leaf(Plan &p, void *S_out, hipStream_t s);
 void run_direct(Plan &p, void *S_out, hipStream_t s);
 
 // learned selector (k_mlp.hip)
-void selector_apply(Plan &p, hipStream_t s);
+void selector_features(Plan &p, const void *I, const float *E, hipStream_t s);  // rows -> d_feat
+void selector_apply(Plan &p, const void *I, const float *E, void *S_out, hipStream_t s);
 void launch_mlp_forward(const float *params, const float *X, int64_t m, float *logits, int bf16,
                         hipStream_t s);
 void launch_mlp_backward(const float *params, const float *X, const float *y, float pos_weight,

@@ -1,0 +1,207 @@
+"""GPU parity of the learned leaf selector: network kernels vs the FP64 oracle, features vs an
+independent NumPy computation, and the learned evaluation path's keep/drop/fallback behaviour."""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import mlp as omlp
+from oracle import photoionization, rel_l2
+from tests.helpers import MORTON_BITS, plan_kwargs
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=dtype or torch.float32, device="cuda")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------- network kernels
+
+def test_mlp_forward_fp32_and_bf16(gpu_lib):
+    _say("mlp forward")
+    rng = np.random.default_rng(1)
+    p = omlp.init_params(3)
+    X = rng.normal(size=(1000, 8)) * 2
+    z_ref, _ = omlp.forward(p, X)
+    z32 = gpu_lib.mlp_forward(_t(p), _t(X)).cpu().numpy()
+    assert np.all(np.abs(z32 - z_ref) <= 2e-5 * (1 + np.abs(z_ref)))
+    zbf = gpu_lib.mlp_forward(_t(p), _t(X), bf16=True).cpu().numpy()
+    # BF16 weights/activations (8-bit mantissa) with FP32 accumulation: relative error a few 2^-8
+    W1, b1, W2, b2, W3, b3 = omlp.unpack(p)
+    bound = np.abs(W3) @ np.abs(omlp.gelu(omlp.forward(p, X)[1][3])).T  # scale of the last layer
+    assert np.all(np.abs(zbf - z_ref) <= 4 * 2.0 ** -8 * (bound + 1.0))
+
+
+def test_mlp_backward_matches_oracle(gpu_lib):
+    _say("mlp backward")
+    rng = np.random.default_rng(2)
+    p = omlp.init_params(5) * 0.8
+    X = rng.normal(size=(777, 8))
+    y = (rng.uniform(size=777) < 0.25).astype(np.float64)
+    loss_ref, g_ref = omlp.loss_and_grad(p, X, y, 3.0)
+    g, loss = gpu_lib.mlp_backward(_t(p), _t(X), _t(y), 3.0)
+    g = g.cpu().numpy().astype(np.float64)
+    assert float(loss.cpu()) == pytest.approx(loss_ref, rel=1e-5)
+    assert rel_l2(g, g_ref) <= 1e-4
+    assert np.allclose(g, g_ref, rtol=1e-3, atol=1e-5 * np.abs(g_ref).max())
+
+
+def test_adam_matches_oracle(gpu_lib):
+    _say("adam")
+    rng = np.random.default_rng(3)
+    n = omlp.NPARAM
+    p, m1, m2, g = (rng.normal(size=n) for _ in range(4))
+    m2 = np.abs(m2)
+    p_ref, m1_ref, m2_ref = omlp.adam_step(p, m1, m2, g, 1e-3, 0.9, 0.999, 1e-8, 7)
+    tp, tm1, tm2 = _t(p), _t(m1), _t(m2)
+    gpu_lib.adam_step(tp, tm1, tm2, _t(g), 1e-3, 0.9, 0.999, 1e-8, 7)
+    assert np.allclose(tp.cpu().numpy(), p_ref, rtol=1e-5, atol=1e-6)
+    assert np.allclose(tm1.cpu().numpy(), m1_ref, rtol=1e-5, atol=1e-6)
+    assert np.allclose(tm2.cpu().numpy(), m2_ref, rtol=1e-5, atol=1e-6)
+
+
+# ---------------------------------------------------------------- features
+
+def _ranges(keys, level, anchors):
+    shift = np.uint64(3 * (MORTON_BITS - level))
+    pre = keys >> shift
+    from tests.helpers import _spread
+    a = np.asarray(anchors, dtype=np.uint64)
+    p = (_spread(a[:, 0]) << np.uint64(2)) | (_spread(a[:, 1]) << np.uint64(1)) | _spread(a[:, 2])
+    return np.searchsorted(pre, p, side="left"), np.searchsorted(pre, p, side="right")
+
+
+def test_selector_features_match_numpy(gpu_lib):
+    import torch
+    wl = gen.config2(seed=1010, n_axis=48)
+    thr = dict(src_rel=1e-7, e_abs=3e6)
+    _say("selector features c2_48")
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
+    I32, E32 = wl.I.astype(np.float32), wl.E.astype(np.float32)
+    tI, tE = _t(I32), _t(E32)
+    plan.evaluate(tI, tE)
+    F = gpu_lib.selector_features(plan, tI, tE).cpu().numpy().astype(np.float64)
+    keys = plan.debug_fetch("keys")
+    perm = plan.debug_fetch("perm")
+    src = plan.debug_fetch("src")
+    boxes = plan.debug_fetch("boxes")
+    leaves = boxes[(boxes[:, 9] & 1 == 1) & (boxes[:, 5] > 0)]
+    assert F.shape == (leaves.shape[0], 8)
+    Imax, Emax = float(I32.max()), float(E32.max())
+    w_ref = wl.h ** 3
+    lo, hi = wl.domain
+    cube = hi - lo
+    Es = E32[perm].astype(np.float64)
+    kE = int(np.argmax(Es))
+    xE = wl.xyz[perm[kE]]
+    ref = np.zeros_like(F)
+    for r, row in enumerate(leaves):
+        lev, ax, ay, az, sf, sn = (int(v) for v in row[:6])
+        idx = perm[src[sf:sf + sn]]
+        Iv = I32[idx].astype(np.float64)
+        side = cube / 2 ** lev
+        ctr = lo + (np.array([ax, ay, az]) + 0.5) * side
+        st, en = _ranges(keys, lev, [[ax, ay, az]])
+        e = Es[st[0]:en[0]] / Emax
+        nb = [[ax + dx, ay + dy, az + dz] for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
+              if 0 <= ax + dx < 2 ** lev and 0 <= ay + dy < 2 ** lev and 0 <= az + dz < 2 ** lev]
+        cs, ce = _ranges(keys, lev, nb)
+        emx_nb = max(Es[a:b].max() / Emax for a, b in zip(cs, ce) if b > a)
+        ref[r] = [math.log10(Iv.max() / Imax), math.log10(Iv.sum() * w_ref / (Imax * w_ref)),
+                  math.log2(side / w_ref ** (1 / 3)), math.log10(1 + np.linalg.norm(ctr - xE) / side),
+                  e.max(), e.mean(), e.std(), emx_nb]
+    assert np.allclose(F, ref, rtol=2e-5, atol=2e-5)
+    plan.close()
+
+
+# ---------------------------------------------------------------- learned evaluation path
+
+def _const_net(bias):
+    p = np.zeros(omlp.NPARAM, dtype=np.float32)
+    p[-1] = bias
+    return p
+
+
+def test_learned_keep_all_equals_threshold_bitwise(gpu_lib):
+    wl = gen.config2(seed=1011, n_axis=48)
+    thr = dict(src_rel=1e-6, e_abs=3e6)
+    _say("learned keep-all vs threshold")
+    tI, tE = _t(wl.I.astype(np.float32)), _t(wl.E.astype(np.float32))
+    p0 = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
+    a = p0.evaluate(tI, tE).cpu().numpy()
+    p1 = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, selector="learned",
+                      selector_weights=_const_net(50.0), **plan_kwargs(wl))
+    b, st = p1.evaluate(tI, tE, stats=True)
+    assert st["fell_back"] == 0 and st["n_src_dropped"] == 0
+    assert np.array_equal(a.view(np.uint32), b.cpu().numpy().view(np.uint32))
+    p0.close()
+    p1.close()
+
+
+def test_learned_drop_all_gives_zero(gpu_lib):
+    wl = gen.config2(seed=1012, n_axis=40)
+    thr = dict(src_rel=1e-6, e_abs=3e6)
+    _say("learned drop-all")
+    tI, tE = _t(wl.I.astype(np.float32)), _t(wl.E.astype(np.float32))
+    p1 = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, selector="learned",
+                      selector_weights=_const_net(-50.0), **plan_kwargs(wl))
+    b, st = p1.evaluate(tI, tE, stats=True)
+    assert st["n_src"] == 0 and st["n_src_dropped"] > 0
+    assert np.all(b.cpu().numpy() == 0)
+    p1.close()
+
+
+def test_learned_nonfinite_logits_fall_back_to_threshold(gpu_lib):
+    wl = gen.config2(seed=1013, n_axis=40)
+    thr = dict(src_rel=1e-6, e_abs=3e6)
+    _say("learned fallback")
+    tI, tE = _t(wl.I.astype(np.float32)), _t(wl.E.astype(np.float32))
+    w = np.zeros(omlp.NPARAM, dtype=np.float32)
+    w[:512] = 1e30   # W1: every hidden unit saturates to +inf or -inf ...
+    w[576:4672] = 1e30
+    w[4736:4800] = np.where(np.arange(64) % 2 == 0, 1.0, -1.0).astype(np.float32)  # ... and inf - inf
+    p1 = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, selector="learned", selector_weights=w,
+                      selector_fallback_rel=1e-4, **plan_kwargs(wl))
+    b, st = p1.evaluate(tI, tE, stats=True)
+    assert st["fell_back"] == 1
+    p0 = gpu_lib.Plan(wl.xyz, wl.gas, dict(src_rel=1e-4, e_abs=3e6), leaf_capacity=32, **plan_kwargs(wl))
+    a = p0.evaluate(tI, tE).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.cpu().numpy().view(np.uint32))
+    p0.close()
+    p1.close()
+
+
+def test_selector_contrib_matches_oracle(gpu_lib):
+    """Per-leaf field norms at sampled targets equal the FP64 direct sum restricted to the leaf."""
+    wl = gen.config2(seed=1014, n_axis=32)
+    thr = dict(src_rel=1e-3, e_abs=3e6)
+    _say("selector contributions")
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
+    I32, E32 = wl.I.astype(np.float32), wl.E.astype(np.float32)
+    tI, tE = _t(I32), _t(E32)
+    plan.evaluate(tI, tE)
+    F = gpu_lib.selector_features(plan, tI, tE)
+    rng = np.random.default_rng(5)
+    tg = np.sort(rng.choice(wl.n, size=300, replace=False)).astype(np.int32)
+    import torch
+    c = gpu_lib.selector_contrib(plan, torch.tensor(tg, device="cuda"), F.shape[0]).cpu().numpy()
+    perm, src, boxes = plan.debug_fetch("perm"), plan.debug_fetch("src"), plan.debug_fetch("boxes")
+    leaves = boxes[(boxes[:, 9] & 1 == 1) & (boxes[:, 5] > 0)]
+    e = int(plan.debug_fetch("scale_exp")[0])
+    from oracle import gas_constants
+    P = gas_constants(wl.gas).P
+    for r in range(0, leaves.shape[0], max(1, leaves.shape[0] // 12)):
+        sf, sn = int(leaves[r, 4]), int(leaves[r, 5])
+        sm = np.zeros(wl.n, dtype=bool)
+        sm[perm[src[sf:sf + sn]]] = True
+        res = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, smask=sm, targets=tg)
+        ref = np.linalg.norm(res.S_t) / (P * 2.0 ** e)
+        assert c[r] == pytest.approx(ref, rel=2e-4)
+    plan.close()
