@@ -121,7 +121,7 @@ typedef struct {
     int64_t n_src;          /* selected sources                                                 */
     int64_t n_tgt;          /* selected targets                                                 */
     int64_t n_boxes;        /* boxes of the per-call tree                                       */
-    int64_t n_leaves;
+    int64_t n_leaves;       /* source leaves the learned selector decided on (learned plans)    */
     int32_t levels;         /* deepest level + 1                                                */
     int32_t fell_back;      /* 1 if the learned selector fell back                              */
     int64_t n_src_dropped;  /* sources removed by the learned selector                          */
@@ -248,8 +248,8 @@ ph_status ph_selector_features(ph_plan *plan, const void *I, const float *absE, 
 /*
  * Training labels: for every row of the last ph_selector_features call, the Euclidean
  * norm over the given targets of that leaf's exact field sum_{j in leaf} w_j I_j K(|x - y_j|)
- * (own-cell term included), in units of P * 2^e (e the scale exponent of ph_debug_fetch 7),
- * i.e. comparable with S_out / (P 2^e) at the same targets.
+ * (own-cell term included), times P: the units of S_out, so that leaf b's share of the
+ * field is contrib_b / ||S_out||_2 over the same targets.
  * targets: device, n_targets caller-order point indices.  contrib: device, one float per
  * row (cap_rows of them).  Synchronous.
  */

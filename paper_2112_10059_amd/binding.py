@@ -217,7 +217,8 @@ class Plan:
         _check(_lib.ph_evaluate(self._h, _dptr(I), _dptr(E), _dptr(out), _stream_ptr(stream),
                                 ctypes.byref(st) if stats else None))
         if stats:
-            return out, {"n_src": st.n_src, "n_tgt": st.n_tgt, "n_boxes": st.n_boxes, "levels": st.levels,
+            return out, {"n_src": st.n_src, "n_tgt": st.n_tgt, "n_boxes": st.n_boxes, "n_leaves": st.n_leaves,
+                         "levels": st.levels,
                          "fell_back": st.fell_back, "n_src_dropped": st.n_src_dropped,
                          "t_ms": list(st.t_ms), "work": dict(zip(WORK, list(st.work)))}
         return out

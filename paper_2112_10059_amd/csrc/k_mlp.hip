@@ -326,14 +326,15 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a, const T *__re
     if (lane < 8) a.feats[(size_t)r * 8 + lane] = fe[lane];
 }
 
-// ||field of leaf b||_2 over the sampled targets (one workgroup per row)
+// ||field of leaf b||_2 over the sampled targets, in the units of S (one workgroup per row)
 template <class T>
 __global__ __launch_bounds__(256) void contrib_kernel(BoxArrays bx, const int32_t *__restrict__ rows,
                                                       const CallScalars *__restrict__ sc,
                                                       const V4<T> *__restrict__ s_dat, const int32_t *__restrict__ s_pos,
                                                       const int32_t *__restrict__ iperm, const double *__restrict__ xyz,
                                                       const int32_t *__restrict__ targets, int64_t nt, KParams<T> kp,
-                                                      double c_self_over_w, float *__restrict__ out, int64_t cap)
+                                                      double c_self_over_w, double P, float *__restrict__ out,
+                                                      int64_t cap)
 {
     __shared__ V4<T> tile[256];
     __shared__ int32_t tpos[256];
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(256) void contrib_kernel(BoxArrays bx, const int32_
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[r] = (float)sqrt(red[0]);
+    if (threadIdx.x == 0) out[r] = (float)(sqrt(red[0]) * P * ldexp(1.0, sc->scale_exp));
 }
 
 __global__ void zero_bytes_kernel(uint8_t *__restrict__ p, int64_t n)
@@ -499,11 +500,12 @@ extern "C" ph_status ph_selector_contrib(ph_plan *plan, const int32_t *targets, 
         if (p.precision == PH_FP64)
             contrib_kernel<double><<<g, 256, 0, s>>>(p.box, p.d_feat_box, p.d_sc, (const double4 *)p.d_s_dat,
                                                      p.d_s_pos, p.d_iperm, p.d_xyz, targets, n_targets,
-                                                     make_kparams<double>(p.gas), csw, contrib, cap_rows);
+                                                     make_kparams<double>(p.gas), csw, p.gas.P, contrib, cap_rows);
         else
             contrib_kernel<float><<<g, 256, 0, s>>>(p.box, p.d_feat_box, p.d_sc, (const float4 *)p.d_s_dat, p.d_s_pos,
                                                     p.d_iperm, p.d_xyz, targets, n_targets,
-                                                    make_kparams<float>(p.gas), csw, contrib, cap_rows);
+                                                    make_kparams<float>(p.gas), csw, p.gas.P, contrib,
+                                                    cap_rows);
         PH_HIP(hipGetLastError());
         PH_HIP(hipStreamSynchronize(s));
         return PH_OK;
