@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -90,6 +92,13 @@ def main():
     I32 = wl.I.astype(np.float32)
     E32 = wl.E.astype(np.float32)
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 268435456 B read, 268435456 B written")
+        del src, dst
     I = torch.from_numpy(I32).to(dev)
     E = torch.from_numpy(E32).to(dev)
     lo, hi = wl.domain
@@ -107,8 +116,7 @@ def main():
     value = n_tgt / (ms * 1e-3)
     log(f"fp32 adaptive: {ms:.4f} ms/step, {value:.4e} targets/s; phases {phases}")
 
-    # roofline of the dominant phase
-    roof = roofline(phases, st, plan_n_lam(args), wl.n)
+    roof = roofline(phases, st)
 
     # ---------------- parity on sampled targets + CPU oracle baseline
     from oracle import photoionization, rel_l2
@@ -193,47 +201,67 @@ def plan_q(args):
     return args.order_q or 4
 
 
-def plan_n_lam(args):
-    return plan_q(args) ** 3
+def near_work(st):
+    """Algorithmic FP operations and HBM bytes of one launch of the near-field kernel (FP32 form).
+
+    FLOPs: FLOPS_PER_EVAL per source-target pair of the U lists (work counter p2p_pairs).
+    Bytes: per target of a leaf with a non-empty U list (work counter near_targets) its
+    packed position and own-cell value (16 B), its far-field value (4 B), its sorted
+    position and caller index (8 B) and its output S (4 B); per selected source its packed
+    position and weighted strength (16 B), read once.
+    """
+    return {"flops": FLOPS_PER_EVAL * float(st["work"]["p2p_pairs"]),
+            "bytes": st["work"]["near_targets"] * (16.0 + 4.0 + 8.0 + 4.0) + st["n_src"] * 16.0}
 
 
-def phase_work(st, n_lam, n_points):
-    """Algorithmic FP operations and HBM bytes of each phase of one call (FP32 form)."""
-    w = st["work"]
-    n_src, n_tgt = st["n_src"], st["n_tgt"]
-    ev = FLOPS_PER_EVAL
-    return {
-        # reads I and |E| (4 B each) and the permutation (4 B) per point, writes the packed
-        # flags (8 B) and scans them (8 B read + 8 B write), writes 32 B per selected source
-        # and target (position + value) plus its key (8 B)
-        "select": {"flops": 0.0, "bytes": n_points * (4 + 4 + 4 + 8 + 16) + (n_src + n_tgt) * 40.0},
-        "upward": {"flops": ev * w["p2m_evals"] + 2.0 * w["grid_p2m_madds"] + 2.0 * n_lam * n_lam * w["m2m_children"],
-                   "bytes": n_src * 16.0},
-        "downward": {"flops": 2.0 * n_lam * n_lam * (w["m2l_pairs"] + w["l2l_boxes"]) + ev * w["p2l_evals"],
-                     "bytes": 0.0},
-        # leaf evaluation reads each target (16 B), its cell index and position (8 B) and the
-        # sorted->caller map (4 B), writes S (4 B); sources of the near field are re-read from L2
-        "leaf": {"flops": ev * (w["p2p_pairs"] + w["l2p_evals"] + w["m2p_evals"]) + 2.0 * w["grid_l2p_madds"],
-                 "bytes": n_tgt * (16.0 + 8.0 + 4.0 + 4.0)},
-    }
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "near_kernel_streamer128_fp32_traffic.txt")
 
 
-def roofline(phases, st, n_lam, n_points):
-    dom = max(phases, key=lambda k: phases[k])
-    pw = phase_work(st, n_lam, n_points).get(dom, {"flops": 0.0, "bytes": 0.0})
-    sec = phases[dom] * 1e-3
+def near_kernel_source_hash():
+    """SHA-256 of the near-field kernel's source: its function in k_fmm.hip plus k_common.h."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2112_10059_amd", "csrc")
+    text = open(os.path.join(csrc, "k_fmm.hip")).read()
+    i = text.index("template <class T, class TO, bool GUARD>\n__global__ __launch_bounds__(256) void near_kernel(")
+    j = text.index("\n}\n", i) + 3
+    h = hashlib.sha256(text[i:j].encode())
+    h.update(open(os.path.join(csrc, "k_common.h")).read().encode())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the near-field kernel from the committed counter summary, or None
+    when that summary is missing or was taken on a different version of the kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != near_kernel_source_hash():
+        return None
+    return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+
+
+def roofline(phases, st):
+    """Roofline of the near-field (P2P) kernel, the largest single kernel of a call.
+
+    Its phase holds exactly one launch, so the per-call event time of that phase is the
+    kernel's average duration over the timed steps.
+    """
+    pw = near_work(st)
+    sec = phases["near"] * 1e-3
     tf = pw["flops"] / sec / 1e12
     gb = pw["bytes"] / sec / 1e9
-    kernels = {"select": "select_flags + scan + compact", "tree": "split_count/split_emit/colleagues",
-               "lists": "list_count/list_fill", "upward": "p2m_kernel + m2m_kernel",
-               "downward": "down_kernel (L2L + M2L + P2L)", "leaf": "leaf_kernel (L2P + M2P + P2P + output)"}
     if tf / PEAK_FP32_TFLOPS >= gb / PEAK_HBM_GBS:
         r = {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
     else:
         r = {"bound": "hbm", "achieved": gb, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r.update({"kernel": kernels.get(dom, dom), "phase": dom, "avg_ms": phases[dom],
-              "algorithmic_flops": pw["flops"], "algorithmic_bytes": pw["bytes"], "traffic": None})
+    r.update({"traffic": measured_traffic(), "kernel": "near_kernel (P2P over the U lists, FP64 combine, scatter to caller order)",
+              "avg_ms": phases["near"], "algorithmic_flops": pw["flops"], "algorithmic_bytes": pw["bytes"],
+              "other_bound_frac": (gb / PEAK_HBM_GBS) if r["bound"] == "alu" else (tf / PEAK_FP32_TFLOPS)})
     return r
 
 

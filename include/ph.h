@@ -130,7 +130,9 @@ typedef struct {
                                evaluations, [2] W-list evaluations, [3] P2M kernel evaluations,
                                [4] X-list evaluations, [5] M2L box pairs, [6] M2M child
                                translations, [7] L2L translations, [8] grid local-to-target
-                               multiply-adds, [9] grid P2M multiply-adds, [10-11] reserved      */
+                               multiply-adds, [9] grid P2M multiply-adds, [10] targets of leaves
+                               with a non-empty U list (those the near-field kernel visits),
+                               [11] reserved                                                    */
 } ph_stats;
 
 /* Returns a static description of a status code. */
@@ -175,7 +177,8 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
  * summed hipEvent time of every call recorded since the previous query, per phase:
  *   0 selection + compaction   1 octree        2 learned selector   3 interaction lists
  *   4 upward pass (P2M, M2M)   5 downward pass (M2L, L2L, P2L)
- *   6 leaf evaluation (L2P, M2P, P2P, output) or the direct sum
+ *   6 far field at the targets (L2P, M2P, own cell)
+ *   7 near field (P2P) and the output, or the whole direct sum
  * *n_calls (nullable) the number of calls.  The sums are then reset.  record = 1
  * turns recording on for every later ph_evaluate (events on the caller's stream,
  * no extra synchronisation), 0 turns it off, -1 leaves it unchanged.  Synchronous.

@@ -63,7 +63,7 @@ class PhStats(ctypes.Structure):
 
 
 WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pairs", "m2m_children",
-        "l2l_boxes", "grid_l2p_madds", "grid_p2m_madds", "reserved10", "reserved11")
+        "l2l_boxes", "grid_l2p_madds", "grid_p2m_madds", "near_targets", "reserved11")
 
 
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",
@@ -223,7 +223,7 @@ class Plan:
                          "t_ms": list(st.t_ms), "work": dict(zip(WORK, list(st.work)))}
         return out
 
-    PHASES = ("select", "tree", "selector", "lists", "upward", "downward", "leaf")
+    PHASES = ("select", "tree", "selector", "lists", "upward", "downward", "leaf", "near")
 
     def phase_times(self, record: int = -1):
         """Summed per-phase device ms since the last query, and the number of calls."""

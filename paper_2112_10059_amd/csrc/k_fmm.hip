@@ -185,6 +185,7 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict_
         for (uint32_t e = u0; e < u1; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
         w_eval = (unsigned long long)(w1 - w0) * nl;
         atomicAdd(&a.work[0], near_src * tn);
+        if (u1 > u0) atomicAdd(&a.work[10], (unsigned long long)tn);  // targets the near-field kernel visits
         if (has_far && gm == 0) atomicAdd(&a.work[1], (unsigned long long)tn * ns);
         if (has_far && gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
         if (w_eval) atomicAdd(&a.work[2], w_eval * tn);
@@ -316,6 +317,12 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
     } else {
         leaf_kernel<T, T, false><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far, 0);
     }
+}
+
+template <class T>
+void fmm_near_t(Plan &p, void *S_out, hipStream_t s)
+{
+    FmmArgs<T> a = make_args<T>(p);
     if (p.near_guard)
         near_kernel<T, T, true><<<(unsigned)p.box_cap, 256, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
     else
@@ -334,6 +341,12 @@ void fmm_leaf(Plan &p, void *S_out, hipStream_t s)
 {
     if (p.precision == PH_FP64) fmm_leaf_t<double>(p, S_out, s);
     else fmm_leaf_t<float>(p, S_out, s);
+}
+
+void fmm_near(Plan &p, void *S_out, hipStream_t s)
+{
+    if (p.precision == PH_FP64) fmm_near_t<double>(p, S_out, s);
+    else fmm_near_t<float>(p, S_out, s);
 }
 
 }  // namespace ph

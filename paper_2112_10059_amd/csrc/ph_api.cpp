@@ -586,9 +586,9 @@ static ph_status fetch_scalars(Plan &p, hipStream_t s)
     return PH_OK;
 }
 
-// Phase boundaries recorded per call (events 0..7): 0 start, 1 selection done,
+// Phase boundaries recorded per call (events 0..8): 0 start, 1 selection done,
 // 2 tree done, 3 learned selector done, 4 lists done, 5 upward done,
-// 6 downward done, 7 leaf evaluation (or direct sum) done.
+// 6 downward done, 7 far field at the targets done, 8 near field (or direct sum) done.
 static void harvest_slot(Plan &p, int slot)
 {
     if (!p.ring_used[slot]) return;
@@ -632,9 +632,9 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
         launch_compact(p, I, s);
         mark(1);
         if (p.method == PH_METHOD_DIRECT) {
-            for (int k = 2; k <= 6; ++k) mark(k);
+            for (int k = 2; k <= 7; ++k) mark(k);
             run_direct(p, S_out, s);
-            mark(7);
+            mark(8);
         } else {
             build_tree(p, s);
             mark(2);
@@ -648,6 +648,8 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             mark(6);
             fmm_leaf(p, S_out, s);
             mark(7);
+            fmm_near(p, S_out, s);
+            mark(8);
         }
         PH_HIP(hipGetLastError());
         if (timed) p.ring_used[slot] = true;

@@ -189,7 +189,7 @@ struct Plan {
     float *d_sel_params = nullptr;  // device copy of the selector weights
     // per-phase timing: a ring of event sets, one set per recorded call
     static constexpr int kRing = 32;
-    static constexpr int kMarks = 8;          // boundaries of the 7 phases
+    static constexpr int kMarks = 9;          // boundaries of the 8 phases
     hipEvent_t ring[kRing][kMarks] = {};
     bool ring_used[kRing] = {};
     int ring_pos = 0;
@@ -256,7 +256,8 @@ void fmm_upward(Plan &p, hipStream_t s);
 void fmm_downward(Plan &p, hipStream_t s);
 void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
-void fmm_leaf(Plan &p, void *S_out, hipStream_t s);
+void fmm_leaf(Plan &p, void *S_out, hipStream_t s);  // far field at targets (L2P, M2P, own cell)
+void fmm_near(Plan &p, void *S_out, hipStream_t s);  // near field (P2P) and the final combine
 
 // direct sum (k_direct.hip)
 void run_direct(Plan &p, void *S_out, hipStream_t s);
