@@ -79,6 +79,8 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
     if (!finite(thr->e_applied) || thr->e_applied < 0) bad("thresholds.e_applied must be >= 0");
     if (thr->r_s != 0.0) throw Error{PH_EUNSUPPORTED, "thresholds.r_s (third strategy) must be 0"};
     if (opt->precision < PH_FP64 || opt->precision > PH_FP32_BF16SPLIT) bad("options.precision out of range");
+    if (opt->precision == PH_FP32_BF16SPLIT)
+        throw Error{PH_EUNSUPPORTED, "options.precision PH_FP32_BF16SPLIT is not implemented"};
     if (opt->method < PH_METHOD_FMM || opt->method > PH_METHOD_DIRECT) bad("options.method out of range");
     if (opt->selector < PH_SEL_THRESHOLD || opt->selector > PH_SEL_LEARNED) bad("options.selector out of range");
     if (opt->order_q != 0 && (opt->order_q < 2 || opt->order_q > 8)) bad("options.order_q must be 0 or 2..8");

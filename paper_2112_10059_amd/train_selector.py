@@ -1,7 +1,7 @@
 """Train the learned leaf selector on synthetic streamer fields with the library's own GPU kernels.
 
 The selector decides, per source leaf of the first-pass tree, whether the leaf's sources enter
-the photoionization sum (adaptive source selection of Sec. 2.3 of the paper, made per leaf by
+the photoionization sum (adaptive source selection of Sec. 3 of the paper, made per leaf by
 a network instead of a fixed relative threshold on I).
 
 Recipe:
