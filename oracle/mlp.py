@@ -115,3 +115,24 @@ def budgeted_keep_labels(contrib, budget):
     lab = np.ones(c.size, dtype=np.float64)
     lab[order[:ndrop]] = 0.0
     return lab
+
+
+def budgeted_keep_labels_gram(G, s_norm, budget):
+    """Keep/drop labels of source leaves from the Gram matrix of their fields at the targets.
+
+    G[b, b'] = <S_b, S_b'> over the targets; s_norm = ||S|| over the same targets.  Leaves are
+    taken in increasing order of ||S_b|| = sqrt(G[b, b]) and dropped while the norm of the sum
+    of the dropped fields, sqrt(sum over b, b' in D of G[b, b']), stays <= budget * s_norm: the
+    exact change of S that dropping D causes.  Returns 1 = keep, 0 = drop.
+    """
+    G = np.asarray(G, dtype=np.float64)
+    order = np.argsort(np.sqrt(np.maximum(np.diag(G), 0.0)), kind="stable")
+    dropped = []
+    for b in order:
+        trial = dropped + [int(b)]
+        if np.sqrt(G[np.ix_(trial, trial)].sum()) > budget * s_norm:
+            break
+        dropped = trial
+    lab = np.ones(G.shape[0], dtype=np.float64)
+    lab[dropped] = 0.0
+    return lab

@@ -62,3 +62,41 @@ def test_budgeted_labels():
     # 1e-4 + 2e-4 = 3e-4 <= 5e-4; adding 3e-4 exceeds the budget
     assert lab.tolist() == [1, 0, 0, 1, 1, 1]
     assert mlp.budgeted_keep_labels(c, 0.0).tolist() == [1] * 6
+
+
+def test_gram_labels_parallel_fields_reduce_to_the_triangle_rule():
+    # identical directions: ||sum|| = sum of norms, so the rule is the running-sum rule
+    rng = np.random.default_rng(3)
+    c = rng.lognormal(-7, 2, size=40)
+    G = np.outer(c, c)
+    for budget in (1e-4, 1e-3, 1e-2):
+        assert np.array_equal(mlp.budgeted_keep_labels_gram(G, 1.0, budget),
+                              mlp.budgeted_keep_labels(c, budget))
+
+
+def test_gram_labels_orthogonal_fields_drop_by_root_sum_of_squares():
+    # disjoint supports: ||sum||^2 = sum of squared norms; hand-checked case
+    c = np.array([3e-4, 1e-4, 0.5, 2e-4, 4e-4])
+    G = np.diag(c ** 2)
+    lab = mlp.budgeted_keep_labels_gram(G, 1.0, 4e-4)
+    # sqrt(1e-8 + 4e-8 + 9e-8) = 3.74e-4 <= 4e-4; adding 4e-4 gives 5.48e-4
+    assert lab.tolist() == [0, 0, 1, 0, 1]
+
+
+def test_gram_labels_brute_force_on_explicit_fields():
+    rng = np.random.default_rng(4)
+    for trial in range(20):
+        m, nt = int(rng.integers(2, 30)), 50
+        F = rng.lognormal(-6, 2, size=(m, 1)) * rng.uniform(0, 1, size=(m, nt)) ** 3
+        S = F.sum(axis=0)
+        budget = float(rng.choice([1e-3, 1e-2, 1e-1]))
+        lab = mlp.budgeted_keep_labels_gram(F @ F.T, np.linalg.norm(S), budget)
+        drop = np.flatnonzero(lab == 0)
+        # the dropped set changes S by at most the budget ...
+        assert np.linalg.norm(F[drop].sum(axis=0)) <= budget * np.linalg.norm(S) * (1 + 1e-12)
+        # ... and is the longest prefix in order of ||S_b|| with that property
+        order = np.argsort(np.linalg.norm(F, axis=1), kind="stable")
+        assert np.array_equal(np.sort(drop), np.sort(order[:drop.size]))
+        if drop.size < m:
+            nxt = order[:drop.size + 1]
+            assert np.linalg.norm(F[nxt].sum(axis=0)) > budget * np.linalg.norm(S)
