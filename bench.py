@@ -2,17 +2,20 @@
 
 Workload: the streamer field on a uniform 128^3 cell-centred grid in a 1 cm
 cube at 760 Torr (Gaussian head sigma 0.2 mm on an exponentially decaying
-channel spanning 8 decades, head-enhanced |E|), sources kept where
-I >= 1e-4 max I, targets where |E| >= 3e6 V/m, FP32 kernels with an FP64
-final combine.  A step is one ph_evaluate: selection + compaction, per-call
-octree, interaction lists, upward pass, translations, leaf evaluation and the
-scatter to caller order, with I and |E| already resident in HBM.
+channel spanning 8 decades, head-enhanced |E|), targets where |E| >= 3e6 V/m.
+The measured configuration is the learned leaf selector (committed weights,
+candidates I >= base_src_rel max I, threshold fallback 1e-4) with FP32 kernels
+and an FP64 final combine.  A step is one ph_evaluate: maxima, selector
+decisions, selection + compaction, per-call octree, interaction lists, upward
+pass, translations, far field at the targets, near field and the scatter to
+caller order, with I and |E| already resident in HBM.
 
-The printed JSON line carries targets/s, the roofline of the dominant kernel
-(hipEvent time of that phase inside the timed region), the FP64 oracle timed
-on the host cores on a bounded sample, the relative L2 error against it, and
-the plain FP64 FMM (all points sources and targets, no adaptivity) on the
-same grid for the speed-up ratio.
+The printed JSON line carries targets/s, the roofline of the near-field kernel
+(hipEvent time of its phase inside the timed region), the FP64 oracle timed on
+the host cores on a bounded sample, the relative L2 error against it on the
+same source set and against all sources (method error), the paper's threshold
+rule (tau_s = 1e-4) on the same field, and the plain FP64 FMM (all points
+sources and targets, no adaptivity) on the same grid for the speed-up ratio.
 """
 from __future__ import annotations
 
@@ -80,13 +83,14 @@ def time_steps(plan, I, E, steps, warmup, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; the path's sharding is described in "
-                          "DESIGN.md and no multi-GPU run is implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; no multi-GPU path is implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
     import gen
     from paper_2112_10059_amd import binding
+    from paper_2112_10059_amd.train_selector import load_selector
 
     wl = gen.config2(seed=args.seed, n_axis=args.n_axis)
     I32 = wl.I.astype(np.float32)
@@ -104,34 +108,53 @@ def main():
     lo, hi = wl.domain
     common = dict(h=wl.h, cube_lo=(lo, lo, lo), cube_size=hi - lo)
 
-    # ---------------- adaptive FP32 FMM (the measured configuration)
+    # ---------------- learned selector + adaptive FP32 FMM (the measured configuration)
+    sel_w, sel_meta = load_selector()
+    thr_l = dict(wl.thresholds, src_rel=sel_meta["base_src_rel"])
     t = time.perf_counter()
-    plan = binding.Plan(wl.xyz, wl.gas, wl.thresholds, precision="fp32", order_q=args.order_q, **common)
+    plan = binding.Plan(wl.xyz, wl.gas, thr_l, precision="fp32", order_q=args.order_q, selector="learned",
+                        selector_weights=sel_w, selector_logit_threshold=sel_meta["threshold"],
+                        selector_fallback_rel=1e-4, **common)
     plan_ms = (time.perf_counter() - t) * 1e3
-    log(f"plan fp32: {plan_ms:.1f} ms")
+    log(f"plan fp32 learned: {plan_ms:.1f} ms")
     _, st = plan.evaluate(I, E, stats=True)
     log(f"stats: {st}")
     S, ms, phases = time_steps(plan, I, E, args.steps, args.warmup, torch)
     n_tgt = st["n_tgt"]
     value = n_tgt / (ms * 1e-3)
-    log(f"fp32 adaptive: {ms:.4f} ms/step, {value:.4e} targets/s; phases {phases}")
-
+    log(f"learned fp32: {ms:.4f} ms/step, {value:.4e} targets/s; phases {phases}")
     roof = roofline(phases, st)
+    perm = plan.debug_fetch("perm")
+    smask = np.zeros(wl.n, dtype=bool)
+    smask[perm[plan.debug_fetch("src")]] = True
 
-    # ---------------- parity on sampled targets + CPU oracle baseline
+    # ---------------- the paper's threshold rule (tau_s = 1e-4) on the same field, for comparison
+    plan_t = binding.Plan(wl.xyz, wl.gas, wl.thresholds, precision="fp32", order_q=args.order_q, **common)
+    _, st_t = plan_t.evaluate(I, E, stats=True)
+    S_t, ms_t, phases_t = time_steps(plan_t, I, E, args.steps, args.warmup, torch)
+    plan_t.close()
+    threshold = {"targets_per_s": n_tgt / (ms_t * 1e-3), "ms_per_step": ms_t, "n_src": st_t["n_src"],
+                 "phases_ms": phases_t}
+    log(f"threshold fp32: {threshold}")
+
+    # ---------------- parity on sampled targets: same source set, and all sources (method error)
     from oracle import photoionization, rel_l2
     S_host = S.double().cpu().numpy()
-    r_all = photoionization(wl.xyz[:1], I32[:1].astype(np.float64), wl.gas, h=wl.h)  # warms the C library
-    smask_i = I32.astype(np.float64) >= 1e-4 * float(I32.max())
-    tmask = E32.astype(np.float64) >= 3e6
-    tgt_all = np.flatnonzero(tmask)
+    St_host = S_t.double().cpu().numpy()
+    photoionization(wl.xyz[:1], I32[:1].astype(np.float64), wl.gas, h=wl.h)  # loads the C library
+    tgt_all = np.flatnonzero(E32.astype(np.float64) >= 3e6)
     sample = gen.sample_targets(tgt_all, wl.xyz, wl.head, k=10_000)
     t = time.perf_counter()
-    r = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, src_rel=1e-4,
-                        E=E32.astype(np.float64), e_abs=3e6, targets=sample)
+    r = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, smask=smask, targets=sample)
     t_or = time.perf_counter() - t
     err = rel_l2(S_host[sample], r.S_t)
-    log(f"parity (sampled {sample.size} targets): rel-L2 = {err:.3e}; oracle {t_or:.2f} s on {r.threads} threads")
+    log(f"parity (sampled {sample.size} targets, learned source set): rel-L2 = {err:.3e}; oracle {t_or:.2f} s")
+    msample = gen.sample_targets(tgt_all, wl.xyz, wl.head, k=1000, seed=777, head_cap=1000)
+    r_all = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, targets=msample)
+    method_err = rel_l2(S_host[msample], r_all.S_t)
+    method_err_t = rel_l2(St_host[msample], r_all.S_t)
+    threshold["method_rel_l2_sampled"] = method_err_t
+    log(f"method error vs all sources (sampled {msample.size}): learned {method_err:.3e}, threshold {method_err_t:.3e}")
     cpu = None
     if not args.skip_cpu:
         # bounded oracle sample sized to about cpu_seconds of wall time
@@ -140,13 +163,13 @@ def main():
         rng = np.random.default_rng(7)
         cs = np.sort(rng.choice(tgt_all, size=k, replace=False))
         t = time.perf_counter()
-        rc = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, src_rel=1e-4,
-                             E=E32.astype(np.float64), e_abs=3e6, targets=cs)
+        rc = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, smask=smask, targets=cs)
         t_c = time.perf_counter() - t
         err_c = rel_l2(S_host[cs], rc.S_t)
         cpu = {"value": k / t_c, "unit": "targets/s", "cores": int(rc.threads), "kind": "oracle",
                "sample": f"{k} targets drawn uniformly (seed 7) from the {tgt_all.size} selected targets, "
-                         f"all {int(smask_i.sum())} selected sources, FP64 direct sum; {t_c:.1f} s wall",
+                         f"the {int(smask.sum())} sources the learned selector kept, FP64 direct sum; "
+                         f"{t_c:.1f} s wall",
                "rel_l2_gpu_vs_oracle_on_sample": err_c}
         log(f"cpu oracle: {cpu}")
 
@@ -166,12 +189,14 @@ def main():
         r64 = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, targets=s64)
         e64 = rel_l2(S64.cpu().numpy()[s64], r64.S_t)
         plain = {"targets_per_s": v64, "ms_per_step": ms64, "plan_ms": plan64_ms, "rel_l2_sampled": e64,
-                 "sample_targets": int(s64.size), "phases_ms": ph64, "speedup_adaptive_fp32": value / v64}
+                 "sample_targets": int(s64.size), "phases_ms": ph64, "speedup_learned_fp32": value / v64,
+                 "speedup_threshold_fp32": threshold["targets_per_s"] / v64}
         log(f"plain fp64: {plain}")
         p64.close()
 
     line = {
-        "metric": "targets/s at rel-L2 <=1e-3 vs FP64 direct sum (adaptive FP32 FMM); plain FP64 FMM for the ratio",
+        "metric": "targets/s at rel-L2 <=1e-3 vs FP64 direct sum (learned selector + adaptive FP32 FMM); "
+                  "plain FP64 FMM for the ratio",
         "value": value,
         "unit": "targets/s",
         "n_gpus": 1,
@@ -184,17 +209,22 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"streamer head+channel on a {args.n_axis}^3 grid, 1 cm cube, 760 Torr, seed "
-                               f"{args.seed}; sources I >= 1e-4 max I, targets |E| >= 3e6 V/m",
-                   "n_points": wl.n, "n_src": st["n_src"], "n_tgt": n_tgt, "order_q": plan_q(args),
-                   "leaf_capacity": 64, "selector": "threshold", "plan_ms": plan_ms},
+                               f"{args.seed}; learned leaf selector over candidates I >= "
+                               f"{sel_meta['base_src_rel']:g} max I (fallback 1e-4), targets |E| >= 3e6 V/m",
+                   "n_points": wl.n, "n_src": st["n_src"], "n_src_dropped": st["n_src_dropped"],
+                   "selector_rows": st["n_leaves"], "fell_back": st["fell_back"], "n_tgt": n_tgt,
+                   "order_q": plan_q(args), "leaf_capacity": 64, "selector": "learned", "plan_ms": plan_ms},
         "rel_l2_sampled": err,
+        "method_rel_l2_sampled": method_err,
         "phases_ms": phases,
         "work": st["work"],
         "roofline": roof,
         "cpu_baseline": cpu,
+        "threshold_fp32": threshold,
         "plain_fp64_fmm": plain,
     }
     print(json.dumps(line), flush=True)
+    plan.close()
 
 
 def plan_q(args):

@@ -175,10 +175,11 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
 /*
  * Per-phase device time.  ms_sum (host, PH_NPHASES doubles, nullable) receives the
  * summed hipEvent time of every call recorded since the previous query, per phase:
- *   0 selection + compaction   1 octree        2 learned selector   3 interaction lists
- *   4 upward pass (P2M, M2M)   5 downward pass (M2L, L2L, P2L)
- *   6 far field at the targets (L2P, M2P, own cell)
- *   7 near field (P2P) and the output, or the whole direct sum
+ *   0 maxima of I and |E|      1 learned selector (rows, features, network, drop mask)
+ *   2 selection + compaction   3 octree        4 interaction lists
+ *   5 upward pass (P2M, M2M)   6 downward pass (M2L, L2L, P2L)
+ *   7 far field at the targets (L2P, M2P, own cell)
+ *   8 near field (P2P) and the output, or the whole direct sum
  * *n_calls (nullable) the number of calls.  The sums are then reset.  record = 1
  * turns recording on for every later ph_evaluate (events on the caller's stream,
  * no extra synchronisation), 0 turns it off, -1 leaves it unchanged.  Synchronous.
@@ -195,15 +196,16 @@ int64_t ph_plan_size(const ph_plan *plan);
  * Test/inspection access to plan-internal device arrays after the last
  * ph_evaluate (or after ph_plan_create for the plan-time arrays).  Copies at
  * most cap_bytes into the host buffer dst and stores the array length (in
- * elements) in *n_out.  Synchronous.  what:
+ * elements; in rows for the two-dimensional arrays 4 and 8) in *n_out.
+ * Synchronous.  what:
  *   0 sorted Morton keys (uint64, n)      1 permutation sorted->caller (int32, n)
  *   2 selected sources, sorted positions (int32, n_src)
  *   3 selected targets, sorted positions (int32, n_tgt)
  *   4 box table (int32, n_boxes x PH_BOX_FIELDS, fields below)
  *   5 level offsets (int32, levels + 1)   6 own-cell coefficient (double, 1)
  *   7 scale exponent e of the FP32 forms (int32, 1)
- *   8 learned-selector leaf features (float, n_leaves x 8)
- *   9 learned-selector leaf boxes (int32, n_leaves)
+ *   8 learned-selector row features (float, rows x 8)
+ *   9 learned-selector row boxes: plan-tree box ids (int32, rows)
  */
 #define PH_BOX_FIELDS 10  /* level, ax, ay, az, src_first, src_count, tgt_first, tgt_count, parent, flags */
 ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, int64_t *n_out);
@@ -234,30 +236,37 @@ ph_status ph_adam_step(float *params, float *m1, float *m2, const float *grad, i
                        float lr, float beta1, float beta2, float eps, int64_t step, void *stream);
 
 /*
- * Learned selector rows: the source leaves (leaves holding selected sources) of the
- * last ph_evaluate's tree, in box order.  Eight features per leaf b (E_max = max |E|,
- * I_max = max I over all points, w_ref = h^3 on grids else cube volume / n):
+ * Learned selector rows (adaptive source selection of Sec. 3, decided per leaf by the
+ * network; not in the paper): the leaves of the plan's tree over all points that hold at
+ * least one candidate source, I >= thresholds.src_rel * I_max, in box order.  Eight
+ * features per row b (E_max = max |E|, I_max = max I over all points, w_ref = h^3 on grids
+ * else cube volume / n; sums and maxima of I over b's candidates):
  *   0 log10(max_b I / I_max)              1 log10(sum_b w I / (I_max w_ref))
  *   2 log2(side_b / w_ref^(1/3))          3 log10(1 + |centre_b - x_Emax| / side_b)
  *   4 max |E| / E_max over b's points     5 mean |E| / E_max    6 std |E| / E_max
  *   7 max |E| / E_max over the 27 boxes around b (features 3-7 are 0 without |E|)
- * I and absE must be the arrays of that evaluation.  feats: device, cap_leaves x 8
- * floats; *n_leaves receives the row count (rows beyond cap_leaves are not written).
- * Synchronous.  Threshold-selector plans give the rows a learned plan would decide on.
+ * x_Emax is the point of largest |E| (first in caller order among ties).  A learned plan
+ * keeps row b iff the network's BF16 logit is >= selector_logit_threshold.
+ * I (device, plan precision) and absE (device, nullable) are a call's inputs; this call
+ * resets the plan's per-call scalars (run ph_evaluate again before fetching its results).
+ * feats: device, cap_leaves x 8 floats (nullable); *n_leaves receives the row count, rows
+ * beyond cap_leaves are not written.  Synchronous.
  */
 ph_status ph_selector_features(ph_plan *plan, const void *I, const float *absE, float *feats,
                                int64_t cap_leaves, int64_t *n_leaves, void *stream);
 
 /*
- * Training labels: for every row of the last ph_selector_features call, the Euclidean
- * norm over the given targets of that leaf's exact field sum_{j in leaf} w_j I_j K(|x - y_j|)
- * (own-cell term included), times P: the units of S_out, so that leaf b's share of the
- * field is contrib_b / ||S_out||_2 over the same targets.
- * targets: device, n_targets caller-order point indices.  contrib: device, one float per
- * row (cap_rows of them).  Synchronous.
+ * Training labels: for the first n_rows rows of the last ph_selector_features call (same
+ * I), the field of each row's candidate sources at the given targets, in the units of
+ * S_out (Sec. 2.4 eq. (15) restricted to those sources, own-cell term included, times P):
+ *   out[r * ld + t] = P sum_{j in row r} G(x_{targets[t]}, y_j) I_j.
+ * Every such field is non-negative, so the Gram matrix of the rows bounds exactly how
+ * much S changes when a set of rows is dropped.  targets: device, n_targets caller-order
+ * indices; out: device, n_rows x ld floats, ld >= n_targets.  Kernel values in the plan's
+ * precision, sums in FP64.  PH_EINVAL if n_rows exceeds the row count.  Synchronous.
  */
-ph_status ph_selector_contrib(ph_plan *plan, const int32_t *targets, int64_t n_targets, float *contrib,
-                              int64_t cap_rows, void *stream);
+ph_status ph_selector_fields(ph_plan *plan, const void *I, const int32_t *targets, int64_t n_targets,
+                             float *out, int64_t ld, int64_t n_rows, void *stream);
 
 #ifdef __cplusplus
 }

@@ -68,7 +68,7 @@ WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pa
 
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
-            "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_contrib"]
+            "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_fields"]
 
 _lib = None
 
@@ -124,8 +124,8 @@ def load(path: Optional[str] = None):
     lib.ph_phase_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ph_selector_features.restype = ctypes.c_int
     lib.ph_selector_features.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), vp]
-    lib.ph_selector_contrib.restype = ctypes.c_int
-    lib.ph_selector_contrib.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
+    lib.ph_selector_fields.restype = ctypes.c_int
+    lib.ph_selector_fields.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, ctypes.c_int64, vp]
     _lib = lib
     return lib
 
@@ -223,7 +223,7 @@ class Plan:
                          "t_ms": list(st.t_ms), "work": dict(zip(WORK, list(st.work)))}
         return out
 
-    PHASES = ("select", "tree", "selector", "lists", "upward", "downward", "leaf", "near")
+    PHASES = ("reduce", "selector", "select", "tree", "lists", "upward", "downward", "leaf", "near")
 
     def phase_times(self, record: int = -1):
         """Summed per-phase device ms since the last query, and the number of calls."""
@@ -296,10 +296,14 @@ def selector_features(plan: Plan, I, E=None, stream=None):
     return feats[: n.value]
 
 
-def selector_contrib(plan: Plan, targets, rows: int, stream=None):
-    """Per-row field norms at the caller-order target indices (int32 device tensor)."""
+def selector_fields(plan: Plan, I, targets, rows: int, ld: int = 0, out=None, stream=None):
+    """Fields (rows x n_targets, device FP32, units of S) of the first ``rows`` selector rows at the
+    caller-order target indices (int32 device tensor), for the I of the last selector_features call."""
     import torch
-    out = torch.empty(max(rows, 1), dtype=torch.float32, device=targets.device)
-    _check(load().ph_selector_contrib(plan._h, _dptr(targets), targets.numel(), _dptr(out), out.numel(),
-                                      _stream_ptr(stream)))
-    return out[:rows]
+    nt = targets.numel()
+    ld = ld or nt
+    if out is None:
+        out = torch.empty((max(rows, 1), ld), dtype=torch.float32, device=targets.device)
+    _check(load().ph_selector_fields(plan._h, _dptr(I), _dptr(targets), nt, _dptr(out), ld, rows,
+                                     _stream_ptr(stream)))
+    return out[:rows, :nt]

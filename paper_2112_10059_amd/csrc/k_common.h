@@ -114,4 +114,19 @@ __host__ __device__ __forceinline__ int m2l_slot(int dx, int dy, int dz)
     return full - skipped;
 }
 
+// A source value the method cannot use: negative, NaN or infinite.
+template <class T>
+__device__ __forceinline__ bool bad_value(T v)
+{
+    return !(v >= T(0)) || isinf(v);
+}
+
+// Order key of |E| at caller index i: the float's bits (|E| >= 0 orders like its bits) above the
+// complemented index, so the largest key is the largest |E|, first in caller order among ties.
+__device__ __forceinline__ uint64_t e_key(float e, int64_t i)
+{
+    const float c = e > 0.f ? e : 0.f;  // NaN and negative values rank lowest
+    return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
+}
+
 }  // namespace ph

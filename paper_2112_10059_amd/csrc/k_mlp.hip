@@ -40,32 +40,69 @@ __device__ __forceinline__ float q(float x)
     return BF16 ? round_bf16(x) : x;
 }
 
+// Inference, one wave per row: lane i owns hidden unit i of both layers.  The first two
+// weight matrices are staged transposed in LDS so that the 64 lanes read consecutive words;
+// the hidden activations of layer 1 are broadcast lane by lane, and the output layer is a
+// fixed butterfly sum over the wave.  Every inference (the evaluation path and the
+// standalone forward call) runs mlp_row, so their logits agree bit for bit.
+struct MlpLds {
+    float w1t[NIN * NH], w2t[NH * NH], b1[NH], b2[NH], w3[NH], b3;
+};
+
 template <bool BF16>
-__global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restrict__ params, const float *__restrict__ X,
-                                                          int64_t m, float *__restrict__ logits)
+__device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
 {
-    __shared__ float w[NP];
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) w[i] = q<BF16>(params[i]);
+    // walk the LDS side in order (consecutive threads, consecutive banks)
+    for (int t = threadIdx.x; t < NH * NIN; t += blockDim.x) {
+        const int k = t / NH, u = t % NH;
+        L.w1t[t] = q<BF16>(params[OFF_W1 + u * NIN + k]);
+    }
+    for (int t = threadIdx.x; t < NH * NH; t += blockDim.x) {
+        const int j = t / NH, u = t % NH;
+        L.w2t[t] = q<BF16>(params[OFF_W2 + u * NH + j]);
+    }
+    if (threadIdx.x < NH) {
+        L.b1[threadIdx.x] = q<BF16>(params[OFF_B1 + threadIdx.x]);
+        L.b2[threadIdx.x] = q<BF16>(params[OFF_B2 + threadIdx.x]);
+        L.w3[threadIdx.x] = q<BF16>(params[OFF_W3 + threadIdx.x]);
+    }
+    if (threadIdx.x == 0) L.b3 = q<BF16>(params[OFF_B3]);
+}
+
+// x: the row's 8 inputs, the same values in every lane.  Returns the logit in every lane.
+template <bool BF16>
+__device__ __forceinline__ float mlp_row(const float (&x)[NIN], const MlpLds &L, int lane)
+{
+    float a = L.b1[lane];
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) a += L.w1t[k * NH + lane] * q<BF16>(x[k]);
+    const float h1 = q<BF16>(gelu(a));
+    float a2 = L.b2[lane];
+#pragma unroll 16
+    for (int j = 0; j < NH; ++j) a2 += L.w2t[j * NH + lane] * __shfl(h1, j);
+    float z = L.w3[lane] * q<BF16>(gelu(a2));
+    for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
+    return z + L.b3;
+}
+
+// m_dev (nullable) caps the row count from the device.
+template <bool BF16>
+__global__ __launch_bounds__(256) void mlp_rows_kernel(const float *__restrict__ params, const float *__restrict__ X,
+                                                       int64_t m, const int32_t *__restrict__ m_dev,
+                                                       float *__restrict__ logits)
+{
+    __shared__ MlpLds L;
+    stage_weights<BF16>(params, L);
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= m) return;
-    float x[NIN];
-    for (int k = 0; k < NIN; ++k) x[k] = q<BF16>(X[r * NIN + k]);
-    float h1[NH];
+    const int64_t rows = m_dev ? min(m, (int64_t)*m_dev) : m;
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gridDim.x * 4) {
+        float x[NIN];
 #pragma unroll
-    for (int i = 0; i < NH; ++i) {
-        float a = w[OFF_B1 + i];
-        for (int k = 0; k < NIN; ++k) a += w[OFF_W1 + i * NIN + k] * x[k];
-        h1[i] = q<BF16>(gelu(a));
+        for (int k = 0; k < NIN; ++k) x[k] = X[r * NIN + k];
+        const float z = mlp_row<BF16>(x, L, lane);
+        if (lane == 0) logits[r] = z;
     }
-    float z = w[OFF_B3];
-    for (int i = 0; i < NH; ++i) {
-        float a = w[OFF_B2 + i];
-#pragma unroll
-        for (int j = 0; j < NH; ++j) a += w[OFF_W2 + i * NH + j] * h1[j];
-        z += w[OFF_W3 + i] * q<BF16>(gelu(a));
-    }
-    logits[r] = z;
 }
 
 constexpr int kRows = 32;  // rows per backward block
@@ -186,12 +223,14 @@ size_t g_partial_bytes = 0;
 
 }  // namespace
 
-void launch_mlp_forward(const float *params, const float *X, int64_t m, float *logits, int bf16, hipStream_t s)
+void launch_mlp_forward(const float *params, const float *X, int64_t m, const int32_t *m_dev, float *logits,
+                        int bf16, hipStream_t s)
 {
     if (m == 0) return;
-    const unsigned g = (unsigned)((m + 255) / 256);
-    if (bf16) mlp_forward_kernel<true><<<g, 256, 0, s>>>(params, X, m, logits);
-    else mlp_forward_kernel<false><<<g, 256, 0, s>>>(params, X, m, logits);
+    // a device-side row count is small (selector rows): fewer blocks stage the weights
+    const unsigned g = (unsigned)std::min<int64_t>((m + 3) / 4, m_dev ? 256 : 1024);
+    if (bf16) mlp_rows_kernel<true><<<g, 256, 0, s>>>(params, X, m, m_dev, logits);
+    else mlp_rows_kernel<false><<<g, 256, 0, s>>>(params, X, m, m_dev, logits);
 }
 
 void launch_mlp_backward(const float *params, const float *X, const float *y, float pos_weight, int64_t m,
@@ -221,26 +260,16 @@ void launch_adam(float *params, float *m1, float *m2, const float *grad, int64_t
     adam_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(params, m1, m2, grad, n, lr, b1, b2, eps, c1, c2);
 }
 
-// ---------------------------------------------------------------- selector rows and features
+
+// ---------------------------------------------------------------- selector rows, features, decisions
+//
+// The selector decides on the leaves of the plan's tree (the tree over all points, fixed at
+// plan time), straight from the sorted arrays, before any selection of the call: a row is a
+// plan leaf holding at least one candidate source (I >= src_rel I_max, the threshold rule of
+// the plan), and a dropped row removes all its candidates from the call's source set.
+// Two passes over the plan leaves: per-leaf statistics, then features and decisions.
 
 namespace {
-
-__global__ void leaf_flag_kernel(BoxArrays bx, int32_t nbox, uint32_t *__restrict__ flag)
-{
-    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f == 0) flag[nbox] = 0;
-    if (f >= nbox) return;
-    flag[f] = ((bx.flags[f] & kBoxLeaf) && bx.s_cnt[f] > 0) ? 1u : 0u;
-}
-
-__global__ void leaf_rows_kernel(int32_t nbox, const uint32_t *__restrict__ scanned, int32_t *__restrict__ rows,
-                                 CallScalars *__restrict__ sc)
-{
-    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f == 0) sc->n_srcleaf = (int32_t)scanned[nbox];
-    if (f >= nbox) return;
-    if (scanned[f + 1] != scanned[f]) rows[scanned[f]] = f;
-}
 
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -253,204 +282,407 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-struct FeatArgs {
+__device__ __forceinline__ bool candidate(double v, double src_rel, double imax)
+{
+    // the same expression as the selection kernel's source rule
+    return (src_rel <= 0.0) || (v >= src_rel * imax);
+}
+
+struct LeafArgs {
     BoxArrays bx;
-    const int32_t *s_pos, *perm, *rows;
+    const int32_t *pleaf, *pleaf_of_box, *perm, *iperm;
+    int32_t n_pleaf;
     const double *xyz;
     const double *w;  // sorted quadrature weights, null on uniform grids (w = w_ref)
     const float *E;
-    const CallScalars *sc;
+    CallScalars *sc;
+    uint32_t *flag, *flag2;  // candidate flags (flag2: a copy for the row compaction, nullable)
+    int32_t *list;           // candidate leaves (plan-leaf indices, any order)
+    double *lstat;           // per leaf: max I, sum |E|, sum |E|^2, max |E|
+    float *box_emax;         // per leaf box: max |E|
     float *feats;
-    double lo0, lo1, lo2, cube, w_ref;
-    int64_t n;
+    int32_t *cnt;
+    double lo0, lo1, lo2, cube, w_ref, src_rel;
+    // decisions (evaluation path)
+    const float *params;
+    float threshold;
+    float *logits;
+    uint8_t *drop;
 };
 
-// one wave per source leaf; the wave sums in a fixed lane/stride order
-template <class T>
-__global__ __launch_bounds__(256) void features_kernel(FeatArgs a, const T *__restrict__ I)
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
 {
-    const int lane = threadIdx.x & 63;
-    const int32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= a.sc->n_srcleaf) return;
-    const int32_t f = a.rows[r];
-    const double imax = a.sc->imax, emax = a.sc->emax;
-    const int level = a.bx.level[f];
-    const double side = a.cube / (double)(1 << level), hw = 0.5 * side;
-    const double cx = a.lo0 + (2.0 * a.bx.ax[f] + 1.0) * hw, cy = a.lo1 + (2.0 * a.bx.ay[f] + 1.0) * hw,
-                 cz = a.lo2 + (2.0 * a.bx.az[f] + 1.0) * hw;
-    // sources: max I and sum of w I over the leaf
-    double mx = 0.0, swi = 0.0;
-    const int32_t sf = a.bx.s_first[f], sn = a.bx.s_cnt[f];
-    for (int32_t j = lane; j < sn; j += 64) {
-        const int32_t k = a.s_pos[sf + j];
-        const double v = (double)I[a.perm[k]];
-        mx = fmax(mx, v);
-        swi += v * (a.w ? a.w[k] : a.w_ref);
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o), hi = __shfl_xor((uint32_t)(v >> 32), o);
+        const uint64_t u = ((uint64_t)hi << 32) | lo;
+        v = u > v ? u : v;
     }
-    mx = wave_max(mx);
-    swi = wave_sum(swi);
-    float fe[8];
-    fe[0] = (float)log10(fmax(mx / imax, 1e-300));
-    fe[1] = (float)log10(fmax(swi / (imax * a.w_ref), 1e-300));
-    fe[2] = (float)log2(side / cbrt(a.w_ref));
-    for (int q = 3; q < 8; ++q) fe[q] = 0.0f;
-    if (a.E && emax > 0.0) {
-        const int64_t kp = a.n - a.sc->emax_pos_rev;
-        const double dx = cx - a.xyz[3 * kp], dy = cy - a.xyz[3 * kp + 1], dz = cz - a.xyz[3 * kp + 2];
-        fe[3] = (float)log10(1.0 + sqrt(dx * dx + dy * dy + dz * dz) / side);
-        const int32_t st = a.bx.start[f], en = a.bx.end[f];
-        double emx = 0.0, es = 0.0, es2 = 0.0;
-        for (int32_t k = st + lane; k < en; k += 64) {
-            const double e = (double)a.E[a.perm[k]] / emax;
-            emx = fmax(emx, e);
-            es += e;
-            es2 += e * e;
-        }
-        emx = wave_max(emx);
-        es = wave_sum(es);
-        es2 = wave_sum(es2);
-        const double cnt = (double)(en - st);
-        const double mean = es / cnt;
-        fe[4] = (float)emx;
-        fe[5] = (float)mean;
-        fe[6] = (float)sqrt(fmax(es2 / cnt - mean * mean, 0.0));
-        double nmx = 0.0;
-        for (int d = 0; d < 27; ++d) {
-            const int32_t C = a.bx.coll[(size_t)f * 27 + d];
-            if (C < 0) continue;
-            const int32_t cs = a.bx.start[C], ce = a.bx.end[C];
-            for (int32_t k = cs + lane; k < ce; k += 64) nmx = fmax(nmx, (double)a.E[a.perm[k]] / emax);
-        }
-        fe[7] = (float)wave_max(nmx);
-    }
-    if (lane < 8) a.feats[(size_t)r * 8 + lane] = fe[lane];
+    return v;
 }
 
-// ||field of leaf b||_2 over the sampled targets, in the units of S (one workgroup per row)
+constexpr int kLPW = 4;  // plan leaves per wave in the statistics pass: 16 lanes each
+
+// sum / max over the 16 lanes of a quarter-wave (butterfly, fixed order)
+__device__ __forceinline__ double quarter_sum(double v)
+{
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double quarter_max(double v)
+{
+    for (int o = 8; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Pass 1, over the plan leaves in sorted order (grid-stride; a wave takes kLPW leaves, 16
+// lanes each, so one set of 16-lane reductions serves four leaves): per leaf the largest I and
+// the sum, sum of squares and maximum of |E|; per block the partial maxima of I and of the
+// |E| order key over all points (the same maxima as the plain reduction).
 template <class T>
-__global__ __launch_bounds__(256) void contrib_kernel(BoxArrays bx, const int32_t *__restrict__ rows,
-                                                      const CallScalars *__restrict__ sc,
-                                                      const V4<T> *__restrict__ s_dat, const int32_t *__restrict__ s_pos,
-                                                      const int32_t *__restrict__ iperm, const double *__restrict__ xyz,
-                                                      const int32_t *__restrict__ targets, int64_t nt, KParams<T> kp,
-                                                      double c_self_over_w, double P, float *__restrict__ out,
-                                                      int64_t cap)
+__global__ __launch_bounds__(256) void leaf_reduce_kernel(LeafArgs a, const T *__restrict__ I,
+                                                          double *__restrict__ partial,
+                                                          uint64_t *__restrict__ partial_key)
+{
+    __shared__ double smI[4];
+    __shared__ uint64_t smE[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int slot = lane >> 4, sub = lane & 15;
+    const bool has_e = a.E != nullptr;
+    double gmax = 0.0;
+    uint64_t gkey = 0;
+    int bad = 0;
+    for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * kLPW; base < a.n_pleaf;
+         base += (int64_t)gridDim.x * 4 * kLPW) {
+        const int64_t i = base + slot;
+        const int32_t f = i < a.n_pleaf ? a.pleaf[i] : -1;
+        const int32_t st = f >= 0 ? a.bx.start[f] : 0, en = f >= 0 ? a.bx.end[f] : 0;
+        double mx = 0.0, es = 0.0, es2 = 0.0;
+        float emx = 0.0f;
+        for (int32_t k0 = st; k0 < en; k0 += 64) {
+            // up to four points per lane, all loads issued before use
+            int32_t o[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int32_t k = k0 + sub + 16 * m;
+                o[m] = k < en ? a.perm[k] : -1;
+            }
+            T v[4];
+            float e[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                v[m] = o[m] >= 0 ? I[o[m]] : T(0);
+                e[m] = (has_e && o[m] >= 0) ? a.E[o[m]] : 0.0f;
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (o[m] < 0) continue;
+                if (bad_value(v[m])) bad = 1;
+                else mx = fmax(mx, (double)v[m]);
+                if (has_e) {
+                    gkey = max(gkey, e_key(e[m], o[m]));
+                    emx = fmaxf(emx, e[m]);
+                    es += (double)e[m];
+                    es2 += (double)e[m] * (double)e[m];
+                }
+            }
+        }
+        gmax = fmax(gmax, mx);
+        mx = quarter_max(mx);
+        es = quarter_sum(es);
+        es2 = quarter_sum(es2);
+        const double em = quarter_max((double)emx);
+        if (sub == 0 && f >= 0) {
+            double *L = a.lstat + (size_t)i * 4;
+            L[0] = mx;
+            L[1] = es;
+            L[2] = es2;
+            L[3] = em;
+            a.box_emax[f] = (float)em;
+        }
+    }
+    if (bad) atomicOr(&a.sc->err, 1);
+    gmax = wave_max(gmax);
+    gkey = wave_max_u64(gkey);
+    if (lane == 0) {
+        smI[wv] = gmax;
+        smE[wv] = gkey;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = smI[0];
+        uint64_t k = smE[0];
+        for (int q = 1; q < 4; ++q) {
+            m = fmax(m, smI[q]);
+            k = max(k, smE[q]);
+        }
+        partial[blockIdx.x] = m;
+        partial_key[blockIdx.x] = k;
+    }
+}
+
+// Pass 2, one thread per plan leaf: it is a row iff its largest I passes the source rule.
+__global__ void leaf_pick_kernel(LeafArgs a)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && a.flag2) a.flag2[a.n_pleaf] = 0;
+    if (i >= a.n_pleaf) return;
+    const bool cand = candidate(a.lstat[(size_t)i * 4], a.src_rel, a.sc->imax);
+    a.flag[i] = cand ? 1u : 0u;
+    if (a.flag2) a.flag2[i] = cand ? 1u : 0u;
+    if (cand) a.list[atomicAdd(&a.sc->n_srcleaf, 1)] = i;
+}
+
+// Pass 3, one wave per row (grid-stride over the candidate list): the candidates' count and
+// sum of w I, the eight features; with DECIDE also the network (BF16) and the keep/drop
+// decision, keep iff logit >= threshold.  The drop byte of every point of a decided leaf is
+// written (0 or 1), so the mask needs no clearing: points outside candidate leaves fail the
+// source rule anyway.  A non-finite logit switches the call to the fallback rule.  Sums run
+// in a fixed lane/stride/butterfly order; results do not depend on the list's order.
+template <class T, bool DECIDE>
+__global__ __launch_bounds__(256) void leaf_features_kernel(LeafArgs a, const T *__restrict__ I)
+{
+    __shared__ MlpLds L;
+    const int lane = threadIdx.x & 63;
+    const int32_t nrow = a.sc->n_srcleaf;
+    if ((int32_t)blockIdx.x * 4 >= nrow) return;  // the whole block
+    if (DECIDE) {
+        stage_weights<true>(a.params, L);
+        __syncthreads();
+    }
+    const double imax = a.sc->imax, emax = a.sc->emax;
+    for (int32_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrow; r += gridDim.x * 4) {
+        const int32_t i = a.list[r];
+        const int32_t f = a.pleaf[i];
+        const int32_t st = a.bx.start[f], en = a.bx.end[f];
+        double swi = 0.0, cnt = 0.0;
+        for (int32_t k = st + lane; k < en; k += 64) {
+            const double v = (double)I[a.perm[k]];
+            if (!candidate(v, a.src_rel, imax)) continue;
+            swi += v * (a.w ? a.w[k] : a.w_ref);
+            cnt += 1.0;
+        }
+        swi = wave_sum(swi);
+        cnt = wave_sum(cnt);
+        const double *S = a.lstat + (size_t)i * 4;
+        const int level = a.bx.level[f];
+        const double side = a.cube / (double)(1 << level), hw = 0.5 * side;
+        float fe[8];
+        fe[0] = (float)log10(fmax(S[0] / imax, 1e-300));
+        fe[1] = (float)log10(fmax(swi / (imax * a.w_ref), 1e-300));
+        fe[2] = (float)log2(side / cbrt(a.w_ref));
+        for (int q = 3; q < 8; ++q) fe[q] = 0.0f;
+        if (a.E && emax > 0.0) {
+            const double cx = a.lo0 + (2.0 * a.bx.ax[f] + 1.0) * hw, cy = a.lo1 + (2.0 * a.bx.ay[f] + 1.0) * hw,
+                         cz = a.lo2 + (2.0 * a.bx.az[f] + 1.0) * hw;
+            const int64_t kp = a.iperm[0xffffffffu - (uint32_t)(a.sc->emax_key & 0xffffffffu)];
+            const double dx = cx - a.xyz[3 * kp], dy = cy - a.xyz[3 * kp + 1], dz = cz - a.xyz[3 * kp + 2];
+            fe[3] = (float)log10(1.0 + sqrt(dx * dx + dy * dy + dz * dz) / side);
+            const double nn = (double)(en - st);
+            const double mean = S[1] / emax / nn;
+            fe[4] = (float)(S[3] / emax);
+            fe[5] = (float)mean;
+            fe[6] = (float)sqrt(fmax(S[2] / (emax * emax) / nn - mean * mean, 0.0));
+            // the 27 boxes around the leaf, one lane each: a leaf's stored maximum, or the box's range
+            double nmx = 0.0;
+            if (lane < 27) {
+                const int32_t C = a.bx.coll[(size_t)f * 27 + lane];
+                if (C >= 0) {
+                    if (a.pleaf_of_box[C] >= 0) {
+                        nmx = (double)a.box_emax[C];
+                    } else {
+                        for (int32_t k = a.bx.start[C]; k < a.bx.end[C]; ++k)
+                            nmx = fmax(nmx, (double)a.E[a.perm[k]]);
+                    }
+                }
+            }
+            fe[7] = (float)(wave_max(nmx) / emax);
+        }
+        if (lane < 8) a.feats[(size_t)i * 8 + lane] = fe[lane];
+        if (lane == 0) a.cnt[i] = (int32_t)cnt;
+        if (DECIDE) {
+            const float z = mlp_row<true>(fe, L, lane);
+            if (lane == 0) a.logits[i] = z;
+            if (!isfinite(z)) {
+                if (lane == 0) atomicOr(&a.sc->fallback, 1);
+                continue;
+            }
+            if (lane == 0) atomicAdd(&a.sc->n_src_base, (int32_t)cnt);
+            const uint8_t d = z >= a.threshold ? 0 : 1;
+            for (int32_t k = st + lane; k < en; k += 64) a.drop[k] = d;
+        }
+    }
+}
+
+// Row compaction for the training entry points: rows in box order, with their features.
+__global__ void rows_kernel(const int32_t *__restrict__ pleaf, int32_t n_pleaf, const uint32_t *__restrict__ scanned,
+                            const float *__restrict__ feats, int32_t *__restrict__ rows,
+                            float *__restrict__ row_feats)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pleaf) return;
+    if (scanned[i + 1] == scanned[i]) return;
+    const uint32_t r = scanned[i];
+    rows[r] = pleaf[i];
+    for (int k = 0; k < 8; ++k) row_feats[(size_t)r * 8 + k] = feats[(size_t)i * 8 + k];
+}
+
+// Field of each row's candidate sources at the given targets, in the units of S:
+// out[r ld + t] = P 2^e sum_{k in row r} (w_k I_k 2^-e K(|x_t - x_k|), or c_self I_k 2^-e when
+// x_t is x_k).  Kernel values in FP32 (FP64 plans: FP64), sums in FP64.
+struct FieldArgs {
+    BoxArrays bx;
+    const int32_t *perm, *iperm, *rows;
+    const double *xyz, *w;
+    const CallScalars *sc;
+    double w_ref, c_self, src_rel, P;
+};
+
+constexpr int kFieldTargets = 2048;  // targets per block (eight passes of 256)
+
+template <class T>
+__global__ __launch_bounds__(256) void fields_kernel(FieldArgs a, KParams<T> kp, const T *__restrict__ I,
+                                                     const int32_t *__restrict__ targets, int64_t nt,
+                                                     float *__restrict__ out, int64_t ld)
 {
     __shared__ V4<T> tile[256];
     __shared__ int32_t tpos[256];
-    __shared__ double red[256];
-    const int32_t r = blockIdx.x;
-    if (r >= sc->n_srcleaf || r >= cap) return;
-    const int32_t f = rows[r];
-    const int32_t sf = bx.s_first[f], sn = bx.s_cnt[f];
-    double acc = 0.0;
-    for (int64_t t0 = 0; t0 < nt; t0 += 256) {
-        const int64_t t = t0 + threadIdx.x;
-        const bool act = t < nt;
-        int32_t kt = 0;
-        T x = 0, y = 0, z = 0;
-        if (act) {
-            kt = iperm[targets[t]];
-            x = (T)xyz[3 * (int64_t)kt];
-            y = (T)xyz[3 * (int64_t)kt + 1];
-            z = (T)xyz[3 * (int64_t)kt + 2];
-        }
-        double sfield = 0.0;
-        for (int base = 0; base < sn; base += 256) {
-            const int m = min(256, sn - base);
-            __syncthreads();
-            if ((int)threadIdx.x < m) {
-                tile[threadIdx.x] = s_dat[sf + base + threadIdx.x];
-                tpos[threadIdx.x] = s_pos[sf + base + threadIdx.x];
-            }
-            __syncthreads();
-            if (act)
-                for (int j = 0; j < m; ++j) {
-                    const V4<T> yj = tile[j];
-                    const T dx = x - yj.x, dy = y - yj.y, dz = z - yj.z;
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    if (tpos[j] == kt) sfield += c_self_over_w * (double)yj.w;
-                    else if (r2 > T(0)) sfield += (double)(kernel_eval<true>(r2, kp) * yj.w);
-                }
-        }
-        acc += sfield * sfield;
+    const int32_t r = blockIdx.y;
+    const int32_t f = a.rows[r];
+    const int32_t st = a.bx.start[f], en = a.bx.end[f];
+    const double imax = a.sc->imax;
+    int e = 0;
+    if (imax > 0.0) {
+        (void)frexp(imax, &e);
+        e -= 1;
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    const double scale = ldexp(1.0, -e);
+    const bool one_tile = en - st <= 256;
+    auto load_tile = [&](int32_t base) {
+        const int32_t k = base + (int32_t)threadIdx.x;
+        if (k < en) {
+            const double v = (double)I[a.perm[k]];
+            const double wk = a.w ? a.w[k] : a.w_ref;
+            V4<T> y;
+            y.x = (T)a.xyz[3 * (int64_t)k];
+            y.y = (T)a.xyz[3 * (int64_t)k + 1];
+            y.z = (T)a.xyz[3 * (int64_t)k + 2];
+            y.w = candidate(v, a.src_rel, imax) ? (T)(wk * v * scale) : T(0);
+            tile[threadIdx.x] = y;
+            tpos[threadIdx.x] = k;
+        }
+    };
+    if (one_tile) {
+        load_tile(st);
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[r] = (float)(sqrt(red[0]) * P * ldexp(1.0, sc->scale_exp));
-}
-
-__global__ void zero_bytes_kernel(uint8_t *__restrict__ p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
-// keep a source leaf iff its logit >= threshold; sources of dropped leaves are marked.
-// A non-finite logit switches the call to the threshold fallback.
-__global__ void decide_kernel(BoxArrays bx, const int32_t *__restrict__ rows, const float *__restrict__ logits,
-                              float thr, const int32_t *__restrict__ s_pos, uint8_t *__restrict__ drop,
-                              CallScalars *__restrict__ sc)
-{
-    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r == 0) sc->n_src_base = sc->n_src;
-    if (r >= sc->n_srcleaf) return;
-    const float z = logits[r];
-    if (!isfinite(z)) {
-        atomicOr(&sc->fallback, 1);
-        return;
+    const double own = a.w ? 0.0 : a.c_self / a.w_ref;  // own cell on uniform grids only
+    const int64_t t0 = (int64_t)blockIdx.x * kFieldTargets;
+    for (int64_t tb = t0; tb < min(nt, t0 + kFieldTargets); tb += 256) {
+        const int64_t t = tb + threadIdx.x;
+        const bool act = t < nt;
+        int32_t kt = -1;
+        T x = 0, y = 0, z = 0;
+        if (act) {
+            kt = a.iperm[targets[t]];
+            x = (T)a.xyz[3 * (int64_t)kt];
+            y = (T)a.xyz[3 * (int64_t)kt + 1];
+            z = (T)a.xyz[3 * (int64_t)kt + 2];
+        }
+        double acc = 0.0;
+        for (int32_t base = st; base < en; base += 256) {
+            if (!one_tile) {
+                __syncthreads();
+                load_tile(base);
+                __syncthreads();
+            }
+            const int m = min(256, en - base);
+            if (act)
+                for (int j = 0; j < m; ++j) {
+                    const V4<T> s = tile[j];
+                    if (s.w == T(0)) continue;
+                    if (tpos[j] == kt) {
+                        acc += own * (double)s.w;
+                        continue;
+                    }
+                    const T dx = x - s.x, dy = y - s.y, dz = z - s.z;
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 > T(0)) acc += (double)(kernel_eval<true>(r2, kp) * s.w);
+                }
+        }
+        if (act) out[(int64_t)r * ld + t] = (float)(a.P * ldexp(acc, e));
     }
-    if (z >= thr) return;
-    const int32_t f = rows[r];
-    const int32_t sf = bx.s_first[f], sn = bx.s_cnt[f];
-    for (int32_t j = 0; j < sn; ++j) drop[s_pos[sf + j]] = 1;
 }
 
 }  // namespace
 
-void selector_features(Plan &p, const void *I, const float *E, hipStream_t s)
+static LeafArgs leaf_args(Plan &p, const float *E)
 {
-    const int32_t nbox = (int32_t)p.box_cap;
-    const unsigned g = (unsigned)((nbox + 256) / 256);
-    leaf_flag_kernel<<<g, 256, 0, s>>>(p.box, nbox, p.d_leafflag);
-    exclusive_scan_u32(p.d_leafflag, nbox + 1, p.d_scan_tmp, nullptr, s);
-    leaf_rows_kernel<<<g, 256, 0, s>>>(nbox, p.d_leafflag, p.d_feat_box, p.d_sc);
-    FeatArgs fa;
-    fa.bx = p.box;
-    fa.s_pos = p.d_s_pos;
-    fa.perm = p.d_perm;
-    fa.rows = p.d_feat_box;
-    fa.xyz = p.d_xyz;
-    fa.w = p.d_w;
-    fa.E = E;
-    fa.sc = p.d_sc;
-    fa.feats = p.d_feat;
-    fa.lo0 = p.cube_lo[0];
-    fa.lo1 = p.cube_lo[1];
-    fa.lo2 = p.cube_lo[2];
-    fa.cube = p.cube_size;
-    fa.w_ref = p.uniform_w ? p.w_uniform : p.cube_size * p.cube_size * p.cube_size / (double)p.n;
-    fa.n = p.n;
-    const unsigned gr = (unsigned)((p.box_cap + 3) / 4);
-    if (p.precision == PH_FP64) features_kernel<double><<<gr, 256, 0, s>>>(fa, (const double *)I);
-    else features_kernel<float><<<gr, 256, 0, s>>>(fa, (const float *)I);
+    LeafArgs a{};
+    a.bx = p.box;
+    a.pleaf = p.d_pleaf;
+    a.pleaf_of_box = p.d_pleaf_of_box;
+    a.perm = p.d_perm;
+    a.iperm = p.d_iperm;
+    a.n_pleaf = p.n_pleaf;
+    a.xyz = p.d_xyz;
+    a.w = p.d_w;
+    a.E = E;
+    a.sc = p.d_sc;
+    a.flag = p.d_leafflag;
+    a.list = p.d_cand_list;
+    a.lstat = p.d_lstat;
+    a.box_emax = p.d_box_emax;
+    a.feats = p.d_feat;
+    a.cnt = p.d_feat_cnt;
+    a.lo0 = p.cube_lo[0];
+    a.lo1 = p.cube_lo[1];
+    a.lo2 = p.cube_lo[2];
+    a.cube = p.cube_size;
+    a.w_ref = p.uniform_w ? p.w_uniform : p.cube_size * p.cube_size * p.cube_size / (double)p.n;
+    a.src_rel = p.thr.src_rel;
+    return a;
 }
 
-void selector_apply(Plan &p, const void *I, const float *E, void *S_out, hipStream_t s)
+static unsigned feature_blocks(const Plan &p) { return (unsigned)std::min<int64_t>((p.n_pleaf + 3) / 4, 256); }
+
+// the maxima of I and |E| and the per-leaf statistics in one pass (scalars reset)
+void selector_reduce(Plan &p, const void *I, const float *E, hipStream_t s)
 {
-    selector_features(p, I, E, s);
-    launch_mlp_forward(p.d_sel_params, p.d_feat, p.box_cap, p.d_logit, 1, s);
-    zero_bytes_kernel<<<1024, 256, 0, s>>>(p.d_drop, p.n);
-    decide_kernel<<<(unsigned)((p.box_cap + 255) / 256), 256, 0, s>>>(p.box, p.d_feat_box, p.d_logit,
-                                                                       p.sel_threshold, p.d_s_pos, p.d_drop, p.d_sc);
-    launch_select_flags(p, I, E, S_out, s, p.d_drop);
-    exclusive_scan_u64(p.d_flag, p.n, p.d_scan_tmp, &p.d_sc->packed_total, s);
-    launch_compact(p, I, s);
-    build_tree(p, s);
+    LeafArgs a = leaf_args(p, E);
+    const int nb = (int)std::min<int64_t>((p.n_pleaf + 4 * kLPW - 1) / (4 * kLPW), 1024);
+    double *partial = reinterpret_cast<double *>(p.d_scan_tmp);
+    uint64_t *partial_key = reinterpret_cast<uint64_t *>(partial + 1024);
+    if (p.precision == PH_FP64)
+        leaf_reduce_kernel<double><<<nb, 256, 0, s>>>(a, (const double *)I, partial, partial_key);
+    else
+        leaf_reduce_kernel<float><<<nb, 256, 0, s>>>(a, (const float *)I, partial, partial_key);
+    launch_reduce_max_final(partial, partial_key, nb, p.d_sc, s);
+}
+
+// rows, their features, and the rows compacted in box order (after selector_reduce)
+void selector_features(Plan &p, const void *I, const float *E, hipStream_t s)
+{
+    LeafArgs a = leaf_args(p, E);
+    a.flag2 = p.d_leafscan;
+    leaf_pick_kernel<<<(unsigned)((p.n_pleaf + 255) / 256), 256, 0, s>>>(a);
+    if (p.precision == PH_FP64) leaf_features_kernel<double, false><<<feature_blocks(p), 256, 0, s>>>(a, (const double *)I);
+    else leaf_features_kernel<float, false><<<feature_blocks(p), 256, 0, s>>>(a, (const float *)I);
+    exclusive_scan_u32(p.d_leafscan, p.n_pleaf + 1, p.d_scan_tmp, nullptr, s);
+    rows_kernel<<<(unsigned)((p.n_pleaf + 255) / 256), 256, 0, s>>>(p.d_pleaf, p.n_pleaf, p.d_leafscan, p.d_feat,
+                                                                    p.d_row_box, p.d_row_feat);
+}
+
+// the evaluation path after selector_reduce: rows, features, network and drop mask
+void selector_decide(Plan &p, const void *I, const float *E, hipStream_t s)
+{
+    LeafArgs a = leaf_args(p, E);
+    a.params = p.d_sel_params;
+    a.threshold = p.sel_threshold;
+    a.logits = p.d_logit;
+    a.drop = p.d_drop;
+    leaf_pick_kernel<<<(unsigned)((p.n_pleaf + 255) / 256), 256, 0, s>>>(a);
+    if (p.precision == PH_FP64) leaf_features_kernel<double, true><<<feature_blocks(p), 256, 0, s>>>(a, (const double *)I);
+    else leaf_features_kernel<float, true><<<feature_blocks(p), 256, 0, s>>>(a, (const float *)I);
 }
 
 }  // namespace ph
@@ -459,14 +691,16 @@ extern "C" ph_status ph_selector_features(ph_plan *plan, const void *I, const fl
                                           int64_t cap_leaves, int64_t *n_leaves, void *stream)
 {
     using namespace ph;
-    if (!plan || !I || !n_leaves) {
-        set_last_error("plan, I and n_leaves must be non-null");
+    if (!plan || !I || !n_leaves || cap_leaves < 0) {
+        set_last_error("plan, I and n_leaves must be non-null and cap_leaves >= 0");
         return PH_EINVAL;
     }
     Plan &p = *reinterpret_cast<Plan *>(plan);
     try {
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         PH_HIP(hipSetDevice(p.device));
+        launch_reset_scalars(p.d_sc, s);
+        selector_reduce(p, I, absE, s);
         selector_features(p, I, absE, s);
         int32_t nrow = 0;
         PH_HIP(hipMemcpyAsync(&nrow, &p.d_sc->n_srcleaf, 4, hipMemcpyDeviceToHost, s));
@@ -474,7 +708,7 @@ extern "C" ph_status ph_selector_features(ph_plan *plan, const void *I, const fl
         *n_leaves = nrow;
         const int64_t k = std::min<int64_t>(nrow, cap_leaves);
         if (feats && k > 0)
-            PH_HIP(hipMemcpyAsync(feats, p.d_feat, (size_t)k * 8 * 4, hipMemcpyDeviceToDevice, s));
+            PH_HIP(hipMemcpyAsync(feats, p.d_row_feat, (size_t)k * 8 * 4, hipMemcpyDeviceToDevice, s));
         PH_HIP(hipStreamSynchronize(s));
         return PH_OK;
     } catch (const Error &e) {
@@ -483,29 +717,42 @@ extern "C" ph_status ph_selector_features(ph_plan *plan, const void *I, const fl
     }
 }
 
-extern "C" ph_status ph_selector_contrib(ph_plan *plan, const int32_t *targets, int64_t n_targets, float *contrib,
-                                         int64_t cap_rows, void *stream)
+extern "C" ph_status ph_selector_fields(ph_plan *plan, const void *I, const int32_t *targets, int64_t n_targets,
+                                        float *out, int64_t ld, int64_t n_rows, void *stream)
 {
     using namespace ph;
-    if (!plan || !targets || !contrib || n_targets < 1 || cap_rows < 0) {
-        set_last_error("bad selector_contrib arguments");
+    if (!plan || !I || !targets || !out || n_targets < 1 || ld < n_targets || n_rows < 0) {
+        set_last_error("bad selector_fields arguments (null pointer, n_targets < 1, ld < n_targets or n_rows < 0)");
         return PH_EINVAL;
     }
     Plan &p = *reinterpret_cast<Plan *>(plan);
     try {
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         PH_HIP(hipSetDevice(p.device));
-        const double csw = p.uniform_w && p.w_uniform > 0 ? p.c_self / p.w_uniform : 0.0;
-        const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.box_cap, cap_rows));
+        int32_t nrow = 0;
+        PH_HIP(hipMemcpyAsync(&nrow, &p.d_sc->n_srcleaf, 4, hipMemcpyDeviceToHost, s));
+        PH_HIP(hipStreamSynchronize(s));
+        if (n_rows > nrow) throw Error{PH_EINVAL, "n_rows exceeds the rows of the last ph_selector_features call"};
+        if (n_rows == 0) return PH_OK;
+        FieldArgs fa;
+        fa.bx = p.box;
+        fa.perm = p.d_perm;
+        fa.iperm = p.d_iperm;
+        fa.rows = p.d_row_box;
+        fa.xyz = p.d_xyz;
+        fa.w = p.d_w;
+        fa.sc = p.d_sc;
+        fa.w_ref = p.uniform_w ? p.w_uniform : 0.0;
+        fa.c_self = p.c_self;
+        fa.src_rel = p.thr.src_rel;
+        fa.P = p.gas.P;
+        const dim3 grid((unsigned)((n_targets + kFieldTargets - 1) / kFieldTargets), (unsigned)n_rows);
         if (p.precision == PH_FP64)
-            contrib_kernel<double><<<g, 256, 0, s>>>(p.box, p.d_feat_box, p.d_sc, (const double4 *)p.d_s_dat,
-                                                     p.d_s_pos, p.d_iperm, p.d_xyz, targets, n_targets,
-                                                     make_kparams<double>(p.gas), csw, p.gas.P, contrib, cap_rows);
+            fields_kernel<double><<<grid, 256, 0, s>>>(fa, make_kparams<double>(p.gas), (const double *)I, targets,
+                                                       n_targets, out, ld);
         else
-            contrib_kernel<float><<<g, 256, 0, s>>>(p.box, p.d_feat_box, p.d_sc, (const float4 *)p.d_s_dat, p.d_s_pos,
-                                                    p.d_iperm, p.d_xyz, targets, n_targets,
-                                                    make_kparams<float>(p.gas), csw, p.gas.P, contrib,
-                                                    cap_rows);
+            fields_kernel<float><<<grid, 256, 0, s>>>(fa, make_kparams<float>(p.gas), (const float *)I, targets,
+                                                      n_targets, out, ld);
         PH_HIP(hipGetLastError());
         PH_HIP(hipStreamSynchronize(s));
         return PH_OK;

@@ -8,7 +8,7 @@
 // every octree box is a contiguous run in each list.
 #include <hip/hip_runtime.h>
 
-#include "ph_internal.h"
+#include "k_common.h"
 
 namespace ph {
 
@@ -20,30 +20,24 @@ __global__ void reset_scalars_kernel(CallScalars *sc)
     for (int i = threadIdx.x; i < (int)(sizeof(CallScalars) / 4); i += blockDim.x) w[i] = 0;
 }
 
-template <class T>
-__device__ __forceinline__ bool bad_value(T v)
-{
-    return !(v >= T(0)) || isinf(v);
-}
-
-// Maxima of I and |E|: each block reduces its grid-stride share into partial[],
-// one block then reduces the partials (no contended atomics).
+// Maxima of I and |E| (with the position of the largest |E|): each block reduces its
+// grid-stride share into partials, one block then reduces the partials (no contended atomics).
 template <class T>
 __global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restrict__ E, int64_t n,
-                                  double *__restrict__ partial, CallScalars *sc)
+                                  double *__restrict__ partial, uint64_t *__restrict__ partial_key, CallScalars *sc)
 {
     __shared__ double smI[256];
-    __shared__ float smE[256];
+    __shared__ uint64_t smE[256];
     double mi = 0.0;
-    float me = 0.f;
+    uint64_t me = 0;
     int bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         T v = I[i];
         if (bad_value(v)) bad = 1;
         else mi = fmax(mi, (double)v);
         if (E) {
-            float e = E[i];
-            if (e > me) me = e;
+            const uint64_t k = e_key(E[i], i);
+            if (k > me) me = k;
         }
     }
     smI[threadIdx.x] = mi;
@@ -52,24 +46,27 @@ __global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restri
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             smI[threadIdx.x] = fmax(smI[threadIdx.x], smI[threadIdx.x + o]);
-            smE[threadIdx.x] = fmaxf(smE[threadIdx.x], smE[threadIdx.x + o]);
+            smE[threadIdx.x] = max(smE[threadIdx.x], smE[threadIdx.x + o]);
         }
         __syncthreads();
     }
     if (bad) atomicOr(&sc->err, 1);
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = smI[0];
-        partial[2 * blockIdx.x + 1] = (double)smE[0];
+        partial[blockIdx.x] = smI[0];
+        partial_key[blockIdx.x] = smE[0];
     }
 }
 
-__global__ void reduce_max_final_kernel(const double *__restrict__ partial, int nb, CallScalars *sc)
+__global__ void reduce_max_final_kernel(const double *__restrict__ partial, const uint64_t *__restrict__ partial_key,
+                                        int nb, CallScalars *sc)
 {
-    __shared__ double a[256], b[256];
-    double mi = 0.0, me = 0.0;
+    __shared__ double a[256];
+    __shared__ uint64_t b[256];
+    double mi = 0.0;
+    uint64_t me = 0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        mi = fmax(mi, partial[2 * i]);
-        me = fmax(me, partial[2 * i + 1]);
+        mi = fmax(mi, partial[i]);
+        me = max(me, partial_key[i]);
     }
     a[threadIdx.x] = mi;
     b[threadIdx.x] = me;
@@ -77,13 +74,14 @@ __global__ void reduce_max_final_kernel(const double *__restrict__ partial, int 
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             a[threadIdx.x] = fmax(a[threadIdx.x], a[threadIdx.x + o]);
-            b[threadIdx.x] = fmax(b[threadIdx.x], b[threadIdx.x + o]);
+            b[threadIdx.x] = max(b[threadIdx.x], b[threadIdx.x + o]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         sc->imax = a[0];
-        sc->emax = b[0];
+        sc->emax = (double)__uint_as_float((uint32_t)(b[0] >> 32));
+        sc->emax_key = b[0];
     }
 }
 
@@ -119,8 +117,6 @@ __global__ void select_flags_kernel(const T *__restrict__ I, const float *__rest
     }
     flag[k] = (uint64_t)(src ? 1u : 0u) | ((uint64_t)(tgt ? 1u : 0u) << 32);
     if (!tgt) S_out[o] = T(0);
-    // position of the largest |E| (smallest sorted index among ties): max of n - k
-    if (E && !drop && (double)E[o] == sc->emax) atomicMax(&sc->emax_pos_rev, (int32_t)(n - k));
 }
 
 template <class T>
@@ -202,16 +198,25 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
 
 void launch_reset_scalars(CallScalars *sc, hipStream_t s) { reset_scalars_kernel<<<1, 256, 0, s>>>(sc); }
 
+void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
+                             hipStream_t s)
+{
+    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, nb, sc);
+}
+
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n, CallScalars *sc,
                        void *tmp, hipStream_t s)
 {
     int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
     double *partial = reinterpret_cast<double *>(tmp);
+    uint64_t *partial_key = reinterpret_cast<uint64_t *>(partial + 1024);
     if (fp64)
-        reduce_max_kernel<double><<<blocks, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, n, partial, sc);
+        reduce_max_kernel<double><<<blocks, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, n, partial,
+                                                         partial_key, sc);
     else
-        reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, n, partial, sc);
-    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, blocks, sc);
+        reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, n, partial,
+                                                        partial_key, sc);
+    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, blocks, sc);
 }
 
 static SelectParams params_of(const Plan &p)

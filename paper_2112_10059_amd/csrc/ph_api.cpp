@@ -225,13 +225,20 @@ void alloc_workspace(Plan &p)
         p.z_cap_cols = (size_t)widest_par;
         p.d_z = dev_alloc(p, p.z_cap_cols * 8 * p.n_lam * rs);
     }
-    p.d_srcbox_mark = (int32_t *)dev_alloc(p, B * 4);
-    p.d_feat = (float *)dev_alloc(p, (size_t)B * 8 * 4);
-    p.d_feat_box = (int32_t *)dev_alloc(p, B * 4);
-    p.d_logit = (float *)dev_alloc(p, B * 4);
+    const int64_t NL = std::max<int32_t>(p.n_pleaf, 1);
+    p.d_feat = (float *)dev_alloc(p, (size_t)NL * 8 * 4);
+    p.d_feat_cnt = (int32_t *)dev_alloc(p, NL * 4);
+    p.d_logit = (float *)dev_alloc(p, NL * 4);
+    p.d_leafscan = (uint32_t *)dev_alloc(p, (NL + 1) * 4);
+    p.d_lstat = (double *)dev_alloc(p, (size_t)NL * 6 * 8);
+    p.d_box_emax = (float *)dev_alloc(p, (size_t)B * 4);
+    p.d_cand_list = (int32_t *)dev_alloc(p, NL * 4);
+    p.d_row_box = (int32_t *)dev_alloc(p, NL * 4);
+    p.d_row_feat = (float *)dev_alloc(p, (size_t)NL * 8 * 4);
     p.d_sel_params = (float *)dev_alloc(p, PH_MLP_NPARAM * 4);
     p.d_drop = (uint8_t *)dev_alloc(p, (size_t)n);
-    p.d_leafflag = (uint32_t *)dev_alloc(p, (B + 1) * 4);
+    p.d_leafflag = (uint32_t *)dev_alloc(p, (NL + 1) * 4);
+    PH_HIP(hipMemset(p.d_leafflag, 0, (NL + 1) * 4));  // no selector pass has run yet
     if (!p.sel_weights.empty())
         PH_HIP(hipMemcpy(p.d_sel_params, p.sel_weights.data(), PH_MLP_NPARAM * 4, hipMemcpyHostToDevice));
 }
@@ -248,7 +255,9 @@ void free_plan(Plan *p)
                     p->box.child, p->box.coll, p->box.start, p->box.end, p->box.srcflag, p->box.src_rank, p->box.tpar_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->d_phi, p->d_u,
-                    p->d_srcbox_mark, p->d_feat, p->d_feat_box, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
+                    p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
+                    p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
+                    p->d_row_feat,
                     p->d_cell,
                     p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_far};
     for (void *q : ptrs) dev_free(q);
@@ -413,6 +422,19 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         up(&bx.parent, FT.parent);
         up(&bx.child, FT.child);
         up(&bx.coll, FT.coll);
+        // leaves of the full tree (no child), in box order: the rows of the learned selector
+        std::vector<int32_t> leaves;
+        for (size_t f = 0; f < FT.level.size(); ++f) {
+            bool leaf = true;
+            for (int o = 0; o < 8 && leaf; ++o) leaf = FT.child[f * 8 + o] < 0;
+            if (leaf) leaves.push_back((int32_t)f);
+        }
+        p.n_pleaf = (int32_t)leaves.size();
+        up(&p.d_pleaf, leaves);
+        std::vector<int32_t> of_box(FT.level.size(), -1);
+        for (size_t i = 0; i < leaves.size(); ++i) of_box[leaves[i]] = (int32_t)i;
+        up(&p.d_pleaf_of_box, of_box);
+        p.h_pleaf = std::move(leaves);
     }
     p.level_base.assign(p.level_cap.size() + 1, 0);
     for (size_t l = 0; l < p.level_cap.size(); ++l) p.level_base[l + 1] = p.level_base[l] + p.level_cap[l];
@@ -512,8 +534,10 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         }
     }
     alloc_workspace(p);
+    // timing-only events: no system-scope fence, so a mark does not write back L2 (that
+    // write-back would otherwise be charged to the next phase)
     for (auto &set : p.ring)
-        for (auto &e : set) PH_HIP(hipEventCreate(&e));
+        for (auto &e : set) PH_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     p.events_ready = true;
 }
 
@@ -588,9 +612,10 @@ static ph_status fetch_scalars(Plan &p, hipStream_t s)
     return PH_OK;
 }
 
-// Phase boundaries recorded per call (events 0..8): 0 start, 1 selection done,
-// 2 tree done, 3 learned selector done, 4 lists done, 5 upward done,
-// 6 downward done, 7 far field at the targets done, 8 near field (or direct sum) done.
+// Phase boundaries recorded per call (events 0..9): 0 start, 1 maxima reduced,
+// 2 learned selector done, 3 selection and compaction done, 4 tree done, 5 lists done,
+// 6 upward done, 7 downward done, 8 far field at the targets done, 9 near field (or
+// direct sum) done.
 static void harvest_slot(Plan &p, int slot)
 {
     if (!p.ring_used[slot]) return;
@@ -626,32 +651,35 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
         auto mark = [&](int k) {
             if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], s));
         };
+        const bool learned = p.selector == PH_SEL_LEARNED;
         mark(0);
         launch_reset_scalars(p.d_sc, s);
-        launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_scan_tmp, s);
-        launch_select_flags(p, I, absE, S_out, s);
+        if (learned) selector_reduce(p, I, absE, s);  // the maxima come with the per-leaf statistics
+        else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_scan_tmp, s);
+        mark(1);
+        if (learned) selector_decide(p, I, absE, s);
+        mark(2);
+        launch_select_flags(p, I, absE, S_out, s, learned ? p.d_drop : nullptr);
         exclusive_scan_u64(p.d_flag, p.n, p.d_scan_tmp, &p.d_sc->packed_total, s);
         launch_compact(p, I, s);
-        mark(1);
+        mark(3);
         if (p.method == PH_METHOD_DIRECT) {
-            for (int k = 2; k <= 7; ++k) mark(k);
+            for (int k = 4; k <= 8; ++k) mark(k);
             run_direct(p, S_out, s);
-            mark(8);
+            mark(9);
         } else {
             build_tree(p, s);
-            mark(2);
-            if (p.selector == PH_SEL_LEARNED) selector_apply(p, I, absE, S_out, s);
-            mark(3);
-            build_lists(p, s);
             mark(4);
-            fmm_upward(p, s);
+            build_lists(p, s);
             mark(5);
-            fmm_downward(p, s);
+            fmm_upward(p, s);
             mark(6);
-            fmm_leaf(p, S_out, s);
+            fmm_downward(p, s);
             mark(7);
-            fmm_near(p, S_out, s);
+            fmm_leaf(p, S_out, s);
             mark(8);
+            fmm_near(p, S_out, s);
+            mark(9);
         }
         PH_HIP(hipGetLastError());
         if (timed) p.ring_used[slot] = true;
@@ -668,9 +696,10 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             }
             stats->n_boxes = p.method == PH_METHOD_FMM ? nb : 0;
             stats->levels = levels;
-            stats->n_src_dropped = p.selector == PH_SEL_LEARNED ? (int64_t)p.h_sc.n_src_base - p.h_sc.n_src : 0;
             stats->fell_back = p.h_sc.fallback;
-            stats->n_leaves = p.h_sc.n_srcleaf;
+            stats->n_src_dropped =
+                (learned && !p.h_sc.fallback) ? (int64_t)p.h_sc.n_src_base - p.h_sc.n_src : 0;
+            stats->n_leaves = learned ? p.h_sc.n_srcleaf : 0;
             for (int k = 0; k < 12; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
             for (int k = 0; k + 1 < Plan::kMarks; ++k) {
                 float ms = 0;
@@ -777,6 +806,26 @@ ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, 
             *n_out = 1;
             if (dst && cap_bytes >= 4) std::memcpy(dst, &p.h_sc.scale_exp, 4);
             break;
+        case 8:
+        case 9: {
+            // selector rows: the plan leaves flagged by the last selector pass, in box order
+            std::vector<uint32_t> flag(p.n_pleaf);
+            std::vector<float> feat((size_t)p.n_pleaf * 8);
+            PH_HIP(hipMemcpy(flag.data(), p.d_leafflag, (size_t)p.n_pleaf * 4, hipMemcpyDeviceToHost));
+            PH_HIP(hipMemcpy(feat.data(), p.d_feat, feat.size() * 4, hipMemcpyDeviceToHost));
+            std::vector<float> rf;
+            std::vector<int32_t> rb;
+            for (int32_t i = 0; i < p.n_pleaf; ++i) {
+                if (!flag[i]) continue;
+                rb.push_back(p.h_pleaf[i]);
+                rf.insert(rf.end(), feat.begin() + (size_t)i * 8, feat.begin() + (size_t)i * 8 + 8);
+            }
+            *n_out = (int64_t)rb.size();  // rows
+            const size_t total = what == 8 ? rf.size() * 4 : rb.size() * 4;
+            size_t bytes = std::min<size_t>(total, cap_bytes > 0 ? (size_t)cap_bytes : 0);
+            if (bytes && dst) std::memcpy(dst, what == 8 ? (const void *)rf.data() : (const void *)rb.data(), bytes);
+            break;
+        }
         default: throw Error{PH_EINVAL, "unknown debug array"};
         }
         return PH_OK;
@@ -790,7 +839,7 @@ ph_status ph_mlp_forward(const float *params, const float *X, int64_t m, float *
     g_last_error.clear();
     if (!params || !X || !logits || m < 0) return fail(Error{PH_EINVAL, "bad mlp_forward arguments"});
     try {
-        launch_mlp_forward(params, X, m, logits, bf16, reinterpret_cast<hipStream_t>(stream));
+        launch_mlp_forward(params, X, m, nullptr, logits, bf16, reinterpret_cast<hipStream_t>(stream));
         PH_HIP(hipGetLastError());
         return PH_OK;
     } catch (const Error &e) {

@@ -54,11 +54,11 @@ struct CallScalars {
     int32_t n_u, n_w, n_x;              // list lengths
     int32_t n_src_dropped;              // learned selector
     int32_t min_leafsrc_level;          // lowest level holding a leaf with sources
-    int32_t emax_pos_rev;               // n - (sorted position of the largest |E|)
     int32_t fallback;                   // learned selector fell back to the threshold rule
-    int32_t n_srcleaf;                  // source leaves (rows of the selector features)
-    int32_t n_src_base;                 // sources before the learned decisions
+    int32_t n_srcleaf;                  // selector rows: plan leaves holding candidate sources
+    int32_t n_src_base;                 // candidate sources of the learned decisions (kept + dropped)
     uint64_t packed_total;              // selected (sources | targets << 32)
+    uint64_t emax_key;                  // |E| bits << 32 | ~caller index of the largest |E|
     uint64_t lvl_pack[kMaxDepth + 2];   // packed per-level totals (boxes | source boxes << 32)
     // algorithmic work of the call (integer counters, order independent)
     unsigned long long work[12];        // p2p pairs, l2p evals, m2p evals, p2m evals,
@@ -151,8 +151,18 @@ struct Plan {
     std::vector<float> sel_weights;
     float sel_threshold = 0.f;
     double fallback_rel = 1e-4;     // threshold rule of the learned selector's fallback
-    uint8_t *d_drop = nullptr;      // per sorted point: source removed by the learned selector
-    uint32_t *d_leafflag = nullptr; // scan scratch over boxes (source leaves)
+    uint8_t *d_drop = nullptr;      // per sorted point of a candidate leaf: 1 if the leaf was dropped
+    uint32_t *d_leafflag = nullptr; // per plan leaf: 1 if it holds a candidate source
+    int32_t n_pleaf = 0;            // leaves of the plan's tree over all points
+    int32_t *d_pleaf = nullptr;     // their box ids in box order
+    std::vector<int32_t> h_pleaf;   // host copy
+    int32_t *d_pleaf_of_box = nullptr; // per box: its plan-leaf index, -1 for split boxes
+    uint32_t *d_leafscan = nullptr; // per plan leaf: candidate flag, scanned by the row compaction
+    double *d_lstat = nullptr;      // per plan leaf: max I, sum |E|, sum |E|^2, max |E|
+    float *d_box_emax = nullptr;    // per box (plan leaves only): max |E|
+    int32_t *d_cand_list = nullptr; // plan-leaf indices of the candidate leaves (any order)
+    int32_t *d_row_box = nullptr;   // compacted rows (training entry points): plan-leaf box ids
+    float *d_row_feat = nullptr;    // and their features
 
     // plan-time device arrays
     uint64_t *d_key = nullptr;      // sorted Morton keys (n)
@@ -182,14 +192,13 @@ struct Plan {
     Lists lists;
     void *d_phi = nullptr;          // box_cap x n_lam upward densities
     void *d_u = nullptr;            // box_cap x n_lam downward check potentials
-    int32_t *d_srcbox_mark = nullptr; // learned selector: per-box drop mark
-    float *d_feat = nullptr;        // learned selector features (box_cap x 8)
-    int32_t *d_feat_box = nullptr;  // box of each feature row
-    float *d_logit = nullptr;       // per-feature-row logits
+    float *d_feat = nullptr;        // learned selector features per plan leaf (n_pleaf x 8)
+    int32_t *d_feat_cnt = nullptr;  // candidate sources per plan leaf
+    float *d_logit = nullptr;       // logits per plan leaf
     float *d_sel_params = nullptr;  // device copy of the selector weights
     // per-phase timing: a ring of event sets, one set per recorded call
     static constexpr int kRing = 32;
-    static constexpr int kMarks = 9;          // boundaries of the 8 phases
+    static constexpr int kMarks = 10;         // boundaries of the 9 phases
     hipEvent_t ring[kRing][kMarks] = {};
     bool ring_used[kRing] = {};
     int ring_pos = 0;
@@ -243,6 +252,8 @@ void launch_gather_sorted(const double *xyz, const double *w, const int32_t *per
 void launch_reset_scalars(CallScalars *sc, hipStream_t s);
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
                        CallScalars *sc, void *tmp /* >= 16 KiB */, hipStream_t s);
+void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
+                             hipStream_t s);  // partials: up to 1024 blocks
 void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s,
                          const uint8_t *drop = nullptr);
 void launch_compact(const Plan &p, const void *I, hipStream_t s);
@@ -263,10 +274,11 @@ void fmm_near(Plan &p, void *S_out, hipStream_t s);  // near field (P2P) and the
 void run_direct(Plan &p, void *S_out, hipStream_t s);
 
 // learned selector (k_mlp.hip)
-void selector_features(Plan &p, const void *I, const float *E, hipStream_t s);  // rows -> d_feat
-void selector_apply(Plan &p, const void *I, const float *E, void *S_out, hipStream_t s);
-void launch_mlp_forward(const float *params, const float *X, int64_t m, float *logits, int bf16,
-                        hipStream_t s);
+void selector_reduce(Plan &p, const void *I, const float *E, hipStream_t s);    // maxima + per-leaf statistics
+void selector_features(Plan &p, const void *I, const float *E, hipStream_t s);  // rows, features (compacted)
+void selector_decide(Plan &p, const void *I, const float *E, hipStream_t s);    // features, network -> d_drop
+void launch_mlp_forward(const float *params, const float *X, int64_t m, const int32_t *m_dev, float *logits,
+                        int bf16, hipStream_t s);
 void launch_mlp_backward(const float *params, const float *X, const float *y, float pos_weight,
                          int64_t m, float *grad, float *loss, hipStream_t s);
 void launch_adam(float *params, float *m1, float *m2, const float *grad, int64_t nparam, float lr,

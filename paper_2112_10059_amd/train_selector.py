@@ -7,18 +7,20 @@ a network instead of a fixed relative threshold on I).
 Recipe:
   * fields: the seeded streamer generator (head + channel on the uniform grid); seeds
     [0, n_train) train, [n_train, n_train + n_cal) calibrate the decision threshold;
-  * rows: the source leaves of an evaluation with the candidate threshold base_src_rel;
-    features from ph_selector_features;
-  * contribution of leaf b: c_b = ||S_b|| / ||S|| over every active target (ph_selector_contrib
-    over all targets, ||S|| from the same evaluation).  Every S_b is non-negative, so dropping a
-    set D of leaves changes S by at most sum_{b in D} c_b in relative L2 (triangle inequality);
-  * labels: drop the longest run of smallest c_b whose sum stays within label_budget (1 = keep);
+  * rows: the plan leaves holding candidate sources (I >= base_src_rel I_max), with their
+    features (ph_selector_features);
+  * per row b its field S_b at every active target (ph_selector_fields, in chunks of targets)
+    and the Gram matrix G[b, b'] = <S_b, S_b'>; S = sum_b S_b is the candidates' field.  All
+    S_b are non-negative, and dropping a set D of rows changes S by exactly
+    sqrt(sum_{b, b' in D} G[b, b']) in L2;
+  * labels: rows in increasing order of ||S_b|| are dropped while that change stays within
+    label_budget ||S|| (1 = keep);
   * network 8 -> 64 -> 64 -> 1 (exact-erf GELU), BCE with logits, positive weight
     n_drop / n_keep, Adam; features standardised on the training rows and the standardisation
     folded into the first layer, so inference takes raw features;
-  * decision threshold: the largest logit threshold at which the bound sum_{dropped} c_b stays
-    within gate_budget on every calibration field, taken with the BF16 forward pass that the
-    evaluation path runs.
+  * decision threshold: the largest logit threshold at which the change of S caused by the
+    dropped rows stays within gate_budget ||S|| on every calibration field, with the BF16
+    logits that the evaluation path computes.
 
 Output: a text file (header lines with the metadata, then the 4801 parameters in the C ABI's
 layout, one per line) read by ``load_selector``.
@@ -43,13 +45,23 @@ NPARAM = B.MLP_NPARAM
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_c2.txt")
 
 
-def keep_labels(c: np.ndarray, budget: float) -> np.ndarray:
-    """1 = keep.  The smallest contributions are dropped while their running sum is <= budget."""
-    c = np.asarray(c, dtype=np.float64)
-    order = np.argsort(c, kind="stable")
-    run = np.cumsum(c[order])
-    n_drop = int(np.searchsorted(run, budget, side="right"))
-    lab = np.ones(c.size, dtype=np.float32)
+def keep_labels(G: np.ndarray, s_norm: float, budget: float) -> np.ndarray:
+    """1 = keep.  Rows in increasing order of sqrt(G[b, b]) are dropped while the norm of the
+    dropped rows' summed field stays <= budget * s_norm (G: Gram matrix of the row fields)."""
+    G = np.asarray(G, dtype=np.float64)
+    d = np.diag(G)
+    order = np.argsort(np.sqrt(np.maximum(d, 0.0)), kind="stable")
+    acc = np.zeros(G.shape[0])  # sum over the dropped rows of G[:, b]
+    e2 = 0.0
+    n_drop = 0
+    for b in order:
+        e2n = e2 + d[b] + 2.0 * acc[b]
+        if np.sqrt(e2n) > budget * s_norm:
+            break
+        e2 = e2n
+        acc += G[:, b]
+        n_drop += 1
+    lab = np.ones(G.shape[0], dtype=np.float32)
     lab[order[:n_drop]] = 0.0
     return lab
 
@@ -75,16 +87,21 @@ def fold_standardisation(p: np.ndarray, mu: np.ndarray, sd: np.ndarray) -> np.nd
 
 
 def calibrate_threshold(fields, gate_budget: float) -> float:
-    """Largest t such that, on every field, sum of c over rows with logit < t is <= gate_budget."""
+    """Largest t such that on every field (z, G, s_norm) the rows with logit < t change S by
+    at most gate_budget * s_norm (exact, from the Gram matrix)."""
     best = math.inf
-    for z, c in fields:
+    for z, G, s_norm in fields:
         order = np.argsort(z, kind="stable")
-        run = np.cumsum(c[order])
-        over = np.flatnonzero(run > gate_budget)
-        if over.size == 0:
-            continue
-        # rows strictly below z[order[k]] are dropped, k the first row that breaks the budget
-        best = min(best, float(z[order[over[0]]]))
+        acc = np.zeros(G.shape[0])
+        e2 = 0.0
+        for b in order:
+            e2n = e2 + G[b, b] + 2.0 * acc[b]
+            if np.sqrt(e2n) > gate_budget * s_norm:
+                # rows strictly below z[b] are dropped: they are the prefix before b
+                best = min(best, float(z[b]))
+                break
+            e2 = e2n
+            acc += G[:, b]
     return best
 
 
@@ -106,17 +123,19 @@ def load_selector(path: str | None = None):
     return w, meta
 
 
-def _field_rows(plan, wl, label_budget, torch):
-    I = torch.tensor(wl.I.astype(np.float32), device="cuda")
-    E = torch.tensor(wl.E.astype(np.float32), device="cuda")
-    S = plan.evaluate(I, E)
+def field_rows(plan, I, E, targets, torch, chunk: int = 65536):
+    """Features (rows x 8), Gram matrix of the row fields over the targets, and ||S||."""
     F = B.selector_features(plan, I, E)
-    # the evaluation's own target set, in caller order
-    targets = np.sort(plan.debug_fetch("perm")[plan.debug_fetch("tgt")]).astype(np.int32)
-    tdev = torch.tensor(targets, device="cuda")
-    c = B.selector_contrib(plan, tdev, F.shape[0]).double().cpu().numpy()
-    c = c / float(torch.linalg.vector_norm(S[tdev.long()].double()))
-    return F.cpu().numpy(), c, keep_labels(c, label_budget)
+    m = F.shape[0]
+    G = torch.zeros((m, m), dtype=torch.float64, device="cuda")
+    s2 = 0.0
+    buf = torch.empty((max(m, 1), chunk), dtype=torch.float32, device="cuda")
+    for t0 in range(0, targets.numel(), chunk):
+        tc = targets[t0:t0 + chunk]
+        Fc = B.selector_fields(plan, I, tc, m, ld=chunk, out=buf).double()
+        G += Fc @ Fc.T
+        s2 += float((Fc.sum(dim=0) ** 2).sum())
+    return F.cpu().numpy(), G.cpu().numpy(), math.sqrt(s2)
 
 
 def main(argv=None):
@@ -145,18 +164,25 @@ def main(argv=None):
     thr = dict(wl0.thresholds)
     thr["src_rel"] = a.base_src_rel
     plan = B.Plan(wl0.xyz, wl0.gas, thr, h=wl0.h, w=wl0.w, cube_lo=(lo, lo, lo), cube_size=hi - lo)
-    rows = []
+    rows, grams = [], []
     for s in range(a.n_train + a.n_cal):
         wl = wl0 if s == 0 else gen.config2(seed=s, n_axis=a.n_axis)
-        F, c, y = _field_rows(plan, wl, a.label_budget, torch)
-        rows.append((F, c, y))
+        I = torch.tensor(wl.I.astype(np.float32), device="cuda")
+        E = torch.tensor(wl.E.astype(np.float32), device="cuda")
+        plan.evaluate(I, E)
+        # the call's own target set, in caller order
+        targets = np.sort(plan.debug_fetch("perm")[plan.debug_fetch("tgt")]).astype(np.int32)
+        F, G, s_norm = field_rows(plan, I, E, torch.tensor(targets, device="cuda"), torch)
+        y = keep_labels(G, s_norm, a.label_budget)
+        rows.append((F, y))
+        if s >= a.n_train:
+            grams.append((G, s_norm))
         if s % 20 == 0 or s + 1 == a.n_train + a.n_cal:
-            print(f"field {s}: {F.shape[0]} leaves, keep {int(y.sum())}, sum c {c.sum():.3f} "
-                  f"({time.time() - t0:.0f} s)", flush=True)
+            print(f"field {s}: {F.shape[0]} rows, keep {int(y.sum())} ({time.time() - t0:.0f} s)", flush=True)
     plan.close()
 
     Xtr = np.concatenate([r[0] for r in rows[:a.n_train]]).astype(np.float64)
-    ytr = np.concatenate([r[2] for r in rows[:a.n_train]]).astype(np.float32)
+    ytr = np.concatenate([r[1] for r in rows[:a.n_train]]).astype(np.float32)
     mu = Xtr.mean(axis=0)
     sd = np.maximum(Xtr.std(axis=0), 1e-3)
     n_keep = float(ytr.sum())
@@ -190,24 +216,27 @@ def main(argv=None):
     pf = fold_standardisation(p.cpu().numpy(), mu, sd)
     wdev = torch.tensor(pf, device="cuda")
     cal, agree = [], []
-    for F, c, y in rows[a.n_train:]:
+    for (F, y), (G, s_norm) in zip(rows[a.n_train:], grams):
         z = B.mlp_forward(wdev, torch.tensor(F, device="cuda"), bf16=True).cpu().numpy().astype(np.float64)
-        cal.append((z, c))
+        cal.append((z, G, s_norm))
+        agree.append(y)
     tau = calibrate_threshold(cal, a.gate_budget)
     if not math.isfinite(tau):
         tau = 1e30
-    for (z, c), (_, _, y) in zip(cal, rows[a.n_train:]):
-        agree.append(float(np.mean((z >= tau) == (y > 0.5))))
-    kept = [float(np.mean(z >= tau)) for z, _ in cal]
-    bound = [float(c[z < tau].sum()) for z, c in cal]
+    kept, change, agreement = [], [], []
+    for (z, G, s_norm), y in zip(cal, agree):
+        d = z < tau
+        kept.append(float(np.mean(~d)))
+        change.append(float(np.sqrt(G[np.ix_(d, d)].sum()) / s_norm))
+        agreement.append(float(np.mean((~d) == (y > 0.5))))
     meta = dict(threshold=tau, base_src_rel=a.base_src_rel, label_budget=a.label_budget,
                 gate_budget=a.gate_budget, n_train=a.n_train, n_cal=a.n_cal, n_axis=a.n_axis,
                 epochs=a.epochs, batch=a.batch, lr=a.lr, seed=a.seed, pos_weight=pos_weight,
                 feature_mean=mu.tolist(), feature_std=sd.tolist(),
-                cal_kept_leaf_fraction=float(np.mean(kept)), cal_bound_max=float(max(bound)),
-                cal_label_agreement=float(np.mean(agree)))
-    print("calibration:", json.dumps({k: meta[k] for k in ("threshold", "cal_kept_leaf_fraction",
-                                                             "cal_bound_max", "cal_label_agreement")}),
+                cal_kept_row_fraction=float(np.mean(kept)), cal_change_max=float(max(change)),
+                cal_label_agreement=float(np.mean(agreement)))
+    print("calibration:", json.dumps({k: meta[k] for k in ("threshold", "cal_kept_row_fraction",
+                                                             "cal_change_max", "cal_label_agreement")}),
           flush=True)
     with open(a.out, "w") as f:
         f.write("# learned leaf selector: 8 -> 64 -> 64 -> 1 GELU network, parameters in the C ABI layout\n")

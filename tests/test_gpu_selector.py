@@ -8,7 +8,7 @@ import pytest
 import gen
 from oracle import mlp as omlp
 from oracle import photoionization, rel_l2
-from tests.helpers import MORTON_BITS, plan_kwargs
+from tests.helpers import MORTON_BITS, plan_kwargs, reference_tree
 
 pytestmark = pytest.mark.gpu
 
@@ -78,38 +78,53 @@ def _ranges(keys, level, anchors):
     return np.searchsorted(pre, p, side="left"), np.searchsorted(pre, p, side="right")
 
 
+def _plan_rows(plan, I32, src_rel, leaf_cap):
+    """Selector rows from NumPy: leaves of the full tree over all points (box ids in the plan's
+    box order) holding a point with I >= src_rel max I, and each leaf's sorted range."""
+    keys = plan.debug_fetch("keys")
+    perm = plan.debug_fetch("perm")
+    full = reference_tree(keys, keys, leaf_cap, 16)
+    Is = I32[perm].astype(np.float64)
+    thr = src_rel * float(I32.max())
+    ids, rng = [], []
+    for b, row in enumerate(full):
+        if row[8] != 1:
+            continue
+        st, n = int(row[4]), int(row[5])
+        if n and (src_rel <= 0 or np.any(Is[st:st + n] >= thr)):
+            ids.append(b)
+            rng.append((st, st + n))
+    return full, np.array(ids, dtype=np.int32), rng
+
+
 def test_selector_features_match_numpy(gpu_lib):
-    import torch
     wl = gen.config2(seed=1010, n_axis=48)
-    thr = dict(src_rel=1e-7, e_abs=3e6)
+    src_rel = 1e-7
+    thr = dict(src_rel=src_rel, e_abs=3e6)
     _say("selector features c2_48")
     plan = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
     I32, E32 = wl.I.astype(np.float32), wl.E.astype(np.float32)
     tI, tE = _t(I32), _t(E32)
-    plan.evaluate(tI, tE)
     F = gpu_lib.selector_features(plan, tI, tE).cpu().numpy().astype(np.float64)
-    keys = plan.debug_fetch("keys")
-    perm = plan.debug_fetch("perm")
-    src = plan.debug_fetch("src")
-    boxes = plan.debug_fetch("boxes")
-    leaves = boxes[(boxes[:, 9] & 1 == 1) & (boxes[:, 5] > 0)]
-    assert F.shape == (leaves.shape[0], 8)
+    full, ids, rng = _plan_rows(plan, I32, src_rel, 32)
+    assert np.array_equal(plan.debug_fetch("feature_boxes"), ids)
+    assert F.shape == (ids.size, 8)
+    keys, perm = plan.debug_fetch("keys"), plan.debug_fetch("perm")
     Imax, Emax = float(I32.max()), float(E32.max())
     w_ref = wl.h ** 3
     lo, hi = wl.domain
     cube = hi - lo
     Es = E32[perm].astype(np.float64)
-    kE = int(np.argmax(Es))
-    xE = wl.xyz[perm[kE]]
+    Is = I32[perm].astype(np.float64)
+    xE = wl.xyz[int(np.argmax(E32))]  # first in caller order among ties
     ref = np.zeros_like(F)
-    for r, row in enumerate(leaves):
-        lev, ax, ay, az, sf, sn = (int(v) for v in row[:6])
-        idx = perm[src[sf:sf + sn]]
-        Iv = I32[idx].astype(np.float64)
+    for r, (b, (st, en)) in enumerate(zip(ids, rng)):
+        lev, ax, ay, az = (int(v) for v in full[b, :4])
+        Iv = Is[st:en]
+        Iv = Iv[Iv >= src_rel * Imax]
         side = cube / 2 ** lev
         ctr = lo + (np.array([ax, ay, az]) + 0.5) * side
-        st, en = _ranges(keys, lev, [[ax, ay, az]])
-        e = Es[st[0]:en[0]] / Emax
+        e = Es[st:en] / Emax
         nb = [[ax + dx, ay + dy, az + dz] for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
               if 0 <= ax + dx < 2 ** lev and 0 <= ay + dy < 2 ** lev and 0 <= az + dz < 2 ** lev]
         cs, ce = _ranges(keys, lev, nb)
@@ -118,6 +133,36 @@ def test_selector_features_match_numpy(gpu_lib):
                   math.log2(side / w_ref ** (1 / 3)), math.log10(1 + np.linalg.norm(ctr - xE) / side),
                   e.max(), e.mean(), e.std(), emx_nb]
     assert np.allclose(F, ref, rtol=2e-5, atol=2e-5)
+    plan.close()
+
+
+def test_selector_fields_match_oracle(gpu_lib):
+    """Each row's field at sampled targets equals the FP64 direct sum over that row's candidates."""
+    import torch
+    wl = gen.config2(seed=1014, n_axis=32)
+    src_rel = 1e-3
+    _say("selector fields c2_32")
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, dict(src_rel=src_rel, e_abs=3e6), leaf_capacity=32, **plan_kwargs(wl))
+    I32, E32 = wl.I.astype(np.float32), wl.E.astype(np.float32)
+    tI = _t(I32)
+    F = gpu_lib.selector_features(plan, tI, _t(E32))
+    rng_ = np.random.default_rng(5)
+    tg = np.sort(rng_.choice(wl.n, size=3000, replace=False)).astype(np.int32)
+    # a ragged tail: 3000 targets are one block of 2048 plus a partial one
+    fields = gpu_lib.selector_fields(plan, tI, torch.tensor(tg, device="cuda"), F.shape[0]).cpu().numpy()
+    _, ids, rng = _plan_rows(plan, I32, src_rel, 32)
+    perm = plan.debug_fetch("perm")
+    Is = I32[perm].astype(np.float64)
+    for r in range(0, ids.size, max(1, ids.size // 10)):
+        st, en = rng[r]
+        k = np.arange(st, en)
+        k = k[Is[k] >= src_rel * float(I32.max())]
+        sm = np.zeros(wl.n, dtype=bool)
+        sm[perm[k]] = True
+        res = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, smask=sm, targets=tg)
+        assert np.allclose(fields[r], res.S_t, rtol=2e-5, atol=1e-6 * np.abs(res.S_t).max())
+    with pytest.raises(gpu_lib.PhError):
+        gpu_lib.selector_fields(plan, tI, torch.tensor(tg, device="cuda"), F.shape[0] + 1)
     plan.close()
 
 
@@ -178,27 +223,65 @@ def test_learned_nonfinite_logits_fall_back_to_threshold(gpu_lib):
     p1.close()
 
 
-def test_selector_contrib_matches_oracle(gpu_lib):
-    """Per-leaf field norms at sampled targets equal the FP64 direct sum restricted to the leaf."""
-    wl = gen.config2(seed=1014, n_axis=32)
-    thr = dict(src_rel=1e-3, e_abs=3e6)
-    _say("selector contributions")
-    plan = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
+def test_learned_decisions_select_exactly_the_kept_rows(gpu_lib):
+    """A network with real decisions: the selected sources are exactly the candidates of the rows
+    whose BF16 logit (same kernel, same features) clears the threshold, and S matches the oracle
+    on that source set."""
+    wl = gen.config2(seed=1015, n_axis=40)
+    src_rel = 1e-7
+    thr = dict(src_rel=src_rel, e_abs=3e6)
+    _say("learned decisions c2_40")
     I32, E32 = wl.I.astype(np.float32), wl.E.astype(np.float32)
     tI, tE = _t(I32), _t(E32)
-    plan.evaluate(tI, tE)
-    F = gpu_lib.selector_features(plan, tI, tE)
-    rng = np.random.default_rng(5)
-    tg = np.sort(rng.choice(wl.n, size=300, replace=False)).astype(np.int32)
-    import torch
-    c = gpu_lib.selector_contrib(plan, torch.tensor(tg, device="cuda"), F.shape[0]).cpu().numpy()
-    perm, src, boxes = plan.debug_fetch("perm"), plan.debug_fetch("src"), plan.debug_fetch("boxes")
-    leaves = boxes[(boxes[:, 9] & 1 == 1) & (boxes[:, 5] > 0)]
-    for r in range(0, leaves.shape[0], max(1, leaves.shape[0] // 12)):
-        sf, sn = int(leaves[r, 4]), int(leaves[r, 5])
-        sm = np.zeros(wl.n, dtype=bool)
-        sm[perm[src[sf:sf + sn]]] = True
-        res = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, smask=sm, targets=tg)
-        ref = np.linalg.norm(res.S_t)
-        assert c[r] == pytest.approx(ref, rel=2e-4)
+    w = omlp.init_params(11).astype(np.float32)
+    probe = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, **plan_kwargs(wl))
+    z0 = gpu_lib.mlp_forward(_t(w), gpu_lib.selector_features(probe, tI, tE), bf16=True).cpu().numpy()
+    probe.close()
+    tau = float(np.median(z0))
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, selector="learned", selector_weights=w,
+                        selector_logit_threshold=tau, **plan_kwargs(wl))
+    S, st = plan.evaluate(tI, tE, stats=True)
+    feats = plan.debug_fetch("features").reshape(-1, 8)
+    z = gpu_lib.mlp_forward(_t(w), _t(feats), bf16=True).cpu().numpy()
+    assert np.array_equal(z, z0)
+    keep = z >= tau
+    assert 0 < keep.sum() < keep.size
+    _, ids, rng = _plan_rows(plan, I32, src_rel, 32)
+    assert np.array_equal(plan.debug_fetch("feature_boxes"), ids)
+    perm = plan.debug_fetch("perm")
+    Is = I32[perm].astype(np.float64)
+    kept = np.concatenate([np.arange(*rng[r]) for r in np.flatnonzero(keep)])
+    kept = np.sort(kept[Is[kept] >= src_rel * float(I32.max())])
+    assert np.array_equal(plan.debug_fetch("src"), kept.astype(np.int32))
+    assert st["n_leaves"] == ids.size and st["fell_back"] == 0
+    cand = int(np.sum([np.sum(Is[a:b] >= src_rel * float(I32.max())) for a, b in rng]))
+    assert st["n_src_dropped"] == cand - kept.size
+    sm = np.zeros(wl.n, dtype=bool)
+    sm[perm[kept]] = True
+    r = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, smask=sm,
+                        E=E32.astype(np.float64), e_abs=3e6)
+    assert rel_l2(S.double().cpu().numpy(), r.full(wl.n)) <= 1e-3
+    plan.close()
+
+
+@pytest.mark.parametrize("seed", [200, 217, 249])
+def test_trained_selector_on_held_out_fields(gpu_lib, seed):
+    """The committed selector on fields it was neither trained nor calibrated on: the method error
+    against the FP64 direct sum over all sources stays within 1e-3 on sampled targets (head ball
+    plus a uniform sample), it drops sources, and it does not fall back."""
+    from paper_2112_10059_amd.train_selector import load_selector
+    w, meta = load_selector()
+    wl = gen.config2(seed=seed, n_axis=128)
+    _say(f"trained selector, held-out field seed {seed}")
+    I32, E32 = wl.I.astype(np.float32), wl.E.astype(np.float32)
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, dict(src_rel=meta["base_src_rel"], e_abs=3e6), selector="learned",
+                        selector_weights=w, selector_logit_threshold=meta["threshold"],
+                        selector_fallback_rel=1e-4, **plan_kwargs(wl))
+    S, st = plan.evaluate(_t(I32), _t(E32), stats=True)
+    assert st["fell_back"] == 0 and st["n_src_dropped"] > 0
+    tg = gen.sample_targets(np.arange(wl.n), wl.xyz, wl.head, k=400, seed=seed, head_cap=400)
+    ref = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, targets=tg)
+    err = rel_l2(S.double().cpu().numpy()[tg], ref.S_t)
+    _say(f"  kept {st['n_src']} of {st['n_src'] + st['n_src_dropped']} candidates, method rel-L2 {err:.3e}")
+    assert err <= 1e-3
     plan.close()

@@ -7,17 +7,22 @@ from oracle import mlp as omlp
 from paper_2112_10059_amd import train_selector as ts
 
 
-def test_keep_labels_match_oracle_budget_rule():
+def _fields(rng, m, nt=60):
+    return rng.lognormal(-6, 2, size=(m, 1)) * rng.uniform(0, 1, size=(m, nt)) ** 3
+
+
+def test_keep_labels_match_oracle_gram_rule():
     rng = np.random.default_rng(0)
-    for trial in range(50):
-        c = rng.lognormal(-8, 3, size=rng.integers(1, 400))
+    for trial in range(40):
+        F = _fields(rng, int(rng.integers(1, 60)))
         if trial % 5 == 0:
-            c[: c.size // 3] = c[0]  # ties
-        budget = float(rng.choice([0.0, 1e-4, 5e-4, 1e-2, 10.0]))
-        ours = ts.keep_labels(c, budget)
-        ref = omlp.budgeted_keep_labels(c, budget)
+            F[: F.shape[0] // 3] = F[0]  # equal norms
+        G = F @ F.T
+        s_norm = float(np.linalg.norm(F.sum(axis=0)))
+        budget = float(rng.choice([0.0, 1e-3, 1e-2, 1e-1, 10.0]))
+        ours = ts.keep_labels(G, s_norm, budget)
+        ref = omlp.budgeted_keep_labels_gram(G, s_norm, budget)
         assert np.array_equal(ours, ref.astype(np.float32))
-        assert c[ours == 0].sum() <= budget
 
 
 def test_fold_standardisation_matches_oracle_forward():
@@ -33,16 +38,23 @@ def test_fold_standardisation_matches_oracle_forward():
 
 def test_calibrated_threshold_keeps_every_field_within_budget():
     rng = np.random.default_rng(2)
-    fields = [(rng.normal(size=300), rng.lognormal(-9, 2, size=300)) for _ in range(20)]
-    budget = 3e-3
+    fields, raw = [], []
+    for _ in range(12):
+        F = _fields(rng, 80)
+        z = rng.normal(size=80)
+        fields.append((z, F @ F.T, float(np.linalg.norm(F.sum(axis=0)))))
+        raw.append((z, F))
+    budget = 2e-2
     t = ts.calibrate_threshold(fields, budget)
     assert math.isfinite(t)
-    assert all(c[z < t].sum() <= budget for z, c in fields)
-    # the next larger logit would break the budget on at least one field
-    above = min(z[z > t].min() for z, _ in fields if np.any(z > t))
-    assert any(c[z < above + 1e-12].sum() > budget for z, c in fields)
-    # nothing to drop within the budget -> threshold at -inf side never binds
-    assert ts.calibrate_threshold([(np.zeros(3), np.ones(3))], 1e-3) == 0.0
+    change = lambda z, F, t: np.linalg.norm(F[z < t].sum(axis=0)) / np.linalg.norm(F.sum(axis=0))
+    assert all(change(z, F, t) <= budget * (1 + 1e-12) for z, F in raw)
+    # the next larger logit breaks the budget on at least one field
+    above = min(z[z > t].min() for z, _ in raw if np.any(z > t))
+    assert any(change(z, F, above + 1e-12) > budget for z, F in raw)
+    # a field that never breaks the budget does not bind
+    F = _fields(rng, 5)
+    assert ts.calibrate_threshold([(np.zeros(5), F @ F.T, 1e30)], 1e-3) == math.inf
 
 
 def test_weights_file_round_trip(tmp_path):
