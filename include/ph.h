@@ -105,10 +105,12 @@ typedef struct {
     ph_precision precision;
     ph_selector selector;
     ph_method method;
-    int order_q;            /* lattice points per box edge (2..8); 0 => 6 for FP64, 4 otherwise */
+    int order_q;            /* lattice points per box edge (2..8); 0 => FP64: 6 on uniform grids,
+                               7 on point clouds; other precisions: 4                      */
     int leaf_capacity;      /* split a box while max(#sources, #targets) > this; 0 => 64         */
     int max_depth;          /* 0 => depth of the tree over all points (bounded by 16)           */
-    double pinv_rel_cutoff; /* singular values below cutoff * sigma_max are dropped; 0 => default */
+    double pinv_rel_cutoff; /* singular values below cutoff * sigma_max are dropped; 0 => 1e-15 for
+                               FP64, 1e-7 for FP32 on uniform grids, 1e-4 for FP32 on clouds */
     const float *selector_weights; /* host, PH_MLP_NPARAM floats (learned selector) or NULL     */
     float selector_logit_threshold;/* keep a source leaf iff its logit >= threshold           */
     double selector_fallback_rel;  /* source rule I >= rel * max I used when the learned

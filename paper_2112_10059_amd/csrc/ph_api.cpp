@@ -398,6 +398,14 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     }
     // on a grid the closest distinct pair is h apart: the guarded form is needed only if (b - a) h < 1/4
     p.near_guard = !(p.grid_mode && (p.gas.b - p.gas.a) * p.h >= 0.25);
+    // default order from measured error: the FP64 form reaches 1e-7 at q = 6 on uniform grids
+    // but needs q = 7 on clustered point clouds (1.0e-6 at q = 6, 2.6e-7 at q = 7)
+    if (!opt->order_q && p.precision == PH_FP64 && !p.grid_mode) p.q = 7;
+    // FP32 forms: the pseudo-inverses are regularised so that FP32 rounding is not amplified by
+    // their conditioning; on clustered clouds (boxes over many absorption lengths, and at low
+    // pressure few) 1e-4 sigma_max keeps the error near 1e-4 at 40 and 760 Torr, where 1e-7
+    // reaches 1.5e-3 at 40 Torr; uniform grids at 760 Torr are best at 1e-7 (5e-5)
+    if (opt->pinv_rel_cutoff <= 0 && p.precision != PH_FP64 && !p.grid_mode) p.pinv_cut = 1e-4;
     // tree bound from the tree over all points
     std::vector<uint64_t> hkeys(n);
     PH_HIP(hipMemcpy(hkeys.data(), p.d_key, (size_t)n * 8, hipMemcpyDeviceToHost));
