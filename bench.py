@@ -50,8 +50,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n-axis", type=int, default=128)
-    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--workload", choices=("c2", "c5"), default="c2",
+                    help="c2: streamer head + channel, 1 cm cube (n-axis^3, default 128^3); "
+                         "c5: head ahead of a plasma-cloud shell, 2 cm cube (n-axis^3, default 256^3)")
+    ap.add_argument("--precision", choices=("fp32", "bf16split"), default="fp32")
+    ap.add_argument("--n-axis", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--order-q", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the oracle sample")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -92,7 +96,14 @@ def main():
     from paper_2112_10059_amd import binding
     from paper_2112_10059_amd.train_selector import load_selector
 
-    wl = gen.config2(seed=args.seed, n_axis=args.n_axis)
+    if args.workload == "c2":
+        args.n_axis = args.n_axis or 128
+        args.seed = args.seed or 1000
+        wl = gen.config2(seed=args.seed, n_axis=args.n_axis)
+    else:
+        args.n_axis = args.n_axis or 256
+        args.seed = args.seed or 3000
+        wl = gen.config5(seed=args.seed, n_axis=args.n_axis)
     I32 = wl.I.astype(np.float32)
     E32 = wl.E.astype(np.float32)
     dev = torch.device("cuda:0")
@@ -112,11 +123,11 @@ def main():
     sel_w, sel_meta = load_selector()
     thr_l = dict(wl.thresholds, src_rel=sel_meta["base_src_rel"])
     t = time.perf_counter()
-    plan = binding.Plan(wl.xyz, wl.gas, thr_l, precision="fp32", order_q=args.order_q, selector="learned",
+    plan = binding.Plan(wl.xyz, wl.gas, thr_l, precision=args.precision, order_q=args.order_q, selector="learned",
                         selector_weights=sel_w, selector_logit_threshold=sel_meta["threshold"],
                         selector_fallback_rel=1e-4, **common)
     plan_ms = (time.perf_counter() - t) * 1e3
-    log(f"plan fp32 learned: {plan_ms:.1f} ms")
+    log(f"plan {args.precision} learned: {plan_ms:.1f} ms")
     _, st = plan.evaluate(I, E, stats=True)
     log(f"stats: {st}")
     S, ms, phases = time_steps(plan, I, E, args.steps, args.warmup, torch)
@@ -129,7 +140,7 @@ def main():
     smask[perm[plan.debug_fetch("src")]] = True
 
     # ---------------- the paper's threshold rule (tau_s = 1e-4) on the same field, for comparison
-    plan_t = binding.Plan(wl.xyz, wl.gas, wl.thresholds, precision="fp32", order_q=args.order_q, **common)
+    plan_t = binding.Plan(wl.xyz, wl.gas, wl.thresholds, precision=args.precision, order_q=args.order_q, **common)
     _, st_t = plan_t.evaluate(I, E, stats=True)
     S_t, ms_t, phases_t = time_steps(plan_t, I, E, args.steps, args.warmup, torch)
     plan_t.close()
@@ -149,7 +160,8 @@ def main():
     t_or = time.perf_counter() - t
     err = rel_l2(S_host[sample], r.S_t)
     log(f"parity (sampled {sample.size} targets, learned source set): rel-L2 = {err:.3e}; oracle {t_or:.2f} s")
-    msample = gen.sample_targets(tgt_all, wl.xyz, wl.head, k=1000, seed=777, head_cap=1000)
+    mk = 1000 if args.workload == "c2" else 200  # all-source oracle cost: n points per target
+    msample = gen.sample_targets(tgt_all, wl.xyz, wl.head, k=mk, seed=777, head_cap=mk)
     r_all = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h, targets=msample)
     method_err = rel_l2(S_host[msample], r_all.S_t)
     method_err_t = rel_l2(St_host[msample], r_all.S_t)
@@ -206,11 +218,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "f32 (M2L: bf16 hi/lo split)",
         "data": "synthetic",
-        "config": {"workload": f"streamer head+channel on a {args.n_axis}^3 grid, 1 cm cube, 760 Torr, seed "
-                               f"{args.seed}; learned leaf selector over candidates I >= "
-                               f"{sel_meta['base_src_rel']:g} max I (fallback 1e-4), targets |E| >= 3e6 V/m",
+        "config": {"workload": (f"streamer head+channel on a {args.n_axis}^3 grid, 1 cm cube" if args.workload == "c2"
+                                else f"streamer head ahead of a plasma-cloud shell on a {args.n_axis}^3 grid, 2 cm cube")
+                               + f", 760 Torr, seed {args.seed}; learned leaf selector over candidates I >= "
+                               f"{sel_meta['base_src_rel']:g} max I (fallback 1e-4), targets |E| >= 3e6 V/m; "
+                               f"M2L in {args.precision}",
                    "n_points": wl.n, "n_src": st["n_src"], "n_src_dropped": st["n_src_dropped"],
                    "selector_rows": st["n_leaves"], "fell_back": st["fell_back"], "n_tgt": n_tgt,
                    "order_q": plan_q(args), "leaf_capacity": 64, "selector": "learned", "plan_ms": plan_ms},

@@ -12,6 +12,8 @@
 // computed as Y^T = Phi^T M_all^T so that each wave writes contiguous rows of Y.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "k_fmm_args.h"
 
 namespace ph {
@@ -111,6 +113,93 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op, in
                 for (int r = 0; r < 4; ++r) {
                     const int nl_ = wn * 32 + i * 16 + Mfma<T>::row(lane, r);
                     const int gn = n0 + nl_;
+                    if (gn >= ncols || gm >= M) continue;
+                    out[(size_t)gn * M + gm] = acc[i][j][r];
+                }
+            }
+    }
+}
+
+// M2L GEMM of the split-BF16 form (same tiling and output as tgemm_kernel in M2L mode):
+// every operand x is taken as hi + lo with hi = bf16(x), lo = bf16(x - hi) (the operator's
+// parts precomputed in FP64, the densities split while staged), and
+//   Y = Phi^T (Op_hi + Op_lo)^T ~ Phi_hi Op_hi + Phi_hi Op_lo + Phi_lo Op_hi
+// runs as three v_mfma_f32_16x16x16_bf16 per 16-deep k step with FP32 accumulation; the
+// dropped lo * lo term is below 2^-16 of the product.
+// Operand layout of v_mfma_f32_16x16x16_bf16: A lane l holds A[l%16][4 (l/16) + v],
+// B lane l holds B[4 (l/16) + v][l%16] (v = 0..3); D as for the FP32 form.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int kPadB = 4;  // LDS row padding (bfloat16 elements; rows stay 8-byte aligned)
+
+__device__ __forceinline__ uint16_t bf16_rne(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__restrict__ Oh,
+                                                              const uint16_t *__restrict__ Ol, int kp, int M,
+                                                              int nl, const float *__restrict__ vec,
+                                                              const int32_t *__restrict__ list,
+                                                              const int32_t *__restrict__ count, int32_t lvl_base,
+                                                              int32_t r0, int32_t ccap, float *__restrict__ out)
+{
+    __shared__ __align__(16) uint16_t Ah[kTile][kTK + kPadB], Al[kTile][kTK + kPadB];
+    __shared__ __align__(16) uint16_t Bh[kTile][kTK + kPadB], Bl[kTile][kTK + kPadB];
+    __shared__ int32_t boxes[kTile];
+    const int32_t ncols = min(ccap, *count - r0);
+    const int m0 = blockIdx.x * kTile;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wn = w >> 1, wm = w & 1;
+    for (int n0 = blockIdx.y * kTile; n0 < ncols; n0 += gridDim.y * kTile) {
+        __syncthreads();
+        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[lvl_base + r0 + n0 + t] : -1;
+        f32x4 acc[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < kp; k0 += kTK) {
+            __syncthreads();
+            for (int e = t; e < kTK * kTile; e += 256) {
+                const int n = e / kTK, k = e % kTK;
+                const int gk = k0 + k;
+                const int32_t bx = boxes[n];
+                const float v = (bx >= 0 && gk < nl) ? vec[(size_t)bx * nl + gk] : 0.0f;
+                const uint16_t h = bf16_rne(v);
+                Ah[n][k] = h;
+                Al[n][k] = bf16_rne(v - __uint_as_float((unsigned)h << 16));
+                const int gm = m0 + n;
+                Bh[n][k] = gm < M ? Oh[(size_t)gm * kp + gk] : (uint16_t)0;
+                Bl[n][k] = gm < M ? Ol[(size_t)gm * kp + gk] : (uint16_t)0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kTK; ks += 16) {
+                const int kk = ks + 4 * (lane >> 4);
+                bf16x4 ah[2], al[2], bh[2], bl[2];
+                for (int i = 0; i < 2; ++i) {
+                    const int n = wn * 32 + i * 16 + (lane & 15);
+                    ah[i] = *reinterpret_cast<const bf16x4 *>(&Ah[n][kk]);
+                    al[i] = *reinterpret_cast<const bf16x4 *>(&Al[n][kk]);
+                }
+                for (int j = 0; j < 2; ++j) {
+                    const int m = wm * 32 + j * 16 + (lane & 15);
+                    bh[j] = *reinterpret_cast<const bf16x4 *>(&Bh[m][kk]);
+                    bl[j] = *reinterpret_cast<const bf16x4 *>(&Bl[m][kk]);
+                }
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+        }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                const int gm = m0 + wm * 32 + j * 16 + (lane & 15);
+                for (int r = 0; r < 4; ++r) {
+                    const int gn = n0 + wn * 32 + i * 16 + 4 * (lane >> 4) + r;
                     if (gn >= ncols || gm >= M) continue;
                     out[(size_t)gn * M + gm] = acc[i][j][r];
                 }
@@ -244,9 +333,18 @@ void fmm_downward_t(Plan &p, hipStream_t s)
         for (int c = 0; c < nchunk; ++c) {
             const int32_t r0 = (int32_t)(c * ccap);
             dim3 g((M + kTile - 1) / kTile, (unsigned)std::min<int64_t>(256, (ccap + kTile - 1) / kTile));
-            tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>(Ml, p.k_pad, M, nl, (const T *)p.d_phi, p.box.src_box,
-                                                        &p.d_sc->lvl_src[l], (int32_t)p.level_base[l], r0,
-                                                        (int32_t)ccap, nullptr, nullptr, nullptr, (T *)p.d_y);
+            if (std::is_same<T, float>::value && p.precision == PH_FP32_BF16SPLIT) {
+                const size_t off = (size_t)l * M * p.k_pad;
+                tgemm_m2l_bf16s_kernel<<<g, 256, 0, s>>>((const uint16_t *)p.ops.m2l_hi + off,
+                                                         (const uint16_t *)p.ops.m2l_lo + off, p.k_pad, M, nl,
+                                                         (const float *)p.d_phi, p.box.src_box, &p.d_sc->lvl_src[l],
+                                                         (int32_t)p.level_base[l], r0, (int32_t)ccap,
+                                                         (float *)p.d_y);
+            } else {
+                tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>(Ml, p.k_pad, M, nl, (const T *)p.d_phi, p.box.src_box,
+                                                            &p.d_sc->lvl_src[l], (int32_t)p.level_base[l], r0,
+                                                            (int32_t)ccap, nullptr, nullptr, nullptr, (T *)p.d_y);
+            }
             down_gather_kernel<T><<<(unsigned)((cap + 3) / 4), 256, 0, s>>>(a, l, (const T *)p.d_y, M, r0,
                                                                              (int32_t)ccap, c == 0 ? 1 : 0,
                                                                              (const T *)p.d_z);

@@ -32,6 +32,34 @@ std::vector<T> convert(const std::vector<double> &v)
 
 bool finite(double x) { return std::isfinite(x); }
 
+// bfloat16 bits of x, round to nearest even (x finite)
+uint16_t bf16_bits(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+// x = hi + lo + O(2^-16 |x|): the two bfloat16 terms of each value
+void split_bf16(const std::vector<double> &v, std::vector<uint16_t> &hi, std::vector<uint16_t> &lo)
+{
+    hi.resize(v.size());
+    lo.resize(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+        hi[i] = bf16_bits((float)v[i]);
+        lo[i] = bf16_bits((float)(v[i] - (double)bf16_value(hi[i])));
+    }
+}
+
 // Validation happens entirely on the host, before any device call.
 void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr, const ph_options *opt)
 {
@@ -79,8 +107,6 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
     if (!finite(thr->e_applied) || thr->e_applied < 0) bad("thresholds.e_applied must be >= 0");
     if (thr->r_s != 0.0) throw Error{PH_EUNSUPPORTED, "thresholds.r_s (third strategy) must be 0"};
     if (opt->precision < PH_FP64 || opt->precision > PH_FP32_BF16SPLIT) bad("options.precision out of range");
-    if (opt->precision == PH_FP32_BF16SPLIT)
-        throw Error{PH_EUNSUPPORTED, "options.precision PH_FP32_BF16SPLIT is not implemented"};
     if (opt->method < PH_METHOD_FMM || opt->method > PH_METHOD_DIRECT) bad("options.method out of range");
     if (opt->selector < PH_SEL_THRESHOLD || opt->selector > PH_SEL_LEARNED) bad("options.selector out of range");
     if (opt->order_q != 0 && (opt->order_q < 2 || opt->order_q > 8)) bad("options.order_q must be 0 or 2..8");
@@ -533,6 +559,12 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
             upload(p, &p.ops.m2m, convert<float>(m2m));
             upload(p, &p.ops.l2l, convert<float>(l2l));
             upload(p, &p.ops.m2l, convert<float>(m2l));
+            if (p.precision == PH_FP32_BF16SPLIT) {
+                std::vector<uint16_t> hi, lo;
+                split_bf16(m2l, hi, lo);
+                upload(p, &p.ops.m2l_hi, hi);
+                upload(p, &p.ops.m2l_lo, lo);
+            }
             upload(p, &p.ops.lat_unit, convert<float>(lat));
             upload(p, &p.ops.shell_unit, convert<float>(shell));
             if (p.grid_mode) {
