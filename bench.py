@@ -266,8 +266,9 @@ def near_kernel_source_hash():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2112_10059_amd", "csrc")
     text = open(os.path.join(csrc, "k_fmm.hip")).read()
-    i = text.index("template <class T, class TO, bool GUARD>\n__global__ __launch_bounds__(256) void near_kernel(")
-    j = text.index("\n}\n", i) + 3
+    k = text.index(" void near_kernel(")
+    i = text.rindex("template <", 0, k)
+    j = text.index("\n}\n", k) + 3
     h = hashlib.sha256(text[i:j].encode())
     h.update(open(os.path.join(csrc, "k_common.h")).read().encode())
     return h.hexdigest()

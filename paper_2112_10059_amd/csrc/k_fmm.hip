@@ -15,6 +15,8 @@
 //           + sum_{U(B)} K(x, y) q (Kahan in FP32) + own-cell term, combined in FP64.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "k_fmm_args.h"
 
 namespace ph {
@@ -135,33 +137,339 @@ __device__ __forceinline__ double lane_bcast(double v, int j)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Far field of every target leaf (lattice or shell L2P, W list) plus the own-cell term.
-// Leaves without near sources are finished here; the others leave their far field in
-// t_far for the near-field kernel.
-template <class T, class TO, bool GRIDF>
-__global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far, int role)
+// Output of a target whose sums are complete: S = P 2^e (far + near + own cell), in FP64.
+template <class TO>
+__device__ __forceinline__ void put_output(TO *__restrict__ S_out, const int32_t *__restrict__ t_out, int32_t k,
+                                           double P, double tot, int scale_exp)
 {
-    const int32_t b = blockIdx.x;
+    S_out[t_out[k]] = (TO)(P * ldexp(tot, scale_exp));
+}
+
+// W list of target leaf b for the lanes' targets: artificial sources of smaller non-adjacent
+// boxes.  The wave holds the source box's densities in registers, lane li of slot k holding
+// phi[64 k + li], and broadcasts them lane by lane.
+template <class T, int NK>
+__device__ __forceinline__ T w_list_far(const FmmArgs<T> &a, int32_t b, const V4<T> &x, bool act, int lane)
+{
+    T far = 0;
+    const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
+    const int nl = a.n_lam;
+    for (uint32_t e = w0; e < w1; ++e) {
+        const int32_t A = a.L.w[e];
+        const double hwa = a.lt.hw[a.bx.level[A]];
+        T ax, ay, az;
+        box_centre(a, A, hwa, ax, ay, az);
+        const T ha = (T)hwa;
+        T ph[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) ph[k] = 64 * k + lane < nl ? a.phi[(size_t)A * nl + 64 * k + lane] : T(0);
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+            for (int j = 0; j < 64 && 64 * k + j < nl; ++j) {
+                const int li = 64 * k + j;
+                const T wv = lane_bcast(ph[k], j);
+                const T dx = x.x - (ax + ha * a.lat[3 * li]);
+                const T dy = x.y - (ay + ha * a.lat[3 * li + 1]);
+                const T dz = x.z - (az + ha * a.lat[3 * li + 2]);
+                if (act) far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * wv;
+            }
+    }
+    return far;
+}
+
+// This workgroup's level and the first entry of its slice of that level's far_a segment, for
+// the levels in mask, at per leaves per workgroup; false if the workgroup has no slice.
+__device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint32_t mask, int per, int &level,
+                                          int32_t &first)
+{
+    int32_t cnt[kMaxDepth + 2];
+#pragma unroll
+    for (int l = 0; l < kMaxDepth + 2; ++l) cnt[l] = sc->n_far_a_lvl[l];  // loads issued together
+    int32_t acc = 0;
+#pragma unroll
+    for (int l = 0; l < kMaxDepth + 2; ++l) {
+        if (l > depth || !((mask >> l) & 1u)) continue;
+        const int32_t nb = (cnt[l] + per - 1) / per;
+        if ((int32_t)blockIdx.x < acc + nb) {
+            level = l;
+            first = ((int32_t)blockIdx.x - acc) * per;
+            return true;
+        }
+        acc += nb;
+    }
+    return false;
+}
+
+// Far field of grid-operator leaves with n_lam <= 64 and at most 4^3 cells (FP32), on the
+// matrix cores.  A workgroup takes kFarMLeaves leaves of one level: with their check values
+// U (leaves x n_lam) and the level operator G (n_lam x cells) in LDS, C = U G is a
+// 16 x 64 x 64 product (wave j: the 16 x 16 tile of cells 16 j .. 16 j + 15,
+// v_mfma_f32_16x16x4_f32 over k), written back to LDS; then the 256 threads walk the
+// workgroup's targets in one flat range, their loads issued together, and finish them as the
+// wave kernel does (far = C[leaf][cell], W list, own cell, output or t_far).  Many small
+// workgroups keep many dependent load chains in flight.
+constexpr int kFarMLeaves = 16;
+
+template <class TO>
+__global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__restrict__ S_out,
+                                                       float *__restrict__ t_far, uint32_t level_mask)
+{
+    __shared__ float Us[kFarMLeaves][65];  // U, then C = U G
+    __shared__ float Gs[64][65];
+    __shared__ int32_t lbox[kFarMLeaves], lt0[kFarMLeaves], loff[kFarMLeaves + 1];
+    __shared__ uint8_t lnear[kFarMLeaves], lw[kFarMLeaves];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int level;
-    if (!box_live(a.lt, a.sc, b, level)) return;
-    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.t_cnt[b] == 0) return;
+    int32_t first;
+    if (!far_slice(a.sc, a.lt.depth, level_mask, kFarMLeaves, level, first)) return;
+    const int32_t cnt = min(kFarMLeaves, a.sc->n_far_a_lvl[level] - first);
+    const int nl = a.n_lam;
+    const int gm = level >= 2 ? a.grid_m[level] : 0;  // 0: no far field at this level
+    const int R = gm * gm * gm;
+    const float *G = a.grid_g + a.grid_off[level];
+    if (w == 0 && lane < kFarMLeaves) {
+        const bool valid = lane < cnt;
+        const int4 en = valid ? a.L.far_a[a.lt.base[level] + first + lane] : make_int4(-1, 0, 0, 0);
+        lbox[lane] = en.x;
+        lt0[lane] = en.y;
+        lnear[lane] = (en.w & 1) != 0;
+        lw[lane] = (en.w & 2) != 0;
+        // inclusive scan of the target counts over the 16 lanes
+        int32_t v = en.z;
+        for (int o = 1; o < kFarMLeaves; o <<= 1) {
+            const int32_t y = __shfl_up(v, o, kFarMLeaves);
+            if (lane >= o) v += y;
+        }
+        loff[lane + 1] = v;
+        if (lane == 0) loff[0] = 0;
+    }
+    for (int i = t; i < 64 * 64; i += 256) {
+        const int li = i >> 6, c = i & 63;
+        Gs[li][c] = (li < nl && c < R) ? G[li * R + c] : 0.0f;
+    }
+    __syncthreads();
+    const int32_t total = loff[cnt];
+    // the targets' data (issued with the check values: one round trip for both)
+    constexpr int kU = 4;  // targets per thread, kU x 256 >= kFarMLeaves x 64
+    const int32_t *__restrict__ tcell = a.t_cell;
+    const int32_t *__restrict__ tout = a.t_out;
+    const V4<float> *__restrict__ tdat = a.t_dat;
+    int32_t q[kU], k[kU], cell[kU], out[kU];
+    V4<float> x[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int32_t f = u * 256 + t;
+        q[u] = -1;
+        if (f < total) {
+            // the leaf of flat target f: the last q with loff[q] <= f
+            int lo = 0, hi = cnt - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (loff[mid] <= f) lo = mid;
+                else hi = mid - 1;
+            }
+            q[u] = lo;
+            k[u] = lt0[lo] + (f - loff[lo]);
+        }
+    }
+    for (int i = t; i < kFarMLeaves * 64; i += 256) {
+        const int qq = i >> 6, li = i & 63;
+        const int32_t b = lbox[qq];
+        Us[qq][li] = (b >= 0 && li < nl) ? a.u[(size_t)b * nl + li] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        if (q[u] >= 0) {
+            cell[u] = gm > 0 ? tcell[k[u]] : 0;
+            out[u] = tout[k[u]];
+            x[u] = tdat[k[u]];
+        }
+    __syncthreads();
+    f32x4 acc = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < 64; k0 += 4)
+        acc = Mfma<float>::mma(Us[lane & 15][k0 + (lane >> 4)], Gs[k0 + (lane >> 4)][16 * w + (lane & 15)], acc);
+    __syncthreads();  // every wave has read U
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Us[Mfma<float>::row(lane, r)][16 * w + (lane & 15)] = acc[r];
+    __syncthreads();
+    const int scale_exp = a.sc->scale_exp;
+    auto finish = [&](int qq, int32_t kk, int32_t cl, int32_t ot, const V4<float> &xx) {
+        const int32_t b = lbox[qq];
+        float far = gm > 0 ? Us[qq][local_cell(a, cl, b, gm)] : 0.0f;
+        if (lw[qq]) {
+            // W list (rare on grids): the source boxes' lattice densities, one thread per target
+            for (uint32_t e = a.L.w_off[b]; e < a.L.w_off[b + 1]; ++e) {
+                const int32_t A = a.L.w[e];
+                const double hwa = a.lt.hw[a.bx.level[A]];
+                float ax, ay, az;
+                box_centre(a, A, hwa, ax, ay, az);
+                const float ha = (float)hwa;
+                for (int li = 0; li < nl; ++li) {
+                    const float dx = xx.x - (ax + ha * a.lat[3 * li]);
+                    const float dy = xx.y - (ay + ha * a.lat[3 * li + 1]);
+                    const float dz = xx.z - (az + ha * a.lat[3 * li + 2]);
+                    far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * a.phi[(size_t)A * nl + li];
+                }
+            }
+        }
+        if (lnear[qq]) t_far[kk] = far;
+        else S_out[ot] = (TO)(a.P * ldexp((double)far + (double)xx.w, scale_exp));
+    };
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        if (q[u] >= 0) finish(q[u], k[u], cell[u], out[u], x[u]);
+    // targets beyond the first kU x 256 (leaves of levels without an operator may hold more)
+    for (int32_t f = kU * 256 + t; f < total; f += 256) {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (loff[mid] <= f) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t kk = lt0[lo] + (f - loff[lo]);
+        finish(lo, kk, gm > 0 ? tcell[kk] : 0, tout[kk], tdat[kk]);
+    }
+    if (a.work && t < cnt) {
+        const int32_t b = lbox[t];
+        const int32_t tn = a.bx.t_cnt[b];
+        unsigned long long near_src = 0;
+        for (uint32_t e = a.L.u_off[b]; e < a.L.u_off[b + 1]; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+        atomicAdd(&a.work[0], near_src * tn);
+        if (lnear[t]) atomicAdd(&a.work[10], (unsigned long long)tn);
+        if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
+        const uint32_t nw = a.L.w_off[b + 1] - a.L.w_off[b];
+        if (nw) atomicAdd(&a.work[2], (unsigned long long)nw * nl * tn);
+    }
+}
+
+// Far field of the target leaves whose level has a grid operator (uniform grids).  Each
+// workgroup takes up to kFarLeaves leaves of one level (the list's per-level segments), stages
+// that level's operator G_l (n_lam x m^3) in LDS once, and gives one wave per leaf:
+// far(t) = sum_li G_l[li][cell(t)] u[li], with the leaf's u in registers (lane li of slot k
+// holds u[64 k + li]) broadcast lane by lane, plus the W list and the own-cell term.  Leaves
+// without near sources are finished here; the others leave their far field in t_far.
+constexpr int kFarLeaves = 4;      // leaves per workgroup: one per wave, all in flight at once
+constexpr int kGridStage = 8192;   // operator entries staged in LDS (larger operators stay in L2)
+
+template <class T, int NK, bool LDSG>
+__device__ __forceinline__ T grid_far(const T *__restrict__ G, int R, int nl, int r, const T (&uv)[NK])
+{
+    // four independent partial sums (latency), added in a fixed order
+    T f4[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+#pragma unroll 16
+        for (int j = 0; j < 64; ++j)
+            if (64 * k + j < nl) f4[j & 3] += G[(64 * k + j) * R + r] * lane_bcast(uv[k], j);
+    return (f4[0] + f4[1]) + (f4[2] + f4[3]);
+}
+
+template <class T, class TO, int NK>
+__global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far,
+                                                       int stage_cap, uint32_t level_mask)
+{
+    extern __shared__ __align__(16) unsigned char far_lds[];  // stage_cap operator entries
+    T *Gs = reinterpret_cast<T *>(far_lds);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int level;
+    int32_t first;
+    if (!far_slice(a.sc, a.lt.depth, level_mask, kFarLeaves, level, first)) return;  // the whole workgroup
+    const int32_t cnt = min(kFarLeaves, a.sc->n_far_a_lvl[level] - first);
+    const int nl = a.n_lam;
+    const int gm = level >= 2 ? a.grid_m[level] : 0;
+    const int R = gm * gm * gm;
+    const T *G = a.grid_g + a.grid_off[level];
+    const bool staged = gm > 0 && nl * R <= stage_cap;
+    if (staged) {
+        // 16-byte loads, all issued before any store (one round trip to L2, not one per element);
+        // the level offsets are multiples of 16 bytes whenever n_lam m^3 is a multiple of 4
+        const int ne = nl * R;
+        if ((ne & 3) == 0 && (a.grid_off[level] & 3) == 0) {
+            using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+            constexpr int per = 16 / sizeof(T);
+            const V *src = reinterpret_cast<const V *>(G);
+            V *dst = reinterpret_cast<V *>(Gs);
+            const int nv = ne / per;
+            V buf[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = threadIdx.x + u * blockDim.x;
+                if (i < nv) buf[u] = src[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = threadIdx.x + u * blockDim.x;
+                if (i < nv) dst[i] = buf[u];
+            }
+            for (int i = threadIdx.x + 8 * blockDim.x; i < nv; i += blockDim.x) dst[i] = src[i];
+        } else {
+            for (int i = threadIdx.x; i < ne; i += blockDim.x) Gs[i] = G[i];
+        }
+        __syncthreads();
+    }
+    const int scale_exp = a.sc->scale_exp;
+    for (int32_t q = w; q < cnt; q += 4) {
+        const int32_t b = a.L.far_a[a.lt.base[level] + first + q].x;
+        T uv[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+            uv[k] = (gm > 0 && 64 * k + lane < nl) ? a.u[(size_t)b * nl + 64 * k + lane] : T(0);
+        const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+        const bool near = a.L.u_off[b + 1] > a.L.u_off[b];
+        const bool has_w = a.L.w_off[b + 1] > a.L.w_off[b];
+        if (a.work && lane == 0) {
+            unsigned long long near_src = 0;
+            for (uint32_t e = a.L.u_off[b]; e < a.L.u_off[b + 1]; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+            atomicAdd(&a.work[0], near_src * tn);
+            if (near) atomicAdd(&a.work[10], (unsigned long long)tn);
+            if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
+            if (has_w) atomicAdd(&a.work[2], (unsigned long long)(a.L.w_off[b + 1] - a.L.w_off[b]) * nl * tn);
+        }
+        for (int tb = 0; tb < tn; tb += 64) {
+            const int t = tb + lane;
+            const bool act = t < tn;
+            V4<T> x;
+            if (act) x = a.t_dat[tf + t];
+            else x.x = x.y = x.z = x.w = T(0);
+            T far = 0;
+            if (gm > 0) {
+                const int r = act ? local_cell(a, a.t_cell[tf + t], b, gm) : 0;
+                far = staged ? grid_far<T, NK, true>(Gs, R, nl, r, uv) : grid_far<T, NK, false>(G, R, nl, r, uv);
+            }
+            if (has_w) far += w_list_far<T, NK>(a, b, x, act, lane);
+            if (act) {
+                if (near) t_far[tf + t] = far;
+                else put_output(S_out, a.t_out, tf + t, a.P, (double)far + (double)x.w, scale_exp);
+            }
+        }
+    }
+}
+
+// Far field of the other target leaves (point clouds, or grid levels without an operator),
+// one workgroup per leaf over the list: the leaf's check values give the intensities of its
+// shell points, which are then evaluated at every target; plus the W list and the own cell.
+template <class T, class TO>
+__global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far)
+{
     __shared__ T uvec[kMaxLattice];
     __shared__ T wphi[kMaxLattice];
-    __shared__ V4<T> shp[GRIDF ? 1 : kMaxShell];  // shell point position and its intensity psi
+    __shared__ V4<T> shp[kMaxShell];  // shell point position and its intensity
+    const int32_t n = a.sc->n_far_b;
     const int nl = a.n_lam, ns = a.n_sig;
-    const bool has_far = level >= 2;
-    const int gm = has_far ? a.grid_m[level] : 0;
-    // role 1: boxes with a lattice operator (or no far field); role 2: the others; role 0: all
-    if (role == 1 && has_far && gm == 0) return;
-    if (role == 2 && !(has_far && gm == 0)) return;
-    const double hw = a.lt.hw[level];
-    T cx, cy, cz;
-    box_centre(a, b, hw, cx, cy, cz);
-    const T h = (T)hw;
-    if (has_far) {
-        for (int li = threadIdx.x; li < nl; li += blockDim.x) uvec[li] = a.u[(size_t)b * nl + li];
-        __syncthreads();
-        if (!GRIDF && gm == 0) {
+    const int scale_exp = a.sc->scale_exp;
+    for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
+        const int32_t b = a.L.far_b[idx];
+        const int level = a.bx.level[b];
+        const bool has_far = level >= 2;
+        const double hw = a.lt.hw[level];
+        T cx, cy, cz;
+        box_centre(a, b, hw, cx, cy, cz);
+        const T h = (T)hw;
+        __syncthreads();  // the previous leaf's use of the shared arrays is over
+        if (has_far) {
+            for (int li = threadIdx.x; li < nl; li += blockDim.x) uvec[li] = a.u[(size_t)b * nl + li];
+            __syncthreads();
             const T *U = a.uc2e_rm + (size_t)level * nl * ns;
             for (int sg = threadIdx.x; sg < ns; sg += blockDim.x) {
                 T s = 0;
@@ -175,122 +483,110 @@ __global__ void leaf_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict_
             }
             __syncthreads();
         }
-    }
-    const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
-    const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
-    const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
-    const int scale_exp = a.sc->scale_exp;
-    if (a.work && threadIdx.x == 0) {
-        unsigned long long near_src = 0, w_eval = 0;
-        for (uint32_t e = u0; e < u1; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
-        w_eval = (unsigned long long)(w1 - w0) * nl;
-        atomicAdd(&a.work[0], near_src * tn);
-        if (u1 > u0) atomicAdd(&a.work[10], (unsigned long long)tn);  // targets the near-field kernel visits
-        if (has_far && gm == 0) atomicAdd(&a.work[1], (unsigned long long)tn * ns);
-        if (has_far && gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
-        if (w_eval) atomicAdd(&a.work[2], w_eval * tn);
-    }
-    for (int tb = 0; tb < tn; tb += blockDim.x) {
-        const int t = tb + threadIdx.x;
-        const bool act = t < tn;
-        V4<T> x;
-        if (act) x = a.t_dat[tf + t];
-        else x.x = x.y = x.z = x.w = T(0);
-        T far = 0;
-        if (has_far && act) {
-            if (GRIDF || gm > 0) {
-                const T *G = a.grid_g + a.grid_off[level];
-                const int R = gm * gm * gm;
-                const int r = local_cell(a, a.t_cell[tf + t], b, gm);
-                for (int li = 0; li < nl; ++li) far += G[(size_t)li * R + r] * uvec[li];
-            } else if (!GRIDF) {
+        const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+        const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
+        const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
+        if (a.work && threadIdx.x == 0) {
+            unsigned long long near_src = 0;
+            for (uint32_t e = u0; e < u1; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+            atomicAdd(&a.work[0], near_src * tn);
+            if (u1 > u0) atomicAdd(&a.work[10], (unsigned long long)tn);
+            if (has_far) atomicAdd(&a.work[1], (unsigned long long)tn * ns);
+            if (w1 > w0) atomicAdd(&a.work[2], (unsigned long long)(w1 - w0) * nl * tn);
+        }
+        for (int tb = 0; tb < tn; tb += blockDim.x) {
+            const int t = tb + threadIdx.x;
+            const bool act = t < tn;
+            V4<T> x;
+            if (act) x = a.t_dat[tf + t];
+            else x.x = x.y = x.z = x.w = T(0);
+            T far = 0;
+            if (has_far && act)
                 for (int sg = 0; sg < ns; ++sg) {
-                    const V4<T> q = shp[GRIDF ? 0 : sg];
+                    const V4<T> q = shp[sg];
                     const T dx = x.x - q.x, dy = x.y - q.y, dz = x.z - q.z;
                     far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * q.w;
                 }
+            for (uint32_t e = w0; e < w1; ++e) {
+                const int32_t A = a.L.w[e];
+                const double hwa = a.lt.hw[a.bx.level[A]];
+                T ax, ay, az;
+                box_centre(a, A, hwa, ax, ay, az);
+                const T ha = (T)hwa;
+                __syncthreads();
+                for (int li = threadIdx.x; li < nl; li += blockDim.x) wphi[li] = a.phi[(size_t)A * nl + li];
+                __syncthreads();
+                if (act)
+                    for (int li = 0; li < nl; ++li) {
+                        const T dx = x.x - (ax + ha * a.lat[3 * li]);
+                        const T dy = x.y - (ay + ha * a.lat[3 * li + 1]);
+                        const T dz = x.z - (az + ha * a.lat[3 * li + 2]);
+                        far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * wphi[li];
+                    }
             }
-        }
-        // W list: artificial sources of smaller non-adjacent boxes
-        for (uint32_t e = w0; e < w1; ++e) {
-            const int32_t A = a.L.w[e];
-            const int la = a.bx.level[A];
-            const double hwa = a.lt.hw[la];
-            T ax, ay, az;
-            box_centre(a, A, hwa, ax, ay, az);
-            const T ha = (T)hwa;
-            __syncthreads();
-            for (int li = threadIdx.x; li < nl; li += blockDim.x) wphi[li] = a.phi[(size_t)A * nl + li];
-            __syncthreads();
-            if (act)
-                for (int li = 0; li < nl; ++li) {
-                    const T dx = x.x - (ax + ha * a.lat[3 * li]);
-                    const T dy = x.y - (ay + ha * a.lat[3 * li + 1]);
-                    const T dz = x.z - (az + ha * a.lat[3 * li + 2]);
-                    far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * wphi[li];
-                }
-        }
-        if (act) {
-            if (u1 > u0) {
-                t_far[tf + t] = far;
-            } else {
-                const double tot = (double)far + (double)x.w;
-                S_out[a.perm[a.t_pos[tf + t]]] = (TO)(a.P * ldexp(tot, scale_exp));
+            if (act) {
+                if (u1 > u0) t_far[tf + t] = far;
+                else put_output(S_out, a.t_out, tf + t, a.P, (double)far + (double)x.w, scale_exp);
             }
         }
     }
 }
 
-// Exact near field (Sec. 2.4 eq. (16)) of leaves with a U list: four waves per leaf,
-// wave w sums the U entries w, w+4, ...; each wave keeps a Kahan-compensated FP32 sum
-// (FP64 in the FP64 form); the partial sums, the far field and the own-cell term are
-// combined in FP64 in a fixed order.  Sources are broadcast lane by lane from registers.
+// Exact near field (Sec. 2.4 eq. (16)) of the leaves with a U list, one workgroup of
+// kNearWaves waves per leaf over the list.  The leaf's work items are (U entry, chunk of 64
+// of its sources), dealt to the waves in turn; each wave keeps a Kahan-compensated FP32 sum
+// (FP64 in the FP64 form) per target with the sources broadcast lane by lane from
+// registers.  The partial sums, the far field and the own-cell term are combined in FP64
+// in wave order, so the result does not depend on scheduling.
+constexpr int kNearWaves = 16;
+
 template <class T, class TO, bool GUARD>
-__global__ __launch_bounds__(256) void near_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
-                                                   const T *__restrict__ t_far)
+__global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
+                                                               const T *__restrict__ t_far)
 {
-    const int32_t b = blockIdx.x;
-    int level;
-    if (!box_live(a.lt, a.sc, b, level)) return;
-    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.t_cnt[b] == 0) return;
-    const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
-    if (u1 == u0) return;
-    __shared__ double part[4][64];
+    __shared__ double part[kNearWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+    const int32_t n = a.sc->n_near;
     const int scale_exp = a.sc->scale_exp;
-    for (int tb = 0; tb < tn; tb += 64) {
-        const int t = tb + lane;
-        const bool act = t < tn;
-        V4<T> x;
-        if (act) x = a.t_dat[tf + t];
-        else x.x = x.y = x.z = x.w = T(0);
-        Acc<T> near;
-        for (uint32_t e = u0 + w; e < u1; e += 4) {
-            const int32_t C = a.L.u[e];
-            const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
-            for (int base = 0; base < sn; base += 64) {
-                const int m = min(64, sn - base);
-                V4<T> y;
-                if (lane < m) y = a.s_dat[sf + base + lane];
-                else y.x = y.y = y.z = y.w = T(0);
-                for (int j = 0; j < m; ++j) {
-                    const T yx = lane_bcast(y.x, j), yy = lane_bcast(y.y, j), yz = lane_bcast(y.z, j),
-                            yw = lane_bcast(y.w, j);
-                    const T dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    if (act && r2 > T(0)) near.add(kernel_eval<GUARD>(r2, a.kp) * yw);
+    for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
+        const int32_t b = a.L.near_leaves[idx];
+        const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
+        const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+        for (int tb = 0; tb < tn; tb += 64) {
+            const int t = tb + lane;
+            const bool act = t < tn;
+            V4<T> x;
+            if (act) x = a.t_dat[tf + t];
+            else x.x = x.y = x.z = x.w = T(0);
+            Acc<T> near;
+            int item = 0;
+            for (uint32_t e = u0; e < u1; ++e) {
+                const int32_t C = a.L.u[e];
+                const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
+                for (int base = 0; base < sn; base += 64, ++item) {
+                    if (item % kNearWaves != w) continue;
+                    const int m = min(64, sn - base);
+                    V4<T> y;
+                    if (lane < m) y = a.s_dat[sf + base + lane];
+                    else y.x = y.y = y.z = y.w = T(0);
+                    for (int j = 0; j < m; ++j) {
+                        const T yx = lane_bcast(y.x, j), yy = lane_bcast(y.y, j), yz = lane_bcast(y.z, j),
+                                yw = lane_bcast(y.w, j);
+                        const T dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
+                        const T r2 = dx * dx + dy * dy + dz * dz;
+                        if (act && r2 > T(0)) near.add(kernel_eval<GUARD>(r2, a.kp) * yw);
+                    }
                 }
             }
+            __syncthreads();  // the previous pass's partial sums have been read
+            part[w][lane] = near.value();
+            __syncthreads();
+            if (w == 0 && act) {
+                double tot = (double)t_far[tf + t];
+                for (int q = 0; q < kNearWaves; ++q) tot += part[q][lane];
+                put_output(S_out, a.t_out, tf + t, a.P, tot + (double)x.w, scale_exp);
+            }
         }
-        part[w][lane] = near.value();
-        __syncthreads();
-        if (w == 0 && act) {
-            const double tot = (double)t_far[tf + t] + part[0][lane] + part[1][lane] + part[2][lane] +
-                               part[3][lane] + (double)x.w;
-            S_out[a.perm[a.t_pos[tf + t]]] = (TO)(a.P * ldexp(tot, scale_exp));
-        }
-        __syncthreads();
     }
 }
 
@@ -309,24 +605,61 @@ template <class T>
 void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
-    bool shell_levels = !p.grid_mode;
-    for (int l = 2; l <= p.max_depth; ++l) shell_levels = shell_levels || p.grid_m[l] == 0;
+    // upper bounds on the list lengths (the counts are on the device)
+    const int64_t B = p.box_cap;
     if (p.grid_mode) {
-        leaf_kernel<T, T, true><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far, 1);
-        if (shell_levels) leaf_kernel<T, T, false><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far, 2);
-    } else {
-        leaf_kernel<T, T, false><<<(unsigned)p.box_cap, 64, 0, s>>>(a, (T *)S_out, (T *)p.d_t_far, 0);
+        // levels of the grid-operator lists: the matrix-core kernel where the operator is at most
+        // 64 x 64 (FP32), the wave kernel elsewhere (and for levels without a far field)
+        uint32_t mfma_levels = 0, wave_levels = 0;
+        for (int l = 0; l <= p.max_depth; ++l) {
+            if (!(l < 2 || p.grid_m[l] > 0)) continue;
+            const bool mf = std::is_same<T, float>::value && (l < 2 || p.grid_m[l] <= 4) && p.n_lam <= 64;
+            (mf ? mfma_levels : wave_levels) |= 1u << l;
+        }
+        int64_t gm_blocks = 0, gw_blocks = 0;
+        for (int l = 0; l <= p.max_depth; ++l) {
+            if ((mfma_levels >> l) & 1u) gm_blocks += (p.level_cap[l] + kFarMLeaves - 1) / kFarMLeaves;
+            if ((wave_levels >> l) & 1u) gw_blocks += (p.level_cap[l] + kFarLeaves - 1) / kFarLeaves;
+        }
+        if (gm_blocks > 0 && std::is_same<T, float>::value)
+            far_mfma_kernel<float><<<(unsigned)gm_blocks, 256, 0, s>>>(*reinterpret_cast<FmmArgs<float> *>(&a),
+                                                                       (float *)S_out, (float *)p.d_t_far,
+                                                                       mfma_levels);
+        if (gw_blocks > 0) {
+            // LDS for the largest level operator that fits the staging cap
+            int cap = 0;
+            for (int l = 2; l <= p.max_depth; ++l) {
+                const int e = p.n_lam * p.grid_m[l] * p.grid_m[l] * p.grid_m[l];
+                if (((wave_levels >> l) & 1u) && p.grid_m[l] > 0 && e <= kGridStage) cap = std::max(cap, e);
+            }
+            const size_t lds = (size_t)cap * sizeof(T);
+            const unsigned g = (unsigned)gw_blocks;
+            switch ((p.n_lam + 63) / 64) {
+            case 1: far_grid_kernel<T, T, 1><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
+            case 2: far_grid_kernel<T, T, 2><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
+            case 3:
+            case 4: far_grid_kernel<T, T, 4><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
+            default: far_grid_kernel<T, T, 8><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
+            }
+        }
     }
+    // on grids this list holds only leaves of levels >= 2 without an operator
+    bool shell_leaves = !p.grid_mode;
+    for (int l = 2; l <= p.max_depth; ++l) shell_leaves = shell_leaves || p.grid_m[l] == 0;
+    if (shell_leaves)
+        far_shell_kernel<T, T><<<(unsigned)std::min<int64_t>(B, p.grid_mode ? 256 : 4096), 64, 0, s>>>(
+            a, (T *)S_out, (T *)p.d_t_far);
 }
 
 template <class T>
 void fmm_near_t(Plan &p, void *S_out, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
+    const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 1024);
     if (p.near_guard)
-        near_kernel<T, T, true><<<(unsigned)p.box_cap, 256, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
+        near_kernel<T, T, true><<<g, 64 * kNearWaves, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
     else
-        near_kernel<T, T, false><<<(unsigned)p.box_cap, 256, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
+        near_kernel<T, T, false><<<g, 64 * kNearWaves, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
 }
 
 }  // namespace

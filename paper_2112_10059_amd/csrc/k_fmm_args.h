@@ -18,6 +18,7 @@ struct FmmArgs {
     const V4<T> *s_dat;
     const V4<T> *t_dat;
     const int32_t *t_pos;
+    const int32_t *t_out;  // caller index of each selected target
     const int32_t *perm;
     const T *uc2e_rm;   // levels x n_lam x n_sig
     const T *uc2e_cm;   // levels x n_sig x n_lam
@@ -71,6 +72,7 @@ inline FmmArgs<T> make_args(Plan &p)
     a.s_dat = (const V4<T> *)p.d_s_dat;
     a.t_dat = (const V4<T> *)p.d_t_dat;
     a.t_pos = p.d_t_pos;
+    a.t_out = p.d_t_out;
     a.perm = p.d_perm;
     a.uc2e_rm = (const T *)p.ops.uc2e_rm;
     a.uc2e_cm = (const T *)p.ops.uc2e_cm;

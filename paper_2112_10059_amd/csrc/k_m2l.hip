@@ -20,35 +20,6 @@ namespace ph {
 
 namespace {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <class T>
-struct Mfma;
-
-// v_mfma_f32_16x16x4_f32: A lane l = A[l%16][l/16], B lane l = B[l/16][l%16],
-// D register r of lane l = D[4 (l/16) + r][l%16]
-template <>
-struct Mfma<float> {
-    using acc_t = f32x4;
-    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
-};
-
-// v_mfma_f64_16x16x4_f64: same operand layout, D register r of lane l = D[(l/16) + 4 r][l%16]
-template <>
-struct Mfma<double> {
-    using acc_t = f64x4;
-    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
-};
-
 constexpr int kTile = 64;     // tile of source boxes (rows of Y) and of stacked rows m
 constexpr int kTK = kGemmK;   // K chunk staged in LDS
 constexpr int kPad = 4;       // LDS row padding (bank spread)

@@ -139,7 +139,7 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
                                const double *__restrict__ w, double w_uniform, double c_self, int64_t n,
                                CallScalars *__restrict__ sc, const uint64_t *__restrict__ scanned,
                                int32_t *__restrict__ s_pos, int32_t *__restrict__ t_pos,
-                               uint64_t *__restrict__ s_key, uint64_t *__restrict__ t_key,
+                               int32_t *__restrict__ t_out,
                                typename Vec4<T>::type *__restrict__ s_dat, typename Vec4<T>::type *__restrict__ t_dat,
                                const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell,
                                int32_t *__restrict__ t_cell)
@@ -172,7 +172,6 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
     if (is_src) {
         const double wk = w ? w[k] : w_uniform;
         s_pos[sp_lo] = (int32_t)k;
-        s_key[sp_lo] = key[k];
         typename Vec4<T>::type d;
         d.x = (T)x;
         d.y = (T)y;
@@ -183,7 +182,7 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
     }
     if (is_tgt) {
         t_pos[sp_hi] = (int32_t)k;
-        t_key[sp_hi] = key[k];
+        t_out[sp_hi] = o;
         typename Vec4<T>::type d;
         d.x = (T)x;
         d.y = (T)y;
@@ -243,12 +242,12 @@ void launch_compact(const Plan &p, const void *I, hipStream_t s)
     if (p.precision == PH_FP64)
         compact_kernel<double, double><<<g, 256, 0, s>>>(
             (const double *)I, p.d_perm, p.d_key, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_flag,
-            p.d_s_pos, p.d_t_pos, p.d_s_key, p.d_t_key, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
+            p.d_s_pos, p.d_t_pos, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
     else
         compact_kernel<float, float><<<g, 256, 0, s>>>(
             (const float *)I, p.d_perm, p.d_key, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_flag,
-            p.d_s_pos, p.d_t_pos, p.d_s_key, p.d_t_key, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
+            p.d_s_pos, p.d_t_pos, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
 }
 

@@ -189,8 +189,24 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_lev
     }
 }
 
-__global__ void list_count_kernel(BoxArrays bx, LevelInfo li, const CallScalars *__restrict__ sc, int32_t nbox,
-                                  Lists L)
+// Append val to list for the lanes with pred: one atomic per wave, lanes in lane order.
+template <class V>
+__device__ __forceinline__ void wave_append(bool pred, V *__restrict__ list, int32_t *counter, V val)
+{
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
+// List lengths per box, and the leaf lists of the target-side kernels.  grid_levels: bit l
+// set when leaves of level l take their far field from a grid operator (or have none).
+__global__ void list_count_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc, int32_t nbox,
+                                  Lists L, uint32_t grid_levels)
 {
     const int32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid == 0) L.u_off[nbox] = L.w_off[nbox] = L.x_off[nbox] = 0;  // scanned into the totals
@@ -207,6 +223,21 @@ __global__ void list_count_kernel(BoxArrays bx, LevelInfo li, const CallScalars 
     L.u_off[gid] = nu;
     L.w_off[gid] = nw;
     L.x_off[gid] = nx;
+    const bool tleaf = b >= 0 && (bx.flags[b] & kBoxLeaf) && bx.t_cnt[b] > 0;
+    const int lev = b >= 0 ? bx.level[b] : 0;
+    const bool grid_leaf = tleaf && ((grid_levels >> lev) & 1u);
+    // grid-operator leaves go to their level's segment (a wave rarely spans two levels)
+    uint64_t pending = __ballot(grid_leaf);
+    const int4 entry = make_int4(b, b >= 0 ? bx.t_first[b] : 0, b >= 0 ? bx.t_cnt[b] : 0,
+                                 (nu > 0 ? 1 : 0) | (nw > 0 ? 2 : 0));
+    while (pending) {
+        const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
+        const bool mine = grid_leaf && lev == l0;
+        wave_append(mine, L.far_a + li.base[l0], &sc->n_far_a_lvl[l0], entry);
+        pending &= ~__ballot(mine);
+    }
+    wave_append(tleaf && !grid_leaf, L.far_b, &sc->n_far_b, b);
+    wave_append(tleaf && nu > 0, L.near_leaves, &sc->n_near, b);
 }
 
 __global__ void list_fill_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc, int32_t nbox, Lists L)
@@ -266,7 +297,11 @@ void build_lists(Plan &p, hipStream_t s)
     LevelInfo li = level_info(p);
     const int32_t nbox = (int32_t)p.box_cap;
     const unsigned g = (unsigned)((nbox + 255) / 256);
-    list_count_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists);
+    uint32_t grid_levels = 0;
+    if (p.grid_mode)
+        for (int l = 0; l <= p.max_depth; ++l)
+            if (l < 2 || p.grid_m[l] > 0) grid_levels |= 1u << l;
+    list_count_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels);
     // nbox + 1 entries: the last one (0 before the scan) receives the total
     exclusive_scan_u32(p.lists.u_off, nbox + 1, p.d_scan_tmp, reinterpret_cast<uint32_t *>(&p.d_sc->n_u), s);
     exclusive_scan_u32(p.lists.w_off, nbox + 1, p.d_scan_tmp, reinterpret_cast<uint32_t *>(&p.d_sc->n_w), s);

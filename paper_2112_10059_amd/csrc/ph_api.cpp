@@ -204,8 +204,7 @@ void alloc_workspace(Plan &p)
     p.d_scan_tmp = dev_alloc(p, p.scan_tmp_bytes);
     p.d_s_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
     p.d_t_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
-    p.d_s_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
-    p.d_t_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
+    p.d_t_out = (int32_t *)dev_alloc(p, (size_t)n * 4);
     p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);
     p.d_t_dat = dev_alloc(p, (size_t)n * 4 * rs);
     p.d_t_far = dev_alloc(p, (size_t)n * rs);
@@ -235,6 +234,9 @@ void alloc_workspace(Plan &p)
     L.u = (int32_t *)dev_alloc(p, L.u_cap * 4);
     L.w = (int32_t *)dev_alloc(p, L.w_cap * 4);
     L.x = (int32_t *)dev_alloc(p, L.x_cap * 4);
+    L.far_a = (int4 *)dev_alloc(p, B * sizeof(int4));
+    L.far_b = (int32_t *)dev_alloc(p, B * 4);
+    L.near_leaves = (int32_t *)dev_alloc(p, B * 4);
     if (p.method == PH_METHOD_FMM) {
         p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
         p.d_u = dev_alloc(p, (size_t)B * p.n_lam * rs);
@@ -275,12 +277,13 @@ void free_plan(Plan *p)
     // every pointer member that came from dev_alloc
     void *ptrs[] = {p->d_key, p->d_perm, p->d_iperm, p->d_xyz, p->d_w, p->ops.uc2e_rm, p->ops.uc2e_cm,
                     p->ops.m2m, p->ops.l2l, p->ops.m2l, p->ops.lat_unit, p->ops.shell_unit, p->ops.m2l_hi,
-                    p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_scan_tmp, p->d_s_pos, p->d_t_pos, p->d_s_key,
-                    p->d_t_key, p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
+                    p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_scan_tmp, p->d_s_pos, p->d_t_pos, p->d_t_out,
+                    p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
                     p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
                     p->box.child, p->box.coll, p->box.start, p->box.end, p->box.srcflag, p->box.src_rank, p->box.tpar_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_off,
-                    p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->d_phi, p->d_u,
+                    p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
+                    p->lists.far_b, p->lists.near_leaves, p->d_phi, p->d_u,
                     p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
                     p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
                     p->d_row_feat,

@@ -52,6 +52,8 @@ struct CallScalars {
     int32_t lvl_tpar[kMaxDepth + 2];    // split boxes with targets per level
     int32_t lvl_start[kMaxDepth + 3];   // first box of each level
     int32_t n_u, n_w, n_x;              // list lengths
+    int32_t n_far_a, n_far_b, n_near;   // leaf lists of the target-side kernels
+    int32_t n_far_a_lvl[kMaxDepth + 2]; // grid-operator leaves per level (segments of far_a)
     int32_t n_src_dropped;              // learned selector
     int32_t min_leafsrc_level;          // lowest level holding a leaf with sources
     int32_t fallback;                   // learned selector fell back to the threshold rule
@@ -91,6 +93,11 @@ struct Lists {
     uint32_t *u_off = nullptr, *w_off = nullptr, *x_off = nullptr;  // scanned counts
     int32_t *u = nullptr, *w = nullptr, *x = nullptr;
     int64_t u_cap = 0, w_cap = 0, x_cap = 0;
+    // leaves with targets (any order within a list): far field by a grid operator (a, in
+    // per-level segments at the level's box base) or by shell points (b), and the leaves with a
+    // non-empty U list (near field); box_cap entries each
+    int32_t *far_b = nullptr, *near_leaves = nullptr;
+    int4 *far_a = nullptr;  // (box, first target, target count, 1 near | 2 W list)
 };
 
 struct Gas {
@@ -183,7 +190,7 @@ struct Plan {
     void *d_scan_tmp = nullptr;     // scan partials
     size_t scan_tmp_bytes = 0;
     int32_t *d_s_pos = nullptr, *d_t_pos = nullptr;   // sorted positions of selected points
-    uint64_t *d_s_key = nullptr, *d_t_key = nullptr;  // their keys
+    int32_t *d_t_out = nullptr;     // caller index of each selected target (output position)
     void *d_s_dat = nullptr;        // sources: (x, y, z, q = w * I * 2^-e), float4 or double4
     void *d_t_dat = nullptr;        // targets: (x, y, z, self = c_self * I * 2^-e or 0)
     int32_t *d_s_cell = nullptr, *d_t_cell = nullptr; // packed cell indices (grid mode)
