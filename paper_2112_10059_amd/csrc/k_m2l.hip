@@ -189,94 +189,127 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
                                                           const T *__restrict__ Z)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= a.sc->lvl_count[level]) return;
-    const int32_t b = a.lt.base[level] + i;
-    if (a.bx.t_cnt[b] == 0) return;
     const int32_t ns = a.sc->lvl_src[level];
     const int32_t ncols = min(ccap, ns - r0);
-    if (!first && ncols <= 0) return;
+    if (!first && ncols <= 0) return;  // an empty chunk: the whole grid
     const int nl = a.n_lam;
-    const int32_t par = a.bx.parent[b];
-    T acc[kMaxLattice / 64];
     const int nk = (nl + 63) / 64;
-    for (int k = 0; k < kMaxLattice / 64; ++k) acc[k] = T(0);
-    unsigned long long n_m2l = 0, n_p2l = 0;
-    if (first) {
-        if (level >= 3) {
-            const int oct = ((a.bx.ax[b] & 1) << 2) | ((a.bx.ay[b] & 1) << 1) | (a.bx.az[b] & 1);
-            const T *z = Z + ((size_t)a.bx.tpar_rank[par] * 8 + oct) * nl;
-            for (int k = 0; k < nk; ++k) {
-                const int li = lane + 64 * k;
-                if (li < nl) acc[k] = z[li];
+    const int32_t nbox = a.sc->lvl_count[level];
+    for (int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nbox; i += gridDim.x * 4) {
+        const int32_t b = a.lt.base[level] + i;
+        if (a.bx.t_cnt[b] == 0) continue;
+        const int32_t par = a.bx.parent[b];
+        T acc[kMaxLattice / 64];
+        for (int k = 0; k < kMaxLattice / 64; ++k) acc[k] = T(0);
+        unsigned long long n_m2l = 0, n_p2l = 0;
+        if (first) {
+            if (level >= 3) {
+                const int oct = ((a.bx.ax[b] & 1) << 2) | ((a.bx.ay[b] & 1) << 1) | (a.bx.az[b] & 1);
+                const T *z = Z + ((size_t)a.bx.tpar_rank[par] * 8 + oct) * nl;
+                for (int k = 0; k < nk; ++k) {
+                    const int li = lane + 64 * k;
+                    if (li < nl) acc[k] = z[li];
+                }
             }
-        }
-        // X list: sources of coarser leaves straight onto the check points
-        const uint32_t x0 = a.L.x_off[b], x1 = a.L.x_off[b + 1];
-        if (x1 > x0) {
-            const double hw = a.lt.hw[level];
-            T cx, cy, cz;
-            box_centre(a, b, hw, cx, cy, cz);
-            const T h = (T)hw;
-            for (uint32_t e = x0; e < x1; ++e) {
-                const int32_t C = a.L.x[e];
-                const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
-                n_p2l += (unsigned long long)sn * nl;
-                for (int j = 0; j < sn; ++j) {
-                    const V4<T> y = a.s_dat[sf + j];
-                    for (int k = 0; k < nk; ++k) {
-                        const int li = lane + 64 * k;
-                        if (li >= nl) break;
-                        const T ddx = cx + h * a.lat[3 * li] - y.x, ddy = cy + h * a.lat[3 * li + 1] - y.y,
-                                ddz = cz + h * a.lat[3 * li + 2] - y.z;
-                        acc[k] += kernel_eval<true>(ddx * ddx + ddy * ddy + ddz * ddz, a.kp) * y.w;
+            // X list: sources of coarser leaves straight onto the check points
+            const uint32_t x0 = a.L.x_off[b], x1 = a.L.x_off[b + 1];
+            if (x1 > x0) {
+                const double hw = a.lt.hw[level];
+                T cx, cy, cz;
+                box_centre(a, b, hw, cx, cy, cz);
+                const T h = (T)hw;
+                for (uint32_t e = x0; e < x1; ++e) {
+                    const int32_t C = a.L.x[e];
+                    const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
+                    n_p2l += (unsigned long long)sn * nl;
+                    for (int j = 0; j < sn; ++j) {
+                        const V4<T> y = a.s_dat[sf + j];
+                        for (int k = 0; k < nk; ++k) {
+                            const int li = lane + 64 * k;
+                            if (li >= nl) break;
+                            const T ddx = cx + h * a.lat[3 * li] - y.x, ddy = cy + h * a.lat[3 * li + 1] - y.y,
+                                    ddz = cz + h * a.lat[3 * li + 2] - y.z;
+                            acc[k] += kernel_eval<true>(ddx * ddx + ddy * ddy + ddz * ddz, a.kp) * y.w;
+                        }
                     }
                 }
             }
+        } else {
+            for (int k = 0; k < nk; ++k) {
+                const int li = lane + 64 * k;
+                if (li < nl) acc[k] = a.u[(size_t)b * nl + li];
+            }
         }
-    } else {
-        for (int k = 0; k < nk; ++k) {
-            const int li = lane + 64 * k;
-            if (li < nl) acc[k] = a.u[(size_t)b * nl + li];
+        // V list candidates: the children of the parent's colleagues, in candidate order
+        // (colleague d, child o); only colleagues holding sources are expanded
+        const int bx0 = a.bx.ax[b], by0 = a.bx.ay[b], bz0 = a.bx.az[b];
+        int32_t Qd = -1;
+        if (lane < 27) {
+            const int32_t Q = a.bx.coll[(size_t)par * 27 + lane];
+            if (Q >= 0 && a.bx.s_cnt[Q] > 0) Qd = Q;
         }
-    }
-    const int bx0 = a.bx.ax[b], by0 = a.bx.ay[b], bz0 = a.bx.az[b];
-    for (int c0 = 0; c0 < 216; c0 += 64) {
-        const int c = c0 + lane;
-        int32_t code = -1;  // rank * 316 + slot
-        if (c < 216) {
-            const int32_t Q = a.bx.coll[(size_t)par * 27 + (c >> 3)];
-            const int32_t A = Q >= 0 ? a.bx.child[(size_t)Q * 8 + (c & 7)] : -1;
-            if (A >= 0) {
-                const int32_t rk = a.bx.src_rank[A] - r0;
-                if (a.bx.src_rank[A] >= 0 && rk >= 0 && rk < ncols) {
-                    const int dx = a.bx.ax[A] - bx0, dy = a.bx.ay[A] - by0, dz = a.bx.az[A] - bz0;
-                    if (!(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1))
-                        code = rk * kNumM2L + m2l_slot(dx, dy, dz);
+        const uint64_t qmask = __ballot(Qd >= 0);
+        const int nc = 8 * __popcll(qmask);
+        for (int f0 = 0; f0 < nc; f0 += 64) {
+            const int f = f0 + lane;
+            const bool valid = f < nc;
+            // colleague of flat candidate f: the (f / 8)-th colleague with sources
+            uint64_t m = qmask;
+            for (int j = valid ? (f >> 3) : 0; j > 0; --j) m &= m - 1;
+            const int d = m ? __ffsll((long long)m) - 1 : 0;
+            const int32_t Q = __shfl(Qd, d);  // every lane takes part
+            int32_t code = -1;              // rank * 316 + slot
+            if (valid) {
+                const int32_t A = a.bx.child[(size_t)Q * 8 + (f & 7)];
+                if (A >= 0) {
+                    const int32_t sr = a.bx.src_rank[A];
+                    const int32_t rk = sr - r0;
+                    if (sr >= 0 && rk >= 0 && rk < ncols) {
+                        const int dx = a.bx.ax[A] - bx0, dy = a.bx.ay[A] - by0, dz = a.bx.az[A] - bz0;
+                        if (!(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1))
+                            code = rk * kNumM2L + m2l_slot(dx, dy, dz);
+                    }
+                }
+            }
+            // four translations at a time: their loads issued together, then added in order
+            uint64_t mask = __ballot(code >= 0);
+            n_m2l += __popcll(mask);
+            while (mask) {
+                constexpr int kB = 4;
+                int32_t cd[kB];
+                int nb = 0;
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    cd[u] = -1;
+                    if (mask) {
+                        const int src_lane = __ffsll((long long)mask) - 1;
+                        mask &= mask - 1;
+                        cd[u] = __builtin_amdgcn_readlane(code, src_lane);
+                        ++nb;
+                    }
+                }
+                for (int k = 0; k < nk; ++k) {
+                    const int li = lane + 64 * k;
+                    T v[kB];
+#pragma unroll
+                    for (int u = 0; u < kB; ++u)
+                        v[u] = (u < nb && li < nl) ? Y[(size_t)(cd[u] / kNumM2L) * M + (size_t)(cd[u] % kNumM2L) * nl + li]
+                                                   : T(0);
+#pragma unroll
+                    for (int u = 0; u < kB; ++u)
+                        if (u < nb && li < nl) acc[k] += v[u];
                 }
             }
         }
-        uint64_t mask = __ballot(code >= 0);
-        while (mask) {
-            const int src_lane = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-            const int32_t cd = __builtin_amdgcn_readlane(code, src_lane);
-            ++n_m2l;
-            const T *y = Y + (size_t)(cd / kNumM2L) * M + (size_t)(cd % kNumM2L) * nl;
-            for (int k = 0; k < nk; ++k) {
-                const int li = lane + 64 * k;
-                if (li < nl) acc[k] += y[li];
-            }
+        for (int k = 0; k < nk; ++k) {
+            const int li = lane + 64 * k;
+            if (li < nl) a.u[(size_t)b * nl + li] = acc[k];
         }
-    }
-    for (int k = 0; k < nk; ++k) {
-        const int li = lane + 64 * k;
-        if (li < nl) a.u[(size_t)b * nl + li] = acc[k];
-    }
-    if (a.work && lane == 0) {
-        if (n_m2l) atomicAdd(&a.work[5], n_m2l);
-        if (n_p2l) atomicAdd(&a.work[4], n_p2l);
-        if (first && level >= 3) atomicAdd(&a.work[7], 1ull);
+        if (a.work && lane == 0) {
+            if (n_m2l) atomicAdd(&a.work[5], n_m2l);
+            if (n_p2l) atomicAdd(&a.work[4], n_p2l);
+            if (first && level >= 3) atomicAdd(&a.work[7], 1ull);
+        }
     }
 }
 
@@ -303,7 +336,8 @@ void fmm_downward_t(Plan &p, hipStream_t s)
         const T *Ml = (const T *)p.ops.m2l + (size_t)l * M * p.k_pad;
         for (int c = 0; c < nchunk; ++c) {
             const int32_t r0 = (int32_t)(c * ccap);
-            dim3 g((M + kTile - 1) / kTile, (unsigned)std::min<int64_t>(256, (ccap + kTile - 1) / kTile));
+            // a bounded grid striding over the column tiles: an empty chunk costs little
+            dim3 g((M + kTile - 1) / kTile, (unsigned)std::min<int64_t>(16, (ccap + kTile - 1) / kTile));
             if (std::is_same<T, float>::value && p.precision == PH_FP32_BF16SPLIT) {
                 const size_t off = (size_t)l * M * p.k_pad;
                 tgemm_m2l_bf16s_kernel<<<g, 256, 0, s>>>((const uint16_t *)p.ops.m2l_hi + off,
@@ -316,7 +350,7 @@ void fmm_downward_t(Plan &p, hipStream_t s)
                                                             &p.d_sc->lvl_src[l], (int32_t)p.level_base[l], r0,
                                                             (int32_t)ccap, nullptr, nullptr, nullptr, (T *)p.d_y);
             }
-            down_gather_kernel<T><<<(unsigned)((cap + 3) / 4), 256, 0, s>>>(a, l, (const T *)p.d_y, M, r0,
+            down_gather_kernel<T><<<(unsigned)std::min<int64_t>((cap + 3) / 4, 4096), 256, 0, s>>>(a, l, (const T *)p.d_y, M, r0,
                                                                              (int32_t)ccap, c == 0 ? 1 : 0,
                                                                              (const T *)p.d_z);
         }
