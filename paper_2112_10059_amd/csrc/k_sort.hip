@@ -145,88 +145,181 @@ __global__ void radix_scatter_kernel(const uint64_t *__restrict__ keys, const in
 }
 
 // ---------------------------------------------------------------- scan
+//
+// Exclusive scan in three passes over tiles of kScanTile elements (256 threads, 16 per thread):
+// tile sums, a scan of the tile sums, and the tile scans.  Inside a tile each wave owns a
+// contiguous quarter, read as 16 coalesced strips of 64 and scanned across lanes with shuffles;
+// the waves' totals are exchanged once through LDS.  Integer sums: the order does not matter.
 
 template <class T>
-__device__ T block_exclusive_scan(T v, T *smem, T &total)
+__device__ __forceinline__ T shfl_up_t(T v, int d)
 {
-    // Hillis-Steele over 256 values in shared memory
-    const int t = threadIdx.x;
-    smem[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        T x = (t >= off) ? smem[t - off] : T(0);
-        __syncthreads();
-        smem[t] += x;
-        __syncthreads();
+    if constexpr (sizeof(T) == 8) {
+        const uint32_t lo = __shfl_up((uint32_t)v, (unsigned)d), hi = __shfl_up((uint32_t)(v >> 32), (unsigned)d);
+        return ((T)hi << 32) | lo;
+    } else {
+        return (T)__shfl_up((uint32_t)v, (unsigned)d);
     }
-    total = smem[kBlock - 1];
-    T incl = smem[t];
-    __syncthreads();
-    return incl - v;
 }
 
 template <class T>
-__global__ void scan_reduce_kernel(const T *__restrict__ data, int64_t n, T *__restrict__ partial)
+__device__ __forceinline__ T lane_value(T v, int l)
 {
-    __shared__ T sm[kBlock];
-    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if constexpr (sizeof(T) == 8) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+        return ((T)hi << 32) | lo;
+    } else {
+        return (T)(uint32_t)__builtin_amdgcn_readlane((int)v, l);
+    }
+}
+
+// inclusive scan across the 64 lanes
+template <class T>
+__device__ __forceinline__ T wave_inclusive(T v, int lane)
+{
+    for (int d = 1; d < 64; d <<= 1) {
+        const T y = shfl_up_t(v, d);
+        if (lane >= d) v += y;
+    }
+    return v;
+}
+
+constexpr int kWaveSpan = kScanTile / 4;  // elements per wave in a tile
+
+template <class T>
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const T *__restrict__ data, int64_t n, T *__restrict__ partial)
+{
+    __shared__ T wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)w * kWaveSpan;
     T acc = 0;
-    for (int it = 0; it < kScanItems; ++it) {
-        int64_t i = base + (int64_t)it * kBlock + threadIdx.x;
+#pragma unroll
+    for (int st = 0; st < kWaveSpan / 64; ++st) {
+        const int64_t i = base + st * 64 + lane;
         if (i < n) acc += data[i];
     }
-    T tot;
-    block_exclusive_scan<T>(acc, sm, tot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+    acc = lane_value(wave_inclusive(acc, lane), 63);
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
+// one workgroup of 1024 threads: exclusive scan of the nb tile sums, total to *total
 template <class T>
-__global__ void scan_partials_kernel(T *__restrict__ partial, int64_t nb, T *__restrict__ total)
+__global__ __launch_bounds__(1024) void scan_partials_kernel(T *__restrict__ partial, int64_t nb, T *__restrict__ total)
 {
-    __shared__ T sm[kBlock];
+    __shared__ T wtot[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     T carry = 0;
-    for (int64_t base = 0; base < nb; base += kBlock) {
-        int64_t i = base + threadIdx.x;
-        T v = i < nb ? partial[i] : T(0);
-        T tot;
-        T ex = block_exclusive_scan<T>(v, sm, tot);
-        if (i < nb) partial[i] = carry + ex;
-        carry += tot;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const T v = i < nb ? partial[i] : T(0);
+        const T incl = wave_inclusive(v, lane);
+        __syncthreads();  // the previous strip's totals have been read
+        if (lane == 63) wtot[w] = incl;
+        __syncthreads();
+        T before = carry;
+        for (int q = 0; q < w; ++q) before += wtot[q];
+        if (i < nb) partial[i] = before + incl - v;
+        for (int q = 0; q < 16; ++q) carry += wtot[q];
     }
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
 template <class T>
-__global__ void scan_apply_kernel(T *__restrict__ data, int64_t n, const T *__restrict__ partial)
+__global__ __launch_bounds__(256) void scan_apply_kernel(T *__restrict__ data, int64_t n, const T *__restrict__ partial)
 {
-    __shared__ T sm[kBlock];
-    // each thread owns kScanItems consecutive elements
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    T loc[kScanItems];
+    __shared__ T wsum[4];
+    constexpr int kStrips = kWaveSpan / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)w * kWaveSpan;
+    T loc[kStrips];
     T acc = 0;
-    for (int it = 0; it < kScanItems; ++it) {
-        int64_t i = base + it;
-        loc[it] = i < n ? data[i] : T(0);
-        acc += loc[it];
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) {
+        const int64_t i = base + st * 64 + lane;
+        loc[st] = i < n ? data[i] : T(0);
+        acc += loc[st];
     }
-    T tot;
-    T ex = block_exclusive_scan<T>(acc, sm, tot) + partial[blockIdx.x];
-    for (int it = 0; it < kScanItems; ++it) {
-        int64_t i = base + it;
-        if (i < n) data[i] = ex;
-        ex += loc[it];
+    acc = lane_value(wave_inclusive(acc, lane), 63);
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    T carry = partial[blockIdx.x];
+    for (int q = 0; q < w; ++q) carry += wsum[q];
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) {
+        const T incl = wave_inclusive(loc[st], lane);
+        const int64_t i = base + st * 64 + lane;
+        if (i < n) data[i] = carry + incl - loc[st];
+        carry += lane_value(incl, 63);
     }
+}
+
+// Small arrays in one launch: one workgroup of 16 waves, wave w owning a contiguous range of
+// kSmallStrips strips of 64 held in registers (loads issued together).
+constexpr int kSmallStrips = 40;
+constexpr int64_t kSmallScan = 16 * 64 * kSmallStrips;
+
+template <class T>
+struct ScanJob {
+    T *data;
+    T *total;
+};
+
+// workgroup j scans array j of up to three (one launch for independent small scans)
+template <class T>
+__global__ __launch_bounds__(1024) void scan_small_kernel(ScanJob<T> j0, ScanJob<T> j1, ScanJob<T> j2, int64_t n)
+{
+    const ScanJob<T> job = blockIdx.x == 0 ? j0 : (blockIdx.x == 1 ? j1 : j2);
+    T *__restrict__ data = job.data;
+    T *__restrict__ total = job.total;
+    __shared__ T wsum[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t span = ((n + 16 * 64 - 1) / (16 * 64)) * 64;  // elements per wave, a multiple of 64
+    const int64_t base = (int64_t)w * span;
+    const int strips = (int)(span / 64);
+    T loc[kSmallStrips];
+    T acc = 0;
+#pragma unroll
+    for (int st = 0; st < kSmallStrips; ++st) {
+        const int64_t i = base + st * 64 + lane;
+        loc[st] = (st < strips && i < n) ? data[i] : T(0);
+        acc += loc[st];
+    }
+    acc = lane_value(wave_inclusive(acc, lane), 63);
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    T carry = 0;
+    for (int q = 0; q < w; ++q) carry += wsum[q];
+#pragma unroll
+    for (int st = 0; st < kSmallStrips; ++st) {
+        if (st < strips) {  // a guard, not a break: the strips stay in registers
+            const T incl = wave_inclusive(loc[st], lane);
+            const int64_t i = base + st * 64 + lane;
+            if (i < n) data[i] = carry + incl - loc[st];
+            carry += lane_value(incl, 63);
+        }
+    }
+    if (threadIdx.x == 1023 && total) *total = carry;
 }
 
 template <class T>
 void exclusive_scan(T *data, int64_t n, void *tmp, T *total, hipStream_t s)
 {
     if (n <= 0) return;
+    if constexpr (sizeof(T) == 4) {
+        if (n <= kSmallScan) {
+            const ScanJob<T> j{data, total};
+            scan_small_kernel<T><<<1, 1024, 0, s>>>(j, j, j, n);
+            return;
+        }
+    }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     T *partial = (T *)tmp;
-    scan_reduce_kernel<T><<<(unsigned)nb, kBlock, 0, s>>>(data, n, partial);
-    scan_partials_kernel<T><<<1, kBlock, 0, s>>>(partial, nb, total);
-    scan_apply_kernel<T><<<(unsigned)nb, kBlock, 0, s>>>(data, n, partial);
+    scan_reduce_kernel<T><<<(unsigned)nb, 256, 0, s>>>(data, n, partial);
+    scan_partials_kernel<T><<<1, 1024, 0, s>>>(partial, nb, total);
+    scan_apply_kernel<T><<<(unsigned)nb, 256, 0, s>>>(data, n, partial);
 }
 
 }  // namespace
@@ -245,6 +338,20 @@ void exclusive_scan_u32(uint32_t *data, int64_t n, void *tmp, uint32_t *total, h
 void exclusive_scan_u64(uint64_t *data, int64_t n, void *tmp, uint64_t *total, hipStream_t s)
 {
     exclusive_scan<uint64_t>(data, n, tmp, total, s);
+}
+
+void exclusive_scan3_u32(uint32_t *a, uint32_t *ta, uint32_t *b, uint32_t *tb, uint32_t *c, uint32_t *tc, int64_t n,
+                         void *tmp, hipStream_t s)
+{
+    if (n <= 0) return;
+    if (n <= kSmallScan) {
+        scan_small_kernel<uint32_t><<<3, 1024, 0, s>>>(ScanJob<uint32_t>{a, ta}, ScanJob<uint32_t>{b, tb},
+                                                       ScanJob<uint32_t>{c, tc}, n);
+        return;
+    }
+    exclusive_scan<uint32_t>(a, n, tmp, ta, s);
+    exclusive_scan<uint32_t>(b, n, tmp, tb, s);
+    exclusive_scan<uint32_t>(c, n, tmp, tc, s);
 }
 
 void launch_morton_keys(const double *xyz, int64_t n, double lo0, double lo1, double lo2, double size,

@@ -303,9 +303,9 @@ void build_lists(Plan &p, hipStream_t s)
             if (l < 2 || p.grid_m[l] > 0) grid_levels |= 1u << l;
     list_count_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels);
     // nbox + 1 entries: the last one (0 before the scan) receives the total
-    exclusive_scan_u32(p.lists.u_off, nbox + 1, p.d_scan_tmp, reinterpret_cast<uint32_t *>(&p.d_sc->n_u), s);
-    exclusive_scan_u32(p.lists.w_off, nbox + 1, p.d_scan_tmp, reinterpret_cast<uint32_t *>(&p.d_sc->n_w), s);
-    exclusive_scan_u32(p.lists.x_off, nbox + 1, p.d_scan_tmp, reinterpret_cast<uint32_t *>(&p.d_sc->n_x), s);
+    exclusive_scan3_u32(p.lists.u_off, reinterpret_cast<uint32_t *>(&p.d_sc->n_u), p.lists.w_off,
+                        reinterpret_cast<uint32_t *>(&p.d_sc->n_w), p.lists.x_off,
+                        reinterpret_cast<uint32_t *>(&p.d_sc->n_x), nbox + 1, p.d_scan_tmp, s);
     list_fill_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists);
 }
 

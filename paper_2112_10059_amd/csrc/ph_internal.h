@@ -252,6 +252,9 @@ size_t radix_sort_tmp_bytes(int64_t n);
 size_t scan_tmp_bytes(int64_t n, size_t elem);
 void exclusive_scan_u32(uint32_t *data, int64_t n, void *tmp, uint32_t *total, hipStream_t s);
 void exclusive_scan_u64(uint64_t *data, int64_t n, void *tmp, uint64_t *total, hipStream_t s);
+// three independent scans of n elements (totals nullable)
+void exclusive_scan3_u32(uint32_t *a, uint32_t *ta, uint32_t *b, uint32_t *tb, uint32_t *c, uint32_t *tc, int64_t n,
+                         void *tmp, hipStream_t s);
 void launch_gather_sorted(const double *xyz, const double *w, const int32_t *perm, int64_t n,
                           double *xyz_sorted, double *w_sorted, int32_t *iperm, hipStream_t s);
 
