@@ -66,20 +66,31 @@ def parse():
     return ap.parse_args()
 
 
-def time_steps(plan, I, E, steps, warmup, torch):
+def time_steps(plan, I, E, steps, warmup, torch, host=None):
+    """ms per call over `steps` calls (no per-phase events), then the per-phase times over as
+    many calls again with the phase events on.  host (a dict, optional) receives the host time
+    per call spent enqueueing the timed calls."""
     out = torch.empty(plan.n, dtype=plan.dtype, device="cuda")
     for _ in range(warmup):
         plan.evaluate(I, E, out=out)
     torch.cuda.synchronize()
-    plan.phase_times(record=1)  # discard, start recording
+    plan.phase_times(record=0)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
+    h0 = time.perf_counter()
     for _ in range(steps):
         plan.evaluate(I, E, out=out)
+    h1 = time.perf_counter()
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
+    if host is not None:
+        host["enqueue_ms_per_call"] = (h1 - h0) * 1e3 / steps
+    plan.phase_times(record=1)  # discard, start recording
+    for _ in range(steps):
+        plan.evaluate(I, E, out=out)
+    torch.cuda.synchronize()
     phases, ncalls = plan.phase_times(record=0)
     return out, ms, {k: v / max(ncalls, 1) for k, v in phases.items()}
 
@@ -130,10 +141,12 @@ def main():
     log(f"plan {args.precision} learned: {plan_ms:.1f} ms")
     _, st = plan.evaluate(I, E, stats=True)
     log(f"stats: {st}")
-    S, ms, phases = time_steps(plan, I, E, args.steps, args.warmup, torch)
+    host = {}
+    S, ms, phases = time_steps(plan, I, E, args.steps, args.warmup, torch, host=host)
     n_tgt = st["n_tgt"]
     value = n_tgt / (ms * 1e-3)
-    log(f"learned fp32: {ms:.4f} ms/step, {value:.4e} targets/s; phases {phases}")
+    log(f"learned fp32: {ms:.4f} ms/step, {value:.4e} targets/s; host enqueue {host['enqueue_ms_per_call']:.4f} "
+        f"ms/call; phases {phases}")
     roof = roofline(phases, st)
     perm = plan.debug_fetch("perm")
     smask = np.zeros(wl.n, dtype=bool)
@@ -215,6 +228,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "host_enqueue_ms_per_call": host["enqueue_ms_per_call"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

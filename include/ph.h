@@ -170,6 +170,11 @@ void ph_plan_destroy(ph_plan *plan);
  *         the counts and per-phase times, and reports PH_ENUMERIC if the device
  *         flagged a bad source value.  When NULL the call is fully asynchronous
  *         and a numeric fault is reported by the next ph_plan_check().
+ * The interaction lists, the near field and the far field of leaves without a
+ * small grid operator run on a stream the plan owns, forked from `stream` after
+ * the octree and joined back into it before the call's last phase ends (events,
+ * no host synchronisation), so the call stays ordered on `stream` and may be
+ * captured into a HIP graph.  Calls on one plan must not overlap.
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);
@@ -179,9 +184,11 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
  * summed hipEvent time of every call recorded since the previous query, per phase:
  *   0 maxima of I and |E|      1 learned selector (rows, features, network, drop mask)
  *   2 selection + compaction   3 octree        4 interaction lists
- *   5 upward pass (P2M, M2M)   6 downward pass (M2L, L2L, P2L)
- *   7 far field at the targets (L2P, M2P, own cell)
- *   8 near field (P2P) and the output, or the whole direct sum
+ *   5 upward pass (P2M, M2M)   6 downward pass (M2L, L2L, P2L; waits for the lists)
+ *   7 far field at the targets (L2P, M2P, own cell) and the output (waits for 8)
+ *   8 near field (P2P), or the whole direct sum
+ * Phases 4 and 8 run on the plan's second stream beside phases 5-7, so their
+ * times overlap those.
  * *n_calls (nullable) the number of calls.  The sums are then reset.  record = 1
  * turns recording on for every later ph_evaluate (events on the caller's stream,
  * no extra synchronisation), 0 turns it off, -1 leaves it unchanged.  Synchronous.

@@ -158,4 +158,40 @@ __device__ __forceinline__ uint64_t e_key(float e, int64_t i)
     return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
 }
 
+// ---------------------------------------------------------------- wave scans
+
+template <class T>
+__device__ __forceinline__ T shfl_up_t(T v, int d)
+{
+    if constexpr (sizeof(T) == 8) {
+        const uint32_t lo = __shfl_up((uint32_t)v, (unsigned)d), hi = __shfl_up((uint32_t)(v >> 32), (unsigned)d);
+        return ((T)hi << 32) | lo;
+    } else {
+        return (T)__shfl_up((uint32_t)v, (unsigned)d);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T lane_value(T v, int l)
+{
+    if constexpr (sizeof(T) == 8) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+        return ((T)hi << 32) | lo;
+    } else {
+        return (T)(uint32_t)__builtin_amdgcn_readlane((int)v, l);
+    }
+}
+
+// inclusive scan across the 64 lanes
+template <class T>
+__device__ __forceinline__ T wave_inclusive(T v, int lane)
+{
+    for (int d = 1; d < 64; d <<= 1) {
+        const T y = shfl_up_t(v, d);
+        if (lane >= d) v += y;
+    }
+    return v;
+}
+
 }  // namespace ph

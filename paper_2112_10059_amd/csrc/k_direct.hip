@@ -16,8 +16,7 @@ using V4 = typename Vec4T<T>::type;
 
 template <class T, class TO>
 __global__ __launch_bounds__(256) void direct_kernel(const V4<T> *__restrict__ s_dat, const V4<T> *__restrict__ t_dat,
-                                                     const int32_t *__restrict__ t_pos,
-                                                     const int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ t_out,
                                                      const CallScalars *__restrict__ sc, KParams<T> kp, double P,
                                                      TO *__restrict__ S_out, unsigned long long *work)
 {
@@ -54,7 +53,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const V4<T> *__restrict__ s
     }
     if (act) {
         const double tot = (double)s - (double)c + (double)x.w;
-        S_out[perm[t_pos[t]]] = (TO)(P * ldexp(tot, sc->scale_exp));
+        S_out[t_out[t]] = (TO)(P * ldexp(tot, sc->scale_exp));
     }
 }
 
@@ -66,12 +65,12 @@ void run_direct(Plan &p, void *S_out, hipStream_t s)
     const unsigned g = (unsigned)((p.n + 255) / 256);
     if (p.precision == PH_FP64)
         direct_kernel<double, double><<<g, 256, 0, s>>>((const double4 *)p.d_s_dat, (const double4 *)p.d_t_dat,
-                                                        p.d_t_pos, p.d_perm, p.d_sc, make_kparams<double>(p.gas),
+                                                        p.d_t_out, p.d_sc, make_kparams<double>(p.gas),
                                                         p.gas.P, (double *)S_out,
                                                         p.count_work ? p.d_sc->work : nullptr);
     else
-        direct_kernel<float, float><<<g, 256, 0, s>>>((const float4 *)p.d_s_dat, (const float4 *)p.d_t_dat, p.d_t_pos,
-                                                      p.d_perm, p.d_sc, make_kparams<float>(p.gas), p.gas.P,
+        direct_kernel<float, float><<<g, 256, 0, s>>>((const float4 *)p.d_s_dat, (const float4 *)p.d_t_dat, p.d_t_out,
+                                                      p.d_sc, make_kparams<float>(p.gas), p.gas.P,
                                                       (float *)S_out,
                                                       p.count_work ? p.d_sc->work : nullptr);
 }

@@ -23,84 +23,6 @@ namespace ph {
 
 namespace {
 
-// ---------------------------------------------------------------- P2M
-
-template <class T>
-__global__ void p2m_kernel(FmmArgs<T> a, int level)
-{
-  for (int32_t rk = blockIdx.x; rk < a.sc->lvl_src[level]; rk += gridDim.x) {
-    const int32_t b = a.bx.src_box[a.lt.base[level] + rk];
-    if (!(a.bx.flags[b] & kBoxLeaf) || a.bx.s_cnt[b] == 0) continue;
-    __shared__ V4<T> tile[128];
-    __shared__ T chk[kMaxShell];
-    __shared__ int32_t rloc[128];
-    const int32_t sf = a.bx.s_first[b], sn = a.bx.s_cnt[b];
-    const int gm = a.grid_m[level];
-    if (gm > 0) {
-        // grid box: phi = G q over the box's cells (G = uc2e K(shell, cells))
-        const T *G = a.grid_gt + a.grid_off[level];
-        T accg[4] = {0, 0, 0, 0};
-        for (int base = 0; base < sn; base += 128) {
-            const int m = min(128, sn - base);
-            __syncthreads();
-            if ((int)threadIdx.x < m) {
-                tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
-                rloc[threadIdx.x] = local_cell(a, a.s_cell[sf + base + threadIdx.x], b, gm);
-            }
-            __syncthreads();
-            for (int k = 0; k < 4; ++k) {
-                const int li = threadIdx.x + k * blockDim.x;
-                if (li >= a.n_lam) break;
-                T sacc = 0;
-                for (int j = 0; j < m; ++j) sacc += G[(size_t)rloc[j] * a.n_lam + li] * tile[j].w;
-                accg[k] += sacc;
-            }
-        }
-        for (int k = 0; k < 4; ++k) {
-            const int li = threadIdx.x + k * blockDim.x;
-            if (li < a.n_lam) a.phi[(size_t)b * a.n_lam + li] = accg[k];
-        }
-        if (a.work && threadIdx.x == 0) atomicAdd(&a.work[9], (unsigned long long)sn * a.n_lam);
-        continue;
-    }
-    const double hw = a.lt.hw[level];
-    T cx, cy, cz;
-    box_centre(a, b, hw, cx, cy, cz);
-    const T h = (T)hw;
-    T acc[4] = {0, 0, 0, 0};  // n_sig <= 4 * 128 check points per thread slot
-    for (int base = 0; base < sn; base += 128) {
-        const int m = min(128, sn - base);
-        __syncthreads();
-        if ((int)threadIdx.x < m) tile[threadIdx.x] = a.s_dat[sf + base + threadIdx.x];
-        __syncthreads();
-        for (int r = 0; r < 4; ++r) {
-            const int sg = threadIdx.x + r * 128;
-            if (sg >= a.n_sig) break;
-            const T px = cx + h * a.shell[3 * sg], py = cy + h * a.shell[3 * sg + 1], pz = cz + h * a.shell[3 * sg + 2];
-            T s = 0;
-            for (int j = 0; j < m; ++j) {
-                const V4<T> y = tile[j];
-                const T dx = px - y.x, dy = py - y.y, dz = pz - y.z;
-                s += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * y.w;
-            }
-            acc[r] += s;
-        }
-    }
-    for (int r = 0; r < 4; ++r) {
-        const int sg = threadIdx.x + r * 128;
-        if (sg < a.n_sig) chk[sg] = acc[r];
-    }
-    __syncthreads();
-    const T *U = a.uc2e_cm + (size_t)level * a.n_sig * a.n_lam;
-    for (int li = threadIdx.x; li < a.n_lam; li += blockDim.x) {
-        T s = 0;
-        for (int sg = 0; sg < a.n_sig; ++sg) s += U[(size_t)sg * a.n_lam + li] * chk[sg];
-        a.phi[(size_t)b * a.n_lam + li] = s;
-    }
-    if (a.work && threadIdx.x == 0) atomicAdd(&a.work[3], (unsigned long long)sn * a.n_sig);
-  }
-}
-
 // ---------------------------------------------------------------- leaf evaluation
 
 template <class T>
@@ -135,6 +57,187 @@ __device__ __forceinline__ double lane_bcast(double v, int j)
     const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), j);
     const int hi = __builtin_amdgcn_readlane((int)(u >> 32), j);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---------------------------------------------------------------- upward pass
+
+constexpr int kUpThreads = 256;
+constexpr int kUpGroups = kUpThreads / 64;
+
+// Artificial sources of source leaf b (Sec. 2.4): on a grid level, phi = G q with G the
+// level's lattice operator over the box's cells; elsewhere the sources' field at the check
+// shell, then the level's pseudo-inverse.  Wave g takes every kUpGroups-th source (or check
+// point) and the partial sums are added in wave order.
+static_assert(kMaxShell <= 2 * kUpThreads, "two check points per thread");
+
+template <class T>
+__device__ void p2m_box(const FmmArgs<T> &a, int32_t b, int level, V4<T> *tile, int32_t *rloc, T *chk,
+                        T (*part)[kMaxLattice])
+{
+    const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+    const int nl = a.n_lam, nk = (nl + 63) / 64;
+    const int32_t sf = a.bx.s_first[b], sn = a.bx.s_cnt[b];
+    const int gm = a.grid_m[level];
+    T acc[kMaxLattice / 64];
+#pragma unroll
+    for (int k = 0; k < kMaxLattice / 64; ++k) acc[k] = T(0);
+    if (gm > 0) {
+        const T *G = a.grid_gt + a.grid_off[level];  // [cell][lambda]
+        for (int base = 0; base < sn; base += 128) {
+            const int m = min(128, sn - base);
+            __syncthreads();
+            if (t < m) {
+                tile[t] = a.s_dat[sf + base + t];
+                rloc[t] = local_cell(a, a.s_cell[sf + base + t], b, gm);
+            }
+            __syncthreads();
+            for (int j = g; j < m; j += kUpGroups)
+#pragma unroll
+                for (int k = 0; k < kMaxLattice / 64; ++k) {
+                    const int li = lane + 64 * k;
+                    if (k < nk && li < nl) acc[k] += G[(size_t)rloc[j] * nl + li] * tile[j].w;
+                }
+        }
+        if (a.work && t == 0) atomicAdd(&a.work[9], (unsigned long long)sn * nl);
+    } else {
+        const double hw = a.lt.hw[level];
+        T cx, cy, cz;
+        box_centre(a, b, hw, cx, cy, cz);
+        const T h = (T)hw;
+        // n_sig <= kMaxShell <= 2 kUpThreads: check points t and t + kUpThreads
+        const bool own = t < a.n_sig, own2 = t + kUpThreads < a.n_sig;
+        T px = 0, py = 0, pz = 0, qx = 0, qy = 0, qz = 0, s = 0, s2 = 0;
+        if (own) {
+            px = cx + h * a.shell[3 * t];
+            py = cy + h * a.shell[3 * t + 1];
+            pz = cz + h * a.shell[3 * t + 2];
+        }
+        if (own2) {
+            const int u = t + kUpThreads;
+            qx = cx + h * a.shell[3 * u];
+            qy = cy + h * a.shell[3 * u + 1];
+            qz = cz + h * a.shell[3 * u + 2];
+        }
+        for (int base = 0; base < sn; base += 128) {
+            const int m = min(128, sn - base);
+            __syncthreads();
+            if (t < m) tile[t] = a.s_dat[sf + base + t];
+            __syncthreads();
+            if (own)
+                for (int j = 0; j < m; ++j) {
+                    const V4<T> y = tile[j];
+                    const T dx = px - y.x, dy = py - y.y, dz = pz - y.z;
+                    s += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * y.w;
+                }
+            if (own2)
+                for (int j = 0; j < m; ++j) {
+                    const V4<T> y = tile[j];
+                    const T dx = qx - y.x, dy = qy - y.y, dz = qz - y.z;
+                    s2 += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * y.w;
+                }
+        }
+        if (own) chk[t] = s;
+        if (own2) chk[t + kUpThreads] = s2;
+        __syncthreads();
+        const T *U = a.uc2e_cm + (size_t)level * a.n_sig * nl;  // [check point][lambda]
+        for (int sg = g; sg < a.n_sig; sg += kUpGroups)
+#pragma unroll
+            for (int k = 0; k < kMaxLattice / 64; ++k) {
+                const int li = lane + 64 * k;
+                if (k < nk && li < nl) acc[k] += U[(size_t)sg * nl + li] * chk[sg];
+            }
+        if (a.work && t == 0) atomicAdd(&a.work[3], (unsigned long long)sn * a.n_sig);
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxLattice / 64; ++k) {
+        const int li = lane + 64 * k;
+        if (k < nk && li < nl) part[g][li] = acc[k];
+    }
+    __syncthreads();
+    for (int li = t; li < nl; li += kUpThreads) {
+        T v = part[0][li];
+        for (int o = 1; o < kUpGroups; ++o) v += part[o][li];
+        a.phi[(size_t)b * nl + li] = v;
+    }
+}
+
+// P2M of every source leaf of levels >= 2 in one launch: the source boxes of those levels are
+// dealt to the workgroups as one flat range (boxes that are not leaves get their densities
+// from their children afterwards).
+template <class T>
+__global__ __launch_bounds__(kUpThreads) void p2m_kernel(FmmArgs<T> a, int depth)
+{
+    __shared__ V4<T> tile[128];
+    __shared__ int32_t rloc[128];
+    __shared__ T chk[kMaxShell];
+    __shared__ T part[kUpGroups][kMaxLattice];
+    for (int32_t idx = blockIdx.x;; idx += gridDim.x) {
+        int level = -1;
+        int32_t r = idx;
+        for (int l = 2; l <= depth; ++l) {
+            const int32_t c = a.sc->lvl_src[l];
+            if (r < c) {
+                level = l;
+                break;
+            }
+            r -= c;
+        }
+        if (level < 0) break;
+        const int32_t b = a.bx.src_box[a.lt.base[level] + r];
+        if (a.bx.flags[b] & kBoxLeaf) p2m_box(a, b, level, tile, rloc, chk, part);
+    }
+}
+
+// M2M for the split source boxes of one level when n_lam <= 64: one workgroup per parent, wave
+// g translating the children in octants g and g + 4 (lane = parent lattice index, the
+// operator of the child's octant read from L2), the translations summed in octant order.
+template <class T>
+__global__ __launch_bounds__(kUpThreads) void m2m_kernel(FmmArgs<T> a, int level)
+{
+    __shared__ T mpart[8][64];
+    __shared__ int32_t kids[8];
+    const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+    const int nl = a.n_lam;
+    for (int32_t rk = blockIdx.x; rk < a.sc->lvl_src[level]; rk += gridDim.x) {
+        const int32_t P = a.bx.src_box[a.lt.base[level] + rk];
+        if (a.bx.flags[P] & kBoxLeaf) continue;
+        __syncthreads();  // the previous parent's kids and partial sums have been read
+        if (t < 8) {
+            const int32_t C = a.bx.child[(size_t)P * 8 + t];
+            kids[t] = (C >= 0 && a.bx.s_cnt[C] > 0) ? C : -1;
+        }
+        __syncthreads();
+        for (int o = g; o < 8; o += kUpGroups) {
+            const int32_t C = kids[o];
+            T acc = T(0);
+            if (C >= 0) {
+                const T ph = lane < nl ? a.phi[(size_t)C * nl + lane] : T(0);
+                const T *op = a.l2l + ((size_t)(level + 1) * 8 + o) * nl * a.k_pad;  // [child j][parent i]
+                for (int j0 = 0; j0 < nl; j0 += 16) {
+                    T v[16];  // sixteen operator rows in flight, then added in order
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        v[u] = (lane < nl && j0 + u < nl) ? op[(size_t)(j0 + u) * a.k_pad + lane] : T(0);
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (j0 + u < nl) acc += v[u] * lane_bcast(ph, j0 + u);
+                }
+            }
+            mpart[o][lane] = acc;
+        }
+        __syncthreads();
+        if (t < nl) {
+            T v = T(0);
+            int nc = 0;
+            for (int o = 0; o < 8; ++o)
+                if (kids[o] >= 0) {
+                    v += mpart[o][t];
+                    ++nc;
+                }
+            a.phi[(size_t)P * nl + t] = v;
+            if (a.work && t == 0) atomicAdd(&a.work[6], (unsigned long long)nc);
+        }
+    }
 }
 
 // Output of a target whose sums are complete: S = P 2^e (far + near + own cell), in FP64.
@@ -206,13 +309,13 @@ __device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint
 // 16 x 64 x 64 product (wave j: the 16 x 16 tile of cells 16 j .. 16 j + 15,
 // v_mfma_f32_16x16x4_f32 over k), written back to LDS; then the 256 threads walk the
 // workgroup's targets in one flat range, their loads issued together, and finish them as the
-// wave kernel does (far = C[leaf][cell], W list, own cell, output or t_far).  Many small
+// wave kernel does (far = C[leaf][cell], W list, near field, own cell, output).  Many small
 // workgroups keep many dependent load chains in flight.
 constexpr int kFarMLeaves = 16;
 
 template <class TO>
 __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__restrict__ S_out,
-                                                       float *__restrict__ t_far, uint32_t level_mask)
+                                                       const double *__restrict__ t_near, uint32_t level_mask)
 {
     __shared__ float Us[kFarMLeaves][65];  // U, then C = U G
     __shared__ float Gs[64][65];
@@ -313,8 +416,8 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
                 }
             }
         }
-        if (lnear[qq]) t_far[kk] = far;
-        else S_out[ot] = (TO)(a.P * ldexp((double)far + (double)xx.w, scale_exp));
+        const double tot = (double)far + (lnear[qq] ? t_near[kk] : 0.0) + (double)xx.w;
+        S_out[ot] = (TO)(a.P * ldexp(tot, scale_exp));
     };
 #pragma unroll
     for (int u = 0; u < kU; ++u)
@@ -347,8 +450,8 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
 // workgroup takes up to kFarLeaves leaves of one level (the list's per-level segments), stages
 // that level's operator G_l (n_lam x m^3) in LDS once, and gives one wave per leaf:
 // far(t) = sum_li G_l[li][cell(t)] u[li], with the leaf's u in registers (lane li of slot k
-// holds u[64 k + li]) broadcast lane by lane, plus the W list and the own-cell term.  Leaves
-// without near sources are finished here; the others leave their far field in t_far.
+// holds u[64 k + li]) broadcast lane by lane, plus the W list, the near field of leaves with a
+// U list (computed beforehand) and the own-cell term, which gives the output.
 constexpr int kFarLeaves = 4;      // leaves per workgroup: one per wave, all in flight at once
 constexpr int kGridStage = 8192;   // operator entries staged in LDS (larger operators stay in L2)
 
@@ -366,7 +469,8 @@ __device__ __forceinline__ T grid_far(const T *__restrict__ G, int R, int nl, in
 }
 
 template <class T, class TO, int NK>
-__global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far,
+__global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
+                                                       const double *__restrict__ t_near,
                                                        int stage_cap, uint32_t level_mask)
 {
     extern __shared__ __align__(16) unsigned char far_lds[];  // stage_cap operator entries
@@ -438,10 +542,9 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
                 far = staged ? grid_far<T, NK, true>(Gs, R, nl, r, uv) : grid_far<T, NK, false>(G, R, nl, r, uv);
             }
             if (has_w) far += w_list_far<T, NK>(a, b, x, act, lane);
-            if (act) {
-                if (near) t_far[tf + t] = far;
-                else put_output(S_out, a.t_out, tf + t, a.P, (double)far + (double)x.w, scale_exp);
-            }
+            if (act)
+                put_output(S_out, a.t_out, tf + t, a.P, (double)far + (near ? t_near[tf + t] : 0.0) + (double)x.w,
+                           scale_exp);
         }
     }
 }
@@ -450,7 +553,7 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
 // one workgroup per leaf over the list: the leaf's check values give the intensities of its
 // shell points, which are then evaluated at every target; plus the W list and the own cell.
 template <class T, class TO>
-__global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__restrict__ t_far)
+__global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const double *__restrict__ t_near)
 {
     __shared__ T uvec[kMaxLattice];
     __shared__ T wphi[kMaxLattice];
@@ -524,10 +627,9 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__rest
                         far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * wphi[li];
                     }
             }
-            if (act) {
-                if (u1 > u0) t_far[tf + t] = far;
-                else put_output(S_out, a.t_out, tf + t, a.P, (double)far + (double)x.w, scale_exp);
-            }
+            if (act)
+                put_output(S_out, a.t_out, tf + t, a.P, (double)far + (u1 > u0 ? t_near[tf + t] : 0.0) + (double)x.w,
+                           scale_exp);
         }
     }
 }
@@ -536,18 +638,18 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, T *__rest
 // kNearWaves waves per leaf over the list.  The leaf's work items are (U entry, chunk of 64
 // of its sources), dealt to the waves in turn; each wave keeps a Kahan-compensated FP32 sum
 // (FP64 in the FP64 form) per target with the sources broadcast lane by lane from
-// registers.  The partial sums, the far field and the own-cell term are combined in FP64
-// in wave order, so the result does not depend on scheduling.
+// registers.  The partial sums are combined in FP64 in wave order (so the result does not
+// depend on scheduling) into t_near, which the far-field kernels add to the far field and
+// the own-cell term.  The kernel reads only the tree and the lists, so it can run beside
+// the upward and downward passes.
 constexpr int kNearWaves = 16;
 
-template <class T, class TO, bool GUARD>
-__global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
-                                                               const T *__restrict__ t_far)
+template <class T, bool GUARD>
+__global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, double *__restrict__ t_near)
 {
     __shared__ double part[kNearWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t n = a.sc->n_near;
-    const int scale_exp = a.sc->scale_exp;
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
         const int32_t b = a.L.near_leaves[idx];
         const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
@@ -582,9 +684,9 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, TO 
             part[w][lane] = near.value();
             __syncthreads();
             if (w == 0 && act) {
-                double tot = (double)t_far[tf + t];
+                double tot = 0.0;
                 for (int q = 0; q < kNearWaves; ++q) tot += part[q][lane];
-                put_output(S_out, a.t_out, tf + t, a.P, tot + (double)x.w, scale_exp);
+                t_near[tf + t] = tot;
             }
         }
     }
@@ -595,14 +697,22 @@ void fmm_upward_t(Plan &p, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int D = p.max_depth;
-    const int threads = std::max(128, ((p.n_lam + 63) / 64) * 64);
-    for (int l = 2; l <= D; ++l)
-        p2m_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 4096), 128, 0, s>>>(a, l);
-    for (int l = D - 1; l >= 2; --l) fmm_m2m_level(p, l, s);
+    int64_t cap = 0;
+    for (int l = 2; l <= D; ++l) cap += p.level_cap[l];
+    if (cap == 0) return;
+    p2m_kernel<T><<<(unsigned)std::min<int64_t>(cap, 4096), kUpThreads, 0, s>>>(a, D);
+    for (int l = D - 1; l >= 2; --l) {
+        // a direct product per parent for small lattices; the level GEMM (all eight octant
+        // translations of every child, on the matrix cores) for large ones
+        if (p.n_lam <= 64)
+            m2m_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 2048), kUpThreads, 0, s>>>(a, l);
+        else
+            fmm_m2m_level(p, l, s);
+    }
 }
 
 template <class T>
-void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
+void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
 {
     FmmArgs<T> a = make_args<T>(p);
     // upper bounds on the list lengths (the counts are on the device)
@@ -623,7 +733,7 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
         }
         if (gm_blocks > 0 && std::is_same<T, float>::value)
             far_mfma_kernel<float><<<(unsigned)gm_blocks, 256, 0, s>>>(*reinterpret_cast<FmmArgs<float> *>(&a),
-                                                                       (float *)S_out, (float *)p.d_t_far,
+                                                                       (float *)S_out, p.d_t_near,
                                                                        mfma_levels);
         if (gw_blocks > 0) {
             // LDS for the largest level operator that fits the staging cap
@@ -634,12 +744,13 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
             }
             const size_t lds = (size_t)cap * sizeof(T);
             const unsigned g = (unsigned)gw_blocks;
+            hipStream_t sg = std::is_same<T, float>::value ? s_aux : s;  // beside the matrix-core kernel
             switch ((p.n_lam + 63) / 64) {
-            case 1: far_grid_kernel<T, T, 1><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
-            case 2: far_grid_kernel<T, T, 2><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
+            case 1: far_grid_kernel<T, T, 1><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
+            case 2: far_grid_kernel<T, T, 2><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
             case 3:
-            case 4: far_grid_kernel<T, T, 4><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
-            default: far_grid_kernel<T, T, 8><<<g, 256, lds, s>>>(a, (T *)S_out, (T *)p.d_t_far, cap, wave_levels); break;
+            case 4: far_grid_kernel<T, T, 4><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
+            default: far_grid_kernel<T, T, 8><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
             }
         }
     }
@@ -647,19 +758,19 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s)
     bool shell_leaves = !p.grid_mode;
     for (int l = 2; l <= p.max_depth; ++l) shell_leaves = shell_leaves || p.grid_m[l] == 0;
     if (shell_leaves)
-        far_shell_kernel<T, T><<<(unsigned)std::min<int64_t>(B, p.grid_mode ? 256 : 4096), 64, 0, s>>>(
-            a, (T *)S_out, (T *)p.d_t_far);
+        far_shell_kernel<T, T><<<(unsigned)std::min<int64_t>(B, p.grid_mode ? 256 : 4096), 64, 0, s_aux>>>(
+            a, (T *)S_out, p.d_t_near);
 }
 
 template <class T>
-void fmm_near_t(Plan &p, void *S_out, hipStream_t s)
+void fmm_near_t(Plan &p, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
-    const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 1024);
-    if (p.near_guard)
-        near_kernel<T, T, true><<<g, 64 * kNearWaves, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
-    else
-        near_kernel<T, T, false><<<g, 64 * kNearWaves, 0, s>>>(a, (T *)S_out, (const T *)p.d_t_far);
+    // one workgroup (16 waves) per CU at most: the upward and downward passes run beside this
+    // kernel on the other stream, and a full grid would hold every wave slot until it drains
+    const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 256);
+    if (p.near_guard) near_kernel<T, true><<<g, 64 * kNearWaves, 0, s>>>(a, p.d_t_near);
+    else near_kernel<T, false><<<g, 64 * kNearWaves, 0, s>>>(a, p.d_t_near);
 }
 
 }  // namespace
@@ -670,16 +781,16 @@ void fmm_upward(Plan &p, hipStream_t s)
     else fmm_upward_t<float>(p, s);
 }
 
-void fmm_leaf(Plan &p, void *S_out, hipStream_t s)
+void fmm_leaf(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
 {
-    if (p.precision == PH_FP64) fmm_leaf_t<double>(p, S_out, s);
-    else fmm_leaf_t<float>(p, S_out, s);
+    if (p.precision == PH_FP64) fmm_leaf_t<double>(p, S_out, s, s_aux);
+    else fmm_leaf_t<float>(p, S_out, s, s_aux);
 }
 
-void fmm_near(Plan &p, void *S_out, hipStream_t s)
+void fmm_near(Plan &p, hipStream_t s)
 {
-    if (p.precision == PH_FP64) fmm_near_t<double>(p, S_out, s);
-    else fmm_near_t<float>(p, S_out, s);
+    if (p.precision == PH_FP64) fmm_near_t<double>(p, s);
+    else fmm_near_t<float>(p, s);
 }
 
 }  // namespace ph

@@ -17,7 +17,6 @@ struct FmmArgs {
     const CallScalars *sc;
     const V4<T> *s_dat;
     const V4<T> *t_dat;
-    const int32_t *t_pos;
     const int32_t *t_out;  // caller index of each selected target
     const int32_t *perm;
     const T *uc2e_rm;   // levels x n_lam x n_sig
@@ -38,6 +37,7 @@ struct FmmArgs {
     int grid_m[kMaxDepth + 2];
     int64_t grid_off[kMaxDepth + 2];
     int n_lam, n_sig;
+    int k_pad;  // padded row length of the stacked translation operators
     double lo0, lo1, lo2;
     double P;
 };
@@ -71,7 +71,6 @@ inline FmmArgs<T> make_args(Plan &p)
     a.sc = p.d_sc;
     a.s_dat = (const V4<T> *)p.d_s_dat;
     a.t_dat = (const V4<T> *)p.d_t_dat;
-    a.t_pos = p.d_t_pos;
     a.t_out = p.d_t_out;
     a.perm = p.d_perm;
     a.uc2e_rm = (const T *)p.ops.uc2e_rm;
@@ -94,6 +93,7 @@ inline FmmArgs<T> make_args(Plan &p)
     }
     a.n_lam = p.n_lam;
     a.n_sig = p.n_sig;
+    a.k_pad = p.k_pad;
     a.lo0 = p.cube_lo[0];
     a.lo1 = p.cube_lo[1];
     a.lo2 = p.cube_lo[2];

@@ -26,50 +26,92 @@ constexpr int kPad = 4;       // LDS row padding (bank spread)
 
 enum { kModeM2L = 0, kModeL2L = 1, kModeM2M = 2 };
 
+// One level's part of a translation GEMM: the columns are the boxes list[list_base + r0 + n],
+// n < min(ccap, count[count_idx] - r0); the operator starts op_off elements in; column n
+// goes to row out_row + n of the output.
+struct GemmSeg {
+    int32_t count_idx, list_base, r0, ccap;
+    int64_t op_off, out_row;
+};
+struct GemmSegs {
+    int n;
+    GemmSeg s[kMaxDepth + 1];
+};
+
+// Column tile `tile` of the segments taken in order: its segment and first column, or false
+__device__ __forceinline__ bool seg_tile(const GemmSegs &sg, const int32_t *__restrict__ count, int32_t tile,
+                                         int &si, int32_t &n0, int32_t &ncols)
+{
+    for (si = 0; si < sg.n; ++si) {
+        ncols = max(0, min(sg.s[si].ccap, count[sg.s[si].count_idx] - sg.s[si].r0));
+        const int32_t nt = (ncols + kTile - 1) / kTile;
+        if (tile < nt) {
+            n0 = tile * kTile;
+            return true;
+        }
+        tile -= nt;
+    }
+    return false;
+}
+
 // Translation GEMM on the matrix cores, out^T = X^T Op^T with Op (M x kp, row-major) a
-// stacked translation operator and X (kp x ncols) the gathered columns
-//   X[:, n] = vec of the n-th listed box of the level (rank r0 + n), out[n][m] row per box:
+// stacked translation operator and X (kp x ncols) the gathered columns, over one or more
+// levels (segments) in one launch:
+//   X[:, n] = vec of the n-th listed box of the segment, out[n][m] row per box:
 //   M2L: phi of the boxes with sources, Op = 316 stacked offsets   -> Y
-//   L2L: u of the split boxes with targets, Op = 8 stacked octants -> Z (parent to child c)
+//   L2L: u of the split boxes with targets, Op = 8 stacked octants -> u of child c
 //   M2M: phi of the boxes with sources, Op = 8 stacked octants     -> Z (child c to parent)
 template <class T, int MODE>
-__global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op, int kp, int M, int nl,
+__global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, int kp, int M, int nl,
                                                     const T *__restrict__ vec, const int32_t *__restrict__ list,
-                                                    const int32_t *__restrict__ count, int32_t lvl_base, int32_t r0,
-                                                    int32_t ccap, const int32_t *__restrict__ child,
-                                                    const int32_t *__restrict__ s_cnt, const int32_t *__restrict__ flags,
-                                                    T *__restrict__ out)
+                                                    const int32_t *__restrict__ count, GemmSegs segs,
+                                                    T *__restrict__ out0, const int32_t *__restrict__ child,
+                                                    const int32_t *__restrict__ t_cnt,
+                                                    unsigned long long *__restrict__ work)
 {
-    __shared__ T As[kTK][kTile + kPad];  // X^T tile, k-major
-    __shared__ T Bs[kTK][kTile + kPad];  // Op^T tile, k-major
+    // K staged 64 deep for FP32 (one LDS fill when n_lam <= 64), 32 for FP64
+    constexpr int KT = sizeof(T) == 4 ? 2 * kTK : kTK;
+    __shared__ T As[KT][kTile + kPad];  // X^T tile, k-major
+    __shared__ T Bs[KT][kTile + kPad];  // Op^T tile, k-major
     __shared__ int32_t boxes[kTile];
-    const int32_t ncols = min(ccap, *count - r0);
+    __shared__ int32_t kid[MODE == kModeL2L ? kTile : 1][8];  // L2L: children of the column boxes
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wn = w >> 1, wm = w & 1;
     using acc_t = typename Mfma<T>::acc_t;
-    // blockIdx.y strides over the tiles of columns (a bounded grid for any count)
-    for (int n0 = blockIdx.y * kTile; n0 < ncols; n0 += gridDim.y * kTile) {
+    // blockIdx.y strides over the column tiles of all segments (a bounded grid for any count)
+    for (int32_t tile = blockIdx.y;; tile += gridDim.y) {
+        int si;
+        int32_t n0, ncols;
+        if (!seg_tile(segs, count, tile, si, n0, ncols)) break;
+        const GemmSeg sg = segs.s[si];
+        const T *Op = Op0 + sg.op_off;
+        T *out = out0 + (size_t)sg.out_row * M;
         __syncthreads();
-        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[lvl_base + r0 + n0 + t] : -1;
+        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         acc_t acc[2][2];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-        for (int k0 = 0; k0 < kp; k0 += kTK) {
+        for (int k0 = 0; k0 < kp; k0 += KT) {
             __syncthreads();
-            for (int e = t; e < kTK * kTile; e += 256) {
-                const int n = e / kTK, k = e % kTK;
+            if (MODE == kModeL2L && k0 == 0)
+                for (int e = t; e < kTile * 8; e += 256) {
+                    const int32_t bx = boxes[e >> 3];
+                    kid[e >> 3][e & 7] = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
+                }
+            for (int e = t; e < KT * kTile; e += 256) {
+                const int n = e / KT, k = e % KT;
                 const int gk = k0 + k;
                 const int32_t bx = boxes[n];
                 T v = T(0);
                 if (bx >= 0 && gk < nl) v = vec[(size_t)bx * nl + gk];
                 As[k][n] = v;
                 const int gm = m0 + n;
-                Bs[k][n] = gm < M ? Op[(size_t)gm * kp + gk] : T(0);
+                Bs[k][n] = (gm < M && gk < kp) ? Op[(size_t)gm * kp + gk] : T(0);
             }
             __syncthreads();
 #pragma unroll
-            for (int ks = 0; ks < kTK; ks += 4) {
+            for (int ks = 0; ks < KT; ks += 4) {
                 const int kk = ks + (lane >> 4);
                 T a[2], b[2];
                 for (int i = 0; i < 2; ++i) a[i] = As[kk][wn * 32 + i * 16 + (lane & 15)];
@@ -85,7 +127,16 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op, in
                     const int nl_ = wn * 32 + i * 16 + Mfma<T>::row(lane, r);
                     const int gn = n0 + nl_;
                     if (gn >= ncols || gm >= M) continue;
-                    out[(size_t)gn * M + gm] = acc[i][j][r];
+                    if (MODE == kModeL2L) {
+                        // row c n_lam + li is the check potential li of child c: straight into its u
+                        const int c = gm / nl, li = gm - c * nl;
+                        const int32_t C = kid[nl_][c];
+                        if (C < 0) continue;
+                        out0[(size_t)C * nl + li] = acc[i][j][r];
+                        if (work && li == 0 && t_cnt[C] > 0) atomicAdd(&work[7], 1ull);
+                    } else {
+                        out[(size_t)gn * M + gm] = acc[i][j][r];
+                    }
                 }
             }
     }
@@ -109,23 +160,28 @@ __device__ __forceinline__ uint16_t bf16_rne(float x)
     return (uint16_t)(u >> 16);
 }
 
-__global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__restrict__ Oh,
-                                                              const uint16_t *__restrict__ Ol, int kp, int M,
+__global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__restrict__ Oh0,
+                                                              const uint16_t *__restrict__ Ol0, int kp, int M,
                                                               int nl, const float *__restrict__ vec,
                                                               const int32_t *__restrict__ list,
-                                                              const int32_t *__restrict__ count, int32_t lvl_base,
-                                                              int32_t r0, int32_t ccap, float *__restrict__ out)
+                                                              const int32_t *__restrict__ count, GemmSegs segs,
+                                                              float *__restrict__ out0)
 {
     __shared__ __align__(16) uint16_t Ah[kTile][kTK + kPadB], Al[kTile][kTK + kPadB];
     __shared__ __align__(16) uint16_t Bh[kTile][kTK + kPadB], Bl[kTile][kTK + kPadB];
     __shared__ int32_t boxes[kTile];
-    const int32_t ncols = min(ccap, *count - r0);
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wn = w >> 1, wm = w & 1;
-    for (int n0 = blockIdx.y * kTile; n0 < ncols; n0 += gridDim.y * kTile) {
+    for (int32_t tile = blockIdx.y;; tile += gridDim.y) {
+        int si;
+        int32_t n0, ncols;
+        if (!seg_tile(segs, count, tile, si, n0, ncols)) break;
+        const GemmSeg sg = segs.s[si];
+        const uint16_t *Oh = Oh0 + sg.op_off, *Ol = Ol0 + sg.op_off;
+        float *out = out0 + (size_t)sg.out_row * M;
         __syncthreads();
-        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[lvl_base + r0 + n0 + t] : -1;
+        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         f32x4 acc[2][2];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
@@ -178,39 +234,37 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
     }
 }
 
-// One wave per target box B (four per workgroup):
-//   u_B = [first chunk: Z(parent, octant of B) + X-list sources of B] + sum over V(B) in this chunk of Y.
-// V(B) = children of the parent's colleagues not adjacent to B: each lane resolves one of the
-// 216 candidates, a ballot marks those with sources in this chunk, and the wave walks the
-// set bits in candidate order, broadcasting rank and offset slot from the owning lane.
+// One workgroup per target box B:
+//   u_B = base + [first chunk: X-list sources of B] + sum over V(B) in this chunk of Y,
+// base = 0 on level 2 in the first chunk, else the current u_B (the parent's expansion
+// translated by the L2L product, plus earlier chunks).  V(B) = children of the parent's
+// colleagues not adjacent to B: the 8 x (colleagues with sources) candidates are dealt to the
+// four waves in 64-candidate slices (lane = candidate; a ballot marks those with sources in
+// this chunk) and each wave walks its set bits in candidate order, kB translations in flight;
+// the X list is dealt to the waves in turn.  The waves' partial sums are added to the base in
+// wave order.  boxes == nullptr: every box of the level, else the listed ones.
 template <class T>
 __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int level, const T *__restrict__ Y, int M,
-                                                          int32_t r0, int32_t ccap, int first,
-                                                          const T *__restrict__ Z)
+                                                          int32_t r0, int32_t ccap, int init, int with_x,
+                                                          const int32_t *__restrict__ boxes,
+                                                          const int32_t *__restrict__ n_boxes)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ T part[4][kMaxLattice];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t ns = a.sc->lvl_src[level];
     const int32_t ncols = min(ccap, ns - r0);
-    if (!first && ncols <= 0) return;  // an empty chunk: the whole grid
+    if (!with_x && ncols <= 0) return;  // an empty chunk: the whole grid
     const int nl = a.n_lam;
     const int nk = (nl + 63) / 64;
-    const int32_t nbox = a.sc->lvl_count[level];
-    for (int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nbox; i += gridDim.x * 4) {
-        const int32_t b = a.lt.base[level] + i;
+    const int32_t nbox = boxes ? *n_boxes : a.sc->lvl_count[level];
+    for (int32_t i = blockIdx.x; i < nbox; i += gridDim.x) {
+        const int32_t b = boxes ? boxes[i] : a.lt.base[level] + i;
         if (a.bx.t_cnt[b] == 0) continue;
         const int32_t par = a.bx.parent[b];
         T acc[kMaxLattice / 64];
         for (int k = 0; k < kMaxLattice / 64; ++k) acc[k] = T(0);
         unsigned long long n_m2l = 0, n_p2l = 0;
-        if (first) {
-            if (level >= 3) {
-                const int oct = ((a.bx.ax[b] & 1) << 2) | ((a.bx.ay[b] & 1) << 1) | (a.bx.az[b] & 1);
-                const T *z = Z + ((size_t)a.bx.tpar_rank[par] * 8 + oct) * nl;
-                for (int k = 0; k < nk; ++k) {
-                    const int li = lane + 64 * k;
-                    if (li < nl) acc[k] = z[li];
-                }
-            }
+        if (with_x) {
             // X list: sources of coarser leaves straight onto the check points
             const uint32_t x0 = a.L.x_off[b], x1 = a.L.x_off[b + 1];
             if (x1 > x0) {
@@ -218,7 +272,7 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
                 T cx, cy, cz;
                 box_centre(a, b, hw, cx, cy, cz);
                 const T h = (T)hw;
-                for (uint32_t e = x0; e < x1; ++e) {
+                for (uint32_t e = x0 + w; e < x1; e += 4) {
                     const int32_t C = a.L.x[e];
                     const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
                     n_p2l += (unsigned long long)sn * nl;
@@ -234,11 +288,6 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
                     }
                 }
             }
-        } else {
-            for (int k = 0; k < nk; ++k) {
-                const int li = lane + 64 * k;
-                if (li < nl) acc[k] = a.u[(size_t)b * nl + li];
-            }
         }
         // V list candidates: the children of the parent's colleagues, in candidate order
         // (colleague d, child o); only colleagues holding sources are expanded
@@ -250,7 +299,7 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
         }
         const uint64_t qmask = __ballot(Qd >= 0);
         const int nc = 8 * __popcll(qmask);
-        for (int f0 = 0; f0 < nc; f0 += 64) {
+        for (int f0 = 64 * w; f0 < nc; f0 += 256) {
             const int f = f0 + lane;
             const bool valid = f < nc;
             // colleague of flat candidate f: the (f / 8)-th colleague with sources
@@ -271,11 +320,11 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
                     }
                 }
             }
-            // four translations at a time: their loads issued together, then added in order
+            // kB translations at a time: their loads issued together, then added in order
             uint64_t mask = __ballot(code >= 0);
             n_m2l += __popcll(mask);
             while (mask) {
-                constexpr int kB = 4;
+                constexpr int kB = sizeof(T) == 4 ? 16 : 8;
                 int32_t cd[kB];
                 int nb = 0;
 #pragma unroll
@@ -303,56 +352,96 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
         }
         for (int k = 0; k < nk; ++k) {
             const int li = lane + 64 * k;
-            if (li < nl) a.u[(size_t)b * nl + li] = acc[k];
+            if (li < nl) part[w][li] = acc[k];
         }
+        __syncthreads();
+        for (int li = threadIdx.x; li < nl; li += 256) {
+            T v = init ? T(0) : a.u[(size_t)b * nl + li];
+            for (int q = 0; q < 4; ++q) v += part[q][li];
+            a.u[(size_t)b * nl + li] = v;
+        }
+        __syncthreads();  // part is free for the next box
         if (a.work && lane == 0) {
             if (n_m2l) atomicAdd(&a.work[5], n_m2l);
             if (n_p2l) atomicAdd(&a.work[4], n_p2l);
-            if (first && level >= 3) atomicAdd(&a.work[7], 1ull);
         }
     }
 }
 
+GemmSegs one_seg(int32_t count_idx, int64_t list_base, int64_t r0, int64_t ccap, int64_t op_off, int64_t out_row)
+{
+    GemmSegs sg{};
+    sg.n = 1;
+    sg.s[0] = GemmSeg{count_idx, (int32_t)list_base, (int32_t)r0, (int32_t)ccap, op_off, out_row};
+    return sg;
+}
+
+// Y = M2L products of the segments' source boxes (FP32 / FP64 operator, or its split-BF16 form)
 template <class T>
-void fmm_downward_t(Plan &p, hipStream_t s)
+void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
+{
+    const int nl = p.n_lam, M = kNumM2L * nl;
+    // a bounded grid striding over the column tiles: an empty segment costs little
+    dim3 g((M + kTile - 1) / kTile, (unsigned)std::max<int64_t>(1, std::min<int64_t>(16, col_tiles)));
+    if (std::is_same<T, float>::value && p.precision == PH_FP32_BF16SPLIT)
+        tgemm_m2l_bf16s_kernel<<<g, 256, 0, s>>>((const uint16_t *)p.ops.m2l_hi, (const uint16_t *)p.ops.m2l_lo,
+                                                 p.k_pad, M, nl, (const float *)p.d_phi, p.box.src_box,
+                                                 p.d_sc->lvl_src, sg, (float *)p.d_y);
+    else
+        tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>((const T *)p.ops.m2l, p.k_pad, M, nl, (const T *)p.d_phi,
+                                                    p.box.src_box, p.d_sc->lvl_src, sg, (T *)p.d_y, nullptr,
+                                                    nullptr, nullptr);
+}
+
+template <class T>
+void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t lists_ready)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int nl = p.n_lam;
     const int M = kNumM2L * nl;
-    for (int l = 2; l <= p.max_depth; ++l) {
+    const int D = p.max_depth;
+    if (p.y_all_levels && D >= 2) {
+        // every level's M2L products in one launch (they depend on the upward pass only)
+        GemmSegs sg{};
+        int64_t tiles = 0;
+        for (int l = 2; l <= D; ++l) {
+            sg.s[sg.n++] = GemmSeg{l, (int32_t)p.level_base[l], 0, (int32_t)p.level_cap[l], (int64_t)l * M * p.k_pad,
+                                   p.y_lvl_col[l]};
+            tiles += (p.level_cap[l] + kTile - 1) / kTile;
+        }
+        m2l_product<T>(p, sg, tiles, s);
+    }
+    PH_HIP(hipStreamWaitEvent(s, lists_ready, 0));  // the gathers read the X lists
+    for (int l = 2; l <= D; ++l) {
         const int64_t cap = p.level_cap[l];
         if (l >= 3) {
-            // Z = L2L_all (8 n_lam x n_lam) applied to every split box with targets at level l - 1
+            // u of every child of the split boxes with targets at level l - 1 = L2L_all (8 n_lam x
+            // n_lam) applied to the parent's u, written straight into the children's rows
             const int Mz = 8 * nl;
             const int64_t pcap = p.level_cap[l - 1];
             dim3 gz((Mz + kTile - 1) / kTile, (unsigned)std::min<int64_t>(1024, (pcap + kTile - 1) / kTile));
-            const T *Lop = (const T *)p.ops.l2l + (size_t)l * Mz * p.k_pad;
-            tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(Lop, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box,
-                                                         &p.d_sc->lvl_tpar[l - 1], (int32_t)p.level_base[l - 1], 0,
-                                                         (int32_t)pcap, nullptr, nullptr, nullptr, (T *)p.d_z);
+            tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(
+                (const T *)p.ops.l2l, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box, p.d_sc->lvl_tpar,
+                one_seg(l - 1, p.level_base[l - 1], 0, pcap, (int64_t)l * Mz * p.k_pad, 0), (T *)p.d_u, p.box.child,
+                p.box.t_cnt, a.work);
+        }
+        // level 2: every box (its u starts from zero); deeper levels: the boxes with a V or X list
+        const int32_t *vb = l >= 3 ? p.lists.vt + p.level_base[l] : nullptr;
+        const int32_t *vn = l >= 3 ? &p.d_sc->n_vt_lvl[l] : nullptr;
+        const unsigned gg = (unsigned)std::min<int64_t>(cap, 8192);
+        if (p.y_all_levels) {
+            down_gather_kernel<T><<<gg, 256, 0, s>>>(a, l, (const T *)p.d_y + (size_t)p.y_lvl_col[l] * M, M, 0,
+                                                     (int32_t)cap, l == 2, 1, vb, vn);
+            continue;
         }
         const int64_t ccap = std::min<int64_t>((int64_t)p.y_cap_cols, cap);
         const int nchunk = (int)((cap + ccap - 1) / ccap);
-        const T *Ml = (const T *)p.ops.m2l + (size_t)l * M * p.k_pad;
         for (int c = 0; c < nchunk; ++c) {
-            const int32_t r0 = (int32_t)(c * ccap);
-            // a bounded grid striding over the column tiles: an empty chunk costs little
-            dim3 g((M + kTile - 1) / kTile, (unsigned)std::min<int64_t>(16, (ccap + kTile - 1) / kTile));
-            if (std::is_same<T, float>::value && p.precision == PH_FP32_BF16SPLIT) {
-                const size_t off = (size_t)l * M * p.k_pad;
-                tgemm_m2l_bf16s_kernel<<<g, 256, 0, s>>>((const uint16_t *)p.ops.m2l_hi + off,
-                                                         (const uint16_t *)p.ops.m2l_lo + off, p.k_pad, M, nl,
-                                                         (const float *)p.d_phi, p.box.src_box, &p.d_sc->lvl_src[l],
-                                                         (int32_t)p.level_base[l], r0, (int32_t)ccap,
-                                                         (float *)p.d_y);
-            } else {
-                tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>(Ml, p.k_pad, M, nl, (const T *)p.d_phi, p.box.src_box,
-                                                            &p.d_sc->lvl_src[l], (int32_t)p.level_base[l], r0,
-                                                            (int32_t)ccap, nullptr, nullptr, nullptr, (T *)p.d_y);
-            }
-            down_gather_kernel<T><<<(unsigned)std::min<int64_t>((cap + 3) / 4, 4096), 256, 0, s>>>(a, l, (const T *)p.d_y, M, r0,
-                                                                             (int32_t)ccap, c == 0 ? 1 : 0,
-                                                                             (const T *)p.d_z);
+            const int64_t r0 = c * ccap;
+            m2l_product<T>(p, one_seg(l, p.level_base[l], r0, ccap, (int64_t)l * M * p.k_pad, 0),
+                           (ccap + kTile - 1) / kTile, s);
+            down_gather_kernel<T><<<gg, 256, 0, s>>>(a, l, (const T *)p.d_y, M, (int32_t)r0, (int32_t)ccap,
+                                                     l == 2 && c == 0, c == 0, vb, vn);
         }
     }
 }
@@ -366,9 +455,11 @@ __global__ void m2m_gather_kernel(FmmArgs<T> a, int level, const T *__restrict__
         const int32_t P = a.bx.src_box[a.lt.base[level] + rk];
         if (a.bx.flags[P] & kBoxLeaf) continue;
         T acc[4] = {0, 0, 0, 0};
+        unsigned long long nc = 0;
         for (int o = 0; o < 8; ++o) {
             const int32_t C = a.bx.child[(size_t)P * 8 + o];
             if (C < 0 || a.bx.src_rank[C] < 0) continue;
+            ++nc;
             const T *w = W + ((size_t)a.bx.src_rank[C] * 8 + o) * nl;
             for (int k = 0; k < 4; ++k) {
                 const int li = threadIdx.x + k * blockDim.x;
@@ -379,6 +470,7 @@ __global__ void m2m_gather_kernel(FmmArgs<T> a, int level, const T *__restrict__
             const int li = threadIdx.x + k * blockDim.x;
             if (li < nl) a.phi[(size_t)P * nl + li] = acc[k];
         }
+        if (a.work && threadIdx.x == 0) atomicAdd(&a.work[6], nc);
     }
 }
 
@@ -392,10 +484,10 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
     const int Mw = 8 * nl;
     const int64_t ccap = p.level_cap[l + 1];
     dim3 g((Mw + kTile - 1) / kTile, (unsigned)std::min<int64_t>(1024, (ccap + kTile - 1) / kTile));
-    const T *Op = (const T *)p.ops.m2m + (size_t)(l + 1) * Mw * p.k_pad;
-    tgemm_kernel<T, kModeM2M><<<g, 256, 0, s>>>(Op, p.k_pad, Mw, nl, (const T *)p.d_phi, p.box.src_box,
-                                                &p.d_sc->lvl_src[l + 1], (int32_t)p.level_base[l + 1], 0,
-                                                (int32_t)ccap, nullptr, nullptr, nullptr, (T *)p.d_z);
+    tgemm_kernel<T, kModeM2M><<<g, 256, 0, s>>>(
+        (const T *)p.ops.m2m, p.k_pad, Mw, nl, (const T *)p.d_phi, p.box.src_box, p.d_sc->lvl_src,
+        one_seg(l + 1, p.level_base[l + 1], 0, ccap, (int64_t)(l + 1) * Mw * p.k_pad, 0), (T *)p.d_z, nullptr,
+        nullptr, nullptr);
     const int threads = nl <= 64 ? 64 : (nl <= 128 ? 128 : 256);
     m2m_gather_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 8192), threads, 0, s>>>(a, l,
                                                                                               (const T *)p.d_z);
@@ -403,10 +495,10 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
 
 }  // namespace
 
-void fmm_downward(Plan &p, hipStream_t s)
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t lists_ready)
 {
-    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s);
-    else fmm_downward_t<float>(p, s);
+    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, lists_ready);
+    else fmm_downward_t<float>(p, s, lists_ready);
 }
 
 void fmm_m2m_level(Plan &p, int l, hipStream_t s)

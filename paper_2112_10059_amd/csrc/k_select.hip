@@ -90,17 +90,14 @@ struct SelectParams {
     double fallback_rel;          // source rule used when the learned selector falls back
 };
 
-// drop: per sorted point, 1 if a learned decision removed its source leaf (null: none).
-// When the selector has fallen back (sc->fallback) the source rule is fallback_rel instead.
+// Selection flags of sorted point k (bit 0 source, bit 1 target).  drop: per sorted point, 1
+// if a learned decision removed its source leaf (null: none).  When the selector has fallen
+// back (sc->fallback) the source rule is fallback_rel instead.
 template <class T>
-__global__ void select_flags_kernel(const T *__restrict__ I, const float *__restrict__ E,
-                                    const int32_t *__restrict__ perm, int64_t n, SelectParams sp,
-                                    CallScalars *__restrict__ sc, uint64_t *__restrict__ flag,
-                                    T *__restrict__ S_out, const uint8_t *__restrict__ drop)
+__device__ __forceinline__ uint32_t select_one(const T *__restrict__ I, const float *__restrict__ E, int32_t o,
+                                               int64_t k, const SelectParams &sp, const CallScalars *__restrict__ sc,
+                                               const uint8_t *__restrict__ drop)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int32_t o = perm[k];
     const double v = (double)I[o];
     bool src;
     if (drop && sc->fallback) {
@@ -115,36 +112,77 @@ __global__ void select_flags_kernel(const T *__restrict__ I, const float *__rest
         if (sp.e_abs >= 0.0) tgt = tgt && (e >= sp.e_abs);
         if (sp.e_rel >= 0.0) tgt = tgt && (e >= sp.e_applied + sp.e_rel * (sc->emax - sp.e_applied));
     }
-    flag[k] = (uint64_t)(src ? 1u : 0u) | ((uint64_t)(tgt ? 1u : 0u) << 32);
-    if (!tgt) S_out[o] = T(0);
+    return (src ? 1u : 0u) | (tgt ? 2u : 0u);
 }
 
-template <class T>
-struct Vec4;
-template <>
-struct Vec4<float> {
-    using type = float4;
-};
-template <>
-struct Vec4<double> {
-    using type = double4;
-};
-
-// flag[] now holds the exclusive scan of the packed (src, tgt) indicators and
-// sc->packed_total the packed totals, so element k is selected iff its scan
-// value differs from the next one.
-template <class T, class TI>
-__global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restrict__ perm,
-                               const uint64_t *__restrict__ key, const double *__restrict__ xyz,
-                               const double *__restrict__ w, double w_uniform, double c_self, int64_t n,
-                               CallScalars *__restrict__ sc, const uint64_t *__restrict__ scanned,
-                               int32_t *__restrict__ s_pos, int32_t *__restrict__ t_pos,
-                               int32_t *__restrict__ t_out,
-                               typename Vec4<T>::type *__restrict__ s_dat, typename Vec4<T>::type *__restrict__ t_dat,
-                               const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell,
-                               int32_t *__restrict__ t_cell)
+__device__ __forceinline__ uint64_t packed_of(uint32_t f)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    return (uint64_t)(f & 1u) | ((uint64_t)(f >> 1) << 32);
+}
+
+// Selection in two passes over tiles of kSelTile sorted points (1024 threads; wave w owns a
+// contiguous sixteenth, read as kSelStrips coalesced strips of 64), with a scan of the tile
+// sums between them.  Pass one: the flags of every point (one byte each), S = 0 at points that
+// are not targets, and each tile's packed count (sources | targets << 32).
+constexpr int kSelWaves = 16;
+constexpr int kSelStrips = 4;
+constexpr int kSelSpan = 64 * kSelStrips;  // points per wave in a tile
+constexpr int kSelTile = kSelWaves * kSelSpan;
+
+template <class T>
+__global__ __launch_bounds__(64 * kSelWaves) void select_tiles_kernel(const T *__restrict__ I, const float *__restrict__ E,
+                                                           const int32_t *__restrict__ perm, int64_t n,
+                                                           SelectParams sp, const CallScalars *__restrict__ sc,
+                                                           const uint8_t *__restrict__ drop, uint8_t *__restrict__ sel,
+                                                           T *__restrict__ S_out, uint64_t *__restrict__ partial)
+{
+    __shared__ uint64_t wsum[kSelWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)w * kSelSpan;
+    int32_t o[kSelStrips];
+#pragma unroll
+    for (int st = 0; st < kSelStrips; ++st) {
+        const int64_t k = base + st * 64 + lane;
+        o[st] = k < n ? perm[k] : 0;
+    }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int st = 0; st < kSelStrips; ++st) {
+        const int64_t k = base + st * 64 + lane;
+        if (k < n) {
+            const uint32_t f = select_one(I, E, o[st], k, sp, sc, drop);
+            sel[k] = (uint8_t)f;
+            if (!(f & 2u)) S_out[o[st]] = T(0);
+            acc += packed_of(f);
+        }
+    }
+    acc = lane_value(wave_inclusive(acc, lane), 63);
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int q = 0; q < kSelWaves; ++q) t += wsum[q];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// Pass two: the exclusive scan of the packed counts where the tree build reads it (the first
+// point of a box and the point after a box: bnd), and the compaction of the selected points in
+// Morton order: sources (x, y, z, w I 2^-e) and targets (x, y, z, own-cell term c_self I 2^-e if
+// the point is also a source) with their caller indices and grid cells.  Coordinates come from
+// the plan's sorted copy in the working precision (C: float4, FP64: three doubles).
+template <class TI, class T, class C>
+__global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
+    const TI *__restrict__ I, const int32_t *__restrict__ perm, const C *__restrict__ xyz,
+    const double *__restrict__ w, double w_uniform, double c_self, int64_t n, CallScalars *__restrict__ sc,
+    const uint8_t *__restrict__ sel, const uint8_t *__restrict__ bnd, const uint64_t *__restrict__ partial,
+    uint64_t *__restrict__ scanned, int32_t *__restrict__ t_out,
+    typename Vec4T<T>::type *__restrict__ s_dat, typename Vec4T<T>::type *__restrict__ t_dat,
+    const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell, int32_t *__restrict__ t_cell)
+{
+    __shared__ uint64_t wsum[kSelWaves];
+    constexpr int kStrips = kSelStrips;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double imax = sc->imax;
     // scale I by 2^-e, e = floor(log2(max I)), so FP32 sums stay near unit magnitude
     int e = 0;
@@ -152,48 +190,88 @@ __global__ void compact_kernel(const TI *__restrict__ I, const int32_t *__restri
         (void)frexp(imax, &e);
         e -= 1;
     }
-    const uint64_t total = sc->packed_total;
-    if (k == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint64_t total = sc->packed_total;
         sc->scale_exp = e;
         sc->n_src = (int32_t)(total & 0xffffffffu);
         sc->n_tgt = (int32_t)(total >> 32);
     }
-    if (k >= n) return;
-    const uint64_t here = scanned[k];
-    const uint64_t next = (k + 1 < n) ? scanned[k + 1] : total;
-    const uint32_t sp_lo = (uint32_t)(here & 0xffffffffu), sp_hi = (uint32_t)(here >> 32);
-    const bool is_src = (uint32_t)(next & 0xffffffffu) != sp_lo;
-    const bool is_tgt = (uint32_t)(next >> 32) != sp_hi;
-    if (!is_src && !is_tgt) return;
-    const int32_t o = perm[k];
     const double scale = ldexp(1.0, -e);
-    const double Iv = (double)I[o] * scale;
-    const double x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
-    if (is_src) {
-        const double wk = w ? w[k] : w_uniform;
-        s_pos[sp_lo] = (int32_t)k;
-        typename Vec4<T>::type d;
-        d.x = (T)x;
-        d.y = (T)y;
-        d.z = (T)z;
-        d.w = (T)(wk * Iv);
-        s_dat[sp_lo] = d;
-        if (cell) s_cell[sp_lo] = cell[k];
+    const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)wv * kSelSpan;
+    uint32_t f[kStrips];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) {
+        const int64_t k = base + st * 64 + lane;
+        f[st] = k < n ? sel[k] : 0u;
+        acc += packed_of(f[st]);
     }
-    if (is_tgt) {
-        t_pos[sp_hi] = (int32_t)k;
-        t_out[sp_hi] = o;
-        typename Vec4<T>::type d;
-        d.x = (T)x;
-        d.y = (T)y;
-        d.z = (T)z;
-        d.w = is_src ? (T)(c_self * Iv) : T(0);
-        t_dat[sp_hi] = d;
-        if (cell) t_cell[sp_hi] = cell[k];
+    acc = lane_value(wave_inclusive(acc, lane), 63);
+    if (lane == 0) wsum[wv] = acc;
+    __syncthreads();
+    uint64_t carry = partial[blockIdx.x];
+    for (int q = 0; q < wv; ++q) carry += wsum[q];
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) {
+        const uint64_t v = packed_of(f[st]);
+        const uint64_t incl = wave_inclusive(v, lane);
+        const uint64_t here = carry + incl - v;
+        carry += lane_value(incl, 63);
+        const int64_t k = base + st * 64 + lane;
+        if (k >= n) continue;
+        if (bnd[k]) scanned[k] = here;
+        if (!f[st]) continue;
+        const uint32_t sp_lo = (uint32_t)(here & 0xffffffffu), sp_hi = (uint32_t)(here >> 32);
+        const int32_t o = perm[k];
+        const double Iv = (double)I[o] * scale;
+        T x, y, z;
+        if constexpr (sizeof(C) == 8) {
+            x = (T)xyz[3 * k];
+            y = (T)xyz[3 * k + 1];
+            z = (T)xyz[3 * k + 2];
+        } else {
+            const C q = xyz[k];
+            x = q.x;
+            y = q.y;
+            z = q.z;
+        }
+        const bool is_src = f[st] & 1u;
+        if (is_src) {
+            const double wk = w ? w[k] : w_uniform;
+            typename Vec4T<T>::type d;
+            d.x = (T)x;
+            d.y = (T)y;
+            d.z = (T)z;
+            d.w = (T)(wk * Iv);
+            s_dat[sp_lo] = d;
+            if (cell) s_cell[sp_lo] = cell[k];
+        }
+        if (f[st] & 2u) {
+            t_out[sp_hi] = o;
+            typename Vec4T<T>::type d;
+            d.x = (T)x;
+            d.y = (T)y;
+            d.z = (T)z;
+            d.w = is_src ? (T)(c_self * Iv) : T(0);
+            t_dat[sp_hi] = d;
+            if (cell) t_cell[sp_hi] = cell[k];
+        }
     }
 }
 
+// plan time: the sorted coordinates rounded to FP32, as float4 (x, y, z, 0)
+__global__ void pack_xyzf_kernel(const double *__restrict__ xyz, int64_t n, float4 *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = make_float4((float)xyz[3 * k], (float)xyz[3 * k + 1], (float)xyz[3 * k + 2], 0.f);
+}
+
 }  // namespace
+
+void launch_pack_xyzf(const double *xyz, int64_t n, float4 *out, hipStream_t s)
+{
+    if (n > 0) pack_xyzf_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xyz, n, out);
+}
 
 void launch_reset_scalars(CallScalars *sc, hipStream_t s) { reset_scalars_kernel<<<1, 256, 0, s>>>(sc); }
 
@@ -223,31 +301,31 @@ static SelectParams params_of(const Plan &p)
     return SelectParams{p.thr.src_rel, p.thr.e_abs, p.thr.e_applied, p.thr.e_rel, p.fallback_rel};
 }
 
-void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s,
-                         const uint8_t *drop)
+void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop)
 {
     const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
-    unsigned g = (unsigned)((p.n + 255) / 256);
+    if (p.n <= 0) return;
+    const int64_t nb = (p.n + kSelTile - 1) / kSelTile;
+    uint64_t *partial = (uint64_t *)p.d_scan_tmp;
+    const SelectParams sp = params_of(p);
     if (p.precision == PH_FP64)
-        select_flags_kernel<double><<<g, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, p.d_perm, p.n,
-                                                      params_of(p), p.d_sc, p.d_flag, (double *)S_out, drop);
+        select_tiles_kernel<double><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>((const double *)I, need_e ? E : nullptr, p.d_perm,
+                                                                  p.n, sp, p.d_sc, drop, p.d_sel, (double *)S_out,
+                                                                  partial);
     else
-        select_flags_kernel<float><<<g, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, p.d_perm, p.n,
-                                                     params_of(p), p.d_sc, p.d_flag, (float *)S_out, drop);
-}
-
-void launch_compact(const Plan &p, const void *I, hipStream_t s)
-{
-    unsigned g = (unsigned)((p.n + 255) / 256);
+        select_tiles_kernel<float><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>((const float *)I, need_e ? E : nullptr, p.d_perm,
+                                                                 p.n, sp, p.d_sc, drop, p.d_sel, (float *)S_out,
+                                                                 partial);
+    scan_tile_sums_u64(partial, nb, &p.d_sc->packed_total, s);
     if (p.precision == PH_FP64)
-        compact_kernel<double, double><<<g, 256, 0, s>>>(
-            (const double *)I, p.d_perm, p.d_key, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_flag,
-            p.d_s_pos, p.d_t_pos, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
+        select_compact_kernel<double, double, double><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
+            (const double *)I, p.d_perm, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
+            partial, p.d_flag, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
     else
-        compact_kernel<float, float><<<g, 256, 0, s>>>(
-            (const float *)I, p.d_perm, p.d_key, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_flag,
-            p.d_s_pos, p.d_t_pos, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
+        select_compact_kernel<float, float, float4><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
+            (const float *)I, p.d_perm, p.d_xyzf, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
+            partial, p.d_flag, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
 }
 

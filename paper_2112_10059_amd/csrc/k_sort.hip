@@ -6,7 +6,7 @@
 // most significant end, so every octree box is a contiguous run of keys.
 #include <hip/hip_runtime.h>
 
-#include "ph_internal.h"
+#include "k_common.h"
 
 namespace ph {
 
@@ -151,40 +151,6 @@ __global__ void radix_scatter_kernel(const uint64_t *__restrict__ keys, const in
 // contiguous quarter, read as 16 coalesced strips of 64 and scanned across lanes with shuffles;
 // the waves' totals are exchanged once through LDS.  Integer sums: the order does not matter.
 
-template <class T>
-__device__ __forceinline__ T shfl_up_t(T v, int d)
-{
-    if constexpr (sizeof(T) == 8) {
-        const uint32_t lo = __shfl_up((uint32_t)v, (unsigned)d), hi = __shfl_up((uint32_t)(v >> 32), (unsigned)d);
-        return ((T)hi << 32) | lo;
-    } else {
-        return (T)__shfl_up((uint32_t)v, (unsigned)d);
-    }
-}
-
-template <class T>
-__device__ __forceinline__ T lane_value(T v, int l)
-{
-    if constexpr (sizeof(T) == 8) {
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-        return ((T)hi << 32) | lo;
-    } else {
-        return (T)(uint32_t)__builtin_amdgcn_readlane((int)v, l);
-    }
-}
-
-// inclusive scan across the 64 lanes
-template <class T>
-__device__ __forceinline__ T wave_inclusive(T v, int lane)
-{
-    for (int d = 1; d < 64; d <<= 1) {
-        const T y = shfl_up_t(v, d);
-        if (lane >= d) v += y;
-    }
-    return v;
-}
-
 constexpr int kWaveSpan = kScanTile / 4;  // elements per wave in a tile
 
 template <class T>
@@ -279,26 +245,49 @@ __global__ __launch_bounds__(1024) void scan_small_kernel(ScanJob<T> j0, ScanJob
     const int64_t span = ((n + 16 * 64 - 1) / (16 * 64)) * 64;  // elements per wave, a multiple of 64
     const int64_t base = (int64_t)w * span;
     const int strips = (int)(span / 64);
-    T loc[kSmallStrips];
+    T loc[sizeof(T) == 4 ? kSmallStrips : 1];
     T acc = 0;
 #pragma unroll
     for (int st = 0; st < kSmallStrips; ++st) {
         const int64_t i = base + st * 64 + lane;
-        loc[st] = (st < strips && i < n) ? data[i] : T(0);
-        acc += loc[st];
+        const T v = (st < strips && i < n) ? data[i] : T(0);
+        if constexpr (sizeof(T) == 4) loc[st] = v;
+        acc += v;
     }
     acc = lane_value(wave_inclusive(acc, lane), 63);
     if (lane == 0) wsum[w] = acc;
     __syncthreads();
     T carry = 0;
     for (int q = 0; q < w; ++q) carry += wsum[q];
+    if constexpr (sizeof(T) == 4) {
 #pragma unroll
-    for (int st = 0; st < kSmallStrips; ++st) {
-        if (st < strips) {  // a guard, not a break: the strips stay in registers
-            const T incl = wave_inclusive(loc[st], lane);
-            const int64_t i = base + st * 64 + lane;
-            if (i < n) data[i] = carry + incl - loc[st];
-            carry += lane_value(incl, 63);
+        for (int st = 0; st < kSmallStrips; ++st) {
+            if (st < strips) {  // a guard, not a break: the strips stay in registers
+                const T incl = wave_inclusive(loc[st], lane);
+                const int64_t i = base + st * 64 + lane;
+                if (i < n) data[i] = carry + incl - loc[st];
+                carry += lane_value(incl, 63);
+            }
+        }
+    } else {
+        // 64-bit values: read again (from L2) half a span at a time; 40 held would spill
+        constexpr int kHalf = kSmallStrips / 2;
+        for (int h = 0; h < kSmallStrips; h += kHalf) {
+            T v[kHalf];
+#pragma unroll
+            for (int u = 0; u < kHalf; ++u) {
+                const int64_t i = base + (h + u) * 64 + lane;
+                v[u] = (h + u < strips && i < n) ? data[i] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kHalf; ++u) {
+                if (h + u < strips) {
+                    const T incl = wave_inclusive(v[u], lane);
+                    const int64_t i = base + (h + u) * 64 + lane;
+                    if (i < n) data[i] = carry + incl - v[u];
+                    carry += lane_value(incl, 63);
+                }
+            }
         }
     }
     if (threadIdx.x == 1023 && total) *total = carry;
@@ -308,12 +297,10 @@ template <class T>
 void exclusive_scan(T *data, int64_t n, void *tmp, T *total, hipStream_t s)
 {
     if (n <= 0) return;
-    if constexpr (sizeof(T) == 4) {
-        if (n <= kSmallScan) {
-            const ScanJob<T> j{data, total};
-            scan_small_kernel<T><<<1, 1024, 0, s>>>(j, j, j, n);
-            return;
-        }
+    if (n <= kSmallScan) {
+        const ScanJob<T> j{data, total};
+        scan_small_kernel<T><<<1, 1024, 0, s>>>(j, j, j, n);
+        return;
     }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     T *partial = (T *)tmp;
@@ -323,6 +310,11 @@ void exclusive_scan(T *data, int64_t n, void *tmp, T *total, hipStream_t s)
 }
 
 }  // namespace
+
+void scan_tile_sums_u64(uint64_t *partial, int64_t nb, uint64_t *total, hipStream_t s)
+{
+    scan_partials_kernel<uint64_t><<<1, 1024, 0, s>>>(partial, nb, total);
+}
 
 size_t scan_tmp_bytes(int64_t n, size_t elem)
 {

@@ -17,7 +17,8 @@
 //   X(B), any B  : leaves not adjacent to B but adjacent to B's parent, coarser than B
 //                  (their sources act on B's check points)
 //   V(B)         : children of the parent's colleagues not adjacent to B; enumerated
-//                  on the fly by the translation kernel, not stored.
+//                  on the fly by the translation gather, not stored (the boxes with a
+//                  non-empty V or X list are listed per level).
 #include <hip/hip_runtime.h>
 
 #include "ph_internal.h"
@@ -31,6 +32,34 @@ struct LevelInfo {
     int32_t cap[kMaxDepth + 2];
     int32_t depth;  // deepest level
 };
+
+// Append val to list for the lanes with pred: one atomic per wave, lanes in lane order.
+template <class V>
+__device__ __forceinline__ void wave_append(bool pred, V *__restrict__ list, int32_t *counter, V val)
+{
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
+// Slot of each lane with pred in a list whose length is *counter: one atomic per wave, lanes in
+// lane order; -1 for the other lanes.
+__device__ __forceinline__ int32_t wave_slot(bool pred, int32_t *counter)
+{
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, leader);
+    return pred ? base + (int32_t)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
 
 // Per-call tree: the plan's tree over all points, pruned to the selected sets.
 // Box ranges come from the exclusive scan of the packed (source | target << 32)
@@ -51,7 +80,6 @@ __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int
     if (f == 0) {
         for (int l = 0; l <= li.depth; ++l) sc->lvl_count[l] = li.cap[l];
         for (int l = 0; l <= li.depth + 1; ++l) sc->lvl_start[l] = li.base[l];
-        bx.srcflag[nbox] = 0;
     }
     const int32_t st = bx.start[f], en = bx.end[f];
     const uint64_t a = scan_at(scanned, st, n, total), b = scan_at(scanned, en, n, total);
@@ -73,43 +101,35 @@ __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int
         bx.t_first[f] = exists ? t0 : 0;
         bx.t_cnt[f] = exists ? tn : 0;
         bx.flags[f] = exists ? (kBoxExists | (split ? 0 : kBoxLeaf)) : 0;
-        // low word: box with sources; high word: split box with targets (parent of target boxes)
-        bx.srcflag[f] = (uint64_t)((exists && sn > 0) ? 1u : 0u) | ((uint64_t)((split && tn > 0) ? 1u : 0u) << 32);
+    }
+    // per level: the boxes with sources and the split boxes with targets (the parents whose
+    // local fields the next level needs), each with its slot in the level's list.  The slots
+    // come from atomic appends (a wave rarely spans two levels): the order of the boxes within
+    // a level enters no result, only the layout of the per-level products.
+    const bool has_src = mine && exists && sn > 0, is_tpar = mine && split && tn > 0;
+    const int lev = bx.level[f];
+    int32_t srank = -1, trank = -1;
+    uint64_t pending = __ballot(has_src || is_tpar);
+    while (pending) {
+        const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
+        const bool here = lev == l0;
+        const int32_t rs = wave_slot(has_src && here, &sc->lvl_src[l0]);
+        const int32_t rt = wave_slot(is_tpar && here, &sc->lvl_tpar[l0]);
+        if (here) {
+            srank = rs;
+            trank = rt;
+        }
+        pending &= ~__ballot(here);
+    }
+    if (mine) {
+        bx.src_rank[f] = srank;
+        if (srank >= 0) bx.src_box[li.base[lev] + srank] = f;
+        if (trank >= 0) bx.tpar_box[li.base[lev] + trank] = f;
     }
     // lowest level holding a leaf with sources, as max of (depth + 1 - level), one atomic per wave
     int v = (mine && exists && !split && sn > 0) ? (li.depth + 1 - bx.level[f]) : 0;
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
     if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(&sc->min_leafsrc_level, v);
-}
-
-// srcflag holds its exclusive scan: per level, the rank of every box with sources and of
-// every split box with targets (the parents whose local fields the next level needs)
-__global__ void tree_srcrank_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, CallScalars *__restrict__ sc)
-{
-    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nbox) return;
-    const int l = bx.level[f];
-    const int32_t base = li.base[l];
-    const uint64_t here = bx.srcflag[f], next = bx.srcflag[f + 1], first = bx.srcflag[base];
-    if (f == base) {
-        const uint64_t end = bx.srcflag[li.base[l + 1]];
-        sc->lvl_src[l] = (int32_t)((end & 0xffffffffu) - (first & 0xffffffffu));
-        sc->lvl_tpar[l] = (int32_t)((end >> 32) - (first >> 32));
-    }
-    if ((next & 0xffffffffu) != (here & 0xffffffffu)) {
-        const int32_t rank = (int32_t)((here & 0xffffffffu) - (first & 0xffffffffu));
-        bx.src_rank[f] = rank;
-        bx.src_box[base + rank] = f;
-    } else {
-        bx.src_rank[f] = -1;
-    }
-    if ((next >> 32) != (here >> 32)) {
-        const int32_t rank = (int32_t)((here >> 32) - (first >> 32));
-        bx.tpar_rank[f] = rank;
-        bx.tpar_box[base + rank] = f;
-    } else {
-        bx.tpar_rank[f] = -1;
-    }
 }
 
 // ---------------------------------------------------------------- lists
@@ -189,24 +209,10 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_lev
     }
 }
 
-// Append val to list for the lanes with pred: one atomic per wave, lanes in lane order.
-template <class V>
-__device__ __forceinline__ void wave_append(bool pred, V *__restrict__ list, int32_t *counter, V val)
-{
-    const uint64_t m = __ballot(pred);
-    if (m == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
-    base = __shfl(base, leader);
-    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
-}
-
 // List lengths per box, and the leaf lists of the target-side kernels.  grid_levels: bit l
 // set when leaves of level l take their far field from a grid operator (or have none).
 __global__ void list_count_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc, int32_t nbox,
-                                  Lists L, uint32_t grid_levels)
+                                  Lists L, uint32_t grid_levels, uint32_t gen)
 {
     const int32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid == 0) L.u_off[nbox] = L.w_off[nbox] = L.x_off[nbox] = 0;  // scanned into the totals
@@ -238,6 +244,66 @@ __global__ void list_count_kernel(BoxArrays bx, LevelInfo li, CallScalars *__res
     }
     wave_append(tleaf && !grid_leaf, L.far_b, &sc->n_far_b, b);
     wave_append(tleaf && nu > 0, L.near_leaves, &sc->n_near, b);
+    // boxes of levels >= 3 with an X list join their level's V/X target segment
+    const bool xbox = nx > 0 && lev >= 3 && atomicExch(&L.vt_tag[b], (int)gen) != (int)gen;
+    pending = __ballot(xbox);
+    while (pending) {
+        const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
+        const bool mine = xbox && lev == l0;
+        wave_append(mine, L.vt + li.base[l0], &sc->n_vt_lvl[l0], b);
+        pending &= ~__ballot(mine);
+    }
+}
+
+// Boxes of levels >= 3 that receive M2L translations.  B has source box S in its V list iff
+// B is a child of a colleague of S's parent, not adjacent to S, at S's level; so one wave per
+// source box S walks those candidates (the children of the parent's split colleagues) and
+// enters each one with targets once per call into its level's segment of vt.
+__global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc,
+                                                      Lists L, uint32_t gen)
+{
+    const int lane = threadIdx.x & 63;
+    for (int32_t idx = blockIdx.x * 4 + (threadIdx.x >> 6);; idx += gridDim.x * 4) {
+        int level = -1;
+        int32_t r = idx;
+        for (int l = 3; l <= li.depth; ++l) {
+            const int32_t c = sc->lvl_src[l];
+            if (r < c) {
+                level = l;
+                break;
+            }
+            r -= c;
+        }
+        if (level < 0) return;
+        const int32_t S = bx.src_box[li.base[level] + r];
+        const int32_t P = bx.parent[S];
+        const int sx = bx.ax[S], sy = bx.ay[S], sz = bx.az[S];
+        int32_t Qd = -1;
+        if (lane < 27) {
+            const int32_t Q = bx.coll[(size_t)P * 27 + lane];
+            if (Q >= 0 && (bx.flags[Q] & (kBoxExists | kBoxLeaf)) == kBoxExists) Qd = Q;
+        }
+        const uint64_t qmask = __ballot(Qd >= 0);
+        const int nc = 8 * __popcll(qmask);
+        for (int f0 = 0; f0 < nc; f0 += 64) {
+            const int f = f0 + lane;
+            uint64_t m = qmask;
+            for (int j = f < nc ? (f >> 3) : 0; j > 0; --j) m &= m - 1;
+            const int d = m ? __ffsll((long long)m) - 1 : 0;
+            const int32_t Q = __shfl(Qd, d);
+            int32_t B = -1;
+            bool fresh = false;
+            if (f < nc) {
+                B = bx.child[(size_t)Q * 8 + (f & 7)];
+                if (B >= 0 && bx.t_cnt[B] > 0) {
+                    const int dx = bx.ax[B] - sx, dy = bx.ay[B] - sy, dz = bx.az[B] - sz;
+                    const bool near = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+                    fresh = !near && atomicExch(&L.vt_tag[B], (int)gen) != (int)gen;
+                }
+            }
+            wave_append(fresh, L.vt + li.base[level], &sc->n_vt_lvl[level], B);
+        }
+    }
 }
 
 __global__ void list_fill_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc, int32_t nbox, Lists L)
@@ -288,8 +354,6 @@ void build_tree(Plan &p, hipStream_t s)
     const int32_t nbox = (int32_t)p.box_cap;
     const unsigned g = (unsigned)((nbox + 255) / 256);
     tree_status_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.leaf_cap, p.max_depth, p.d_flag, p.n, p.d_sc);
-    exclusive_scan_u64(p.box.srcflag, nbox + 1, p.d_scan_tmp, nullptr, s);
-    tree_srcrank_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.d_sc);
 }
 
 void build_lists(Plan &p, hipStream_t s)
@@ -301,7 +365,13 @@ void build_lists(Plan &p, hipStream_t s)
     if (p.grid_mode)
         for (int l = 0; l <= p.max_depth; ++l)
             if (l < 2 || p.grid_m[l] > 0) grid_levels |= 1u << l;
-    list_count_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels);
+    if (p.method == PH_METHOD_FMM && p.max_depth >= 3) {
+        int64_t cap = 0;
+        for (int l = 3; l <= p.max_depth; ++l) cap += p.level_cap[l];
+        vtarget_kernel<<<(unsigned)std::min<int64_t>((cap + 3) / 4, 1024), 256, 0, s>>>(p.box, li, p.d_sc, p.lists,
+                                                                                        p.call_gen);
+    }
+    list_count_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels, p.call_gen);
     // nbox + 1 entries: the last one (0 before the scan) receives the total
     exclusive_scan3_u32(p.lists.u_off, reinterpret_cast<uint32_t *>(&p.d_sc->n_u), p.lists.w_off,
                         reinterpret_cast<uint32_t *>(&p.d_sc->n_w), p.lists.x_off,

@@ -200,14 +200,14 @@ void alloc_workspace(Plan &p)
     const size_t rs = p.precision == PH_FP64 ? sizeof(double) : sizeof(float);
     p.d_sc = (CallScalars *)dev_alloc(p, sizeof(CallScalars));
     p.d_flag = (uint64_t *)dev_alloc(p, (size_t)n * sizeof(uint64_t));
+    p.d_sel = (uint8_t *)dev_alloc(p, (size_t)n);
+    PH_HIP(hipMemset(p.d_sel, 0, (size_t)n));  // nothing selected before the first call
     p.scan_tmp_bytes = std::max({scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4), (size_t)16384});
     p.d_scan_tmp = dev_alloc(p, p.scan_tmp_bytes);
-    p.d_s_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
-    p.d_t_pos = (int32_t *)dev_alloc(p, (size_t)n * 4);
     p.d_t_out = (int32_t *)dev_alloc(p, (size_t)n * 4);
     p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);
     p.d_t_dat = dev_alloc(p, (size_t)n * 4 * rs);
-    p.d_t_far = dev_alloc(p, (size_t)n * rs);
+    p.d_t_near = (double *)dev_alloc(p, (size_t)n * 8);
     if (p.grid_mode) {
         p.d_s_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
         p.d_t_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
@@ -219,8 +219,6 @@ void alloc_workspace(Plan &p)
     b.t_first = (int32_t *)dev_alloc(p, B * 4);
     b.t_cnt = (int32_t *)dev_alloc(p, B * 4);
     b.flags = (int32_t *)dev_alloc(p, B * 4);
-    b.srcflag = (uint64_t *)dev_alloc(p, (B + 1) * 8);
-    b.tpar_rank = (int32_t *)dev_alloc(p, B * 4);
     b.tpar_box = (int32_t *)dev_alloc(p, B * 4);
     b.src_rank = (int32_t *)dev_alloc(p, B * 4);
     b.src_box = (int32_t *)dev_alloc(p, B * 4);
@@ -237,16 +235,32 @@ void alloc_workspace(Plan &p)
     L.far_a = (int4 *)dev_alloc(p, B * sizeof(int4));
     L.far_b = (int32_t *)dev_alloc(p, B * 4);
     L.near_leaves = (int32_t *)dev_alloc(p, B * 4);
+    L.vt = (int32_t *)dev_alloc(p, B * 4);
+    L.vt_tag = (int32_t *)dev_alloc(p, B * 4);
+    PH_HIP(hipMemset(L.vt_tag, 0, B * 4));  // no call has tagged a box yet
     if (p.method == PH_METHOD_FMM) {
         p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
         p.d_u = dev_alloc(p, (size_t)B * p.n_lam * rs);
-        // translation products: at most 2 GiB, at least one tile of source boxes
+        // translation products: the source boxes of every level at once (one M2L product for
+        // all levels) if that takes at most an eighth of the device memory (a quarter of a
+        // workspace cap); else one level at a time, in chunks of at most that size (at least
+        // one tile of source boxes)
         const size_t col_bytes = (size_t)kNumM2L * p.n_lam * rs;
         int64_t widest2 = 1;
         for (int l = 2; l <= p.max_depth; ++l) widest2 = std::max<int64_t>(widest2, p.level_cap[l]);
-        size_t budget = 2ull << 30;
+        size_t total_mem = 0;
+        PH_HIP(hipDeviceTotalMem(&total_mem, p.device));
+        size_t budget = std::max<size_t>(total_mem / 8, 256ull << 20);
+        if (p.workspace_cap) budget = std::min<size_t>(budget, p.workspace_cap / 4);
         if (const char *env = std::getenv("PH_TRANSLATION_BUFFER_MB")) budget = (size_t)std::atoll(env) << 20;
-        p.y_cap_cols = (size_t)std::max<int64_t>(64, std::min<int64_t>(widest2, (int64_t)(budget / col_bytes)));
+        int64_t all_cols = 0;
+        for (int l = 2; l <= p.max_depth; ++l) {
+            p.y_lvl_col[l] = all_cols;
+            all_cols += p.level_cap[l];
+        }
+        p.y_all_levels = all_cols > 0 && (size_t)all_cols * col_bytes <= budget;
+        if (p.y_all_levels) p.y_cap_cols = (size_t)all_cols;
+        else p.y_cap_cols = (size_t)std::max<int64_t>(64, std::min<int64_t>(widest2, (int64_t)(budget / col_bytes)));
         p.d_y = dev_alloc(p, p.y_cap_cols * col_bytes);
         int64_t widest_par = 1;
         for (int l = 2; l <= p.max_depth; ++l) widest_par = std::max<int64_t>(widest_par, p.level_cap[l]);
@@ -277,22 +291,28 @@ void free_plan(Plan *p)
     // every pointer member that came from dev_alloc
     void *ptrs[] = {p->d_key, p->d_perm, p->d_iperm, p->d_xyz, p->d_w, p->ops.uc2e_rm, p->ops.uc2e_cm,
                     p->ops.m2m, p->ops.l2l, p->ops.m2l, p->ops.lat_unit, p->ops.shell_unit, p->ops.m2l_hi,
-                    p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_scan_tmp, p->d_s_pos, p->d_t_pos, p->d_t_out,
+                    p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_sel, p->d_scan_tmp, p->d_xyzf, p->d_bnd, p->d_t_out,
                     p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
                     p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
-                    p->box.child, p->box.coll, p->box.start, p->box.end, p->box.srcflag, p->box.src_rank, p->box.tpar_rank, p->box.tpar_box, p->d_z,
+                    p->box.child, p->box.coll, p->box.start, p->box.end, p->box.src_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
-                    p->lists.far_b, p->lists.near_leaves, p->d_phi, p->d_u,
+                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->d_phi, p->d_u,
                     p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
                     p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
                     p->d_row_feat,
                     p->d_cell,
-                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_far};
+                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
         for (auto &set : p->ring)
             for (auto &e : set) (void)hipEventDestroy(e);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->ev_lists) (void)hipEventDestroy(p->ev_lists);
+    if (p->ev_down) (void)hipEventDestroy(p->ev_down);
+    if (p->ev_rest) (void)hipEventDestroy(p->ev_rest);
+    if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
 }
 
@@ -389,6 +409,10 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     p.d_iperm = (int32_t *)dev_alloc(p, (size_t)n * 4);
     if (d_w_in) p.d_w = (double *)dev_alloc(p, (size_t)n * 8);
     launch_gather_sorted(d_xyz_in, d_w_in, p.d_perm, n, p.d_xyz, p.d_w, p.d_iperm, s);
+    if (p.precision != PH_FP64) {
+        p.d_xyzf = (float4 *)dev_alloc(p, (size_t)n * sizeof(float4));
+        launch_pack_xyzf(p.d_xyz, n, p.d_xyzf, s);
+    }
     PH_HIP(hipStreamSynchronize(s));
     dev_free(ktmp);
     dev_free(vtmp);
@@ -456,6 +480,14 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         up(&bx.az, FT.az);
         up(&bx.start, FT.start);
         up(&bx.end, FT.end);
+        // the points where the tree build reads the selection scan: box starts and ends
+        std::vector<uint8_t> bnd((size_t)n, 0);
+        for (size_t f = 0; f < FT.start.size(); ++f) {
+            if (FT.start[f] < n) bnd[FT.start[f]] = 1;
+            if (FT.end[f] < n) bnd[FT.end[f]] = 1;
+        }
+        p.d_bnd = (uint8_t *)dev_alloc(p, (size_t)n);
+        PH_HIP(hipMemcpy(p.d_bnd, bnd.data(), (size_t)n, hipMemcpyHostToDevice));
         up(&bx.parent, FT.parent);
         up(&bx.child, FT.child);
         up(&bx.coll, FT.coll);
@@ -582,6 +614,13 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     for (auto &set : p.ring)
         for (auto &e : set) PH_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     p.events_ready = true;
+    // second stream (default priority) and its ordering events
+    PH_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_lists, hipEventDisableTiming));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_down, hipEventDisableTiming));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_rest, hipEventDisableTiming));
 }
 
 }  // namespace ph
@@ -659,15 +698,24 @@ static ph_status fetch_scalars(Plan &p, hipStream_t s)
 // 2 learned selector done, 3 selection and compaction done, 4 tree done, 5 lists done,
 // 6 upward done, 7 downward done, 8 far field at the targets done, 9 near field (or
 // direct sum) done.
+// Event k of a slot: 0..7 on the caller's stream (start, then the ends of reduce, selector,
+// select, tree, upward, downward, far field); 8..10 on the second stream (start of the lists,
+// end of the lists, end of the near field).
+static float phase_ms(Plan &p, int slot, int k)
+{
+    static const int from[9] = {0, 1, 2, 3, 8, 4, 5, 6, 9};
+    static const int to[9] = {1, 2, 3, 4, 9, 5, 6, 7, 10};
+    float ms = 0;
+    PH_HIP(hipEventElapsedTime(&ms, p.ring[slot][from[k]], p.ring[slot][to[k]]));
+    return ms;
+}
+
 static void harvest_slot(Plan &p, int slot)
 {
     if (!p.ring_used[slot]) return;
-    PH_HIP(hipEventSynchronize(p.ring[slot][Plan::kMarks - 1]));
-    for (int k = 0; k + 1 < Plan::kMarks; ++k) {
-        float ms = 0;
-        PH_HIP(hipEventElapsedTime(&ms, p.ring[slot][k], p.ring[slot][k + 1]));
-        p.phase_sum[k] += ms;
-    }
+    PH_HIP(hipEventSynchronize(p.ring[slot][7]));
+    PH_HIP(hipEventSynchronize(p.ring[slot][10]));
+    for (int k = 0; k < 9; ++k) p.phase_sum[k] += phase_ms(p, slot, k);
     p.phase_calls += 1;
     p.ring_used[slot] = false;
 }
@@ -691,38 +739,54 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             harvest_slot(p, slot);  // a slot from kRing calls ago: long finished
             p.ring_pos = (p.ring_pos + 1) % Plan::kRing;
         }
-        auto mark = [&](int k) {
-            if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], s));
+        auto mark = [&](int k, hipStream_t on) {
+            if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], on));
         };
         const bool learned = p.selector == PH_SEL_LEARNED;
-        mark(0);
+        if (++p.call_gen == 0) p.call_gen = 1;
+        mark(0, s);
         launch_reset_scalars(p.d_sc, s);
         if (learned) selector_reduce(p, I, absE, s);  // the maxima come with the per-leaf statistics
         else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_scan_tmp, s);
-        mark(1);
+        mark(1, s);
         if (learned) selector_decide(p, I, absE, s);
-        mark(2);
-        launch_select_flags(p, I, absE, S_out, s, learned ? p.d_drop : nullptr);
-        exclusive_scan_u64(p.d_flag, p.n, p.d_scan_tmp, &p.d_sc->packed_total, s);
-        launch_compact(p, I, s);
-        mark(3);
+        mark(2, s);
+        launch_select(p, I, absE, S_out, s, learned ? p.d_drop : nullptr);
+        mark(3, s);
         if (p.method == PH_METHOD_DIRECT) {
-            for (int k = 4; k <= 8; ++k) mark(k);
+            for (int k = 4; k <= 7; ++k) mark(k, s);
+            mark(8, s);
+            mark(9, s);
             run_direct(p, S_out, s);
-            mark(9);
+            mark(10, s);
         } else {
             build_tree(p, s);
-            mark(4);
-            build_lists(p, s);
-            mark(5);
+            mark(4, s);
+            // The lists and the near field run on the second stream: the upward pass and the M2L
+            // products need only the tree; the L2L / gather chain waits for the lists (X lists),
+            // and the far-field kernels, which combine both fields into the output, for the near
+            // field.
+            PH_HIP(hipEventRecord(p.ev_fork, s));
+            PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+            mark(8, p.side);
+            build_lists(p, p.side);
+            mark(9, p.side);
+            PH_HIP(hipEventRecord(p.ev_lists, p.side));
+            fmm_near(p, p.side);
+            mark(10, p.side);
+            PH_HIP(hipEventRecord(p.ev_join, p.side));
             fmm_upward(p, s);
-            mark(6);
-            fmm_downward(p, s);
-            mark(7);
-            fmm_leaf(p, S_out, s);
-            mark(8);
-            fmm_near(p, S_out, s);
-            mark(9);
+            mark(5, s);
+            fmm_downward(p, s, p.ev_lists);
+            mark(6, s);
+            // far field: the matrix-core kernel here, the other leaf kernels on the second stream
+            PH_HIP(hipEventRecord(p.ev_down, s));
+            PH_HIP(hipStreamWaitEvent(p.side, p.ev_down, 0));
+            PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));
+            fmm_leaf(p, S_out, s, p.side);
+            PH_HIP(hipEventRecord(p.ev_rest, p.side));
+            PH_HIP(hipStreamWaitEvent(s, p.ev_rest, 0));
+            mark(7, s);
         }
         PH_HIP(hipGetLastError());
         if (timed) p.ring_used[slot] = true;
@@ -744,11 +808,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
                 (learned && !p.h_sc.fallback) ? (int64_t)p.h_sc.n_src_base - p.h_sc.n_src : 0;
             stats->n_leaves = learned ? p.h_sc.n_srcleaf : 0;
             for (int k = 0; k < 12; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
-            for (int k = 0; k + 1 < Plan::kMarks; ++k) {
-                float ms = 0;
-                PH_HIP(hipEventElapsedTime(&ms, p.ring[slot][k], p.ring[slot][k + 1]));
-                stats->t_ms[k] = ms;
-            }
+            for (int k = 0; k < 9; ++k) stats->t_ms[k] = phase_ms(p, slot, k);
         }
         if (stats && stats->fell_back) return PH_EFALLBACK;
         return PH_OK;
@@ -766,7 +826,7 @@ ph_status ph_phase_times(ph_plan *plan, int record, double *ms_sum, int64_t *n_c
         PH_HIP(hipSetDevice(p.device));
         for (int k = 0; k < Plan::kRing; ++k) harvest_slot(p, k);
         if (ms_sum)
-            for (int k = 0; k < PH_NPHASES; ++k) ms_sum[k] = k + 1 < Plan::kMarks ? p.phase_sum[k] : 0.0;
+            for (int k = 0; k < PH_NPHASES; ++k) ms_sum[k] = k < 9 ? p.phase_sum[k] : 0.0;
         if (n_calls) *n_calls = p.phase_calls;
         for (double &v : p.phase_sum) v = 0.0;
         p.phase_calls = 0;
@@ -809,8 +869,20 @@ ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, 
         switch (what) {
         case 0: copy(p.d_key, p.n, 8); break;
         case 1: copy(p.d_perm, p.n, 4); break;
-        case 2: copy(p.d_s_pos, p.h_sc.n_src, 4); break;
-        case 3: copy(p.d_t_pos, p.h_sc.n_tgt, 4); break;
+        case 2:
+        case 3: {
+            // sorted positions of the selected sources (2) or targets (3), from the flags
+            std::vector<uint8_t> sel((size_t)p.n);
+            PH_HIP(hipMemcpy(sel.data(), p.d_sel, (size_t)p.n, hipMemcpyDeviceToHost));
+            const uint8_t bit = what == 2 ? 1 : 2;
+            std::vector<int32_t> pos;
+            for (int64_t k = 0; k < p.n; ++k)
+                if (sel[k] & bit) pos.push_back((int32_t)k);
+            *n_out = (int64_t)pos.size();
+            size_t bytes = std::min<size_t>(pos.size() * 4, cap_bytes > 0 ? (size_t)cap_bytes : 0);
+            if (bytes && dst) std::memcpy(dst, pos.data(), bytes);
+            break;
+        }
         case 4: {
             // assemble the box table level by level (levels are stored at fixed bases)
             std::vector<int32_t> tab;

@@ -54,6 +54,7 @@ struct CallScalars {
     int32_t n_u, n_w, n_x;              // list lengths
     int32_t n_far_a, n_far_b, n_near;   // leaf lists of the target-side kernels
     int32_t n_far_a_lvl[kMaxDepth + 2]; // grid-operator leaves per level (segments of far_a)
+    int32_t n_vt_lvl[kMaxDepth + 2];    // boxes with a V or X list per level (segments of vt)
     int32_t n_src_dropped;              // learned selector
     int32_t min_leafsrc_level;          // lowest level holding a leaf with sources
     int32_t fallback;                   // learned selector fell back to the threshold rule
@@ -61,7 +62,6 @@ struct CallScalars {
     int32_t n_src_base;                 // candidate sources of the learned decisions (kept + dropped)
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t emax_key;                  // |E| bits << 32 | ~caller index of the largest |E|
-    uint64_t lvl_pack[kMaxDepth + 2];   // packed per-level totals (boxes | source boxes << 32)
     // algorithmic work of the call (integer counters, order independent)
     unsigned long long work[12];        // p2p pairs, l2p evals, m2p evals, p2m evals,
                                         // p2l evals, m2l pairs, m2m children, l2l boxes,
@@ -81,11 +81,9 @@ struct BoxArrays {
     // per call (boxes outside the per-call tree have zero counts and no flags)
     int32_t *s_first = nullptr, *s_cnt = nullptr, *t_first = nullptr, *t_cnt = nullptr;
     int32_t *flags = nullptr;
-    uint64_t *srcflag = nullptr;    // scan scratch: (has sources | split with targets << 32) (box_cap + 1)
-    int32_t *src_rank = nullptr;    // rank of a box among its level's boxes with sources (-1 if none)
+    int32_t *src_rank = nullptr;    // slot of a box among its level's boxes with sources (-1 if none)
     int32_t *src_box = nullptr;     // per-level slots: box of each source rank
-    int32_t *tpar_rank = nullptr;   // rank among the level's split boxes with targets (-1 if none)
-    int32_t *tpar_box = nullptr;    // per-level slots: box of each such rank
+    int32_t *tpar_box = nullptr;    // per-level slots: the split boxes with targets
 };
 
 // Interaction lists in CSR form over all boxes (offsets box_cap + 1)
@@ -98,6 +96,9 @@ struct Lists {
     // non-empty U list (near field); box_cap entries each
     int32_t *far_b = nullptr, *near_leaves = nullptr;
     int4 *far_a = nullptr;  // (box, first target, target count, 1 near | 2 W list)
+    // boxes of levels >= 3 with targets and a non-empty V or X list, per-level segments at the
+    // level's box base; a box is entered once per call through vt_tag (the call's number)
+    int32_t *vt = nullptr, *vt_tag = nullptr;
 };
 
 struct Gas {
@@ -136,6 +137,8 @@ struct Plan {
     size_t z_cap_cols = 0;   // target parents per level (Z buffer columns)
     void *d_z = nullptr;     // parent-to-child (and child-to-parent) translations: z_cap_cols x (8 n_lam)
     size_t y_cap_cols = 0;   // source boxes per translation chunk (Y buffer columns)
+    bool y_all_levels = false;            // Y holds every level at once (one M2L product)
+    int64_t y_lvl_col[kMaxDepth + 2] = {};  // ... at these first columns
     void *d_y = nullptr;     // translation products: y_cap_cols x (316 n_lam)
     int leaf_cap = 64;
     int max_depth = 0;       // deepest level any per-call tree may reach
@@ -189,12 +192,14 @@ struct Plan {
     uint64_t *d_flag = nullptr;     // n packed (src | tgt << 32) flags, scanned in place
     void *d_scan_tmp = nullptr;     // scan partials
     size_t scan_tmp_bytes = 0;
-    int32_t *d_s_pos = nullptr, *d_t_pos = nullptr;   // sorted positions of selected points
+    float4 *d_xyzf = nullptr;       // FP32 plans: sorted coordinates as float4 (x, y, z, 0)
+    uint8_t *d_bnd = nullptr;       // 1 at the first point of a box and at the point after a box
     int32_t *d_t_out = nullptr;     // caller index of each selected target (output position)
     void *d_s_dat = nullptr;        // sources: (x, y, z, q = w * I * 2^-e), float4 or double4
     void *d_t_dat = nullptr;        // targets: (x, y, z, self = c_self * I * 2^-e or 0)
+    uint8_t *d_sel = nullptr;       // selection flags per sorted point (bit 0 source, bit 1 target)
     int32_t *d_s_cell = nullptr, *d_t_cell = nullptr; // packed cell indices (grid mode)
-    void *d_t_far = nullptr;        // far field of targets whose leaf has near sources
+    double *d_t_near = nullptr;     // near field (P2P) of targets whose leaf has a U list
     BoxArrays box;
     Lists lists;
     void *d_phi = nullptr;          // box_cap x n_lam upward densities
@@ -205,7 +210,8 @@ struct Plan {
     float *d_sel_params = nullptr;  // device copy of the selector weights
     // per-phase timing: a ring of event sets, one set per recorded call
     static constexpr int kRing = 32;
-    static constexpr int kMarks = 10;         // boundaries of the 9 phases
+    // marks 0..7 on the caller's stream, 8..10 on the plan's second stream (lists, near field)
+    static constexpr int kMarks = 11;
     hipEvent_t ring[kRing][kMarks] = {};
     bool ring_used[kRing] = {};
     int ring_pos = 0;
@@ -213,6 +219,13 @@ struct Plan {
     double phase_sum[PH_NPHASES] = {};
     int64_t phase_calls = 0;
     bool events_ready = false;
+    // the interaction lists and the near field run on a second stream, forked from the
+    // caller's stream after the tree; the downward chain waits for the lists (ev_lists), the
+    // far-field kernels (which write the output) for the near field (ev_join)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_lists = nullptr, ev_join = nullptr;
+    hipEvent_t ev_down = nullptr, ev_rest = nullptr;  // downward done (main); far kernels on side done
+    uint32_t call_gen = 0;  // number of the current call (never 0)
     bool count_work = false;        // algorithmic work counters (only for calls that fetch stats)
     bool near_guard = true;         // near pairs may have (b - a) r < 1/4: small-argument series needed
     size_t bytes_allocated = 0;
@@ -264,9 +277,10 @@ void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, in
                        CallScalars *sc, void *tmp /* >= 16 KiB */, hipStream_t s);
 void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
                              hipStream_t s);  // partials: up to 1024 blocks
-void launch_select_flags(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s,
-                         const uint8_t *drop = nullptr);
-void launch_compact(const Plan &p, const void *I, hipStream_t s);
+// selection flags, their scan (kept in d_flag for the tree build) and the compaction
+void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop);
+void scan_tile_sums_u64(uint64_t *partial, int64_t nb, uint64_t *total, hipStream_t s);
+void launch_pack_xyzf(const double *xyz, int64_t n, float4 *out, hipStream_t s);
 
 // tree (k_tree.hip)
 void build_tree(Plan &p, hipStream_t s);
@@ -274,11 +288,14 @@ void build_lists(Plan &p, hipStream_t s);
 
 // fmm (k_fmm.hip, k_m2l.hip)
 void fmm_upward(Plan &p, hipStream_t s);
-void fmm_downward(Plan &p, hipStream_t s);
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t lists_ready);  // waits for lists_ready before the gathers
 void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
-void fmm_leaf(Plan &p, void *S_out, hipStream_t s);  // far field at targets (L2P, M2P, own cell)
-void fmm_near(Plan &p, void *S_out, hipStream_t s);  // near field (P2P) and the final combine
+// far field at targets (L2P, M2P, own cell) + output: the matrix-core kernel on s, the other
+// leaf kernels on s_aux (both streams must already be ordered after the downward pass and
+// the near field)
+void fmm_leaf(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux);
+void fmm_near(Plan &p, hipStream_t s);  // near field (P2P) of the targets of leaves with a U list
 
 // direct sum (k_direct.hip)
 void run_direct(Plan &p, void *S_out, hipStream_t s);
