@@ -54,6 +54,22 @@ __device__ __forceinline__ bool seg_tile(const GemmSegs &sg, const int32_t *__re
     return false;
 }
 
+// Whether any source box of the column tile sends one of the offsets of rows m0 .. m0 + 63 to a
+// target (use: the per-box offset masks); a tile that reaches no target is not computed (the
+// gathers never read those rows).  Called by the whole workgroup.
+__device__ __forceinline__ bool tile_used(const uint32_t *__restrict__ use, const GemmSeg &sg, int32_t n0,
+                                          int32_t ncols, int m0, int M, int nl)
+{
+    const int t = threadIdx.x;
+    const int o_lo = m0 / nl, o_hi = min(M - 1, m0 + kTile - 1) / nl;
+    bool any = false;
+    if (t < kTile && n0 + t < ncols) {
+        const uint32_t *um = use + (size_t)(sg.list_base + sg.r0 + n0 + t) * kUseWords;
+        for (int o = o_lo; o <= o_hi && !any; ++o) any = (um[o >> 5] >> (o & 31)) & 1u;
+    }
+    return __syncthreads_or(any) != 0;
+}
+
 // Translation GEMM on the matrix cores, out^T = X^T Op^T with Op (M x kp, row-major) a
 // stacked translation operator and X (kp x ncols) the gathered columns, over one or more
 // levels (segments) in one launch:
@@ -67,7 +83,8 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                                                     const int32_t *__restrict__ count, GemmSegs segs,
                                                     T *__restrict__ out0, const int32_t *__restrict__ child,
                                                     const int32_t *__restrict__ t_cnt,
-                                                    unsigned long long *__restrict__ work)
+                                                    unsigned long long *__restrict__ work,
+                                                    const uint32_t *__restrict__ use)
 {
     // K staged 64 deep for FP32 (one LDS fill when n_lam <= 64), 32 for FP64
     constexpr int KT = sizeof(T) == 4 ? 2 * kTK : kTK;
@@ -87,6 +104,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
         const GemmSeg sg = segs.s[si];
         const T *Op = Op0 + sg.op_off;
         T *out = out0 + (size_t)sg.out_row * M;
+        if (MODE == kModeM2L && use && !tile_used(use, sg, n0, ncols, m0, M, nl)) continue;
         __syncthreads();
         if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         acc_t acc[2][2];
@@ -165,7 +183,8 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
                                                               int nl, const float *__restrict__ vec,
                                                               const int32_t *__restrict__ list,
                                                               const int32_t *__restrict__ count, GemmSegs segs,
-                                                              float *__restrict__ out0)
+                                                              float *__restrict__ out0,
+                                                              const uint32_t *__restrict__ use)
 {
     __shared__ __align__(16) uint16_t Ah[kTile][kTK + kPadB], Al[kTile][kTK + kPadB];
     __shared__ __align__(16) uint16_t Bh[kTile][kTK + kPadB], Bl[kTile][kTK + kPadB];
@@ -180,6 +199,7 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
         const GemmSeg sg = segs.s[si];
         const uint16_t *Oh = Oh0 + sg.op_off, *Ol = Ol0 + sg.op_off;
         float *out = out0 + (size_t)sg.out_row * M;
+        if (use && !tile_used(use, sg, n0, ncols, m0, M, nl)) continue;
         __syncthreads();
         if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         f32x4 acc[2][2];
@@ -386,22 +406,24 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
     if (std::is_same<T, float>::value && p.precision == PH_FP32_BF16SPLIT)
         tgemm_m2l_bf16s_kernel<<<g, 256, 0, s>>>((const uint16_t *)p.ops.m2l_hi, (const uint16_t *)p.ops.m2l_lo,
                                                  p.k_pad, M, nl, (const float *)p.d_phi, p.box.src_box,
-                                                 p.d_sc->lvl_src, sg, (float *)p.d_y);
+                                                 p.d_sc->lvl_src, sg, (float *)p.d_y, p.lists.m2l_use);
     else
         tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>((const T *)p.ops.m2l, p.k_pad, M, nl, (const T *)p.d_phi,
                                                     p.box.src_box, p.d_sc->lvl_src, sg, (T *)p.d_y, nullptr,
-                                                    nullptr, nullptr);
+                                                    nullptr, nullptr, p.lists.m2l_use);
 }
 
 template <class T>
-void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t lists_ready)
+void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int nl = p.n_lam;
     const int M = kNumM2L * nl;
     const int D = p.max_depth;
     if (p.y_all_levels && D >= 2) {
-        // every level's M2L products in one launch (they depend on the upward pass only)
+        // every level's M2L products in one launch (they depend on the upward pass and on the
+        // offset masks only)
+        PH_HIP(hipStreamWaitEvent(s, vt_ready, 0));
         GemmSegs sg{};
         int64_t tiles = 0;
         for (int l = 2; l <= D; ++l) {
@@ -423,7 +445,7 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t lists_ready)
             tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(
                 (const T *)p.ops.l2l, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box, p.d_sc->lvl_tpar,
                 one_seg(l - 1, p.level_base[l - 1], 0, pcap, (int64_t)l * Mz * p.k_pad, 0), (T *)p.d_u, p.box.child,
-                p.box.t_cnt, a.work);
+                p.box.t_cnt, a.work, nullptr);
         }
         // level 2: every box (its u starts from zero); deeper levels: the boxes with a V or X list
         const int32_t *vb = l >= 3 ? p.lists.vt + p.level_base[l] : nullptr;
@@ -487,7 +509,7 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
     tgemm_kernel<T, kModeM2M><<<g, 256, 0, s>>>(
         (const T *)p.ops.m2m, p.k_pad, Mw, nl, (const T *)p.d_phi, p.box.src_box, p.d_sc->lvl_src,
         one_seg(l + 1, p.level_base[l + 1], 0, ccap, (int64_t)(l + 1) * Mw * p.k_pad, 0), (T *)p.d_z, nullptr,
-        nullptr, nullptr);
+        nullptr, nullptr, nullptr);
     const int threads = nl <= 64 ? 64 : (nl <= 128 ? 128 : 256);
     m2m_gather_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 8192), threads, 0, s>>>(a, l,
                                                                                               (const T *)p.d_z);
@@ -495,10 +517,10 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
 
 }  // namespace
 
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t lists_ready)
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready)
 {
-    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, lists_ready);
-    else fmm_downward_t<float>(p, s, lists_ready);
+    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, vt_ready, lists_ready);
+    else fmm_downward_t<float>(p, s, vt_ready, lists_ready);
 }
 
 void fmm_m2m_level(Plan &p, int l, hipStream_t s)

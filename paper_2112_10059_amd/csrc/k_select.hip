@@ -176,7 +176,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     const TI *__restrict__ I, const int32_t *__restrict__ perm, const C *__restrict__ xyz,
     const double *__restrict__ w, double w_uniform, double c_self, int64_t n, CallScalars *__restrict__ sc,
     const uint8_t *__restrict__ sel, const uint8_t *__restrict__ bnd, const uint64_t *__restrict__ partial,
-    uint64_t *__restrict__ scanned, int32_t *__restrict__ t_out,
+    int64_t nb, int tile_sums, uint64_t *__restrict__ scanned, int32_t *__restrict__ t_out,
     typename Vec4T<T>::type *__restrict__ s_dat, typename Vec4T<T>::type *__restrict__ t_dat,
     const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell, int32_t *__restrict__ t_cell)
 {
@@ -190,12 +190,34 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
         (void)frexp(imax, &e);
         e -= 1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint64_t total = sc->packed_total;
-        sc->scale_exp = e;
-        sc->n_src = (int32_t)(total & 0xffffffffu);
-        sc->n_tgt = (int32_t)(total >> 32);
+    // the tile's offset: partial holds the tile sums (tile_sums: each workgroup adds up those of
+    // the earlier tiles, and workgroup 0 all of them for the totals) or their exclusive scan
+    uint64_t tile_off;
+    if (tile_sums) {
+        const int64_t upto = blockIdx.x == 0 ? nb : blockIdx.x;
+        uint64_t acc = 0;
+        for (int64_t j = threadIdx.x; j < upto; j += blockDim.x) acc += partial[j];
+        acc = lane_value(wave_inclusive(acc, lane), 63);
+        if (lane == 0) wsum[wv] = acc;
+        __syncthreads();
+        uint64_t sum = 0;
+        for (int q = 0; q < kSelWaves; ++q) sum += wsum[q];
+        __syncthreads();  // wsum is reused below
+        tile_off = blockIdx.x == 0 ? 0 : sum;
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->packed_total = sum;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->n_src = (int32_t)(sum & 0xffffffffu);
+            sc->n_tgt = (int32_t)(sum >> 32);
+        }
+    } else {
+        tile_off = partial[blockIdx.x];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const uint64_t total = sc->packed_total;
+            sc->n_src = (int32_t)(total & 0xffffffffu);
+            sc->n_tgt = (int32_t)(total >> 32);
+        }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->scale_exp = e;
     const double scale = ldexp(1.0, -e);
     const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)wv * kSelSpan;
     uint32_t f[kStrips];
@@ -209,7 +231,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     acc = lane_value(wave_inclusive(acc, lane), 63);
     if (lane == 0) wsum[wv] = acc;
     __syncthreads();
-    uint64_t carry = partial[blockIdx.x];
+    uint64_t carry = tile_off;
     for (int q = 0; q < wv; ++q) carry += wsum[q];
 #pragma unroll
     for (int st = 0; st < kStrips; ++st) {
@@ -316,16 +338,19 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
         select_tiles_kernel<float><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>((const float *)I, need_e ? E : nullptr, p.d_perm,
                                                                  p.n, sp, p.d_sc, drop, p.d_sel, (float *)S_out,
                                                                  partial);
-    scan_tile_sums_u64(partial, nb, &p.d_sc->packed_total, s);
+    // up to 2048 tiles the compaction adds up the earlier tiles' sums itself; beyond, one
+    // workgroup scans them first
+    const int tile_sums = nb <= 2048 ? 1 : 0;
+    if (!tile_sums) scan_tile_sums_u64(partial, nb, &p.d_sc->packed_total, s);
     if (p.precision == PH_FP64)
         select_compact_kernel<double, double, double><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
             (const double *)I, p.d_perm, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
-            partial, p.d_flag, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
+            partial, nb, tile_sums, p.d_flag, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
     else
         select_compact_kernel<float, float, float4><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
             (const float *)I, p.d_perm, p.d_xyzf, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
-            partial, p.d_flag, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
+            partial, nb, tile_sums, p.d_flag, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
 }
 

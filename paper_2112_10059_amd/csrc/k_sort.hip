@@ -332,19 +332,6 @@ void exclusive_scan_u64(uint64_t *data, int64_t n, void *tmp, uint64_t *total, h
     exclusive_scan<uint64_t>(data, n, tmp, total, s);
 }
 
-void exclusive_scan3_u32(uint32_t *a, uint32_t *ta, uint32_t *b, uint32_t *tb, uint32_t *c, uint32_t *tc, int64_t n,
-                         void *tmp, hipStream_t s)
-{
-    if (n <= 0) return;
-    if (n <= kSmallScan) {
-        scan_small_kernel<uint32_t><<<3, 1024, 0, s>>>(ScanJob<uint32_t>{a, ta}, ScanJob<uint32_t>{b, tb},
-                                                       ScanJob<uint32_t>{c, tc}, n);
-        return;
-    }
-    exclusive_scan<uint32_t>(a, n, tmp, ta, s);
-    exclusive_scan<uint32_t>(b, n, tmp, tb, s);
-    exclusive_scan<uint32_t>(c, n, tmp, tc, s);
-}
 
 void launch_morton_keys(const double *xyz, int64_t n, double lo0, double lo1, double lo2, double size,
                         uint64_t *keys, int32_t *idx, hipStream_t s)

@@ -21,7 +21,7 @@
 //                  non-empty V or X list are listed per level).
 #include <hip/hip_runtime.h>
 
-#include "ph_internal.h"
+#include "k_common.h"
 
 namespace ph {
 
@@ -167,11 +167,26 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_lev
     if (bx.t_cnt[b] == 0) return;
     const bool leaf = bx.flags[b] & kBoxLeaf;
     if (leaf) {
-        int32_t stack[8 * kMaxDepth];
+        // the colleagues, then their counts and flags, each set of loads issued together
+        int32_t Cs[27];
+#pragma unroll
+        for (int d = 0; d < 27; ++d) Cs[d] = bx.coll[(size_t)b * 27 + d];
+        uint32_t lmask = 0, smask = 0;  // colleagues with sources: leaves, split boxes
+#pragma unroll
         for (int d = 0; d < 27; ++d) {
+            const int32_t C = Cs[d];
+            const int32_t sn = C >= 0 ? bx.s_cnt[C] : 0;
+            const int32_t fl = C >= 0 ? bx.flags[C] : 0;
+            if (sn > 0) {
+                if (fl & kBoxLeaf) lmask |= 1u << d;
+                else smask |= 1u << d;
+            }
+        }
+        int32_t stack[8 * kMaxDepth];
+        for (uint32_t m = lmask | smask; m; m &= m - 1) {
+            const int d = __ffs((int)m) - 1;
             const int32_t C = bx.coll[(size_t)b * 27 + d];
-            if (C < 0 || bx.s_cnt[C] == 0) continue;
-            if (bx.flags[C] & kBoxLeaf) {
+            if ((lmask >> d) & 1u) {
                 emit(kListU, C);
                 continue;
             }
@@ -209,15 +224,37 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_lev
     }
 }
 
+constexpr int kListBlock = 256;
+
+// Per-workgroup totals of three counts (every thread of the workgroup takes part)
+__device__ __forceinline__ void block_totals3(uint32_t a, uint32_t b, uint32_t c, uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t part[3][kListBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t v[3] = {a, b, c};
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t s = lane_value(wave_inclusive(v[k], lane), 63);
+        if (lane == 0) part[k][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t s = 0;
+        for (int q = 0; q < kListBlock / 64; ++q) s += part[threadIdx.x][q];
+        out[threadIdx.x] = s;
+    }
+}
+
 // List lengths per box, and the leaf lists of the target-side kernels.  grid_levels: bit l
 // set when leaves of level l take their far field from a grid operator (or have none).
-__global__ void list_count_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc, int32_t nbox,
-                                  Lists L, uint32_t grid_levels, uint32_t gen)
+__global__ __launch_bounds__(kListBlock) void list_count_kernel(BoxArrays bx, LevelInfo li,
+                                                                CallScalars *__restrict__ sc, int32_t nbox, Lists L,
+                                                                uint32_t grid_levels, uint32_t gen,
+                                                                uint32_t *__restrict__ block_tot)
 {
-    const int32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid == 0) L.u_off[nbox] = L.w_off[nbox] = L.x_off[nbox] = 0;  // scanned into the totals
-    if (gid >= nbox) return;
-    const int32_t b = box_of_thread(li, sc, gid);
+    const int32_t gid0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = gid0 < nbox;
+    const int32_t gid = in ? gid0 : nbox - 1;  // whole waves reach the block totals
+    const int32_t b = in ? box_of_thread(li, sc, gid) : -1;
     uint32_t nu = 0, nw = 0, nx = 0;
     const int mll = li.depth + 1 - sc->min_leafsrc_level;
     if (b >= 0)
@@ -226,9 +263,12 @@ __global__ void list_count_kernel(BoxArrays bx, LevelInfo li, CallScalars *__res
             else if (kind == kListW) ++nw;
             else ++nx;
         });
-    L.u_off[gid] = nu;
-    L.w_off[gid] = nw;
-    L.x_off[gid] = nx;
+    if (in) {
+        L.u_off[gid] = nu;
+        L.w_off[gid] = nw;
+        L.x_off[gid] = nx;
+    }
+    block_totals3(nu, nw, nx, block_tot + 3 * blockIdx.x);
     const bool tleaf = b >= 0 && (bx.flags[b] & kBoxLeaf) && bx.t_cnt[b] > 0;
     const int lev = b >= 0 ? bx.level[b] : 0;
     const bool grid_leaf = tleaf && ((grid_levels >> lev) & 1u);
@@ -255,18 +295,21 @@ __global__ void list_count_kernel(BoxArrays bx, LevelInfo li, CallScalars *__res
     }
 }
 
-// Boxes of levels >= 3 that receive M2L translations.  B has source box S in its V list iff
-// B is a child of a colleague of S's parent, not adjacent to S, at S's level; so one wave per
-// source box S walks those candidates (the children of the parent's split colleagues) and
-// enters each one with targets once per call into its level's segment of vt.
+// Boxes of levels >= 3 that receive M2L translations, and the offsets each source box sends
+// along.  B has source box S in its V list iff B is a child of a colleague of S's parent, not
+// adjacent to S, at S's level; so one wave per source box S (levels >= 2) walks those
+// candidates (the children of the parent's split colleagues), enters each one with targets
+// once per call into its level's segment of vt (levels >= 3), and records the offset slots
+// used as a 316-bit mask at S's slot in the level's source list (kUseWords words).
 __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc,
                                                       Lists L, uint32_t gen)
 {
-    const int lane = threadIdx.x & 63;
-    for (int32_t idx = blockIdx.x * 4 + (threadIdx.x >> 6);; idx += gridDim.x * 4) {
+    __shared__ uint32_t use[4][kUseWords];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int32_t idx = blockIdx.x * 4 + wv;; idx += gridDim.x * 4) {
         int level = -1;
         int32_t r = idx;
-        for (int l = 3; l <= li.depth; ++l) {
+        for (int l = 2; l <= li.depth; ++l) {
             const int32_t c = sc->lvl_src[l];
             if (r < c) {
                 level = l;
@@ -278,6 +321,7 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
         const int32_t S = bx.src_box[li.base[level] + r];
         const int32_t P = bx.parent[S];
         const int sx = bx.ax[S], sy = bx.ay[S], sz = bx.az[S];
+        if (lane < kUseWords) use[wv][lane] = 0u;
         int32_t Qd = -1;
         if (lane < 27) {
             const int32_t Q = bx.coll[(size_t)P * 27 + lane];
@@ -285,6 +329,7 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
         }
         const uint64_t qmask = __ballot(Qd >= 0);
         const int nc = 8 * __popcll(qmask);
+        __builtin_amdgcn_wave_barrier();
         for (int f0 = 0; f0 < nc; f0 += 64) {
             const int f = f0 + lane;
             uint64_t m = qmask;
@@ -296,23 +341,78 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
             if (f < nc) {
                 B = bx.child[(size_t)Q * 8 + (f & 7)];
                 if (B >= 0 && bx.t_cnt[B] > 0) {
-                    const int dx = bx.ax[B] - sx, dy = bx.ay[B] - sy, dz = bx.az[B] - sz;
+                    const int dx = sx - bx.ax[B], dy = sy - bx.ay[B], dz = sz - bx.az[B];
                     const bool near = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-                    fresh = !near && atomicExch(&L.vt_tag[B], (int)gen) != (int)gen;
+                    if (!near) {
+                        const int slot = m2l_slot(dx, dy, dz);
+                        atomicOr(&use[wv][slot >> 5], 1u << (slot & 31));
+                        fresh = level >= 3 && atomicExch(&L.vt_tag[B], (int)gen) != (int)gen;
+                    }
                 }
             }
             wave_append(fresh, L.vt + li.base[level], &sc->n_vt_lvl[level], B);
         }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < kUseWords) L.m2l_use[(size_t)(li.base[level] + r) * kUseWords + lane] = use[wv][lane];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-__global__ void list_fill_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc, int32_t nbox, Lists L)
+// The lists' entries.  Each workgroup turns its boxes' counts into offsets: the sum of the
+// earlier workgroups' totals (a short loop over block_tot) plus a scan inside the workgroup;
+// the last workgroup also writes the end offsets and the list lengths.
+__global__ __launch_bounds__(kListBlock) void list_fill_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc,
+                                                               int32_t nbox, Lists L,
+                                                               const uint32_t *__restrict__ block_tot)
 {
-    const int32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= nbox) return;
+    __shared__ uint32_t part[3][kListBlock / 64];
+    __shared__ uint32_t base[3];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int32_t gid0 = blockIdx.x * blockDim.x + t;
+    const bool in = gid0 < nbox;
+    const int32_t gid = in ? gid0 : nbox - 1;
+    uint32_t cnt[3] = {0, 0, 0};
+    if (in) {
+        cnt[0] = L.u_off[gid];
+        cnt[1] = L.w_off[gid];
+        cnt[2] = L.x_off[gid];
+    }
+    if (t < 3) {
+        uint32_t acc = 0;
+        for (uint32_t j = 0; j < blockIdx.x; ++j) acc += block_tot[3 * j + t];
+        base[t] = acc;
+    }
+    uint32_t incl[3];
+    for (int k = 0; k < 3; ++k) {
+        incl[k] = wave_inclusive(cnt[k], lane);
+        if (lane == 63) part[k][w] = incl[k];
+    }
+    __syncthreads();
+    uint32_t off[3];
+    for (int k = 0; k < 3; ++k) {
+        uint32_t o = base[k];
+        for (int q = 0; q < w; ++q) o += part[k][q];
+        off[k] = o + incl[k] - cnt[k];
+    }
+    if (in) {
+        L.u_off[gid] = off[0];
+        L.w_off[gid] = off[1];
+        L.x_off[gid] = off[2];
+    }
+    if (blockIdx.x == gridDim.x - 1 && t == blockDim.x - 1) {
+        // the last thread of the last workgroup holds the totals (its box, if any, is the last)
+        const uint32_t tu = off[0] + cnt[0], tw = off[1] + cnt[1], tx = off[2] + cnt[2];
+        L.u_off[nbox] = tu;
+        L.w_off[nbox] = tw;
+        L.x_off[nbox] = tx;
+        sc->n_u = (int32_t)tu;
+        sc->n_w = (int32_t)tw;
+        sc->n_x = (int32_t)tx;
+    }
+    if (!in) return;
     const int32_t b = box_of_thread(li, sc, gid);
     if (b < 0) return;
-    uint32_t pu = L.u_off[gid], pw = L.w_off[gid], px = L.x_off[gid];
+    uint32_t pu = off[0], pw = off[1], px = off[2];
     bool over = false;
     const int mll = li.depth + 1 - sc->min_leafsrc_level;
     enumerate_lists(bx, b, mll, [&](int kind, int32_t C) {
@@ -356,7 +456,7 @@ void build_tree(Plan &p, hipStream_t s)
     tree_status_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.leaf_cap, p.max_depth, p.d_flag, p.n, p.d_sc);
 }
 
-void build_lists(Plan &p, hipStream_t s)
+void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready)
 {
     LevelInfo li = level_info(p);
     const int32_t nbox = (int32_t)p.box_cap;
@@ -365,18 +465,16 @@ void build_lists(Plan &p, hipStream_t s)
     if (p.grid_mode)
         for (int l = 0; l <= p.max_depth; ++l)
             if (l < 2 || p.grid_m[l] > 0) grid_levels |= 1u << l;
-    if (p.method == PH_METHOD_FMM && p.max_depth >= 3) {
+    if (p.method == PH_METHOD_FMM && p.max_depth >= 2) {
         int64_t cap = 0;
-        for (int l = 3; l <= p.max_depth; ++l) cap += p.level_cap[l];
+        for (int l = 2; l <= p.max_depth; ++l) cap += p.level_cap[l];
         vtarget_kernel<<<(unsigned)std::min<int64_t>((cap + 3) / 4, 1024), 256, 0, s>>>(p.box, li, p.d_sc, p.lists,
                                                                                         p.call_gen);
     }
-    list_count_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels, p.call_gen);
-    // nbox + 1 entries: the last one (0 before the scan) receives the total
-    exclusive_scan3_u32(p.lists.u_off, reinterpret_cast<uint32_t *>(&p.d_sc->n_u), p.lists.w_off,
-                        reinterpret_cast<uint32_t *>(&p.d_sc->n_w), p.lists.x_off,
-                        reinterpret_cast<uint32_t *>(&p.d_sc->n_x), nbox + 1, p.d_scan_tmp, s);
-    list_fill_kernel<<<g, 256, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists);
+    PH_HIP(hipEventRecord(vt_ready, s));
+    uint32_t *block_tot = reinterpret_cast<uint32_t *>(p.d_scan_tmp);  // 3 per workgroup
+    list_count_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels, p.call_gen, block_tot);
+    list_fill_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, block_tot);
 }
 
 }  // namespace ph

@@ -202,7 +202,9 @@ void alloc_workspace(Plan &p)
     p.d_flag = (uint64_t *)dev_alloc(p, (size_t)n * sizeof(uint64_t));
     p.d_sel = (uint8_t *)dev_alloc(p, (size_t)n);
     PH_HIP(hipMemset(p.d_sel, 0, (size_t)n));  // nothing selected before the first call
-    p.scan_tmp_bytes = std::max({scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4), (size_t)16384});
+    // also the list build's per-workgroup totals (3 words per 256 boxes)
+    p.scan_tmp_bytes = std::max({scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4),
+                                 (size_t)12 * ((p.box_cap + 255) / 256) + 256, (size_t)16384});
     p.d_scan_tmp = dev_alloc(p, p.scan_tmp_bytes);
     p.d_t_out = (int32_t *)dev_alloc(p, (size_t)n * 4);
     p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);
@@ -237,6 +239,7 @@ void alloc_workspace(Plan &p)
     L.near_leaves = (int32_t *)dev_alloc(p, B * 4);
     L.vt = (int32_t *)dev_alloc(p, B * 4);
     L.vt_tag = (int32_t *)dev_alloc(p, B * 4);
+    L.m2l_use = (uint32_t *)dev_alloc(p, B * 4 * kUseWords);
     PH_HIP(hipMemset(L.vt_tag, 0, B * 4));  // no call has tagged a box yet
     if (p.method == PH_METHOD_FMM) {
         p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
@@ -297,7 +300,7 @@ void free_plan(Plan *p)
                     p->box.child, p->box.coll, p->box.start, p->box.end, p->box.src_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
-                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->d_phi, p->d_u,
+                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_use, p->d_phi, p->d_u,
                     p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
                     p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
                     p->d_row_feat,
@@ -311,6 +314,7 @@ void free_plan(Plan *p)
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->ev_lists) (void)hipEventDestroy(p->ev_lists);
     if (p->ev_down) (void)hipEventDestroy(p->ev_down);
+    if (p->ev_vt) (void)hipEventDestroy(p->ev_vt);
     if (p->ev_rest) (void)hipEventDestroy(p->ev_rest);
     if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
@@ -620,6 +624,7 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     PH_HIP(hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming));
     PH_HIP(hipEventCreateWithFlags(&p.ev_lists, hipEventDisableTiming));
     PH_HIP(hipEventCreateWithFlags(&p.ev_down, hipEventDisableTiming));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_vt, hipEventDisableTiming));
     PH_HIP(hipEventCreateWithFlags(&p.ev_rest, hipEventDisableTiming));
 }
 
@@ -769,7 +774,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             PH_HIP(hipEventRecord(p.ev_fork, s));
             PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
             mark(8, p.side);
-            build_lists(p, p.side);
+            build_lists(p, p.side, p.ev_vt);
             mark(9, p.side);
             PH_HIP(hipEventRecord(p.ev_lists, p.side));
             fmm_near(p, p.side);
@@ -777,7 +782,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             PH_HIP(hipEventRecord(p.ev_join, p.side));
             fmm_upward(p, s);
             mark(5, s);
-            fmm_downward(p, s, p.ev_lists);
+            fmm_downward(p, s, p.ev_vt, p.ev_lists);
             mark(6, s);
             // far field: the matrix-core kernel here, the other leaf kernels on the second stream
             PH_HIP(hipEventRecord(p.ev_down, s));

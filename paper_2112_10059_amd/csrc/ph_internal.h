@@ -32,6 +32,7 @@ void set_last_error(const std::string &s);
 constexpr int kMortonBits = 21;                 // bits per axis of the Morton key
 constexpr int kMaxDepth = 16;                   // deepest octree level supported
 constexpr int kNumM2L = 316;                    // 7^3 - 3^3 well-separated offsets
+constexpr int kUseWords = (kNumM2L + 31) / 32;  // words of a per-box offset mask
 constexpr int kMaxLattice = 512;                // q <= 8
 constexpr int kMaxShell = 6 * 8 * 8 + 2;        // shell of q+1 <= 9 points per edge
 
@@ -99,6 +100,9 @@ struct Lists {
     // boxes of levels >= 3 with targets and a non-empty V or X list, per-level segments at the
     // level's box base; a box is entered once per call through vt_tag (the call's number)
     int32_t *vt = nullptr, *vt_tag = nullptr;
+    // M2L offsets that reach a target, per source box (316 bits in kUseWords words), at the
+    // box's slot in its level's source list
+    uint32_t *m2l_use = nullptr;
 };
 
 struct Gas {
@@ -225,6 +229,7 @@ struct Plan {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_lists = nullptr, ev_join = nullptr;
     hipEvent_t ev_down = nullptr, ev_rest = nullptr;  // downward done (main); far kernels on side done
+    hipEvent_t ev_vt = nullptr;  // V/X targets and M2L offset masks known (side)
     uint32_t call_gen = 0;  // number of the current call (never 0)
     bool count_work = false;        // algorithmic work counters (only for calls that fetch stats)
     bool near_guard = true;         // near pairs may have (b - a) r < 1/4: small-argument series needed
@@ -266,8 +271,6 @@ size_t scan_tmp_bytes(int64_t n, size_t elem);
 void exclusive_scan_u32(uint32_t *data, int64_t n, void *tmp, uint32_t *total, hipStream_t s);
 void exclusive_scan_u64(uint64_t *data, int64_t n, void *tmp, uint64_t *total, hipStream_t s);
 // three independent scans of n elements (totals nullable)
-void exclusive_scan3_u32(uint32_t *a, uint32_t *ta, uint32_t *b, uint32_t *tb, uint32_t *c, uint32_t *tc, int64_t n,
-                         void *tmp, hipStream_t s);
 void launch_gather_sorted(const double *xyz, const double *w, const int32_t *perm, int64_t n,
                           double *xyz_sorted, double *w_sorted, int32_t *iperm, hipStream_t s);
 
@@ -284,11 +287,12 @@ void launch_pack_xyzf(const double *xyz, int64_t n, float4 *out, hipStream_t s);
 
 // tree (k_tree.hip)
 void build_tree(Plan &p, hipStream_t s);
-void build_lists(Plan &p, hipStream_t s);
+void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready);  // records vt_ready once the V/X targets are known
 
 // fmm (k_fmm.hip, k_m2l.hip)
 void fmm_upward(Plan &p, hipStream_t s);
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t lists_ready);  // waits for lists_ready before the gathers
+// waits for vt_ready (offset masks) before the M2L products and for lists_ready before the gathers
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready);
 void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
 // far field at targets (L2P, M2P, own cell) + output: the matrix-core kernel on s, the other
