@@ -158,6 +158,14 @@ __device__ __forceinline__ uint64_t e_key(float e, int64_t i)
     return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
 }
 
+// LDS written by some lanes of a wave and then read by others of the same wave
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- wave scans
 
 template <class T>

@@ -189,14 +189,16 @@ __global__ __launch_bounds__(kUpThreads) void p2m_kernel(FmmArgs<T> a, int depth
 }
 
 // M2M for the split source boxes of one level when n_lam <= 64: one workgroup per parent, wave
-// g translating the children in octants g and g + 4 (lane = parent lattice index, the
-// operator of the child's octant read from L2), the translations summed in octant order.
+// o translating the child in octant o (lane = parent lattice index; the octant's operator rows
+// are read from L2 a batch at a time), the translations summed in octant order.
+constexpr int kM2MThreads = 512;
+
 template <class T>
-__global__ __launch_bounds__(kUpThreads) void m2m_kernel(FmmArgs<T> a, int level)
+__global__ __launch_bounds__(kM2MThreads) void m2m_kernel(FmmArgs<T> a, int level)
 {
     __shared__ T mpart[8][64];
     __shared__ int32_t kids[8];
-    const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, o = t >> 6;
     const int nl = a.n_lam;
     for (int32_t rk = blockIdx.x; rk < a.sc->lvl_src[level]; rk += gridDim.x) {
         const int32_t P = a.bx.src_box[a.lt.base[level] + rk];
@@ -207,31 +209,30 @@ __global__ __launch_bounds__(kUpThreads) void m2m_kernel(FmmArgs<T> a, int level
             kids[t] = (C >= 0 && a.bx.s_cnt[C] > 0) ? C : -1;
         }
         __syncthreads();
-        for (int o = g; o < 8; o += kUpGroups) {
-            const int32_t C = kids[o];
-            T acc = T(0);
-            if (C >= 0) {
-                const T ph = lane < nl ? a.phi[(size_t)C * nl + lane] : T(0);
-                const T *op = a.l2l + ((size_t)(level + 1) * 8 + o) * nl * a.k_pad;  // [child j][parent i]
-                for (int j0 = 0; j0 < nl; j0 += 16) {
-                    T v[16];  // sixteen operator rows in flight, then added in order
+        const int32_t C = kids[o];
+        T acc = T(0);
+        if (C >= 0) {
+            const T ph = lane < nl ? a.phi[(size_t)C * nl + lane] : T(0);
+            const T *op = a.l2l + ((size_t)(level + 1) * 8 + o) * nl * a.k_pad;  // [child j][parent i]
+            constexpr int kRB = sizeof(T) == 4 ? 32 : 16;  // operator rows in flight
+            for (int j0 = 0; j0 < nl; j0 += kRB) {
+                T v[kRB];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u)
-                        v[u] = (lane < nl && j0 + u < nl) ? op[(size_t)(j0 + u) * a.k_pad + lane] : T(0);
+                for (int u = 0; u < kRB; ++u)
+                    v[u] = (lane < nl && j0 + u < nl) ? op[(size_t)(j0 + u) * a.k_pad + lane] : T(0);
 #pragma unroll
-                    for (int u = 0; u < 16; ++u)
-                        if (j0 + u < nl) acc += v[u] * lane_bcast(ph, j0 + u);
-                }
+                for (int u = 0; u < kRB; ++u)
+                    if (j0 + u < nl) acc += v[u] * lane_bcast(ph, j0 + u);
             }
-            mpart[o][lane] = acc;
         }
+        mpart[o][lane] = acc;
         __syncthreads();
         if (t < nl) {
             T v = T(0);
             int nc = 0;
-            for (int o = 0; o < 8; ++o)
-                if (kids[o] >= 0) {
-                    v += mpart[o][t];
+            for (int q = 0; q < 8; ++q)
+                if (kids[q] >= 0) {
+                    v += mpart[q][t];
                     ++nc;
                 }
             a.phi[(size_t)P * nl + t] = v;
@@ -705,7 +706,7 @@ void fmm_upward_t(Plan &p, hipStream_t s)
         // a direct product per parent for small lattices; the level GEMM (all eight octant
         // translations of every child, on the matrix cores) for large ones
         if (p.n_lam <= 64)
-            m2m_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 2048), kUpThreads, 0, s>>>(a, l);
+            m2m_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 2048), kM2MThreads, 0, s>>>(a, l);
         else
             fmm_m2m_level(p, l, s);
     }

@@ -84,7 +84,8 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                                                     T *__restrict__ out0, const int32_t *__restrict__ child,
                                                     const int32_t *__restrict__ t_cnt,
                                                     unsigned long long *__restrict__ work,
-                                                    const uint32_t *__restrict__ use)
+                                                    const uint32_t *__restrict__ use,
+                                                    const int32_t *__restrict__ tag, uint32_t gen)
 {
     // K staged 64 deep for FP32 (one LDS fill when n_lam <= 64), 32 for FP64
     constexpr int KT = sizeof(T) == 4 ? 2 * kTK : kTK;
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
     __shared__ T Bs[KT][kTile + kPad];  // Op^T tile, k-major
     __shared__ int32_t boxes[kTile];
     __shared__ int32_t kid[MODE == kModeL2L ? kTile : 1][8];  // L2L: children of the column boxes
+    __shared__ uint8_t klisted[MODE == kModeL2L ? kTile : 1][8];  // ... holding a level-local part
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wn = w >> 1, wm = w & 1;
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
         __syncthreads();
         if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         acc_t acc[2][2];
+        T own[2][2][4];  // L2L: the children's level-local parts
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
         for (int k0 = 0; k0 < kp; k0 += KT) {
@@ -115,7 +118,9 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
             if (MODE == kModeL2L && k0 == 0)
                 for (int e = t; e < kTile * 8; e += 256) {
                     const int32_t bx = boxes[e >> 3];
-                    kid[e >> 3][e & 7] = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
+                    const int32_t C = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
+                    kid[e >> 3][e & 7] = C;
+                    klisted[e >> 3][e & 7] = C >= 0 && tag[C] == (int32_t)gen;
                 }
             for (int e = t; e < KT * kTile; e += 256) {
                 const int n = e / KT, k = e % KT;
@@ -128,6 +133,20 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                 Bs[k][n] = (gm < M && gk < kp) ? Op[(size_t)gm * kp + gk] : T(0);
             }
             __syncthreads();
+            if (MODE == kModeL2L && k0 == 0) {
+                // the children's level-local parts, loaded while the products run
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j) {
+                        const int gm = m0 + wm * 32 + j * 16 + (lane & 15);
+                        const int c = gm / nl, li = gm - c * nl;
+                        for (int r = 0; r < 4; ++r) {
+                            const int nl_ = wn * 32 + i * 16 + Mfma<T>::row(lane, r);
+                            own[i][j][r] = (n0 + nl_ < ncols && gm < M && klisted[nl_][c])
+                                               ? out0[(size_t)kid[nl_][c] * nl + li]
+                                               : T(0);
+                        }
+                    }
+            }
 #pragma unroll
             for (int ks = 0; ks < KT; ks += 4) {
                 const int kk = ks + (lane >> 4);
@@ -146,11 +165,12 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                     const int gn = n0 + nl_;
                     if (gn >= ncols || gm >= M) continue;
                     if (MODE == kModeL2L) {
-                        // row c n_lam + li is the check potential li of child c: straight into its u
+                        // row c n_lam + li is the check potential li of child c: into its u, plus
+                        // the level-local part already there if the child has a V or X list
                         const int c = gm / nl, li = gm - c * nl;
                         const int32_t C = kid[nl_][c];
                         if (C < 0) continue;
-                        out0[(size_t)C * nl + li] = acc[i][j][r];
+                        out0[(size_t)C * nl + li] = acc[i][j][r] + own[i][j][r];
                         if (work && li == 0 && t_cnt[C] > 0) atomicAdd(&work[7], 1ull);
                     } else {
                         out[(size_t)gn * M + gm] = acc[i][j][r];
@@ -254,35 +274,55 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
     }
 }
 
-// One workgroup per target box B:
-//   u_B = base + [first chunk: X-list sources of B] + sum over V(B) in this chunk of Y,
-// base = 0 on level 2 in the first chunk, else the current u_B (the parent's expansion
-// translated by the L2L product, plus earlier chunks).  V(B) = children of the parent's
-// colleagues not adjacent to B: the 8 x (colleagues with sources) candidates are dealt to the
-// four waves in 64-candidate slices (lane = candidate; a ballot marks those with sources in
-// this chunk) and each wave walks its set bits in candidate order, kB translations in flight;
-// the X list is dealt to the waves in turn.  The waves' partial sums are added to the base in
-// wave order.  boxes == nullptr: every box of the level, else the listed ones.
-template <class T>
-__global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int level, const T *__restrict__ Y, int M,
-                                                          int32_t r0, int32_t ccap, int init, int with_x,
-                                                          const int32_t *__restrict__ boxes,
-                                                          const int32_t *__restrict__ n_boxes)
+// The level-local part of the check values, one workgroup per target box B:
+//   w_B = base + [first chunk: X-list sources of B] + sum over V(B) in this chunk of Y,
+// base = 0 in the first chunk, else the earlier chunks' sum; w_B is stored in u_B, and the L2L
+// product of the next level adds the parent's expansion to it.  V(B) = children of the
+// parent's colleagues not adjacent to B: the 8 x (colleagues with sources) candidates are
+// dealt to the four waves in 64-candidate slices (lane = candidate; a ballot marks those with
+// sources in this chunk) and each wave walks its set bits in candidate order, kB translations
+// in flight; the X list is dealt to the waves in turn.  The waves' partial sums are added to
+// the base in wave order.  The boxes: every box of level 2 and the listed boxes (V or X list)
+// of the deeper levels in gl.lo .. gl.hi, dealt to the workgroups as one flat range.
+struct GatherLevels {
+    int lo, hi;                      // levels
+    int64_t y_row[kMaxDepth + 2];    // first row of each level's products in Y
+};
+
+template <class T, int NK>
+__global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, GatherLevels gl, const T *__restrict__ Y0,
+                                                          int M, int32_t r0, int32_t ccap, int init, int with_x)
 {
     __shared__ T part[4][kMaxLattice];
+    __shared__ int32_t qs[4][27];   // per wave: the parent's colleagues with sources
+    __shared__ int32_t cds[4][64];  // per wave: a slice's translations
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int32_t ns = a.sc->lvl_src[level];
-    const int32_t ncols = min(ccap, ns - r0);
-    if (!with_x && ncols <= 0) return;  // an empty chunk: the whole grid
     const int nl = a.n_lam;
-    const int nk = (nl + 63) / 64;
-    const int32_t nbox = boxes ? *n_boxes : a.sc->lvl_count[level];
-    for (int32_t i = blockIdx.x; i < nbox; i += gridDim.x) {
-        const int32_t b = boxes ? boxes[i] : a.lt.base[level] + i;
+    constexpr int nk = NK;  // lattice values per lane: n_lam <= 64 NK
+    for (int32_t idx = blockIdx.x;; idx += gridDim.x) {
+        int level = -1;
+        int32_t i = idx;
+        for (int l = gl.lo; l <= gl.hi; ++l) {
+            const int32_t c = l == 2 ? a.sc->lvl_count[2] : a.sc->n_vt_lvl[l];
+            if (i < c) {
+                level = l;
+                break;
+            }
+            i -= c;
+        }
+        if (level < 0) break;
+        const int32_t ncols = min(ccap, a.sc->lvl_src[level] - r0);
+        if (!with_x && ncols <= 0) continue;  // nothing of this level in the chunk
+        const int32_t b = level == 2 ? a.lt.base[2] + i : a.L.vt[a.lt.base[level] + i];
         if (a.bx.t_cnt[b] == 0) continue;
+        int64_t yrow = 0;  // constant indices only (no private copy of the argument block)
+#pragma unroll
+        for (int l = 0; l < kMaxDepth + 2; ++l)
+            if (l == level) yrow = gl.y_row[l];
+        const T *__restrict__ Y = Y0 + (size_t)yrow * M;
         const int32_t par = a.bx.parent[b];
-        T acc[kMaxLattice / 64];
-        for (int k = 0; k < kMaxLattice / 64; ++k) acc[k] = T(0);
+        T acc[NK];
+        for (int k = 0; k < NK; ++k) acc[k] = T(0);
         unsigned long long n_m2l = 0, n_p2l = 0;
         if (with_x) {
             // X list: sources of coarser leaves straight onto the check points
@@ -298,9 +338,10 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
                     n_p2l += (unsigned long long)sn * nl;
                     for (int j = 0; j < sn; ++j) {
                         const V4<T> y = a.s_dat[sf + j];
-                        for (int k = 0; k < nk; ++k) {
+#pragma unroll
+                        for (int k = 0; k < NK; ++k) {
                             const int li = lane + 64 * k;
-                            if (li >= nl) break;
+                            if (k >= nk || li >= nl) break;
                             const T ddx = cx + h * a.lat[3 * li] - y.x, ddy = cy + h * a.lat[3 * li + 1] - y.y,
                                     ddz = cz + h * a.lat[3 * li + 2] - y.z;
                             acc[k] += kernel_eval<true>(ddx * ddx + ddy * ddy + ddz * ddz, a.kp) * y.w;
@@ -319,16 +360,16 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
         }
         const uint64_t qmask = __ballot(Qd >= 0);
         const int nc = 8 * __popcll(qmask);
+        const uint64_t below = (1ull << lane) - 1ull;
+        // the colleagues with sources, compacted in colleague order (this wave's LDS row)
+        if (Qd >= 0) qs[w][__popcll(qmask & below)] = Qd;
+        wave_lds_sync();
         for (int f0 = 64 * w; f0 < nc; f0 += 256) {
             const int f = f0 + lane;
             const bool valid = f < nc;
-            // colleague of flat candidate f: the (f / 8)-th colleague with sources
-            uint64_t m = qmask;
-            for (int j = valid ? (f >> 3) : 0; j > 0; --j) m &= m - 1;
-            const int d = m ? __ffsll((long long)m) - 1 : 0;
-            const int32_t Q = __shfl(Qd, d);  // every lane takes part
-            int32_t code = -1;              // rank * 316 + slot
+            int32_t code = -1;  // rank * 316 + slot
             if (valid) {
+                const int32_t Q = qs[w][f >> 3];  // the (f / 8)-th colleague with sources
                 const int32_t A = a.bx.child[(size_t)Q * 8 + (f & 7)];
                 if (A >= 0) {
                     const int32_t sr = a.bx.src_rank[A];
@@ -340,39 +381,38 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
                     }
                 }
             }
-            // kB translations at a time: their loads issued together, then added in order
-            uint64_t mask = __ballot(code >= 0);
-            n_m2l += __popcll(mask);
-            while (mask) {
-                constexpr int kB = sizeof(T) == 4 ? 16 : 8;
-                int32_t cd[kB];
-                int nb = 0;
+            // the slice's translations compacted in candidate order, then read kB at a time
+            // (loads issued together, added in order)
+            const uint64_t mask = __ballot(code >= 0);
+            const int n = __popcll(mask);
+            n_m2l += n;
+            if (code >= 0) cds[w][__popcll(mask & below)] = code;
+            wave_lds_sync();
+            constexpr int kB = sizeof(T) == 4 ? 16 : 8;
+            for (int u0 = 0; u0 < n; u0 += kB) {
 #pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    cd[u] = -1;
-                    if (mask) {
-                        const int src_lane = __ffsll((long long)mask) - 1;
-                        mask &= mask - 1;
-                        cd[u] = __builtin_amdgcn_readlane(code, src_lane);
-                        ++nb;
-                    }
-                }
-                for (int k = 0; k < nk; ++k) {
+                for (int k = 0; k < NK; ++k) {
+                    if (k >= nk) break;
                     const int li = lane + 64 * k;
                     T v[kB];
 #pragma unroll
-                    for (int u = 0; u < kB; ++u)
-                        v[u] = (u < nb && li < nl) ? Y[(size_t)(cd[u] / kNumM2L) * M + (size_t)(cd[u] % kNumM2L) * nl + li]
-                                                   : T(0);
+                    for (int u = 0; u < kB; ++u) {
+                        const int32_t c = u0 + u < n ? cds[w][u0 + u] : 0;
+                        v[u] = (u0 + u < n && li < nl)
+                                   ? Y[(size_t)(c / kNumM2L) * M + (size_t)(c % kNumM2L) * nl + li]
+                                   : T(0);
+                    }
 #pragma unroll
                     for (int u = 0; u < kB; ++u)
-                        if (u < nb && li < nl) acc[k] += v[u];
+                        if (u0 + u < n && li < nl) acc[k] += v[u];
                 }
             }
+            wave_lds_sync();  // the slice's codes have been read
         }
-        for (int k = 0; k < nk; ++k) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
             const int li = lane + 64 * k;
-            if (li < nl) part[w][li] = acc[k];
+            if (k < nk && li < nl) part[w][li] = acc[k];
         }
         __syncthreads();
         for (int li = threadIdx.x; li < nl; li += 256) {
@@ -385,6 +425,20 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, int leve
             if (n_m2l) atomicAdd(&a.work[5], n_m2l);
             if (n_p2l) atomicAdd(&a.work[4], n_p2l);
         }
+    }
+}
+
+template <class T>
+void launch_gather(Plan &p, const FmmArgs<T> &a, unsigned grid, const GatherLevels &gl, int M, int32_t r0,
+                   int32_t ccap, int init, int with_x, hipStream_t s)
+{
+    const T *Y = (const T *)p.d_y;
+    switch ((p.n_lam + 63) / 64) {
+    case 1: down_gather_kernel<T, 1><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
+    case 2: down_gather_kernel<T, 2><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
+    case 3:
+    case 4: down_gather_kernel<T, 4><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
+    default: down_gather_kernel<T, 8><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
     }
 }
 
@@ -410,7 +464,7 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
     else
         tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>((const T *)p.ops.m2l, p.k_pad, M, nl, (const T *)p.d_phi,
                                                     p.box.src_box, p.d_sc->lvl_src, sg, (T *)p.d_y, nullptr,
-                                                    nullptr, nullptr, p.lists.m2l_use);
+                                                    nullptr, nullptr, p.lists.m2l_use, nullptr, 0u);
 }
 
 template <class T>
@@ -433,38 +487,43 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
         }
         m2l_product<T>(p, sg, tiles, s);
     }
-    PH_HIP(hipStreamWaitEvent(s, lists_ready, 0));  // the gathers read the X lists
-    for (int l = 2; l <= D; ++l) {
-        const int64_t cap = p.level_cap[l];
-        if (l >= 3) {
-            // u of every child of the split boxes with targets at level l - 1 = L2L_all (8 n_lam x
-            // n_lam) applied to the parent's u, written straight into the children's rows
-            const int Mz = 8 * nl;
-            const int64_t pcap = p.level_cap[l - 1];
-            dim3 gz((Mz + kTile - 1) / kTile, (unsigned)std::min<int64_t>(1024, (pcap + kTile - 1) / kTile));
-            tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(
-                (const T *)p.ops.l2l, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box, p.d_sc->lvl_tpar,
-                one_seg(l - 1, p.level_base[l - 1], 0, pcap, (int64_t)l * Mz * p.k_pad, 0), (T *)p.d_u, p.box.child,
-                p.box.t_cnt, a.work, nullptr);
+    PH_HIP(hipStreamWaitEvent(s, lists_ready, 0));  // the gathers read the X and V/X target lists
+    // level-local parts (V and X lists) of every level: no dependence between levels
+    int64_t gcap = 0;
+    for (int l = 2; l <= D; ++l) gcap += p.level_cap[l];
+    const unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>(gcap, 16384));
+    if (p.y_all_levels) {
+        GatherLevels gl{};
+        gl.lo = 2;
+        gl.hi = D;
+        for (int l = 2; l <= D; ++l) gl.y_row[l] = p.y_lvl_col[l];
+        if (D >= 2) launch_gather<T>(p, a, gg, gl, M, 0, INT32_MAX, 1, 1, s);
+    } else {
+        for (int l = 2; l <= D; ++l) {
+            GatherLevels gl{};
+            gl.lo = gl.hi = l;
+            const int64_t cap = p.level_cap[l];
+            const int64_t ccap = std::min<int64_t>((int64_t)p.y_cap_cols, cap);
+            const int nchunk = (int)((cap + ccap - 1) / ccap);
+            const unsigned gl_grid = (unsigned)std::min<int64_t>(cap, 8192);
+            for (int c = 0; c < nchunk; ++c) {
+                const int64_t r0 = c * ccap;
+                m2l_product<T>(p, one_seg(l, p.level_base[l], r0, ccap, (int64_t)l * M * p.k_pad, 0),
+                               (ccap + kTile - 1) / kTile, s);
+                launch_gather<T>(p, a, gl_grid, gl, M, (int32_t)r0, (int32_t)ccap, c == 0, c == 0, s);
+            }
         }
-        // level 2: every box (its u starts from zero); deeper levels: the boxes with a V or X list
-        const int32_t *vb = l >= 3 ? p.lists.vt + p.level_base[l] : nullptr;
-        const int32_t *vn = l >= 3 ? &p.d_sc->n_vt_lvl[l] : nullptr;
-        const unsigned gg = (unsigned)std::min<int64_t>(cap, 8192);
-        if (p.y_all_levels) {
-            down_gather_kernel<T><<<gg, 256, 0, s>>>(a, l, (const T *)p.d_y + (size_t)p.y_lvl_col[l] * M, M, 0,
-                                                     (int32_t)cap, l == 2, 1, vb, vn);
-            continue;
-        }
-        const int64_t ccap = std::min<int64_t>((int64_t)p.y_cap_cols, cap);
-        const int nchunk = (int)((cap + ccap - 1) / ccap);
-        for (int c = 0; c < nchunk; ++c) {
-            const int64_t r0 = c * ccap;
-            m2l_product<T>(p, one_seg(l, p.level_base[l], r0, ccap, (int64_t)l * M * p.k_pad, 0),
-                           (ccap + kTile - 1) / kTile, s);
-            down_gather_kernel<T><<<gg, 256, 0, s>>>(a, l, (const T *)p.d_y, M, (int32_t)r0, (int32_t)ccap,
-                                                     l == 2 && c == 0, c == 0, vb, vn);
-        }
+    }
+    // u of every child of the split boxes with targets at level l - 1 = L2L_all (8 n_lam x n_lam)
+    // applied to the parent's u, plus the child's level-local part
+    for (int l = 3; l <= D; ++l) {
+        const int Mz = 8 * nl;
+        const int64_t pcap = p.level_cap[l - 1];
+        dim3 gz((Mz + kTile - 1) / kTile, (unsigned)std::min<int64_t>(1024, (pcap + kTile - 1) / kTile));
+        tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(
+            (const T *)p.ops.l2l, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box, p.d_sc->lvl_tpar,
+            one_seg(l - 1, p.level_base[l - 1], 0, pcap, (int64_t)l * Mz * p.k_pad, 0), (T *)p.d_u, p.box.child,
+            p.box.t_cnt, a.work, nullptr, p.lists.vt_tag, p.call_gen);
     }
 }
 
@@ -509,7 +568,7 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
     tgemm_kernel<T, kModeM2M><<<g, 256, 0, s>>>(
         (const T *)p.ops.m2m, p.k_pad, Mw, nl, (const T *)p.d_phi, p.box.src_box, p.d_sc->lvl_src,
         one_seg(l + 1, p.level_base[l + 1], 0, ccap, (int64_t)(l + 1) * Mw * p.k_pad, 0), (T *)p.d_z, nullptr,
-        nullptr, nullptr, nullptr);
+        nullptr, nullptr, nullptr, nullptr, 0u);
     const int threads = nl <= 64 ? 64 : (nl <= 128 ? 128 : 256);
     m2m_gather_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 8192), threads, 0, s>>>(a, l,
                                                                                               (const T *)p.d_z);
