@@ -7,8 +7,8 @@ The measured configuration is the learned leaf selector (committed weights,
 candidates I >= base_src_rel max I, threshold fallback 1e-4) with FP32 kernels
 and an FP64 final combine.  A step is one ph_evaluate: maxima, selector
 decisions, selection + compaction, per-call octree, interaction lists, upward
-pass, translations, far field at the targets, near field and the scatter to
-caller order, with I and |E| already resident in HBM.
+pass, translations, near field, far field at the targets with the final combine
+and the scatter to caller order, with I and |E| already resident in HBM.
 
 The printed JSON line carries targets/s, the roofline of the near-field kernel
 (hipEvent time of its phase inside the timed region), the FP64 oracle timed on
@@ -318,7 +318,7 @@ def roofline(phases, st):
     else:
         r = {"bound": "hbm", "achieved": gb, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r.update({"traffic": measured_traffic(), "kernel": "near_kernel (P2P over the U lists, FP64 combine, scatter to caller order)",
+    r.update({"traffic": measured_traffic(), "kernel": "near_kernel (P2P over the U lists, FP64 combine into the near-field buffer)",
               "avg_ms": phases["near"], "algorithmic_flops": pw["flops"], "algorithmic_bytes": pw["bytes"],
               "other_bound_frac": (gb / PEAK_HBM_GBS) if r["bound"] == "alu" else (tf / PEAK_FP32_TFLOPS)})
     return r

@@ -637,9 +637,10 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
 
 // Exact near field (Sec. 2.4 eq. (16)) of the leaves with a U list, one workgroup of
 // kNearWaves waves per leaf over the list.  The leaf's work items are (U entry, chunk of 64
-// of its sources), dealt to the waves in turn; each wave keeps a Kahan-compensated FP32 sum
-// (FP64 in the FP64 form) per target with the sources broadcast lane by lane from
-// registers.  The partial sums are combined in FP64 in wave order (so the result does not
+// of its sources), dealt to the waves in turn; a wave stages an item's sources in LDS, reads
+// them back with broadcast reads, sums the item's terms per target in a plain FP32 sum (at
+// most 64 terms) and adds that to a Kahan-compensated FP32 total (FP64 throughout in the FP64
+// form).  The partial sums are combined in FP64 in wave order (so the result does not
 // depend on scheduling) into t_near, which the far-field kernels add to the far field and
 // the own-cell term.  The kernel reads only the tree and the lists, so it can run beside
 // the upward and downward passes.
@@ -649,6 +650,7 @@ template <class T, bool GUARD>
 __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, double *__restrict__ t_near)
 {
     __shared__ double part[kNearWaves][64];
+    __shared__ V4<T> ysh[kNearWaves][64];  // per wave: the current item's sources
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t n = a.sc->n_near;
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
@@ -669,16 +671,20 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
                 for (int base = 0; base < sn; base += 64, ++item) {
                     if (item % kNearWaves != w) continue;
                     const int m = min(64, sn - base);
-                    V4<T> y;
-                    if (lane < m) y = a.s_dat[sf + base + lane];
-                    else y.x = y.y = y.z = y.w = T(0);
+                    if (lane < m) ysh[w][lane] = a.s_dat[sf + base + lane];
+                    wave_lds_sync();
+                    // the item's terms in a plain sum (at most 64), added to the compensated total
+                    T blk = T(0);
+#pragma unroll 8
                     for (int j = 0; j < m; ++j) {
-                        const T yx = lane_bcast(y.x, j), yy = lane_bcast(y.y, j), yz = lane_bcast(y.z, j),
-                                yw = lane_bcast(y.w, j);
-                        const T dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
+                        const V4<T> y = ysh[w][j];  // one address for the wave: a broadcast read
+                        const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
                         const T r2 = dx * dx + dy * dy + dz * dz;
-                        if (act && r2 > T(0)) near.add(kernel_eval<GUARD>(r2, a.kp) * yw);
+                        const T v = kernel_eval<GUARD>(r2, a.kp) * y.w;
+                        blk += r2 > T(0) ? v : T(0);
                     }
+                    near.add(blk);
+                    wave_lds_sync();  // the item's sources have been read
                 }
             }
             __syncthreads();  // the previous pass's partial sums have been read
