@@ -321,6 +321,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     __shared__ float Us[kFarMLeaves][65];  // U, then C = U G
     __shared__ float Gs[64][65];
     __shared__ int32_t lbox[kFarMLeaves], lt0[kFarMLeaves], loff[kFarMLeaves + 1];
+    __shared__ int32_t lorg[kFarMLeaves][3];  // the leaves' first cells (anchor * m)
     __shared__ uint8_t lnear[kFarMLeaves], lw[kFarMLeaves];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int level;
@@ -346,6 +347,10 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
         }
         loff[lane + 1] = v;
         if (lane == 0) loff[0] = 0;
+        const int32_t b = en.x;
+        lorg[lane][0] = b >= 0 ? a.bx.ax[b] * gm : 0;
+        lorg[lane][1] = b >= 0 ? a.bx.ay[b] * gm : 0;
+        lorg[lane][2] = b >= 0 ? a.bx.az[b] * gm : 0;
     }
     for (int i = t; i < 64 * 64; i += 256) {
         const int li = i >> 6, c = i & 63;
@@ -360,6 +365,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     const V4<float> *__restrict__ tdat = a.t_dat;
     int32_t q[kU], k[kU], cell[kU], out[kU];
     V4<float> x[kU];
+    double tnear[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const int32_t f = u * 256 + t;
@@ -387,6 +393,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
             cell[u] = gm > 0 ? tcell[k[u]] : 0;
             out[u] = tout[k[u]];
             x[u] = tdat[k[u]];
+            tnear[u] = lnear[q[u]] ? t_near[k[u]] : 0.0;
         }
     __syncthreads();
     f32x4 acc = f32x4{0, 0, 0, 0};
@@ -398,9 +405,14 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     for (int r = 0; r < 4; ++r) Us[Mfma<float>::row(lane, r)][16 * w + (lane & 15)] = acc[r];
     __syncthreads();
     const int scale_exp = a.sc->scale_exp;
-    auto finish = [&](int qq, int32_t kk, int32_t cl, int32_t ot, const V4<float> &xx) {
+    auto finish = [&](int qq, int32_t cl, int32_t ot, const V4<float> &xx, double tnr) {
         const int32_t b = lbox[qq];
-        float far = gm > 0 ? Us[qq][local_cell(a, cl, b, gm)] : 0.0f;
+        float far = 0.0f;
+        if (gm > 0) {
+            const int i = (cl & 1023) - lorg[qq][0], j = ((cl >> 10) & 1023) - lorg[qq][1],
+                      kz = ((cl >> 20) & 1023) - lorg[qq][2];
+            far = Us[qq][(i * gm + j) * gm + kz];
+        }
         if (lw[qq]) {
             // W list (rare on grids): the source boxes' lattice densities, one thread per target
             for (uint32_t e = a.L.w_off[b]; e < a.L.w_off[b + 1]; ++e) {
@@ -417,12 +429,12 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
                 }
             }
         }
-        const double tot = (double)far + (lnear[qq] ? t_near[kk] : 0.0) + (double)xx.w;
+        const double tot = (double)far + tnr + (double)xx.w;
         S_out[ot] = (TO)(a.P * ldexp(tot, scale_exp));
     };
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-        if (q[u] >= 0) finish(q[u], k[u], cell[u], out[u], x[u]);
+        if (q[u] >= 0) finish(q[u], cell[u], out[u], x[u], tnear[u]);
     // targets beyond the first kU x 256 (leaves of levels without an operator may hold more)
     for (int32_t f = kU * 256 + t; f < total; f += 256) {
         int lo = 0, hi = cnt - 1;
@@ -432,7 +444,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
             else hi = mid - 1;
         }
         const int32_t kk = lt0[lo] + (f - loff[lo]);
-        finish(lo, kk, gm > 0 ? tcell[kk] : 0, tout[kk], tdat[kk]);
+        finish(lo, gm > 0 ? tcell[kk] : 0, tout[kk], tdat[kk], lnear[lo] ? t_near[kk] : 0.0);
     }
     if (a.work && t < cnt) {
         const int32_t b = lbox[t];

@@ -32,6 +32,7 @@ enum { kModeM2L = 0, kModeL2L = 1, kModeM2M = 2 };
 struct GemmSeg {
     int32_t count_idx, list_base, r0, ccap;
     int64_t op_off, out_row;
+    int32_t tile_base;  // M2L: the segment's first tile in the per-tile offset masks
 };
 struct GemmSegs {
     int n;
@@ -54,20 +55,18 @@ __device__ __forceinline__ bool seg_tile(const GemmSegs &sg, const int32_t *__re
     return false;
 }
 
-// Whether any source box of the column tile sends one of the offsets of rows m0 .. m0 + 63 to a
-// target (use: the per-box offset masks); a tile that reaches no target is not computed (the
-// gathers never read those rows).  Called by the whole workgroup.
-__device__ __forceinline__ bool tile_used(const uint32_t *__restrict__ use, const GemmSeg &sg, int32_t n0,
-                                          int32_t ncols, int m0, int M, int nl)
+// Whether a source box of the column tile (slots r0 + n0 .. + 63 of its level, r0 + n0 a
+// multiple of 64) sends one of the offsets of rows m0 .. m0 + 63 to a target; a tile that
+// reaches no target is not computed (the gathers never read those rows).  One mask word per
+// offset range, the same for the whole workgroup.
+__device__ __forceinline__ bool tile_used(const uint32_t *__restrict__ tuse, const GemmSeg &sg, int32_t n0, int m0,
+                                          int M, int nl)
 {
-    const int t = threadIdx.x;
+    const uint32_t *tu = tuse + (size_t)(sg.tile_base + (sg.r0 + n0) / kTile) * kUseWords;
     const int o_lo = m0 / nl, o_hi = min(M - 1, m0 + kTile - 1) / nl;
-    bool any = false;
-    if (t < kTile && n0 + t < ncols) {
-        const uint32_t *um = use + (size_t)(sg.list_base + sg.r0 + n0 + t) * kUseWords;
-        for (int o = o_lo; o <= o_hi && !any; ++o) any = (um[o >> 5] >> (o & 31)) & 1u;
-    }
-    return __syncthreads_or(any) != 0;
+    for (int o = o_lo; o <= o_hi; ++o)
+        if ((tu[o >> 5] >> (o & 31)) & 1u) return true;
+    return false;
 }
 
 // Translation GEMM on the matrix cores, out^T = X^T Op^T with Op (M x kp, row-major) a
@@ -89,8 +88,11 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
 {
     // K staged 64 deep for FP32 (one LDS fill when n_lam <= 64), 32 for FP64
     constexpr int KT = sizeof(T) == 4 ? 2 * kTK : kTK;
-    __shared__ T As[KT][kTile + kPad];  // X^T tile, k-major
-    __shared__ T Bs[KT][kTile + kPad];  // Op^T tile, k-major
+    // tiles row-major (a row of K per box / per operator row), rows KT + kPad apart: the staging
+    // writes (K fastest) and the matrix-core operand reads (16 rows x 4 K per wave) both spread
+    // over all 64 LDS banks
+    __shared__ T As[kTile][KT + kPad];  // X^T tile
+    __shared__ T Bs[kTile][KT + kPad];  // Op tile
     __shared__ int32_t boxes[kTile];
     __shared__ int32_t kid[MODE == kModeL2L ? kTile : 1][8];  // L2L: children of the column boxes
     __shared__ uint8_t klisted[MODE == kModeL2L ? kTile : 1][8];  // ... holding a level-local part
@@ -98,7 +100,10 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wn = w >> 1, wm = w & 1;
     using acc_t = typename Mfma<T>::acc_t;
-    // blockIdx.y strides over the column tiles of all segments (a bounded grid for any count)
+    // blockIdx.y strides over the column tiles of all segments (a bounded grid for any count);
+    // when K fits one stage the operator tile stays in LDS while the segment does not change
+    const bool resident = kp <= KT;
+    int bseg = -1;
     for (int32_t tile = blockIdx.y;; tile += gridDim.y) {
         int si;
         int32_t n0, ncols;
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
         const GemmSeg sg = segs.s[si];
         const T *Op = Op0 + sg.op_off;
         T *out = out0 + (size_t)sg.out_row * M;
-        if (MODE == kModeM2L && use && !tile_used(use, sg, n0, ncols, m0, M, nl)) continue;
+        if (MODE == kModeM2L && use && !tile_used(use, sg, n0, m0, M, nl)) continue;
         __syncthreads();
         if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         acc_t acc[2][2];
@@ -122,16 +127,18 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                     kid[e >> 3][e & 7] = C;
                     klisted[e >> 3][e & 7] = C >= 0 && tag[C] == (int32_t)gen;
                 }
+            const bool load_b = !resident || si != bseg;
             for (int e = t; e < KT * kTile; e += 256) {
                 const int n = e / KT, k = e % KT;
                 const int gk = k0 + k;
                 const int32_t bx = boxes[n];
                 T v = T(0);
                 if (bx >= 0 && gk < nl) v = vec[(size_t)bx * nl + gk];
-                As[k][n] = v;
+                As[n][k] = v;
                 const int gm = m0 + n;
-                Bs[k][n] = (gm < M && gk < kp) ? Op[(size_t)gm * kp + gk] : T(0);
+                if (load_b) Bs[n][k] = (gm < M && gk < kp) ? Op[(size_t)gm * kp + gk] : T(0);
             }
+            bseg = si;
             __syncthreads();
             if (MODE == kModeL2L && k0 == 0) {
                 // the children's level-local parts, loaded while the products run
@@ -151,8 +158,8 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
             for (int ks = 0; ks < KT; ks += 4) {
                 const int kk = ks + (lane >> 4);
                 T a[2], b[2];
-                for (int i = 0; i < 2; ++i) a[i] = As[kk][wn * 32 + i * 16 + (lane & 15)];
-                for (int j = 0; j < 2; ++j) b[j] = Bs[kk][wm * 32 + j * 16 + (lane & 15)];
+                for (int i = 0; i < 2; ++i) a[i] = As[wn * 32 + i * 16 + (lane & 15)][kk];
+                for (int j = 0; j < 2; ++j) b[j] = Bs[wm * 32 + j * 16 + (lane & 15)][kk];
                 for (int i = 0; i < 2; ++i)
                     for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
             }
@@ -219,7 +226,7 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
         const GemmSeg sg = segs.s[si];
         const uint16_t *Oh = Oh0 + sg.op_off, *Ol = Ol0 + sg.op_off;
         float *out = out0 + (size_t)sg.out_row * M;
-        if (use && !tile_used(use, sg, n0, ncols, m0, M, nl)) continue;
+        if (use && !tile_used(use, sg, n0, m0, M, nl)) continue;
         __syncthreads();
         if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         f32x4 acc[2][2];
@@ -442,11 +449,12 @@ void launch_gather(Plan &p, const FmmArgs<T> &a, unsigned grid, const GatherLeve
     }
 }
 
-GemmSegs one_seg(int32_t count_idx, int64_t list_base, int64_t r0, int64_t ccap, int64_t op_off, int64_t out_row)
+GemmSegs one_seg(int32_t count_idx, int64_t list_base, int64_t r0, int64_t ccap, int64_t op_off, int64_t out_row,
+                 int32_t tile_base = 0)
 {
     GemmSegs sg{};
     sg.n = 1;
-    sg.s[0] = GemmSeg{count_idx, (int32_t)list_base, (int32_t)r0, (int32_t)ccap, op_off, out_row};
+    sg.s[0] = GemmSeg{count_idx, (int32_t)list_base, (int32_t)r0, (int32_t)ccap, op_off, out_row, tile_base};
     return sg;
 }
 
@@ -455,16 +463,16 @@ template <class T>
 void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
 {
     const int nl = p.n_lam, M = kNumM2L * nl;
-    // a bounded grid striding over the column tiles: an empty segment costs little
+    // a bounded grid striding over the column tiles (an empty segment costs little)
     dim3 g((M + kTile - 1) / kTile, (unsigned)std::max<int64_t>(1, std::min<int64_t>(16, col_tiles)));
     if (std::is_same<T, float>::value && p.precision == PH_FP32_BF16SPLIT)
         tgemm_m2l_bf16s_kernel<<<g, 256, 0, s>>>((const uint16_t *)p.ops.m2l_hi, (const uint16_t *)p.ops.m2l_lo,
                                                  p.k_pad, M, nl, (const float *)p.d_phi, p.box.src_box,
-                                                 p.d_sc->lvl_src, sg, (float *)p.d_y, p.lists.m2l_use);
+                                                 p.d_sc->lvl_src, sg, (float *)p.d_y, p.lists.m2l_tile_use);
     else
         tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>((const T *)p.ops.m2l, p.k_pad, M, nl, (const T *)p.d_phi,
                                                     p.box.src_box, p.d_sc->lvl_src, sg, (T *)p.d_y, nullptr,
-                                                    nullptr, nullptr, p.lists.m2l_use, nullptr, 0u);
+                                                    nullptr, nullptr, p.lists.m2l_tile_use, nullptr, 0u);
 }
 
 template <class T>
@@ -481,8 +489,8 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
         GemmSegs sg{};
         int64_t tiles = 0;
         for (int l = 2; l <= D; ++l) {
-            sg.s[sg.n++] = GemmSeg{l, (int32_t)p.level_base[l], 0, (int32_t)p.level_cap[l], (int64_t)l * M * p.k_pad,
-                                   p.y_lvl_col[l]};
+            sg.s[sg.n++] = GemmSeg{l,           (int32_t)p.level_base[l], 0, (int32_t)p.level_cap[l],
+                                   (int64_t)l * M * p.k_pad, p.y_lvl_col[l], p.m2l_tile_base[l]};
             tiles += (p.level_cap[l] + kTile - 1) / kTile;
         }
         m2l_product<T>(p, sg, tiles, s);
@@ -508,7 +516,7 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
             const unsigned gl_grid = (unsigned)std::min<int64_t>(cap, 8192);
             for (int c = 0; c < nchunk; ++c) {
                 const int64_t r0 = c * ccap;
-                m2l_product<T>(p, one_seg(l, p.level_base[l], r0, ccap, (int64_t)l * M * p.k_pad, 0),
+                m2l_product<T>(p, one_seg(l, p.level_base[l], r0, ccap, (int64_t)l * M * p.k_pad, 0, p.m2l_tile_base[l]),
                                (ccap + kTile - 1) / kTile, s);
                 launch_gather<T>(p, a, gl_grid, gl, M, (int32_t)r0, (int32_t)ccap, c == 0, c == 0, s);
             }

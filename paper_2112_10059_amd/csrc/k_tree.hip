@@ -30,7 +30,8 @@ namespace {
 struct LevelInfo {
     int32_t base[kMaxDepth + 2];
     int32_t cap[kMaxDepth + 2];
-    int32_t depth;  // deepest level
+    int32_t tbase[kMaxDepth + 2];  // first 64-slot tile of each level's source list
+    int32_t depth;                 // deepest level
 };
 
 // Append val to list for the lanes with pred: one atomic per wave, lanes in lane order.
@@ -71,9 +72,11 @@ __device__ __forceinline__ uint64_t scan_at(const uint64_t *__restrict__ scanned
 }
 
 __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int leaf_cap, int max_depth,
-                                   const uint64_t *__restrict__ scanned, int64_t n, CallScalars *__restrict__ sc)
+                                   const uint64_t *__restrict__ scanned, int64_t n, CallScalars *__restrict__ sc,
+                                   uint32_t *__restrict__ tile_use, int32_t n_tile_words)
 {
     const int32_t f0 = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int32_t i = f0; i < n_tile_words; i += gridDim.x * blockDim.x) tile_use[i] = 0u;  // filled by the lists
     const int32_t f = f0 < nbox ? f0 : nbox - 1;  // whole waves reach the reduction below
     const bool mine = f0 < nbox;
     const uint64_t total = sc->packed_total;
@@ -299,8 +302,8 @@ __global__ __launch_bounds__(kListBlock) void list_count_kernel(BoxArrays bx, Le
 // along.  B has source box S in its V list iff B is a child of a colleague of S's parent, not
 // adjacent to S, at S's level; so one wave per source box S (levels >= 2) walks those
 // candidates (the children of the parent's split colleagues), enters each one with targets
-// once per call into its level's segment of vt (levels >= 3), and records the offset slots
-// used as a 316-bit mask at S's slot in the level's source list (kUseWords words).
+// once per call into its level's segment of vt (levels >= 3), and ORs the offset slots used
+// into the 316-bit mask of the 64-slot tile of the level's source list that holds S.
 __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc,
                                                       Lists L, uint32_t gen)
 {
@@ -353,7 +356,8 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
             wave_append(fresh, L.vt + li.base[level], &sc->n_vt_lvl[level], B);
         }
         __builtin_amdgcn_wave_barrier();
-        if (lane < kUseWords) L.m2l_use[(size_t)(li.base[level] + r) * kUseWords + lane] = use[wv][lane];
+        if (lane < kUseWords && use[wv][lane])
+            atomicOr(&L.m2l_tile_use[(size_t)(li.tbase[level] + r / 64) * kUseWords + lane], use[wv][lane]);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -442,6 +446,7 @@ LevelInfo level_info(const Plan &p)
     }
     li.base[p.max_depth + 1] = (int32_t)p.level_base[p.max_depth + 1];
     li.cap[p.max_depth + 1] = 0;
+    for (int l = 0; l <= p.max_depth; ++l) li.tbase[l] = p.m2l_tile_base[l];
     li.depth = p.max_depth;
     return li;
 }
@@ -453,7 +458,8 @@ void build_tree(Plan &p, hipStream_t s)
     LevelInfo li = level_info(p);
     const int32_t nbox = (int32_t)p.box_cap;
     const unsigned g = (unsigned)((nbox + 255) / 256);
-    tree_status_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.leaf_cap, p.max_depth, p.d_flag, p.n, p.d_sc);
+    tree_status_kernel<<<g, 256, 0, s>>>(p.box, li, nbox, p.leaf_cap, p.max_depth, p.d_flag, p.n, p.d_sc,
+                                         p.lists.m2l_tile_use, p.m2l_tiles * kUseWords);
 }
 
 void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready)

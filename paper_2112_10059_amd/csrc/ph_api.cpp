@@ -239,7 +239,11 @@ void alloc_workspace(Plan &p)
     L.near_leaves = (int32_t *)dev_alloc(p, B * 4);
     L.vt = (int32_t *)dev_alloc(p, B * 4);
     L.vt_tag = (int32_t *)dev_alloc(p, B * 4);
-    L.m2l_use = (uint32_t *)dev_alloc(p, B * 4 * kUseWords);
+    for (int l = 0; l <= p.max_depth; ++l) {
+        p.m2l_tile_base[l] = p.m2l_tiles;
+        p.m2l_tiles += (int32_t)((p.level_cap[l] + 63) / 64);
+    }
+    L.m2l_tile_use = (uint32_t *)dev_alloc(p, (size_t)std::max(p.m2l_tiles, 1) * kUseWords * 4);
     PH_HIP(hipMemset(L.vt_tag, 0, B * 4));  // no call has tagged a box yet
     if (p.method == PH_METHOD_FMM) {
         p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
@@ -263,7 +267,7 @@ void alloc_workspace(Plan &p)
         }
         p.y_all_levels = all_cols > 0 && (size_t)all_cols * col_bytes <= budget;
         if (p.y_all_levels) p.y_cap_cols = (size_t)all_cols;
-        else p.y_cap_cols = (size_t)std::max<int64_t>(64, std::min<int64_t>(widest2, (int64_t)(budget / col_bytes)));
+        else p.y_cap_cols = (size_t)std::max<int64_t>(64, std::min<int64_t>(widest2, (int64_t)(budget / col_bytes)) / 64 * 64);
         p.d_y = dev_alloc(p, p.y_cap_cols * col_bytes);
         int64_t widest_par = 1;
         for (int l = 2; l <= p.max_depth; ++l) widest_par = std::max<int64_t>(widest_par, p.level_cap[l]);
@@ -300,7 +304,7 @@ void free_plan(Plan *p)
                     p->box.child, p->box.coll, p->box.start, p->box.end, p->box.src_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_off,
                     p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
-                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_use, p->d_phi, p->d_u,
+                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_tile_use, p->d_phi, p->d_u,
                     p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
                     p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
                     p->d_row_feat,

@@ -100,9 +100,9 @@ struct Lists {
     // boxes of levels >= 3 with targets and a non-empty V or X list, per-level segments at the
     // level's box base; a box is entered once per call through vt_tag (the call's number)
     int32_t *vt = nullptr, *vt_tag = nullptr;
-    // M2L offsets that reach a target, per source box (316 bits in kUseWords words), at the
-    // box's slot in its level's source list
-    uint32_t *m2l_use = nullptr;
+    // M2L offsets that reach a target, per tile of 64 slots of a level's source list (316 bits
+    // in kUseWords words; the tiles of level l start at Plan::m2l_tile_base[l])
+    uint32_t *m2l_tile_use = nullptr;
 };
 
 struct Gas {
@@ -142,6 +142,8 @@ struct Plan {
     void *d_z = nullptr;     // parent-to-child (and child-to-parent) translations: z_cap_cols x (8 n_lam)
     size_t y_cap_cols = 0;   // source boxes per translation chunk (Y buffer columns)
     bool y_all_levels = false;            // Y holds every level at once (one M2L product)
+    int32_t m2l_tile_base[kMaxDepth + 2] = {};  // first tile of each level's source list
+    int32_t m2l_tiles = 0;                      // tiles of all levels
     int64_t y_lvl_col[kMaxDepth + 2] = {};  // ... at these first columns
     void *d_y = nullptr;     // translation products: y_cap_cols x (316 n_lam)
     int leaf_cap = 64;
