@@ -164,13 +164,19 @@ __device__ void p2m_box(const FmmArgs<T> &a, int32_t b, int level, V4<T> *tile, 
 // P2M of every source leaf of levels >= 2 in one launch: the source boxes of those levels are
 // dealt to the workgroups as one flat range (boxes that are not leaves get their densities
 // from their children afterwards).
+// The same launch also clears the check values of every box of levels >= 3 (u_zero .. u_end
+// elements): the downward gather then stores only the level-local parts of the boxes with a V
+// or X list, and the L2L products add whatever their children hold.
 template <class T>
-__global__ __launch_bounds__(kUpThreads) void p2m_kernel(FmmArgs<T> a, int depth)
+__global__ __launch_bounds__(kUpThreads) void p2m_kernel(FmmArgs<T> a, int depth, int64_t u_zero, int64_t u_end)
 {
     __shared__ V4<T> tile[128];
     __shared__ int32_t rloc[128];
     __shared__ T chk[kMaxShell];
     __shared__ T part[kUpGroups][kMaxLattice];
+    for (int64_t i = u_zero + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < u_end;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a.u[i] = T(0);
     for (int32_t idx = blockIdx.x;; idx += gridDim.x) {
         int level = -1;
         int32_t r = idx;
@@ -719,7 +725,9 @@ void fmm_upward_t(Plan &p, hipStream_t s)
     int64_t cap = 0;
     for (int l = 2; l <= D; ++l) cap += p.level_cap[l];
     if (cap == 0) return;
-    p2m_kernel<T><<<(unsigned)std::min<int64_t>(cap, 4096), kUpThreads, 0, s>>>(a, D);
+    const int64_t u_zero = D >= 3 ? p.level_base[3] * (int64_t)p.n_lam : 0;
+    const int64_t u_end = D >= 3 ? p.box_cap * (int64_t)p.n_lam : 0;
+    p2m_kernel<T><<<(unsigned)std::min<int64_t>(cap, 4096), kUpThreads, 0, s>>>(a, D, u_zero, u_end);
     for (int l = D - 1; l >= 2; --l) {
         // a direct product per parent for small lattices; the level GEMM (all eight octant
         // translations of every child, on the matrix cores) for large ones

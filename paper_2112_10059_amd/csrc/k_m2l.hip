@@ -83,8 +83,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                                                     T *__restrict__ out0, const int32_t *__restrict__ child,
                                                     const int32_t *__restrict__ t_cnt,
                                                     unsigned long long *__restrict__ work,
-                                                    const uint32_t *__restrict__ use,
-                                                    const int32_t *__restrict__ tag, uint32_t gen)
+                                                    const uint32_t *__restrict__ use)
 {
     // K staged 64 deep for FP32 (one LDS fill when n_lam <= 64), 32 for FP64
     constexpr int KT = sizeof(T) == 4 ? 2 * kTK : kTK;
@@ -95,7 +94,6 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
     __shared__ T Bs[kTile][KT + kPad];  // Op tile
     __shared__ int32_t boxes[kTile];
     __shared__ int32_t kid[MODE == kModeL2L ? kTile : 1][8];  // L2L: children of the column boxes
-    __shared__ uint8_t klisted[MODE == kModeL2L ? kTile : 1][8];  // ... holding a level-local part
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wn = w >> 1, wm = w & 1;
@@ -123,9 +121,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
             if (MODE == kModeL2L && k0 == 0)
                 for (int e = t; e < kTile * 8; e += 256) {
                     const int32_t bx = boxes[e >> 3];
-                    const int32_t C = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
-                    kid[e >> 3][e & 7] = C;
-                    klisted[e >> 3][e & 7] = C >= 0 && tag[C] == (int32_t)gen;
+                    kid[e >> 3][e & 7] = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
                 }
             const bool load_b = !resident || si != bseg;
             for (int e = t; e < KT * kTile; e += 256) {
@@ -141,16 +137,15 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
             bseg = si;
             __syncthreads();
             if (MODE == kModeL2L && k0 == 0) {
-                // the children's level-local parts, loaded while the products run
+                // the children's level-local parts (cleared where none), loaded while the products run
                 for (int i = 0; i < 2; ++i)
                     for (int j = 0; j < 2; ++j) {
                         const int gm = m0 + wm * 32 + j * 16 + (lane & 15);
                         const int c = gm / nl, li = gm - c * nl;
                         for (int r = 0; r < 4; ++r) {
                             const int nl_ = wn * 32 + i * 16 + Mfma<T>::row(lane, r);
-                            own[i][j][r] = (n0 + nl_ < ncols && gm < M && klisted[nl_][c])
-                                               ? out0[(size_t)kid[nl_][c] * nl + li]
-                                               : T(0);
+                            const int32_t C = (n0 + nl_ < ncols && gm < M) ? kid[nl_][c] : -1;
+                            own[i][j][r] = C >= 0 ? out0[(size_t)C * nl + li] : T(0);
                         }
                     }
             }
@@ -173,7 +168,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                     if (gn >= ncols || gm >= M) continue;
                     if (MODE == kModeL2L) {
                         // row c n_lam + li is the check potential li of child c: into its u, plus
-                        // the level-local part already there if the child has a V or X list
+                        // the level-local part already there (zero unless it has a V or X list)
                         const int c = gm / nl, li = gm - c * nl;
                         const int32_t C = kid[nl_][c];
                         if (C < 0) continue;
@@ -472,7 +467,7 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
     else
         tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>((const T *)p.ops.m2l, p.k_pad, M, nl, (const T *)p.d_phi,
                                                     p.box.src_box, p.d_sc->lvl_src, sg, (T *)p.d_y, nullptr,
-                                                    nullptr, nullptr, p.lists.m2l_tile_use, nullptr, 0u);
+                                                    nullptr, nullptr, p.lists.m2l_tile_use);
 }
 
 template <class T>
@@ -531,7 +526,7 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
         tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(
             (const T *)p.ops.l2l, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box, p.d_sc->lvl_tpar,
             one_seg(l - 1, p.level_base[l - 1], 0, pcap, (int64_t)l * Mz * p.k_pad, 0), (T *)p.d_u, p.box.child,
-            p.box.t_cnt, a.work, nullptr, p.lists.vt_tag, p.call_gen);
+            p.box.t_cnt, a.work, nullptr);
     }
 }
 
@@ -576,7 +571,7 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
     tgemm_kernel<T, kModeM2M><<<g, 256, 0, s>>>(
         (const T *)p.ops.m2m, p.k_pad, Mw, nl, (const T *)p.d_phi, p.box.src_box, p.d_sc->lvl_src,
         one_seg(l + 1, p.level_base[l + 1], 0, ccap, (int64_t)(l + 1) * Mw * p.k_pad, 0), (T *)p.d_z, nullptr,
-        nullptr, nullptr, nullptr, nullptr, 0u);
+        nullptr, nullptr, nullptr);
     const int threads = nl <= 64 ? 64 : (nl <= 128 ? 128 : 256);
     m2m_gather_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 8192), threads, 0, s>>>(a, l,
                                                                                               (const T *)p.d_z);
