@@ -667,8 +667,9 @@ constexpr int kNearWaves = 16;
 template <class T, bool GUARD>
 __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, double *__restrict__ t_near)
 {
+    constexpr int kNB = sizeof(T) == 4 ? 2 : 1;  // items staged together per wave
     __shared__ double part[kNearWaves][64];
-    __shared__ V4<T> ysh[kNearWaves][64];  // per wave: the current item's sources
+    __shared__ V4<T> ysh[kNearWaves][kNB][64];  // per wave: the current items' sources
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t n = a.sc->n_near;
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
@@ -682,28 +683,61 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
             if (act) x = a.t_dat[tf + t];
             else x.x = x.y = x.z = x.w = T(0);
             Acc<T> near;
-            int item = 0;
-            for (uint32_t e = u0; e < u1; ++e) {
+            // this wave's items in list order, kNB at a time (their source loads issued together)
+            int item = 0, base = 0;
+            uint32_t e = u0;
+            int32_t sf = 0, sn = 0;
+            if (e < u1) {
                 const int32_t C = a.L.u[e];
-                const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
-                for (int base = 0; base < sn; base += 64, ++item) {
-                    if (item % kNearWaves != w) continue;
-                    const int m = min(64, sn - base);
-                    if (lane < m) ysh[w][lane] = a.s_dat[sf + base + lane];
-                    wave_lds_sync();
+                sf = a.bx.s_first[C];
+                sn = a.bx.s_cnt[C];
+            }
+            while (true) {
+                int32_t isf[kNB];
+                int im[kNB];
+                int nb = 0;
+                while (nb < kNB && e < u1) {
+                    if (item % kNearWaves == w) {
+#pragma unroll
+                        for (int q = 0; q < kNB; ++q)
+                            if (q == nb) {
+                                isf[q] = sf + base;
+                                im[q] = min(64, sn - base);
+                            }
+                        ++nb;
+                    }
+                    ++item;
+                    base += 64;
+                    if (base >= sn) {  // next U entry (every entry holds sources)
+                        base = 0;
+                        if (++e < u1) {
+                            const int32_t C = a.L.u[e];
+                            sf = a.bx.s_first[C];
+                            sn = a.bx.s_cnt[C];
+                        }
+                    }
+                }
+                if (nb == 0) break;
+#pragma unroll
+                for (int q = 0; q < kNB; ++q)
+                    if (q < nb && lane < im[q]) ysh[w][q][lane] = a.s_dat[isf[q] + lane];
+                wave_lds_sync();
+#pragma unroll
+                for (int q = 0; q < kNB; ++q) {
+                    if (q >= nb) break;
                     // the item's terms in a plain sum (at most 64), added to the compensated total
                     T blk = T(0);
 #pragma unroll 8
-                    for (int j = 0; j < m; ++j) {
-                        const V4<T> y = ysh[w][j];  // one address for the wave: a broadcast read
+                    for (int j = 0; j < im[q]; ++j) {
+                        const V4<T> y = ysh[w][q][j];  // one address for the wave: a broadcast read
                         const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
                         const T r2 = dx * dx + dy * dy + dz * dz;
                         const T v = kernel_eval<GUARD>(r2, a.kp) * y.w;
                         blk += r2 > T(0) ? v : T(0);
                     }
                     near.add(blk);
-                    wave_lds_sync();  // the item's sources have been read
                 }
+                wave_lds_sync();  // the items' sources have been read
             }
             __syncthreads();  // the previous pass's partial sums have been read
             part[w][lane] = near.value();
