@@ -662,7 +662,7 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
 // depend on scheduling) into t_near, which the far-field kernels add to the far field and
 // the own-cell term.  The kernel reads only the tree and the lists, so it can run beside
 // the upward and downward passes.
-constexpr int kNearWaves = 16;
+constexpr int kNearWaves = 4;
 
 template <class T, bool GUARD>
 __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, double *__restrict__ t_near)
@@ -827,9 +827,9 @@ template <class T>
 void fmm_near_t(Plan &p, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
-    // one workgroup (16 waves) per CU at most: the upward and downward passes run beside this
+    // at most four workgroups (16 waves) per CU: the upward and downward passes run beside this
     // kernel on the other stream, and a full grid would hold every wave slot until it drains
-    const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 256);
+    const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 1024);
     if (p.near_guard) near_kernel<T, true><<<g, 64 * kNearWaves, 0, s>>>(a, p.d_t_near);
     else near_kernel<T, false><<<g, 64 * kNearWaves, 0, s>>>(a, p.d_t_near);
 }

@@ -110,6 +110,17 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
         const T *Op = Op0 + sg.op_off;
         T *out = out0 + (size_t)sg.out_row * M;
         if (MODE == kModeM2L && use && !tile_used(use, sg, n0, m0, M, nl)) continue;
+        // the operator's first K stage does not depend on the column boxes: its loads go out
+        // before the boxes' (into registers, stored to LDS with the boxes' values)
+        constexpr int kBV = KT * kTile / 256;
+        T breg[kBV];
+        const bool load_b0 = !resident || si != bseg;
+        if (load_b0)
+#pragma unroll
+            for (int u = 0; u < kBV; ++u) {
+                const int e = t + 256 * u, n = e / KT, k = e % KT, gm = m0 + n;
+                breg[u] = (gm < M && k < kp) ? Op[(size_t)gm * kp + k] : T(0);
+            }
         __syncthreads();
         if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         acc_t acc[2][2];
@@ -123,7 +134,6 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                     const int32_t bx = boxes[e >> 3];
                     kid[e >> 3][e & 7] = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
                 }
-            const bool load_b = !resident || si != bseg;
             for (int e = t; e < KT * kTile; e += 256) {
                 const int n = e / KT, k = e % KT;
                 const int gk = k0 + k;
@@ -132,8 +142,14 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                 if (bx >= 0 && gk < nl) v = vec[(size_t)bx * nl + gk];
                 As[n][k] = v;
                 const int gm = m0 + n;
-                if (load_b) Bs[n][k] = (gm < M && gk < kp) ? Op[(size_t)gm * kp + gk] : T(0);
+                if (k0 > 0) Bs[n][k] = (gm < M && gk < kp) ? Op[(size_t)gm * kp + gk] : T(0);
             }
+            if (k0 == 0 && load_b0)
+#pragma unroll
+                for (int u = 0; u < kBV; ++u) {
+                    const int e = t + 256 * u;
+                    Bs[e / KT][e % KT] = breg[u];
+                }
             bseg = si;
             __syncthreads();
             if (MODE == kModeL2L && k0 == 0) {
