@@ -220,16 +220,25 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(FmmArgs<T> a, int leve
         if (C >= 0) {
             const T ph = lane < nl ? a.phi[(size_t)C * nl + lane] : T(0);
             const T *op = a.l2l + ((size_t)(level + 1) * 8 + o) * nl * a.k_pad;  // [child j][parent i]
+            // rows addressed as a uniform row pointer plus the lane's 32-bit offset, so that a
+            // batch in flight holds only the loaded values (the kernel runs beside the near
+            // field, whose waves leave about 190 registers per SIMD)
             constexpr int kRB = sizeof(T) == 4 ? 32 : 16;  // operator rows in flight
+            const unsigned ln = (unsigned)min(lane, nl - 1);
+            const int kp = a.k_pad;
+#pragma unroll 1
             for (int j0 = 0; j0 < nl; j0 += kRB) {
                 T v[kRB];
 #pragma unroll
-                for (int u = 0; u < kRB; ++u)
-                    v[u] = (lane < nl && j0 + u < nl) ? op[(size_t)(j0 + u) * a.k_pad + lane] : T(0);
+                for (int u = 0; u < kRB; ++u) {
+                    const T *row = op + (size_t)min(j0 + u, nl - 1) * kp;
+                    v[u] = row[ln];
+                }
 #pragma unroll
                 for (int u = 0; u < kRB; ++u)
                     if (j0 + u < nl) acc += v[u] * lane_bcast(ph, j0 + u);
             }
+            if (lane >= nl) acc = T(0);
         }
         mpart[o][lane] = acc;
         __syncthreads();
@@ -655,10 +664,13 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
 
 // Exact near field (Sec. 2.4 eq. (16)) of the leaves with a U list, one workgroup of
 // kNearWaves waves per leaf over the list.  The leaf's work items are (U entry, chunk of 64
-// of its sources), dealt to the waves in turn; a wave stages an item's sources in LDS, reads
-// them back with broadcast reads, sums the item's terms per target in a plain FP32 sum (at
-// most 64 terms) and adds that to a Kahan-compensated FP32 total (FP64 throughout in the FP64
-// form).  The partial sums are combined in FP64 in wave order (so the result does not
+// of its sources), dealt to the waves in turn (the entries' source ranges are read into LDS
+// 64 at a time, so that walking the list costs no dependent loads); a wave stages an item's
+// sources in LDS, reads them back with broadcast reads, sums the item's terms per target in
+// a plain FP32 sum (at most 64 terms) and adds that to a Kahan-compensated FP32 total (FP64
+// throughout in the FP64 form).  On uniform grids the kernel between two finest-level
+// leaves is read from a table indexed by the integer cell offset (built in FP64 at plan
+// time, held in LDS) instead of being evaluated from FP32 coordinates.  The partial sums are combined in FP64 in wave order (so the result does not
 // depend on scheduling) into t_near, which the far-field kernels add to the far field and
 // the own-cell term.  The kernel reads only the tree and the lists, so it can run beside
 // the upward and downward passes.
@@ -670,74 +682,122 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
     constexpr int kNB = sizeof(T) == 4 ? 2 : 1;  // items staged together per wave
     __shared__ double part[kNearWaves][64];
     __shared__ V4<T> ysh[kNearWaves][kNB][64];  // per wave: the current items' sources
+    __shared__ int32_t esf[64], esn[64];          // a chunk of the U list: source ranges
+    __shared__ uint8_t etab[64];                  // and whether the table serves the entry
+    extern __shared__ float ntab[];              // the near-field kernel table, when present
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t n = a.sc->n_near;
+    if ((int32_t)blockIdx.x >= n) return;  // the whole workgroup
+    // uniform grids (FP32): between two leaves of the table's level the kernel is read from the
+    // table at the integer cell offset instead of being evaluated
+    const bool tab = sizeof(T) == 4 && a.near_tab != nullptr;
+    const int TR = a.near_R, TS = 2 * TR + 1, TS3 = TS * TS * TS;
+    if (tab) {
+        for (int i = threadIdx.x; i < TS3; i += blockDim.x) ntab[i] = a.near_tab[i];
+        __syncthreads();
+    }
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
         const int32_t b = a.L.near_leaves[idx];
         const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
         const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+        const bool tab_b = tab && a.bx.level[b] == a.near_level;
         for (int tb = 0; tb < tn; tb += 64) {
             const int t = tb + lane;
             const bool act = t < tn;
             V4<T> x;
             if (act) x = a.t_dat[tf + t];
             else x.x = x.y = x.z = x.w = T(0);
-            Acc<T> near;
-            // this wave's items in list order, kNB at a time (their source loads issued together)
-            int item = 0, base = 0;
-            uint32_t e = u0;
-            int32_t sf = 0, sn = 0;
-            if (e < u1) {
-                const int32_t C = a.L.u[e];
-                sf = a.bx.s_first[C];
-                sn = a.bx.s_cnt[C];
+            // table index of the target's cell with every offset bias folded in (lanes without
+            // a target take the leaf's first one, so that their reads stay inside the table)
+            int tl = 0;
+            if (tab_b) {
+                const int32_t c = a.t_cell[tf + (act ? t : 0)];
+                tl = (((c & 1023) + TR) * TS + (((c >> 10) & 1023) + TR)) * TS + ((c >> 20) + TR);
             }
-            while (true) {
-                int32_t isf[kNB];
-                int im[kNB];
-                int nb = 0;
-                while (nb < kNB && e < u1) {
-                    if (item % kNearWaves == w) {
+            Acc<T> near;
+            // the U list a chunk of 64 entries at a time: the entries' source ranges (and whether
+            // the table serves them) are read in parallel into LDS, then each wave walks the
+            // chunk there, taking every kNearWaves-th item in list order, kNB at a time (their
+            // source loads issued together)
+            int item = 0;
+            for (uint32_t c0 = u0; c0 < u1; c0 += 64) {
+                const int ne = (int)min(64u, u1 - c0);
+                __syncthreads();  // every wave is done with the previous chunk
+                if ((int)threadIdx.x < ne) {
+                    const int32_t C = a.L.u[c0 + threadIdx.x];
+                    esf[threadIdx.x] = a.bx.s_first[C];
+                    esn[threadIdx.x] = a.bx.s_cnt[C];
+                    etab[threadIdx.x] = tab_b && a.bx.level[C] == a.near_level;
+                }
+                __syncthreads();
+                int e = 0, base = 0;
+                while (true) {
+                    int32_t isf[kNB];
+                    int im[kNB];
+                    bool itab[kNB];
+                    int nb = 0;
+                    while (nb < kNB && e < ne) {
+                        const int32_t sn = esn[e];
+                        if (item % kNearWaves == w) {
 #pragma unroll
-                        for (int q = 0; q < kNB; ++q)
-                            if (q == nb) {
-                                isf[q] = sf + base;
-                                im[q] = min(64, sn - base);
-                            }
-                        ++nb;
-                    }
-                    ++item;
-                    base += 64;
-                    if (base >= sn) {  // next U entry (every entry holds sources)
-                        base = 0;
-                        if (++e < u1) {
-                            const int32_t C = a.L.u[e];
-                            sf = a.bx.s_first[C];
-                            sn = a.bx.s_cnt[C];
+                            for (int q = 0; q < kNB; ++q)
+                                if (q == nb) {
+                                    isf[q] = esf[e] + base;
+                                    im[q] = min(64, sn - base);
+                                    itab[q] = etab[e] != 0;
+                                }
+                            ++nb;
+                        }
+                        ++item;
+                        base += 64;
+                        if (base >= sn) {  // next entry (every entry holds sources)
+                            base = 0;
+                            ++e;
                         }
                     }
-                }
-                if (nb == 0) break;
+                    if (nb == 0) break;
+                    // staged per source: its position and weight, or (table items) the linear
+                    // index of its cell in the table's strides and its weight
 #pragma unroll
-                for (int q = 0; q < kNB; ++q)
-                    if (q < nb && lane < im[q]) ysh[w][q][lane] = a.s_dat[isf[q] + lane];
-                wave_lds_sync();
+                    for (int q = 0; q < kNB; ++q)
+                        if (q < nb && lane < im[q]) {
+                            V4<T> y = a.s_dat[isf[q] + lane];
+                            if (itab[q]) {
+                                const int32_t c = a.s_cell[isf[q] + lane];
+                                const int sl = ((c & 1023) * TS + ((c >> 10) & 1023)) * TS + (c >> 20);
+                                y.x = (T)__int_as_float(sl);
+                            }
+                            ysh[w][q][lane] = y;
+                        }
+                    wave_lds_sync();
 #pragma unroll
-                for (int q = 0; q < kNB; ++q) {
-                    if (q >= nb) break;
-                    // the item's terms in a plain sum (at most 64), added to the compensated total
-                    T blk = T(0);
+                    for (int q = 0; q < kNB; ++q) {
+                        if (q >= nb) break;
+                        // the item's terms in a plain sum (at most 64), added to the compensated total
+                        T blk = T(0);
+                        if (sizeof(T) == 4 && itab[q]) {
 #pragma unroll 8
-                    for (int j = 0; j < im[q]; ++j) {
-                        const V4<T> y = ysh[w][q][j];  // one address for the wave: a broadcast read
-                        const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
-                        const T r2 = dx * dx + dy * dy + dz * dz;
-                        const T v = kernel_eval<GUARD>(r2, a.kp) * y.w;
-                        blk += r2 > T(0) ? v : T(0);
+                            for (int j = 0; j < im[q]; ++j) {
+                                const V4<T> y = ysh[w][q][j];  // a broadcast read
+                                // adjacent leaves keep the offset inside the table; the clamp
+                                // keeps every read inside it regardless
+                                const int id = min(max(tl - __float_as_int((float)y.x), 0), TS3 - 1);
+                                blk += (T)ntab[id] * y.w;
+                            }
+                        } else {
+#pragma unroll 8
+                            for (int j = 0; j < im[q]; ++j) {
+                                const V4<T> y = ysh[w][q][j];  // one address for the wave: a broadcast read
+                                const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+                                const T r2 = dx * dx + dy * dy + dz * dz;
+                                const T v = kernel_eval<GUARD>(r2, a.kp) * y.w;
+                                blk += r2 > T(0) ? v : T(0);
+                            }
+                        }
+                        near.add(blk);
                     }
-                    near.add(blk);
+                    wave_lds_sync();  // the items' sources have been read
                 }
-                wave_lds_sync();  // the items' sources have been read
             }
             __syncthreads();  // the previous pass's partial sums have been read
             part[w][lane] = near.value();
@@ -830,8 +890,10 @@ void fmm_near_t(Plan &p, hipStream_t s)
     // at most four workgroups (16 waves) per CU: the upward and downward passes run beside this
     // kernel on the other stream, and a full grid would hold every wave slot until it drains
     const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 1024);
-    if (p.near_guard) near_kernel<T, true><<<g, 64 * kNearWaves, 0, s>>>(a, p.d_t_near);
-    else near_kernel<T, false><<<g, 64 * kNearWaves, 0, s>>>(a, p.d_t_near);
+    const int S = 2 * p.ops.near_R + 1;
+    const size_t lds = (std::is_same<T, float>::value && p.ops.near_tab) ? (size_t)S * S * S * sizeof(float) : 0;
+    if (p.near_guard) near_kernel<T, true><<<g, 64 * kNearWaves, lds, s>>>(a, p.d_t_near);
+    else near_kernel<T, false><<<g, 64 * kNearWaves, lds, s>>>(a, p.d_t_near);
 }
 
 }  // namespace

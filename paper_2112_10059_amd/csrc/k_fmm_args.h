@@ -34,6 +34,10 @@ struct FmmArgs {
     const T *grid_gt;
     const int32_t *s_cell;
     const int32_t *t_cell;
+    // near-field kernel table (uniform grids, FP32): entries at the cell offsets of adjacent
+    // leaves of level near_level, offsets within [-near_R, near_R] per axis; null if absent
+    const float *near_tab;
+    int near_R, near_level;
     int grid_m[kMaxDepth + 2];
     int64_t grid_off[kMaxDepth + 2];
     int n_lam, n_sig;
@@ -87,6 +91,9 @@ inline FmmArgs<T> make_args(Plan &p)
     a.grid_gt = (const T *)p.ops.grid_gt;
     a.s_cell = p.d_s_cell;
     a.t_cell = p.d_t_cell;
+    a.near_tab = (const float *)p.ops.near_tab;
+    a.near_R = p.ops.near_R;
+    a.near_level = p.ops.near_level;
     for (int l = 0; l < kMaxDepth + 2; ++l) {
         a.grid_m[l] = p.grid_mode ? p.grid_m[l] : 0;
         a.grid_off[l] = p.grid_off[l];

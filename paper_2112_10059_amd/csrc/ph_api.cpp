@@ -309,7 +309,8 @@ void free_plan(Plan *p)
                     p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
                     p->d_row_feat,
                     p->d_cell,
-                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near};
+                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near,
+                    p->ops.near_tab};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
         for (auto &set : p->ring)
@@ -583,6 +584,20 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
                     for (int r = 0; r < R; ++r) ggt[p.grid_off[l] + (size_t)r * nl + li] = G[(size_t)li * R + r];
             }
             if (gg.empty()) gg.push_back(0.0), ggt.push_back(0.0);
+        }
+        // near-field kernel table (FP32 forms): offsets between two adjacent leaves of the
+        // finest level, m^3 cells each, lie within [-(2m - 1), 2m - 1] per axis
+        if (p.grid_mode && p.precision != PH_FP64) {
+            const int D = p.max_depth;
+            const int m = (p.grid_n % (1 << D) == 0) ? (p.grid_n >> D) : 0;
+            const int R = 2 * m - 1;
+            if (m >= 1 && (2 * R + 1) * (2 * R + 1) * (2 * R + 1) <= kNearTabMax) {
+                std::vector<double> tab;
+                build_near_table(p.gas, p.h, R, tab);
+                upload(p, &p.ops.near_tab, convert<float>(tab));
+                p.ops.near_R = R;
+                p.ops.near_level = D;
+            }
         }
         if (p.precision == PH_FP64) {
             upload(p, &p.ops.uc2e_rm, rm);
