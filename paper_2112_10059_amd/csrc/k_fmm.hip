@@ -258,10 +258,9 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(FmmArgs<T> a, int leve
 
 // Output of a target whose sums are complete: S = P 2^e (far + near + own cell), in FP64.
 template <class TO>
-__device__ __forceinline__ void put_output(TO *__restrict__ S_out, const int32_t *__restrict__ t_out, int32_t k,
-                                           double P, double tot, int scale_exp)
+__device__ __forceinline__ void put_output(TO *__restrict__ S_out, int32_t o, double P, double tot, int scale_exp)
 {
-    S_out[t_out[k]] = (TO)(P * ldexp(tot, scale_exp));
+    S_out[o] = (TO)(P * ldexp(tot, scale_exp));
 }
 
 // W list of target leaf b for the lanes' targets: artificial sources of smaller non-adjacent
@@ -324,8 +323,9 @@ __device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint
 // U (leaves x n_lam) and the level operator G (n_lam x cells) in LDS, C = U G is a
 // 16 x 64 x 64 product (wave j: the 16 x 16 tile of cells 16 j .. 16 j + 15,
 // v_mfma_f32_16x16x4_f32 over k), written back to LDS; then the 256 threads walk the
-// workgroup's targets in one flat range, their loads issued together, and finish them as the
-// wave kernel does (far = C[leaf][cell], W list, near field, own cell, output).  Many small
+// workgroup's points (each leaf's sorted range) in one flat range, their loads issued
+// together, and finish the targets among them as the wave kernel does (far = C[leaf][cell],
+// W list, near field, own cell, output).  Many small
 // workgroups keep many dependent load chains in flight.
 constexpr int kFarMLeaves = 16;
 
@@ -373,20 +373,20 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     }
     __syncthreads();
     const int32_t total = loff[cnt];
-    // the targets' data (issued with the check values: one round trip for both)
-    constexpr int kU = 4;  // targets per thread, kU x 256 >= kFarMLeaves x 64
-    const int32_t *__restrict__ tcell = a.t_cell;
-    const int32_t *__restrict__ tout = a.t_out;
-    const V4<float> *__restrict__ tdat = a.t_dat;
+    // the points' data (issued with the check values: one round trip for both)
+    constexpr int kU = 4;  // points per thread, kU x 256 >= kFarMLeaves x 64
+    const int32_t *__restrict__ pcell = a.pcell;
+    const int32_t *__restrict__ perm = a.perm;
+    const uint8_t *__restrict__ sel = a.sel;
     int32_t q[kU], k[kU], cell[kU], out[kU];
-    V4<float> x[kU];
+    uint32_t sb[kU];
     double tnear[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const int32_t f = u * 256 + t;
         q[u] = -1;
         if (f < total) {
-            // the leaf of flat target f: the last q with loff[q] <= f
+            // the leaf of flat point f: the last q with loff[q] <= f
             int lo = 0, hi = cnt - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
@@ -405,9 +405,9 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
 #pragma unroll
     for (int u = 0; u < kU; ++u)
         if (q[u] >= 0) {
-            cell[u] = gm > 0 ? tcell[k[u]] : 0;
-            out[u] = tout[k[u]];
-            x[u] = tdat[k[u]];
+            sb[u] = sel[k[u]];
+            cell[u] = gm > 0 ? pcell[k[u]] : 0;
+            out[u] = perm[k[u]];
             tnear[u] = lnear[q[u]] ? t_near[k[u]] : 0.0;
         }
     __syncthreads();
@@ -420,7 +420,8 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     for (int r = 0; r < 4; ++r) Us[Mfma<float>::row(lane, r)][16 * w + (lane & 15)] = acc[r];
     __syncthreads();
     const int scale_exp = a.sc->scale_exp;
-    auto finish = [&](int qq, int32_t cl, int32_t ot, const V4<float> &xx, double tnr) {
+    auto finish = [&](int qq, int32_t cl, int32_t ot, int32_t kk, uint32_t sbit, double tnr) {
+        if (!(sbit & 2u)) return;  // not a target (its output was cleared at selection)
         const int32_t b = lbox[qq];
         float far = 0.0f;
         if (gm > 0) {
@@ -430,6 +431,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
         }
         if (lw[qq]) {
             // W list (rare on grids): the source boxes' lattice densities, one thread per target
+            const V4<float> xx = point_xyz(a, kk);
             for (uint32_t e = a.L.w_off[b]; e < a.L.w_off[b + 1]; ++e) {
                 const int32_t A = a.L.w[e];
                 const double hwa = a.lt.hw[a.bx.level[A]];
@@ -444,13 +446,13 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
                 }
             }
         }
-        const double tot = (double)far + tnr + (double)xx.w;
+        const double tot = (double)far + tnr + own_term(a, sbit, ot, scale_exp);
         S_out[ot] = (TO)(a.P * ldexp(tot, scale_exp));
     };
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-        if (q[u] >= 0) finish(q[u], cell[u], out[u], x[u], tnear[u]);
-    // targets beyond the first kU x 256 (leaves of levels without an operator may hold more)
+        if (q[u] >= 0) finish(q[u], cell[u], out[u], k[u], sb[u], tnear[u]);
+    // points beyond the first kU x 256 (leaves of levels without an operator may hold more)
     for (int32_t f = kU * 256 + t; f < total; f += 256) {
         int lo = 0, hi = cnt - 1;
         while (lo < hi) {
@@ -459,11 +461,11 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
             else hi = mid - 1;
         }
         const int32_t kk = lt0[lo] + (f - loff[lo]);
-        finish(lo, gm > 0 ? tcell[kk] : 0, tout[kk], tdat[kk], lnear[lo] ? t_near[kk] : 0.0);
+        finish(lo, gm > 0 ? pcell[kk] : 0, perm[kk], kk, sel[kk], lnear[lo] ? t_near[kk] : 0.0);
     }
     if (a.work && t < cnt) {
         const int32_t b = lbox[t];
-        const int32_t tn = a.bx.t_cnt[b];
+        const int32_t tn = a.bx.t_cnt[b];  // targets (the entry counts all the leaf's points)
         unsigned long long near_src = 0;
         for (uint32_t e = a.L.u_off[b]; e < a.L.u_off[b + 1]; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
         atomicAdd(&a.work[0], near_src * tn);
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
 #pragma unroll
         for (int k = 0; k < NK; ++k)
             uv[k] = (gm > 0 && 64 * k + lane < nl) ? a.u[(size_t)b * nl + 64 * k + lane] : T(0);
-        const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+        const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
         const bool near = a.L.u_off[b + 1] > a.L.u_off[b];
         const bool has_w = a.L.w_off[b + 1] > a.L.w_off[b];
         if (a.work && lane == 0) {
@@ -558,21 +560,25 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
             if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
             if (has_w) atomicAdd(&a.work[2], (unsigned long long)(a.L.w_off[b + 1] - a.L.w_off[b]) * nl * tn);
         }
-        for (int tb = 0; tb < tn; tb += 64) {
-            const int t = tb + lane;
-            const bool act = t < tn;
+        // the leaf's points in sorted order, the targets among them flagged
+        for (int tb = 0; tb < np; tb += 64) {
+            const int32_t k = p0 + tb + lane;
+            const uint32_t sb = tb + lane < np ? a.sel[k] : 0u;
+            const bool act = (sb & 2u) != 0;
             V4<T> x;
-            if (act) x = a.t_dat[tf + t];
+            if (act && has_w) x = point_xyz(a, k);
             else x.x = x.y = x.z = x.w = T(0);
             T far = 0;
             if (gm > 0) {
-                const int r = act ? local_cell(a, a.t_cell[tf + t], b, gm) : 0;
+                const int r = act ? local_cell(a, a.pcell[k], b, gm) : 0;
                 far = staged ? grid_far<T, NK, true>(Gs, R, nl, r, uv) : grid_far<T, NK, false>(G, R, nl, r, uv);
             }
             if (has_w) far += w_list_far<T, NK>(a, b, x, act, lane);
-            if (act)
-                put_output(S_out, a.t_out, tf + t, a.P, (double)far + (near ? t_near[tf + t] : 0.0) + (double)x.w,
+            if (act) {
+                const int32_t o = a.perm[k];
+                put_output(S_out, o, a.P, (double)far + (near ? t_near[k] : 0.0) + own_term(a, sb, o, scale_exp),
                            scale_exp);
+            }
         }
     }
 }
@@ -614,7 +620,7 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
             }
             __syncthreads();
         }
-        const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+        const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
         const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
         const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
         if (a.work && threadIdx.x == 0) {
@@ -625,11 +631,13 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
             if (has_far) atomicAdd(&a.work[1], (unsigned long long)tn * ns);
             if (w1 > w0) atomicAdd(&a.work[2], (unsigned long long)(w1 - w0) * nl * tn);
         }
-        for (int tb = 0; tb < tn; tb += blockDim.x) {
-            const int t = tb + threadIdx.x;
-            const bool act = t < tn;
+        // the leaf's points in sorted order, the targets among them flagged
+        for (int tb = 0; tb < np; tb += blockDim.x) {
+            const int32_t k = p0 + tb + threadIdx.x;
+            const uint32_t sb = tb + (int)threadIdx.x < np ? a.sel[k] : 0u;
+            const bool act = (sb & 2u) != 0;
             V4<T> x;
-            if (act) x = a.t_dat[tf + t];
+            if (act) x = point_xyz(a, k);
             else x.x = x.y = x.z = x.w = T(0);
             T far = 0;
             if (has_far && act)
@@ -655,9 +663,11 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
                         far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * wphi[li];
                     }
             }
-            if (act)
-                put_output(S_out, a.t_out, tf + t, a.P, (double)far + (u1 > u0 ? t_near[tf + t] : 0.0) + (double)x.w,
+            if (act) {
+                const int32_t o = a.perm[k];
+                put_output(S_out, o, a.P, (double)far + (u1 > u0 ? t_near[k] : 0.0) + own_term(a, sb, o, scale_exp),
                            scale_exp);
+            }
         }
     }
 }
@@ -699,19 +709,21 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
         const int32_t b = a.L.near_leaves[idx];
         const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
-        const int32_t tf = a.bx.t_first[b], tn = a.bx.t_cnt[b];
+        const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0;
         const bool tab_b = tab && a.bx.level[b] == a.near_level;
-        for (int tb = 0; tb < tn; tb += 64) {
+        // the leaf's points in sorted order, the targets among them flagged
+        for (int tb = 0; tb < np; tb += 64) {
             const int t = tb + lane;
-            const bool act = t < tn;
+            const int32_t k = p0 + min(t, np - 1);
+            const bool act = t < np && (a.sel[k] & 2u) != 0;
             V4<T> x;
-            if (act) x = a.t_dat[tf + t];
+            if (act) x = point_xyz(a, k);
             else x.x = x.y = x.z = x.w = T(0);
-            // table index of the target's cell with every offset bias folded in (lanes without
-            // a target take the leaf's first one, so that their reads stay inside the table)
+            // table index of the point's cell with every offset bias folded in (lanes past the
+            // leaf's end take its last point, so that their reads stay inside the table)
             int tl = 0;
             if (tab_b) {
-                const int32_t c = a.t_cell[tf + (act ? t : 0)];
+                const int32_t c = a.pcell[k];
                 tl = (((c & 1023) + TR) * TS + (((c >> 10) & 1023) + TR)) * TS + ((c >> 20) + TR);
             }
             Acc<T> near;
@@ -805,7 +817,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
             if (w == 0 && act) {
                 double tot = 0.0;
                 for (int q = 0; q < kNearWaves; ++q) tot += part[q][lane];
-                t_near[tf + t] = tot;
+                t_near[k] = tot;
             }
         }
     }

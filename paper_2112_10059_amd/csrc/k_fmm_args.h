@@ -34,6 +34,14 @@ struct FmmArgs {
     const T *grid_gt;
     const int32_t *s_cell;
     const int32_t *t_cell;
+    // targets are read in place: the points of a target leaf in sorted order, flagged by sel
+    // (bit 0 source, bit 1 target), with their plan-time cells and coordinates
+    const uint8_t *sel;
+    const int32_t *pcell;   // sorted packed cells (uniform grids), else null
+    const float4 *xyzf;     // FP32 plans: sorted coordinates
+    const double *xyzd;     // sorted coordinates (n x 3)
+    const T *I;             // source intensities in caller order (own-cell term)
+    double c_self;
     // near-field kernel table (uniform grids, FP32): entries at the cell offsets of adjacent
     // leaves of level near_level, offsets within [-near_R, near_R] per axis; null if absent
     const float *near_tab;
@@ -64,6 +72,31 @@ __device__ __forceinline__ int local_cell(const FmmArgs<T> &a, int32_t cell, int
     return (i * m + j) * m + k;
 }
 
+// coordinates of sorted point k in the working precision
+template <class T>
+__device__ __forceinline__ V4<T> point_xyz(const FmmArgs<T> &a, int64_t k)
+{
+    V4<T> x;
+    if constexpr (sizeof(T) == 4) {
+        x = a.xyzf[k];
+    } else {
+        x.x = a.xyzd[3 * k];
+        x.y = a.xyzd[3 * k + 1];
+        x.z = a.xyzd[3 * k + 2];
+    }
+    x.w = T(0);
+    return x;
+}
+
+// own-cell term of a target that is also a source (Sec. 2.4): c_self I 2^-e, rounded to the
+// working precision as the source's other terms are; o is the point's caller index
+template <class T>
+__device__ __forceinline__ double own_term(const FmmArgs<T> &a, uint8_t sel, int32_t o, int scale_exp)
+{
+    if (!(sel & 1u)) return 0.0;
+    return (double)(T)(a.c_self * ldexp((double)a.I[o], -scale_exp));
+}
+
 template <class T>
 inline FmmArgs<T> make_args(Plan &p)
 {
@@ -91,6 +124,12 @@ inline FmmArgs<T> make_args(Plan &p)
     a.grid_gt = (const T *)p.ops.grid_gt;
     a.s_cell = p.d_s_cell;
     a.t_cell = p.d_t_cell;
+    a.sel = p.d_sel;
+    a.pcell = p.grid_mode ? p.d_cell : nullptr;
+    a.xyzf = p.d_xyzf;
+    a.xyzd = p.d_xyz;
+    a.I = (const T *)p.cur_I;
+    a.c_self = p.c_self;
     a.near_tab = (const float *)p.ops.near_tab;
     a.near_R = p.ops.near_R;
     a.near_level = p.ops.near_level;

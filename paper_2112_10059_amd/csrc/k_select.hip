@@ -168,15 +168,16 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_tiles_kernel(const T *_
 
 // Pass two: the exclusive scan of the packed counts where the tree build reads it (the first
 // point of a box and the point after a box: bnd), and the compaction of the selected points in
-// Morton order: sources (x, y, z, w I 2^-e) and targets (x, y, z, own-cell term c_self I 2^-e if
-// the point is also a source) with their caller indices and grid cells.  Coordinates come from
-// the plan's sorted copy in the working precision (C: float4, FP64: three doubles).
+// Morton order: sources (x, y, z, w I 2^-e) and, with tgt_compact (the direct method), targets
+// (x, y, z, own-cell term c_self I 2^-e if the point is also a source) with their caller
+// indices and grid cells; the FMM reads its targets in place.  Coordinates come from the
+// plan's sorted copy in the working precision (C: float4, FP64: three doubles).
 template <class TI, class T, class C>
 __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     const TI *__restrict__ I, const int32_t *__restrict__ perm, const C *__restrict__ xyz,
     const double *__restrict__ w, double w_uniform, double c_self, int64_t n, CallScalars *__restrict__ sc,
     const uint8_t *__restrict__ sel, const uint8_t *__restrict__ bnd, const uint64_t *__restrict__ partial,
-    int64_t nb, int tile_sums, uint64_t *__restrict__ scanned, int32_t *__restrict__ t_out,
+    int64_t nb, int tile_sums, int tgt_compact, uint64_t *__restrict__ scanned, int32_t *__restrict__ t_out,
     typename Vec4T<T>::type *__restrict__ s_dat, typename Vec4T<T>::type *__restrict__ t_dat,
     const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell, int32_t *__restrict__ t_cell)
 {
@@ -242,7 +243,8 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
         const int64_t k = base + st * 64 + lane;
         if (k >= n) continue;
         if (bnd[k]) scanned[k] = here;
-        if (!f[st]) continue;
+        // points that are only targets need nothing more unless targets are compacted
+        if (!(tgt_compact ? f[st] : (f[st] & 1u))) continue;
         const uint32_t sp_lo = (uint32_t)(here & 0xffffffffu), sp_hi = (uint32_t)(here >> 32);
         const int32_t o = perm[k];
         const double Iv = (double)I[o] * scale;
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
             s_dat[sp_lo] = d;
             if (cell) s_cell[sp_lo] = cell[k];
         }
-        if (f[st] & 2u) {
+        if ((f[st] & 2u) && tgt_compact) {
             t_out[sp_hi] = o;
             typename Vec4T<T>::type d;
             d.x = (T)x;
@@ -345,12 +347,12 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
     if (p.precision == PH_FP64)
         select_compact_kernel<double, double, double><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
             (const double *)I, p.d_perm, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
-            partial, nb, tile_sums, p.d_flag, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
+            partial, nb, tile_sums, p.method == PH_METHOD_DIRECT ? 1 : 0, p.d_flag, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
     else
         select_compact_kernel<float, float, float4><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
             (const float *)I, p.d_perm, p.d_xyzf, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
-            partial, nb, tile_sums, p.d_flag, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
+            partial, nb, tile_sums, p.method == PH_METHOD_DIRECT ? 1 : 0, p.d_flag, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
 }
 

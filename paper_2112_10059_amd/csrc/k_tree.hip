@@ -277,7 +277,8 @@ __global__ __launch_bounds__(kListBlock) void list_count_kernel(BoxArrays bx, Le
     const bool grid_leaf = tleaf && ((grid_levels >> lev) & 1u);
     // grid-operator leaves go to their level's segment (a wave rarely spans two levels)
     uint64_t pending = __ballot(grid_leaf);
-    const int4 entry = make_int4(b, b >= 0 ? bx.t_first[b] : 0, b >= 0 ? bx.t_cnt[b] : 0,
+    // the leaf's points in sorted order (its targets are those with the target flag)
+    const int4 entry = make_int4(b, b >= 0 ? bx.start[b] : 0, b >= 0 ? bx.end[b] - bx.start[b] : 0,
                                  (nu > 0 ? 1 : 0) | (nw > 0 ? 2 : 0));
     while (pending) {
         const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);

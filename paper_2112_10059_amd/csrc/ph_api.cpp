@@ -768,6 +768,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
         };
         const bool learned = p.selector == PH_SEL_LEARNED;
         if (++p.call_gen == 0) p.call_gen = 1;
+        p.cur_I = I;  // the target kernels read the own-cell term's intensity from it
         mark(0, s);
         launch_reset_scalars(p.d_sc, s);
         if (learned) selector_reduce(p, I, absE, s);  // the maxima come with the per-leaf statistics

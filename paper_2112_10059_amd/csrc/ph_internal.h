@@ -160,6 +160,7 @@ struct Plan {
     double cube_size = 1;
     double h = 0;
     double c_self = 0;
+    const void *cur_I = nullptr;             // the evaluation's source intensities (caller order)
     Gas gas{};
     ph_thresholds thr{};
     bool uniform_w = true;
