@@ -320,8 +320,8 @@ __device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint
 
 // Far field of grid-operator leaves with n_lam <= 64 and at most 4^3 cells (FP32), on the
 // matrix cores.  A workgroup takes kFarMLeaves leaves of one level: with their check values
-// U (leaves x n_lam) and the level operator G (n_lam x cells) in LDS, C = U G is a
-// 16 x 64 x 64 product (wave j: the 16 x 16 tile of cells 16 j .. 16 j + 15,
+// U (leaves x n_lam) in LDS and the level operator G (n_lam x cells) read by each wave as its
+// MFMA operand fragment, C = U G is a 16 x 64 x 64 product (wave j: the 16 x 16 tile of cells 16 j .. 16 j + 15,
 // v_mfma_f32_16x16x4_f32 over k), written back to LDS; then the 256 threads walk the
 // workgroup's points (each leaf's sorted range) in one flat range, their loads issued
 // together, and finish the targets among them as the wave kernel does (far = C[leaf][cell],
@@ -334,7 +334,6 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
                                                        const double *__restrict__ t_near, uint32_t level_mask)
 {
     __shared__ float Us[kFarMLeaves][65];  // U, then C = U G
-    __shared__ float Gs[64][65];
     __shared__ int32_t lbox[kFarMLeaves], lt0[kFarMLeaves], loff[kFarMLeaves + 1];
     __shared__ int32_t lorg[kFarMLeaves][3];  // the leaves' first cells (anchor * m)
     __shared__ uint8_t lnear[kFarMLeaves], lw[kFarMLeaves];
@@ -347,6 +346,14 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     const int gm = level >= 2 ? a.grid_m[level] : 0;  // 0: no far field at this level
     const int R = gm * gm * gm;
     const float *G = a.grid_g + a.grid_off[level];
+    // this wave's B operand straight from memory, all 16 loads in flight at once: lane l holds
+    // G[4 kk + l / 16][16 w + l % 16] for step kk of the product
+    float gb[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        const int li = 4 * kk + (lane >> 4), c = 16 * w + (lane & 15);
+        gb[kk] = (li < nl && c < R) ? G[li * R + c] : 0.0f;
+    }
     if (w == 0 && lane < kFarMLeaves) {
         const bool valid = lane < cnt;
         const int4 en = valid ? a.L.far_a[a.lt.base[level] + first + lane] : make_int4(-1, 0, 0, 0);
@@ -366,10 +373,6 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
         lorg[lane][0] = b >= 0 ? a.bx.ax[b] * gm : 0;
         lorg[lane][1] = b >= 0 ? a.bx.ay[b] * gm : 0;
         lorg[lane][2] = b >= 0 ? a.bx.az[b] * gm : 0;
-    }
-    for (int i = t; i < 64 * 64; i += 256) {
-        const int li = i >> 6, c = i & 63;
-        Gs[li][c] = (li < nl && c < R) ? G[li * R + c] : 0.0f;
     }
     __syncthreads();
     const int32_t total = loff[cnt];
@@ -397,10 +400,13 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
             k[u] = lt0[lo] + (f - loff[lo]);
         }
     }
-    for (int i = t; i < kFarMLeaves * 64; i += 256) {
-        const int qq = i >> 6, li = i & 63;
+    constexpr int kUR = kFarMLeaves * 64 / 256;  // check values per thread
+    float uv[kUR];
+#pragma unroll
+    for (int r = 0; r < kUR; ++r) {
+        const int i = t + 256 * r, qq = i >> 6, li = i & 63;
         const int32_t b = lbox[qq];
-        Us[qq][li] = (b >= 0 && li < nl) ? a.u[(size_t)b * nl + li] : 0.0f;
+        uv[r] = (b >= 0 && li < nl) ? a.u[(size_t)b * nl + li] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u)
@@ -410,11 +416,13 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
             out[u] = perm[k[u]];
             tnear[u] = lnear[q[u]] ? t_near[k[u]] : 0.0;
         }
+#pragma unroll
+    for (int r = 0; r < kUR; ++r) Us[(t + 256 * r) >> 6][(t + 256 * r) & 63] = uv[r];
     __syncthreads();
     f32x4 acc = f32x4{0, 0, 0, 0};
 #pragma unroll
     for (int k0 = 0; k0 < 64; k0 += 4)
-        acc = Mfma<float>::mma(Us[lane & 15][k0 + (lane >> 4)], Gs[k0 + (lane >> 4)][16 * w + (lane & 15)], acc);
+        acc = Mfma<float>::mma(Us[lane & 15][k0 + (lane >> 4)], gb[k0 / 4], acc);
     __syncthreads();  // every wave has read U
 #pragma unroll
     for (int r = 0; r < 4; ++r) Us[Mfma<float>::row(lane, r)][16 * w + (lane & 15)] = acc[r];

@@ -76,6 +76,53 @@ __device__ __forceinline__ bool tile_used(const uint32_t *__restrict__ tuse, con
 //   M2L: phi of the boxes with sources, Op = 316 stacked offsets   -> Y
 //   L2L: u of the split boxes with targets, Op = 8 stacked octants -> u of child c
 //   M2M: phi of the boxes with sources, Op = 8 stacked octants     -> Z (child c to parent)
+// Stage loads of a GEMM tile, all issued before any use (one round trip), into v[u] for the
+// tile element e = t + 256 u (row e / KT, column e % KT).  With KT = 64 a wave covers whole
+// rows (row ws + 4 u, column = lane), so each row's base address is a scalar and a load costs
+// one register for its value.
+// Rows m0 + n of a row-major matrix (row length ld), columns k0 + k below kcols.
+template <class T, int KT>
+__device__ __forceinline__ void load_rows(T (&v)[KT * kTile / 256], const T *__restrict__ A, int ld, int m0,
+                                          int M, int kcols, int k0, int ws, int t)
+{
+    constexpr int kV = KT * kTile / 256;
+    const int lane = t & 63;
+#pragma unroll
+    for (int u = 0; u < kV; ++u) {
+        if constexpr (KT == 64) {
+            const int gm = m0 + ws + 4 * u;
+            const T *row = A + (size_t)(gm < M ? gm : 0) * ld + k0;
+            v[u] = (gm < M && k0 + lane < kcols) ? row[lane] : T(0);
+        } else {
+            const int e = t + 256 * u, gm = m0 + e / KT, gk = k0 + e % KT;
+            v[u] = (gm < M && gk < kcols) ? A[(size_t)gm * ld + gk] : T(0);
+        }
+    }
+}
+// Rows of the boxes listed in LDS (box < 0: zero row), columns k0 + k below nl.
+template <class T, int KT>
+__device__ __forceinline__ void load_box_rows(T (&v)[KT * kTile / 256], const T *__restrict__ X, int nl,
+                                              const int32_t *boxes, int k0, int ws, int t)
+{
+    constexpr int kV = KT * kTile / 256;
+    static_assert(kV <= 64, "one row per lane of the box read");
+    const int lane = t & 63;
+    // with KT = 64 lane u reads row u's box, all of them in one LDS access
+    const int32_t rb = KT == 64 ? boxes[ws + 4 * (lane % kV)] : -1;
+#pragma unroll
+    for (int u = 0; u < kV; ++u) {
+        if constexpr (KT == 64) {
+            const int32_t bx = __builtin_amdgcn_readlane(rb, u);
+            const T *row = X + (size_t)(bx >= 0 ? bx : 0) * nl + k0;
+            v[u] = (bx >= 0 && k0 + lane < nl) ? row[lane] : T(0);
+        } else {
+            const int e = t + 256 * u, gk = k0 + e % KT;
+            const int32_t bx = boxes[e / KT];
+            v[u] = (bx >= 0 && gk < nl) ? X[(size_t)bx * nl + gk] : T(0);
+        }
+    }
+}
+
 template <class T, int MODE>
 __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, int kp, int M, int nl,
                                                     const T *__restrict__ vec, const int32_t *__restrict__ list,
@@ -96,6 +143,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
     __shared__ int32_t kid[MODE == kModeL2L ? kTile : 1][8];  // L2L: children of the column boxes
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int ws = __builtin_amdgcn_readfirstlane(w);  // the wave index in a scalar register
     const int wn = w >> 1, wm = w & 1;
     using acc_t = typename Mfma<T>::acc_t;
     // blockIdx.y strides over the column tiles of all segments (a bounded grid for any count);
@@ -115,12 +163,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
         constexpr int kBV = KT * kTile / 256;
         T breg[kBV];
         const bool load_b0 = !resident || si != bseg;
-        if (load_b0)
-#pragma unroll
-            for (int u = 0; u < kBV; ++u) {
-                const int e = t + 256 * u, n = e / KT, k = e % KT, gm = m0 + n;
-                breg[u] = (gm < M && k < kp) ? Op[(size_t)gm * kp + k] : T(0);
-            }
+        if (load_b0) load_rows<T, KT>(breg, Op, kp, m0, M, kp, 0, ws, t);
         __syncthreads();
         if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
         acc_t acc[2][2];
@@ -129,22 +172,31 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
             for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
         for (int k0 = 0; k0 < kp; k0 += KT) {
             __syncthreads();
+            // every load of the stage goes out before the first LDS store (one round trip)
+            constexpr int kKid = kTile * 8 / 256;
+            int32_t kreg[MODE == kModeL2L ? kKid : 1];
             if (MODE == kModeL2L && k0 == 0)
-                for (int e = t; e < kTile * 8; e += 256) {
+#pragma unroll
+                for (int u = 0; u < kKid; ++u) {
+                    const int e = t + 256 * u;
                     const int32_t bx = boxes[e >> 3];
-                    kid[e >> 3][e & 7] = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
+                    kreg[u] = bx >= 0 ? child[(size_t)bx * 8 + (e & 7)] : -1;
                 }
-            for (int e = t; e < KT * kTile; e += 256) {
-                const int n = e / KT, k = e % KT;
-                const int gk = k0 + k;
-                const int32_t bx = boxes[n];
-                T v = T(0);
-                if (bx >= 0 && gk < nl) v = vec[(size_t)bx * nl + gk];
-                As[n][k] = v;
-                const int gm = m0 + n;
-                if (k0 > 0) Bs[n][k] = (gm < M && gk < kp) ? Op[(size_t)gm * kp + gk] : T(0);
+            T areg[kBV];
+            load_box_rows<T, KT>(areg, vec, nl, boxes, k0, ws, t);
+            if (k0 > 0) load_rows<T, KT>(breg, Op, kp, m0, M, kp, k0, ws, t);
+            if (MODE == kModeL2L && k0 == 0)
+#pragma unroll
+                for (int u = 0; u < kKid; ++u) {
+                    const int e = t + 256 * u;
+                    kid[e >> 3][e & 7] = kreg[u];
+                }
+#pragma unroll
+            for (int u = 0; u < kBV; ++u) {
+                const int e = t + 256 * u;
+                As[e / KT][e % KT] = areg[u];
             }
-            if (k0 == 0 && load_b0)
+            if (k0 > 0 || load_b0)
 #pragma unroll
                 for (int u = 0; u < kBV; ++u) {
                     const int e = t + 256 * u;
