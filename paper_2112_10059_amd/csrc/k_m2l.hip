@@ -69,6 +69,18 @@ __device__ __forceinline__ bool tile_used(const uint32_t *__restrict__ tuse, con
     return false;
 }
 
+// The offsets of the row tile at m0 (rows o n_lam + i) that the column's source box sends
+// along, as bits from o_lo: its stored mask (slot: the box's index in the source list)
+__device__ __forceinline__ uint32_t col_offsets(const uint32_t *__restrict__ buse, int32_t slot, int m0, int M,
+                                                int nl)
+{
+    const uint32_t *bu = buse + (size_t)slot * kUseWords;
+    const int o_lo = m0 / nl, o_hi = min(M - 1, m0 + kTile - 1) / nl;
+    uint32_t bits = 0;
+    for (int o = o_lo; o <= o_hi; ++o) bits |= ((bu[o >> 5] >> (o & 31)) & 1u) << (o - o_lo);
+    return bits;
+}
+
 // Translation GEMM on the matrix cores, out^T = X^T Op^T with Op (M x kp, row-major) a
 // stacked translation operator and X (kp x ncols) the gathered columns, over one or more
 // levels (segments) in one launch:
@@ -130,7 +142,8 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                                                     T *__restrict__ out0, const int32_t *__restrict__ child,
                                                     const int32_t *__restrict__ t_cnt,
                                                     unsigned long long *__restrict__ work,
-                                                    const uint32_t *__restrict__ use)
+                                                    const uint32_t *__restrict__ use,
+                                                    const uint32_t *__restrict__ buse)
 {
     // K staged 64 deep for FP32 (one LDS fill when n_lam <= 64), 32 for FP64
     constexpr int KT = sizeof(T) == 4 ? 2 * kTK : kTK;
@@ -141,6 +154,7 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
     __shared__ T Bs[kTile][KT + kPad];  // Op tile
     __shared__ int32_t boxes[kTile];
     __shared__ int32_t kid[MODE == kModeL2L ? kTile : 1][8];  // L2L: children of the column boxes
+    __shared__ uint32_t cols_used[MODE == kModeM2L ? kTile : 1];  // M2L: offsets each column sends
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int ws = __builtin_amdgcn_readfirstlane(w);  // the wave index in a scalar register
@@ -165,7 +179,12 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
         const bool load_b0 = !resident || si != bseg;
         if (load_b0) load_rows<T, KT>(breg, Op, kp, m0, M, kp, 0, ws, t);
         __syncthreads();
-        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
+        if (t < kTile) {
+            const bool in = n0 + t < ncols;
+            const int32_t slot = sg.list_base + sg.r0 + n0 + t;
+            boxes[t] = in ? list[slot] : -1;
+            if (MODE == kModeM2L) cols_used[t] = (in && buse) ? col_offsets(buse, slot, m0, M, nl) : ~0u;
+        }
         acc_t acc[2][2];
         T own[2][2][4];  // L2L: the children's level-local parts
         for (int i = 0; i < 2; ++i)
@@ -243,10 +262,131 @@ __global__ __launch_bounds__(256) void tgemm_kernel(const T *__restrict__ Op0, i
                         out0[(size_t)C * nl + li] = acc[i][j][r] + own[i][j][r];
                         if (work && li == 0 && t_cnt[C] > 0) atomicAdd(&work[7], 1ull);
                     } else {
+                        // only the offsets some target of the box's V lists reads
+                        if (MODE == kModeM2L && !((cols_used[nl_] >> (gm / nl - m0 / nl)) & 1u)) continue;
                         out[(size_t)gn * M + gm] = acc[i][j][r];
                     }
                 }
             }
+    }
+}
+
+// M2L products in FP32 when a row tile's K fits one stage (k_pad <= 64): the workgroup keeps
+// one 64-row tile of the stacked offset slots and walks the column tiles blockIdx.y,
+// blockIdx.y + gridDim.y, ... of all levels.  Their boxes, and the offsets each box sends
+// along, are listed in LDS kPipeTiles tiles at a time; then the next used tile's densities
+// (and its operator tile, when its level differs) are loaded into registers while the current
+// tile's products run and its columns are stored, so that loads, matrix-core work and stores
+// of consecutive tiles overlap.
+constexpr int kPipeTiles = 8;
+
+__global__ __launch_bounds__(256) void m2l_pipe_kernel(const float *__restrict__ Op0, int kp, int M, int nl,
+                                                       const float *__restrict__ phi,
+                                                       const int32_t *__restrict__ list,
+                                                       const int32_t *__restrict__ count, GemmSegs segs,
+                                                       float *__restrict__ out0,
+                                                       const uint32_t *__restrict__ use,
+                                                       const uint32_t *__restrict__ buse)
+{
+    constexpr int KT = 64, kV = KT * kTile / 256;
+    __shared__ float As[kTile][KT + kPad];  // the current tile's densities, a row per box
+    __shared__ float Bs[kTile][KT + kPad];  // the operator tile, a row per offset slot row
+    __shared__ int32_t boxes[kPipeTiles][kTile];
+    __shared__ uint32_t cols[kPipeTiles][kTile];
+    __shared__ int32_t tseg[kPipeTiles], tn0[kPipeTiles], tnc[kPipeTiles];
+    const int m0 = blockIdx.x * kTile;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int ws = __builtin_amdgcn_readfirstlane(w);
+    const int wn = w >> 1, wm = w & 1;
+    for (int32_t tb = blockIdx.y;; tb += kPipeTiles * (int32_t)gridDim.y) {
+        __syncthreads();  // the previous batch's lists have been read
+        if (t < kPipeTiles) {
+            int si;
+            int32_t n0, nc;
+            const bool ok = seg_tile(segs, count, tb + t * (int32_t)gridDim.y, si, n0, nc);
+            // -1: past the last tile, -2: a tile whose offsets no target reads
+            tseg[t] = !ok ? -1 : ((use && !tile_used(use, segs.s[si], n0, m0, M, nl)) ? -2 : si);
+            tn0[t] = ok ? n0 : 0;
+            tnc[t] = ok ? nc : 0;
+        }
+        __syncthreads();
+        if (tseg[0] == -1) return;
+        // every listed column's box and offset bits, the loads issued together
+        constexpr int kL = kPipeTiles * kTile / 256;
+        int32_t bv[kL];
+        uint32_t cv[kL];
+#pragma unroll
+        for (int u = 0; u < kL; ++u) {
+            const int e = t + 256 * u, j = e / kTile, c = e % kTile;
+            const int si = tseg[j];
+            bv[u] = -1;
+            cv[u] = 0u;
+            if (si >= 0 && tn0[j] + c < tnc[j]) {
+                const int32_t slot = segs.s[si].list_base + segs.s[si].r0 + tn0[j] + c;
+                bv[u] = list[slot];
+                cv[u] = buse ? col_offsets(buse, slot, m0, M, nl) : ~0u;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kL; ++u) {
+            const int e = t + 256 * u;
+            boxes[e / kTile][e % kTile] = bv[u];
+            cols[e / kTile][e % kTile] = cv[u];
+        }
+        __syncthreads();
+        int j = 0;
+        while (j < kPipeTiles && tseg[j] == -2) ++j;
+        if (j >= kPipeTiles || tseg[j] < 0) continue;
+        float areg[kV], breg[kV];
+        load_box_rows<float, KT>(areg, phi, nl, boxes[j], 0, ws, t);
+        load_rows<float, KT>(breg, Op0 + segs.s[tseg[j]].op_off, kp, m0, M, kp, 0, ws, t);
+        int bseg = -1;  // the segment whose operator tile is in Bs
+        while (true) {
+            const int sj = tseg[j];
+            int jn = j + 1;
+            while (jn < kPipeTiles && tseg[jn] == -2) ++jn;
+            const bool has_next = jn < kPipeTiles && tseg[jn] >= 0;
+#pragma unroll
+            for (int u = 0; u < kV; ++u) As[ws + 4 * u][lane] = areg[u];
+            if (sj != bseg)
+#pragma unroll
+                for (int u = 0; u < kV; ++u) Bs[ws + 4 * u][lane] = breg[u];
+            __syncthreads();
+            bseg = sj;
+            // the next tile's loads go out before this tile's products
+            if (has_next) {
+                load_box_rows<float, KT>(areg, phi, nl, boxes[jn], 0, ws, t);
+                if (tseg[jn] != sj) load_rows<float, KT>(breg, Op0 + segs.s[tseg[jn]].op_off, kp, m0, M, kp, 0, ws, t);
+            }
+            f32x4 acc[2][2];
+            for (int i = 0; i < 2; ++i)
+                for (int q = 0; q < 2; ++q) acc[i][q] = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KT; ks += 4) {
+                const int kk = ks + (lane >> 4);
+                float a[2], b[2];
+                for (int i = 0; i < 2; ++i) a[i] = As[wn * 32 + i * 16 + (lane & 15)][kk];
+                for (int q = 0; q < 2; ++q) b[q] = Bs[wm * 32 + q * 16 + (lane & 15)][kk];
+                for (int i = 0; i < 2; ++i)
+                    for (int q = 0; q < 2; ++q) acc[i][q] = Mfma<float>::mma(a[i], b[q], acc[i][q]);
+            }
+            float *out = out0 + (size_t)segs.s[sj].out_row * M;
+            const int32_t n0 = tn0[j], nc = tnc[j];
+            for (int i = 0; i < 2; ++i)
+                for (int q = 0; q < 2; ++q) {
+                    const int gm = m0 + wm * 32 + q * 16 + (lane & 15);
+                    for (int r = 0; r < 4; ++r) {
+                        const int cn = wn * 32 + i * 16 + Mfma<float>::row(lane, r), gn = n0 + cn;
+                        if (gn >= nc || gm >= M) continue;
+                        // only the offsets some target of the box's V lists reads
+                        if (!((cols[j][cn] >> (gm / nl - m0 / nl)) & 1u)) continue;
+                        out[(size_t)gn * M + gm] = acc[i][q][r];
+                    }
+                }
+            __syncthreads();  // every wave is done with As and Bs
+            if (!has_next) break;
+            j = jn;
+        }
     }
 }
 
@@ -274,11 +414,13 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
                                                               const int32_t *__restrict__ list,
                                                               const int32_t *__restrict__ count, GemmSegs segs,
                                                               float *__restrict__ out0,
-                                                              const uint32_t *__restrict__ use)
+                                                              const uint32_t *__restrict__ use,
+                                                              const uint32_t *__restrict__ buse)
 {
     __shared__ __align__(16) uint16_t Ah[kTile][kTK + kPadB], Al[kTile][kTK + kPadB];
     __shared__ __align__(16) uint16_t Bh[kTile][kTK + kPadB], Bl[kTile][kTK + kPadB];
     __shared__ int32_t boxes[kTile];
+    __shared__ uint32_t cols_used[kTile];
     const int m0 = blockIdx.x * kTile;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wn = w >> 1, wm = w & 1;
@@ -291,7 +433,12 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
         float *out = out0 + (size_t)sg.out_row * M;
         if (use && !tile_used(use, sg, n0, m0, M, nl)) continue;
         __syncthreads();
-        if (t < kTile) boxes[t] = (n0 + t < ncols) ? list[sg.list_base + sg.r0 + n0 + t] : -1;
+        if (t < kTile) {
+            const bool in = n0 + t < ncols;
+            const int32_t slot = sg.list_base + sg.r0 + n0 + t;
+            boxes[t] = in ? list[slot] : -1;
+            cols_used[t] = (in && buse) ? col_offsets(buse, slot, m0, M, nl) : ~0u;
+        }
         f32x4 acc[2][2];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
@@ -336,8 +483,9 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
             for (int j = 0; j < 2; ++j) {
                 const int gm = m0 + wm * 32 + j * 16 + (lane & 15);
                 for (int r = 0; r < 4; ++r) {
-                    const int gn = n0 + wn * 32 + i * 16 + 4 * (lane >> 4) + r;
+                    const int nl_ = wn * 32 + i * 16 + 4 * (lane >> 4) + r, gn = n0 + nl_;
                     if (gn >= ncols || gm >= M) continue;
+                    if (!((cols_used[nl_] >> (gm / nl - m0 / nl)) & 1u)) continue;
                     out[(size_t)gn * M + gm] = acc[i][j][r];
                 }
             }
@@ -531,11 +679,18 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
     if (std::is_same<T, float>::value && p.precision == PH_FP32_BF16SPLIT)
         tgemm_m2l_bf16s_kernel<<<g, 256, 0, s>>>((const uint16_t *)p.ops.m2l_hi, (const uint16_t *)p.ops.m2l_lo,
                                                  p.k_pad, M, nl, (const float *)p.d_phi, p.box.src_box,
-                                                 p.d_sc->lvl_src, sg, (float *)p.d_y, p.lists.m2l_tile_use);
-    else
+                                                 p.d_sc->lvl_src, sg, (float *)p.d_y, p.lists.m2l_tile_use,
+                                                 p.lists.m2l_box_use);
+    else if (std::is_same<T, float>::value && p.k_pad <= 64) {
+        // two workgroups per row tile, each walking every second column tile
+        dim3 gp((M + kTile - 1) / kTile, (unsigned)std::max<int64_t>(1, std::min<int64_t>(2, col_tiles)));
+        m2l_pipe_kernel<<<gp, 256, 0, s>>>((const float *)p.ops.m2l, p.k_pad, M, nl, (const float *)p.d_phi,
+                                           p.box.src_box, p.d_sc->lvl_src, sg, (float *)p.d_y,
+                                           p.lists.m2l_tile_use, p.lists.m2l_box_use);
+    } else
         tgemm_kernel<T, kModeM2L><<<g, 256, 0, s>>>((const T *)p.ops.m2l, p.k_pad, M, nl, (const T *)p.d_phi,
                                                     p.box.src_box, p.d_sc->lvl_src, sg, (T *)p.d_y, nullptr,
-                                                    nullptr, nullptr, p.lists.m2l_tile_use);
+                                                    nullptr, nullptr, p.lists.m2l_tile_use, p.lists.m2l_box_use);
 }
 
 template <class T>
@@ -594,7 +749,7 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
         tgemm_kernel<T, kModeL2L><<<gz, 256, 0, s>>>(
             (const T *)p.ops.l2l, p.k_pad, Mz, nl, (const T *)p.d_u, p.box.tpar_box, p.d_sc->lvl_tpar,
             one_seg(l - 1, p.level_base[l - 1], 0, pcap, (int64_t)l * Mz * p.k_pad, 0), (T *)p.d_u, p.box.child,
-            p.box.t_cnt, a.work, nullptr);
+            p.box.t_cnt, a.work, nullptr, nullptr);
     }
 }
 
@@ -639,7 +794,7 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
     tgemm_kernel<T, kModeM2M><<<g, 256, 0, s>>>(
         (const T *)p.ops.m2m, p.k_pad, Mw, nl, (const T *)p.d_phi, p.box.src_box, p.d_sc->lvl_src,
         one_seg(l + 1, p.level_base[l + 1], 0, ccap, (int64_t)(l + 1) * Mw * p.k_pad, 0), (T *)p.d_z, nullptr,
-        nullptr, nullptr, nullptr);
+        nullptr, nullptr, nullptr, nullptr);
     const int threads = nl <= 64 ? 64 : (nl <= 128 ? 128 : 256);
     m2m_gather_kernel<T><<<(unsigned)std::min<int64_t>(p.level_cap[l], 8192), threads, 0, s>>>(a, l,
                                                                                               (const T *)p.d_z);

@@ -303,8 +303,9 @@ __global__ __launch_bounds__(kListBlock) void list_count_kernel(BoxArrays bx, Le
 // along.  B has source box S in its V list iff B is a child of a colleague of S's parent, not
 // adjacent to S, at S's level; so one wave per source box S (levels >= 2) walks those
 // candidates (the children of the parent's split colleagues), enters each one with targets
-// once per call into its level's segment of vt (levels >= 3), and ORs the offset slots used
-// into the 316-bit mask of the 64-slot tile of the level's source list that holds S.
+// once per call into its level's segment of vt (levels >= 3), stores the 316-bit mask of the
+// offset slots used at S's slot, and ORs it into the mask of the 64-slot tile of the level's
+// source list that holds S.
 __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc,
                                                       Lists L, uint32_t gen)
 {
@@ -357,8 +358,11 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
             wave_append(fresh, L.vt + li.base[level], &sc->n_vt_lvl[level], B);
         }
         __builtin_amdgcn_wave_barrier();
-        if (lane < kUseWords && use[wv][lane])
-            atomicOr(&L.m2l_tile_use[(size_t)(li.tbase[level] + r / 64) * kUseWords + lane], use[wv][lane]);
+        if (lane < kUseWords) {
+            L.m2l_box_use[(size_t)(li.base[level] + r) * kUseWords + lane] = use[wv][lane];
+            if (use[wv][lane])
+                atomicOr(&L.m2l_tile_use[(size_t)(li.tbase[level] + r / 64) * kUseWords + lane], use[wv][lane]);
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }

@@ -103,6 +103,9 @@ struct Lists {
     // M2L offsets that reach a target, per tile of 64 slots of a level's source list (316 bits
     // in kUseWords words; the tiles of level l start at Plan::m2l_tile_base[l])
     uint32_t *m2l_tile_use = nullptr;
+    // the same per source box (at the box's slot in the level's source list), so that the
+    // products store only the columns some target reads
+    uint32_t *m2l_box_use = nullptr;
 };
 
 struct Gas {
