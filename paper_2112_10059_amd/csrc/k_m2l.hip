@@ -492,29 +492,28 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
     }
 }
 
-// The level-local part of the check values, one workgroup per target box B:
+// The level-local part of the check values, one wave (a workgroup of 64) per target box B:
 //   w_B = base + [first chunk: X-list sources of B] + sum over V(B) in this chunk of Y,
 // base = 0 in the first chunk, else the earlier chunks' sum; w_B is stored in u_B, and the L2L
 // product of the next level adds the parent's expansion to it.  V(B) = children of the
 // parent's colleagues not adjacent to B: the 8 x (colleagues with sources) candidates are
-// dealt to the four waves in 64-candidate slices (lane = candidate; a ballot marks those with
-// sources in this chunk) and each wave walks its set bits in candidate order, kB translations
-// in flight; the X list is dealt to the waves in turn.  The waves' partial sums are added to
-// the base in wave order.  The boxes: every box of level 2 and the listed boxes (V or X list)
-// of the deeper levels in gl.lo .. gl.hi, dealt to the workgroups as one flat range.
+// taken in 64-candidate slices (lane = candidate), the slice's translations compacted in
+// candidate order and read kB at a time (loads in flight together), added in candidate order.
+// A box's work is a chain of dependent loads, so a wave per box keeps many boxes in flight.
+// The boxes: every box of level 2 and the listed boxes (V or X list) of the deeper levels in
+// gl.lo .. gl.hi, dealt to the workgroups as one flat range.
 struct GatherLevels {
     int lo, hi;                      // levels
     int64_t y_row[kMaxDepth + 2];    // first row of each level's products in Y
 };
 
 template <class T, int NK>
-__global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, GatherLevels gl, const T *__restrict__ Y0,
-                                                          int M, int32_t r0, int32_t ccap, int init, int with_x)
+__global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLevels gl, const T *__restrict__ Y0,
+                                                         int M, int32_t r0, int32_t ccap, int init, int with_x)
 {
-    __shared__ T part[4][kMaxLattice];
-    __shared__ int32_t qs[4][27];   // per wave: the parent's colleagues with sources
-    __shared__ int32_t cds[4][64];  // per wave: a slice's translations
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int32_t qs[27];   // the parent's colleagues with sources
+    __shared__ int32_t cds[64];  // a slice's translations
+    const int lane = threadIdx.x & 63;
     const int nl = a.n_lam;
     constexpr int nk = NK;  // lattice values per lane: n_lam <= 64 NK
     for (int32_t idx = blockIdx.x;; idx += gridDim.x) {
@@ -550,7 +549,7 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, GatherLe
                 T cx, cy, cz;
                 box_centre(a, b, hw, cx, cy, cz);
                 const T h = (T)hw;
-                for (uint32_t e = x0 + w; e < x1; e += 4) {
+                for (uint32_t e = x0; e < x1; ++e) {
                     const int32_t C = a.L.x[e];
                     const int32_t sf = a.bx.s_first[C], sn = a.bx.s_cnt[C];
                     n_p2l += (unsigned long long)sn * nl;
@@ -579,15 +578,15 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, GatherLe
         const uint64_t qmask = __ballot(Qd >= 0);
         const int nc = 8 * __popcll(qmask);
         const uint64_t below = (1ull << lane) - 1ull;
-        // the colleagues with sources, compacted in colleague order (this wave's LDS row)
-        if (Qd >= 0) qs[w][__popcll(qmask & below)] = Qd;
+        // the colleagues with sources, compacted in colleague order
+        if (Qd >= 0) qs[__popcll(qmask & below)] = Qd;
         wave_lds_sync();
-        for (int f0 = 64 * w; f0 < nc; f0 += 256) {
+        for (int f0 = 0; f0 < nc; f0 += 64) {
             const int f = f0 + lane;
             const bool valid = f < nc;
             int32_t code = -1;  // rank * 316 + slot
             if (valid) {
-                const int32_t Q = qs[w][f >> 3];  // the (f / 8)-th colleague with sources
+                const int32_t Q = qs[f >> 3];  // the (f / 8)-th colleague with sources
                 const int32_t A = a.bx.child[(size_t)Q * 8 + (f & 7)];
                 if (A >= 0) {
                     const int32_t sr = a.bx.src_rank[A];
@@ -604,7 +603,8 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, GatherLe
             const uint64_t mask = __ballot(code >= 0);
             const int n = __popcll(mask);
             n_m2l += n;
-            if (code >= 0) cds[w][__popcll(mask & below)] = code;
+            wave_lds_sync();  // the previous slice's codes have been read
+            if (code >= 0) cds[__popcll(mask & below)] = code;
             wave_lds_sync();
             constexpr int kB = sizeof(T) == 4 ? 16 : 8;
             for (int u0 = 0; u0 < n; u0 += kB) {
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, GatherLe
                     T v[kB];
 #pragma unroll
                     for (int u = 0; u < kB; ++u) {
-                        const int32_t c = u0 + u < n ? cds[w][u0 + u] : 0;
+                        const int32_t c = u0 + u < n ? cds[u0 + u] : 0;
                         v[u] = (u0 + u < n && li < nl)
                                    ? Y[(size_t)(c / kNumM2L) * M + (size_t)(c % kNumM2L) * nl + li]
                                    : T(0);
@@ -625,20 +625,16 @@ __global__ __launch_bounds__(256) void down_gather_kernel(FmmArgs<T> a, GatherLe
                         if (u0 + u < n && li < nl) acc[k] += v[u];
                 }
             }
-            wave_lds_sync();  // the slice's codes have been read
         }
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int li = lane + 64 * k;
-            if (k < nk && li < nl) part[w][li] = acc[k];
+            if (k < nk && li < nl) {
+                const size_t o = (size_t)b * nl + li;
+                a.u[o] = init ? acc[k] : a.u[o] + acc[k];
+            }
         }
-        __syncthreads();
-        for (int li = threadIdx.x; li < nl; li += 256) {
-            T v = init ? T(0) : a.u[(size_t)b * nl + li];
-            for (int q = 0; q < 4; ++q) v += part[q][li];
-            a.u[(size_t)b * nl + li] = v;
-        }
-        __syncthreads();  // part is free for the next box
+        wave_lds_sync();  // qs and cds are free for the next box
         if (a.work && lane == 0) {
             if (n_m2l) atomicAdd(&a.work[5], n_m2l);
             if (n_p2l) atomicAdd(&a.work[4], n_p2l);
@@ -652,11 +648,11 @@ void launch_gather(Plan &p, const FmmArgs<T> &a, unsigned grid, const GatherLeve
 {
     const T *Y = (const T *)p.d_y;
     switch ((p.n_lam + 63) / 64) {
-    case 1: down_gather_kernel<T, 1><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
-    case 2: down_gather_kernel<T, 2><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
+    case 1: down_gather_kernel<T, 1><<<grid, 64, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
+    case 2: down_gather_kernel<T, 2><<<grid, 64, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
     case 3:
-    case 4: down_gather_kernel<T, 4><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
-    default: down_gather_kernel<T, 8><<<grid, 256, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
+    case 4: down_gather_kernel<T, 4><<<grid, 64, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
+    default: down_gather_kernel<T, 8><<<grid, 64, 0, s>>>(a, gl, Y, M, r0, ccap, init, with_x); break;
     }
 }
 
@@ -717,7 +713,8 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
     // level-local parts (V and X lists) of every level: no dependence between levels
     int64_t gcap = 0;
     for (int l = 2; l <= D; ++l) gcap += p.level_cap[l];
-    const unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>(gcap, 16384));
+    // one wave per box: 8192 single-wave workgroups fill every wave slot of the chip
+    const unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>(gcap, 8192));
     if (p.y_all_levels) {
         GatherLevels gl{};
         gl.lo = 2;
