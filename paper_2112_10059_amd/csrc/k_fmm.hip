@@ -270,7 +270,7 @@ template <class T, int NK>
 __device__ __forceinline__ T w_list_far(const FmmArgs<T> &a, int32_t b, const V4<T> &x, bool act, int lane)
 {
     T far = 0;
-    const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
+    const uint32_t w0 = a.L.w_rng[b].x, w1 = a.L.w_rng[b].y;
     const int nl = a.n_lam;
     for (uint32_t e = w0; e < w1; ++e) {
         const int32_t A = a.L.w[e];
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
         if (lw[qq]) {
             // W list (rare on grids): the source boxes' lattice densities, one thread per target
             const V4<float> xx = point_xyz(a, kk);
-            for (uint32_t e = a.L.w_off[b]; e < a.L.w_off[b + 1]; ++e) {
+            for (uint32_t e = a.L.w_rng[b].x; e < a.L.w_rng[b].y; ++e) {
                 const int32_t A = a.L.w[e];
                 const double hwa = a.lt.hw[a.bx.level[A]];
                 float ax, ay, az;
@@ -475,11 +475,11 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
         const int32_t b = lbox[t];
         const int32_t tn = a.bx.t_cnt[b];  // targets (the entry counts all the leaf's points)
         unsigned long long near_src = 0;
-        for (uint32_t e = a.L.u_off[b]; e < a.L.u_off[b + 1]; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+        for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
         atomicAdd(&a.work[0], near_src * tn);
         if (lnear[t]) atomicAdd(&a.work[10], (unsigned long long)tn);
         if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
-        const uint32_t nw = a.L.w_off[b + 1] - a.L.w_off[b];
+        const uint32_t nw = a.L.w_rng[b].y - a.L.w_rng[b].x;
         if (nw) atomicAdd(&a.work[2], (unsigned long long)nw * nl * tn);
     }
 }
@@ -558,15 +558,15 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
         for (int k = 0; k < NK; ++k)
             uv[k] = (gm > 0 && 64 * k + lane < nl) ? a.u[(size_t)b * nl + 64 * k + lane] : T(0);
         const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
-        const bool near = a.L.u_off[b + 1] > a.L.u_off[b];
-        const bool has_w = a.L.w_off[b + 1] > a.L.w_off[b];
+        const bool near = a.L.u_rng[b].y > a.L.u_rng[b].x;
+        const bool has_w = a.L.w_rng[b].y > a.L.w_rng[b].x;
         if (a.work && lane == 0) {
             unsigned long long near_src = 0;
-            for (uint32_t e = a.L.u_off[b]; e < a.L.u_off[b + 1]; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+            for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
             atomicAdd(&a.work[0], near_src * tn);
             if (near) atomicAdd(&a.work[10], (unsigned long long)tn);
             if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
-            if (has_w) atomicAdd(&a.work[2], (unsigned long long)(a.L.w_off[b + 1] - a.L.w_off[b]) * nl * tn);
+            if (has_w) atomicAdd(&a.work[2], (unsigned long long)(a.L.w_rng[b].y - a.L.w_rng[b].x) * nl * tn);
         }
         // the leaf's points in sorted order, the targets among them flagged
         for (int tb = 0; tb < np; tb += 64) {
@@ -629,8 +629,8 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
             __syncthreads();
         }
         const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
-        const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
-        const uint32_t w0 = a.L.w_off[b], w1 = a.L.w_off[b + 1];
+        const uint32_t u0 = a.L.u_rng[b].x, u1 = a.L.u_rng[b].y;
+        const uint32_t w0 = a.L.w_rng[b].x, w1 = a.L.w_rng[b].y;
         if (a.work && threadIdx.x == 0) {
             unsigned long long near_src = 0;
             for (uint32_t e = u0; e < u1; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
@@ -716,7 +716,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
     }
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
         const int32_t b = a.L.near_leaves[idx];
-        const uint32_t u0 = a.L.u_off[b], u1 = a.L.u_off[b + 1];
+        const uint32_t u0 = a.L.u_rng[b].x, u1 = a.L.u_rng[b].y;
         const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0;
         const bool tab_b = tab && a.bx.level[b] == a.near_level;
         // the leaf's points in sorted order, the targets among them flagged

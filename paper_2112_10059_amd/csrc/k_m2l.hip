@@ -543,7 +543,7 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
         unsigned long long n_m2l = 0, n_p2l = 0;
         if (with_x) {
             // X list: sources of coarser leaves straight onto the check points
-            const uint32_t x0 = a.L.x_off[b], x1 = a.L.x_off[b + 1];
+            const uint32_t x0 = a.L.x_rng[b].x, x1 = a.L.x_rng[b].y;
             if (x1 > x0) {
                 const double hw = a.lt.hw[level];
                 T cx, cy, cz;

@@ -164,6 +164,18 @@ __device__ __forceinline__ int32_t box_of_thread(const LevelInfo &li, const Call
 
 enum { kListU = 0, kListW = 1, kListX = 2 };
 
+// The first existing child of P after child `after` (any child if after < 0), or -1
+__device__ __forceinline__ int32_t first_child(const BoxArrays &bx, int32_t P, int32_t after)
+{
+    const int32_t *ch = bx.child + (size_t)P * 8;
+    int o = 0;
+    if (after >= 0)
+        while (o < 8 && ch[o] != after) ++o;
+    for (o = after >= 0 ? o + 1 : 0; o < 8; ++o)
+        if (ch[o] >= 0) return ch[o];
+    return -1;
+}
+
 template <class F>
 __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_level, F &&emit)
 {
@@ -185,7 +197,6 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_lev
                 else smask |= 1u << d;
             }
         }
-        int32_t stack[8 * kMaxDepth];
         for (uint32_t m = lmask | smask; m; m &= m - 1) {
             const int d = __ffs((int)m) - 1;
             const int32_t C = bx.coll[(size_t)b * 27 + d];
@@ -193,21 +204,36 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_lev
                 emit(kListU, C);
                 continue;
             }
-            int top = 0;
-            for (int o = 0; o < 8; ++o) {
-                const int32_t D = bx.child[(size_t)C * 8 + o];
-                if (D >= 0) stack[top++] = D;
-            }
-            while (top > 0) {
-                const int32_t D = stack[--top];
-                if (bx.s_cnt[D] == 0) continue;
-                if (!adjacent(bx, D, b)) emit(kListW, D);
-                else if (bx.flags[D] & kBoxLeaf) emit(kListU, D);
-                else
-                    for (int o = 0; o < 8; ++o) {
-                        const int32_t E = bx.child[(size_t)D * 8 + o];
-                        if (E >= 0 && top < 8 * kMaxDepth) stack[top++] = E;
+            // the split colleague's descendants depth first in child order, walked through
+            // the parent and child links (no stack): a box with sources that is not adjacent
+            // to b joins W, an adjacent leaf joins U, an adjacent split box is descended into
+            int32_t D = first_child(bx, C, -1);
+            while (D >= 0) {
+                bool down = false;
+                if (bx.s_cnt[D] > 0) {
+                    if (!adjacent(bx, D, b)) emit(kListW, D);
+                    else if (bx.flags[D] & kBoxLeaf) emit(kListU, D);
+                    else down = true;
+                }
+                const int32_t E = down ? first_child(bx, D, -1) : -1;
+                if (E >= 0) {
+                    D = E;
+                    continue;
+                }
+                // the next sibling, else that of the nearest ancestor below C that has one
+                while (true) {
+                    const int32_t P = bx.parent[D];
+                    const int32_t S = first_child(bx, P, D);
+                    if (S >= 0) {
+                        D = S;
+                        break;
                     }
+                    if (P == C) {
+                        D = -1;
+                        break;
+                    }
+                    D = P;
+                }
             }
         }
     }
@@ -229,34 +255,30 @@ __device__ void enumerate_lists(const BoxArrays &bx, int32_t b, int min_leaf_lev
 
 constexpr int kListBlock = 256;
 
-// Per-workgroup totals of three counts (every thread of the workgroup takes part)
-__device__ __forceinline__ void block_totals3(uint32_t a, uint32_t b, uint32_t c, uint32_t *__restrict__ out)
+// Space for n entries per lane from a shared counter: one atomic per wave, lanes in order.
+// Every lane of the wave takes part.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t n, int32_t *counter)
 {
-    __shared__ uint32_t part[3][kListBlock / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t v[3] = {a, b, c};
-    for (int k = 0; k < 3; ++k) {
-        const uint32_t s = lane_value(wave_inclusive(v[k], lane), 63);
-        if (lane == 0) part[k][w] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        uint32_t s = 0;
-        for (int q = 0; q < kListBlock / 64; ++q) s += part[threadIdx.x][q];
-        out[threadIdx.x] = s;
-    }
+    const int lane = threadIdx.x & 63;
+    const uint32_t incl = wave_inclusive(n, lane);
+    const uint32_t tot = lane_value(incl, 63);
+    uint32_t base = 0;
+    if (lane == 63 && tot) base = atomicAdd(reinterpret_cast<unsigned int *>(counter), tot);
+    return lane_value(base, 63) + incl - n;
 }
 
-// List lengths per box, and the leaf lists of the target-side kernels.  grid_levels: bit l
-// set when leaves of level l take their far field from a grid operator (or have none).
-__global__ __launch_bounds__(kListBlock) void list_count_kernel(BoxArrays bx, LevelInfo li,
+// The interaction lists of every box in one pass: a thread per box enumerates its lists to
+// count them, reserves each list's space (one atomic per wave and list), stores its ranges and
+// enumerates again to write the entries (the second pass reads what the first brought into
+// the caches).  Also the leaf lists of the target-side kernels.  grid_levels: bit l set when
+// leaves of level l take their far field from a grid operator (or have none).
+__global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, LevelInfo li,
                                                                 CallScalars *__restrict__ sc, int32_t nbox, Lists L,
-                                                                uint32_t grid_levels, uint32_t gen,
-                                                                uint32_t *__restrict__ block_tot)
+                                                                uint32_t grid_levels, uint32_t gen)
 {
     const int32_t gid0 = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = gid0 < nbox;
-    const int32_t gid = in ? gid0 : nbox - 1;  // whole waves reach the block totals
+    const int32_t gid = in ? gid0 : nbox - 1;  // whole waves reach the reservations
     const int32_t b = in ? box_of_thread(li, sc, gid) : -1;
     uint32_t nu = 0, nw = 0, nx = 0;
     const int mll = li.depth + 1 - sc->min_leafsrc_level;
@@ -266,12 +288,34 @@ __global__ __launch_bounds__(kListBlock) void list_count_kernel(BoxArrays bx, Le
             else if (kind == kListW) ++nw;
             else ++nx;
         });
+    const uint32_t ub = wave_reserve(nu, &sc->n_u);
+    const uint32_t wb = wave_reserve(nw, &sc->n_w);
+    const uint32_t xb = wave_reserve(nx, &sc->n_x);
     if (in) {
-        L.u_off[gid] = nu;
-        L.w_off[gid] = nw;
-        L.x_off[gid] = nx;
+        L.u_rng[gid] = make_uint2(ub, ub + nu);
+        L.w_rng[gid] = make_uint2(wb, wb + nw);
+        L.x_rng[gid] = make_uint2(xb, xb + nx);
     }
-    block_totals3(nu, nw, nx, block_tot + 3 * blockIdx.x);
+    if (b >= 0 && (nu | nw | nx)) {
+        uint32_t pu = ub, pw = wb, px = xb;
+        bool over = false;
+        enumerate_lists(bx, b, mll, [&](int kind, int32_t C) {
+            if (kind == kListU) {
+                if (pu < (uint32_t)L.u_cap) L.u[pu] = C;
+                else over = true;
+                ++pu;
+            } else if (kind == kListW) {
+                if (pw < (uint32_t)L.w_cap) L.w[pw] = C;
+                else over = true;
+                ++pw;
+            } else {
+                if (px < (uint32_t)L.x_cap) L.x[px] = C;
+                else over = true;
+                ++px;
+            }
+        });
+        if (over) atomicOr(&sc->err, 2);
+    }
     const bool tleaf = b >= 0 && (bx.flags[b] & kBoxLeaf) && bx.t_cnt[b] > 0;
     const int lev = b >= 0 ? bx.level[b] : 0;
     const bool grid_leaf = tleaf && ((grid_levels >> lev) & 1u);
@@ -367,81 +411,6 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
     }
 }
 
-// The lists' entries.  Each workgroup turns its boxes' counts into offsets: the sum of the
-// earlier workgroups' totals (a short loop over block_tot) plus a scan inside the workgroup;
-// the last workgroup also writes the end offsets and the list lengths.
-__global__ __launch_bounds__(kListBlock) void list_fill_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc,
-                                                               int32_t nbox, Lists L,
-                                                               const uint32_t *__restrict__ block_tot)
-{
-    __shared__ uint32_t part[3][kListBlock / 64];
-    __shared__ uint32_t base[3];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int32_t gid0 = blockIdx.x * blockDim.x + t;
-    const bool in = gid0 < nbox;
-    const int32_t gid = in ? gid0 : nbox - 1;
-    uint32_t cnt[3] = {0, 0, 0};
-    if (in) {
-        cnt[0] = L.u_off[gid];
-        cnt[1] = L.w_off[gid];
-        cnt[2] = L.x_off[gid];
-    }
-    if (t < 3) {
-        uint32_t acc = 0;
-        for (uint32_t j = 0; j < blockIdx.x; ++j) acc += block_tot[3 * j + t];
-        base[t] = acc;
-    }
-    uint32_t incl[3];
-    for (int k = 0; k < 3; ++k) {
-        incl[k] = wave_inclusive(cnt[k], lane);
-        if (lane == 63) part[k][w] = incl[k];
-    }
-    __syncthreads();
-    uint32_t off[3];
-    for (int k = 0; k < 3; ++k) {
-        uint32_t o = base[k];
-        for (int q = 0; q < w; ++q) o += part[k][q];
-        off[k] = o + incl[k] - cnt[k];
-    }
-    if (in) {
-        L.u_off[gid] = off[0];
-        L.w_off[gid] = off[1];
-        L.x_off[gid] = off[2];
-    }
-    if (blockIdx.x == gridDim.x - 1 && t == blockDim.x - 1) {
-        // the last thread of the last workgroup holds the totals (its box, if any, is the last)
-        const uint32_t tu = off[0] + cnt[0], tw = off[1] + cnt[1], tx = off[2] + cnt[2];
-        L.u_off[nbox] = tu;
-        L.w_off[nbox] = tw;
-        L.x_off[nbox] = tx;
-        sc->n_u = (int32_t)tu;
-        sc->n_w = (int32_t)tw;
-        sc->n_x = (int32_t)tx;
-    }
-    if (!in) return;
-    const int32_t b = box_of_thread(li, sc, gid);
-    if (b < 0) return;
-    uint32_t pu = off[0], pw = off[1], px = off[2];
-    bool over = false;
-    const int mll = li.depth + 1 - sc->min_leafsrc_level;
-    enumerate_lists(bx, b, mll, [&](int kind, int32_t C) {
-        if (kind == kListU) {
-            if (pu < (uint32_t)L.u_cap) L.u[pu] = C;
-            else over = true;
-            ++pu;
-        } else if (kind == kListW) {
-            if (pw < (uint32_t)L.w_cap) L.w[pw] = C;
-            else over = true;
-            ++pw;
-        } else {
-            if (px < (uint32_t)L.x_cap) L.x[px] = C;
-            else over = true;
-            ++px;
-        }
-    });
-    if (over) atomicOr(&sc->err, 2);
-}
-
 LevelInfo level_info(const Plan &p)
 {
     LevelInfo li{};
@@ -483,9 +452,7 @@ void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready)
                                                                                         p.call_gen);
     }
     PH_HIP(hipEventRecord(vt_ready, s));
-    uint32_t *block_tot = reinterpret_cast<uint32_t *>(p.d_scan_tmp);  // 3 per workgroup
-    list_count_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels, p.call_gen, block_tot);
-    list_fill_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, block_tot);
+    list_build_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels, p.call_gen);
 }
 
 }  // namespace ph

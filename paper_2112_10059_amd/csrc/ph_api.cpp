@@ -225,9 +225,9 @@ void alloc_workspace(Plan &p)
     b.src_rank = (int32_t *)dev_alloc(p, B * 4);
     b.src_box = (int32_t *)dev_alloc(p, B * 4);
     Lists &L = p.lists;
-    L.u_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
-    L.w_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
-    L.x_off = (uint32_t *)dev_alloc(p, (B + 1) * 4);
+    L.u_rng = (uint2 *)dev_alloc(p, B * sizeof(uint2));
+    L.w_rng = (uint2 *)dev_alloc(p, B * sizeof(uint2));
+    L.x_rng = (uint2 *)dev_alloc(p, B * sizeof(uint2));
     L.u_cap = std::max<int64_t>(1024, 64 * B);
     L.w_cap = std::max<int64_t>(1024, 32 * B);
     L.x_cap = std::max<int64_t>(1024, 32 * B);
@@ -303,8 +303,8 @@ void free_plan(Plan *p)
                     p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
                     p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
                     p->box.child, p->box.coll, p->box.start, p->box.end, p->box.src_rank, p->box.tpar_box, p->d_z,
-                    p->box.src_box, p->d_y, p->lists.u_off,
-                    p->lists.w_off, p->lists.x_off, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
+                    p->box.src_box, p->d_y, p->lists.u_rng,
+                    p->lists.w_rng, p->lists.x_rng, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
                     p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_tile_use, p->lists.m2l_box_use, p->d_phi, p->d_u,
                     p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
                     p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,

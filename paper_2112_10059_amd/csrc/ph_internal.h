@@ -87,9 +87,10 @@ struct BoxArrays {
     int32_t *tpar_box = nullptr;    // per-level slots: the split boxes with targets
 };
 
-// Interaction lists in CSR form over all boxes (offsets box_cap + 1)
+// Interaction lists over all boxes: each box's entries are contiguous, in enumeration order,
+// at the range (begin, end) stored for the box (ranges of different boxes in any order)
 struct Lists {
-    uint32_t *u_off = nullptr, *w_off = nullptr, *x_off = nullptr;  // scanned counts
+    uint2 *u_rng = nullptr, *w_rng = nullptr, *x_rng = nullptr;
     int32_t *u = nullptr, *w = nullptr, *x = nullptr;
     int64_t u_cap = 0, w_cap = 0, x_cap = 0;
     // leaves with targets (any order within a list): far field by a grid operator (a, in
