@@ -709,9 +709,9 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
     // uniform grids (FP32): between two leaves of the table's level the kernel is read from the
     // table at the integer cell offset instead of being evaluated
     const bool tab = sizeof(T) == 4 && a.near_tab != nullptr;
-    const int TR = a.near_R, TS = 2 * TR + 1, TS3 = TS * TS * TS;
+    const int TR = a.near_R, sx = a.near_sx, sy = a.near_sy, sz = a.near_sz, TN = a.near_n;
     if (tab) {
-        for (int i = threadIdx.x; i < TS3; i += blockDim.x) ntab[i] = a.near_tab[i];
+        for (int i = threadIdx.x; i < TN; i += blockDim.x) ntab[i] = a.near_tab[i];
         __syncthreads();
     }
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
@@ -732,7 +732,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
             int tl = 0;
             if (tab_b) {
                 const int32_t c = a.pcell[k];
-                tl = (((c & 1023) + TR) * TS + (((c >> 10) & 1023) + TR)) * TS + ((c >> 20) + TR);
+                tl = ((c & 1023) + TR) * sx + (((c >> 10) & 1023) + TR) * sy + ((c >> 20) + TR) * sz;
             }
             Acc<T> near;
             // the U list a chunk of 64 entries at a time: the entries' source ranges (and whether
@@ -777,18 +777,23 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
                     }
                     if (nb == 0) break;
                     // staged per source: its position and weight, or (table items) the linear
-                    // index of its cell in the table's strides and its weight
+                    // index of its cell in the table's strides and its weight, two sources to 16
+                    // bytes (lanes past the item's end stage a zero weight)
 #pragma unroll
-                    for (int q = 0; q < kNB; ++q)
-                        if (q < nb && lane < im[q]) {
-                            V4<T> y = a.s_dat[isf[q] + lane];
-                            if (itab[q]) {
+                    for (int q = 0; q < kNB; ++q) {
+                        if (q >= nb) break;
+                        if (itab[q]) {
+                            float2 y2 = make_float2(0.f, 0.f);
+                            if (lane < im[q]) {
                                 const int32_t c = a.s_cell[isf[q] + lane];
-                                const int sl = ((c & 1023) * TS + ((c >> 10) & 1023)) * TS + (c >> 20);
-                                y.x = (T)__int_as_float(sl);
+                                y2.x = __int_as_float((c & 1023) * sx + ((c >> 10) & 1023) * sy + (c >> 20) * sz);
+                                y2.y = (float)a.s_dat[isf[q] + lane].w;
                             }
-                            ysh[w][q][lane] = y;
+                            reinterpret_cast<float2 *>(&ysh[w][q][0])[lane] = y2;
+                        } else if (lane < im[q]) {
+                            ysh[w][q][lane] = a.s_dat[isf[q] + lane];
                         }
+                    }
                     wave_lds_sync();
 #pragma unroll
                     for (int q = 0; q < kNB; ++q) {
@@ -796,13 +801,16 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
                         // the item's terms in a plain sum (at most 64), added to the compensated total
                         T blk = T(0);
                         if (sizeof(T) == 4 && itab[q]) {
-#pragma unroll 8
-                            for (int j = 0; j < im[q]; ++j) {
-                                const V4<T> y = ysh[w][q][j];  // a broadcast read
-                                // adjacent leaves keep the offset inside the table; the clamp
+                            const float4 *y4 = reinterpret_cast<const float4 *>(&ysh[w][q][0]);
+#pragma unroll 4
+                            for (int j = 0; j < (im[q] + 1) / 2; ++j) {
+                                const float4 y = y4[j];  // two sources, a broadcast read
+                                // adjacent leaves keep the offsets inside the table; the clamp
                                 // keeps every read inside it regardless
-                                const int id = min(max(tl - __float_as_int((float)y.x), 0), TS3 - 1);
-                                blk += (T)ntab[id] * y.w;
+                                const int i0 = min(max(tl - __float_as_int(y.x), 0), TN - 1);
+                                const int i1 = min(max(tl - __float_as_int(y.z), 0), TN - 1);
+                                blk += (T)ntab[i0] * (T)y.y;
+                                blk += (T)ntab[i1] * (T)y.w;
                             }
                         } else {
 #pragma unroll 8
@@ -910,8 +918,7 @@ void fmm_near_t(Plan &p, hipStream_t s)
     // at most four workgroups (16 waves) per CU: the upward and downward passes run beside this
     // kernel on the other stream, and a full grid would hold every wave slot until it drains
     const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 1024);
-    const int S = 2 * p.ops.near_R + 1;
-    const size_t lds = (std::is_same<T, float>::value && p.ops.near_tab) ? (size_t)S * S * S * sizeof(float) : 0;
+    const size_t lds = (std::is_same<T, float>::value && p.ops.near_tab) ? (size_t)p.ops.near_n * sizeof(float) : 0;
     if (p.near_guard) near_kernel<T, true><<<g, 64 * kNearWaves, lds, s>>>(a, p.d_t_near);
     else near_kernel<T, false><<<g, 64 * kNearWaves, lds, s>>>(a, p.d_t_near);
 }

@@ -45,7 +45,7 @@ struct FmmArgs {
     // near-field kernel table (uniform grids, FP32): entries at the cell offsets of adjacent
     // leaves of level near_level, offsets within [-near_R, near_R] per axis; null if absent
     const float *near_tab;
-    int near_R, near_level;
+    int near_R, near_level, near_sx, near_sy, near_sz, near_n;
     int grid_m[kMaxDepth + 2];
     int64_t grid_off[kMaxDepth + 2];
     int n_lam, n_sig;
@@ -133,6 +133,10 @@ inline FmmArgs<T> make_args(Plan &p)
     a.near_tab = (const float *)p.ops.near_tab;
     a.near_R = p.ops.near_R;
     a.near_level = p.ops.near_level;
+    a.near_sx = p.ops.near_sx;
+    a.near_sy = p.ops.near_sy;
+    a.near_sz = p.ops.near_sz;
+    a.near_n = p.ops.near_n;
     for (int l = 0; l < kMaxDepth + 2; ++l) {
         a.grid_m[l] = p.grid_mode ? p.grid_m[l] : 0;
         a.grid_off[l] = p.grid_off[l];

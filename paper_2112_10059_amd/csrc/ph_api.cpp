@@ -592,12 +592,49 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
             const int D = p.max_depth;
             const int m = (p.grid_n % (1 << D) == 0) ? (p.grid_n >> D) : 0;
             const int R = 2 * m - 1;
-            if (m >= 1 && (2 * R + 1) * (2 * R + 1) * (2 * R + 1) <= kNearTabMax) {
-                std::vector<double> tab;
-                build_near_table(p.gas, p.h, R, tab);
-                upload(p, &p.ops.near_tab, convert<float>(tab));
-                p.ops.near_R = R;
-                p.ops.near_level = D;
+            if (m >= 1 && R <= kNearTabMaxR) {
+                // strides: y 1, x 16, z chosen so that a leaf's targets (the lanes of a wave, in
+                // the sorted order of the first finest-level box, which holds the first m^3
+                // points) read the table without LDS bank conflicts (32 banks per half wave, 64
+                // per wave), or with as few as any z stride in range allows
+                const int S = 2 * R + 1, mc = (int)std::min<int64_t>(m * m * m, p.n);
+                std::vector<int32_t> c0(mc);
+                PH_HIP(hipMemcpy(c0.data(), p.d_cell, (size_t)mc * 4, hipMemcpyDeviceToHost));
+                int lo[3] = {1 << 30, 1 << 30, 1 << 30};
+                for (int32_t c : c0)
+                    for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], (c >> (10 * d)) & 1023);
+                const int sx = 16, sy = 1;
+                int sz = S * sx, worst_best = 1 << 30;
+                for (int cand = S * sx; cand < S * sx + 64; ++cand) {
+                    int worst = 0;
+                    for (int nb : {32, 64}) {
+                        const int group = nb == 32 ? 32 : 64;
+                        for (int g0 = 0; g0 < mc; g0 += group) {
+                            std::vector<std::vector<int>> banks(nb);
+                            for (int l = g0; l < std::min(mc, g0 + group); ++l) {
+                                const int x = ((c0[l] & 1023) - lo[0]), y = (((c0[l] >> 10) & 1023) - lo[1]),
+                                          z = (((c0[l] >> 20) & 1023) - lo[2]);
+                                const int idx = x * sx + y * sy + z * cand;
+                                auto &bk = banks[idx % nb];
+                                if (std::find(bk.begin(), bk.end(), idx) == bk.end()) bk.push_back(idx);
+                            }
+                            for (auto &bk : banks) worst = std::max(worst, (int)bk.size());
+                        }
+                    }
+                    if (worst < worst_best) worst_best = worst, sz = cand;
+                }
+                const int n_tab = S * sz;
+                if (n_tab <= kNearTabMax) {
+                    std::vector<double> tab;
+                    build_near_table(p.gas, p.h, R, sx, sy, sz, n_tab, tab);
+                    upload(p, &p.ops.near_tab, convert<float>(tab));
+                    p.ops.near_R = R;
+                    p.ops.near_level = D;
+                    p.ops.near_sx = sx;
+                    p.ops.near_sy = sy;
+                    p.ops.near_sz = sz;
+                    p.ops.near_n = n_tab;
+                }
             }
         }
         if (p.precision == PH_FP64) {

@@ -129,13 +129,15 @@ struct OperatorsDev {
     //   grid_gt [r][lambda] = same matrix transposed                      (P2M reads rows)
     void *grid_g = nullptr, *grid_gt = nullptr;
     // uniform grids, FP32: the kernel at the cell offsets of two adjacent finest-level leaves,
-    // near_tab[((i + R) S + (j + R)) S + (k + R)] = K(h |(i, j, k)|), S = 2 R + 1, 0 at the origin
+    // near_tab[(i + R) sx + (j + R) sy + (k + R) sz] = K(h |(i, j, k)|), 0 at the origin
     void *near_tab = nullptr;
     int near_R = 0;        // offsets per axis within [-R, R] (R = 2 m - 1 for leaves of m^3 cells)
     int near_level = -1;   // level of the leaves the table serves
+    int near_sx = 0, near_sy = 0, near_sz = 0, near_n = 0;  // strides and entries
 };
 
-constexpr int kNearTabMax = 3375;  // table entries kept in LDS (R <= 7: leaves of at most 4^3 cells)
+constexpr int kNearTabMaxR = 7;     // table for leaves of at most 4^3 cells
+constexpr int kNearTabMax = 4800;   // entries kept in LDS
 
 constexpr int kGridMaxCells = 16;  // lattice operators for boxes of at most 16^3 cells
 
@@ -268,7 +270,7 @@ struct HostOperators {
 void build_operators(const Gas &gas, int q, double root_size, int max_depth, double cut,
                      HostOperators &out);
 double cube_self_integral(const Gas &gas, double h);
-void build_near_table(const Gas &gas, double h, int R, std::vector<double> &tab);
+void build_near_table(const Gas &gas, double h, int R, int sx, int sy, int sz, int n, std::vector<double> &tab);
 void build_grid_operator(const Gas &gas, const HostOperators &H, int level, double hw, double h, int m,
                          std::vector<double> &G);
 int m2l_index(int dx, int dy, int dz);  // -1 unless the offset is well separated

@@ -251,18 +251,18 @@ void build_operators(const Gas &gas, int q, double root_size, int max_depth, dou
 // Near-field kernel values of a uniform grid of spacing h (Sec. 2.4, eq. (16)): two cells
 // whose indices differ by (i, j, k) are h |(i, j, k)| apart, so the sum over a leaf's
 // neighbours needs the kernel only at the (2R + 1)^3 integer offsets with |i|, |j|, |k| <= R.
-// tab[((i + R) S + (j + R)) S + (k + R)] = K(h |(i, j, k)|), S = 2 R + 1; the origin holds 0
-// (a coincident pair is the own-cell term, handled apart).
-void build_near_table(const Gas &gas, double h, int R, std::vector<double> &tab)
+// tab[(i + R) sx + (j + R) sy + (k + R) sz] = K(h |(i, j, k)|) in a table of n entries (the
+// strides leave unused entries, 0); the origin holds 0 (a coincident pair is the own-cell
+// term, handled apart).
+void build_near_table(const Gas &gas, double h, int R, int sx, int sy, int sz, int n, std::vector<double> &tab)
 {
-    const int S = 2 * R + 1;
-    tab.assign((size_t)S * S * S, 0.0);
+    tab.assign((size_t)n, 0.0);
     for (int i = -R; i <= R; ++i)
         for (int j = -R; j <= R; ++j)
             for (int k = -R; k <= R; ++k) {
                 if (i == 0 && j == 0 && k == 0) continue;
                 const double r = h * std::sqrt((double)(i * i + j * j + k * k));
-                tab[((size_t)(i + R) * S + (j + R)) * S + (k + R)] = kernel_fp64(r, gas);
+                tab[(size_t)(i + R) * sx + (size_t)(j + R) * sy + (size_t)(k + R) * sz] = kernel_fp64(r, gas);
             }
 }
 
