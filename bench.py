@@ -67,26 +67,40 @@ def parse():
 
 
 def time_steps(plan, I, E, steps, warmup, torch, host=None):
-    """ms per call over `steps` calls (no per-phase events), then the per-phase times over as
-    many calls again with the phase events on.  host (a dict, optional) receives the host time
-    per call spent enqueueing the timed calls."""
+    """ms per call over `steps` calls (no per-phase events) replayed as one HIP graph per call
+    (the same calls launched eagerly are timed first, for the host side's share), then the
+    per-phase times over as many eager calls again with the phase events on.  host (a dict,
+    optional) receives the host time per call spent enqueueing the timed calls, and the eager
+    figures."""
     out = torch.empty(plan.n, dtype=plan.dtype, device="cuda")
+
+    def timed_loop():
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        h0 = time.perf_counter()
+        for _ in range(steps):
+            plan.evaluate(I, E, out=out)
+        h1 = time.perf_counter()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps, (h1 - h0) * 1e3 / steps
+
+    plan.phase_times(record=0)
     for _ in range(warmup):
         plan.evaluate(I, E, out=out)
     torch.cuda.synchronize()
-    plan.phase_times(record=0)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    h0 = time.perf_counter()
-    for _ in range(steps):
+    ms_eager, enq_eager = timed_loop()
+    plan.set_graph(True)
+    for _ in range(max(warmup, 1)):  # the first call captures the graph
         plan.evaluate(I, E, out=out)
-    h1 = time.perf_counter()
-    t1.record()
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
+    ms, enq = timed_loop()
+    plan.set_graph(False)
     if host is not None:
-        host["enqueue_ms_per_call"] = (h1 - h0) * 1e3 / steps
+        host["enqueue_ms_per_call"] = enq
+        host["eager_ms_per_step"] = ms_eager
+        host["eager_enqueue_ms_per_call"] = enq_eager
     plan.phase_times(record=1)  # discard, start recording
     for _ in range(steps):
         plan.evaluate(I, E, out=out)
@@ -145,7 +159,8 @@ def main():
     S, ms, phases = time_steps(plan, I, E, args.steps, args.warmup, torch, host=host)
     n_tgt = st["n_tgt"]
     value = n_tgt / (ms * 1e-3)
-    log(f"learned fp32: {ms:.4f} ms/step, {value:.4e} targets/s; host enqueue {host['enqueue_ms_per_call']:.4f} "
+    log(f"learned fp32: {ms:.4f} ms/step (graph replay; eager launches {host['eager_ms_per_step']:.4f} ms/step, "
+        f"host {host['eager_enqueue_ms_per_call']:.4f} ms/call), {value:.4e} targets/s; host enqueue {host['enqueue_ms_per_call']:.4f} "
         f"ms/call; phases {phases}")
     roof = roofline(phases, st)
     perm = plan.debug_fetch("perm")
@@ -229,6 +244,9 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms,
         "host_enqueue_ms_per_call": host["enqueue_ms_per_call"],
+        "launch": "one HIP graph per call (captured once for the buffers, replayed)",
+        "eager_ms_per_step": host["eager_ms_per_step"],
+        "eager_host_enqueue_ms_per_call": host["eager_enqueue_ms_per_call"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -180,6 +180,18 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
                       void *stream, ph_stats *stats);
 
 /*
+ * Graph replay of ph_evaluate.  enable = 1: every later ph_evaluate call without
+ * stats (and without phase recording) runs as one HIP graph launched on its
+ * `stream`.  The graph is captured, on a stream the plan owns, at the first such
+ * call for a set of buffers (I, absE, S_out) and replayed while they stay the
+ * same; their contents may change between calls.  The call's number, which the
+ * interaction lists tag boxes with, lives on the device and advances in every
+ * replay.  Calls with stats or phase recording launch eagerly.  enable = 0 drops
+ * the graph.  Waits for the device.
+ */
+ph_status ph_plan_set_graph(ph_plan *plan, int enable);
+
+/*
  * Per-phase device time.  ms_sum (host, PH_NPHASES doubles, nullable) receives the
  * summed hipEvent time of every call recorded since the previous query, per phase:
  *   0 maxima of I and |E|      1 learned selector (rows, features, network, drop mask)

@@ -68,7 +68,8 @@ WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pa
 
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
-            "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_fields"]
+            "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_fields",
+            "ph_plan_set_graph"]
 
 _lib = None
 
@@ -107,6 +108,8 @@ def load(path: Optional[str] = None):
     lib.ph_plan_destroy.argtypes = [vp]
     lib.ph_evaluate.restype = ctypes.c_int
     lib.ph_evaluate.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(PhStats)]
+    lib.ph_plan_set_graph.restype = ctypes.c_int
+    lib.ph_plan_set_graph.argtypes = [vp, ctypes.c_int]
     lib.ph_plan_check.restype = ctypes.c_int
     lib.ph_plan_check.argtypes = [vp, vp]
     lib.ph_plan_size.restype = ctypes.c_int64
@@ -222,6 +225,10 @@ class Plan:
                          "fell_back": st.fell_back, "n_src_dropped": st.n_src_dropped,
                          "t_ms": list(st.t_ms), "work": dict(zip(WORK, list(st.work)))}
         return out
+
+    def set_graph(self, enable: bool = True):
+        """Later evaluate() calls without stats run as one replayed HIP graph (per set of buffers)."""
+        _check(_lib.ph_plan_set_graph(self._h, 1 if enable else 0))
 
     PHASES = ("reduce", "selector", "select", "tree", "lists", "upward", "downward", "leaf", "near")
 

@@ -840,7 +840,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
 }
 
 template <class T>
-void fmm_upward_t(Plan &p, hipStream_t s)
+void fmm_p2m_t(Plan &p, hipStream_t s)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int D = p.max_depth;
@@ -850,6 +850,13 @@ void fmm_upward_t(Plan &p, hipStream_t s)
     const int64_t u_zero = D >= 3 ? p.level_base[3] * (int64_t)p.n_lam : 0;
     const int64_t u_end = D >= 3 ? p.box_cap * (int64_t)p.n_lam : 0;
     p2m_kernel<T><<<(unsigned)std::min<int64_t>(cap, 4096), kUpThreads, 0, s>>>(a, D, u_zero, u_end);
+}
+
+template <class T>
+void fmm_m2m_t(Plan &p, hipStream_t s)
+{
+    FmmArgs<T> a = make_args<T>(p);
+    const int D = p.max_depth;
     for (int l = D - 1; l >= 2; --l) {
         // a direct product per parent for small lattices; the level GEMM (all eight octant
         // translations of every child, on the matrix cores) for large ones
@@ -925,10 +932,22 @@ void fmm_near_t(Plan &p, hipStream_t s)
 
 }  // namespace
 
+void fmm_p2m(Plan &p, hipStream_t s)
+{
+    if (p.precision == PH_FP64) fmm_p2m_t<double>(p, s);
+    else fmm_p2m_t<float>(p, s);
+}
+
+void fmm_m2m(Plan &p, hipStream_t s)
+{
+    if (p.precision == PH_FP64) fmm_m2m_t<double>(p, s);
+    else fmm_m2m_t<float>(p, s);
+}
+
 void fmm_upward(Plan &p, hipStream_t s)
 {
-    if (p.precision == PH_FP64) fmm_upward_t<double>(p, s);
-    else fmm_upward_t<float>(p, s);
+    fmm_p2m(p, s);
+    fmm_m2m(p, s);
 }
 
 void fmm_leaf(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)

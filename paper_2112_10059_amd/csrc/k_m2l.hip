@@ -690,25 +690,27 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
 }
 
 template <class T>
-void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready)
+void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready, hipEvent_t deep_m2l)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int nl = p.n_lam;
     const int M = kNumM2L * nl;
     const int D = p.max_depth;
-    if (p.y_all_levels && D >= 2) {
-        // every level's M2L products in one launch (they depend on the upward pass and on the
-        // offset masks only)
+    // the levels' M2L products in one launch (they depend on the upward pass and on the offset
+    // masks only); the deepest level's were launched on another stream when deep_m2l is given
+    const int top = deep_m2l ? D - 1 : D;
+    if (p.y_all_levels && top >= 2) {
         PH_HIP(hipStreamWaitEvent(s, vt_ready, 0));
         GemmSegs sg{};
         int64_t tiles = 0;
-        for (int l = 2; l <= D; ++l) {
+        for (int l = 2; l <= top; ++l) {
             sg.s[sg.n++] = GemmSeg{l,           (int32_t)p.level_base[l], 0, (int32_t)p.level_cap[l],
                                    (int64_t)l * M * p.k_pad, p.y_lvl_col[l], p.m2l_tile_base[l]};
             tiles += (p.level_cap[l] + kTile - 1) / kTile;
         }
         m2l_product<T>(p, sg, tiles, s);
     }
+    if (deep_m2l) PH_HIP(hipStreamWaitEvent(s, deep_m2l, 0));
     PH_HIP(hipStreamWaitEvent(s, lists_ready, 0));  // the gathers read the X and V/X target lists
     // level-local parts (V and X lists) of every level: no dependence between levels
     int64_t gcap = 0;
@@ -799,10 +801,24 @@ void m2m_level_t(Plan &p, int l, hipStream_t s)
 
 }  // namespace
 
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready)
+bool fmm_m2l_deepest(Plan &p, hipStream_t s)
 {
-    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, vt_ready, lists_ready);
-    else fmm_downward_t<float>(p, s, vt_ready, lists_ready);
+    const int D = p.max_depth;
+    if (!p.y_all_levels || D < 2) return false;
+    const int M = kNumM2L * p.n_lam;
+    GemmSegs sg{};
+    sg.s[sg.n++] = GemmSeg{D,           (int32_t)p.level_base[D], 0, (int32_t)p.level_cap[D],
+                           (int64_t)D * M * p.k_pad, p.y_lvl_col[D], p.m2l_tile_base[D]};
+    const int64_t tiles = (p.level_cap[D] + kTile - 1) / kTile;
+    if (p.precision == PH_FP64) m2l_product<double>(p, sg, tiles, s);
+    else m2l_product<float>(p, sg, tiles, s);
+    return true;
+}
+
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready, hipEvent_t deep_m2l)
+{
+    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, vt_ready, lists_ready, deep_m2l);
+    else fmm_downward_t<float>(p, s, vt_ready, lists_ready, deep_m2l);
 }
 
 void fmm_m2m_level(Plan &p, int l, hipStream_t s)

@@ -699,7 +699,7 @@ extern "C" ph_status ph_selector_features(ph_plan *plan, const void *I, const fl
     try {
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         PH_HIP(hipSetDevice(p.device));
-        launch_reset_scalars(p.d_sc, s);
+        launch_reset_scalars(p.d_sc, nullptr, s);
         selector_reduce(p, I, absE, s);
         selector_features(p, I, absE, s);
         int32_t nrow = 0;

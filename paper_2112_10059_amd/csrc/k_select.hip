@@ -14,10 +14,18 @@ namespace ph {
 
 namespace {
 
-__global__ void reset_scalars_kernel(CallScalars *sc)
+__global__ void reset_scalars_kernel(CallScalars *sc, int32_t *gen)
 {
     int32_t *w = reinterpret_cast<int32_t *>(sc);
     for (int i = threadIdx.x; i < (int)(sizeof(CallScalars) / 4); i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && gen) {
+        // the call's number, kept on the device so that a replayed launch sequence advances it
+        int32_t g = *gen + 1;
+        if (g <= 0) g = 1;
+        *gen = g;
+        sc->gen = g;
+    }
 }
 
 // Maxima of I and |E| (with the position of the largest |E|): each block reduces its
@@ -297,7 +305,10 @@ void launch_pack_xyzf(const double *xyz, int64_t n, float4 *out, hipStream_t s)
     if (n > 0) pack_xyzf_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xyz, n, out);
 }
 
-void launch_reset_scalars(CallScalars *sc, hipStream_t s) { reset_scalars_kernel<<<1, 256, 0, s>>>(sc); }
+void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s)
+{
+    reset_scalars_kernel<<<1, 256, 0, s>>>(sc, gen);
+}
 
 void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
                              hipStream_t s)

@@ -274,8 +274,9 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t n, int32_t *counter)
 // leaves of level l take their far field from a grid operator (or have none).
 __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, LevelInfo li,
                                                                 CallScalars *__restrict__ sc, int32_t nbox, Lists L,
-                                                                uint32_t grid_levels, uint32_t gen)
+                                                                uint32_t grid_levels)
 {
+    const int gen = sc->gen;
     const int32_t gid0 = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = gid0 < nbox;
     const int32_t gid = in ? gid0 : nbox - 1;  // whole waves reach the reservations
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, Le
     wave_append(tleaf && !grid_leaf, L.far_b, &sc->n_far_b, b);
     wave_append(tleaf && nu > 0, L.near_leaves, &sc->n_near, b);
     // boxes of levels >= 3 with an X list join their level's V/X target segment
-    const bool xbox = nx > 0 && lev >= 3 && atomicExch(&L.vt_tag[b], (int)gen) != (int)gen;
+    const bool xbox = nx > 0 && lev >= 3 && atomicExch(&L.vt_tag[b], gen) != gen;
     pending = __ballot(xbox);
     while (pending) {
         const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
@@ -351,8 +352,9 @@ __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, Le
 // offset slots used at S's slot, and ORs it into the mask of the 64-slot tile of the level's
 // source list that holds S.
 __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li, CallScalars *__restrict__ sc,
-                                                      Lists L, uint32_t gen)
+                                                      Lists L)
 {
+    const int gen = sc->gen;
     __shared__ uint32_t use[4][kUseWords];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int32_t idx = blockIdx.x * 4 + wv;; idx += gridDim.x * 4) {
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
                     if (!near) {
                         const int slot = m2l_slot(dx, dy, dz);
                         atomicOr(&use[wv][slot >> 5], 1u << (slot & 31));
-                        fresh = level >= 3 && atomicExch(&L.vt_tag[B], (int)gen) != (int)gen;
+                        fresh = level >= 3 && atomicExch(&L.vt_tag[B], gen) != gen;
                     }
                 }
             }
@@ -448,11 +450,10 @@ void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready)
     if (p.method == PH_METHOD_FMM && p.max_depth >= 2) {
         int64_t cap = 0;
         for (int l = 2; l <= p.max_depth; ++l) cap += p.level_cap[l];
-        vtarget_kernel<<<(unsigned)std::min<int64_t>((cap + 3) / 4, 1024), 256, 0, s>>>(p.box, li, p.d_sc, p.lists,
-                                                                                        p.call_gen);
+        vtarget_kernel<<<(unsigned)std::min<int64_t>((cap + 3) / 4, 1024), 256, 0, s>>>(p.box, li, p.d_sc, p.lists);
     }
     PH_HIP(hipEventRecord(vt_ready, s));
-    list_build_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels, p.call_gen);
+    list_build_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels);
 }
 
 }  // namespace ph

@@ -199,6 +199,8 @@ void alloc_workspace(Plan &p)
     const int64_t n = p.n;
     const size_t rs = p.precision == PH_FP64 ? sizeof(double) : sizeof(float);
     p.d_sc = (CallScalars *)dev_alloc(p, sizeof(CallScalars));
+    p.d_gen = (int32_t *)dev_alloc(p, sizeof(int32_t));
+    PH_HIP(hipMemset(p.d_gen, 0, sizeof(int32_t)));  // the tags start at 0, the first call is 1
     p.d_flag = (uint64_t *)dev_alloc(p, (size_t)n * sizeof(uint64_t));
     p.d_sel = (uint8_t *)dev_alloc(p, (size_t)n);
     PH_HIP(hipMemset(p.d_sel, 0, (size_t)n));  // nothing selected before the first call
@@ -311,7 +313,7 @@ void free_plan(Plan *p)
                     p->d_row_feat,
                     p->d_cell,
                     p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near,
-                    p->ops.near_tab};
+                    p->ops.near_tab, p->d_gen};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
         for (auto &set : p->ring)
@@ -323,6 +325,12 @@ void free_plan(Plan *p)
     if (p->ev_vt) (void)hipEventDestroy(p->ev_vt);
     if (p->ev_rest) (void)hipEventDestroy(p->ev_rest);
     if (p->side) (void)hipStreamDestroy(p->side);
+    if (p->side2) (void)hipStreamDestroy(p->side2);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->ev_p2m) (void)hipEventDestroy(p->ev_p2m);
+    if (p->ev_m2l) (void)hipEventDestroy(p->ev_m2l);
     delete p;
 }
 
@@ -677,6 +685,10 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     p.events_ready = true;
     // second stream (default priority) and its ordering events
     PH_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+    PH_HIP(hipStreamCreateWithFlags(&p.side2, hipStreamNonBlocking));
+    PH_HIP(hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_p2m, hipEventDisableTiming));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_m2l, hipEventDisableTiming));
     PH_HIP(hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming));
     PH_HIP(hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming));
     PH_HIP(hipEventCreateWithFlags(&p.ev_lists, hipEventDisableTiming));
@@ -782,6 +794,85 @@ static void harvest_slot(Plan &p, int slot)
     p.ring_used[slot] = false;
 }
 
+namespace {
+
+// One evaluation's launches on s (with the plan's second and third streams joined back into s
+// before the end): the same sequence for every call of a plan, so that it can be captured once
+// and replayed.  timed: phase events into ring slot `slot`.
+void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s, bool timed, int slot)
+{
+    auto mark = [&](int k, hipStream_t on) {
+        if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], on));
+    };
+    const bool learned = p.selector == PH_SEL_LEARNED;
+    p.cur_I = I;  // the target kernels read the own-cell term's intensity from it
+    mark(0, s);
+    launch_reset_scalars(p.d_sc, p.d_gen, s);
+    if (learned) selector_reduce(p, I, absE, s);  // the maxima come with the per-leaf statistics
+    else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_scan_tmp, s);
+    mark(1, s);
+    if (learned) selector_decide(p, I, absE, s);
+    mark(2, s);
+    launch_select(p, I, absE, S_out, s, learned ? p.d_drop : nullptr);
+    mark(3, s);
+    if (p.method == PH_METHOD_DIRECT) {
+        for (int k = 4; k <= 7; ++k) mark(k, s);
+        mark(8, s);
+        mark(9, s);
+        run_direct(p, S_out, s);
+        mark(10, s);
+        return;
+    }
+    build_tree(p, s);
+    mark(4, s);
+    // The lists and the near field run on the second stream: the upward pass and the M2L
+    // products need only the tree; the L2L / gather chain waits for the lists (X lists), and
+    // the far-field kernels, which combine both fields into the output, for the near field.
+    PH_HIP(hipEventRecord(p.ev_fork, s));
+    PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+    mark(8, p.side);
+    build_lists(p, p.side, p.ev_vt);
+    mark(9, p.side);
+    PH_HIP(hipEventRecord(p.ev_lists, p.side));
+    fmm_near(p, p.side);
+    mark(10, p.side);
+    PH_HIP(hipEventRecord(p.ev_join, p.side));
+    // the leaf densities, then the deepest level's M2L products on a third stream while the
+    // M2M chain runs here
+    fmm_p2m(p, s);
+    const bool deep = p.y_all_levels && p.max_depth >= 2;
+    if (deep) {
+        PH_HIP(hipEventRecord(p.ev_p2m, s));
+        PH_HIP(hipStreamWaitEvent(p.side2, p.ev_p2m, 0));
+        PH_HIP(hipStreamWaitEvent(p.side2, p.ev_vt, 0));
+        fmm_m2l_deepest(p, p.side2);
+        PH_HIP(hipEventRecord(p.ev_m2l, p.side2));
+    }
+    fmm_m2m(p, s);
+    mark(5, s);
+    fmm_downward(p, s, p.ev_vt, p.ev_lists, deep ? p.ev_m2l : nullptr);
+    mark(6, s);
+    // far field: the matrix-core kernel here, the other leaf kernels on the second stream
+    PH_HIP(hipEventRecord(p.ev_down, s));
+    PH_HIP(hipStreamWaitEvent(p.side, p.ev_down, 0));
+    PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));
+    fmm_leaf(p, S_out, s, p.side);
+    PH_HIP(hipEventRecord(p.ev_rest, p.side));
+    PH_HIP(hipStreamWaitEvent(s, p.ev_rest, 0));
+    mark(7, s);
+}
+
+void drop_graph(Plan &p)
+{
+    if (p.gexec) (void)hipGraphExecDestroy(p.gexec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    p.gexec = nullptr;
+    p.graph = nullptr;
+    p.g_I = p.g_E = p.g_S = nullptr;
+}
+
+}  // namespace
+
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
                       ph_stats *stats)
 {
@@ -801,55 +892,29 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             harvest_slot(p, slot);  // a slot from kRing calls ago: long finished
             p.ring_pos = (p.ring_pos + 1) % Plan::kRing;
         }
-        auto mark = [&](int k, hipStream_t on) {
-            if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], on));
-        };
         const bool learned = p.selector == PH_SEL_LEARNED;
-        if (++p.call_gen == 0) p.call_gen = 1;
-        p.cur_I = I;  // the target kernels read the own-cell term's intensity from it
-        mark(0, s);
-        launch_reset_scalars(p.d_sc, s);
-        if (learned) selector_reduce(p, I, absE, s);  // the maxima come with the per-leaf statistics
-        else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_scan_tmp, s);
-        mark(1, s);
-        if (learned) selector_decide(p, I, absE, s);
-        mark(2, s);
-        launch_select(p, I, absE, S_out, s, learned ? p.d_drop : nullptr);
-        mark(3, s);
-        if (p.method == PH_METHOD_DIRECT) {
-            for (int k = 4; k <= 7; ++k) mark(k, s);
-            mark(8, s);
-            mark(9, s);
-            run_direct(p, S_out, s);
-            mark(10, s);
+        if (p.graph_on && !timed) {
+            // the launch sequence captured once per set of buffers and replayed as one graph
+            if (!p.gexec || p.g_I != I || p.g_E != absE || p.g_S != S_out) {
+                drop_graph(p);
+                PH_HIP(hipStreamBeginCapture(p.cap, hipStreamCaptureModeRelaxed));
+                try {
+                    enqueue_call(p, I, absE, S_out, p.cap, false, 0);
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(p.cap, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                PH_HIP(hipStreamEndCapture(p.cap, &p.graph));
+                PH_HIP(hipGraphInstantiate(&p.gexec, p.graph, nullptr, nullptr, 0));
+                p.g_I = I;
+                p.g_E = absE;
+                p.g_S = S_out;
+            }
+            PH_HIP(hipGraphLaunch(p.gexec, s));
         } else {
-            build_tree(p, s);
-            mark(4, s);
-            // The lists and the near field run on the second stream: the upward pass and the M2L
-            // products need only the tree; the L2L / gather chain waits for the lists (X lists),
-            // and the far-field kernels, which combine both fields into the output, for the near
-            // field.
-            PH_HIP(hipEventRecord(p.ev_fork, s));
-            PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
-            mark(8, p.side);
-            build_lists(p, p.side, p.ev_vt);
-            mark(9, p.side);
-            PH_HIP(hipEventRecord(p.ev_lists, p.side));
-            fmm_near(p, p.side);
-            mark(10, p.side);
-            PH_HIP(hipEventRecord(p.ev_join, p.side));
-            fmm_upward(p, s);
-            mark(5, s);
-            fmm_downward(p, s, p.ev_vt, p.ev_lists);
-            mark(6, s);
-            // far field: the matrix-core kernel here, the other leaf kernels on the second stream
-            PH_HIP(hipEventRecord(p.ev_down, s));
-            PH_HIP(hipStreamWaitEvent(p.side, p.ev_down, 0));
-            PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));
-            fmm_leaf(p, S_out, s, p.side);
-            PH_HIP(hipEventRecord(p.ev_rest, p.side));
-            PH_HIP(hipStreamWaitEvent(s, p.ev_rest, 0));
-            mark(7, s);
+            enqueue_call(p, I, absE, S_out, s, timed, slot);
         }
         PH_HIP(hipGetLastError());
         if (timed) p.ring_used[slot] = true;
@@ -874,6 +939,22 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             for (int k = 0; k < 9; ++k) stats->t_ms[k] = phase_ms(p, slot, k);
         }
         if (stats && stats->fell_back) return PH_EFALLBACK;
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_plan_set_graph(ph_plan *plan, int enable)
+{
+    g_last_error.clear();
+    if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    try {
+        PH_HIP(hipSetDevice(p.device));
+        PH_HIP(hipDeviceSynchronize());  // no replay of the old graph is still running
+        drop_graph(p);
+        p.graph_on = enable != 0;
         return PH_OK;
     } catch (const Error &e) {
         return fail(e);

@@ -61,6 +61,7 @@ struct CallScalars {
     int32_t fallback;                   // learned selector fell back to the threshold rule
     int32_t n_srcleaf;                  // selector rows: plan leaves holding candidate sources
     int32_t n_src_base;                 // candidate sources of the learned decisions (kept + dropped)
+    int32_t gen;                        // number of the call (never 0): V/X target tags
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t emax_key;                  // |E| bits << 32 | ~caller index of the largest |E|
     // algorithmic work of the call (integer counters, order independent)
@@ -243,10 +244,19 @@ struct Plan {
     // caller's stream after the tree; the downward chain waits for the lists (ev_lists), the
     // far-field kernels (which write the output) for the near field (ev_join)
     hipStream_t side = nullptr;
+    hipStream_t side2 = nullptr;  // the deepest level's M2L products, beside the M2M chain
     hipEvent_t ev_fork = nullptr, ev_lists = nullptr, ev_join = nullptr;
     hipEvent_t ev_down = nullptr, ev_rest = nullptr;  // downward done (main); far kernels on side done
     hipEvent_t ev_vt = nullptr;  // V/X targets and M2L offset masks known (side)
-    uint32_t call_gen = 0;  // number of the current call (never 0)
+    hipEvent_t ev_p2m = nullptr, ev_m2l = nullptr;  // leaf densities known (main); deepest M2L done
+    // the evaluation replayed as one graph (ph_plan_set_graph), captured on `cap` for one set of
+    // input and output buffers
+    bool graph_on = false;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *g_I = nullptr, *g_E = nullptr, *g_S = nullptr;
+    int32_t *d_gen = nullptr;  // device: number of the last call (the reset kernel advances it)
     bool count_work = false;        // algorithmic work counters (only for calls that fetch stats)
     bool near_guard = true;         // near pairs may have (b - a) r < 1/4: small-argument series needed
     size_t bytes_allocated = 0;
@@ -292,7 +302,8 @@ void launch_gather_sorted(const double *xyz, const double *w, const int32_t *per
                           double *xyz_sorted, double *w_sorted, int32_t *iperm, hipStream_t s);
 
 // selection (k_select.hip)
-void launch_reset_scalars(CallScalars *sc, hipStream_t s);
+// Clears the call's scalars; with gen, also advances the call number there and stores it in sc
+void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s);
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
                        CallScalars *sc, void *tmp /* >= 16 KiB */, hipStream_t s);
 void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
@@ -308,8 +319,13 @@ void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready);  // records vt_re
 
 // fmm (k_fmm.hip, k_m2l.hip)
 void fmm_upward(Plan &p, hipStream_t s);
+void fmm_p2m(Plan &p, hipStream_t s);  // the upward pass split: leaf densities ...
+void fmm_m2m(Plan &p, hipStream_t s);  // ... and the M2M chain
+// The deepest level's M2L products on s (after the leaf densities and the offset masks);
+// false if this plan computes that level with the others (then nothing is launched)
+bool fmm_m2l_deepest(Plan &p, hipStream_t s);
 // waits for vt_ready (offset masks) before the M2L products and for lists_ready before the gathers
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready);
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready, hipEvent_t deep_m2l);
 void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
 // far field at targets (L2P, M2P, own cell) + output: the matrix-core kernel on s, the other
