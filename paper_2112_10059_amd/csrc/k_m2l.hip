@@ -699,8 +699,8 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
     // the levels' M2L products in one launch (they depend on the upward pass and on the offset
     // masks only); the deepest level's were launched on another stream when deep_m2l is given
     const int top = deep_m2l ? D - 1 : D;
+    PH_HIP(hipStreamWaitEvent(s, vt_ready, 0));  // offset masks and V/X targets
     if (p.y_all_levels && top >= 2) {
-        PH_HIP(hipStreamWaitEvent(s, vt_ready, 0));
         GemmSegs sg{};
         int64_t tiles = 0;
         for (int l = 2; l <= top; ++l) {

@@ -438,7 +438,17 @@ void build_tree(Plan &p, hipStream_t s)
                                          p.lists.m2l_tile_use, p.m2l_tiles * kUseWords);
 }
 
-void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready)
+void build_vtargets(Plan &p, hipStream_t s)
+{
+    LevelInfo li = level_info(p);
+    if (p.method == PH_METHOD_FMM && p.max_depth >= 2) {
+        int64_t cap = 0;
+        for (int l = 2; l <= p.max_depth; ++l) cap += p.level_cap[l];
+        vtarget_kernel<<<(unsigned)std::min<int64_t>((cap + 3) / 4, 1024), 256, 0, s>>>(p.box, li, p.d_sc, p.lists);
+    }
+}
+
+void build_lists(Plan &p, hipStream_t s)
 {
     LevelInfo li = level_info(p);
     const int32_t nbox = (int32_t)p.box_cap;
@@ -447,12 +457,6 @@ void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready)
     if (p.grid_mode)
         for (int l = 0; l <= p.max_depth; ++l)
             if (l < 2 || p.grid_m[l] > 0) grid_levels |= 1u << l;
-    if (p.method == PH_METHOD_FMM && p.max_depth >= 2) {
-        int64_t cap = 0;
-        for (int l = 2; l <= p.max_depth; ++l) cap += p.level_cap[l];
-        vtarget_kernel<<<(unsigned)std::min<int64_t>((cap + 3) / 4, 1024), 256, 0, s>>>(p.box, li, p.d_sc, p.lists);
-    }
-    PH_HIP(hipEventRecord(vt_ready, s));
     list_build_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels);
 }
 

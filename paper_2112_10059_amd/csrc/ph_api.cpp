@@ -830,8 +830,12 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     // the far-field kernels, which combine both fields into the output, for the near field.
     PH_HIP(hipEventRecord(p.ev_fork, s));
     PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+    PH_HIP(hipStreamWaitEvent(p.side2, p.ev_fork, 0));
+    // the V/X targets and M2L offset masks on the third stream, beside the lists
+    build_vtargets(p, p.side2);
+    PH_HIP(hipEventRecord(p.ev_vt, p.side2));
     mark(8, p.side);
-    build_lists(p, p.side, p.ev_vt);
+    build_lists(p, p.side);
     mark(9, p.side);
     PH_HIP(hipEventRecord(p.ev_lists, p.side));
     fmm_near(p, p.side);
@@ -844,7 +848,6 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     if (deep) {
         PH_HIP(hipEventRecord(p.ev_p2m, s));
         PH_HIP(hipStreamWaitEvent(p.side2, p.ev_p2m, 0));
-        PH_HIP(hipStreamWaitEvent(p.side2, p.ev_vt, 0));
         fmm_m2l_deepest(p, p.side2);
         PH_HIP(hipEventRecord(p.ev_m2l, p.side2));
     }

@@ -315,7 +315,10 @@ void launch_pack_xyzf(const double *xyz, int64_t n, float4 *out, hipStream_t s);
 
 // tree (k_tree.hip)
 void build_tree(Plan &p, hipStream_t s);
-void build_lists(Plan &p, hipStream_t s, hipEvent_t vt_ready);  // records vt_ready once the V/X targets are known
+// V/X targets and M2L offset masks, and the interaction lists: independent of each other (both
+// enter boxes into the V/X target lists through atomics), so they may run on different streams
+void build_vtargets(Plan &p, hipStream_t s);
+void build_lists(Plan &p, hipStream_t s);
 
 // fmm (k_fmm.hip, k_m2l.hip)
 void fmm_upward(Plan &p, hipStream_t s);
