@@ -390,6 +390,121 @@ __global__ __launch_bounds__(256) void m2l_pipe_kernel(const float *__restrict__
     }
 }
 
+// Check values of the target leaves of levels 3 .. depth in one launch (FP32, n_lam <= 64):
+// u_B = w_B + sum over the ancestors A of B at levels 2 .. m - 1 of T(l -> m, pos) w_A, with
+// T the composite of the L2L steps from A down to B (the L2L chain unrolled, by linearity) and
+// w the level-local parts (V and X lists) the gather stored in u.  Leaves are nobody's
+// ancestors, so their u is written in place while the ancestors' w are read.  A workgroup
+// takes the 64 boxes of level m whose coordinates are congruent to its class c modulo
+// 2^(m-2) (one below each level-2 box); they share every composite, so each ancestor level is
+// one 64 x 64 x 64 product on the matrix cores (the next level's loads go out before the
+// current product), accumulated in registers.
+struct CompArgs {
+    const float *ops;
+    const int32_t *map;  // boxes by level and coordinates
+    int64_t map_off[kMaxDepth + 2];
+    int64_t off[kMaxDepth + 2][kMaxDepth + 2];
+    int depth;
+};
+
+__global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArgs ca, int kp)
+{
+    constexpr int KT = 64, kV = KT * kTile / 256;
+    __shared__ float As[kTile][KT + kPad];
+    __shared__ float Bs[kTile][KT + kPad];
+    __shared__ int32_t anc[kMaxDepth + 2][kTile];  // per ancestor level, each column's ancestor
+    __shared__ int32_t leafb[kTile];               // the column's leaf (-1: none)
+    __shared__ int anyv;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int ws = __builtin_amdgcn_readfirstlane(w);
+    const int wn = w >> 1, wm = w & 1;
+    const int nl = a.n_lam;
+    int m = -1, cls = blockIdx.x;
+    for (int l = 3; l <= ca.depth; ++l) {
+        const int n = 1 << (3 * (l - 2));
+        if (cls < n) {
+            m = l;
+            break;
+        }
+        cls -= n;
+    }
+    if (m < 0) return;
+    const int sh = m - 2, side = 1 << sh;
+    const int cx = cls >> (2 * sh), cy = (cls >> sh) & (side - 1), cz = cls & (side - 1);
+    if (t == 0) anyv = 0;
+    __syncthreads();
+    if (t < kTile) {
+        // column t: below the level-2 box (t / 16, t / 4 % 4, t % 4)
+        const int X = (t >> 4) * side + cx, Y = ((t >> 2) & 3) * side + cy, Z = (t & 3) * side + cz;
+        const int64_t nm = (int64_t)1 << m;
+        const int32_t B = ca.map[ca.map_off[m] + ((int64_t)X * nm + Y) * nm + Z];
+        const bool v = B >= 0 && (a.bx.flags[B] & kBoxLeaf) && a.bx.t_cnt[B] > 0;
+        leafb[t] = v ? B : -1;
+        for (int l = 2; l < m; ++l) {
+            const int s2 = m - l;
+            const int64_t n2 = (int64_t)1 << l;
+            anc[l][t] = v ? ca.map[ca.map_off[l] + ((int64_t)(X >> s2) * n2 + (Y >> s2)) * n2 + (Z >> s2)] : -1;
+        }
+        if (v) anyv = 1;
+    }
+    __syncthreads();
+    if (!anyv) return;
+    // the leaves' own level-local parts, for the epilogue
+    float own[2][2][4];
+    for (int i = 0; i < 2; ++i)
+        for (int q = 0; q < 2; ++q) {
+            const int gm = wm * 32 + q * 16 + (lane & 15);
+            for (int r = 0; r < 4; ++r) {
+                const int32_t B = leafb[wn * 32 + i * 16 + Mfma<float>::row(lane, r)];
+                own[i][q][r] = (B >= 0 && gm < nl) ? a.u[(size_t)B * nl + gm] : 0.0f;
+            }
+        }
+    auto op_of = [&](int l) {
+        const int s2 = m - l, sd = 1 << s2, msk = sd - 1;
+        const int pos = ((cx & msk) * sd + (cy & msk)) * sd + (cz & msk);
+        return ca.ops + ca.off[m][l] + (int64_t)pos * nl * kp;
+    };
+    float areg[kV], breg[kV];
+    load_box_rows<float, KT>(areg, a.u, nl, anc[2], 0, ws, t);
+    load_rows<float, KT>(breg, op_of(2), kp, 0, nl, kp, 0, ws, t);
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int q = 0; q < 2; ++q) acc[i][q] = f32x4{0, 0, 0, 0};
+    for (int l = 2; l < m; ++l) {
+#pragma unroll
+        for (int u = 0; u < kV; ++u) {
+            As[ws + 4 * u][lane] = areg[u];
+            Bs[ws + 4 * u][lane] = breg[u];
+        }
+        __syncthreads();
+        if (l + 1 < m) {
+            load_box_rows<float, KT>(areg, a.u, nl, anc[l + 1], 0, ws, t);
+            load_rows<float, KT>(breg, op_of(l + 1), kp, 0, nl, kp, 0, ws, t);
+        }
+#pragma unroll
+        for (int ks = 0; ks < KT; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            float av[2], bv[2];
+            for (int i = 0; i < 2; ++i) av[i] = As[wn * 32 + i * 16 + (lane & 15)][kk];
+            for (int q = 0; q < 2; ++q) bv[q] = Bs[wm * 32 + q * 16 + (lane & 15)][kk];
+            for (int i = 0; i < 2; ++i)
+                for (int q = 0; q < 2; ++q) acc[i][q] = Mfma<float>::mma(av[i], bv[q], acc[i][q]);
+        }
+        __syncthreads();  // every wave is done with As and Bs
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int q = 0; q < 2; ++q) {
+            const int gm = wm * 32 + q * 16 + (lane & 15);
+            for (int r = 0; r < 4; ++r) {
+                const int cn = wn * 32 + i * 16 + Mfma<float>::row(lane, r);
+                const int32_t B = leafb[cn];
+                if (B < 0 || gm >= nl) continue;
+                a.u[(size_t)B * nl + gm] = acc[i][q][r] + own[i][q][r];
+                if (a.work && gm == 0) atomicAdd(&a.work[7], 1ull);
+            }
+        }
+}
+
 // M2L GEMM of the split-BF16 form (same tiling and output as tgemm_kernel in M2L mode):
 // every operand x is taken as hi + lo with hi = bf16(x), lo = bf16(x - hi) (the operator's
 // parts precomputed in FP64, the densities split while staged), and
@@ -738,6 +853,22 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
                 launch_gather<T>(p, a, gl_grid, gl, M, (int32_t)r0, (int32_t)ccap, c == 0, c == 0, s);
             }
         }
+    }
+    if (std::is_same<T, float>::value && p.l2l_comp) {
+        // every target leaf of levels >= 3 from its ancestors' level-local parts in one launch
+        CompArgs ca{};
+        ca.ops = (const float *)p.ops.l2l_comp;
+        ca.map = p.d_boxmap;
+        for (int l = 0; l < kMaxDepth + 2; ++l) {
+            ca.map_off[l] = p.boxmap_off[l];
+            for (int k = 0; k < kMaxDepth + 2; ++k) ca.off[l][k] = p.comp_off[l][k];
+        }
+        ca.depth = D;
+        int64_t classes = 0;
+        for (int l = 3; l <= D; ++l) classes += (int64_t)1 << (3 * (l - 2));
+        if (classes > 0)
+            l2l_comp_kernel<<<(unsigned)classes, 256, 0, s>>>(*reinterpret_cast<FmmArgs<float> *>(&a), ca, p.k_pad);
+        return;
     }
     // u of every child of the split boxes with targets at level l - 1 = L2L_all (8 n_lam x n_lam)
     // applied to the parent's u, plus the child's level-local part

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "k_common.h"
@@ -20,6 +21,23 @@ void upload(Plan &p, void **dst, const std::vector<T> &src)
 {
     *dst = dev_alloc(p, src.size() * sizeof(T));
     PH_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// f(i) for i in [0, n) over up to 16 host threads
+template <class F>
+void parallel_for_host(int n, F &&f)
+{
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 4 || nt == 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int i = (int)t; i < n; i += (int)nt) f(i);
+        });
+    for (auto &x : th) x.join();
 }
 
 template <class T>
@@ -313,7 +331,7 @@ void free_plan(Plan *p)
                     p->d_row_feat,
                     p->d_cell,
                     p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near,
-                    p->ops.near_tab, p->d_gen};
+                    p->ops.near_tab, p->d_gen, p->ops.l2l_comp, p->d_boxmap};
     for (void *q : ptrs) dev_free(q);
     if (p->events_ready)
         for (auto &set : p->ring)
@@ -522,6 +540,24 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         for (size_t i = 0; i < leaves.size(); ++i) of_box[leaves[i]] = (int32_t)i;
         up(&p.d_pleaf_of_box, of_box);
         p.h_pleaf = std::move(leaves);
+        // boxes by level and coordinates, for the composite translations
+        const int D = (int)FT.level_cap.size() - 1;
+        if (D >= 3 && D <= kCompMaxDepth) {
+            std::vector<int32_t> map;
+            for (int l = 0; l <= D; ++l) {
+                p.boxmap_off[l] = (int64_t)map.size();
+                if (l < 2) continue;
+                const int64_t nside = (int64_t)1 << l;
+                map.resize(map.size() + (size_t)(nside * nside * nside), -1);
+            }
+            for (size_t f = 0; f < FT.level.size(); ++f) {
+                const int l = FT.level[f];
+                if (l < 2) continue;
+                const int64_t nside = (int64_t)1 << l;
+                map[(size_t)(p.boxmap_off[l] + ((int64_t)FT.ax[f] * nside + FT.ay[f]) * nside + FT.az[f])] = (int32_t)f;
+            }
+            up(&p.d_boxmap, map);
+        }
     }
     p.level_base.assign(p.level_cap.size() + 1, 0);
     for (size_t l = 0; l < p.level_cap.size(); ++l) p.level_base[l + 1] = p.level_base[l] + p.level_cap[l];
@@ -662,6 +698,53 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
             upload(p, &p.ops.uc2e_cm, convert<float>(cm));
             upload(p, &p.ops.m2m, convert<float>(m2m));
             upload(p, &p.ops.l2l, convert<float>(l2l));
+            if (p.d_boxmap && nl <= 64 && p.k_pad <= 64) {
+                // composite translations, level by level in FP64: the one from level l to level m
+                // at position pos is L2L(m, o) times the one from l to m - 1 at the parent's
+                // position (pos / 2 per axis), o the octant of the last step; L2L(m, o)[j][i] =
+                // M2M(m, o)[i][j]
+                const int D = p.max_depth, kp = p.k_pad;
+                std::vector<std::vector<double>> prev(D + 1), cur(D + 1);
+                std::vector<float> comp;
+                for (int m = 3; m <= D; ++m) {
+                    for (int l = 2; l < m; ++l) {
+                        const int side = 1 << (m - l), npos = side * side * side;
+                        cur[l].assign((size_t)npos * nl * nl, 0.0);
+                        parallel_for_host(npos, [&](int pos) {
+                            const int rx = pos / (side * side), ry = (pos / side) % side, rz = pos % side;
+                            const int o = ((rx & 1) << 2) | ((ry & 1) << 1) | (rz & 1);
+                            const double *M = &H.m2m[m][(size_t)o * nl * nl];
+                            double *dst = &cur[l][(size_t)pos * nl * nl];
+                            if (l == m - 1) {
+                                for (int j = 0; j < nl; ++j)
+                                    for (int i = 0; i < nl; ++i) dst[(size_t)j * nl + i] = M[(size_t)i * nl + j];
+                                return;
+                            }
+                            const int hs = side / 2;
+                            const int ppos = ((rx >> 1) * hs + (ry >> 1)) * hs + (rz >> 1);
+                            const double *Tp = &prev[l][(size_t)ppos * nl * nl];
+                            for (int k = 0; k < nl; ++k)
+                                for (int j = 0; j < nl; ++j) {
+                                    const double mkj = M[(size_t)k * nl + j];
+                                    const double *tk = Tp + (size_t)k * nl;
+                                    double *dj = dst + (size_t)j * nl;
+                                    for (int i = 0; i < nl; ++i) dj[i] += mkj * tk[i];
+                                }
+                        });
+                        p.comp_off[m][l] = (int64_t)comp.size();
+                        comp.resize(comp.size() + (size_t)npos * nl * kp, 0.0f);
+                        float *out = comp.data() + p.comp_off[m][l];
+                        for (int pos = 0; pos < npos; ++pos)
+                            for (int j = 0; j < nl; ++j)
+                                for (int i = 0; i < nl; ++i)
+                                    out[((size_t)pos * nl + j) * kp + i] =
+                                        (float)cur[l][((size_t)pos * nl + j) * nl + i];
+                    }
+                    std::swap(prev, cur);
+                }
+                upload(p, &p.ops.l2l_comp, comp);
+                p.l2l_comp = true;
+            }
             upload(p, &p.ops.m2l, convert<float>(m2l));
             if (p.precision == PH_FP32_BF16SPLIT) {
                 std::vector<uint16_t> hi, lo;

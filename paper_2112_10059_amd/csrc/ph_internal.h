@@ -135,7 +135,14 @@ struct OperatorsDev {
     int near_R = 0;        // offsets per axis within [-R, R] (R = 2 m - 1 for leaves of m^3 cells)
     int near_level = -1;   // level of the leaves the table serves
     int near_sx = 0, near_sy = 0, near_sz = 0, near_n = 0;  // strides and entries
+    // composite L2L translations (FP32 forms): from a box of level l to its descendant at level m
+    // in relative position pos (coordinates mod 2^(m-l), pos = (x 2^(m-l) + y) 2^(m-l) + z),
+    // the product of the L2L steps along the path; n_lam rows x k_pad columns each, the ones of
+    // (m, l) from element comp_off[m][l]
+    void *l2l_comp = nullptr;
 };
+
+constexpr int kCompMaxDepth = 6;  // composite translations for trees of at most this depth
 
 constexpr int kNearTabMaxR = 7;     // table for leaves of at most 4^3 cells
 constexpr int kNearTabMax = 4800;   // entries kept in LDS
@@ -249,6 +256,12 @@ struct Plan {
     hipEvent_t ev_down = nullptr, ev_rest = nullptr;  // downward done (main); far kernels on side done
     hipEvent_t ev_vt = nullptr;  // V/X targets and M2L offset masks known (side)
     hipEvent_t ev_p2m = nullptr, ev_m2l = nullptr;  // leaf densities known (main); deepest M2L done
+    // check values of the leaves of levels >= 3 in one launch from the level-local parts of their
+    // ancestors (composite translations) in place of the level-by-level L2L chain
+    bool l2l_comp = false;
+    int32_t *d_boxmap = nullptr;                  // boxes of level l >= 2 by coordinates (8^l, -1)
+    int64_t boxmap_off[kMaxDepth + 2] = {};
+    int64_t comp_off[kMaxDepth + 2][kMaxDepth + 2] = {};
     // the evaluation replayed as one graph (ph_plan_set_graph), captured on `cap` for one set of
     // input and output buffers
     bool graph_on = false;
