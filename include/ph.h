@@ -170,11 +170,11 @@ void ph_plan_destroy(ph_plan *plan);
  *         the counts and per-phase times, and reports PH_ENUMERIC if the device
  *         flagged a bad source value.  When NULL the call is fully asynchronous
  *         and a numeric fault is reported by the next ph_plan_check().
- * The interaction lists, the near field and the far field of leaves without a
- * small grid operator run on a stream the plan owns, forked from `stream` after
- * the octree and joined back into it before the call's last phase ends (events,
- * no host synchronisation), so the call stays ordered on `stream` and may be
- * captured into a HIP graph.  Calls on one plan must not overlap.
+ * The interaction lists and the near field run on a second stream the plan owns,
+ * and the V/X target lists with the deepest level's M2L products on a third, both
+ * forked from `stream` after the octree and joined back into it before the far
+ * field (events, no host synchronisation), so the call stays ordered on `stream`
+ * and may be captured into a HIP graph.  Calls on one plan must not overlap.
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);
@@ -200,7 +200,8 @@ ph_status ph_plan_set_graph(ph_plan *plan, int enable);
  *   7 far field at the targets (L2P, M2P, own cell) and the output (waits for 8)
  *   8 near field (P2P), or the whole direct sum
  * Phases 4 and 8 run on the plan's second stream beside phases 5-7, so their
- * times overlap those.
+ * times overlap those; the V/X target lists and the deepest level's M2L products
+ * run on a third stream (not timed apart: their time shows in phases 5 and 6).
  * *n_calls (nullable) the number of calls.  The sums are then reset.  record = 1
  * turns recording on for every later ph_evaluate (events on the caller's stream,
  * no extra synchronisation), 0 turns it off, -1 leaves it unchanged.  Synchronous.

@@ -297,8 +297,8 @@ __device__ __forceinline__ T w_list_far(const FmmArgs<T> &a, int32_t b, const V4
 
 // This workgroup's level and the first entry of its slice of that level's far_a segment, for
 // the levels in mask, at per leaves per workgroup; false if the workgroup has no slice.
-__device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint32_t mask, int per, int &level,
-                                          int32_t &first)
+__device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint32_t mask, int per, int32_t slice,
+                                          int &level, int32_t &first)
 {
     int32_t cnt[kMaxDepth + 2];
 #pragma unroll
@@ -308,9 +308,9 @@ __device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint
     for (int l = 0; l < kMaxDepth + 2; ++l) {
         if (l > depth || !((mask >> l) & 1u)) continue;
         const int32_t nb = (cnt[l] + per - 1) / per;
-        if ((int32_t)blockIdx.x < acc + nb) {
+        if (slice < acc + nb) {
             level = l;
-            first = ((int32_t)blockIdx.x - acc) * per;
+            first = (slice - acc) * per;
             return true;
         }
         acc += nb;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int level;
     int32_t first;
-    if (!far_slice(a.sc, a.lt.depth, level_mask, kFarMLeaves, level, first)) return;
+    if (!far_slice(a.sc, a.lt.depth, level_mask, kFarMLeaves, (int32_t)blockIdx.x, level, first)) return;
     const int32_t cnt = min(kFarMLeaves, a.sc->n_far_a_lvl[level] - first);
     const int nl = a.n_lam;
     const int gm = level >= 2 ? a.grid_m[level] : 0;  // 0: no far field at this level
@@ -514,78 +514,83 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
     extern __shared__ __align__(16) unsigned char far_lds[];  // stage_cap operator entries
     T *Gs = reinterpret_cast<T *>(far_lds);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int level;
-    int32_t first;
-    if (!far_slice(a.sc, a.lt.depth, level_mask, kFarLeaves, level, first)) return;  // the whole workgroup
-    const int32_t cnt = min(kFarLeaves, a.sc->n_far_a_lvl[level] - first);
-    const int nl = a.n_lam;
-    const int gm = level >= 2 ? a.grid_m[level] : 0;
-    const int R = gm * gm * gm;
-    const T *G = a.grid_g + a.grid_off[level];
-    const bool staged = gm > 0 && nl * R <= stage_cap;
-    if (staged) {
-        // 16-byte loads, all issued before any store (one round trip to L2, not one per element);
-        // the level offsets are multiples of 16 bytes whenever n_lam m^3 is a multiple of 4
-        const int ne = nl * R;
-        if ((ne & 3) == 0 && (a.grid_off[level] & 3) == 0) {
-            using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-            constexpr int per = 16 / sizeof(T);
-            const V *src = reinterpret_cast<const V *>(G);
-            V *dst = reinterpret_cast<V *>(Gs);
-            const int nv = ne / per;
-            V buf[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = threadIdx.x + u * blockDim.x;
-                if (i < nv) buf[u] = src[i];
+    // slices of the per-level leaf lists, grid-stride (a small grid costs little when the lists
+    // are empty)
+    for (int32_t slice = blockIdx.x;; slice += gridDim.x) {
+        int level;
+        int32_t first;
+        if (!far_slice(a.sc, a.lt.depth, level_mask, kFarLeaves, slice, level, first)) return;  // the whole workgroup
+        if (slice != (int32_t)blockIdx.x) __syncthreads();  // the previous slice is done with Gs
+        const int32_t cnt = min(kFarLeaves, a.sc->n_far_a_lvl[level] - first);
+        const int nl = a.n_lam;
+        const int gm = level >= 2 ? a.grid_m[level] : 0;
+        const int R = gm * gm * gm;
+        const T *G = a.grid_g + a.grid_off[level];
+        const bool staged = gm > 0 && nl * R <= stage_cap;
+        if (staged) {
+            // 16-byte loads, all issued before any store (one round trip to L2, not one per element);
+            // the level offsets are multiples of 16 bytes whenever n_lam m^3 is a multiple of 4
+            const int ne = nl * R;
+            if ((ne & 3) == 0 && (a.grid_off[level] & 3) == 0) {
+                using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+                constexpr int per = 16 / sizeof(T);
+                const V *src = reinterpret_cast<const V *>(G);
+                V *dst = reinterpret_cast<V *>(Gs);
+                const int nv = ne / per;
+                V buf[8];
+    #pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = threadIdx.x + u * blockDim.x;
+                    if (i < nv) buf[u] = src[i];
+                }
+    #pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = threadIdx.x + u * blockDim.x;
+                    if (i < nv) dst[i] = buf[u];
+                }
+                for (int i = threadIdx.x + 8 * blockDim.x; i < nv; i += blockDim.x) dst[i] = src[i];
+            } else {
+                for (int i = threadIdx.x; i < ne; i += blockDim.x) Gs[i] = G[i];
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = threadIdx.x + u * blockDim.x;
-                if (i < nv) dst[i] = buf[u];
-            }
-            for (int i = threadIdx.x + 8 * blockDim.x; i < nv; i += blockDim.x) dst[i] = src[i];
-        } else {
-            for (int i = threadIdx.x; i < ne; i += blockDim.x) Gs[i] = G[i];
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    const int scale_exp = a.sc->scale_exp;
-    for (int32_t q = w; q < cnt; q += 4) {
-        const int32_t b = a.L.far_a[a.lt.base[level] + first + q].x;
-        T uv[NK];
-#pragma unroll
-        for (int k = 0; k < NK; ++k)
-            uv[k] = (gm > 0 && 64 * k + lane < nl) ? a.u[(size_t)b * nl + 64 * k + lane] : T(0);
-        const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
-        const bool near = a.L.u_rng[b].y > a.L.u_rng[b].x;
-        const bool has_w = a.L.w_rng[b].y > a.L.w_rng[b].x;
-        if (a.work && lane == 0) {
-            unsigned long long near_src = 0;
-            for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
-            atomicAdd(&a.work[0], near_src * tn);
-            if (near) atomicAdd(&a.work[10], (unsigned long long)tn);
-            if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
-            if (has_w) atomicAdd(&a.work[2], (unsigned long long)(a.L.w_rng[b].y - a.L.w_rng[b].x) * nl * tn);
-        }
-        // the leaf's points in sorted order, the targets among them flagged
-        for (int tb = 0; tb < np; tb += 64) {
-            const int32_t k = p0 + tb + lane;
-            const uint32_t sb = tb + lane < np ? a.sel[k] : 0u;
-            const bool act = (sb & 2u) != 0;
-            V4<T> x;
-            if (act && has_w) x = point_xyz(a, k);
-            else x.x = x.y = x.z = x.w = T(0);
-            T far = 0;
-            if (gm > 0) {
-                const int r = act ? local_cell(a, a.pcell[k], b, gm) : 0;
-                far = staged ? grid_far<T, NK, true>(Gs, R, nl, r, uv) : grid_far<T, NK, false>(G, R, nl, r, uv);
+        const int scale_exp = a.sc->scale_exp;
+        for (int32_t q = w; q < cnt; q += 4) {
+            const int32_t b = a.L.far_a[a.lt.base[level] + first + q].x;
+            T uv[NK];
+    #pragma unroll
+            for (int k = 0; k < NK; ++k)
+                uv[k] = (gm > 0 && 64 * k + lane < nl) ? a.u[(size_t)b * nl + 64 * k + lane] : T(0);
+            const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
+            const bool near = a.L.u_rng[b].y > a.L.u_rng[b].x;
+            const bool has_w = a.L.w_rng[b].y > a.L.w_rng[b].x;
+            if (a.work && lane == 0) {
+                unsigned long long near_src = 0;
+                for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+                atomicAdd(&a.work[0], near_src * tn);
+                if (near) atomicAdd(&a.work[10], (unsigned long long)tn);
+                if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
+                if (has_w) atomicAdd(&a.work[2], (unsigned long long)(a.L.w_rng[b].y - a.L.w_rng[b].x) * nl * tn);
             }
-            if (has_w) far += w_list_far<T, NK>(a, b, x, act, lane);
-            if (act) {
-                const int32_t o = a.perm[k];
-                put_output(S_out, o, a.P, (double)far + (near ? t_near[k] : 0.0) + own_term(a, sb, o, scale_exp),
-                           scale_exp);
+            // the leaf's points in sorted order, the targets among them flagged
+            for (int tb = 0; tb < np; tb += 64) {
+                const int32_t k = p0 + tb + lane;
+                const uint32_t sb = tb + lane < np ? a.sel[k] : 0u;
+                const bool act = (sb & 2u) != 0;
+                V4<T> x;
+                if (act && has_w) x = point_xyz(a, k);
+                else x.x = x.y = x.z = x.w = T(0);
+                T far = 0;
+                if (gm > 0) {
+                    const int r = act ? local_cell(a, a.pcell[k], b, gm) : 0;
+                    far = staged ? grid_far<T, NK, true>(Gs, R, nl, r, uv) : grid_far<T, NK, false>(G, R, nl, r, uv);
+                }
+                if (has_w) far += w_list_far<T, NK>(a, b, x, act, lane);
+                if (act) {
+                    const int32_t o = a.perm[k];
+                    put_output(S_out, o, a.P, (double)far + (near ? t_near[k] : 0.0) + own_term(a, sb, o, scale_exp),
+                               scale_exp);
+                }
             }
         }
     }
@@ -899,8 +904,8 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
                 if (((wave_levels >> l) & 1u) && p.grid_m[l] > 0 && e <= kGridStage) cap = std::max(cap, e);
             }
             const size_t lds = (size_t)cap * sizeof(T);
-            const unsigned g = (unsigned)gw_blocks;
-            hipStream_t sg = std::is_same<T, float>::value ? s_aux : s;  // beside the matrix-core kernel
+            const unsigned g = (unsigned)std::min<int64_t>(gw_blocks, 256);
+            hipStream_t sg = s;
             switch ((p.n_lam + 63) / 64) {
             case 1: far_grid_kernel<T, T, 1><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
             case 2: far_grid_kernel<T, T, 2><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
@@ -914,7 +919,7 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
     bool shell_leaves = !p.grid_mode;
     for (int l = 2; l <= p.max_depth; ++l) shell_leaves = shell_leaves || p.grid_m[l] == 0;
     if (shell_leaves)
-        far_shell_kernel<T, T><<<(unsigned)std::min<int64_t>(B, p.grid_mode ? 256 : 4096), 64, 0, s_aux>>>(
+        far_shell_kernel<T, T><<<(unsigned)std::min<int64_t>(B, p.grid_mode ? 256 : 4096), 64, 0, s>>>(
             a, (T *)S_out, p.d_t_near);
 }
 

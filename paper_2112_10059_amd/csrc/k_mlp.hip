@@ -421,12 +421,42 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(LeafArgs a, const T *_
 }
 
 // Pass 2, one thread per plan leaf: it is a row iff its largest I passes the source rule.
-__global__ void leaf_pick_kernel(LeafArgs a)
+// Every workgroup first reduces pass 1's per-workgroup maxima itself (nb of them, a few KB
+// from L2) for the largest I; workgroup 0 also stores the maxima for the later kernels.
+__global__ __launch_bounds__(256) void leaf_pick_kernel(LeafArgs a, const double *__restrict__ partial,
+                                                        const uint64_t *__restrict__ partial_key, int nb)
 {
+    __shared__ double smI[4];
+    __shared__ uint64_t smE[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double mi = 0.0;
+    uint64_t me = 0;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+        mi = fmax(mi, partial[j]);
+        me = max(me, partial_key[j]);
+    }
+    mi = wave_max(mi);
+    me = wave_max_u64(me);
+    if (lane == 0) {
+        smI[wv] = mi;
+        smE[wv] = me;
+    }
+    __syncthreads();
+    double imax = smI[0];
+    uint64_t ekey = smE[0];
+    for (int q = 1; q < 4; ++q) {
+        imax = fmax(imax, smI[q]);
+        ekey = max(ekey, smE[q]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sc->imax = imax;
+        a.sc->emax = (double)__uint_as_float((uint32_t)(ekey >> 32));
+        a.sc->emax_key = ekey;
+    }
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && a.flag2) a.flag2[a.n_pleaf] = 0;
     if (i >= a.n_pleaf) return;
-    const bool cand = candidate(a.lstat[(size_t)i * 4], a.src_rel, a.sc->imax);
+    const bool cand = candidate(a.lstat[(size_t)i * 4], a.src_rel, imax);
     a.flag[i] = cand ? 1u : 0u;
     if (a.flag2) a.flag2[i] = cand ? 1u : 0u;
     if (cand) a.list[atomicAdd(&a.sc->n_srcleaf, 1)] = i;
@@ -656,7 +686,16 @@ void selector_reduce(Plan &p, const void *I, const float *E, hipStream_t s)
         leaf_reduce_kernel<double><<<nb, 256, 0, s>>>(a, (const double *)I, partial, partial_key);
     else
         leaf_reduce_kernel<float><<<nb, 256, 0, s>>>(a, (const float *)I, partial, partial_key);
-    launch_reduce_max_final(partial, partial_key, nb, p.d_sc, s);
+    // the maxima over the workgroups' partials: reduced by each workgroup of the pick pass
+}
+
+// the pick pass over the plan leaves, with the maxima of pass 1's partials (see selector_reduce)
+static void launch_leaf_pick(Plan &p, const LeafArgs &a, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>((p.n_pleaf + 4 * kLPW - 1) / (4 * kLPW), 1024);
+    const double *partial = reinterpret_cast<const double *>(p.d_scan_tmp);
+    const uint64_t *partial_key = reinterpret_cast<const uint64_t *>(partial + 1024);
+    leaf_pick_kernel<<<(unsigned)((p.n_pleaf + 255) / 256), 256, 0, s>>>(a, partial, partial_key, nb);
 }
 
 // rows, their features, and the rows compacted in box order (after selector_reduce)
@@ -664,7 +703,7 @@ void selector_features(Plan &p, const void *I, const float *E, hipStream_t s)
 {
     LeafArgs a = leaf_args(p, E);
     a.flag2 = p.d_leafscan;
-    leaf_pick_kernel<<<(unsigned)((p.n_pleaf + 255) / 256), 256, 0, s>>>(a);
+    launch_leaf_pick(p, a, s);
     if (p.precision == PH_FP64) leaf_features_kernel<double, false><<<feature_blocks(p), 256, 0, s>>>(a, (const double *)I);
     else leaf_features_kernel<float, false><<<feature_blocks(p), 256, 0, s>>>(a, (const float *)I);
     exclusive_scan_u32(p.d_leafscan, p.n_pleaf + 1, p.d_scan_tmp, nullptr, s);
@@ -680,7 +719,7 @@ void selector_decide(Plan &p, const void *I, const float *E, hipStream_t s)
     a.threshold = p.sel_threshold;
     a.logits = p.d_logit;
     a.drop = p.d_drop;
-    leaf_pick_kernel<<<(unsigned)((p.n_pleaf + 255) / 256), 256, 0, s>>>(a);
+    launch_leaf_pick(p, a, s);
     if (p.precision == PH_FP64) leaf_features_kernel<double, true><<<feature_blocks(p), 256, 0, s>>>(a, (const double *)I);
     else leaf_features_kernel<float, true><<<feature_blocks(p), 256, 0, s>>>(a, (const float *)I);
 }

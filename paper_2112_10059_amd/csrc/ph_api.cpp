@@ -938,13 +938,9 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(5, s);
     fmm_downward(p, s, p.ev_vt, p.ev_lists, deep ? p.ev_m2l : nullptr);
     mark(6, s);
-    // far field: the matrix-core kernel here, the other leaf kernels on the second stream
-    PH_HIP(hipEventRecord(p.ev_down, s));
-    PH_HIP(hipStreamWaitEvent(p.side, p.ev_down, 0));
+    // far field at the targets (every leaf kernel here, after the near field)
     PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));
-    fmm_leaf(p, S_out, s, p.side);
-    PH_HIP(hipEventRecord(p.ev_rest, p.side));
-    PH_HIP(hipStreamWaitEvent(s, p.ev_rest, 0));
+    fmm_leaf(p, S_out, s, s);
     mark(7, s);
 }
 
