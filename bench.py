@@ -39,6 +39,8 @@ PEAK_HBM_GBS = 8000.0
 # (3 sub, 5 for r^2, sqrt, 2 for exp(-a r), 3 for 1 - exp(-(b-a) r), 5 for 1/(4 pi L r^3)
 #  and the products, 2 for the multiply-accumulate); transcendentals count as one
 FLOPS_PER_EVAL = 21
+# a pair whose kernel value comes from the table of cell offsets: its multiply-accumulate
+FLOPS_PER_TABLE_PAIR = 2
 
 
 def log(msg):
@@ -288,13 +290,17 @@ def plan_q(args):
 def near_work(st):
     """Algorithmic FP operations and HBM bytes of one launch of the near-field kernel (FP32 form).
 
-    FLOPs: FLOPS_PER_EVAL per source-target pair of the U lists (work counter p2p_pairs).
+    FLOPs: FLOPS_PER_EVAL per source-target pair of the U lists whose kernel value is evaluated,
+    and FLOPS_PER_TABLE_PAIR per pair between two finest-level leaves of a uniform grid, whose
+    kernel value is read from the table of cell offsets (work counters p2p_pairs and
+    p2p_table_pairs).
     Bytes: per target of a leaf with a non-empty U list (work counter near_targets) its
     packed position and own-cell value (16 B), its far-field value (4 B), its sorted
     position and caller index (8 B) and its output S (4 B); per selected source its packed
     position and weighted strength (16 B), read once.
     """
-    return {"flops": FLOPS_PER_EVAL * float(st["work"]["p2p_pairs"]),
+    tab = float(st["work"].get("p2p_table_pairs", 0))
+    return {"flops": FLOPS_PER_EVAL * (float(st["work"]["p2p_pairs"]) - tab) + FLOPS_PER_TABLE_PAIR * tab,
             "bytes": st["work"]["near_targets"] * (16.0 + 4.0 + 8.0 + 4.0) + st["n_src"] * 16.0}
 
 

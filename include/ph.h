@@ -134,7 +134,8 @@ typedef struct {
                                translations, [7] L2L translations, [8] grid local-to-target
                                multiply-adds, [9] grid P2M multiply-adds, [10] targets of leaves
                                with a non-empty U list (those the near-field kernel visits),
-                               [11] reserved                                                    */
+                               [11] those of the near pairs ([0]) whose kernel value is read from
+                               the uniform-grid table of cell offsets                           */
 } ph_stats;
 
 /* Returns a static description of a status code. */

@@ -63,7 +63,7 @@ class PhStats(ctypes.Structure):
 
 
 WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pairs", "m2m_children",
-        "l2l_boxes", "grid_l2p_madds", "grid_p2m_madds", "near_targets", "reserved11")
+        "l2l_boxes", "grid_l2p_madds", "grid_p2m_madds", "near_targets", "p2p_table_pairs")
 
 
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",

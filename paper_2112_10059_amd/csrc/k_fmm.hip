@@ -474,9 +474,15 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     if (a.work && t < cnt) {
         const int32_t b = lbox[t];
         const int32_t tn = a.bx.t_cnt[b];  // targets (the entry counts all the leaf's points)
-        unsigned long long near_src = 0;
-        for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
+        unsigned long long near_src = 0, tab_src = 0;
+        const bool tab_b = a.near_tab != nullptr && a.bx.level[b] == a.near_level;
+        for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) {
+            const int32_t C = a.L.u[e];
+            near_src += a.bx.s_cnt[C];
+            if (tab_b && a.bx.level[C] == a.near_level) tab_src += a.bx.s_cnt[C];
+        }
         atomicAdd(&a.work[0], near_src * tn);
+        if (tab_src) atomicAdd(&a.work[11], tab_src * tn);
         if (lnear[t]) atomicAdd(&a.work[10], (unsigned long long)tn);
         if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
         const uint32_t nw = a.L.w_rng[b].y - a.L.w_rng[b].x;

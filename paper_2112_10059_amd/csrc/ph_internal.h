@@ -67,7 +67,8 @@ struct CallScalars {
     // algorithmic work of the call (integer counters, order independent)
     unsigned long long work[12];        // p2p pairs, l2p evals, m2p evals, p2m evals,
                                         // p2l evals, m2l pairs, m2m children, l2l boxes,
-                                        // grid l2p multiply-adds, grid p2m multiply-adds
+                                        // grid l2p multiply-adds, grid p2m multiply-adds,
+                                        // near-field targets, table near pairs
 };
 
 // Box table (structure of arrays, capacity box_cap).  Structure fields come from the
