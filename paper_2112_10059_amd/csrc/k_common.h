@@ -143,6 +143,33 @@ struct Mfma<double> {
     static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
+// Start of a call, by workgroup 0 of the call's first kernel (no other kernel of the call has
+// run yet, and no other workgroup of that kernel touches the scalars): clear the call's
+// scalars and, with gen, advance the call number kept on the device and store it in sc.
+__device__ __forceinline__ void begin_call(CallScalars *sc, int32_t *gen)
+{
+    int32_t *w = reinterpret_cast<int32_t *>(sc);
+    for (int i = threadIdx.x; i < (int)(sizeof(CallScalars) / 4); i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && gen) {
+        int32_t g = *gen + 1;
+        if (g <= 0) g = 1;
+        *gen = g;
+        sc->gen = g;
+    }
+}
+
+// Per-workgroup maxima of I carry a bad source value seen by the workgroup as -(max + 1)
+__device__ __forceinline__ double mark_bad(double m, bool bad) { return bad ? -(m + 1.0) : m; }
+__device__ __forceinline__ double partial_max(double v, bool &bad)
+{
+    if (v < 0.0) {
+        bad = true;
+        return -v - 1.0;
+    }
+    return v;
+}
+
 // A source value the method cannot use: negative, NaN or infinite.
 template <class T>
 __device__ __forceinline__ bool bad_value(T v)

@@ -512,44 +512,44 @@ __device__ __forceinline__ T grid_far(const T *__restrict__ G, int R, int nl, in
     return (f4[0] + f4[1]) + (f4[2] + f4[3]);
 }
 
+// The body as a workgroup function: workgroup bid of nblk taking part, Gs the LDS staging area
 template <class T, class TO, int NK>
-__global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
-                                                       const double *__restrict__ t_near,
-                                                       int stage_cap, uint32_t level_mask)
+__device__ void far_grid_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const double *__restrict__ t_near,
+                              int stage_cap, uint32_t level_mask, int32_t bid, int32_t nblk, T *Gs)
 {
-    extern __shared__ __align__(16) unsigned char far_lds[];  // stage_cap operator entries
-    T *Gs = reinterpret_cast<T *>(far_lds);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // slices of the per-level leaf lists, grid-stride (a small grid costs little when the lists
     // are empty)
-    for (int32_t slice = blockIdx.x;; slice += gridDim.x) {
+    for (int32_t slice = bid;; slice += nblk) {
         int level;
         int32_t first;
         if (!far_slice(a.sc, a.lt.depth, level_mask, kFarLeaves, slice, level, first)) return;  // the whole workgroup
-        if (slice != (int32_t)blockIdx.x) __syncthreads();  // the previous slice is done with Gs
+        if (slice != bid) __syncthreads();  // the previous slice is done with Gs
         const int32_t cnt = min(kFarLeaves, a.sc->n_far_a_lvl[level] - first);
         const int nl = a.n_lam;
-        const int gm = level >= 2 ? a.grid_m[level] : 0;
+        const int gm = level >= 2 ? level_pick(a.grid_m, level) : 0;
         const int R = gm * gm * gm;
-        const T *G = a.grid_g + a.grid_off[level];
+        const int64_t goff = level_pick(a.grid_off, level);
+        const T *G = a.grid_g + goff;
         const bool staged = gm > 0 && nl * R <= stage_cap;
         if (staged) {
             // 16-byte loads, all issued before any store (one round trip to L2, not one per element);
             // the level offsets are multiples of 16 bytes whenever n_lam m^3 is a multiple of 4
             const int ne = nl * R;
-            if ((ne & 3) == 0 && (a.grid_off[level] & 3) == 0) {
+            if ((ne & 3) == 0 && (goff & 3) == 0) {
                 using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
                 constexpr int per = 16 / sizeof(T);
                 const V *src = reinterpret_cast<const V *>(G);
                 V *dst = reinterpret_cast<V *>(Gs);
                 const int nv = ne / per;
                 V buf[8];
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int i = threadIdx.x + u * blockDim.x;
-                    if (i < nv) buf[u] = src[i];
+                    // an index clamped into the operator keeps every load unconditional
+                    const int i = min((int)(threadIdx.x + u * blockDim.x), nv - 1);
+                    buf[u] = src[i];
                 }
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int i = threadIdx.x + u * blockDim.x;
                     if (i < nv) dst[i] = buf[u];
@@ -562,9 +562,9 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
         }
         const int scale_exp = a.sc->scale_exp;
         for (int32_t q = w; q < cnt; q += 4) {
-            const int32_t b = a.L.far_a[a.lt.base[level] + first + q].x;
+            const int32_t b = a.L.far_a[level_pick(a.lt.base, level) + first + q].x;
             T uv[NK];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NK; ++k)
                 uv[k] = (gm > 0 && 64 * k + lane < nl) ? a.u[(size_t)b * nl + 64 * k + lane] : T(0);
             const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
@@ -605,8 +605,10 @@ __global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restr
 // Far field of the other target leaves (point clouds, or grid levels without an operator),
 // one workgroup per leaf over the list: the leaf's check values give the intensities of its
 // shell points, which are then evaluated at every target; plus the W list and the own cell.
+// The body as a workgroup function (any workgroup size): workgroup bid of nblk taking part
 template <class T, class TO>
-__global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const double *__restrict__ t_near)
+__device__ void far_shell_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const double *__restrict__ t_near,
+                               int32_t bid, int32_t nblk)
 {
     __shared__ T uvec[kMaxLattice];
     __shared__ T wphi[kMaxLattice];
@@ -614,7 +616,7 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
     const int32_t n = a.sc->n_far_b;
     const int nl = a.n_lam, ns = a.n_sig;
     const int scale_exp = a.sc->scale_exp;
-    for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
+    for (int32_t idx = bid; idx < n; idx += nblk) {
         const int32_t b = a.L.far_b[idx];
         const int level = a.bx.level[b];
         const bool has_far = level >= 2;
@@ -689,6 +691,37 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
             }
         }
     }
+}
+
+template <class T, class TO, int NK>
+__global__ __launch_bounds__(256) void far_grid_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
+                                                       const double *__restrict__ t_near,
+                                                       int stage_cap, uint32_t level_mask)
+{
+    extern __shared__ __align__(16) unsigned char far_lds[];  // stage_cap operator entries
+    far_grid_body<T, TO, NK>(a, S_out, t_near, stage_cap, level_mask, (int32_t)blockIdx.x, (int32_t)gridDim.x,
+                             reinterpret_cast<T *>(far_lds));
+}
+
+template <class T, class TO>
+__global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const double *__restrict__ t_near)
+{
+    far_shell_body<T, TO>(a, S_out, t_near, (int32_t)blockIdx.x, (int32_t)gridDim.x);
+}
+
+// Both in one launch (uniform grids): the first g_grid workgroups take the grid-operator leaves,
+// the others the shell-point leaves
+template <class T, class TO, int NK>
+__global__ __launch_bounds__(256) void far_rest_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
+                                                       const double *__restrict__ t_near, int stage_cap,
+                                                       uint32_t level_mask, int32_t g_grid)
+{
+    extern __shared__ __align__(16) unsigned char far_lds[];
+    if ((int32_t)blockIdx.x < g_grid)
+        far_grid_body<T, TO, NK>(a, S_out, t_near, stage_cap, level_mask, (int32_t)blockIdx.x, g_grid,
+                                 reinterpret_cast<T *>(far_lds));
+    else
+        far_shell_body<T, TO>(a, S_out, t_near, (int32_t)blockIdx.x - g_grid, (int32_t)gridDim.x - g_grid);
 }
 
 // Exact near field (Sec. 2.4 eq. (16)) of the leaves with a U list, one workgroup of
@@ -910,18 +943,23 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
                 if (((wave_levels >> l) & 1u) && p.grid_m[l] > 0 && e <= kGridStage) cap = std::max(cap, e);
             }
             const size_t lds = (size_t)cap * sizeof(T);
-            const unsigned g = (unsigned)std::min<int64_t>(gw_blocks, 256);
-            hipStream_t sg = s;
+            const int32_t g = (int32_t)std::min<int64_t>(gw_blocks, 256);
+            // on grids the shell list holds only leaves of levels >= 2 without an operator: its
+            // workgroups join this launch
+            bool shell_leaves = false;
+            for (int l = 2; l <= p.max_depth; ++l) shell_leaves = shell_leaves || p.grid_m[l] == 0;
+            const unsigned gt = (unsigned)(g + (shell_leaves ? (int32_t)std::min<int64_t>(B, 64) : 0));
             switch ((p.n_lam + 63) / 64) {
-            case 1: far_grid_kernel<T, T, 1><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
-            case 2: far_grid_kernel<T, T, 2><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
+            case 1: far_rest_kernel<T, T, 1><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
+            case 2: far_rest_kernel<T, T, 2><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
             case 3:
-            case 4: far_grid_kernel<T, T, 4><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
-            default: far_grid_kernel<T, T, 8><<<g, 256, lds, sg>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels); break;
+            case 4: far_rest_kernel<T, T, 4><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
+            default: far_rest_kernel<T, T, 8><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
             }
+            return;
         }
     }
-    // on grids this list holds only leaves of levels >= 2 without an operator
+    // point clouds (or grids without grid-operator leaves): the shell-point leaves alone
     bool shell_leaves = !p.grid_mode;
     for (int l = 2; l <= p.max_depth; ++l) shell_leaves = shell_leaves || p.grid_m[l] == 0;
     if (shell_leaves)

@@ -72,6 +72,18 @@ __device__ __forceinline__ int local_cell(const FmmArgs<T> &a, int32_t cell, int
     return (i * m + j) * m + k;
 }
 
+// arr[level] with constant indices only (a dynamic index into the kernel's argument block makes
+// the compiler copy the block to scratch)
+template <class A>
+__device__ __forceinline__ A level_pick(const A (&arr)[kMaxDepth + 2], int level)
+{
+    A v{};
+#pragma unroll
+    for (int l = 0; l < kMaxDepth + 2; ++l)
+        if (l == level) v = arr[l];
+    return v;
+}
+
 // coordinates of sorted point k in the working precision
 template <class T>
 __device__ __forceinline__ V4<T> point_xyz(const FmmArgs<T> &a, int64_t k)

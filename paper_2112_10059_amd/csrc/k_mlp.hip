@@ -341,8 +341,9 @@ __device__ __forceinline__ double quarter_max(double v)
 template <class T>
 __global__ __launch_bounds__(256) void leaf_reduce_kernel(LeafArgs a, const T *__restrict__ I,
                                                           double *__restrict__ partial,
-                                                          uint64_t *__restrict__ partial_key)
+                                                          uint64_t *__restrict__ partial_key, int32_t *gen)
 {
+    if (blockIdx.x == 0 && gen) begin_call(a.sc, gen);
     __shared__ double smI[4];
     __shared__ uint64_t smE[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -400,7 +401,10 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(LeafArgs a, const T *_
             a.box_emax[f] = (float)em;
         }
     }
-    if (bad) atomicOr(&a.sc->err, 1);
+    __shared__ int anybad;
+    if (threadIdx.x == 0) anybad = 0;
+    __syncthreads();
+    if (bad) anybad = 1;
     gmax = wave_max(gmax);
     gkey = wave_max_u64(gkey);
     if (lane == 0) {
@@ -415,7 +419,7 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(LeafArgs a, const T *_
             m = fmax(m, smI[q]);
             k = max(k, smE[q]);
         }
-        partial[blockIdx.x] = m;
+        partial[blockIdx.x] = mark_bad(m, anybad != 0);
         partial_key[blockIdx.x] = k;
     }
 }
@@ -431,10 +435,12 @@ __global__ __launch_bounds__(256) void leaf_pick_kernel(LeafArgs a, const double
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double mi = 0.0;
     uint64_t me = 0;
+    bool bad = false;
     for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-        mi = fmax(mi, partial[j]);
+        mi = fmax(mi, partial_max(partial[j], bad));
         me = max(me, partial_key[j]);
     }
+    if (bad && blockIdx.x == 0) atomicOr(&a.sc->err, 1);
     mi = wave_max(mi);
     me = wave_max_u64(me);
     if (lane == 0) {
@@ -676,16 +682,16 @@ static LeafArgs leaf_args(Plan &p, const float *E)
 static unsigned feature_blocks(const Plan &p) { return (unsigned)std::min<int64_t>((p.n_pleaf + 3) / 4, 256); }
 
 // the maxima of I and |E| and the per-leaf statistics in one pass (scalars reset)
-void selector_reduce(Plan &p, const void *I, const float *E, hipStream_t s)
+void selector_reduce(Plan &p, const void *I, const float *E, int32_t *gen, hipStream_t s)
 {
     LeafArgs a = leaf_args(p, E);
     const int nb = (int)std::min<int64_t>((p.n_pleaf + 4 * kLPW - 1) / (4 * kLPW), 1024);
     double *partial = reinterpret_cast<double *>(p.d_scan_tmp);
     uint64_t *partial_key = reinterpret_cast<uint64_t *>(partial + 1024);
     if (p.precision == PH_FP64)
-        leaf_reduce_kernel<double><<<nb, 256, 0, s>>>(a, (const double *)I, partial, partial_key);
+        leaf_reduce_kernel<double><<<nb, 256, 0, s>>>(a, (const double *)I, partial, partial_key, gen);
     else
-        leaf_reduce_kernel<float><<<nb, 256, 0, s>>>(a, (const float *)I, partial, partial_key);
+        leaf_reduce_kernel<float><<<nb, 256, 0, s>>>(a, (const float *)I, partial, partial_key, gen);
     // the maxima over the workgroups' partials: reduced by each workgroup of the pick pass
 }
 
@@ -739,7 +745,7 @@ extern "C" ph_status ph_selector_features(ph_plan *plan, const void *I, const fl
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         PH_HIP(hipSetDevice(p.device));
         launch_reset_scalars(p.d_sc, nullptr, s);
-        selector_reduce(p, I, absE, s);
+        selector_reduce(p, I, absE, nullptr, s);
         selector_features(p, I, absE, s);
         int32_t nrow = 0;
         PH_HIP(hipMemcpyAsync(&nrow, &p.d_sc->n_srcleaf, 4, hipMemcpyDeviceToHost, s));

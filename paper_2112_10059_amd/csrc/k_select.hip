@@ -32,8 +32,10 @@ __global__ void reset_scalars_kernel(CallScalars *sc, int32_t *gen)
 // grid-stride share into partials, one block then reduces the partials (no contended atomics).
 template <class T>
 __global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restrict__ E, int64_t n,
-                                  double *__restrict__ partial, uint64_t *__restrict__ partial_key, CallScalars *sc)
+                                  double *__restrict__ partial, uint64_t *__restrict__ partial_key, CallScalars *sc,
+                                  int32_t *gen)
 {
+    if (blockIdx.x == 0 && gen) begin_call(sc, gen);
     __shared__ double smI[256];
     __shared__ uint64_t smE[256];
     double mi = 0.0;
@@ -58,9 +60,13 @@ __global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restri
         }
         __syncthreads();
     }
-    if (bad) atomicOr(&sc->err, 1);
+    __shared__ int anybad;
+    if (threadIdx.x == 0) anybad = 0;
+    __syncthreads();
+    if (bad) anybad = 1;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        partial[blockIdx.x] = smI[0];
+        partial[blockIdx.x] = mark_bad(smI[0], anybad != 0);
         partial_key[blockIdx.x] = smE[0];
     }
 }
@@ -72,10 +78,12 @@ __global__ void reduce_max_final_kernel(const double *__restrict__ partial, cons
     __shared__ uint64_t b[256];
     double mi = 0.0;
     uint64_t me = 0;
+    bool bad = false;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        mi = fmax(mi, partial[i]);
+        mi = fmax(mi, partial_max(partial[i], bad));
         me = max(me, partial_key[i]);
     }
+    if (bad) atomicOr(&sc->err, 1);
     a[threadIdx.x] = mi;
     b[threadIdx.x] = me;
     __syncthreads();
@@ -317,17 +325,17 @@ void launch_reduce_max_final(const double *partial, const uint64_t *partial_key,
 }
 
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n, CallScalars *sc,
-                       void *tmp, hipStream_t s)
+                       int32_t *gen, void *tmp, hipStream_t s)
 {
     int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
     double *partial = reinterpret_cast<double *>(tmp);
     uint64_t *partial_key = reinterpret_cast<uint64_t *>(partial + 1024);
     if (fp64)
         reduce_max_kernel<double><<<blocks, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, n, partial,
-                                                         partial_key, sc);
+                                                         partial_key, sc, gen);
     else
         reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, n, partial,
-                                                        partial_key, sc);
+                                                        partial_key, sc, gen);
     reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, blocks, sc);
 }
 

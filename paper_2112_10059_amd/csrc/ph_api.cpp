@@ -890,9 +890,9 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     const bool learned = p.selector == PH_SEL_LEARNED;
     p.cur_I = I;  // the target kernels read the own-cell term's intensity from it
     mark(0, s);
-    launch_reset_scalars(p.d_sc, p.d_gen, s);
-    if (learned) selector_reduce(p, I, absE, s);  // the maxima come with the per-leaf statistics
-    else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_scan_tmp, s);
+    // the first kernel clears the call's scalars and advances the call number
+    if (learned) selector_reduce(p, I, absE, p.d_gen, s);  // the maxima come with the per-leaf statistics
+    else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_gen, p.d_scan_tmp, s);
     mark(1, s);
     if (learned) selector_decide(p, I, absE, s);
     mark(2, s);

@@ -318,8 +318,10 @@ void launch_gather_sorted(const double *xyz, const double *w, const int32_t *per
 // selection (k_select.hip)
 // Clears the call's scalars; with gen, also advances the call number there and stores it in sc
 void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s);
+// maxima of I and |E| (partials, then one workgroup); with gen the first kernel also starts the
+// call (clears the scalars, advances the call number)
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
-                       CallScalars *sc, void *tmp /* >= 16 KiB */, hipStream_t s);
+                       CallScalars *sc, int32_t *gen, void *tmp /* >= 16 KiB */, hipStream_t s);
 void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
                              hipStream_t s);  // partials: up to 1024 blocks
 // selection flags, their scan (kept in d_flag for the tree build) and the compaction
@@ -355,7 +357,8 @@ void fmm_near(Plan &p, hipStream_t s);  // near field (P2P) of the targets of le
 void run_direct(Plan &p, void *S_out, hipStream_t s);
 
 // learned selector (k_mlp.hip)
-void selector_reduce(Plan &p, const void *I, const float *E, hipStream_t s);    // maxima + per-leaf statistics
+// maxima + per-leaf statistics; with gen its kernel also starts the call (see launch_reduce_max)
+void selector_reduce(Plan &p, const void *I, const float *E, int32_t *gen, hipStream_t s);
 void selector_features(Plan &p, const void *I, const float *E, hipStream_t s);  // rows, features (compacted)
 void selector_decide(Plan &p, const void *I, const float *E, hipStream_t s);    // features, network -> d_drop
 void launch_mlp_forward(const float *params, const float *X, int64_t m, const int32_t *m_dev, float *logits,
