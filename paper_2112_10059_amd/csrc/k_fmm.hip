@@ -330,8 +330,8 @@ __device__ __forceinline__ bool far_slice(const CallScalars *sc, int depth, uint
 constexpr int kFarMLeaves = 16;
 
 template <class TO>
-__global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__restrict__ S_out,
-                                                       const double *__restrict__ t_near, uint32_t level_mask)
+__device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, const double *__restrict__ t_near,
+                              uint32_t level_mask, int32_t bid)
 {
     __shared__ float Us[kFarMLeaves][65];  // U, then C = U G
     __shared__ int32_t lbox[kFarMLeaves], lt0[kFarMLeaves], loff[kFarMLeaves + 1];
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void far_mfma_kernel(FmmArgs<float> a, TO *__r
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int level;
     int32_t first;
-    if (!far_slice(a.sc, a.lt.depth, level_mask, kFarMLeaves, (int32_t)blockIdx.x, level, first)) return;
+    if (!far_slice(a.sc, a.lt.depth, level_mask, kFarMLeaves, bid, level, first)) return;
     const int32_t cnt = min(kFarMLeaves, a.sc->n_far_a_lvl[level] - first);
     const int nl = a.n_lam;
     const int gm = level >= 2 ? a.grid_m[level] : 0;  // 0: no far field at this level
@@ -709,19 +709,27 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
     far_shell_body<T, TO>(a, S_out, t_near, (int32_t)blockIdx.x, (int32_t)gridDim.x);
 }
 
-// Both in one launch (uniform grids): the first g_grid workgroups take the grid-operator leaves,
-// the others the shell-point leaves
+// The far field of every kind of grid leaf in one launch (uniform grids): the first g_mfma
+// workgroups take the matrix-core leaves (FP32), the next g_grid the other grid-operator
+// leaves, the rest the shell-point leaves
 template <class T, class TO, int NK>
 __global__ __launch_bounds__(256) void far_rest_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
                                                        const double *__restrict__ t_near, int stage_cap,
-                                                       uint32_t level_mask, int32_t g_grid)
+                                                       uint32_t level_mask, uint32_t mfma_mask, int32_t g_mfma,
+                                                       int32_t g_grid)
 {
     extern __shared__ __align__(16) unsigned char far_lds[];
-    if ((int32_t)blockIdx.x < g_grid)
-        far_grid_body<T, TO, NK>(a, S_out, t_near, stage_cap, level_mask, (int32_t)blockIdx.x, g_grid,
+    if ((int32_t)blockIdx.x < g_mfma) {
+        if constexpr (std::is_same<T, float>::value)
+            far_mfma_body<TO>(a, S_out, t_near, mfma_mask, (int32_t)blockIdx.x);
+        return;
+    }
+    const int32_t bid = (int32_t)blockIdx.x - g_mfma;
+    if (bid < g_grid)
+        far_grid_body<T, TO, NK>(a, S_out, t_near, stage_cap, level_mask, bid, g_grid,
                                  reinterpret_cast<T *>(far_lds));
     else
-        far_shell_body<T, TO>(a, S_out, t_near, (int32_t)blockIdx.x - g_grid, (int32_t)gridDim.x - g_grid);
+        far_shell_body<T, TO>(a, S_out, t_near, bid - g_grid, (int32_t)gridDim.x - g_mfma - g_grid);
 }
 
 // Exact near field (Sec. 2.4 eq. (16)) of the leaves with a U list, one workgroup of
@@ -931,33 +939,29 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
             if ((mfma_levels >> l) & 1u) gm_blocks += (p.level_cap[l] + kFarMLeaves - 1) / kFarMLeaves;
             if ((wave_levels >> l) & 1u) gw_blocks += (p.level_cap[l] + kFarLeaves - 1) / kFarLeaves;
         }
-        if (gm_blocks > 0 && std::is_same<T, float>::value)
-            far_mfma_kernel<float><<<(unsigned)gm_blocks, 256, 0, s>>>(*reinterpret_cast<FmmArgs<float> *>(&a),
-                                                                       (float *)S_out, p.d_t_near,
-                                                                       mfma_levels);
-        if (gw_blocks > 0) {
-            // LDS for the largest level operator that fits the staging cap
-            int cap = 0;
-            for (int l = 2; l <= p.max_depth; ++l) {
-                const int e = p.n_lam * p.grid_m[l] * p.grid_m[l] * p.grid_m[l];
-                if (((wave_levels >> l) & 1u) && p.grid_m[l] > 0 && e <= kGridStage) cap = std::max(cap, e);
-            }
-            const size_t lds = (size_t)cap * sizeof(T);
-            const int32_t g = (int32_t)std::min<int64_t>(gw_blocks, 256);
-            // on grids the shell list holds only leaves of levels >= 2 without an operator: its
-            // workgroups join this launch
-            bool shell_leaves = false;
-            for (int l = 2; l <= p.max_depth; ++l) shell_leaves = shell_leaves || p.grid_m[l] == 0;
-            const unsigned gt = (unsigned)(g + (shell_leaves ? (int32_t)std::min<int64_t>(B, 64) : 0));
-            switch ((p.n_lam + 63) / 64) {
-            case 1: far_rest_kernel<T, T, 1><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
-            case 2: far_rest_kernel<T, T, 2><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
-            case 3:
-            case 4: far_rest_kernel<T, T, 4><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
-            default: far_rest_kernel<T, T, 8><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, g); break;
-            }
-            return;
+        if (!std::is_same<T, float>::value) gm_blocks = 0;
+        // LDS for the largest wave-kernel level operator that fits the staging cap
+        int cap = 0;
+        for (int l = 2; l <= p.max_depth; ++l) {
+            const int e = p.n_lam * p.grid_m[l] * p.grid_m[l] * p.grid_m[l];
+            if (((wave_levels >> l) & 1u) && p.grid_m[l] > 0 && e <= kGridStage) cap = std::max(cap, e);
         }
+        const size_t lds = (size_t)cap * sizeof(T);
+        const int32_t gmb = (int32_t)gm_blocks;
+        const int32_t g = (int32_t)std::min<int64_t>(gw_blocks, 256);
+        // on grids the shell list holds only leaves of levels >= 2 without an operator
+        bool shell_leaves = false;
+        for (int l = 2; l <= p.max_depth; ++l) shell_leaves = shell_leaves || p.grid_m[l] == 0;
+        const unsigned gt = (unsigned)(gmb + g + (shell_leaves ? (int32_t)std::min<int64_t>(B, 64) : 0));
+        if (gt == 0) return;
+        switch ((p.n_lam + 63) / 64) {
+        case 1: far_rest_kernel<T, T, 1><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, mfma_levels, gmb, g); break;
+        case 2: far_rest_kernel<T, T, 2><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, mfma_levels, gmb, g); break;
+        case 3:
+        case 4: far_rest_kernel<T, T, 4><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, mfma_levels, gmb, g); break;
+        default: far_rest_kernel<T, T, 8><<<gt, 256, lds, s>>>(a, (T *)S_out, p.d_t_near, cap, wave_levels, mfma_levels, gmb, g); break;
+        }
+        return;
     }
     // point clouds (or grids without grid-operator leaves): the shell-point leaves alone
     bool shell_leaves = !p.grid_mode;

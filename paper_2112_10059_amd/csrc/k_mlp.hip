@@ -52,14 +52,34 @@ struct MlpLds {
 template <bool BF16>
 __device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
 {
-    // walk the LDS side in order (consecutive threads, consecutive banks)
-    for (int t = threadIdx.x; t < NH * NIN; t += blockDim.x) {
-        const int k = t / NH, u = t % NH;
-        L.w1t[t] = q<BF16>(params[OFF_W1 + u * NIN + k]);
+    // walk the LDS side in order (consecutive threads, consecutive banks); eight loads per thread
+    // in flight before their stores (one round trip per batch, not one per element)
+    constexpr int kB = 8;
+    for (int t0 = threadIdx.x; t0 < NH * NIN; t0 += kB * blockDim.x) {
+        float v[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int t = min(t0 + b * (int)blockDim.x, NH * NIN - 1);
+            v[b] = params[OFF_W1 + (t % NH) * NIN + t / NH];
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int t = t0 + b * (int)blockDim.x;
+            if (t < NH * NIN) L.w1t[t] = q<BF16>(v[b]);
+        }
     }
-    for (int t = threadIdx.x; t < NH * NH; t += blockDim.x) {
-        const int j = t / NH, u = t % NH;
-        L.w2t[t] = q<BF16>(params[OFF_W2 + u * NH + j]);
+    for (int t0 = threadIdx.x; t0 < NH * NH; t0 += kB * blockDim.x) {
+        float v[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int t = min(t0 + b * (int)blockDim.x, NH * NH - 1);
+            v[b] = params[OFF_W2 + (t % NH) * NH + t / NH];
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int t = t0 + b * (int)blockDim.x;
+            if (t < NH * NH) L.w2t[t] = q<BF16>(v[b]);
+        }
     }
     if (threadIdx.x < NH) {
         L.b1[threadIdx.x] = q<BF16>(params[OFF_B1 + threadIdx.x]);
