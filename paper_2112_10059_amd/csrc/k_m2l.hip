@@ -611,10 +611,11 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
 //   w_B = base + [first chunk: X-list sources of B] + sum over V(B) in this chunk of Y,
 // base = 0 in the first chunk, else the earlier chunks' sum; w_B is stored in u_B, and the L2L
 // product of the next level adds the parent's expansion to it.  V(B) = children of the
-// parent's colleagues not adjacent to B: the 8 x (colleagues with sources) candidates are
-// taken in 64-candidate slices (lane = candidate), the slice's translations compacted in
-// candidate order and read kB at a time (loads in flight together), added in candidate order.
-// A box's work is a chain of dependent loads, so a wave per box keeps many boxes in flight.
+// parent's colleagues not adjacent to B: the V-target pass stored each pair's translation code
+// at B's candidate slot 8 c + o (216 slots, tagged with the call's number), so the wave reads
+// the slots in 64-slot slices (lane = slot), compacts a slice's translations in candidate order
+// and reads them kB at a time (loads in flight together), added in candidate order.  A box's
+// work is a chain of dependent loads, so a wave per box keeps many boxes in flight.
 // The boxes: every box of level 2 and the listed boxes (V or X list) of the deeper levels in
 // gl.lo .. gl.hi, dealt to the workgroups as one flat range.
 struct GatherLevels {
@@ -626,10 +627,10 @@ template <class T, int NK>
 __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLevels gl, const T *__restrict__ Y0,
                                                          int M, int32_t r0, int32_t ccap, int init, int with_x)
 {
-    __shared__ int32_t qs[27];   // the parent's colleagues with sources
     __shared__ int32_t cds[64];  // a slice's translations
     const int lane = threadIdx.x & 63;
     const int nl = a.n_lam;
+    const int gen = a.sc->gen;  // this call's tag of the V-list slots
     constexpr int nk = NK;  // lattice values per lane: n_lam <= 64 NK
     for (int32_t idx = blockIdx.x;; idx += gridDim.x) {
         int level = -1;
@@ -652,7 +653,6 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
         for (int l = 0; l < kMaxDepth + 2; ++l)
             if (l == level) yrow = gl.y_row[l];
         const T *__restrict__ Y = Y0 + (size_t)yrow * M;
-        const int32_t par = a.bx.parent[b];
         T acc[NK];
         for (int k = 0; k < NK; ++k) acc[k] = T(0);
         unsigned long long n_m2l = 0, n_p2l = 0;
@@ -682,36 +682,23 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
                 }
             }
         }
-        // V list candidates: the children of the parent's colleagues, in candidate order
-        // (colleague d, child o); only colleagues holding sources are expanded
-        const int bx0 = a.bx.ax[b], by0 = a.bx.ay[b], bz0 = a.bx.az[b];
-        int32_t Qd = -1;
-        if (lane < 27) {
-            const int32_t Q = a.bx.coll[(size_t)par * 27 + lane];
-            if (Q >= 0 && a.bx.s_cnt[Q] > 0) Qd = Q;
+        // V list: the box's candidate slots (the children of the parent's colleagues, in
+        // candidate order), filled by this call's V-target pass, read in one sweep
+        const uint64_t *__restrict__ vs = a.L.vslot + (size_t)b * kVSlots;
+        uint64_t ve[(kVSlots + 63) / 64];
+#pragma unroll
+        for (int q = 0; q < (kVSlots + 63) / 64; ++q) {
+            const int j = 64 * q + lane;
+            ve[q] = j < kVSlots ? vs[j] : 0ull;
         }
-        const uint64_t qmask = __ballot(Qd >= 0);
-        const int nc = 8 * __popcll(qmask);
         const uint64_t below = (1ull << lane) - 1ull;
-        // the colleagues with sources, compacted in colleague order
-        if (Qd >= 0) qs[__popcll(qmask & below)] = Qd;
-        wave_lds_sync();
-        for (int f0 = 0; f0 < nc; f0 += 64) {
-            const int f = f0 + lane;
-            const bool valid = f < nc;
-            int32_t code = -1;  // rank * 316 + slot
-            if (valid) {
-                const int32_t Q = qs[f >> 3];  // the (f / 8)-th colleague with sources
-                const int32_t A = a.bx.child[(size_t)Q * 8 + (f & 7)];
-                if (A >= 0) {
-                    const int32_t sr = a.bx.src_rank[A];
-                    const int32_t rk = sr - r0;
-                    if (sr >= 0 && rk >= 0 && rk < ncols) {
-                        const int dx = a.bx.ax[A] - bx0, dy = a.bx.ay[A] - by0, dz = a.bx.az[A] - bz0;
-                        if (!(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1))
-                            code = rk * kNumM2L + m2l_slot(dx, dy, dz);
-                    }
-                }
+#pragma unroll
+        for (int q = 0; q < (kVSlots + 63) / 64; ++q) {
+            int32_t code = -1;  // rank * 316 + slot, chunk-relative
+            if ((uint32_t)(ve[q] >> 32) == (uint32_t)gen) {
+                const int32_t full = (int32_t)(uint32_t)ve[q];
+                const int32_t rk = full / kNumM2L - r0;
+                if (rk >= 0 && rk < ncols) code = rk * kNumM2L + full % kNumM2L;
             }
             // the slice's translations compacted in candidate order, then read kB at a time
             // (loads issued together, added in order)

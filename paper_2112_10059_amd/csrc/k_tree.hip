@@ -397,6 +397,12 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
                     if (!near) {
                         const int slot = m2l_slot(dx, dy, dz);
                         atomicOr(&use[wv][slot >> 5], 1u << (slot & 31));
+                        // B's V-list entry for S: candidate slot 8 c + o, c the index of S's parent
+                        // among B's parent's colleagues (the mirror of Q's index d among P's), o
+                        // S's octant
+                        const int o = ((sx & 1) << 2) | ((sy & 1) << 1) | (sz & 1);
+                        L.vslot[(size_t)B * kVSlots + (26 - d) * 8 + o] =
+                            ((uint64_t)(uint32_t)gen << 32) | (uint32_t)(r * kNumM2L + slot);
                         fresh = level >= 3 && atomicExch(&L.vt_tag[B], gen) != gen;
                     }
                 }

@@ -265,6 +265,8 @@ void alloc_workspace(Plan &p)
     }
     L.m2l_tile_use = (uint32_t *)dev_alloc(p, (size_t)std::max(p.m2l_tiles, 1) * kUseWords * 4);
     L.m2l_box_use = (uint32_t *)dev_alloc(p, (size_t)B * kUseWords * 4);
+    L.vslot = (uint64_t *)dev_alloc(p, (size_t)B * kVSlots * 8);
+    PH_HIP(hipMemset(L.vslot, 0, (size_t)B * kVSlots * 8));  // no call has tagged a slot yet
     PH_HIP(hipMemset(L.vt_tag, 0, B * 4));  // no call has tagged a box yet
     if (p.method == PH_METHOD_FMM) {
         p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
@@ -325,7 +327,7 @@ void free_plan(Plan *p)
                     p->box.child, p->box.coll, p->box.start, p->box.end, p->box.src_rank, p->box.tpar_box, p->d_z,
                     p->box.src_box, p->d_y, p->lists.u_rng,
                     p->lists.w_rng, p->lists.x_rng, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
-                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_tile_use, p->lists.m2l_box_use, p->d_phi, p->d_u,
+                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_tile_use, p->lists.m2l_box_use, p->lists.vslot, p->d_phi, p->d_u,
                     p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
                     p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
                     p->d_row_feat,

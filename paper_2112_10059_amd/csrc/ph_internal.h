@@ -109,7 +109,13 @@ struct Lists {
     // the same per source box (at the box's slot in the level's source list), so that the
     // products store only the columns some target reads
     uint32_t *m2l_box_use = nullptr;
+    // per target box, its V list as translation codes (source rank * 316 + offset slot) at fixed
+    // candidate slots: 8 c + o for the source box in octant o of the c-th colleague of the box's
+    // parent (216 per box), each tagged with the number of the call that wrote it (high word)
+    uint64_t *vslot = nullptr;
 };
+
+constexpr int kVSlots = 216;
 
 struct Gas {
     double a, b, L, P;   // chi_min pO2, chi_max pO2, ln(chi_max/chi_min), prefactor
