@@ -69,45 +69,27 @@ def parse():
 
 
 def time_steps(plan, I, E, steps, warmup, torch, host=None):
-    """ms per call over `steps` calls (no per-phase events), launched eagerly and replayed as one
-    HIP graph per call: the faster of the two is the result (host["launch"] says which), then
-    the per-phase times over as many eager calls again with the phase events on.  host (a dict,
-    optional) receives the host time per call spent enqueueing the timed calls and both
-    launch modes' figures."""
+    """ms per call over `steps` eagerly launched calls (no per-phase events), then the per-phase
+    times over as many calls again with the phase events on.  host (a dict, optional) receives
+    the host time per call spent enqueueing the timed calls."""
     out = torch.empty(plan.n, dtype=plan.dtype, device="cuda")
-
-    def timed_loop():
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record()
-        h0 = time.perf_counter()
-        for _ in range(steps):
-            plan.evaluate(I, E, out=out)
-        h1 = time.perf_counter()
-        t1.record()
-        torch.cuda.synchronize()
-        return t0.elapsed_time(t1) / steps, (h1 - h0) * 1e3 / steps
-
     plan.phase_times(record=0)
     for _ in range(warmup):
         plan.evaluate(I, E, out=out)
     torch.cuda.synchronize()
-    ms_eager, enq_eager = timed_loop()
-    plan.set_graph(True)
-    for _ in range(max(warmup, 1)):  # the first call captures the graph
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    h0 = time.perf_counter()
+    for _ in range(steps):
         plan.evaluate(I, E, out=out)
+    h1 = time.perf_counter()
+    t1.record()
     torch.cuda.synchronize()
-    ms_graph, enq_graph = timed_loop()
-    plan.set_graph(False)
-    graph = ms_graph < ms_eager
-    ms, enq = (ms_graph, enq_graph) if graph else (ms_eager, enq_eager)
+    ms = t0.elapsed_time(t1) / steps
     if host is not None:
-        host["launch"] = "graph" if graph else "eager"
-        host["enqueue_ms_per_call"] = enq
-        host["eager_ms_per_step"] = ms_eager
-        host["eager_enqueue_ms_per_call"] = enq_eager
-        host["graph_ms_per_step"] = ms_graph
-        host["graph_enqueue_ms_per_call"] = enq_graph
+        host["launch"] = "eager"
+        host["enqueue_ms_per_call"] = (h1 - h0) * 1e3 / steps
     plan.phase_times(record=1)  # discard, start recording
     for _ in range(steps):
         plan.evaluate(I, E, out=out)
@@ -166,10 +148,8 @@ def main():
     S, ms, phases = time_steps(plan, I, E, args.steps, args.warmup, torch, host=host)
     n_tgt = st["n_tgt"]
     value = n_tgt / (ms * 1e-3)
-    log(f"learned fp32: {ms:.4f} ms/step ({host['launch']}; eager {host['eager_ms_per_step']:.4f} ms/step host "
-        f"{host['eager_enqueue_ms_per_call']:.4f}, graph {host['graph_ms_per_step']:.4f} host {host['graph_enqueue_ms_per_call']:.4f}), "
-        f"{value:.4e} targets/s; host enqueue {host['enqueue_ms_per_call']:.4f} "
-        f"ms/call; phases {phases}")
+    log(f"learned fp32: {ms:.4f} ms/step ({host['launch']}), {value:.4e} targets/s; host enqueue "
+        f"{host['enqueue_ms_per_call']:.4f} ms/call; phases {phases}")
     roof = roofline(phases, st)
     perm = plan.debug_fetch("perm")
     smask = np.zeros(wl.n, dtype=bool)
@@ -252,11 +232,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms,
         "host_enqueue_ms_per_call": host["enqueue_ms_per_call"],
-        "launch": host["launch"] + " (the faster of eager launches and one replayed HIP graph per call)",
-        "eager_ms_per_step": host["eager_ms_per_step"],
-        "eager_host_enqueue_ms_per_call": host["eager_enqueue_ms_per_call"],
-        "graph_ms_per_step": host["graph_ms_per_step"],
-        "graph_host_enqueue_ms_per_call": host["graph_enqueue_ms_per_call"],
+        "launch": host["launch"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

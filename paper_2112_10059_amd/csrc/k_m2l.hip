@@ -402,8 +402,8 @@ __global__ __launch_bounds__(256) void m2l_pipe_kernel(const float *__restrict__
 struct CompArgs {
     const float *ops;
     const int32_t *map;  // boxes by level and coordinates
-    int64_t map_off[kMaxDepth + 2];
-    int64_t off[kMaxDepth + 2][kMaxDepth + 2];
+    int64_t map_off[kCompMaxDepth + 1];
+    int64_t off[kCompMaxDepth + 1][kCompMaxDepth + 1];  // levels up to kCompMaxDepth only
     int depth;
 };
 
@@ -846,9 +846,10 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
         CompArgs ca{};
         ca.ops = (const float *)p.ops.l2l_comp;
         ca.map = p.d_boxmap;
-        for (int l = 0; l < kMaxDepth + 2; ++l) {
+        if (D > kCompMaxDepth) throw Error{PH_EINVAL, "composite translations built for a deeper tree"};
+        for (int l = 0; l <= kCompMaxDepth; ++l) {
             ca.map_off[l] = p.boxmap_off[l];
-            for (int k = 0; k < kMaxDepth + 2; ++k) ca.off[l][k] = p.comp_off[l][k];
+            for (int k = 0; k <= kCompMaxDepth; ++k) ca.off[l][k] = p.comp_off[l][k];
         }
         ca.depth = D;
         int64_t classes = 0;

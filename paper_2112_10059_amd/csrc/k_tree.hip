@@ -267,80 +267,169 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t n, int32_t *counter)
     return lane_value(base, 63) + incl - n;
 }
 
-// The interaction lists of every box in one pass: a thread per box enumerates its lists to
-// count them, reserves each list's space (one atomic per wave and list), stores its ranges and
-// enumerates again to write the entries (the second pass reads what the first brought into
-// the caches).  Also the leaf lists of the target-side kernels.  grid_levels: bit l set when
-// leaves of level l take their far field from a grid operator (or have none).
+// The interaction lists of every box in one pass.  A workgroup takes 64 boxes; each half wave
+// resolves 8 of them with one lane per colleague (lane c < 27: colleague c), all their loads
+// issued together.  A leaf with targets whose colleagues with sources are all leaves, and whose
+// level needs no look at coarser leaves (the common case), has only a U list: those colleagues
+// in colleague order, written from the lanes.  Any other box with targets is enumerated by one
+// lane of its half (descents into split colleagues, coarser leaves around the ancestors),
+// counting first and writing after the reservation.  Wave 0 then reserves the workgroup's
+// space (one atomic per list) and enters its boxes into the leaf lists of the target-side
+// kernels (one atomic per list), a box per lane.  Each box stores its ranges.  grid_levels:
+// bit l set when leaves of level l take their far field from a grid operator (or have none).
+constexpr int kLBoxes = 64;               // boxes per workgroup
+constexpr int kLPer = kLBoxes / 8;        // boxes per half wave
+
 __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, LevelInfo li,
                                                                 CallScalars *__restrict__ sc, int32_t nbox, Lists L,
                                                                 uint32_t grid_levels)
 {
+    static_assert(kListBlock == 256, "eight half waves");
+    __shared__ int32_t sbox[kLBoxes], slev[kLBoxes];
+    __shared__ uint32_t su[kLBoxes], sw[kLBoxes], sx[kLBoxes];     // counts, then first entries
+    __shared__ uint32_t sumask[kLBoxes];                           // U colleagues (simple boxes)
+    __shared__ uint8_t sser[kLBoxes], sleaf[kLBoxes];
     const int gen = sc->gen;
-    const int32_t gid0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = gid0 < nbox;
-    const int32_t gid = in ? gid0 : nbox - 1;  // whole waves reach the reservations
-    const int32_t b = in ? box_of_thread(li, sc, gid) : -1;
-    uint32_t nu = 0, nw = 0, nx = 0;
+    const int t = threadIdx.x, lane = t & 63, half = lane >> 5, hl = lane & 31;
+    const int hw = t >> 5;  // half wave 0..7
     const int mll = li.depth + 1 - sc->min_leafsrc_level;
-    if (b >= 0)
-        enumerate_lists(bx, b, mll, [&](int kind, int32_t) {
+    const int32_t g0 = (int32_t)blockIdx.x * kLBoxes;
+    // the half's boxes, their colleagues and the colleagues' counts, each set of loads together
+    int32_t bq[kLPer], C[kLPer];
+    int32_t lv[kLPer];
+    bool tg[kLPer], lf[kLPer];
+#pragma unroll
+    for (int i = 0; i < kLPer; ++i) {
+        const int32_t gid = g0 + hw * kLPer + i;
+        bq[i] = gid < nbox ? box_of_thread(li, sc, gid) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < kLPer; ++i) {
+        const int32_t b = bq[i];
+        tg[i] = b >= 0 && bx.t_cnt[b] > 0;
+        const int32_t fl = b >= 0 ? bx.flags[b] : 0;
+        lv[i] = b >= 0 ? bx.level[b] : 0;
+        lf[i] = tg[i] && (fl & kBoxLeaf);
+    }
+#pragma unroll
+    for (int i = 0; i < kLPer; ++i) C[i] = (lf[i] && hl < 27) ? bx.coll[(size_t)bq[i] * 27 + hl] : -1;
+    uint32_t um[kLPer], sm[kLPer];
+#pragma unroll
+    for (int i = 0; i < kLPer; ++i) {
+        bool isu = false, iss = false;
+        if (C[i] >= 0) {
+            const int32_t sn = bx.s_cnt[C[i]], cf = bx.flags[C[i]];
+            isu = sn > 0 && (cf & kBoxLeaf);
+            iss = sn > 0 && !(cf & kBoxLeaf);
+        }
+        um[i] = (uint32_t)(__ballot(isu) >> (32 * half));
+        sm[i] = (uint32_t)(__ballot(iss) >> (32 * half));
+    }
+    // the half's boxes to LDS (lane i for box i)
+#pragma unroll
+    for (int i = 0; i < kLPer; ++i) {
+        if (hl == i) {
+            const int j = hw * kLPer + i;
+            const bool ser = tg[i] && (sm[i] != 0 || lv[i] > mll);
+            sbox[j] = bq[i];
+            slev[j] = lv[i];
+            su[j] = ser ? 0u : (uint32_t)__popc(um[i]);
+            sw[j] = 0;
+            sx[j] = 0;
+            sumask[j] = um[i];
+            sser[j] = ser;
+            sleaf[j] = lf[i];
+        }
+    }
+    __syncthreads();
+    // boxes that need the full enumeration: counted by lane i of the half for its box i
+    const int jm = hw * kLPer + (hl & (kLPer - 1));
+    const bool my_ser = hl < kLPer && sser[jm];
+    if (my_ser) {
+        uint32_t nu = 0, nw = 0, nx = 0;
+        enumerate_lists(bx, sbox[jm], mll, [&](int kind, int32_t) {
             if (kind == kListU) ++nu;
             else if (kind == kListW) ++nw;
             else ++nx;
         });
-    const uint32_t ub = wave_reserve(nu, &sc->n_u);
-    const uint32_t wb = wave_reserve(nw, &sc->n_w);
-    const uint32_t xb = wave_reserve(nx, &sc->n_x);
-    if (in) {
-        L.u_rng[gid] = make_uint2(ub, ub + nu);
-        L.w_rng[gid] = make_uint2(wb, wb + nw);
-        L.x_rng[gid] = make_uint2(xb, xb + nx);
+        su[jm] = nu;
+        sw[jm] = nw;
+        sx[jm] = nx;
     }
-    if (b >= 0 && (nu | nw | nx)) {
-        uint32_t pu = ub, pw = wb, px = xb;
+    __syncthreads();
+    // wave 0: the workgroup's space, a box per lane (one atomic per list)
+    if (t < kLBoxes) {
+        const uint32_t nu = su[t], nw = sw[t], nx = sx[t];
+        const uint32_t ub = wave_reserve(nu, &sc->n_u);
+        const uint32_t wb = wave_reserve(nw, &sc->n_w);
+        const uint32_t xb = wave_reserve(nx, &sc->n_x);
+        const int32_t gid = g0 + t;
+        if (gid < nbox) {
+            L.u_rng[gid] = make_uint2(ub, ub + nu);
+            L.w_rng[gid] = make_uint2(wb, wb + nw);
+            L.x_rng[gid] = make_uint2(xb, xb + nx);
+        }
+        su[t] = ub;  // first entries from here on
+        sw[t] = wb;
+        sx[t] = xb;
+        // the box's entries in the target-side lists
+        const int32_t b = sbox[t];
+        const int lev = slev[t];
+        const bool tleaf = sleaf[t] != 0;
+        const bool grid_leaf = tleaf && ((grid_levels >> lev) & 1u);
+        // grid-operator leaves go to their level's segment (a wave rarely spans two levels)
+        uint64_t pending = __ballot(grid_leaf);
+        // the leaf's points in sorted order (its targets are those with the target flag)
+        const int4 entry = make_int4(b, b >= 0 ? bx.start[b] : 0, b >= 0 ? bx.end[b] - bx.start[b] : 0,
+                                     (nu > 0 ? 1 : 0) | (nw > 0 ? 2 : 0));
+        while (pending) {
+            const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
+            const bool mine = grid_leaf && lev == l0;
+            wave_append(mine, L.far_a + li.base[l0], &sc->n_far_a_lvl[l0], entry);
+            pending &= ~__ballot(mine);
+        }
+        wave_append(tleaf && !grid_leaf, L.far_b, &sc->n_far_b, b);
+        wave_append(tleaf && nu > 0, L.near_leaves, &sc->n_near, b);
+        // boxes of levels >= 3 with an X list join their level's V/X target segment
+        const bool xbox = nx > 0 && lev >= 3 && atomicExch(&L.vt_tag[b], gen) != gen;
+        pending = __ballot(xbox);
+        while (pending) {
+            const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
+            const bool mine = xbox && lev == l0;
+            wave_append(mine, L.vt + li.base[l0], &sc->n_vt_lvl[l0], b);
+            pending &= ~__ballot(mine);
+        }
+    }
+    __syncthreads();
+    // the entries: enumerated boxes by lane i of the half, simple boxes from the colleague lanes
+    if (my_ser) {
+        uint32_t pu = su[jm], pw = sw[jm], px = sx[jm];
         bool over = false;
-        enumerate_lists(bx, b, mll, [&](int kind, int32_t C) {
+        enumerate_lists(bx, sbox[jm], mll, [&](int kind, int32_t E) {
             if (kind == kListU) {
-                if (pu < (uint32_t)L.u_cap) L.u[pu] = C;
+                if (pu < (uint32_t)L.u_cap) L.u[pu] = E;
                 else over = true;
                 ++pu;
             } else if (kind == kListW) {
-                if (pw < (uint32_t)L.w_cap) L.w[pw] = C;
+                if (pw < (uint32_t)L.w_cap) L.w[pw] = E;
                 else over = true;
                 ++pw;
             } else {
-                if (px < (uint32_t)L.x_cap) L.x[px] = C;
+                if (px < (uint32_t)L.x_cap) L.x[px] = E;
                 else over = true;
                 ++px;
             }
         });
         if (over) atomicOr(&sc->err, 2);
     }
-    const bool tleaf = b >= 0 && (bx.flags[b] & kBoxLeaf) && bx.t_cnt[b] > 0;
-    const int lev = b >= 0 ? bx.level[b] : 0;
-    const bool grid_leaf = tleaf && ((grid_levels >> lev) & 1u);
-    // grid-operator leaves go to their level's segment (a wave rarely spans two levels)
-    uint64_t pending = __ballot(grid_leaf);
-    // the leaf's points in sorted order (its targets are those with the target flag)
-    const int4 entry = make_int4(b, b >= 0 ? bx.start[b] : 0, b >= 0 ? bx.end[b] - bx.start[b] : 0,
-                                 (nu > 0 ? 1 : 0) | (nw > 0 ? 2 : 0));
-    while (pending) {
-        const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
-        const bool mine = grid_leaf && lev == l0;
-        wave_append(mine, L.far_a + li.base[l0], &sc->n_far_a_lvl[l0], entry);
-        pending &= ~__ballot(mine);
-    }
-    wave_append(tleaf && !grid_leaf, L.far_b, &sc->n_far_b, b);
-    wave_append(tleaf && nu > 0, L.near_leaves, &sc->n_near, b);
-    // boxes of levels >= 3 with an X list join their level's V/X target segment
-    const bool xbox = nx > 0 && lev >= 3 && atomicExch(&L.vt_tag[b], gen) != gen;
-    pending = __ballot(xbox);
-    while (pending) {
-        const int l0 = __shfl(lev, __ffsll((long long)pending) - 1);
-        const bool mine = xbox && lev == l0;
-        wave_append(mine, L.vt + li.base[l0], &sc->n_vt_lvl[l0], b);
-        pending &= ~__ballot(mine);
+#pragma unroll
+    for (int i = 0; i < kLPer; ++i) {
+        const int j = hw * kLPer + i;
+        if (!sser[j] && hl < 27 && ((sumask[j] >> hl) & 1u)) {
+            const uint32_t pos = su[j] + __popc(sumask[j] & ((1u << hl) - 1u));
+            if (pos < (uint32_t)L.u_cap) L.u[pos] = C[i];
+            else atomicOr(&sc->err, 2);
+        }
     }
 }
 
@@ -458,7 +547,7 @@ void build_lists(Plan &p, hipStream_t s)
 {
     LevelInfo li = level_info(p);
     const int32_t nbox = (int32_t)p.box_cap;
-    const unsigned g = (unsigned)((nbox + 255) / 256);
+    const unsigned g = (unsigned)((nbox + kLBoxes - 1) / kLBoxes);
     uint32_t grid_levels = 0;
     if (p.grid_mode)
         for (int l = 0; l <= p.max_depth; ++l)
