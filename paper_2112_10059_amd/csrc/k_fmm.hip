@@ -745,6 +745,7 @@ __global__ __launch_bounds__(256) void far_rest_kernel(FmmArgs<T> a, TO *__restr
 // the own-cell term.  The kernel reads only the tree and the lists, so it can run beside
 // the upward and downward passes.
 constexpr int kNearWaves = 4;
+constexpr int32_t kNearTabMark = 0x7fc0dab5;  // a NaN pattern: the staged source is read from the table
 
 template <class T, bool GUARD>
 __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, double *__restrict__ t_near)
@@ -752,9 +753,10 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
     constexpr int kNB = sizeof(T) == 4 ? 2 : 1;  // items staged together per wave
     __shared__ double part[kNearWaves][64];
     __shared__ V4<T> ysh[kNearWaves][kNB][64];  // per wave: the current items' sources
-    __shared__ int32_t esf[64], esn[64];          // a chunk of the U list: source ranges
+    __shared__ int32_t esf[64], esn[64];          // a chunk of the U list: first sources, run offsets
     __shared__ uint8_t etab[64];                  // and whether the table serves the entry
-    extern __shared__ float ntab[];              // the near-field kernel table, when present
+    __shared__ int32_t ecnt;                      // the chunk's sources
+    extern __shared__ __align__(16) float ntab[];  // the near-field kernel table, when present
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t n = a.sc->n_near;
     if ((int32_t)blockIdx.x >= n) return;  // the whole workgroup
@@ -762,15 +764,32 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
     // table at the integer cell offset instead of being evaluated
     const bool tab = sizeof(T) == 4 && a.near_tab != nullptr;
     const int TR = a.near_R, sx = a.near_sx, sy = a.near_sy, sz = a.near_sz, TN = a.near_n;
+    // the table's loads (float4, zero padded) all issued before the first leaf's, and written to
+    // LDS once they have arrived (the chunk staging's barrier publishes them)
+    constexpr int kTabV = (kNearTabMax + 4 * 64 * kNearWaves - 1) / (4 * 64 * kNearWaves);
+    const int TN4 = (TN + 3) >> 2;
+    float4 tv[kTabV];
     if (tab) {
-        for (int i = threadIdx.x; i < TN; i += blockDim.x) ntab[i] = a.near_tab[i];
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTabV; ++u) {
+            const int i4 = (int)threadIdx.x + u * 64 * kNearWaves;
+            tv[u] = i4 < TN4 ? reinterpret_cast<const float4 *>(a.near_tab)[i4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
     }
+    bool staged = !tab;
     for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
         const int32_t b = a.L.near_leaves[idx];
         const uint32_t u0 = a.L.u_rng[b].x, u1 = a.L.u_rng[b].y;
         const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0;
         const bool tab_b = tab && a.bx.level[b] == a.near_level;
+        if (!staged) {
+#pragma unroll
+            for (int u = 0; u < kTabV; ++u) {
+                const int i4 = (int)threadIdx.x + u * 64 * kNearWaves;
+                if (i4 < TN4) reinterpret_cast<float4 *>(ntab)[i4] = tv[u];
+            }
+            staged = true;
+        }
         // the leaf's points in sorted order, the targets among them flagged
         for (int tb = 0; tb < np; tb += 64) {
             const int t = tb + lane;
@@ -787,75 +806,85 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
                 tl = ((c & 1023) + TR) * sx + (((c >> 10) & 1023) + TR) * sy + ((c >> 20) + TR) * sz;
             }
             Acc<T> near;
-            // the U list a chunk of 64 entries at a time: the entries' source ranges (and whether
-            // the table serves them) are read in parallel into LDS, then each wave walks the
-            // chunk there, taking every kNearWaves-th item in list order, kNB at a time (their
-            // source loads issued together)
-            int item = 0;
+            // the U list a chunk of 64 entries at a time: the entries' source ranges (whether
+            // the table serves them, and where each starts in the chunk's run of sources) are
+            // read in parallel into LDS; the chunk's sources, packed 64 to a batch across entry
+            // boundaries, are then shared out to the waves batch by batch, kNB batches at a time
+            // (their source loads issued together)
             for (uint32_t c0 = u0; c0 < u1; c0 += 64) {
                 const int ne = (int)min(64u, u1 - c0);
                 __syncthreads();  // every wave is done with the previous chunk
-                if ((int)threadIdx.x < ne) {
-                    const int32_t C = a.L.u[c0 + threadIdx.x];
-                    esf[threadIdx.x] = a.bx.s_first[C];
-                    esn[threadIdx.x] = a.bx.s_cnt[C];
-                    etab[threadIdx.x] = tab_b && a.bx.level[C] == a.near_level;
+                if (w == 0) {
+                    int32_t sf = 0, sn = 0;
+                    uint8_t et = 0;
+                    if (lane < ne) {
+                        const int32_t C = a.L.u[c0 + lane];
+                        sf = a.bx.s_first[C];
+                        sn = a.bx.s_cnt[C];
+                        et = tab_b && a.bx.level[C] == a.near_level;
+                    }
+                    const int32_t incl = wave_inclusive(sn, lane);
+                    esf[lane] = sf;
+                    esn[lane] = incl - sn;  // the entry's first position in the run
+                    etab[lane] = et;
+                    if (lane == 63) ecnt = incl;
                 }
                 __syncthreads();
-                int e = 0, base = 0;
-                while (true) {
-                    int32_t isf[kNB];
-                    int im[kNB];
-                    bool itab[kNB];
-                    int nb = 0;
-                    while (nb < kNB && e < ne) {
-                        const int32_t sn = esn[e];
-                        if (item % kNearWaves == w) {
-#pragma unroll
-                            for (int q = 0; q < kNB; ++q)
-                                if (q == nb) {
-                                    isf[q] = esf[e] + base;
-                                    im[q] = min(64, sn - base);
-                                    itab[q] = etab[e] != 0;
-                                }
-                            ++nb;
-                        }
-                        ++item;
-                        base += 64;
-                        if (base >= sn) {  // next entry (every entry holds sources)
-                            base = 0;
-                            ++e;
-                        }
-                    }
-                    if (nb == 0) break;
-                    // staged per source: its position and weight, or (table items) the linear
-                    // index of its cell in the table's strides and its weight, two sources to 16
-                    // bytes (lanes past the item's end stage a zero weight)
+                const int32_t S = ecnt, nbat = (S + 63) >> 6;
+                for (int b0 = w; b0 < nbat; b0 += kNearWaves * kNB) {
+                    int cnt[kNB];
+                    uint8_t kind[kNB];  // 0 direct, 1 table, 2 both (a branch per source)
 #pragma unroll
                     for (int q = 0; q < kNB; ++q) {
-                        if (q >= nb) break;
-                        if (itab[q]) {
+                        const int bi = b0 + q * kNearWaves;
+                        cnt[q] = bi < nbat ? min(64, S - bi * 64) : 0;
+                        const int32_t sp = bi * 64 + lane;  // the lane's source in the run
+                        const bool live = lane < cnt[q];
+                        // the entry holding it: the last one starting at or before it (every
+                        // entry holds at least one source)
+                        int e = 0;
+#pragma unroll
+                        for (int st = 32; st > 0; st >>= 1)
+                            if (e + st < ne && esn[e + st] <= sp) e += st;
+                        const int32_t src = esf[e] + (sp - esn[e]);
+                        const bool st = sizeof(T) == 4 && live && etab[e];
+                        const uint64_t m_live = __ballot(live), m_tab = __ballot(st);
+                        kind[q] = m_tab == 0 ? 0 : (m_tab == m_live ? 1 : 2);
+                        if (kind[q] == 1) {
+                            // table sources only: the linear index of the cell in the table's
+                            // strides and the weight, two sources to 16 bytes (lanes past the
+                            // batch stage a zero weight)
                             float2 y2 = make_float2(0.f, 0.f);
-                            if (lane < im[q]) {
-                                const int32_t c = a.s_cell[isf[q] + lane];
+                            if (live) {
+                                const int32_t c = a.s_cell[src];
                                 y2.x = __int_as_float((c & 1023) * sx + ((c >> 10) & 1023) * sy + (c >> 20) * sz);
-                                y2.y = (float)a.s_dat[isf[q] + lane].w;
+                                y2.y = (float)a.s_dat[src].w;
                             }
                             reinterpret_cast<float2 *>(&ysh[w][q][0])[lane] = y2;
-                        } else if (lane < im[q]) {
-                            ysh[w][q][lane] = a.s_dat[isf[q] + lane];
+                        } else if (live) {
+                            if (st) {
+                                // a table source among others: index, weight and the table mark
+                                const int32_t c = a.s_cell[src];
+                                V4<T> y;
+                                y.x = __int_as_float((c & 1023) * sx + ((c >> 10) & 1023) * sy + (c >> 20) * sz);
+                                y.y = a.s_dat[src].w;
+                                y.z = __int_as_float(kNearTabMark);
+                                y.w = T(0);
+                                ysh[w][q][lane] = y;
+                            } else {
+                                ysh[w][q][lane] = a.s_dat[src];
+                            }
                         }
                     }
                     wave_lds_sync();
 #pragma unroll
                     for (int q = 0; q < kNB; ++q) {
-                        if (q >= nb) break;
-                        // the item's terms in a plain sum (at most 64), added to the compensated total
+                        // the batch's terms in a plain sum (at most 64), added to the compensated total
                         T blk = T(0);
-                        if (sizeof(T) == 4 && itab[q]) {
+                        if (sizeof(T) == 4 && kind[q] == 1) {
                             const float4 *y4 = reinterpret_cast<const float4 *>(&ysh[w][q][0]);
 #pragma unroll 4
-                            for (int j = 0; j < (im[q] + 1) / 2; ++j) {
+                            for (int j = 0; j < (cnt[q] + 1) / 2; ++j) {
                                 const float4 y = y4[j];  // two sources, a broadcast read
                                 // adjacent leaves keep the offsets inside the table; the clamp
                                 // keeps every read inside it regardless
@@ -864,19 +893,32 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
                                 blk += (T)ntab[i0] * (T)y.y;
                                 blk += (T)ntab[i1] * (T)y.w;
                             }
-                        } else {
+                        } else if (kind[q] == 0) {
 #pragma unroll 8
-                            for (int j = 0; j < im[q]; ++j) {
+                            for (int j = 0; j < cnt[q]; ++j) {
                                 const V4<T> y = ysh[w][q][j];  // one address for the wave: a broadcast read
                                 const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
                                 const T r2 = dx * dx + dy * dy + dz * dz;
                                 const T v = kernel_eval<GUARD>(r2, a.kp) * y.w;
                                 blk += r2 > T(0) ? v : T(0);
                             }
+                        } else {
+                            for (int j = 0; j < cnt[q]; ++j) {
+                                const V4<T> y = ysh[w][q][j];
+                                if (__float_as_int((float)y.z) == kNearTabMark) {
+                                    const int i0 = min(max(tl - __float_as_int((float)y.x), 0), TN - 1);
+                                    blk += (T)ntab[i0] * y.y;
+                                } else {
+                                    const T dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+                                    const T r2 = dx * dx + dy * dy + dz * dz;
+                                    const T v = kernel_eval<GUARD>(r2, a.kp) * y.w;
+                                    blk += r2 > T(0) ? v : T(0);
+                                }
+                            }
                         }
-                        near.add(blk);
+                        if (cnt[q] > 0) near.add(blk);
                     }
-                    wave_lds_sync();  // the items' sources have been read
+                    wave_lds_sync();  // the batches' sources have been read
                 }
             }
             __syncthreads();  // the previous pass's partial sums have been read
@@ -978,7 +1020,9 @@ void fmm_near_t(Plan &p, hipStream_t s)
     // at most four workgroups (16 waves) per CU: the upward and downward passes run beside this
     // kernel on the other stream, and a full grid would hold every wave slot until it drains
     const unsigned g = (unsigned)std::min<int64_t>(p.box_cap, 1024);
-    const size_t lds = (std::is_same<T, float>::value && p.ops.near_tab) ? (size_t)p.ops.near_n * sizeof(float) : 0;
+    // the table is stored padded with zeros to a whole number of float4
+    const size_t lds =
+        (std::is_same<T, float>::value && p.ops.near_tab) ? (size_t)((p.ops.near_n + 3) & ~3) * sizeof(float) : 0;
     if (p.near_guard) near_kernel<T, true><<<g, 64 * kNearWaves, lds, s>>>(a, p.d_t_near);
     else near_kernel<T, false><<<g, 64 * kNearWaves, lds, s>>>(a, p.d_t_near);
 }

@@ -673,7 +673,9 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
                 if (n_tab <= kNearTabMax) {
                     std::vector<double> tab;
                     build_near_table(p.gas, p.h, R, sx, sy, sz, n_tab, tab);
-                    upload(p, &p.ops.near_tab, convert<float>(tab));
+                    std::vector<float> tf = convert<float>(tab);
+                    tf.resize((tf.size() + 3) & ~(size_t)3, 0.0f);  // whole float4 for the kernel's loads
+                    upload(p, &p.ops.near_tab, tf);
                     p.ops.near_R = R;
                     p.ops.near_level = D;
                     p.ops.near_sx = sx;
