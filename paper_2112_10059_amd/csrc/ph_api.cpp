@@ -770,18 +770,21 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     for (auto &set : p.ring)
         for (auto &e : set) PH_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     p.events_ready = true;
-    // second stream (default priority) and its ordering events
+    // second and third streams (default priority) and their ordering events.  The events order
+    // kernels of one device only: every kernel's completion already makes its writes visible to
+    // later kernels on the device, so a record needs no system-scope fence (host visibility)
+    constexpr unsigned kSyncEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
     PH_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     PH_HIP(hipStreamCreateWithFlags(&p.side2, hipStreamNonBlocking));
     PH_HIP(hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_p2m, hipEventDisableTiming));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_m2l, hipEventDisableTiming));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_lists, hipEventDisableTiming));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_down, hipEventDisableTiming));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_vt, hipEventDisableTiming));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_rest, hipEventDisableTiming));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_p2m, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_m2l, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_fork, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_join, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_lists, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_down, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_vt, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_rest, kSyncEventFlags));
 }
 
 }  // namespace ph
