@@ -792,16 +792,18 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
 }
 
 template <class T>
-void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready, hipEvent_t deep_m2l)
+void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int nl = p.n_lam;
     const int M = kNumM2L * nl;
     const int D = p.max_depth;
     // the levels' M2L products in one launch (they depend on the upward pass and on the offset
-    // masks only); the deepest level's were launched on another stream when deep_m2l is given
-    const int top = deep_m2l ? D - 1 : D;
-    PH_HIP(hipStreamWaitEvent(s, vt_ready, 0));  // offset masks and V/X targets
+    // masks only); the deepest level's were launched on another stream when every level has
+    // its products (m2l_ready then follows them there, else the offset masks and V/X targets)
+    const bool deep = p.y_all_levels && D >= 2;
+    const int top = deep ? D - 1 : D;
+    PH_HIP(hipStreamWaitEvent(s, m2l_ready, 0));
     if (p.y_all_levels && top >= 2) {
         GemmSegs sg{};
         int64_t tiles = 0;
@@ -812,7 +814,6 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t list
         }
         m2l_product<T>(p, sg, tiles, s);
     }
-    if (deep_m2l) PH_HIP(hipStreamWaitEvent(s, deep_m2l, 0));
     PH_HIP(hipStreamWaitEvent(s, lists_ready, 0));  // the gathers read the X and V/X target lists
     // level-local parts (V and X lists) of every level: no dependence between levels
     int64_t gcap = 0;
@@ -934,10 +935,10 @@ bool fmm_m2l_deepest(Plan &p, hipStream_t s)
     return true;
 }
 
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready, hipEvent_t deep_m2l)
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready)
 {
-    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, vt_ready, lists_ready, deep_m2l);
-    else fmm_downward_t<float>(p, s, vt_ready, lists_ready, deep_m2l);
+    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, m2l_ready, lists_ready);
+    else fmm_downward_t<float>(p, s, m2l_ready, lists_ready);
 }
 
 void fmm_m2m_level(Plan &p, int l, hipStream_t s)

@@ -915,26 +915,28 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     }
     build_tree(p, s);
     mark(4, s);
-    // The lists and the near field run on the second stream: the upward pass and the M2L
-    // products need only the tree; the L2L / gather chain waits for the lists (X lists), and
-    // the far-field kernels, which combine both fields into the output, for the near field.
+    // The lists and the near field run on the second stream, the V/X targets and the deepest
+    // level's M2L products on the third, the upward pass and the rest of the downward pass here.
+    // A wait on an event still pending costs the host about as much as several launches, so
+    // each stream's last event covers what precedes it there: the M2L levels here wait for the
+    // deepest level's products (which follow the V/X targets), the gathers for the near field
+    // (which follows the lists), and the far-field kernels, which combine both fields into the
+    // output, come after the gathers.
+    const bool deep = p.y_all_levels && p.max_depth >= 2;
     PH_HIP(hipEventRecord(p.ev_fork, s));
     PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
     PH_HIP(hipStreamWaitEvent(p.side2, p.ev_fork, 0));
-    // the V/X targets and M2L offset masks on the third stream, beside the lists
     build_vtargets(p, p.side2);
-    PH_HIP(hipEventRecord(p.ev_vt, p.side2));
+    if (!deep) PH_HIP(hipEventRecord(p.ev_vt, p.side2));
     mark(8, p.side);
     build_lists(p, p.side);
     mark(9, p.side);
-    PH_HIP(hipEventRecord(p.ev_lists, p.side));
     fmm_near(p, p.side);
     mark(10, p.side);
     PH_HIP(hipEventRecord(p.ev_join, p.side));
-    // the leaf densities, then the deepest level's M2L products on a third stream while the
+    // the leaf densities, then the deepest level's M2L products on the third stream while the
     // M2M chain runs here
     fmm_p2m(p, s);
-    const bool deep = p.y_all_levels && p.max_depth >= 2;
     if (deep) {
         PH_HIP(hipEventRecord(p.ev_p2m, s));
         PH_HIP(hipStreamWaitEvent(p.side2, p.ev_p2m, 0));
@@ -943,10 +945,9 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     }
     fmm_m2m(p, s);
     mark(5, s);
-    fmm_downward(p, s, p.ev_vt, p.ev_lists, deep ? p.ev_m2l : nullptr);
+    fmm_downward(p, s, deep ? p.ev_m2l : p.ev_vt, p.ev_join);
     mark(6, s);
-    // far field at the targets (every leaf kernel here, after the near field)
-    PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));
+    // far field at the targets (every leaf kernel here, after the gathers and so after the near field)
     fmm_leaf(p, S_out, s, s);
     mark(7, s);
 }

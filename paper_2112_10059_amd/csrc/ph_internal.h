@@ -349,8 +349,9 @@ void fmm_m2m(Plan &p, hipStream_t s);  // ... and the M2M chain
 // The deepest level's M2L products on s (after the leaf densities and the offset masks);
 // false if this plan computes that level with the others (then nothing is launched)
 bool fmm_m2l_deepest(Plan &p, hipStream_t s);
-// waits for vt_ready (offset masks) before the M2L products and for lists_ready before the gathers
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t vt_ready, hipEvent_t lists_ready, hipEvent_t deep_m2l);
+// waits for m2l_ready (the offset masks, and the deepest level's M2L products when they run on
+// another stream) before the M2L products and for lists_ready before the gathers
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready);
 void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
 // far field at targets (L2P, M2P, own cell) + output: the matrix-core kernel on s, the other
