@@ -311,6 +311,8 @@ __device__ __forceinline__ bool candidate(double v, double src_rel, double imax)
 struct LeafArgs {
     BoxArrays bx;
     const int32_t *pleaf, *pleaf_of_box, *perm, *iperm;
+    const int4 *pinfo, *pinfo2;  // per plan leaf: (box, first, end, 0), (anchor x, y, z, level)
+    const int32_t *pcoll;        // per plan leaf, 27: C (a plan leaf), -2 - C (split), -1 (none)
     int32_t n_pleaf;
     const double *xyz;
     const double *w;  // sorted quadrature weights, null on uniform grids (w = w_ref)
@@ -475,9 +477,21 @@ __global__ __launch_bounds__(256) void leaf_pick_kernel(LeafArgs a, const double
         ekey = max(ekey, smE[q]);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double emax = (double)__uint_as_float((uint32_t)(ekey >> 32));
         a.sc->imax = imax;
-        a.sc->emax = (double)__uint_as_float((uint32_t)(ekey >> 32));
+        a.sc->emax = emax;
         a.sc->emax_key = ekey;
+        // the position of the largest |E| (the distance feature's reference point)
+        double ex = 0.0, ey = 0.0, ez = 0.0;
+        if (a.E && emax > 0.0) {
+            const int64_t kp = a.iperm[0xffffffffu - (uint32_t)(ekey & 0xffffffffu)];
+            ex = a.xyz[3 * kp];
+            ey = a.xyz[3 * kp + 1];
+            ez = a.xyz[3 * kp + 2];
+        }
+        a.sc->emax_xyz[0] = ex;
+        a.sc->emax_xyz[1] = ey;
+        a.sc->emax_xyz[2] = ez;
     }
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && a.flag2) a.flag2[a.n_pleaf] = 0;
@@ -506,10 +520,16 @@ __global__ __launch_bounds__(256) void leaf_features_kernel(LeafArgs a, const T 
         __syncthreads();
     }
     const double imax = a.sc->imax, emax = a.sc->emax;
+    const double ex = a.sc->emax_xyz[0], ey = a.sc->emax_xyz[1], ez = a.sc->emax_xyz[2];
+    const bool efeat = a.E && emax > 0.0;
     for (int32_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrow; r += gridDim.x * 4) {
         const int32_t i = a.list[r];
-        const int32_t f = a.pleaf[i];
-        const int32_t st = a.bx.start[f], en = a.bx.end[f];
+        // the row's records, all loaded together
+        const int4 inf = a.pinfo[i], inf2 = a.pinfo2[i];
+        const int32_t cq = (efeat && lane < 27) ? a.pcoll[(size_t)i * 27 + lane] : -1;
+        const double *S = a.lstat + (size_t)i * 4;
+        const double S0 = S[0], S1 = S[1], S2 = S[2], S3 = S[3];
+        const int32_t st = inf.y, en = inf.z;
         double swi = 0.0, cnt = 0.0;
         for (int32_t k = st + lane; k < en; k += 64) {
             const double v = (double)I[a.perm[k]];
@@ -519,37 +539,30 @@ __global__ __launch_bounds__(256) void leaf_features_kernel(LeafArgs a, const T 
         }
         swi = wave_sum(swi);
         cnt = wave_sum(cnt);
-        const double *S = a.lstat + (size_t)i * 4;
-        const int level = a.bx.level[f];
+        const int level = inf2.w;
         const double side = a.cube / (double)(1 << level), hw = 0.5 * side;
         float fe[8];
-        fe[0] = (float)log10(fmax(S[0] / imax, 1e-300));
+        fe[0] = (float)log10(fmax(S0 / imax, 1e-300));
         fe[1] = (float)log10(fmax(swi / (imax * a.w_ref), 1e-300));
         fe[2] = (float)log2(side / cbrt(a.w_ref));
         for (int q = 3; q < 8; ++q) fe[q] = 0.0f;
-        if (a.E && emax > 0.0) {
-            const double cx = a.lo0 + (2.0 * a.bx.ax[f] + 1.0) * hw, cy = a.lo1 + (2.0 * a.bx.ay[f] + 1.0) * hw,
-                         cz = a.lo2 + (2.0 * a.bx.az[f] + 1.0) * hw;
-            const int64_t kp = a.iperm[0xffffffffu - (uint32_t)(a.sc->emax_key & 0xffffffffu)];
-            const double dx = cx - a.xyz[3 * kp], dy = cy - a.xyz[3 * kp + 1], dz = cz - a.xyz[3 * kp + 2];
+        if (efeat) {
+            const double cx = a.lo0 + (2.0 * inf2.x + 1.0) * hw, cy = a.lo1 + (2.0 * inf2.y + 1.0) * hw,
+                         cz = a.lo2 + (2.0 * inf2.z + 1.0) * hw;
+            const double dx = cx - ex, dy = cy - ey, dz = cz - ez;
             fe[3] = (float)log10(1.0 + sqrt(dx * dx + dy * dy + dz * dz) / side);
             const double nn = (double)(en - st);
-            const double mean = S[1] / emax / nn;
-            fe[4] = (float)(S[3] / emax);
+            const double mean = S1 / emax / nn;
+            fe[4] = (float)(S3 / emax);
             fe[5] = (float)mean;
-            fe[6] = (float)sqrt(fmax(S[2] / (emax * emax) / nn - mean * mean, 0.0));
+            fe[6] = (float)sqrt(fmax(S2 / (emax * emax) / nn - mean * mean, 0.0));
             // the 27 boxes around the leaf, one lane each: a leaf's stored maximum, or the box's range
             double nmx = 0.0;
-            if (lane < 27) {
-                const int32_t C = a.bx.coll[(size_t)f * 27 + lane];
-                if (C >= 0) {
-                    if (a.pleaf_of_box[C] >= 0) {
-                        nmx = (double)a.box_emax[C];
-                    } else {
-                        for (int32_t k = a.bx.start[C]; k < a.bx.end[C]; ++k)
-                            nmx = fmax(nmx, (double)a.E[a.perm[k]]);
-                    }
-                }
+            if (cq >= 0) {
+                nmx = (double)a.box_emax[cq];
+            } else if (cq < -1) {
+                const int32_t C = -2 - cq;
+                for (int32_t k = a.bx.start[C]; k < a.bx.end[C]; ++k) nmx = fmax(nmx, (double)a.E[a.perm[k]]);
             }
             fe[7] = (float)(wave_max(nmx) / emax);
         }
@@ -677,6 +690,9 @@ static LeafArgs leaf_args(Plan &p, const float *E)
     a.bx = p.box;
     a.pleaf = p.d_pleaf;
     a.pleaf_of_box = p.d_pleaf_of_box;
+    a.pinfo = p.d_pinfo;
+    a.pinfo2 = p.d_pinfo2;
+    a.pcoll = p.d_pcoll;
     a.perm = p.d_perm;
     a.iperm = p.d_iperm;
     a.n_pleaf = p.n_pleaf;

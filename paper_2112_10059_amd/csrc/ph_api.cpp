@@ -329,7 +329,7 @@ void free_plan(Plan *p)
                     p->lists.w_rng, p->lists.x_rng, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
                     p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_tile_use, p->lists.m2l_box_use, p->lists.vslot, p->d_phi, p->d_u,
                     p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
-                    p->d_pleaf, p->d_pleaf_of_box, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
+                    p->d_pleaf, p->d_pleaf_of_box, p->d_pinfo, p->d_pinfo2, p->d_pcoll, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
                     p->d_row_feat,
                     p->d_cell,
                     p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near,
@@ -541,6 +541,23 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         std::vector<int32_t> of_box(FT.level.size(), -1);
         for (size_t i = 0; i < leaves.size(); ++i) of_box[leaves[i]] = (int32_t)i;
         up(&p.d_pleaf_of_box, of_box);
+        // the selector's per-leaf look-ups in one record each (no chains of dependent loads)
+        {
+            std::vector<int4> info(leaves.size()), info2(leaves.size());
+            std::vector<int32_t> pc(leaves.size() * 27);
+            for (size_t i = 0; i < leaves.size(); ++i) {
+                const int32_t f = leaves[i];
+                info[i] = make_int4(f, FT.start[f], FT.end[f], 0);
+                info2[i] = make_int4(FT.ax[f], FT.ay[f], FT.az[f], FT.level[f]);
+                for (int d = 0; d < 27; ++d) {
+                    const int32_t C = FT.coll[(size_t)f * 27 + d];
+                    pc[i * 27 + d] = C < 0 ? -1 : (of_box[C] >= 0 ? C : -2 - C);
+                }
+            }
+            upload(p, reinterpret_cast<void **>(&p.d_pinfo), info);
+            upload(p, reinterpret_cast<void **>(&p.d_pinfo2), info2);
+            up(&p.d_pcoll, pc);
+        }
         p.h_pleaf = std::move(leaves);
         // boxes by level and coordinates, for the composite translations
         const int D = (int)FT.level_cap.size() - 1;

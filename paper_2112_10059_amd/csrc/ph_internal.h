@@ -64,6 +64,7 @@ struct CallScalars {
     int32_t gen;                        // number of the call (never 0): V/X target tags
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t emax_key;                  // |E| bits << 32 | ~caller index of the largest |E|
+    double emax_xyz[3];                 // that point's position (learned selector calls)
     // algorithmic work of the call (integer counters, order independent)
     unsigned long long work[12];        // p2p pairs, l2p evals, m2p evals, p2m evals,
                                         // p2l evals, m2l pairs, m2m children, l2l boxes,
@@ -202,6 +203,10 @@ struct Plan {
     int32_t *d_pleaf = nullptr;     // their box ids in box order
     std::vector<int32_t> h_pleaf;   // host copy
     int32_t *d_pleaf_of_box = nullptr; // per box: its plan-leaf index, -1 for split boxes
+    int4 *d_pinfo = nullptr;           // per plan leaf: box, first point, end, 0
+    int4 *d_pinfo2 = nullptr;          // per plan leaf: anchor x, y, z, level
+    int32_t *d_pcoll = nullptr;        // per plan leaf, 27: colleague box C if a plan leaf,
+                                       // -2 - C if split, -1 if none
     uint32_t *d_leafscan = nullptr; // per plan leaf: candidate flag, scanned by the row compaction
     double *d_lstat = nullptr;      // per plan leaf: max I, sum |E|, sum |E|^2, max |E|
     float *d_box_emax = nullptr;    // per box (plan leaves only): max |E|
