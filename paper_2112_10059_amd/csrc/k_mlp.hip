@@ -52,33 +52,29 @@ struct MlpLds {
 template <bool BF16>
 __device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
 {
-    // walk the LDS side in order (consecutive threads, consecutive banks); eight loads per thread
-    // in flight before their stores (one round trip per batch, not one per element)
+    // walk the parameters in order (consecutive threads, consecutive addresses) and transpose
+    // on the LDS side; eight loads per thread in flight
+    // before their stores (one round trip per batch, not one per element).  Weight (o, i) of a
+    // layer with NI inputs sits at o NI + i in the parameters and at i NH + o in LDS.
     constexpr int kB = 8;
     for (int t0 = threadIdx.x; t0 < NH * NIN; t0 += kB * blockDim.x) {
         float v[kB];
 #pragma unroll
-        for (int b = 0; b < kB; ++b) {
-            const int t = min(t0 + b * (int)blockDim.x, NH * NIN - 1);
-            v[b] = params[OFF_W1 + (t % NH) * NIN + t / NH];
-        }
+        for (int b = 0; b < kB; ++b) v[b] = params[OFF_W1 + min(t0 + b * (int)blockDim.x, NH * NIN - 1)];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            const int t = t0 + b * (int)blockDim.x;
-            if (t < NH * NIN) L.w1t[t] = q<BF16>(v[b]);
+            const int u = t0 + b * (int)blockDim.x;
+            if (u < NH * NIN) L.w1t[(u % NIN) * NH + u / NIN] = q<BF16>(v[b]);
         }
     }
     for (int t0 = threadIdx.x; t0 < NH * NH; t0 += kB * blockDim.x) {
         float v[kB];
 #pragma unroll
-        for (int b = 0; b < kB; ++b) {
-            const int t = min(t0 + b * (int)blockDim.x, NH * NH - 1);
-            v[b] = params[OFF_W2 + (t % NH) * NH + t / NH];
-        }
+        for (int b = 0; b < kB; ++b) v[b] = params[OFF_W2 + min(t0 + b * (int)blockDim.x, NH * NH - 1)];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            const int t = t0 + b * (int)blockDim.x;
-            if (t < NH * NH) L.w2t[t] = q<BF16>(v[b]);
+            const int u = t0 + b * (int)blockDim.x;
+            if (u < NH * NH) L.w2t[(u % NH) * NH + u / NH] = q<BF16>(v[b]);
         }
     }
     if (threadIdx.x < NH) {
