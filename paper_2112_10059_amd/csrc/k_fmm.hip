@@ -208,12 +208,12 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(FmmArgs<T> a, int leve
     const int nl = a.n_lam;
     for (int32_t rk = blockIdx.x; rk < a.sc->lvl_src[level]; rk += gridDim.x) {
         const int32_t P = a.bx.src_box[a.lt.base[level] + rk];
-        if (a.bx.flags[P] & kBoxLeaf) continue;
+        // the children's indices loaded with the parent's flags (a leaf has none)
+        const int32_t fl = a.bx.flags[P];
+        const int32_t Ct = t < 8 ? a.bx.child[(size_t)P * 8 + t] : -1;
+        if (fl & kBoxLeaf) continue;
         __syncthreads();  // the previous parent's kids and partial sums have been read
-        if (t < 8) {
-            const int32_t C = a.bx.child[(size_t)P * 8 + t];
-            kids[t] = (C >= 0 && a.bx.s_cnt[C] > 0) ? C : -1;
-        }
+        if (t < 8) kids[t] = (Ct >= 0 && a.bx.s_cnt[Ct] > 0) ? Ct : -1;
         __syncthreads();
         const int32_t C = kids[o];
         T acc = T(0);

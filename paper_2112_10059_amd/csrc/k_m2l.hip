@@ -438,13 +438,19 @@ __global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArg
         const int X = (t >> 4) * side + cx, Y = ((t >> 2) & 3) * side + cy, Z = (t & 3) * side + cz;
         const int64_t nm = (int64_t)1 << m;
         const int32_t B = ca.map[ca.map_off[m] + ((int64_t)X * nm + Y) * nm + Z];
+        // the ancestors' look-ups issued with the box's (they need only its coordinates)
+        int32_t an[kCompMaxDepth];
+#pragma unroll
+        for (int l = 2; l < kCompMaxDepth; ++l) {
+            const int lc = min(l, m - 1), s2 = m - lc;
+            const int64_t n2 = (int64_t)1 << lc;
+            an[l] = ca.map[ca.map_off[lc] + ((int64_t)(X >> s2) * n2 + (Y >> s2)) * n2 + (Z >> s2)];
+        }
         const bool v = B >= 0 && (a.bx.flags[B] & kBoxLeaf) && a.bx.t_cnt[B] > 0;
         leafb[t] = v ? B : -1;
-        for (int l = 2; l < m; ++l) {
-            const int s2 = m - l;
-            const int64_t n2 = (int64_t)1 << l;
-            anc[l][t] = v ? ca.map[ca.map_off[l] + ((int64_t)(X >> s2) * n2 + (Y >> s2)) * n2 + (Z >> s2)] : -1;
-        }
+#pragma unroll
+        for (int l = 2; l < kCompMaxDepth; ++l)
+            if (l < m) anc[l][t] = v ? an[l] : -1;
         if (v) anyv = 1;
     }
     __syncthreads();
