@@ -165,8 +165,9 @@ __device__ void p2m_box(const FmmArgs<T> &a, int32_t b, int level, V4<T> *tile, 
 // dealt to the workgroups as one flat range (boxes that are not leaves get their densities
 // from their children afterwards).
 // The same launch also clears the check values of every box of levels >= 3 (u_zero .. u_end
-// elements): the downward gather then stores only the level-local parts of the boxes with a V
-// or X list, and the L2L products add whatever their children hold.
+// elements) where the per-level L2L runs: the downward gather then stores only the level-local
+// parts of the boxes with a V or X list, and the L2L products add whatever their children
+// hold.  (The composite L2L reads only the parts the gather wrote: an empty range there.)
 template <class T>
 __global__ __launch_bounds__(kUpThreads) void p2m_kernel(FmmArgs<T> a, int depth, int64_t u_zero, int64_t u_end)
 {
@@ -941,8 +942,10 @@ void fmm_p2m_t(Plan &p, hipStream_t s)
     int64_t cap = 0;
     for (int l = 2; l <= D; ++l) cap += p.level_cap[l];
     if (cap == 0) return;
+    // the composite L2L reads only the check values the gather wrote this call: nothing to clear
+    const bool comp = std::is_same<T, float>::value && p.l2l_comp;
     const int64_t u_zero = D >= 3 ? p.level_base[3] * (int64_t)p.n_lam : 0;
-    const int64_t u_end = D >= 3 ? p.box_cap * (int64_t)p.n_lam : 0;
+    const int64_t u_end = (D >= 3 && !comp) ? p.box_cap * (int64_t)p.n_lam : u_zero;
     p2m_kernel<T><<<(unsigned)std::min<int64_t>(cap, 4096), kUpThreads, 0, s>>>(a, D, u_zero, u_end);
 }
 

@@ -414,6 +414,7 @@ __global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArg
     __shared__ float Bs[kTile][KT + kPad];
     __shared__ int32_t anc[kMaxDepth + 2][kTile];  // per ancestor level, each column's ancestor
     __shared__ int32_t leafb[kTile];               // the column's leaf (-1: none)
+    __shared__ uint8_t lown[kTile];                // whether the leaf holds a level-local part
     __shared__ int anyv;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int ws = __builtin_amdgcn_readfirstlane(w);
@@ -446,11 +447,20 @@ __global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArg
             const int64_t n2 = (int64_t)1 << lc;
             an[l] = ca.map[ca.map_off[lc] + ((int64_t)(X >> s2) * n2 + (Y >> s2)) * n2 + (Z >> s2)];
         }
+        // a box of level >= 3 holds a level-local part only if the gather wrote one this call
+        // (a V/X target: tagged with the call number); the others count as zero, so their
+        // check values need no clearing.  Every box of level 2 is written.
+        const int gen = a.sc->gen;
         const bool v = B >= 0 && (a.bx.flags[B] & kBoxLeaf) && a.bx.t_cnt[B] > 0;
+        const bool vo = B >= 0 && a.L.vt_tag[B] == gen;
+        bool va[kCompMaxDepth];
+#pragma unroll
+        for (int l = 2; l < kCompMaxDepth; ++l) va[l] = l == 2 || (an[l] >= 0 && a.L.vt_tag[an[l]] == gen);
         leafb[t] = v ? B : -1;
+        lown[t] = v && vo;
 #pragma unroll
         for (int l = 2; l < kCompMaxDepth; ++l)
-            if (l < m) anc[l][t] = v ? an[l] : -1;
+            if (l < m) anc[l][t] = (v && va[l]) ? an[l] : -1;
         if (v) anyv = 1;
     }
     __syncthreads();
@@ -461,8 +471,9 @@ __global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArg
         for (int q = 0; q < 2; ++q) {
             const int gm = wm * 32 + q * 16 + (lane & 15);
             for (int r = 0; r < 4; ++r) {
-                const int32_t B = leafb[wn * 32 + i * 16 + Mfma<float>::row(lane, r)];
-                own[i][q][r] = (B >= 0 && gm < nl) ? a.u[(size_t)B * nl + gm] : 0.0f;
+                const int col = wn * 32 + i * 16 + Mfma<float>::row(lane, r);
+                const int32_t B = leafb[col];
+                own[i][q][r] = (B >= 0 && lown[col] && gm < nl) ? a.u[(size_t)B * nl + gm] : 0.0f;
             }
         }
     auto op_of = [&](int l) {
