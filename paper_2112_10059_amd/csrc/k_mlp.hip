@@ -373,8 +373,8 @@ __global__ __launch_bounds__(256) void leaf_reduce_kernel(LeafArgs a, const T *_
     for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * kLPW; base < a.n_pleaf;
          base += (int64_t)gridDim.x * 4 * kLPW) {
         const int64_t i = base + slot;
-        const int32_t f = i < a.n_pleaf ? a.pleaf[i] : -1;
-        const int32_t st = f >= 0 ? a.bx.start[f] : 0, en = f >= 0 ? a.bx.end[f] : 0;
+        const int4 inf = i < a.n_pleaf ? a.pinfo[i] : make_int4(-1, 0, 0, 0);  // box, first, end
+        const int32_t f = inf.x, st = inf.y, en = inf.z;
         double mx = 0.0, es = 0.0, es2 = 0.0;
         float emx = 0.0f;
         for (int32_t k0 = st; k0 < en; k0 += 64) {
@@ -454,9 +454,21 @@ __global__ __launch_bounds__(256) void leaf_pick_kernel(LeafArgs a, const double
     double mi = 0.0;
     uint64_t me = 0;
     bool bad = false;
-    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-        mi = fmax(mi, partial_max(partial[j], bad));
-        me = max(me, partial_key[j]);
+    // eight of each per thread in flight (a zero partial is neutral: not marked, no larger)
+    for (int j0 = threadIdx.x; j0 < nb; j0 += 8 * blockDim.x) {
+        double pv[8];
+        uint64_t kv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u * (int)blockDim.x;
+            pv[u] = j < nb ? partial[j] : 0.0;
+            kv[u] = j < nb ? partial_key[j] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            mi = fmax(mi, partial_max(pv[u], bad));
+            me = max(me, kv[u]);
+        }
     }
     if (bad && blockIdx.x == 0) atomicOr(&a.sc->err, 1);
     mi = wave_max(mi);
@@ -717,9 +729,9 @@ static unsigned feature_blocks(const Plan &p) { return (unsigned)std::min<int64_
 void selector_reduce(Plan &p, const void *I, const float *E, int32_t *gen, hipStream_t s)
 {
     LeafArgs a = leaf_args(p, E);
-    const int nb = (int)std::min<int64_t>((p.n_pleaf + 4 * kLPW - 1) / (4 * kLPW), 1024);
+    const int nb = (int)std::min<int64_t>((p.n_pleaf + 4 * kLPW - 1) / (4 * kLPW), kLeafPartials);
     double *partial = reinterpret_cast<double *>(p.d_scan_tmp);
-    uint64_t *partial_key = reinterpret_cast<uint64_t *>(partial + 1024);
+    uint64_t *partial_key = reinterpret_cast<uint64_t *>(partial + kLeafPartials);
     if (p.precision == PH_FP64)
         leaf_reduce_kernel<double><<<nb, 256, 0, s>>>(a, (const double *)I, partial, partial_key, gen);
     else
@@ -730,9 +742,9 @@ void selector_reduce(Plan &p, const void *I, const float *E, int32_t *gen, hipSt
 // the pick pass over the plan leaves, with the maxima of pass 1's partials (see selector_reduce)
 static void launch_leaf_pick(Plan &p, const LeafArgs &a, hipStream_t s)
 {
-    const int nb = (int)std::min<int64_t>((p.n_pleaf + 4 * kLPW - 1) / (4 * kLPW), 1024);
+    const int nb = (int)std::min<int64_t>((p.n_pleaf + 4 * kLPW - 1) / (4 * kLPW), kLeafPartials);
     const double *partial = reinterpret_cast<const double *>(p.d_scan_tmp);
-    const uint64_t *partial_key = reinterpret_cast<const uint64_t *>(partial + 1024);
+    const uint64_t *partial_key = reinterpret_cast<const uint64_t *>(partial + kLeafPartials);
     leaf_pick_kernel<<<(unsigned)((p.n_pleaf + 255) / 256), 256, 0, s>>>(a, partial, partial_key, nb);
 }
 

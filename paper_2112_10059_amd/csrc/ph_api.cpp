@@ -224,7 +224,7 @@ void alloc_workspace(Plan &p)
     PH_HIP(hipMemset(p.d_sel, 0, (size_t)n));  // nothing selected before the first call
     // also the list build's per-workgroup totals (3 words per 256 boxes)
     p.scan_tmp_bytes = std::max({scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4),
-                                 (size_t)12 * ((p.box_cap + 255) / 256) + 256, (size_t)16384});
+                                 (size_t)12 * ((p.box_cap + 255) / 256) + 256, (size_t)16 * kLeafPartials});
     p.d_scan_tmp = dev_alloc(p, p.scan_tmp_bytes);
     p.d_t_out = (int32_t *)dev_alloc(p, (size_t)n * 4);
     p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);

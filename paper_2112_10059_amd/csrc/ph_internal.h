@@ -150,6 +150,7 @@ struct OperatorsDev {
     void *l2l_comp = nullptr;
 };
 
+constexpr int kLeafPartials = 2048;  // per-workgroup maxima of the selector's statistics pass (at most)
 constexpr int kCompMaxDepth = 6;  // composite translations for trees of at most this depth
 
 constexpr int kNearTabMaxR = 7;     // table for leaves of at most 4^3 cells
