@@ -237,14 +237,16 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->scale_exp = e;
     const double scale = ldexp(1.0, -e);
     const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)wv * kSelSpan;
-    uint32_t f[kStrips];
+    uint32_t f[kStrips], bd[kStrips];  // flags and box-boundary marks, loaded together
     uint64_t acc = 0;
 #pragma unroll
     for (int st = 0; st < kStrips; ++st) {
         const int64_t k = base + st * 64 + lane;
         f[st] = k < n ? sel[k] : 0u;
-        acc += packed_of(f[st]);
+        bd[st] = k < n ? bnd[k] : 0u;
     }
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) acc += packed_of(f[st]);
     acc = lane_value(wave_inclusive(acc, lane), 63);
     if (lane == 0) wsum[wv] = acc;
     __syncthreads();
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
         carry += lane_value(incl, 63);
         const int64_t k = base + st * 64 + lane;
         if (k >= n) continue;
-        if (bnd[k]) scanned[k] = here;
+        if (bd[st]) scanned[k] = here;
         // points that are only targets need nothing more unless targets are compacted
         if (!(tgt_compact ? f[st] : (f[st] & 1u))) continue;
         const uint32_t sp_lo = (uint32_t)(here & 0xffffffffu), sp_hi = (uint32_t)(here >> 32);
