@@ -714,7 +714,7 @@ __global__ void far_shell_kernel(FmmArgs<T> a, TO *__restrict__ S_out, const dou
 // workgroups take the matrix-core leaves (FP32), the next g_grid the other grid-operator
 // leaves, the rest the shell-point leaves
 template <class T, class TO, int NK>
-__global__ __launch_bounds__(256) void far_rest_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
+__global__ __launch_bounds__(256, 8) void far_rest_kernel(FmmArgs<T> a, TO *__restrict__ S_out,
                                                        const double *__restrict__ t_near, int stage_cap,
                                                        uint32_t level_mask, uint32_t mfma_mask, int32_t g_mfma,
                                                        int32_t g_grid)
