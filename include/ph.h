@@ -173,9 +173,11 @@ void ph_plan_destroy(ph_plan *plan);
  *         and a numeric fault is reported by the next ph_plan_check().
  * The interaction lists and the near field run on a second stream the plan owns,
  * and the V/X target lists with the deepest level's M2L products on a third, both
- * forked from `stream` after the octree and joined back into it before the far
- * field (events, no host synchronisation), so the call stays ordered on `stream`
- * and may be captured into a HIP graph.  Calls on one plan must not overlap.
+ * forked from `stream` after the octree and joined back into it in the downward
+ * pass (the third before the other levels' M2L products, the second before the
+ * gathers), so before the far field (events, no host synchronisation): the call
+ * stays ordered on `stream` and may be captured into a HIP graph.  Calls on one
+ * plan must not overlap.
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);
