@@ -340,10 +340,7 @@ void free_plan(Plan *p)
             for (auto &e : set) (void)hipEventDestroy(e);
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
-    if (p->ev_lists) (void)hipEventDestroy(p->ev_lists);
-    if (p->ev_down) (void)hipEventDestroy(p->ev_down);
     if (p->ev_vt) (void)hipEventDestroy(p->ev_vt);
-    if (p->ev_rest) (void)hipEventDestroy(p->ev_rest);
     if (p->side) (void)hipStreamDestroy(p->side);
     if (p->side2) (void)hipStreamDestroy(p->side2);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
@@ -798,10 +795,7 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     PH_HIP(hipEventCreateWithFlags(&p.ev_m2l, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_fork, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_join, kSyncEventFlags));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_lists, kSyncEventFlags));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_down, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_vt, kSyncEventFlags));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_rest, kSyncEventFlags));
 }
 
 }  // namespace ph

@@ -260,14 +260,15 @@ struct Plan {
     double phase_sum[PH_NPHASES] = {};
     int64_t phase_calls = 0;
     bool events_ready = false;
-    // the interaction lists and the near field run on a second stream, forked from the
-    // caller's stream after the tree; the downward chain waits for the lists (ev_lists), the
-    // far-field kernels (which write the output) for the near field (ev_join)
+    // the interaction lists and the near field run on a second stream, the V/X targets, offset
+    // masks and deepest level's M2L products on a third, both forked from the caller's stream
+    // after the tree (ev_fork); the gathers wait for the near field (ev_join, after the lists),
+    // the other levels' M2L products for the deepest level's (ev_m2l, after the offset masks;
+    // ev_vt when that level runs with the others)
     hipStream_t side = nullptr;
-    hipStream_t side2 = nullptr;  // the deepest level's M2L products, beside the M2M chain
-    hipEvent_t ev_fork = nullptr, ev_lists = nullptr, ev_join = nullptr;
-    hipEvent_t ev_down = nullptr, ev_rest = nullptr;  // downward done (main); far kernels on side done
-    hipEvent_t ev_vt = nullptr;  // V/X targets and M2L offset masks known (side)
+    hipStream_t side2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_vt = nullptr;                     // V/X targets and M2L offset masks known
     hipEvent_t ev_p2m = nullptr, ev_m2l = nullptr;  // leaf densities known (main); deepest M2L done
     // check values of the leaves of levels >= 3 in one launch from the level-local parts of their
     // ancestors (composite translations) in place of the level-by-level L2L chain
