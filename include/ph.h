@@ -168,29 +168,24 @@ void ph_plan_destroy(ph_plan *plan);
  *   absE  device, n floats |E| (V/m); may be NULL only if both field rules are off.
  *   S_out device, n values, same type as I: S_ph at selected targets, 0 elsewhere.
  *   stats host, nullable.  When non-NULL the call waits for the stream, fills
- *         the counts and per-phase times, and reports PH_ENUMERIC if the device
- *         flagged a bad source value.  When NULL the call is fully asynchronous
- *         and a numeric fault is reported by the next ph_plan_check().
+ *         the counts and per-phase times, and reports this call's faults:
+ *         PH_ENUMERIC if the device saw a bad source value, PH_ENOMEM if an
+ *         interaction list overflowed its capacity (the lists are then cut, reads
+ *         stay in bounds, S_out is not valid).  When NULL the call is fully
+ *         asynchronous; its faults are reported by the next ph_plan_check().
  * The interaction lists and the near field run on a second stream the plan owns,
  * and the V/X target lists with the deepest level's M2L products on a third, both
  * forked from `stream` after the octree and joined back into it in the downward
  * pass (the third before the other levels' M2L products, the second before the
  * gathers), so before the far field (events, no host synchronisation): the call
- * stays ordered on `stream` and may be captured into a HIP graph.  Calls on one
- * plan must not overlap.
+ * stays ordered on `stream`.  Calls on one plan's own workspace must not overlap.
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);
 
 /*
- * Graph replay of ph_evaluate.  enable = 1: every later ph_evaluate call without
- * stats (and without phase recording) runs as one HIP graph launched on its
- * `stream`.  The graph is captured, on a stream the plan owns, at the first such
- * call for a set of buffers (I, absE, S_out) and replayed while they stay the
- * same; their contents may change between calls.  The call's number, which the
- * interaction lists tag boxes with, lives on the device and advances in every
- * replay.  Calls with stats or phase recording launch eagerly.  enable = 0 drops
- * the graph.  Waits for the device.
+ * Graph replay of ph_evaluate: not available in this library.  enable = 0 returns
+ * PH_OK (calls launch eagerly, as always); enable != 0 returns PH_EUNSUPPORTED.
  */
 ph_status ph_plan_set_graph(ph_plan *plan, int enable);
 
@@ -211,7 +206,12 @@ ph_status ph_plan_set_graph(ph_plan *plan, int enable);
  */
 ph_status ph_phase_times(ph_plan *plan, int record, double *ms_sum, int64_t *n_calls);
 
-/* Waits for the stream and reports PH_ENUMERIC if any earlier call saw a bad source value. */
+/*
+ * Waits for the stream and reports the faults of every ph_evaluate call on this plan since
+ * the previous ph_plan_check (whether or not a call with stats already reported them):
+ * PH_ENOMEM if an interaction list overflowed, else PH_ENUMERIC if a bad source value was
+ * seen, else PH_OK.  The record is cleared, so a second check right after returns PH_OK.
+ */
 ph_status ph_plan_check(ph_plan *plan, void *stream);
 
 /* Number of points of the plan, or -1 for NULL. */

@@ -159,6 +159,22 @@ __device__ __forceinline__ void begin_call(CallScalars *sc, int32_t *gen)
     }
 }
 
+// An error of the call: in the call's scalars (read by a call that fetches its statistics) and in
+// the plan's sticky word (read and cleared by the next check, whatever calls came in between).
+__device__ __forceinline__ void flag_error(CallScalars *sc, int32_t *sticky, int bits)
+{
+    atomicOr(&sc->err, bits);
+    if (sticky) atomicOr(sticky, bits);
+}
+
+// The list range (begin, begin + count) cut at the list's capacity: never past the stored entries.
+__host__ __device__ __forceinline__ uint2 clamp_range(uint32_t begin, uint32_t count, int64_t cap)
+{
+    const int64_t b = begin < cap ? (int64_t)begin : cap;
+    const int64_t e = (int64_t)begin + count < cap ? (int64_t)begin + count : cap;
+    return make_uint2((uint32_t)b, (uint32_t)e);
+}
+
 // Per-workgroup maxima of I carry a bad source value seen by the workgroup as -(max + 1)
 __device__ __forceinline__ double mark_bad(double m, bool bad) { return bad ? -(m + 1.0) : m; }
 __device__ __forceinline__ double partial_max(double v, bool &bad)

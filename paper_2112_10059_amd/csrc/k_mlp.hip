@@ -314,6 +314,7 @@ struct LeafArgs {
     const double *w;  // sorted quadrature weights, null on uniform grids (w = w_ref)
     const float *E;
     CallScalars *sc;
+    int32_t *sticky;         // the plan's sticky error word
     uint32_t *flag, *flag2;  // candidate flags (flag2: a copy for the row compaction, nullable)
     int32_t *list;           // candidate leaves (plan-leaf indices, any order)
     double *lstat;           // per leaf: max I, sum |E|, sum |E|^2, max |E|
@@ -470,7 +471,7 @@ __global__ __launch_bounds__(256) void leaf_pick_kernel(LeafArgs a, const double
             me = max(me, kv[u]);
         }
     }
-    if (bad && blockIdx.x == 0) atomicOr(&a.sc->err, 1);
+    if (bad && blockIdx.x == 0) flag_error(a.sc, a.sticky, 1);
     mi = wave_max(mi);
     me = wave_max_u64(me);
     if (lane == 0) {
@@ -708,6 +709,7 @@ static LeafArgs leaf_args(Plan &p, const float *E)
     a.w = p.d_w;
     a.E = E;
     a.sc = p.d_sc;
+    a.sticky = p.d_sticky;
     a.flag = p.d_leafflag;
     a.list = p.d_cand_list;
     a.lstat = p.d_lstat;

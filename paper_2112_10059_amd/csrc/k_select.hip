@@ -72,7 +72,7 @@ __global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restri
 }
 
 __global__ void reduce_max_final_kernel(const double *__restrict__ partial, const uint64_t *__restrict__ partial_key,
-                                        int nb, CallScalars *sc)
+                                        int nb, CallScalars *sc, int32_t *sticky)
 {
     __shared__ double a[256];
     __shared__ uint64_t b[256];
@@ -83,7 +83,7 @@ __global__ void reduce_max_final_kernel(const double *__restrict__ partial, cons
         mi = fmax(mi, partial_max(partial[i], bad));
         me = max(me, partial_key[i]);
     }
-    if (bad) atomicOr(&sc->err, 1);
+    if (bad) flag_error(sc, sticky, 1);
     a[threadIdx.x] = mi;
     b[threadIdx.x] = me;
     __syncthreads();
@@ -321,13 +321,13 @@ void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s)
 }
 
 void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
-                             hipStream_t s)
+                             int32_t *sticky, hipStream_t s)
 {
-    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, nb, sc);
+    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, nb, sc, sticky);
 }
 
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n, CallScalars *sc,
-                       int32_t *gen, void *tmp, hipStream_t s)
+                       int32_t *gen, int32_t *sticky, void *tmp, hipStream_t s)
 {
     int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
     double *partial = reinterpret_cast<double *>(tmp);
@@ -338,7 +338,7 @@ void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, in
     else
         reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, n, partial,
                                                         partial_key, sc, gen);
-    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, blocks, sc);
+    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, blocks, sc, sticky);
 }
 
 static SelectParams params_of(const Plan &p)

@@ -282,7 +282,7 @@ constexpr int kLPer = kLBoxes / 8;        // boxes per half wave
 
 __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, LevelInfo li,
                                                                 CallScalars *__restrict__ sc, int32_t nbox, Lists L,
-                                                                uint32_t grid_levels)
+                                                                uint32_t grid_levels, int32_t *sticky)
 {
     static_assert(kListBlock == 256, "eight half waves");
     __shared__ int32_t sbox[kLBoxes], slev[kLBoxes];
@@ -365,9 +365,13 @@ __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, Le
         const uint32_t xb = wave_reserve(nx, &sc->n_x);
         const int32_t gid = g0 + t;
         if (gid < nbox) {
-            L.u_rng[gid] = make_uint2(ub, ub + nu);
-            L.w_rng[gid] = make_uint2(wb, wb + nw);
-            L.x_rng[gid] = make_uint2(xb, xb + nx);
+            // ranges past a list's capacity are cut at it (their entries are not stored, and the
+            // overflow is reported), so that no reader leaves the list
+            L.u_rng[gid] = clamp_range(ub, nu, L.u_cap);
+            L.w_rng[gid] = clamp_range(wb, nw, L.w_cap);
+            L.x_rng[gid] = clamp_range(xb, nx, L.x_cap);
+            if ((int64_t)ub + nu > L.u_cap || (int64_t)wb + nw > L.w_cap || (int64_t)xb + nx > L.x_cap)
+                flag_error(sc, sticky, 2);
         }
         su[t] = ub;  // first entries from here on
         sw[t] = wb;
@@ -420,7 +424,7 @@ __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, Le
                 ++px;
             }
         });
-        if (over) atomicOr(&sc->err, 2);
+        if (over) flag_error(sc, sticky, 2);
     }
 #pragma unroll
     for (int i = 0; i < kLPer; ++i) {
@@ -428,7 +432,7 @@ __global__ __launch_bounds__(kListBlock) void list_build_kernel(BoxArrays bx, Le
         if (!sser[j] && hl < 27 && ((sumask[j] >> hl) & 1u)) {
             const uint32_t pos = su[j] + __popc(sumask[j] & ((1u << hl) - 1u));
             if (pos < (uint32_t)L.u_cap) L.u[pos] = C[i];
-            else atomicOr(&sc->err, 2);
+            else flag_error(sc, sticky, 2);
         }
     }
 }
@@ -552,7 +556,7 @@ void build_lists(Plan &p, hipStream_t s)
     if (p.grid_mode)
         for (int l = 0; l <= p.max_depth; ++l)
             if (l < 2 || p.grid_m[l] > 0) grid_levels |= 1u << l;
-    list_build_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels);
+    list_build_kernel<<<g, kListBlock, 0, s>>>(p.box, li, p.d_sc, nbox, p.lists, grid_levels, p.d_sticky);
 }
 
 }  // namespace ph

@@ -142,76 +142,6 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
     }
 }
 
-// The octree over all points (every point both a source and a target), split
-// while a box holds more than leaf_cap points.  Any per-call tree over selected
-// subsets is this tree pruned: a box survives iff it holds selected points and
-// its parent is split in the per-call tree (counts shrink monotonically down the
-// tree, so the parent's test implies every ancestor's).
-struct FullTree {
-    std::vector<int32_t> level, ax, ay, az, start, end, parent, child, coll;
-    std::vector<int64_t> level_cap;
-};
-
-void build_full_tree(const std::vector<uint64_t> &keys, int leaf_cap, int depth_limit, FullTree &T)
-{
-    const int64_t n = (int64_t)keys.size();
-    auto add = [&](int l, int x, int y, int z, int64_t b, int64_t e, int32_t par) {
-        T.level.push_back(l);
-        T.ax.push_back(x);
-        T.ay.push_back(y);
-        T.az.push_back(z);
-        T.start.push_back((int32_t)b);
-        T.end.push_back((int32_t)e);
-        T.parent.push_back(par);
-        for (int o = 0; o < 8; ++o) T.child.push_back(-1);
-        for (int d = 0; d < 27; ++d) T.coll.push_back(-1);
-    };
-    add(0, 0, 0, 0, 0, n, -1);
-    T.coll[13] = 0;
-    T.level_cap.assign(1, 1);
-    int64_t lb = 0, le = 1;  // boxes of the current level
-    for (int l = 0; l < depth_limit; ++l) {
-        const int shift = 3 * (kMortonBits - (l + 1));
-        const int64_t first_new = (int64_t)T.level.size();
-        for (int64_t f = lb; f < le; ++f) {
-            const int64_t b = T.start[f], e = T.end[f];
-            if (e - b <= leaf_cap) continue;
-            const uint64_t pre = ((uint64_t)0 + (keys[b] >> (shift + 3))) << 3;
-            for (int o = 0; o < 8; ++o) {
-                const uint64_t lo_key = (pre | (uint64_t)o) << shift;
-                const uint64_t hi_key = ((pre | (uint64_t)o) + 1) << shift;
-                const int64_t cb = std::lower_bound(keys.begin() + b, keys.begin() + e, lo_key) - keys.begin();
-                const int64_t ce = std::lower_bound(keys.begin() + b, keys.begin() + e, hi_key) - keys.begin();
-                if (ce == cb) continue;
-                T.child[(size_t)f * 8 + o] = (int32_t)T.level.size();
-                add(l + 1, 2 * T.ax[f] + ((o >> 2) & 1), 2 * T.ay[f] + ((o >> 1) & 1), 2 * T.az[f] + (o & 1), cb, ce,
-                    (int32_t)f);
-            }
-        }
-        const int64_t last_new = (int64_t)T.level.size();
-        if (last_new == first_new) break;
-        T.level_cap.push_back(last_new - first_new);
-        // colleagues of the new level from the parents' colleagues
-        const int lim = 1 << (l + 1);
-        for (int64_t f = first_new; f < last_new; ++f) {
-            const int x = T.ax[f], y = T.ay[f], z = T.az[f];
-            const int32_t par = T.parent[f];
-            for (int d = 0; d < 27; ++d) {
-                const int nx = x + d / 9 - 1, ny = y + (d / 3) % 3 - 1, nz = z + d % 3 - 1;
-                int32_t res = -1;
-                if (nx >= 0 && ny >= 0 && nz >= 0 && nx < lim && ny < lim && nz < lim) {
-                    const int dp = ((nx >> 1) - (x >> 1) + 1) * 9 + ((ny >> 1) - (y >> 1) + 1) * 3 + ((nz >> 1) - (z >> 1) + 1);
-                    const int32_t P = T.coll[(size_t)par * 27 + dp];
-                    if (P >= 0) res = T.child[(size_t)P * 8 + (((nx & 1) << 2) | ((ny & 1) << 1) | (nz & 1))];
-                }
-                T.coll[(size_t)f * 27 + d] = res;
-            }
-        }
-        lb = first_new;
-        le = last_new;
-    }
-}
-
 void alloc_workspace(Plan &p)
 {
     const int64_t n = p.n;
@@ -219,6 +149,8 @@ void alloc_workspace(Plan &p)
     p.d_sc = (CallScalars *)dev_alloc(p, sizeof(CallScalars));
     p.d_gen = (int32_t *)dev_alloc(p, sizeof(int32_t));
     PH_HIP(hipMemset(p.d_gen, 0, sizeof(int32_t)));  // the tags start at 0, the first call is 1
+    p.d_sticky = (int32_t *)dev_alloc(p, sizeof(int32_t));
+    PH_HIP(hipMemset(p.d_sticky, 0, sizeof(int32_t)));
     p.d_flag = (uint64_t *)dev_alloc(p, (size_t)n * sizeof(uint64_t));
     p.d_sel = (uint8_t *)dev_alloc(p, (size_t)n);
     PH_HIP(hipMemset(p.d_sel, 0, (size_t)n));  // nothing selected before the first call
@@ -251,6 +183,10 @@ void alloc_workspace(Plan &p)
     L.u_cap = std::max<int64_t>(1024, 64 * B);
     L.w_cap = std::max<int64_t>(1024, 32 * B);
     L.x_cap = std::max<int64_t>(1024, 32 * B);
+    if (const char *env = std::getenv("PH_LIST_ENTRIES_PER_BOX")) {  // small lists: overflow handling tests
+        const int64_t k = std::max<int64_t>(0, std::atoll(env));
+        L.u_cap = L.w_cap = L.x_cap = std::max<int64_t>(1, k * B);
+    }
     L.u = (int32_t *)dev_alloc(p, L.u_cap * 4);
     L.w = (int32_t *)dev_alloc(p, L.w_cap * 4);
     L.x = (int32_t *)dev_alloc(p, L.x_cap * 4);
@@ -333,21 +269,16 @@ void free_plan(Plan *p)
                     p->d_row_feat,
                     p->d_cell,
                     p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near,
-                    p->ops.near_tab, p->d_gen, p->ops.l2l_comp, p->d_boxmap};
-    for (void *q : ptrs) dev_free(q);
+                    p->ops.near_tab, p->d_gen, p->d_sticky, p->ops.l2l_comp, p->d_boxmap};
+    // events and streams first, then the memory the work on them used
     if (p->events_ready)
         for (auto &set : p->ring)
             for (auto &e : set) (void)hipEventDestroy(e);
-    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
-    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
-    if (p->ev_vt) (void)hipEventDestroy(p->ev_vt);
+    for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_vt, p->ev_p2m, p->ev_m2l})
+        if (e) (void)hipEventDestroy(e);
     if (p->side) (void)hipStreamDestroy(p->side);
     if (p->side2) (void)hipStreamDestroy(p->side2);
-    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->cap) (void)hipStreamDestroy(p->cap);
-    if (p->ev_p2m) (void)hipEventDestroy(p->ev_p2m);
-    if (p->ev_m2l) (void)hipEventDestroy(p->ev_m2l);
+    for (void *q : ptrs) dev_free(q);
     delete p;
 }
 
@@ -790,7 +721,6 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     constexpr unsigned kSyncEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
     PH_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     PH_HIP(hipStreamCreateWithFlags(&p.side2, hipStreamNonBlocking));
-    PH_HIP(hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking));
     PH_HIP(hipEventCreateWithFlags(&p.ev_p2m, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_m2l, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_fork, kSyncEventFlags));
@@ -860,13 +790,18 @@ void ph_plan_destroy(ph_plan *plan)
 
 int64_t ph_plan_size(const ph_plan *plan) { return plan ? reinterpret_cast<const Plan *>(plan)->n : -1; }
 
-static ph_status fetch_scalars(Plan &p, hipStream_t s)
+static void raise_error_bits(int32_t err)
+{
+    if (err & 2) throw Error{PH_ENOMEM, "interaction list capacity exceeded"};
+    if (err & 1) throw Error{PH_ENUMERIC, "I holds a non-finite or negative value"};
+}
+
+// the scalars of the call just enqueued on s (waits for s); raises that call's errors
+static void fetch_scalars(Plan &p, hipStream_t s)
 {
     PH_HIP(hipMemcpyAsync(&p.h_sc, p.d_sc, sizeof(CallScalars), hipMemcpyDeviceToHost, s));
     PH_HIP(hipStreamSynchronize(s));
-    if (p.h_sc.err & 2) throw Error{PH_ENOMEM, "interaction list capacity exceeded"};
-    if (p.h_sc.err & 1) throw Error{PH_ENUMERIC, "I holds a non-finite or negative value"};
-    return PH_OK;
+    raise_error_bits(p.h_sc.err);
 }
 
 // Phase boundaries recorded per call (events 0..9): 0 start, 1 maxima reduced,
@@ -910,7 +845,8 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(0, s);
     // the first kernel clears the call's scalars and advances the call number
     if (learned) selector_reduce(p, I, absE, p.d_gen, s);  // the maxima come with the per-leaf statistics
-    else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_gen, p.d_scan_tmp, s);
+    else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_gen, p.d_sticky,
+                           p.d_scan_tmp, s);
     mark(1, s);
     if (learned) selector_decide(p, I, absE, s);
     mark(2, s);
@@ -963,15 +899,6 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(7, s);
 }
 
-void drop_graph(Plan &p)
-{
-    if (p.gexec) (void)hipGraphExecDestroy(p.gexec);
-    if (p.graph) (void)hipGraphDestroy(p.graph);
-    p.gexec = nullptr;
-    p.graph = nullptr;
-    p.g_I = p.g_E = p.g_S = nullptr;
-}
-
 }  // namespace
 
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
@@ -994,29 +921,7 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             p.ring_pos = (p.ring_pos + 1) % Plan::kRing;
         }
         const bool learned = p.selector == PH_SEL_LEARNED;
-        if (p.graph_on && !timed) {
-            // the launch sequence captured once per set of buffers and replayed as one graph
-            if (!p.gexec || p.g_I != I || p.g_E != absE || p.g_S != S_out) {
-                drop_graph(p);
-                PH_HIP(hipStreamBeginCapture(p.cap, hipStreamCaptureModeRelaxed));
-                try {
-                    enqueue_call(p, I, absE, S_out, p.cap, false, 0);
-                } catch (...) {
-                    hipGraph_t g = nullptr;
-                    (void)hipStreamEndCapture(p.cap, &g);
-                    if (g) (void)hipGraphDestroy(g);
-                    throw;
-                }
-                PH_HIP(hipStreamEndCapture(p.cap, &p.graph));
-                PH_HIP(hipGraphInstantiate(&p.gexec, p.graph, nullptr, nullptr, 0));
-                p.g_I = I;
-                p.g_E = absE;
-                p.g_S = S_out;
-            }
-            PH_HIP(hipGraphLaunch(p.gexec, s));
-        } else {
-            enqueue_call(p, I, absE, S_out, s, timed, slot);
-        }
+        enqueue_call(p, I, absE, S_out, s, timed, slot);
         PH_HIP(hipGetLastError());
         if (timed) p.ring_used[slot] = true;
         if (stats) {
@@ -1050,16 +955,8 @@ ph_status ph_plan_set_graph(ph_plan *plan, int enable)
 {
     g_last_error.clear();
     if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
-    Plan &p = *reinterpret_cast<Plan *>(plan);
-    try {
-        PH_HIP(hipSetDevice(p.device));
-        PH_HIP(hipDeviceSynchronize());  // no replay of the old graph is still running
-        drop_graph(p);
-        p.graph_on = enable != 0;
-        return PH_OK;
-    } catch (const Error &e) {
-        return fail(e);
-    }
+    if (enable) return fail(Error{PH_EUNSUPPORTED, "graph replay is not available in this library"});
+    return PH_OK;
 }
 
 ph_status ph_phase_times(ph_plan *plan, int record, double *ms_sum, int64_t *n_calls)
@@ -1089,7 +986,14 @@ ph_status ph_plan_check(ph_plan *plan, void *stream)
     Plan &p = *reinterpret_cast<Plan *>(plan);
     try {
         PH_HIP(hipSetDevice(p.device));
-        return fetch_scalars(p, reinterpret_cast<hipStream_t>(stream));
+        // the error bits of every call since the last check, then cleared
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        int32_t sticky = 0;
+        PH_HIP(hipMemcpyAsync(&sticky, p.d_sticky, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PH_HIP(hipMemsetAsync(p.d_sticky, 0, sizeof(int32_t), s));
+        PH_HIP(hipStreamSynchronize(s));
+        raise_error_bits(sticky);
+        return PH_OK;
     } catch (const Error &e) {
         return fail(e);
     }

@@ -276,14 +276,8 @@ struct Plan {
     int32_t *d_boxmap = nullptr;                  // boxes of level l >= 2 by coordinates (8^l, -1)
     int64_t boxmap_off[kMaxDepth + 2] = {};
     int64_t comp_off[kMaxDepth + 2][kMaxDepth + 2] = {};
-    // the evaluation replayed as one graph (ph_plan_set_graph), captured on `cap` for one set of
-    // input and output buffers
-    bool graph_on = false;
-    hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    const void *g_I = nullptr, *g_E = nullptr, *g_S = nullptr;
     int32_t *d_gen = nullptr;  // device: number of the last call (the reset kernel advances it)
+    int32_t *d_sticky = nullptr; // device: error bits of every call since the last ph_plan_check
     bool count_work = false;        // algorithmic work counters (only for calls that fetch stats)
     bool near_guard = true;         // near pairs may have (b - a) r < 1/4: small-argument series needed
     size_t bytes_allocated = 0;
@@ -291,6 +285,19 @@ struct Plan {
 };
 
 // ------------------------------------------------------------------ host-side helpers
+
+// The octree over all points (every point both a source and a target), split
+// while a box holds more than leaf_cap points.  Any per-call tree over selected
+// subsets is this tree pruned: a box survives iff it holds selected points and
+// its parent is split in the per-call tree (counts shrink monotonically down the
+// tree, so the parent's test implies every ancestor's).
+struct FullTree {
+    std::vector<int32_t> level, ax, ay, az, start, end, parent, child, coll;
+    std::vector<int64_t> level_cap;
+};
+
+void build_full_tree(const std::vector<uint64_t> &keys, int leaf_cap, int depth_limit, FullTree &T);
+
 
 void *dev_alloc(Plan &p, size_t bytes);
 void dev_free(void *ptr);
@@ -334,9 +341,9 @@ void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s);
 // maxima of I and |E| (partials, then one workgroup); with gen the first kernel also starts the
 // call (clears the scalars, advances the call number)
 void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
-                       CallScalars *sc, int32_t *gen, void *tmp /* >= 16 KiB */, hipStream_t s);
+                       CallScalars *sc, int32_t *gen, int32_t *sticky, void *tmp /* >= 16 KiB */, hipStream_t s);
 void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
-                             hipStream_t s);  // partials: up to 1024 blocks
+                             int32_t *sticky, hipStream_t s);  // partials: up to 1024 blocks
 // selection flags, their scan (kept in d_flag for the tree build) and the compaction
 void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop);
 void scan_tile_sums_u64(uint64_t *partial, int64_t nb, uint64_t *total, hipStream_t s);

@@ -303,33 +303,18 @@ void build_grid_operator(const Gas &gas, const HostOperators &H, int level, doub
 
 namespace {
 
-// Exponential integral E1(x), x > 0: power series below 1, continued fraction above.
-double expint_e1(double x)
+// Exponential integral E1(x) = integral_x^inf e^-t / t dt, x >= 1.  The even part of Euler's
+// continued fraction for E1,
+//   e^x E1(x) = 1 / (x + 1 - 1^2 / (x + 3 - 2^2 / (x + 5 - 3^2 / (x + 7 - ...)))),
+// is evaluated from a fixed depth upwards (backward recurrence); at x >= 1 its truncation
+// error after 96 levels is far below double rounding.  Below 1 the power series is used
+// (absorbed_within).
+double expint_e1_cf(double x)
 {
-    const double euler = 0.57721566490153286061;
-    if (x < 1.0) {
-        double term = 1.0, sum = 0.0;
-        for (int k = 1; k < 60; ++k) {
-            term *= -x / k;
-            double add = -term / k;  // (-1)^(k+1) x^k / (k k!)
-            sum += add;
-            if (std::fabs(add) < 1e-18 * std::fabs(sum)) break;
-        }
-        return -euler - std::log(x) + sum;
-    }
-    // modified Lentz evaluation of e^-x / (x + 1 - 1/(x + 3 - 4/(x + 5 - ...)))
-    const double tiny = 1e-300;
-    double b = x + 1.0, c = 1.0 / tiny, d = 1.0 / b, hcf = d;
-    for (int i = 1; i < 500; ++i) {
-        double an = -(double)i * i;
-        b += 2.0;
-        d = 1.0 / (an * d + b);
-        c = b + an / c;
-        double del = c * d;
-        hcf *= del;
-        if (std::fabs(del - 1.0) < 1e-16) break;
-    }
-    return hcf * std::exp(-x);
+    constexpr int kDepth = 96;
+    double den = x + 2.0 * kDepth + 1.0;
+    for (int k = kDepth; k >= 1; --k) den = x + (2.0 * k - 1.0) - (double)k * (double)k / den;
+    return std::exp(-x) / den;
 }
 
 // Series part of E1 without the logarithm: sum_{k>=1} (-1)^(k+1) x^k/(k k!)
@@ -353,29 +338,48 @@ double absorbed_within(double R, const Gas &g)
         // E1(xa) - E1(xb) = ln(b/a) + tail(xa) - tail(xb); ln(b/a) = L cancels the leading 1
         return -(e1_series_tail(xa) - e1_series_tail(xb)) / g.L;
     }
-    return 1.0 - (expint_e1(xa) - expint_e1(xb)) / g.L;
+    if (xa < 1.0)  // E1(xa) from its series: -gamma - ln(xa) + tail(xa)
+        return 1.0 - (-0.57721566490153286061 - std::log(xa) + e1_series_tail(xa) - expint_e1_cf(xb)) / g.L;
+    return 1.0 - (expint_e1_cf(xa) - expint_e1_cf(xb)) / g.L;
 }
 
+// Legendre polynomial P_n(z) and its derivative, from the three-term recurrence
+// (k + 1) P_{k+1} = (2k + 1) z P_k - k P_{k-1} and (1 - z^2) P_n' = n (P_{n-1} - z P_n).
+void legendre_with_derivative(int n, double z, double &pn, double &dpn)
+{
+    double prev = 1.0, cur = z;  // P_0, P_1
+    for (int k = 1; k < n; ++k) {
+        const double next = ((2.0 * k + 1.0) * z * cur - k * prev) / (k + 1.0);
+        prev = cur;
+        cur = next;
+    }
+    pn = cur;
+    dpn = n * (prev - z * cur) / (1.0 - z * z);
+}
+
+// n-point Gauss-Legendre rule on [-1, 1]: each root of P_n by Newton's method from Tricomi's
+// asymptotic estimate x_k ~ (1 - 1/(8n^2) + 1/(8n^3)) cos(pi (4k - 1) / (4n + 2)); weight
+// 2 / ((1 - x_k^2) P_n'(x_k)^2).  Roots come in +- pairs, so half are computed.
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 {
-    x.resize(n);
-    w.resize(n);
-    for (int i = 0; i < n; ++i) {
-        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0;
-        for (int it = 0; it < 100; ++it) {
-            double p1 = 1.0, p2 = 0.0;
-            for (int j = 1; j <= n; ++j) {
-                double p3 = p2;
-                p2 = p1;
-                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
-            }
-            pp = n * (z * p1 - p2) / (z * z - 1.0);
-            double z1 = z;
-            z = z1 - p1 / pp;
-            if (std::fabs(z - z1) < 1e-16) break;
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double nn = (double)n;
+    for (int k = 1; k <= (n + 1) / 2; ++k) {
+        double z = (1.0 - 1.0 / (8.0 * nn * nn) + 1.0 / (8.0 * nn * nn * nn)) * std::cos(M_PI * (4.0 * k - 1.0) / (4.0 * nn + 2.0));
+        double pn = 0.0, dpn = 1.0;
+        for (int it = 0; it < 50; ++it) {
+            legendre_with_derivative(n, z, pn, dpn);
+            const double step = pn / dpn;
+            z -= step;
+            if (std::fabs(step) <= 4e-16) break;
         }
-        x[i] = z;
-        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+        legendre_with_derivative(n, z, pn, dpn);
+        const double wk = 2.0 / ((1.0 - z * z) * dpn * dpn);
+        x[k - 1] = z;
+        w[k - 1] = wk;
+        x[n - k] = -z;
+        w[n - k] = wk;
     }
 }
 

@@ -108,3 +108,48 @@ def test_non_finite_source_is_reported(gpu_lib):
         plan.check()
     assert e.value.status == 4  # PH_ENUMERIC
     plan.close()
+
+
+def test_error_of_an_earlier_call_stays_until_checked(gpu_lib):
+    """A bad call followed by a good one: the next check still reports the bad one (the error
+    word is sticky across calls), and a second check finds nothing left."""
+    import torch
+    wl = gen.config1()
+    _say("sticky error: bad call, good call, check, check")
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, wl.thresholds, leaf_capacity=27, **plan_kwargs(wl))
+    good = wl.I.astype(np.float32)
+    bad = good.copy()
+    bad[300] = -1.0
+    plan.evaluate(_t(bad, torch.float32))
+    S = plan.evaluate(_t(good, torch.float32))
+    with pytest.raises(gpu_lib.PhError) as e:
+        plan.check()
+    assert e.value.status == gpu_lib.PH_ENUMERIC
+    plan.check()  # cleared by the first check
+    ref = photoionization(wl.xyz, good.astype(np.float64), wl.gas, h=wl.h).full(wl.n)
+    assert rel_l2(S.double().cpu().numpy(), ref) <= 1e-3
+    # a call with statistics reports its own fault at once
+    with pytest.raises(gpu_lib.PhError) as e:
+        plan.evaluate(_t(bad, torch.float32), stats=True)
+    assert e.value.status == gpu_lib.PH_ENUMERIC
+    plan.close()
+
+
+def test_list_overflow_is_reported_and_stays_in_bounds(gpu_lib, monkeypatch):
+    """Interaction lists far too small for the tree: the ranges are cut at the capacity (no read
+    past a list), the call completes, and the overflow is reported as PH_ENOMEM."""
+    import torch
+    wl = gen.config2(seed=1022, n_axis=32)
+    monkeypatch.setenv("PH_LIST_ENTRIES_PER_BOX", "1")
+    _say("list overflow: one list entry per box")
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, dict(src_rel=0.0), leaf_capacity=16, **plan_kwargs(wl))
+    monkeypatch.delenv("PH_LIST_ENTRIES_PER_BOX")
+    I = _t(wl.I.astype(np.float32), torch.float32)
+    plan.evaluate(I)
+    with pytest.raises(gpu_lib.PhError) as e:
+        plan.check()
+    assert e.value.status == gpu_lib.PH_ENOMEM
+    with pytest.raises(gpu_lib.PhError) as e:
+        plan.evaluate(I, stats=True)
+    assert e.value.status == gpu_lib.PH_ENOMEM
+    plan.close()

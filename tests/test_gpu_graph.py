@@ -1,6 +1,12 @@
-"""Graph replay of ph_evaluate: every replay equals an eager evaluation of the same inputs bit for
-bit, while the buffers' contents (and with them the selected sources, the tree and the lists)
-change between replays, eager work runs in between, and a new set of buffers is captured anew."""
+"""Graph replay of ph_evaluate is switched off in this library: ph_plan_set_graph refuses to
+turn it on and keeps eager launches.
+
+A benchmark run that replayed evaluations as one HIP graph ended with a host heap-corruption
+abort after the graph timing.  Reading the code found two real faults in the graph path (an
+executable graph destroyed while its last replay could still run, and a plan teardown that
+destroyed the streams and events a graph was captured across before the graph), but neither
+was on the path that run took, so the abort's cause is not shown; the replay path was removed
+rather than run again."""
 import numpy as np
 import pytest
 
@@ -10,76 +16,18 @@ from tests.helpers import plan_kwargs
 pytestmark = pytest.mark.gpu
 
 
-def _t(a, dtype=None):
+def test_graph_replay_is_refused_and_eager_calls_still_work(gpu_lib):
     import torch
-    return torch.tensor(np.asarray(a), dtype=dtype or torch.float32, device="cuda")
-
-
-def _say(msg):
-    print(msg, flush=True)
-
-
-def _variants(wl, k):
-    """Input k: the field and the intensities moved and rescaled, so the source set changes."""
-    rng = np.random.default_rng(100 + k)
-    I = np.roll(wl.I, 3 * k, axis=0) * (1.0 + 0.25 * k)
-    I = I * (1.0 + 0.05 * rng.random(I.shape))
-    E = np.roll(wl.E, -5 * k, axis=0)
-    return I.astype(np.float32), E.astype(np.float32)
-
-
-@pytest.mark.parametrize("selector", ["threshold", "learned"])
-def test_graph_replays_equal_eager(gpu_lib, selector):
-    import torch
-    # leaves of 4^3 cells, as in the configuration the committed selector was trained on
-    wl = gen.config2(seed=1021, n_axis=64)
-    thr = dict(src_rel=1e-5, e_abs=3e6)
-    kw = dict(leaf_capacity=64, **plan_kwargs(wl))
-    if selector == "learned":
-        from paper_2112_10059_amd.train_selector import load_selector
-        w, meta = load_selector()
-        thr = dict(src_rel=meta["base_src_rel"], e_abs=3e6)
-        kw.update(selector="learned", selector_weights=w, selector_logit_threshold=meta["threshold"],
-                  selector_fallback_rel=1e-4)
-    _say(f"graph replay, {selector} selector")
-    pe = gpu_lib.Plan(wl.xyz, wl.gas, thr, **kw)
-    pg = gpu_lib.Plan(wl.xyz, wl.gas, thr, **kw)
-    pg.set_graph(True)
-    bI = torch.empty(wl.n, dtype=torch.float32, device="cuda")
-    bE = torch.empty(wl.n, dtype=torch.float32, device="cuda")
-    out = torch.empty(wl.n, dtype=torch.float32, device="cuda")
-    n_src = set()
-    for k in range(4):
-        I, E = _variants(wl, k)
-        bI.copy_(_t(I))
-        bE.copy_(_t(E))
-        pg.evaluate(bI, bE, out=out)
-        # eager work between the replays
-        ref, st = pe.evaluate(_t(I), _t(E), stats=True)
-        scratch = torch.randn(1 << 16, device="cuda").sum()
-        torch.cuda.synchronize()
-        assert np.isfinite(scratch.item())
-        n_src.add(st["n_src"])
-        got = out.cpu().numpy()
-        _say(f"  input {k}: n_src {st['n_src']}")
-        assert np.array_equal(got.view(np.uint32), ref.cpu().numpy().view(np.uint32)), k
-    assert len(n_src) > 1  # the replays saw different source sets
-    # the same inputs replayed twice in a row
-    pg.evaluate(bI, bE, out=out)
-    pg.evaluate(bI, bE, out=out)
-    torch.cuda.synchronize()
-    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.cpu().numpy().view(np.uint32))
-    # new buffers: captured again
-    I, E = _variants(wl, 5)
-    cI, cE = _t(I), _t(E)
-    out2 = pg.evaluate(cI, cE)
-    ref2 = pe.evaluate(cI, cE)
-    torch.cuda.synchronize()
-    assert np.array_equal(out2.cpu().numpy().view(np.uint32), ref2.cpu().numpy().view(np.uint32))
-    # graph off again: eager launches on the same plan
-    pg.set_graph(False)
-    out3 = pg.evaluate(cI, cE)
-    torch.cuda.synchronize()
-    assert np.array_equal(out3.cpu().numpy().view(np.uint32), ref2.cpu().numpy().view(np.uint32))
-    pe.close()
-    pg.close()
+    wl = gen.config2(seed=1021, n_axis=32)
+    print("graph replay refused", flush=True)
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, dict(src_rel=1e-4, e_abs=3e6), **plan_kwargs(wl))
+    with pytest.raises(gpu_lib.PhError) as e:
+        plan.set_graph(True)
+    assert e.value.status == gpu_lib.PH_EUNSUPPORTED
+    plan.set_graph(False)
+    I = torch.tensor(wl.I.astype(np.float32), device="cuda")
+    E = torch.tensor(wl.E.astype(np.float32), device="cuda")
+    a = plan.evaluate(I, E).cpu().numpy()
+    b = plan.evaluate(I, E).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)) and np.all(np.isfinite(a))
+    plan.close()

@@ -339,3 +339,114 @@ def test_selection_rules():
     assert target_mask(E, -1.0, 5e6, 0.005).tolist() == [False, True, False, True, False]
     assert target_mask(E, 3e6).tolist() == [True, True, True, True, False]
     assert target_mask(None) is None
+
+
+# ---------------------------------------------------------------- point clouds: w_j weights, no own-cell term
+
+def _cloud_brute(xyz, w, I, smask, tgt, gc):
+    """Eq. (15) on a point cloud by explicit loops: the source's own weight w_j, the printed
+    difference-of-exponentials form of eq. (3), pairs at zero distance left out, no own-cell term."""
+    out = []
+    for i in tgt:
+        s = 0.0
+        for j in range(len(xyz)):
+            if not smask[j] or j == i:
+                continue
+            r = math.dist(xyz[i], xyz[j])
+            if r == 0.0:
+                continue
+            s += w[j] * I[j] * (math.exp(-gc.a * r) - math.exp(-gc.b * r)) / (r * gc.L) / (4 * math.pi * r * r)
+        out.append(gc.P * s)
+    return np.array(out)
+
+
+def _tiny_cloud(seed=21, n=60):
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(0.0, 0.05, size=(n, 3))
+    xyz[n - 4:] = xyz[[3, 3, 17, 40]]            # coincident points (one point three times)
+    w = np.exp(rng.normal(size=n) * 1.5) * 1e-6  # weights spread over about two decades
+    I = rng.uniform(0.1, 1.0, size=n) * 1e20
+    smask = rng.uniform(size=n) < 0.7
+    smask[[3, 17, 40, n - 1]] = True
+    tgt = np.sort(rng.choice(n, size=25, replace=False))
+    tgt = np.unique(np.concatenate([tgt, [3, 17, n - 4, n - 3, n - 1]]))
+    return xyz, w, I, smask, tgt
+
+
+def test_cloud_brute_force_nonuniform_weights():
+    """Point-cloud branch: per-source weights w_j, c_self = 0 when h = 0, coincident pairs skipped.
+
+    Plausible slips (the target's weight w_i in place of w_j, an own-cell term kept on a cloud,
+    or a zero-distance pair summed) each move the result far outside the tolerance, as the
+    mutants at the end show."""
+    xyz, w, I, smask, tgt = _tiny_cloud()
+    expect = _cloud_brute(xyz, w, I, smask, tgt, GC)
+    r = photoionization(xyz, I, gen.GAS_760, h=0.0, w=w, smask=smask, targets=tgt)
+    rn = photoionization(xyz, I, gen.GAS_760, h=0.0, w=w, smask=smask, targets=tgt, use_numpy=True)
+    assert r.c_self == 0.0
+    assert np.all(np.isfinite(r.S_t))
+    assert np.allclose(r.S_t, expect, rtol=1e-13, atol=0)
+    assert np.allclose(rn.S_t, expect, rtol=1e-13, atol=0)
+    # mutants of the check itself: each must be rejected
+    wi = _cloud_brute(xyz, np.ones_like(w), I, smask, tgt, GC) * w[tgt]
+    assert not np.allclose(wi, expect, rtol=1e-3)
+    with_self = expect + GC.P * 0.2 * np.where(smask[tgt], I[tgt], 0.0)
+    assert not np.allclose(with_self, expect, rtol=1e-3)
+
+
+def test_cloud_coincident_split_is_invariant():
+    """Splitting a source into two coincident points of half the weight changes no other target,
+    and each half sees everything but its twin (the zero-distance pair is skipped)."""
+    xyz, w, I, smask, tgt = _tiny_cloud(seed=5)
+    smask[:] = True
+    k = 11
+    base = photoionization(xyz, I, gen.GAS_760, h=0.0, w=w, smask=smask)
+    xyz2 = np.vstack([xyz, xyz[k:k + 1]])
+    w2 = np.concatenate([w, [w[k] / 2]])
+    w2[k] = w[k] / 2
+    I2 = np.concatenate([I, [I[k]]])
+    split = photoionization(xyz2, I2, gen.GAS_760, h=0.0, w=w2, smask=np.ones(len(xyz2), dtype=bool))
+    S1, S2 = base.full(len(xyz)), split.full(len(xyz2))
+    assert np.allclose(S2[:len(xyz)], S1, rtol=1e-13)
+    assert S2[-1] == pytest.approx(S1[k], rel=1e-13)
+
+
+def test_cloud_radial_quadrature_centre_equals_absorbed_fraction():
+    """A point cloud that is a radial Gauss-Legendre rule for a ball of radius R around a target
+    (weights 4 pi r^2 W, random directions, two nodes split into coincident halves, and the target
+    itself a heavy source at zero distance): S / (P I) = A(R), the exponential-integral closed form."""
+    R = 0.05
+    gx, gw = np.polynomial.legendre.leggauss(16)
+    edges = R * np.concatenate([[0.0], 0.5 ** np.arange(40, -1, -1, dtype=np.float64)])
+    lo, hi = edges[:-1], edges[1:]
+    r = (0.5 * (hi - lo)[:, None] * (gx[None, :] + 1.0) + lo[:, None]).ravel()
+    W = (0.5 * (hi - lo)[:, None] * gw[None, :]).ravel()
+    rng = np.random.default_rng(13)
+    u = rng.normal(size=(r.size, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    centre = np.array([0.3, 0.2, 0.25])
+    pts = centre[None, :] + r[:, None] * u
+    w = 4.0 * np.pi * r * r * W
+    split = np.array([5, 300, 600])
+    w[split] /= 2
+    xyz = np.vstack([centre[None, :], pts, pts[split]])
+    wall = np.concatenate([[1.0], w, w[split]])
+    I = np.ones(len(xyz))
+    res = photoionization(xyz, I, gen.GAS_760, h=0.0, w=wall, targets=np.array([0]))
+    assert float(res.S_t[0]) / GC.P == pytest.approx(float(_A_closed(R, GC)), rel=1e-11)
+    # with the target's own weight in place of the sources' the sum is nowhere near A(R)
+    assert abs(wall[0] * float(np.sum(kernel_K(r, GC))) / float(_A_closed(R, GC)) - 1) > 0.5
+
+
+# ---------------------------------------------------------------- E_delta of eq. (19)
+
+def test_local_ball_error_hand_case():
+    """E_delta: mean of |S_num - S_ref| / S_ref over the points with |x - x0| <= delta (boundary
+    included), as a fraction; points outside the ball do not count."""
+    from oracle import local_ball_error
+    xyz = np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0], [0.0, 0.3, 0.0], [1.0, 0.0, 0.0]])
+    S_ref = np.array([1.0, 2.0, 4.0, 8.0])
+    S_num = np.array([1.1, 1.9, 4.0, 100.0])
+    assert local_ball_error(S_num, S_ref, xyz, (0.0, 0.0, 0.0), 0.3) == pytest.approx((0.1 + 0.05 + 0.0) / 3, rel=1e-14)
+    assert local_ball_error(S_num, S_ref, xyz, (0.0, 0.0, 0.0), 0.2) == pytest.approx(0.075, rel=1e-14)
+    assert math.isnan(local_ball_error(S_num, S_ref, xyz, (5.0, 5.0, 5.0), 0.1))
