@@ -256,6 +256,19 @@ ph_status ph_mlp_forward(const float *params, const float *X, int64_t m, float *
 ph_status ph_mlp_backward(const float *params, const float *X, const float *y, float pos_weight,
                           int64_t m, float *grad, float *loss, void *stream);
 
+/*
+ * ph_mlp_backward for callers that cannot allocate device memory (code under stream capture,
+ * tight training loops, hosts that forbid allocation): the same result bit for bit, with the
+ * per-block gradient partials in a fixed array inside the library (4.9 MB per GPU, kept until
+ * the process ends) instead of memory allocated at the call.  It makes no allocation of any
+ * kind.  m must be in 1..PH_MLP_NOALLOC_MAX_ROWS (else PH_EINVAL, nothing launched).  Every
+ * call on one GPU shares that array, so calls that overlap on one GPU (different streams or
+ * host threads) race; calls ordered on one stream do not.
+ */
+#define PH_MLP_NOALLOC_MAX_ROWS 8192
+ph_status ph_mlp_backward_noalloc(const float *params, const float *X, const float *y, float pos_weight,
+                                  int64_t m, float *grad, float *loss, void *stream);
+
 /* One Adam step (bias-corrected, step >= 1) on nparam values in place. */
 ph_status ph_adam_step(float *params, float *m1, float *m2, const float *grad, int64_t nparam,
                        float lr, float beta1, float beta2, float eps, int64_t step, void *stream);

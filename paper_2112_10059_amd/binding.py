@@ -69,7 +69,7 @@ WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pa
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
             "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_fields",
-            "ph_plan_set_graph"]
+            "ph_plan_set_graph", "ph_mlp_backward_noalloc"]
 
 _lib = None
 
@@ -120,6 +120,8 @@ def load(path: Optional[str] = None):
     lib.ph_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int, vp]
     lib.ph_mlp_backward.restype = ctypes.c_int
     lib.ph_mlp_backward.argtypes = [vp, vp, vp, ctypes.c_float, ctypes.c_int64, vp, vp, vp]
+    lib.ph_mlp_backward_noalloc.restype = ctypes.c_int
+    lib.ph_mlp_backward_noalloc.argtypes = [vp, vp, vp, ctypes.c_float, ctypes.c_int64, vp, vp, vp]
     lib.ph_adam_step.restype = ctypes.c_int
     lib.ph_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_int64, vp]
@@ -283,6 +285,17 @@ def mlp_backward(params, X, y, pos_weight: float, grad=None, loss=None, stream=N
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
     _check(load().ph_mlp_backward(_dptr(params), _dptr(X), _dptr(y), float(pos_weight), X.shape[0], _dptr(grad),
                                   _dptr(loss), _stream_ptr(stream)))
+    return grad, loss
+
+
+MLP_NOALLOC_MAX_ROWS = 8192
+
+
+def mlp_backward_noalloc(params, X, y, pos_weight: float, grad, loss, stream=None):
+    """ph_mlp_backward without any allocation: grad (MLP_NPARAM floats) and loss (1 float) are
+    caller-provided device tensors; at most MLP_NOALLOC_MAX_ROWS rows."""
+    _check(load().ph_mlp_backward_noalloc(_dptr(params), _dptr(X), _dptr(y), float(pos_weight), X.shape[0],
+                                          _dptr(grad), _dptr(loss), _stream_ptr(stream)))
     return grad, loss
 
 

@@ -237,6 +237,34 @@ std::mutex g_partial_mutex;
 float *g_partial = nullptr;
 size_t g_partial_bytes = 0;
 
+// Gradient partials of the allocation-free backward call: kNoAllocMaxBlocks blocks of
+// NP + 1 floats (4.9 MB), in the code object's own device memory on every GPU the library
+// runs on, held until the process ends.  Host code never passes this name to a kernel: its
+// device address, looked up once per device, is what the launches take.
+constexpr int kNoAllocMaxBlocks = PH_MLP_NOALLOC_MAX_ROWS / kRows;
+static_assert(PH_MLP_NOALLOC_MAX_ROWS % kRows == 0, "whole blocks of rows");
+static __device__ __align__(256) float scratch[(size_t)kNoAllocMaxBlocks * (NP + 1)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (looked up at the first call there)
+float *scratch_on_current_device()
+{
+    int dev = 0;
+    PH_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error{PH_EDEVICE, "device index beyond the scratch table"};
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        PH_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error{PH_EDEVICE, "no device address for the backward scratch"};
+        g_scratch_ptr[dev] = static_cast<float *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 void launch_mlp_forward(const float *params, const float *X, int64_t m, const int32_t *m_dev, float *logits,
@@ -266,6 +294,17 @@ void launch_mlp_backward(const float *params, const float *X, const float *y, fl
     }
     mlp_backward_kernel<<<nblocks, 256, 0, s>>>(params, X, y, pos_weight, m, g_partial);
     mlp_reduce_kernel<<<(NP + 1 + 255) / 256, 256, 0, s>>>(g_partial, nblocks, grad, loss);
+}
+
+void launch_mlp_backward_noalloc(const float *params, const float *X, const float *y, float pos_weight, int64_t m,
+                                 float *grad, float *loss, hipStream_t s)
+{
+    if (m < 1 || m > PH_MLP_NOALLOC_MAX_ROWS) throw Error{PH_EINVAL, "rows must be in 1..PH_MLP_NOALLOC_MAX_ROWS"};
+    float *part = scratch_on_current_device();
+    const int nblocks = (int)((m + kRows - 1) / kRows);
+    // every block writes its whole partial (rows past m count zero), so nothing needs clearing
+    mlp_backward_kernel<<<nblocks, 256, 0, s>>>(params, X, y, pos_weight, m, part);
+    mlp_reduce_kernel<<<(NP + 1 + 255) / 256, 256, 0, s>>>(part, nblocks, grad, loss);
 }
 
 void launch_adam(float *params, float *m1, float *m2, const float *grad, int64_t n, float lr, float b1, float b2,

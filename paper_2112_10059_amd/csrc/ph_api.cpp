@@ -1126,6 +1126,21 @@ ph_status ph_mlp_backward(const float *params, const float *X, const float *y, f
     }
 }
 
+ph_status ph_mlp_backward_noalloc(const float *params, const float *X, const float *y, float pos_weight, int64_t m,
+                                  float *grad, float *loss, void *stream)
+{
+    g_last_error.clear();
+    if (!params || !X || !y || !grad || !loss || !(pos_weight > 0))
+        return fail(Error{PH_EINVAL, "bad mlp_backward_noalloc arguments"});
+    try {
+        launch_mlp_backward_noalloc(params, X, y, pos_weight, m, grad, loss, reinterpret_cast<hipStream_t>(stream));
+        PH_HIP(hipGetLastError());
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
 ph_status ph_adam_step(float *params, float *m1, float *m2, const float *grad, int64_t nparam, float lr,
                        float beta1, float beta2, float eps, int64_t step, void *stream)
 {

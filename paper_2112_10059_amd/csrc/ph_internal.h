@@ -386,6 +386,9 @@ void launch_mlp_forward(const float *params, const float *X, int64_t m, const in
                         int bf16, hipStream_t s);
 void launch_mlp_backward(const float *params, const float *X, const float *y, float pos_weight,
                          int64_t m, float *grad, float *loss, hipStream_t s);
+// the same with the block partials in the library's static device scratch (no allocation)
+void launch_mlp_backward_noalloc(const float *params, const float *X, const float *y, float pos_weight,
+                                 int64_t m, float *grad, float *loss, hipStream_t s);
 void launch_adam(float *params, float *m1, float *m2, const float *grad, int64_t nparam, float lr,
                  float b1, float b2, float eps, int64_t step, hipStream_t s);
 
