@@ -28,8 +28,10 @@
  *  - stream is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work of a call is enqueued on it; the call returns without
  *    waiting unless stated otherwise.
- *  - A plan is not safe for concurrent ph_evaluate calls (it owns one
- *    per-call workspace).
+ *  - A plan owns one per-call workspace: ph_evaluate calls on it must not overlap on the
+ *    device (keep them on one stream, or order their streams).  Calls that bring their own
+ *    workspace (ph_evaluate_ws) may overlap each other and the plan's own calls.  Host
+ *    calls on one plan from several threads are serialised by a lock in the plan.
  */
 #ifndef PH_H_
 #define PH_H_
@@ -116,6 +118,12 @@ typedef struct {
     double selector_fallback_rel;  /* source rule I >= rel * max I used when the learned
                                       selector falls back; 0 => 1e-4                         */
     size_t workspace_cap_bytes;    /* 0 => unlimited                                           */
+    int validate;           /* learned selector only: 1 => every call also runs the plain FMM under
+                               the threshold rule (selector_fallback_rel) and keeps the learned
+                               result only if ||S_learned - S_threshold||_2 <= tol ||S_threshold||_2,
+                               else returns the threshold result and reports the fallback        */
+    double tol;             /* that tolerance; 0 with validate = 1 keeps only identical results;
+                               default (0, validate = 0) 1e-3                                   */
 } ph_options;
 
 #define PH_NPHASES 12
@@ -136,6 +144,8 @@ typedef struct {
                                with a non-empty U list (those the near-field kernel visits),
                                [11] those of the near pairs ([0]) whose kernel value is read from
                                the uniform-grid table of cell offsets                           */
+    double check_rel_l2;    /* validated learned calls: ||S_learned - S_threshold|| / ||S_threshold||
+                               as measured on the device; -1 otherwise                           */
 } ph_stats;
 
 /* Returns a static description of a status code. */
@@ -182,6 +192,39 @@ void ph_plan_destroy(ph_plan *plan);
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);
+
+/*
+ * Size in bytes of the per-call workspace of ph_evaluate_ws (0 for NULL).  Every per-call
+ * array of the hot path lives in it: selection flags and compacted records, the per-call
+ * tree and interaction lists, equivalent densities and check values, translation products,
+ * the near field, the learned selector's rows, and the threshold-rule field of a validated
+ * call.
+ */
+size_t ph_evaluate_workspace_bytes(const ph_plan *plan);
+
+/*
+ * ph_evaluate with a caller-owned workspace (device, ph_evaluate_workspace_bytes bytes,
+ * 256-byte aligned; torch allocations are).  The workspace must be all zero before its first
+ * call with this plan and must not be written by the caller between calls: it carries the
+ * call number and the box tags that let the lists skip clearing.  It may be reused across
+ * calls of the same plan only.  Calls with distinct workspaces may run concurrently on
+ * different streams (their device work overlaps, except the list building and near field,
+ * which share the plan's second and third streams and run one call after the other).
+ * Results are bit-identical to ph_evaluate.  Errors as ph_evaluate, plus PH_EINVAL for a
+ * null or misaligned workspace.
+ */
+ph_status ph_evaluate_ws(ph_plan *plan, const void *I, const float *absE, void *S_out, void *workspace,
+                         void *stream, ph_stats *stats);
+
+/*
+ * Demand-oriented target set (Sec. 3, second strategy: only the points where S_ph is needed,
+ * e.g. a cross-section or a line of interest, Sec. 4.1).  mask: host, n bytes in caller order,
+ * nonzero = the point may be a target; every later call evaluates S only there (intersected
+ * with the field rules of the thresholds, if on) and writes 0 elsewhere.  NULL restores "every
+ * point".  n must equal the plan's point count.  Waits for the device; must not run while a
+ * call on the plan is still executing on another thread's stream.
+ */
+ph_status ph_plan_set_targets(ph_plan *plan, const uint8_t *mask, int64_t n);
 
 /*
  * Graph replay of ph_evaluate: not available in this library.  enable = 0 returns

@@ -52,14 +52,14 @@ class PhOptions(ctypes.Structure):
                 ("order_q", ctypes.c_int), ("leaf_capacity", ctypes.c_int), ("max_depth", ctypes.c_int),
                 ("pinv_rel_cutoff", ctypes.c_double), ("selector_weights", ctypes.POINTER(ctypes.c_float)),
                 ("selector_logit_threshold", ctypes.c_float), ("selector_fallback_rel", ctypes.c_double),
-                ("workspace_cap_bytes", ctypes.c_size_t)]
+                ("workspace_cap_bytes", ctypes.c_size_t), ("validate", ctypes.c_int), ("tol", ctypes.c_double)]
 
 
 class PhStats(ctypes.Structure):
     _fields_ = [("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64), ("n_boxes", ctypes.c_int64),
                 ("n_leaves", ctypes.c_int64), ("levels", ctypes.c_int32), ("fell_back", ctypes.c_int32),
                 ("n_src_dropped", ctypes.c_int64), ("t_ms", ctypes.c_double * NPHASES),
-                ("work", ctypes.c_int64 * 12)]
+                ("work", ctypes.c_int64 * 12), ("check_rel_l2", ctypes.c_double)]
 
 
 WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pairs", "m2m_children",
@@ -69,7 +69,8 @@ WORK = ("p2p_pairs", "l2p_evals", "m2p_evals", "p2m_evals", "p2l_evals", "m2l_pa
 EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_create", "ph_plan_destroy",
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
             "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_fields",
-            "ph_plan_set_graph", "ph_mlp_backward_noalloc"]
+            "ph_plan_set_graph", "ph_mlp_backward_noalloc", "ph_evaluate_workspace_bytes", "ph_evaluate_ws",
+            "ph_plan_set_targets"]
 
 _lib = None
 
@@ -108,6 +109,12 @@ def load(path: Optional[str] = None):
     lib.ph_plan_destroy.argtypes = [vp]
     lib.ph_evaluate.restype = ctypes.c_int
     lib.ph_evaluate.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(PhStats)]
+    lib.ph_evaluate_workspace_bytes.restype = ctypes.c_size_t
+    lib.ph_evaluate_workspace_bytes.argtypes = [vp]
+    lib.ph_evaluate_ws.restype = ctypes.c_int
+    lib.ph_evaluate_ws.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(PhStats)]
+    lib.ph_plan_set_targets.restype = ctypes.c_int
+    lib.ph_plan_set_targets.argtypes = [vp, vp, ctypes.c_int64]
     lib.ph_plan_set_graph.restype = ctypes.c_int
     lib.ph_plan_set_graph.argtypes = [vp, ctypes.c_int]
     lib.ph_plan_check.restype = ctypes.c_int
@@ -169,7 +176,8 @@ class Plan:
                  cube_lo=None, cube_size: float = 0.0, precision: str = "fp32", method: str = "fmm",
                  selector: str = "threshold", order_q: int = 0, leaf_capacity: int = 0, max_depth: int = 0,
                  pinv_rel_cutoff: float = 0.0, selector_weights=None, selector_logit_threshold: float = 0.0,
-                 selector_fallback_rel: float = 0.0, workspace_cap: int = 0):
+                 selector_fallback_rel: float = 0.0, workspace_cap: int = 0, validate: bool = False,
+                 tol: float = 0.0):
         lib = load()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.n = int(self._xyz.shape[0])
@@ -199,6 +207,8 @@ class Plan:
         opt.selector_logit_threshold = float(selector_logit_threshold)
         opt.selector_fallback_rel = float(selector_fallback_rel)
         opt.workspace_cap_bytes = int(workspace_cap)
+        opt.validate = 1 if validate else 0
+        opt.tol = float(tol)
         self.precision = precision
         self.thresholds = dict(thresholds)
         handle = ctypes.c_void_p()
@@ -213,20 +223,42 @@ class Plan:
         import torch
         return torch.float64 if self.precision == "fp64" else torch.float32
 
-    def evaluate(self, I, E=None, out=None, stream=None, stats: bool = False):
-        """S_ph for device tensors I (dtype of the plan) and |E| (float32 or None)."""
+    def workspace_bytes(self) -> int:
+        return int(_lib.ph_evaluate_workspace_bytes(self._h))
+
+    def new_workspace(self, device="cuda"):
+        """A zero-filled workspace for evaluate(workspace=...)."""
+        import torch
+        return torch.zeros(self.workspace_bytes(), dtype=torch.uint8, device=device)
+
+    def evaluate(self, I, E=None, out=None, stream=None, stats: bool = False, workspace=None):
+        """S_ph for device tensors I (dtype of the plan) and |E| (float32 or None); with a
+        workspace (from new_workspace) the call runs on it (ph_evaluate_ws)."""
         import torch
         if out is None:
             out = torch.empty(self.n, dtype=self.dtype, device=I.device)
         st = PhStats() if stats else None
-        _check(_lib.ph_evaluate(self._h, _dptr(I), _dptr(E), _dptr(out), _stream_ptr(stream),
-                                ctypes.byref(st) if stats else None))
+        if workspace is None:
+            _check(_lib.ph_evaluate(self._h, _dptr(I), _dptr(E), _dptr(out), _stream_ptr(stream),
+                                    ctypes.byref(st) if stats else None))
+        else:
+            _check(_lib.ph_evaluate_ws(self._h, _dptr(I), _dptr(E), _dptr(out), _dptr(workspace),
+                                       _stream_ptr(stream), ctypes.byref(st) if stats else None))
         if stats:
             return out, {"n_src": st.n_src, "n_tgt": st.n_tgt, "n_boxes": st.n_boxes, "n_leaves": st.n_leaves,
                          "levels": st.levels,
                          "fell_back": st.fell_back, "n_src_dropped": st.n_src_dropped,
-                         "t_ms": list(st.t_ms), "work": dict(zip(WORK, list(st.work)))}
+                         "t_ms": list(st.t_ms), "work": dict(zip(WORK, list(st.work))),
+                         "check_rel_l2": st.check_rel_l2}
         return out
+
+    def set_targets(self, mask=None):
+        """Caller-supplied target set (boolean array over the points, caller order), or None for all."""
+        if mask is None:
+            _check(_lib.ph_plan_set_targets(self._h, None, 0))
+            return
+        self._tmask = np.ascontiguousarray(np.asarray(mask, dtype=bool).astype(np.uint8).ravel())
+        _check(_lib.ph_plan_set_targets(self._h, self._tmask.ctypes.data_as(ctypes.c_void_p), self._tmask.size))
 
     def set_graph(self, enable: bool = True):
         """Later evaluate() calls without stats run as one replayed HIP graph (per set of buffers)."""

@@ -108,11 +108,12 @@ struct SelectParams {
 
 // Selection flags of sorted point k (bit 0 source, bit 1 target).  drop: per sorted point, 1
 // if a learned decision removed its source leaf (null: none).  When the selector has fallen
-// back (sc->fallback) the source rule is fallback_rel instead.
+// back (sc->fallback) the source rule is fallback_rel instead.  tmask: the caller's target set
+// per sorted point (null: every point), intersected with the field rules.
 template <class T>
 __device__ __forceinline__ uint32_t select_one(const T *__restrict__ I, const float *__restrict__ E, int32_t o,
                                                int64_t k, const SelectParams &sp, const CallScalars *__restrict__ sc,
-                                               const uint8_t *__restrict__ drop)
+                                               const uint8_t *__restrict__ drop, const uint8_t *__restrict__ tmask)
 {
     const double v = (double)I[o];
     bool src;
@@ -122,7 +123,7 @@ __device__ __forceinline__ uint32_t select_one(const T *__restrict__ I, const fl
         src = (sp.src_rel <= 0.0) || (v >= sp.src_rel * sc->imax);
         if (drop) src = src && !drop[k];
     }
-    bool tgt = true;
+    bool tgt = tmask ? tmask[k] != 0 : true;
     if (E) {
         const double e = (double)E[o];
         if (sp.e_abs >= 0.0) tgt = tgt && (e >= sp.e_abs);
@@ -149,7 +150,8 @@ template <class T>
 __global__ __launch_bounds__(64 * kSelWaves) void select_tiles_kernel(const T *__restrict__ I, const float *__restrict__ E,
                                                            const int32_t *__restrict__ perm, int64_t n,
                                                            SelectParams sp, const CallScalars *__restrict__ sc,
-                                                           const uint8_t *__restrict__ drop, uint8_t *__restrict__ sel,
+                                                           const uint8_t *__restrict__ drop,
+                                                           const uint8_t *__restrict__ tmask, uint8_t *__restrict__ sel,
                                                            T *__restrict__ S_out, uint64_t *__restrict__ partial)
 {
     __shared__ uint64_t wsum[kSelWaves];
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_tiles_kernel(const T *_
     for (int st = 0; st < kSelStrips; ++st) {
         const int64_t k = base + st * 64 + lane;
         if (k < n) {
-            const uint32_t f = select_one(I, E, o[st], k, sp, sc, drop);
+            const uint32_t f = select_one(I, E, o[st], k, sp, sc, drop, tmask);
             sel[k] = (uint8_t)f;
             if (!(f & 2u)) S_out[o[st]] = T(0);
             acc += packed_of(f);
@@ -341,25 +343,27 @@ void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, in
     reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, blocks, sc, sticky);
 }
 
-static SelectParams params_of(const Plan &p)
+static SelectParams params_of(const Plan &p, double src_rel)
 {
-    return SelectParams{p.thr.src_rel, p.thr.e_abs, p.thr.e_applied, p.thr.e_rel, p.fallback_rel};
+    return SelectParams{src_rel >= 0.0 ? src_rel : p.thr.src_rel, p.thr.e_abs, p.thr.e_applied, p.thr.e_rel,
+                        p.fallback_rel};
 }
 
-void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop)
+void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop,
+                   double src_rel)
 {
     const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
     if (p.n <= 0) return;
     const int64_t nb = (p.n + kSelTile - 1) / kSelTile;
     uint64_t *partial = (uint64_t *)p.d_scan_tmp;
-    const SelectParams sp = params_of(p);
+    const SelectParams sp = params_of(p, src_rel);
     if (p.precision == PH_FP64)
         select_tiles_kernel<double><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>((const double *)I, need_e ? E : nullptr, p.d_perm,
-                                                                  p.n, sp, p.d_sc, drop, p.d_sel, (double *)S_out,
+                                                                  p.n, sp, p.d_sc, drop, p.d_tmask, p.d_sel, (double *)S_out,
                                                                   partial);
     else
         select_tiles_kernel<float><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>((const float *)I, need_e ? E : nullptr, p.d_perm,
-                                                                 p.n, sp, p.d_sc, drop, p.d_sel, (float *)S_out,
+                                                                 p.n, sp, p.d_sc, drop, p.d_tmask, p.d_sel, (float *)S_out,
                                                                  partial);
     // up to 2048 tiles the compaction adds up the earlier tiles' sums itself; beyond, one
     // workgroup scans them first
@@ -375,6 +379,86 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
             (const float *)I, p.d_perm, p.d_xyzf, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
             partial, nb, tile_sums, p.method == PH_METHOD_DIRECT ? 1 : 0, p.d_flag, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
             p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
+}
+
+// ---------------------------------------------------------------- validation of a learned call
+//
+// The learned result S_l (in S_out) against the threshold rule's S_t (the plain FMM of the
+// same call): rel = ||S_l - S_t||_2 / ||S_t||_2 over every point (non-targets are 0 in both),
+// summed in FP64 in a fixed order.  If rel > tol, or rel is not finite, the threshold result
+// replaces the learned one and the call counts as fallen back.
+
+namespace {
+
+constexpr int kValBlocks = 512;
+
+template <class T>
+__global__ __launch_bounds__(256) void validate_partials_kernel(const T *__restrict__ Sl, const T *__restrict__ Sr,
+                                                                int64_t n, double *__restrict__ partial)
+{
+    __shared__ double sd[256], sr[256];
+    double d2 = 0.0, r2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)Sl[i], b = (double)Sr[i];
+        d2 += (a - b) * (a - b);
+        r2 += b * b;
+    }
+    sd[threadIdx.x] = d2;
+    sr[threadIdx.x] = r2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sd[threadIdx.x] += sd[threadIdx.x + o];
+            sr[threadIdx.x] += sr[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sd[0];
+        partial[2 * blockIdx.x + 1] = sr[0];
+    }
+}
+
+// every workgroup reduces the partials (the same order, so the same decision), then copies
+template <class T>
+__global__ __launch_bounds__(256) void validate_apply_kernel(T *__restrict__ Sl, const T *__restrict__ Sr, int64_t n,
+                                                             const double *__restrict__ partial, int nb, double tol,
+                                                             CallScalars *__restrict__ sc)
+{
+    __shared__ double rel_s;
+    if (threadIdx.x == 0) {
+        double d2 = 0.0, r2 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            d2 += partial[2 * b];
+            r2 += partial[2 * b + 1];
+        }
+        rel_s = r2 > 0.0 ? sqrt(d2 / r2) : (d2 > 0.0 ? INFINITY : 0.0);
+        if (blockIdx.x == 0) sc->check_rel = rel_s;
+    }
+    __syncthreads();
+    const double rel = rel_s;
+    const bool back = !(rel <= tol);
+    if (!back) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->fallback = 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        Sl[i] = Sr[i];
+}
+
+}  // namespace
+
+void launch_validate(const Plan &p, void *S_out, const void *S_ref, double tol, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>(kValBlocks, (p.n + 255) / 256);
+    double *partial = reinterpret_cast<double *>(p.d_scan_tmp);
+    if (p.precision == PH_FP64) {
+        validate_partials_kernel<double><<<nb, 256, 0, s>>>((const double *)S_out, (const double *)S_ref, p.n, partial);
+        validate_apply_kernel<double><<<nb, 256, 0, s>>>((double *)S_out, (const double *)S_ref, p.n, partial, nb, tol,
+                                                         p.d_sc);
+    } else {
+        validate_partials_kernel<float><<<nb, 256, 0, s>>>((const float *)S_out, (const float *)S_ref, p.n, partial);
+        validate_apply_kernel<float><<<nb, 256, 0, s>>>((float *)S_out, (const float *)S_ref, p.n, partial, nb, tol,
+                                                        p.d_sc);
+    }
 }
 
 }  // namespace ph

@@ -3,7 +3,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <thread>
 #include <vector>
@@ -139,47 +141,20 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
         if (!std::isfinite(opt->selector_logit_threshold)) bad("selector_logit_threshold must be finite");
         if (!(opt->selector_fallback_rel >= 0) || opt->selector_fallback_rel > 1)
             bad("selector_fallback_rel must be in [0, 1]");
+        if (!(opt->tol >= 0) || !std::isfinite(opt->tol)) bad("options.tol must be finite and >= 0");
     }
 }
 
-void alloc_workspace(Plan &p)
+// Capacities of the per-call arrays (lists, translation buffers, scan space): fixed per plan.
+void size_workspace(Plan &p)
 {
     const int64_t n = p.n;
     const size_t rs = p.precision == PH_FP64 ? sizeof(double) : sizeof(float);
-    p.d_sc = (CallScalars *)dev_alloc(p, sizeof(CallScalars));
-    p.d_gen = (int32_t *)dev_alloc(p, sizeof(int32_t));
-    PH_HIP(hipMemset(p.d_gen, 0, sizeof(int32_t)));  // the tags start at 0, the first call is 1
-    p.d_sticky = (int32_t *)dev_alloc(p, sizeof(int32_t));
-    PH_HIP(hipMemset(p.d_sticky, 0, sizeof(int32_t)));
-    p.d_flag = (uint64_t *)dev_alloc(p, (size_t)n * sizeof(uint64_t));
-    p.d_sel = (uint8_t *)dev_alloc(p, (size_t)n);
-    PH_HIP(hipMemset(p.d_sel, 0, (size_t)n));  // nothing selected before the first call
+    const int64_t B = p.box_cap;
     // also the list build's per-workgroup totals (3 words per 256 boxes)
     p.scan_tmp_bytes = std::max({scan_tmp_bytes(n, 8), scan_tmp_bytes(p.box_cap + 1, 4),
                                  (size_t)12 * ((p.box_cap + 255) / 256) + 256, (size_t)16 * kLeafPartials});
-    p.d_scan_tmp = dev_alloc(p, p.scan_tmp_bytes);
-    p.d_t_out = (int32_t *)dev_alloc(p, (size_t)n * 4);
-    p.d_s_dat = dev_alloc(p, (size_t)n * 4 * rs);
-    p.d_t_dat = dev_alloc(p, (size_t)n * 4 * rs);
-    p.d_t_near = (double *)dev_alloc(p, (size_t)n * 8);
-    if (p.grid_mode) {
-        p.d_s_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
-        p.d_t_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
-    }
-    const int64_t B = p.box_cap;
-    BoxArrays &b = p.box;
-    b.s_first = (int32_t *)dev_alloc(p, B * 4);
-    b.s_cnt = (int32_t *)dev_alloc(p, B * 4);
-    b.t_first = (int32_t *)dev_alloc(p, B * 4);
-    b.t_cnt = (int32_t *)dev_alloc(p, B * 4);
-    b.flags = (int32_t *)dev_alloc(p, B * 4);
-    b.tpar_box = (int32_t *)dev_alloc(p, B * 4);
-    b.src_rank = (int32_t *)dev_alloc(p, B * 4);
-    b.src_box = (int32_t *)dev_alloc(p, B * 4);
     Lists &L = p.lists;
-    L.u_rng = (uint2 *)dev_alloc(p, B * sizeof(uint2));
-    L.w_rng = (uint2 *)dev_alloc(p, B * sizeof(uint2));
-    L.x_rng = (uint2 *)dev_alloc(p, B * sizeof(uint2));
     L.u_cap = std::max<int64_t>(1024, 64 * B);
     L.w_cap = std::max<int64_t>(1024, 32 * B);
     L.x_cap = std::max<int64_t>(1024, 32 * B);
@@ -187,26 +162,12 @@ void alloc_workspace(Plan &p)
         const int64_t k = std::max<int64_t>(0, std::atoll(env));
         L.u_cap = L.w_cap = L.x_cap = std::max<int64_t>(1, k * B);
     }
-    L.u = (int32_t *)dev_alloc(p, L.u_cap * 4);
-    L.w = (int32_t *)dev_alloc(p, L.w_cap * 4);
-    L.x = (int32_t *)dev_alloc(p, L.x_cap * 4);
-    L.far_a = (int4 *)dev_alloc(p, B * sizeof(int4));
-    L.far_b = (int32_t *)dev_alloc(p, B * 4);
-    L.near_leaves = (int32_t *)dev_alloc(p, B * 4);
-    L.vt = (int32_t *)dev_alloc(p, B * 4);
-    L.vt_tag = (int32_t *)dev_alloc(p, B * 4);
+    p.m2l_tiles = 0;
     for (int l = 0; l <= p.max_depth; ++l) {
         p.m2l_tile_base[l] = p.m2l_tiles;
         p.m2l_tiles += (int32_t)((p.level_cap[l] + 63) / 64);
     }
-    L.m2l_tile_use = (uint32_t *)dev_alloc(p, (size_t)std::max(p.m2l_tiles, 1) * kUseWords * 4);
-    L.m2l_box_use = (uint32_t *)dev_alloc(p, (size_t)B * kUseWords * 4);
-    L.vslot = (uint64_t *)dev_alloc(p, (size_t)B * kVSlots * 8);
-    PH_HIP(hipMemset(L.vslot, 0, (size_t)B * kVSlots * 8));  // no call has tagged a slot yet
-    PH_HIP(hipMemset(L.vt_tag, 0, B * 4));  // no call has tagged a box yet
     if (p.method == PH_METHOD_FMM) {
-        p.d_phi = dev_alloc(p, (size_t)B * p.n_lam * rs);
-        p.d_u = dev_alloc(p, (size_t)B * p.n_lam * rs);
         // translation products: the source boxes of every level at once (one M2L product for
         // all levels) if that takes at most an eighth of the device memory (a quarter of a
         // workspace cap); else one level at a time, in chunks of at most that size (at least
@@ -227,26 +188,89 @@ void alloc_workspace(Plan &p)
         p.y_all_levels = all_cols > 0 && (size_t)all_cols * col_bytes <= budget;
         if (p.y_all_levels) p.y_cap_cols = (size_t)all_cols;
         else p.y_cap_cols = (size_t)std::max<int64_t>(64, std::min<int64_t>(widest2, (int64_t)(budget / col_bytes)) / 64 * 64);
-        p.d_y = dev_alloc(p, p.y_cap_cols * col_bytes);
-        int64_t widest_par = 1;
-        for (int l = 2; l <= p.max_depth; ++l) widest_par = std::max<int64_t>(widest_par, p.level_cap[l]);
-        p.z_cap_cols = (size_t)widest_par;
-        p.d_z = dev_alloc(p, p.z_cap_cols * 8 * p.n_lam * rs);
+        p.z_cap_cols = (size_t)widest2;
+    }
+}
+
+// Points every per-call array of the plan into the workspace at base, in 256-byte aligned
+// slices, and returns the workspace size.  assign = false only measures (no pointer changes).
+// A workspace must be all zero before its first call: call numbers, box tags and the
+// selection flags of "no earlier call" are zeros.
+size_t layout_workspace(Plan &p, char *base, bool assign)
+{
+    size_t off = 0;
+    auto take = [&](auto **dst, size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        if (assign) *dst = reinterpret_cast<std::remove_pointer_t<decltype(dst)>>(base + off);
+        off += std::max<size_t>(bytes, 16);
+    };
+    const int64_t n = p.n;
+    const size_t rs = p.precision == PH_FP64 ? sizeof(double) : sizeof(float);
+    const int64_t B = p.box_cap;
+    take(&p.d_sc, sizeof(CallScalars));
+    take(&p.d_gen, sizeof(int32_t));
+    take(&p.d_flag, (size_t)n * sizeof(uint64_t));
+    take(&p.d_sel, (size_t)n);
+    take(&p.d_scan_tmp, p.scan_tmp_bytes);
+    take(&p.d_t_out, (size_t)n * 4);
+    take(&p.d_s_dat, (size_t)n * 4 * rs);
+    take(&p.d_t_dat, (size_t)n * 4 * rs);
+    take(&p.d_t_near, (size_t)n * 8);
+    take(&p.d_sref, (size_t)n * rs);
+    if (p.grid_mode) {
+        take(&p.d_s_cell, (size_t)n * 4);
+        take(&p.d_t_cell, (size_t)n * 4);
+    }
+    BoxArrays &b = p.box;
+    for (int32_t **f : {&b.s_first, &b.s_cnt, &b.t_first, &b.t_cnt, &b.flags, &b.tpar_box, &b.src_rank, &b.src_box})
+        take(f, (size_t)B * 4);
+    Lists &L = p.lists;
+    take(&L.u_rng, (size_t)B * sizeof(uint2));
+    take(&L.w_rng, (size_t)B * sizeof(uint2));
+    take(&L.x_rng, (size_t)B * sizeof(uint2));
+    take(&L.u, (size_t)L.u_cap * 4);
+    take(&L.w, (size_t)L.w_cap * 4);
+    take(&L.x, (size_t)L.x_cap * 4);
+    take(&L.far_a, (size_t)B * sizeof(int4));
+    take(&L.far_b, (size_t)B * 4);
+    take(&L.near_leaves, (size_t)B * 4);
+    take(&L.vt, (size_t)B * 4);
+    take(&L.vt_tag, (size_t)B * 4);
+    take(&L.m2l_tile_use, (size_t)std::max(p.m2l_tiles, 1) * kUseWords * 4);
+    take(&L.m2l_box_use, (size_t)B * kUseWords * 4);
+    take(&L.vslot, (size_t)B * kVSlots * 8);
+    if (p.method == PH_METHOD_FMM) {
+        take(&p.d_phi, (size_t)B * p.n_lam * rs);
+        take(&p.d_u, (size_t)B * p.n_lam * rs);
+        take(&p.d_y, p.y_cap_cols * (size_t)kNumM2L * p.n_lam * rs);
+        take(&p.d_z, p.z_cap_cols * 8 * (size_t)p.n_lam * rs);
     }
     const int64_t NL = std::max<int32_t>(p.n_pleaf, 1);
-    p.d_feat = (float *)dev_alloc(p, (size_t)NL * 8 * 4);
-    p.d_feat_cnt = (int32_t *)dev_alloc(p, NL * 4);
-    p.d_logit = (float *)dev_alloc(p, NL * 4);
-    p.d_leafscan = (uint32_t *)dev_alloc(p, (NL + 1) * 4);
-    p.d_lstat = (double *)dev_alloc(p, (size_t)NL * 6 * 8);
-    p.d_box_emax = (float *)dev_alloc(p, (size_t)B * 4);
-    p.d_cand_list = (int32_t *)dev_alloc(p, NL * 4);
-    p.d_row_box = (int32_t *)dev_alloc(p, NL * 4);
-    p.d_row_feat = (float *)dev_alloc(p, (size_t)NL * 8 * 4);
+    take(&p.d_feat, (size_t)NL * 8 * 4);
+    take(&p.d_feat_cnt, (size_t)NL * 4);
+    take(&p.d_logit, (size_t)NL * 4);
+    take(&p.d_leafscan, (size_t)(NL + 1) * 4);
+    take(&p.d_lstat, (size_t)NL * 6 * 8);
+    take(&p.d_box_emax, (size_t)B * 4);
+    take(&p.d_cand_list, (size_t)NL * 4);
+    take(&p.d_row_box, (size_t)NL * 4);
+    take(&p.d_row_feat, (size_t)NL * 8 * 4);
+    take(&p.d_drop, (size_t)n);
+    take(&p.d_leafflag, (size_t)(NL + 1) * 4);
+    return (off + 255) & ~(size_t)255;
+}
+
+// The plan's own workspace (zero-filled) and its plan-time neighbours
+void alloc_workspace(Plan &p)
+{
+    size_workspace(p);
+    p.ws_bytes = layout_workspace(p, nullptr, false);
+    p.d_ws_own = (char *)dev_alloc(p, p.ws_bytes);
+    PH_HIP(hipMemset(p.d_ws_own, 0, p.ws_bytes));
+    layout_workspace(p, p.d_ws_own, true);
+    p.d_sticky = (int32_t *)dev_alloc(p, sizeof(int32_t));
+    PH_HIP(hipMemset(p.d_sticky, 0, sizeof(int32_t)));
     p.d_sel_params = (float *)dev_alloc(p, PH_MLP_NPARAM * 4);
-    p.d_drop = (uint8_t *)dev_alloc(p, (size_t)n);
-    p.d_leafflag = (uint32_t *)dev_alloc(p, (NL + 1) * 4);
-    PH_HIP(hipMemset(p.d_leafflag, 0, (NL + 1) * 4));  // no selector pass has run yet
     if (!p.sel_weights.empty())
         PH_HIP(hipMemcpy(p.d_sel_params, p.sel_weights.data(), PH_MLP_NPARAM * 4, hipMemcpyHostToDevice));
 }
@@ -257,19 +281,11 @@ void free_plan(Plan *p)
     // every pointer member that came from dev_alloc
     void *ptrs[] = {p->d_key, p->d_perm, p->d_iperm, p->d_xyz, p->d_w, p->ops.uc2e_rm, p->ops.uc2e_cm,
                     p->ops.m2m, p->ops.l2l, p->ops.m2l, p->ops.lat_unit, p->ops.shell_unit, p->ops.m2l_hi,
-                    p->ops.m2l_lo, p->d_sc, p->d_flag, p->d_sel, p->d_scan_tmp, p->d_xyzf, p->d_bnd, p->d_t_out,
-                    p->d_s_dat, p->d_t_dat, p->box.level, p->box.ax, p->box.ay, p->box.az,
-                    p->box.s_first, p->box.s_cnt, p->box.t_first, p->box.t_cnt, p->box.parent, p->box.flags,
-                    p->box.child, p->box.coll, p->box.start, p->box.end, p->box.src_rank, p->box.tpar_box, p->d_z,
-                    p->box.src_box, p->d_y, p->lists.u_rng,
-                    p->lists.w_rng, p->lists.x_rng, p->lists.u, p->lists.w, p->lists.x, p->lists.far_a,
-                    p->lists.far_b, p->lists.near_leaves, p->lists.vt, p->lists.vt_tag, p->lists.m2l_tile_use, p->lists.m2l_box_use, p->lists.vslot, p->d_phi, p->d_u,
-                    p->d_feat, p->d_feat_cnt, p->d_logit, p->d_sel_params, p->d_drop, p->d_leafflag,
-                    p->d_pleaf, p->d_pleaf_of_box, p->d_pinfo, p->d_pinfo2, p->d_pcoll, p->d_leafscan, p->d_lstat, p->d_box_emax, p->d_row_box, p->d_cand_list,
-                    p->d_row_feat,
-                    p->d_cell,
-                    p->d_s_cell, p->d_t_cell, p->ops.grid_g, p->ops.grid_gt, p->d_t_near,
-                    p->ops.near_tab, p->d_gen, p->d_sticky, p->ops.l2l_comp, p->d_boxmap};
+                    p->ops.m2l_lo, p->d_xyzf, p->d_bnd, p->box.level, p->box.ax, p->box.ay, p->box.az,
+                    p->box.parent, p->box.child, p->box.coll, p->box.start, p->box.end, p->d_ws_own,
+                    p->d_sel_params, p->d_pleaf, p->d_pleaf_of_box, p->d_pinfo, p->d_pinfo2, p->d_pcoll,
+                    p->d_cell, p->ops.grid_g, p->ops.grid_gt, p->ops.near_tab, p->d_sticky, p->ops.l2l_comp,
+                    p->d_boxmap, p->d_tmask};
     // events and streams first, then the memory the work on them used
     if (p->events_ready)
         for (auto &set : p->ring)
@@ -332,6 +348,8 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     p.uniform_w = pts->w == nullptr;
     p.w_uniform = p.uniform_w ? pts->h * pts->h * pts->h : 0.0;
     if (opt->selector == PH_SEL_LEARNED) {
+        p.validate = opt->validate != 0;
+        p.validate_tol = opt->tol > 0 ? opt->tol : (opt->tol == 0 && opt->validate ? 0.0 : 1e-3);
         p.sel_weights.assign(opt->selector_weights, opt->selector_weights + PH_MLP_NPARAM);
         p.sel_threshold = opt->selector_logit_threshold;
         p.fallback_rel = opt->selector_fallback_rel > 0 ? opt->selector_fallback_rel : 1e-4;
@@ -833,14 +851,16 @@ static void harvest_slot(Plan &p, int slot)
 namespace {
 
 // One evaluation's launches on s (with the plan's second and third streams joined back into s
-// before the end): the same sequence for every call of a plan, so that it can be captured once
-// and replayed.  timed: phase events into ring slot `slot`.
-void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s, bool timed, int slot)
+// before the end).  timed: phase events into ring slot `slot`.  threshold_run: a learned plan's
+// plain threshold-rule evaluation (source rule fallback_rel, no network), the reference of a
+// validated call.
+void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s, bool timed, int slot,
+                  bool threshold_run = false)
 {
     auto mark = [&](int k, hipStream_t on) {
         if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], on));
     };
-    const bool learned = p.selector == PH_SEL_LEARNED;
+    const bool learned = p.selector == PH_SEL_LEARNED && !threshold_run;
     p.cur_I = I;  // the target kernels read the own-cell term's intensity from it
     mark(0, s);
     // the first kernel clears the call's scalars and advances the call number
@@ -850,7 +870,7 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(1, s);
     if (learned) selector_decide(p, I, absE, s);
     mark(2, s);
-    launch_select(p, I, absE, S_out, s, learned ? p.d_drop : nullptr);
+    launch_select(p, I, absE, S_out, s, learned ? p.d_drop : nullptr, threshold_run ? p.fallback_rel : -1.0);
     mark(3, s);
     if (p.method == PH_METHOD_DIRECT) {
         for (int k = 4; k <= 7; ++k) mark(k, s);
@@ -901,8 +921,12 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
 
 }  // namespace
 
-ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
-                      ph_stats *stats)
+static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s,
+                                 ph_stats *stats);
+
+// One call on the plan's current workspace, with the arguments checked
+static ph_status evaluate_checked(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
+                                  ph_stats *stats, void *workspace, bool use_ws)
 {
     g_last_error.clear();
     if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
@@ -910,7 +934,41 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
     if (!I || !S_out) return fail(Error{PH_EINVAL, "I and S_out must be device pointers"});
     const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
     if (need_e && !absE) return fail(Error{PH_EINVAL, "absE is required when a field rule is on"});
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (use_ws && (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)))
+        return fail(Error{PH_EINVAL, "workspace must be a 256-byte aligned device pointer"});
+    std::lock_guard<std::mutex> lock(p.mu);
+    if (!use_ws) return evaluate_locked(p, I, absE, S_out, reinterpret_cast<hipStream_t>(stream), stats);
+    // the per-call arrays point into the caller's workspace for this call only
+    struct Restore {
+        Plan &p;
+        ~Restore() { layout_workspace(p, p.d_ws_own, true); }
+    } restore{p};
+    layout_workspace(p, static_cast<char *>(workspace), true);
+    return evaluate_locked(p, I, absE, S_out, reinterpret_cast<hipStream_t>(stream), stats);
+}
+
+ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
+                      ph_stats *stats)
+{
+    return evaluate_checked(plan, I, absE, S_out, stream, stats, nullptr, false);
+}
+
+size_t ph_evaluate_workspace_bytes(const ph_plan *plan)
+{
+    return plan ? reinterpret_cast<const Plan *>(plan)->ws_bytes : 0;
+}
+
+ph_status ph_evaluate_ws(ph_plan *plan, const void *I, const float *absE, void *S_out, void *workspace,
+                         void *stream, ph_stats *stats)
+{
+    return evaluate_checked(plan, I, absE, S_out, stream, stats, workspace, true);
+}
+
+static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s,
+                                 ph_stats *stats)
+{
+    const bool learned_plan = p.selector == PH_SEL_LEARNED;
+    (void)learned_plan;
     try {
         PH_HIP(hipSetDevice(p.device));
         const bool timed = stats != nullptr || p.recording;
@@ -921,7 +979,16 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             p.ring_pos = (p.ring_pos + 1) % Plan::kRing;
         }
         const bool learned = p.selector == PH_SEL_LEARNED;
-        enqueue_call(p, I, absE, S_out, s, timed, slot);
+        const bool validated = learned && p.validate;
+        if (validated) {
+            // the plain FMM under the threshold rule first (into the workspace), then the
+            // learned call, then the comparison that keeps one of the two
+            enqueue_call(p, I, absE, p.d_sref, s, false, slot, true);
+            enqueue_call(p, I, absE, S_out, s, timed, slot);
+            launch_validate(p, S_out, p.d_sref, p.validate_tol, s);
+        } else {
+            enqueue_call(p, I, absE, S_out, s, timed, slot);
+        }
         PH_HIP(hipGetLastError());
         if (timed) p.ring_used[slot] = true;
         if (stats) {
@@ -943,8 +1010,37 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
             stats->n_leaves = learned ? p.h_sc.n_srcleaf : 0;
             for (int k = 0; k < 12; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
             for (int k = 0; k < 9; ++k) stats->t_ms[k] = phase_ms(p, slot, k);
+            stats->check_rel_l2 = validated ? p.h_sc.check_rel : -1.0;
         }
         if (stats && stats->fell_back) return PH_EFALLBACK;
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_plan_set_targets(ph_plan *plan, const uint8_t *mask, int64_t n)
+{
+    g_last_error.clear();
+    if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (mask && n != p.n) return fail(Error{PH_EINVAL, "target mask length must equal the number of points"});
+    try {
+        std::lock_guard<std::mutex> lock(p.mu);
+        PH_HIP(hipSetDevice(p.device));
+        PH_HIP(hipDeviceSynchronize());  // no call still reads the old set
+        if (!mask) {
+            dev_free(p.d_tmask);
+            if (p.d_tmask) p.bytes_allocated -= (size_t)p.n;
+            p.d_tmask = nullptr;
+            return PH_OK;
+        }
+        std::vector<int32_t> perm((size_t)p.n);
+        PH_HIP(hipMemcpy(perm.data(), p.d_perm, (size_t)p.n * 4, hipMemcpyDeviceToHost));
+        std::vector<uint8_t> sorted((size_t)p.n);
+        for (int64_t k = 0; k < p.n; ++k) sorted[k] = mask[perm[k]] ? 1 : 0;
+        if (!p.d_tmask) p.d_tmask = (uint8_t *)dev_alloc(p, (size_t)p.n);
+        PH_HIP(hipMemcpy(p.d_tmask, sorted.data(), (size_t)p.n, hipMemcpyHostToDevice));
         return PH_OK;
     } catch (const Error &e) {
         return fail(e);

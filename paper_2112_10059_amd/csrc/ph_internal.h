@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -65,6 +66,7 @@ struct CallScalars {
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t emax_key;                  // |E| bits << 32 | ~caller index of the largest |E|
     double emax_xyz[3];                 // that point's position (learned selector calls)
+    double check_rel;                   // validated calls: rel-L2 of learned vs threshold result
     // algorithmic work of the call (integer counters, order independent)
     unsigned long long work[12];        // p2p pairs, l2p evals, m2p evals, p2m evals,
                                         // p2l evals, m2l pairs, m2m children, l2l boxes,
@@ -198,6 +200,8 @@ struct Plan {
     std::vector<float> sel_weights;
     float sel_threshold = 0.f;
     double fallback_rel = 1e-4;     // threshold rule of the learned selector's fallback
+    bool validate = false;          // learned calls also run the threshold rule and compare
+    double validate_tol = 1e-3;     // ... falling back when the relative L2 difference exceeds this
     uint8_t *d_drop = nullptr;      // per sorted point of a candidate leaf: 1 if the leaf was dropped
     uint32_t *d_leafflag = nullptr; // per plan leaf: 1 if it holds a candidate source
     int32_t n_pleaf = 0;            // leaves of the plan's tree over all points
@@ -241,6 +245,7 @@ struct Plan {
     uint8_t *d_sel = nullptr;       // selection flags per sorted point (bit 0 source, bit 1 target)
     int32_t *d_s_cell = nullptr, *d_t_cell = nullptr; // packed cell indices (grid mode)
     double *d_t_near = nullptr;     // near field (P2P) of targets whose leaf has a U list
+    void *d_sref = nullptr;         // validated learned calls: the threshold rule's S (caller order)
     BoxArrays box;
     Lists lists;
     void *d_phi = nullptr;          // box_cap x n_lam upward densities
@@ -280,6 +285,13 @@ struct Plan {
     int32_t *d_sticky = nullptr; // device: error bits of every call since the last ph_plan_check
     bool count_work = false;        // algorithmic work counters (only for calls that fetch stats)
     bool near_guard = true;         // near pairs may have (b - a) r < 1/4: small-argument series needed
+    // the per-call arrays live in one workspace: the plan's own (zero-filled at creation) or,
+    // for the duration of a ph_evaluate_ws call, the caller's
+    char *d_ws_own = nullptr;
+    std::mutex mu;                  // one call at a time enqueues on the plan
+    size_t ws_bytes = 0;
+    // caller-supplied target set (sorted order, 1 = may be a target), or null for every point
+    uint8_t *d_tmask = nullptr;
     size_t bytes_allocated = 0;
     size_t workspace_cap = 0;
 };
@@ -345,7 +357,12 @@ void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, in
 void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
                              int32_t *sticky, hipStream_t s);  // partials: up to 1024 blocks
 // selection flags, their scan (kept in d_flag for the tree build) and the compaction
-void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop);
+// src_rel >= 0 replaces the plan's source rule for this pass (the threshold run of a validated call)
+void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop,
+                   double src_rel = -1.0);
+// validated learned call: S_out (learned) against S_ref (threshold rule); S_ref replaces S_out
+// and the call is marked fallen back when their relative L2 difference exceeds tol
+void launch_validate(const Plan &p, void *S_out, const void *S_ref, double tol, hipStream_t s);
 void scan_tile_sums_u64(uint64_t *partial, int64_t nb, uint64_t *total, hipStream_t s);
 void launch_pack_xyzf(const double *xyz, int64_t n, float4 *out, hipStream_t s);
 

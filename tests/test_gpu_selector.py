@@ -285,3 +285,39 @@ def test_trained_selector_on_held_out_fields(gpu_lib, seed):
     _say(f"  kept {st['n_src']} of {st['n_src'] + st['n_src_dropped']} candidates, method rel-L2 {err:.3e}")
     assert err <= 1e-3
     plan.close()
+
+
+def test_validated_learned_call_falls_back_to_the_plain_fmm(gpu_lib):
+    """validate = 1: every learned call is judged by the plain FMM under the threshold rule.  With
+    tol = 0 any difference falls back, and the output is the threshold rule's bit for bit; with a
+    loose tol the learned output is kept, bit for bit as without validation."""
+    from paper_2112_10059_amd.train_selector import load_selector
+    w, meta = load_selector()
+    wl = gen.config2(seed=1016, n_axis=64)
+    _say("validated learned call")
+    tI, tE = _t(wl.I.astype(np.float32)), _t(wl.E.astype(np.float32))
+    kw = dict(selector="learned", selector_weights=w, selector_logit_threshold=meta["threshold"],
+              selector_fallback_rel=1e-4, **plan_kwargs(wl))
+    thr_l = dict(src_rel=meta["base_src_rel"], e_abs=3e6)
+    plain = gpu_lib.Plan(wl.xyz, wl.gas, dict(src_rel=1e-4, e_abs=3e6), **plan_kwargs(wl))
+    S_thr = plain.evaluate(tI, tE).cpu().numpy()
+    unval = gpu_lib.Plan(wl.xyz, wl.gas, thr_l, **kw)
+    S_l, st_l = unval.evaluate(tI, tE, stats=True)
+    S_l = S_l.cpu().numpy()
+    assert st_l["check_rel_l2"] == -1.0
+    strict = gpu_lib.Plan(wl.xyz, wl.gas, thr_l, validate=True, tol=0.0, **kw)
+    S0, st0 = strict.evaluate(tI, tE, stats=True)
+    diff = rel_l2(S_l.astype(np.float64), S_thr.astype(np.float64))
+    assert st0["check_rel_l2"] == pytest.approx(diff, rel=1e-6, abs=1e-12)
+    if diff > 0:
+        assert st0["fell_back"] == 1
+    assert np.array_equal(S0.cpu().numpy().view(np.uint32), S_thr.view(np.uint32))
+    loose = gpu_lib.Plan(wl.xyz, wl.gas, thr_l, validate=True, tol=0.5, **kw)
+    S1, st1 = loose.evaluate(tI, tE, stats=True)
+    assert st1["fell_back"] == 0
+    assert np.array_equal(S1.cpu().numpy().view(np.uint32), S_l.view(np.uint32))
+    # asynchronous validated calls on the same plan give the same results
+    S2 = strict.evaluate(tI, tE)
+    assert np.array_equal(S2.cpu().numpy().view(np.uint32), S_thr.view(np.uint32))
+    for p in (plain, unval, strict, loose):
+        p.close()
