@@ -136,3 +136,40 @@ def budgeted_keep_labels_gram(G, s_norm, budget):
     lab = np.ones(G.shape[0], dtype=np.float64)
     lab[dropped] = 0.0
     return lab
+
+
+def greedy_keep_labels(G, c, d0, s_norm, budget):
+    """Keep/drop labels of the learned selector's rows under one error budget (test infrastructure).
+
+    The rows are the source leaves of the threshold rule's source set (Sec. 3 eq. (18)); the
+    points the rule itself leaves out have the field S_0 at the targets, and row b the field
+    S_b.  Inputs: G[b, b'] = <S_b, S_b'>, c[b] = <S_0, S_b>, d0 = ||S_0||^2 over the targets,
+    and s_norm = ||S|| of every source.  Dropping a set D of rows makes the error
+    ||S_0 + sum_{b in D} S_b||, whose square is d0 + 2 sum_D c + sum_{D x D} G.  Rows are dropped
+    one at a time, each time the row whose drop raises that square the least (ties: the lowest
+    index), while the error stays <= budget * s_norm.  Returns 1 = keep, 0 = drop.
+    """
+    G = np.asarray(G, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    m = G.shape[0]
+    lim = (budget * s_norm) ** 2
+
+    def err2(D):
+        D = list(D)
+        return float(d0) + 2.0 * c[D].sum() + G[np.ix_(D, D)].sum()
+
+    dropped = []
+    while True:
+        best, best_e = None, None
+        for b in range(m):
+            if b in dropped:
+                continue
+            e = err2(dropped + [b])
+            if e <= lim and (best_e is None or e < best_e):
+                best, best_e = b, e
+        if best is None:
+            break
+        dropped.append(best)
+    lab = np.ones(m, dtype=np.float64)
+    lab[dropped] = 0.0
+    return lab

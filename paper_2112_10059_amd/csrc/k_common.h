@@ -234,6 +234,12 @@ __device__ __forceinline__ T lane_value(T v, int l)
     }
 }
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int o)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o), hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // inclusive scan across the 64 lanes
 template <class T>
 __device__ __forceinline__ T wave_inclusive(T v, int lane)

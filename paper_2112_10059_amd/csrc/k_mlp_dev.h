@@ -1,0 +1,187 @@
+// Device code of the learned leaf selector shared by the selection pass and the network
+// kernels: the 8 -> 64 -> 64 -> 1 GELU network's inference, and the per-leaf statistics and
+// features it reads.  One definition, so that the evaluation path and the training entry
+// points compute the same features and logits bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "k_common.h"
+
+namespace ph {
+namespace mlp {
+
+constexpr int NIN = PH_MLP_NIN, NH = PH_MLP_NHID, NP = PH_MLP_NPARAM;
+constexpr int OFF_W1 = 0, OFF_B1 = NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
+              OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH;
+
+__device__ __forceinline__ float round_bf16(float x)
+{
+    // round to nearest even on the upper 16 bits
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+__device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float a)
+{
+    return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * expf(-0.5f * a * a);
+}
+
+template <bool BF16>
+__device__ __forceinline__ float q(float x)
+{
+    return BF16 ? round_bf16(x) : x;
+}
+
+// Inference, one wave per row: lane i owns hidden unit i of both layers.  The first two
+// weight matrices are staged transposed in LDS so that the 64 lanes read consecutive words;
+// the hidden activations of layer 1 are broadcast lane by lane, and the output layer is a
+// fixed butterfly sum over the wave.  Every inference (the evaluation path and the
+// standalone forward call) runs mlp_row, so their logits agree bit for bit.
+struct MlpLds {
+    float w1t[NIN * NH], w2t[NH * NH], b1[NH], b2[NH], w3[NH], b3;
+};
+
+template <bool BF16>
+__device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
+{
+    // walk the parameters in order (consecutive threads, consecutive addresses) and transpose
+    // on the LDS side; eight loads per thread in flight
+    // before their stores (one round trip per batch, not one per element).  Weight (o, i) of a
+    // layer with NI inputs sits at o NI + i in the parameters and at i NH + o in LDS.
+    constexpr int kB = 8;
+    for (int t0 = threadIdx.x; t0 < NH * NIN; t0 += kB * blockDim.x) {
+        float v[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) v[b] = params[OFF_W1 + min(t0 + b * (int)blockDim.x, NH * NIN - 1)];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int u = t0 + b * (int)blockDim.x;
+            if (u < NH * NIN) L.w1t[(u % NIN) * NH + u / NIN] = q<BF16>(v[b]);
+        }
+    }
+    for (int t0 = threadIdx.x; t0 < NH * NH; t0 += kB * blockDim.x) {
+        float v[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) v[b] = params[OFF_W2 + min(t0 + b * (int)blockDim.x, NH * NH - 1)];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int u = t0 + b * (int)blockDim.x;
+            if (u < NH * NH) L.w2t[(u % NH) * NH + u / NH] = q<BF16>(v[b]);
+        }
+    }
+    if (threadIdx.x < NH) {
+        L.b1[threadIdx.x] = q<BF16>(params[OFF_B1 + threadIdx.x]);
+        L.b2[threadIdx.x] = q<BF16>(params[OFF_B2 + threadIdx.x]);
+        L.w3[threadIdx.x] = q<BF16>(params[OFF_W3 + threadIdx.x]);
+    }
+    if (threadIdx.x == 0) L.b3 = q<BF16>(params[OFF_B3]);
+}
+
+// x: the row's 8 inputs, the same values in every lane.  Returns the logit in every lane.
+template <bool BF16>
+__device__ __forceinline__ float mlp_row(const float (&x)[NIN], const MlpLds &L, int lane)
+{
+    float a = L.b1[lane];
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) a += L.w1t[k * NH + lane] * q<BF16>(x[k]);
+    const float h1 = q<BF16>(gelu(a));
+    float a2 = L.b2[lane];
+#pragma unroll 16
+    for (int j = 0; j < NH; ++j) a2 += L.w2t[j * NH + lane] * __shfl(h1, j);
+    float z = L.w3[lane] * q<BF16>(gelu(a2));
+    for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
+    return z + L.b3;
+}
+
+// ---------------------------------------------------------------- per-leaf statistics and features
+
+// wave reductions in a fixed butterfly order
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// The source rule of the plan: the same expression as the selection's
+__device__ __forceinline__ bool candidate(double v, double src_rel, double imax)
+{
+    return (src_rel <= 0.0) || (v >= src_rel * imax);
+}
+
+// Statistics of one plan leaf (sorted points [st, en)) by one thread, in point order: over the
+// candidates (the plan's source rule) the largest I, the sum of w I and their count; over all
+// points the largest, the sum and the sum of squares of |E|.  fetch(k, v, e) gives I and |E| of
+// sorted point k.  One thread per leaf needs no cross-lane reductions, and the fixed order makes
+// the sums the same wherever the values come from.
+struct LeafStats {
+    double imax_c, swi_c, n_c, emax, es, es2, n;
+};
+
+template <class F>
+__device__ __forceinline__ LeafStats leaf_stats_seq(F &&fetch, const double *__restrict__ w, double w_ref, int32_t st,
+                                                    int32_t en, double src_rel, double imax)
+{
+    LeafStats s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, (double)(en - st)};
+    for (int32_t k = st; k < en; ++k) {
+        double v, e;
+        fetch(k, v, e);
+        if (candidate(v, src_rel, imax)) {
+            s.imax_c = fmax(s.imax_c, v);
+            s.swi_c += v * (w ? w[k] : w_ref);
+            s.n_c += 1.0;
+        }
+        s.emax = fmax(s.emax, e);
+        s.es += e;
+        s.es2 += e * e;
+    }
+    return s;
+}
+
+// Reference points and scales of a call's features.
+struct FeatureRefs {
+    double imax, emax, w_ref;
+    double xi[3];       // position of the largest I
+    double xe[3];       // position of the largest |E|
+    double lo[3], cube; // root cube
+    bool efeat;         // |E| given and not all zero
+};
+
+// The eight inputs of a candidate leaf (level, anchor ax/ay/az):
+//   0 log10(max I / I_max) over its candidates       1 log10(sum w I / (I_max w_ref)) over them
+//   2 log10(candidates / points of the leaf)
+//   3 log10(1 + |centre - x_Imax| / side)             4 log10(1 + |centre - x_Emax| / side)
+//   5 max |E| / E_max     6 mean |E| / E_max     7 std |E| / E_max   (over the leaf's points;
+//   features 4-7 are 0 without |E|)
+__device__ __forceinline__ void leaf_features(const LeafStats &s, const FeatureRefs &r, int level, int ax, int ay,
+                                              int az, float (&fe)[NIN])
+{
+    const double side = r.cube / (double)(1 << level), hw = 0.5 * side;
+    const double c0 = r.lo[0] + (2.0 * ax + 1.0) * hw, c1 = r.lo[1] + (2.0 * ay + 1.0) * hw,
+                 c2 = r.lo[2] + (2.0 * az + 1.0) * hw;
+    fe[0] = (float)log10(fmax(s.imax_c / r.imax, 1e-300));
+    fe[1] = (float)log10(fmax(s.swi_c / (r.imax * r.w_ref), 1e-300));
+    fe[2] = (float)log10(fmax(s.n_c / s.n, 1e-300));
+    const double d0 = c0 - r.xi[0], d1 = c1 - r.xi[1], d2 = c2 - r.xi[2];
+    fe[3] = (float)log10(1.0 + sqrt(d0 * d0 + d1 * d1 + d2 * d2) / side);
+    for (int q = 4; q < NIN; ++q) fe[q] = 0.0f;
+    if (r.efeat) {
+        const double e0 = c0 - r.xe[0], e1 = c1 - r.xe[1], e2 = c2 - r.xe[2];
+        fe[4] = (float)log10(1.0 + sqrt(e0 * e0 + e1 * e1 + e2 * e2) / side);
+        const double mean = s.es / r.emax / s.n;
+        fe[5] = (float)(s.emax / r.emax);
+        fe[6] = (float)mean;
+        fe[7] = (float)sqrt(fmax(s.es2 / (r.emax * r.emax) / s.n - mean * mean, 0.0));
+    }
+}
+
+}  // namespace mlp
+}  // namespace ph

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "k_common.h"
+#include "k_mlp_dev.h"
 
 namespace ph {
 
@@ -28,108 +29,185 @@ __global__ void reset_scalars_kernel(CallScalars *sc, int32_t *gen)
     }
 }
 
-// Maxima of I and |E| (with the position of the largest |E|): each block reduces its
-// grid-stride share into partials, one block then reduces the partials (no contended atomics).
+// Maxima of I and |E| and the order keys that locate them.  Each of at most kRedBlocks blocks
+// reduces its grid-stride share (eight elements per thread in flight) into partials: the
+// largest I, marked if a bad value was seen, and the order keys of |E| and of I (value bits
+// above the complemented caller index: the largest key is the largest value, first in caller
+// order among ties).  The consumers reduce the few partials themselves: maxima do not depend on
+// the order of reduction, and no two blocks write one address.
+constexpr int kRedUnroll = 8;
+constexpr int kRedBlocks = 256;
+
 template <class T>
-__global__ void reduce_max_kernel(const T *__restrict__ I, const float *__restrict__ E, int64_t n,
-                                  double *__restrict__ partial, uint64_t *__restrict__ partial_key, CallScalars *sc,
-                                  int32_t *gen)
+__global__ __launch_bounds__(256) void reduce_max_kernel(const T *__restrict__ I, const float *__restrict__ E,
+                                                         int64_t n, double *__restrict__ partial,
+                                                         uint64_t *__restrict__ pkey, uint64_t *__restrict__ pikey,
+                                                         CallScalars *sc, int32_t *gen)
 {
     if (blockIdx.x == 0 && gen) begin_call(sc, gen);
-    __shared__ double smI[256];
-    __shared__ uint64_t smE[256];
-    double mi = 0.0;
-    uint64_t me = 0;
-    int bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        T v = I[i];
-        if (bad_value(v)) bad = 1;
-        else mi = fmax(mi, (double)v);
-        if (E) {
-            const uint64_t k = e_key(E[i], i);
-            if (k > me) me = k;
-        }
-    }
-    smI[threadIdx.x] = mi;
-    smE[threadIdx.x] = me;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            smI[threadIdx.x] = fmax(smI[threadIdx.x], smI[threadIdx.x + o]);
-            smE[threadIdx.x] = max(smE[threadIdx.x], smE[threadIdx.x + o]);
-        }
-        __syncthreads();
-    }
+    __shared__ double smI[4];
+    __shared__ uint64_t smE[4], smK[4];
     __shared__ int anybad;
+    double mi = 0.0;
+    uint64_t me = 0, mk = 0;
+    int bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += kRedUnroll * stride) {
+        T v[kRedUnroll];
+        float e[kRedUnroll];
+#pragma unroll
+        for (int u = 0; u < kRedUnroll; ++u) {
+            const int64_t i = i0 + u * stride;
+            v[u] = i < n ? I[i] : T(0);
+            e[u] = (E && i < n) ? E[i] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kRedUnroll; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i >= n) continue;
+            if (bad_value(v[u])) {
+                bad = 1;
+            } else {
+                mi = fmax(mi, (double)v[u]);
+                mk = max(mk, e_key((float)v[u], i));
+            }
+            if (E) me = max(me, e_key(e[u], i));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mi = fmax(mi, __shfl_xor(mi, o));
+        me = max(me, shfl_xor_u64(me, o));
+        mk = max(mk, shfl_xor_u64(mk, o));
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) anybad = 0;
     __syncthreads();
     if (bad) anybad = 1;
+    if (lane == 0) {
+        smI[wv] = mi;
+        smE[wv] = me;
+        smK[wv] = mk;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        partial[blockIdx.x] = mark_bad(smI[0], anybad != 0);
-        partial_key[blockIdx.x] = smE[0];
+        double m = smI[0];
+        uint64_t k = smE[0], q = smK[0];
+        for (int w = 1; w < 4; ++w) {
+            m = fmax(m, smI[w]);
+            k = max(k, smE[w]);
+            q = max(q, smK[w]);
+        }
+        partial[blockIdx.x] = mark_bad(m, anybad != 0);
+        pkey[blockIdx.x] = k;
+        pikey[blockIdx.x] = q;
     }
 }
 
-__global__ void reduce_max_final_kernel(const double *__restrict__ partial, const uint64_t *__restrict__ partial_key,
-                                        int nb, CallScalars *sc, int32_t *sticky)
+// Sorted position of the point an order key names (caller index in the complemented low word)
+__device__ __forceinline__ int64_t key_point(uint64_t key, const int32_t *__restrict__ iperm)
 {
-    __shared__ double a[256];
-    __shared__ uint64_t b[256];
+    return iperm[0xffffffffu - (uint32_t)(key & 0xffffffffu)];
+}
+
+struct Maxima {
+    double imax, emax;
+    uint64_t ekey, ikey;
+    int bad;
+};
+
+// The maxima over the nb partials at red, by a whole workgroup (every thread gets them)
+__device__ Maxima block_maxima(const double *__restrict__ red, int nb)
+{
+    const double *partial = red;
+    const uint64_t *pkey = reinterpret_cast<const uint64_t *>(red + kRedBlocks), *pikey = pkey + kRedBlocks;
+    __shared__ double sI[16];
+    __shared__ uint64_t sE[16], sK[16];
+    __shared__ int sbad;
     double mi = 0.0;
-    uint64_t me = 0;
-    bool bad = false;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        mi = fmax(mi, partial_max(partial[i], bad));
-        me = max(me, partial_key[i]);
+    uint64_t me = 0, mk = 0;
+    bool b = false;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+        mi = fmax(mi, partial_max(partial[j], b));
+        me = max(me, pkey[j]);
+        mk = max(mk, pikey[j]);
     }
-    if (bad) flag_error(sc, sticky, 1);
-    a[threadIdx.x] = mi;
-    b[threadIdx.x] = me;
+    for (int o = 32; o > 0; o >>= 1) {
+        mi = fmax(mi, __shfl_xor(mi, o));
+        me = max(me, shfl_xor_u64(me, o));
+        mk = max(mk, shfl_xor_u64(mk, o));
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) sbad = 0;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            a[threadIdx.x] = fmax(a[threadIdx.x], a[threadIdx.x + o]);
-            b[threadIdx.x] = max(b[threadIdx.x], b[threadIdx.x + o]);
-        }
-        __syncthreads();
+    if (b) sbad = 1;
+    if (lane == 0) {
+        sI[wv] = mi;
+        sE[wv] = me;
+        sK[wv] = mk;
     }
-    if (threadIdx.x == 0) {
-        sc->imax = a[0];
-        sc->emax = (double)__uint_as_float((uint32_t)(b[0] >> 32));
-        sc->emax_key = b[0];
+    __syncthreads();
+    Maxima m{0.0, 0.0, 0, 0, 0};
+    const int nw = (int)(blockDim.x >> 6);
+    for (int q = 0; q < nw; ++q) {
+        m.imax = fmax(m.imax, sI[q]);
+        m.ekey = max(m.ekey, sE[q]);
+        m.ikey = max(m.ikey, sK[q]);
     }
+    m.emax = (double)__uint_as_float((uint32_t)(m.ekey >> 32));
+    m.bad = sbad;
+    return m;
+}
+
+// The call's maxima, their keys and the positions of the two points into its scalars (one thread)
+__device__ void store_maxima(const Maxima &m, CallScalars *sc, int32_t *sticky, const int32_t *__restrict__ iperm,
+                             const double *__restrict__ xyz, bool has_e)
+{
+    if (m.bad) flag_error(sc, sticky, 1);
+    sc->imax = m.imax;
+    sc->emax = m.emax;
+    sc->emax_key = m.ekey;
+    sc->imax_key = m.ikey;
+    double xe[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
+    if (has_e && m.emax > 0.0) {
+        const int64_t k = key_point(m.ekey, iperm);
+        for (int d = 0; d < 3; ++d) xe[d] = xyz[3 * k + d];
+    }
+    if (m.imax > 0.0) {
+        const int64_t k = key_point(m.ikey, iperm);
+        for (int d = 0; d < 3; ++d) xi[d] = xyz[3 * k + d];
+    }
+    for (int d = 0; d < 3; ++d) {
+        sc->emax_xyz[d] = xe[d];
+        sc->imax_xyz[d] = xi[d];
+    }
+}
+
+// The training entry points' step between the reduction and their own passes
+__global__ __launch_bounds__(256) void maxima_store_kernel(const double *__restrict__ red, int nb, CallScalars *sc,
+                                                           int32_t *sticky, const int32_t *__restrict__ iperm,
+                                                           const double *__restrict__ xyz, int has_e)
+{
+    const Maxima m = block_maxima(red, nb);
+    if (threadIdx.x == 0) store_maxima(m, sc, sticky, iperm, xyz, has_e != 0);
 }
 
 struct SelectParams {
     double src_rel, e_abs, e_applied, e_rel;
-    double fallback_rel;          // source rule used when the learned selector falls back
+    double fallback_rel;          // source rule of a leaf whose learned decision is not finite
 };
 
-// Selection flags of sorted point k (bit 0 source, bit 1 target).  drop: per sorted point, 1
-// if a learned decision removed its source leaf (null: none).  When the selector has fallen
-// back (sc->fallback) the source rule is fallback_rel instead.  tmask: the caller's target set
-// per sorted point (null: every point), intersected with the field rules.
-template <class T>
-__device__ __forceinline__ uint32_t select_one(const T *__restrict__ I, const float *__restrict__ E, int32_t o,
-                                               int64_t k, const SelectParams &sp, const CallScalars *__restrict__ sc,
-                                               const uint8_t *__restrict__ drop, const uint8_t *__restrict__ tmask)
+__device__ __forceinline__ bool src_rule(double v, double rel, double imax) { return (rel <= 0.0) || (v >= rel * imax); }
+
+// Target flag of a point: the caller's set (tmask, null: every point) and the field rules
+__device__ __forceinline__ bool tgt_rule(const SelectParams &sp, float ev, bool has_e, double emax, uint8_t tm)
 {
-    const double v = (double)I[o];
-    bool src;
-    if (drop && sc->fallback) {
-        src = (sp.fallback_rel <= 0.0) || (v >= sp.fallback_rel * sc->imax);
-    } else {
-        src = (sp.src_rel <= 0.0) || (v >= sp.src_rel * sc->imax);
-        if (drop) src = src && !drop[k];
-    }
-    bool tgt = tmask ? tmask[k] != 0 : true;
-    if (E) {
-        const double e = (double)E[o];
+    bool tgt = tm != 0;
+    if (has_e) {
+        const double e = (double)ev;
         if (sp.e_abs >= 0.0) tgt = tgt && (e >= sp.e_abs);
-        if (sp.e_rel >= 0.0) tgt = tgt && (e >= sp.e_applied + sp.e_rel * (sc->emax - sp.e_applied));
+        if (sp.e_rel >= 0.0) tgt = tgt && (e >= sp.e_applied + sp.e_rel * (emax - sp.e_applied));
     }
-    return (src ? 1u : 0u) | (tgt ? 2u : 0u);
+    return tgt;
 }
 
 __device__ __forceinline__ uint64_t packed_of(uint32_t f)
@@ -139,41 +217,244 @@ __device__ __forceinline__ uint64_t packed_of(uint32_t f)
 
 // Selection in two passes over tiles of kSelTile sorted points (1024 threads; wave w owns a
 // contiguous sixteenth, read as kSelStrips coalesced strips of 64), with a scan of the tile
-// sums between them.  Pass one: the flags of every point (one byte each), S = 0 at points that
-// are not targets, and each tile's packed count (sources | targets << 32).
+// sums between them.  Pass one: the flags of every point (one byte each: bit 0 source, bit 1
+// target), S = 0 at points that are not targets, and each tile's packed count (sources |
+// targets << 32).  With the learned selector it also decides on the plan leaves that hold
+// candidates (below).
 constexpr int kSelWaves = 16;
 constexpr int kSelStrips = 4;
 constexpr int kSelSpan = 64 * kSelStrips;  // points per wave in a tile
 constexpr int kSelTile = kSelWaves * kSelSpan;
+static_assert(kSelTile == kSelTilePoints, "the plan's tile table uses the same tile");
+
+// Learned decisions inside the selection pass.  The plan leaves are listed by first point
+// (leaf_pos: first, end, plan-leaf index), and each tile knows the range of them that overlaps
+// it (tile_leaves).  The tile's I and |E| are staged in LDS with a candidate bit per point (the
+// plan's source rule); a leaf with no candidate needs nothing more.  For a candidate leaf a wave
+// takes its statistics (points outside the tile from memory), its features and the network's
+// BF16 logit: keep iff logit >= threshold; a non-finite logit keeps the leaf under the fallback
+// rule.  The decision becomes the state of the leaf's points in the tile (0 the plan's rule,
+// 1 dropped, 2 the fallback rule); a leaf that straddles two tiles is decided by both,
+// identically.  The tile whose range holds a leaf's first point records its flag, features and
+// counts for the inspection and training entry points.
+struct LearnArgs {
+    const int2 *tile_leaves;     // per tile: [first, end) in leaf_pos
+    const int4 *leaf_pos;        // plan leaves by first point: (first, end, plan-leaf index, 0)
+    const int4 *pinfo2;          // per plan leaf: anchor x, y, z, level
+    const double *w;             // sorted weights (null on grids)
+    const float *params;         // network weights (FP32; BF16 in use)
+    float threshold;
+    double w_ref, lo0, lo1, lo2, cube;
+    float *feats;                // per plan leaf: its features (candidate leaves)
+    uint32_t *leafflag;          // per plan leaf: 1 if it held a candidate in this call
+    int32_t *featcnt;            // per plan leaf: candidates
+    int count;                   // count rows and candidates into the scalars (calls with statistics)
+};
+
+constexpr int kLearnBatch = 64;  // leaves examined per round (at most 4 candidate leaves per wave)
 
 template <class T>
-__global__ __launch_bounds__(64 * kSelWaves) void select_tiles_kernel(const T *__restrict__ I, const float *__restrict__ E,
-                                                           const int32_t *__restrict__ perm, int64_t n,
-                                                           SelectParams sp, const CallScalars *__restrict__ sc,
-                                                           const uint8_t *__restrict__ drop,
-                                                           const uint8_t *__restrict__ tmask, uint8_t *__restrict__ sel,
-                                                           T *__restrict__ S_out, uint64_t *__restrict__ partial)
+struct TileLds {
+    T I[kSelTile];
+    float E[kSelTile];
+    uint64_t cand[kSelWaves * kSelStrips];  // candidate bit per point, a word per strip
+    uint8_t state[kSelTile];
+    mlp::MlpLds net;
+    float rowf[kLearnBatch][PH_MLP_NIN];
+    int32_t rowleaf[kLearnBatch];
+    int32_t nrow;
+};
+
+// Is a candidate among the tile's points [a, b) (tile-relative)?
+template <class T>
+__device__ __forceinline__ bool any_cand(const TileLds<T> &S, int a, int b)
+{
+    for (int q = a >> 6; q <= (b - 1) >> 6; ++q) {
+        uint64_t wq = S.cand[q];
+        const int lo = q * 64;
+        if (a > lo) wq &= ~0ull << (a - lo);
+        if (b < lo + 64) wq &= (1ull << (b - lo)) - 1ull;
+        if (wq) return true;
+    }
+    return false;
+}
+
+template <class T>
+__device__ void learned_decisions(const T *__restrict__ I, const float *__restrict__ E,
+                                  const int32_t *__restrict__ perm, int64_t n, const SelectParams &sp,
+                                  const Maxima &mx, const int32_t *__restrict__ iperm, const double *__restrict__ xyz,
+                                  const LearnArgs &la, CallScalars *__restrict__ sc, TileLds<T> &S)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * kSelTile, t1 = min(n, t0 + kSelTile);
+    const int2 range = la.tile_leaves[blockIdx.x];
+    bool staged = false;
+    for (int32_t b0 = range.x; b0 < range.y; b0 += kLearnBatch) {
+        // the candidate leaves among the next leaves, compacted into the round's rows
+        if (threadIdx.x == 0) S.nrow = 0;
+        __syncthreads();
+        for (int32_t li = b0 + (int32_t)threadIdx.x; li < min(range.y, b0 + kLearnBatch); li += blockDim.x) {
+            const int4 lp = la.leaf_pos[li];
+            bool c;
+            if (lp.x >= t0 && lp.y <= t1) {
+                c = any_cand(S, (int)(lp.x - t0), (int)(lp.y - t0));
+            } else {  // a leaf that leaves the tile: its points from memory
+                c = false;
+                for (int32_t k = lp.x; k < lp.y && !c; ++k) c = src_rule((double)I[perm[k]], sp.src_rel, mx.imax);
+            }
+            if (c) S.rowleaf[atomicAdd(&S.nrow, 1)] = li;
+            else if (lp.x >= t0) la.leafflag[lp.z] = 0u;
+        }
+        __syncthreads();
+        const int nrow = S.nrow;
+        if (nrow == 0) continue;
+        // statistics and features, a wave per candidate leaf
+        mlp::FeatureRefs r;
+        r.imax = mx.imax;
+        r.emax = mx.emax;
+        r.w_ref = la.w_ref;
+        r.lo[0] = la.lo0;
+        r.lo[1] = la.lo1;
+        r.lo[2] = la.lo2;
+        r.cube = la.cube;
+        r.efeat = E && r.emax > 0.0;
+        for (int d = 0; d < 3; ++d) r.xi[d] = r.xe[d] = 0.0;
+        if (mx.imax > 0.0) {
+            const int64_t k = key_point(mx.ikey, iperm);
+            for (int d = 0; d < 3; ++d) r.xi[d] = xyz[3 * k + d];
+        }
+        if (r.efeat) {
+            const int64_t k = key_point(mx.ekey, iperm);
+            for (int d = 0; d < 3; ++d) r.xe[d] = xyz[3 * k + d];
+        }
+        // statistics and features, a thread of wave 0 per candidate leaf
+        if (wv == 0 && lane < nrow) {
+            const int j = lane;
+            const int4 lp = la.leaf_pos[S.rowleaf[j]];
+            auto fetch = [&](int32_t k, double &v, double &e) {
+                if (k >= t0 && k < t1) {
+                    v = (double)S.I[k - t0];
+                    e = (double)S.E[k - t0];
+                } else {
+                    const int32_t o = perm[k];
+                    v = (double)I[o];
+                    e = E ? (double)E[o] : 0.0;
+                }
+            };
+            const mlp::LeafStats s = mlp::leaf_stats_seq(fetch, la.w, la.w_ref, lp.x, lp.y, sp.src_rel, r.imax);
+            const int4 g = la.pinfo2[lp.z];
+            float fe[PH_MLP_NIN];
+            mlp::leaf_features(s, r, g.w, g.x, g.y, g.z, fe);
+#pragma unroll
+            for (int q = 0; q < PH_MLP_NIN; ++q) S.rowf[j][q] = fe[q];
+            if (lp.x >= t0) {
+#pragma unroll
+                for (int q = 0; q < PH_MLP_NIN; ++q) la.feats[(size_t)lp.z * PH_MLP_NIN + q] = fe[q];
+                la.leafflag[lp.z] = 1u;
+                la.featcnt[lp.z] = (int32_t)s.n_c;
+                if (la.count) {  // calls that report statistics: the rows and their candidates
+                    atomicAdd(&sc->n_src_base, (int32_t)s.n_c);
+                    atomicAdd(&sc->n_srcleaf, 1);
+                }
+            }
+        }
+        if (!staged) {
+            mlp::stage_weights<true>(la.params, S.net);
+            staged = true;
+        }
+        __syncthreads();
+        for (int j = wv; j < nrow; j += kSelWaves) {
+            float fe[PH_MLP_NIN];
+#pragma unroll
+            for (int q = 0; q < PH_MLP_NIN; ++q) fe[q] = S.rowf[j][q];
+            const float z = mlp::mlp_row<true>(fe, S.net, lane);
+            const int4 lp = la.leaf_pos[S.rowleaf[j]];
+            const uint8_t st = !isfinite(z) ? 2 : (z >= la.threshold ? 0 : 1);
+            if (st == 2 && lp.x >= t0 && lane == 0) atomicOr(&sc->fallback, 1);
+            const int64_t a0 = max((int64_t)lp.x, t0), a1 = min((int64_t)lp.y, t1);
+            for (int64_t k = a0 + lane; k < a1; k += 64) S.state[k - t0] = st;
+        }
+        __syncthreads();
+    }
+}
+
+template <class T, bool LEARNED>
+__global__ __launch_bounds__(64 * kSelWaves, LEARNED ? 4 : 8) void select_tiles_kernel(
+    const T *__restrict__ I, const float *__restrict__ E, const int32_t *__restrict__ perm, int64_t n,
+    SelectParams sp, CallScalars *__restrict__ sc, const double *__restrict__ red, int red_nb, int32_t *sticky,
+    const int32_t *__restrict__ iperm, const double *__restrict__ xyz, const uint8_t *__restrict__ tmask,
+    uint8_t *__restrict__ sel, T *__restrict__ S_out, uint64_t *__restrict__ partial, LearnArgs la)
 {
     __shared__ uint64_t wsum[kSelWaves];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)w * kSelSpan;
+    const int64_t tile0 = (int64_t)blockIdx.x * kSelTile;
+    const int64_t base = tile0 + (int64_t)w * kSelSpan;
+    // the tile's values first (they do not depend on the maxima), then the maxima from the partials
     int32_t o[kSelStrips];
+    T v[kSelStrips];
+    float e[kSelStrips];
+    uint8_t tm[kSelStrips];
 #pragma unroll
     for (int st = 0; st < kSelStrips; ++st) {
         const int64_t k = base + st * 64 + lane;
-        o[st] = k < n ? perm[k] : 0;
+        o[st] = k < n ? perm[k] : -1;
+        tm[st] = (tmask && k < n) ? tmask[k] : 1;
     }
-    uint64_t acc = 0;
 #pragma unroll
     for (int st = 0; st < kSelStrips; ++st) {
-        const int64_t k = base + st * 64 + lane;
-        if (k < n) {
-            const uint32_t f = select_one(I, E, o[st], k, sp, sc, drop, tmask);
-            sel[k] = (uint8_t)f;
-            if (!(f & 2u)) S_out[o[st]] = T(0);
-            acc += packed_of(f);
+        v[st] = o[st] >= 0 ? I[o[st]] : T(0);
+        e[st] = (E && o[st] >= 0) ? E[o[st]] : 0.0f;
+    }
+    const Maxima mx = block_maxima(red, red_nb);
+    const double imax = mx.imax, emax = mx.emax;
+    uint64_t acc = 0;
+    if constexpr (!LEARNED) {
+#pragma unroll
+        for (int st = 0; st < kSelStrips; ++st) {
+            const int64_t k = base + st * 64 + lane;
+            if (k < n) {
+                const bool src = src_rule((double)v[st], sp.src_rel, imax);
+                const bool tgt = tgt_rule(sp, e[st], E != nullptr, emax, tm[st]);
+                const uint32_t f = (src ? 1u : 0u) | (tgt ? 2u : 0u);
+                sel[k] = (uint8_t)f;
+                if (!tgt) S_out[o[st]] = T(0);
+                acc += packed_of(f);
+            }
+        }
+    } else {
+        __shared__ TileLds<T> S;
+        // stage the tile's values, one candidate word per strip
+#pragma unroll
+        for (int st = 0; st < kSelStrips; ++st) {
+            const int64_t k = base + st * 64 + lane;
+            const int q = (int)(k - tile0);
+            S.I[q] = v[st];
+            S.E[q] = e[st];
+            S.state[q] = 0;
+            const uint64_t cw = __ballot(k < n && src_rule((double)v[st], sp.src_rel, imax));
+            if (lane == 0) S.cand[w * kSelStrips + st] = cw;
+        }
+        __syncthreads();
+        learned_decisions(I, E, perm, n, sp, mx, iperm, xyz, la, sc, S);
+        // the points again from LDS (nothing of the staging loop stays live across the decisions)
+#pragma unroll
+        for (int st = 0; st < kSelStrips; ++st) {
+            const int64_t k = base + st * 64 + lane;
+            if (k < n) {
+                const int q = (int)(k - tile0);
+                const uint32_t state = S.state[q];
+                const bool src = state == 2u ? src_rule((double)S.I[q], sp.fallback_rel, imax)
+                                             : (state == 0u && ((S.cand[q >> 6] >> (q & 63)) & 1ull));
+                const bool tgt = tgt_rule(sp, S.E[q], E != nullptr, emax, tmask ? tmask[k] : 1);
+                const uint32_t f = (src ? 1u : 0u) | (tgt ? 2u : 0u);
+                sel[k] = (uint8_t)f;
+                if (!tgt) S_out[perm[k]] = T(0);
+                acc += packed_of(f);
+            }
         }
     }
+    // workgroup 0 publishes the maxima for the later kernels (after its own points)
+    if (blockIdx.x == 0 && threadIdx.x == 0) store_maxima(mx, sc, sticky, iperm, xyz, E != nullptr);
     acc = lane_value(wave_inclusive(acc, lane), 63);
     if (lane == 0) wsum[w] = acc;
     __syncthreads();
@@ -322,25 +603,24 @@ void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s)
     reset_scalars_kernel<<<1, 256, 0, s>>>(sc, gen);
 }
 
-void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
-                             int32_t *sticky, hipStream_t s)
+
+int reduce_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (n + 2047) / 2048)); }
+
+void launch_reduce_max(const Plan &p, const void *I, const float *E, int32_t *gen, hipStream_t s)
 {
-    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, nb, sc, sticky);
+    const int blocks = reduce_blocks(p.n);
+    double *red = p.d_red;
+    uint64_t *key = reinterpret_cast<uint64_t *>(red + kRedBlocks), *ikey = key + kRedBlocks;
+    if (p.precision == PH_FP64)
+        reduce_max_kernel<double><<<blocks, 256, 0, s>>>((const double *)I, E, p.n, red, key, ikey, p.d_sc, gen);
+    else
+        reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, E, p.n, red, key, ikey, p.d_sc, gen);
 }
 
-void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n, CallScalars *sc,
-                       int32_t *gen, int32_t *sticky, void *tmp, hipStream_t s)
+void launch_maxima_store(const Plan &p, bool has_e, hipStream_t s)
 {
-    int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
-    double *partial = reinterpret_cast<double *>(tmp);
-    uint64_t *partial_key = reinterpret_cast<uint64_t *>(partial + 1024);
-    if (fp64)
-        reduce_max_kernel<double><<<blocks, 256, 0, s>>>((const double *)I, need_e ? E : nullptr, n, partial,
-                                                         partial_key, sc, gen);
-    else
-        reduce_max_kernel<float><<<blocks, 256, 0, s>>>((const float *)I, need_e ? E : nullptr, n, partial,
-                                                        partial_key, sc, gen);
-    reduce_max_final_kernel<<<1, 256, 0, s>>>(partial, partial_key, blocks, sc, sticky);
+    maxima_store_kernel<<<1, 256, 0, s>>>(p.d_red, reduce_blocks(p.n), p.d_sc, p.d_sticky, p.d_iperm, p.d_xyz,
+                                          has_e ? 1 : 0);
 }
 
 static SelectParams params_of(const Plan &p, double src_rel)
@@ -349,22 +629,47 @@ static SelectParams params_of(const Plan &p, double src_rel)
                         p.fallback_rel};
 }
 
-void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop,
+void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, bool learned,
                    double src_rel)
 {
-    const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
     if (p.n <= 0) return;
     const int64_t nb = (p.n + kSelTile - 1) / kSelTile;
     uint64_t *partial = (uint64_t *)p.d_scan_tmp;
     const SelectParams sp = params_of(p, src_rel);
-    if (p.precision == PH_FP64)
-        select_tiles_kernel<double><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>((const double *)I, need_e ? E : nullptr, p.d_perm,
-                                                                  p.n, sp, p.d_sc, drop, p.d_tmask, p.d_sel, (double *)S_out,
-                                                                  partial);
-    else
-        select_tiles_kernel<float><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>((const float *)I, need_e ? E : nullptr, p.d_perm,
-                                                                 p.n, sp, p.d_sc, drop, p.d_tmask, p.d_sel, (float *)S_out,
-                                                                 partial);
+    LearnArgs la{};
+    if (learned) {
+        la.tile_leaves = p.d_tile_leaves;
+        la.leaf_pos = p.d_leaf_pos;
+        la.pinfo2 = p.d_pinfo2;
+        la.w = p.d_w;
+        la.params = p.d_sel_params;
+        la.threshold = p.sel_threshold;
+        la.w_ref = p.uniform_w ? p.w_uniform : p.cube_size * p.cube_size * p.cube_size / (double)p.n;
+        la.lo0 = p.cube_lo[0];
+        la.lo1 = p.cube_lo[1];
+        la.lo2 = p.cube_lo[2];
+        la.cube = p.cube_size;
+        la.feats = p.d_feat;
+        la.leafflag = p.d_leafflag;
+        la.featcnt = p.d_feat_cnt;
+        la.count = p.count_work ? 1 : 0;
+    }
+    const unsigned g = (unsigned)nb, bs = 64 * kSelWaves;
+    const int rnb = reduce_blocks(p.n);
+    if (p.precision == PH_FP64) {
+        if (learned)
+            select_tiles_kernel<double, true><<<g, bs, 0, s>>>((const double *)I, E, p.d_perm, p.n, sp, p.d_sc, p.d_red, rnb, p.d_sticky, p.d_iperm, p.d_xyz, p.d_tmask,
+                                                               p.d_sel, (double *)S_out, partial, la);
+        else
+            select_tiles_kernel<double, false><<<g, bs, 0, s>>>((const double *)I, E, p.d_perm, p.n, sp, p.d_sc, p.d_red, rnb, p.d_sticky, p.d_iperm, p.d_xyz, p.d_tmask, p.d_sel, (double *)S_out, partial, la);
+    } else {
+        if (learned)
+            select_tiles_kernel<float, true><<<g, bs, 0, s>>>((const float *)I, E, p.d_perm, p.n, sp, p.d_sc, p.d_red, rnb, p.d_sticky, p.d_iperm, p.d_xyz, p.d_tmask,
+                                                              p.d_sel, (float *)S_out, partial, la);
+        else
+            select_tiles_kernel<float, false><<<g, bs, 0, s>>>((const float *)I, E, p.d_perm, p.n, sp, p.d_sc, p.d_red, rnb, p.d_sticky, p.d_iperm, p.d_xyz, p.d_tmask,
+                                                               p.d_sel, (float *)S_out, partial, la);
+    }
     // up to 2048 tiles the compaction adds up the earlier tiles' sums itself; beyond, one
     // workgroup scans them first
     const int tile_sums = nb <= 2048 ? 1 : 0;

@@ -212,6 +212,7 @@ size_t layout_workspace(Plan &p, char *base, bool assign)
     take(&p.d_flag, (size_t)n * sizeof(uint64_t));
     take(&p.d_sel, (size_t)n);
     take(&p.d_scan_tmp, p.scan_tmp_bytes);
+    take(&p.d_red, kRedBytes);
     take(&p.d_t_out, (size_t)n * 4);
     take(&p.d_s_dat, (size_t)n * 4 * rs);
     take(&p.d_t_dat, (size_t)n * 4 * rs);
@@ -248,14 +249,9 @@ size_t layout_workspace(Plan &p, char *base, bool assign)
     const int64_t NL = std::max<int32_t>(p.n_pleaf, 1);
     take(&p.d_feat, (size_t)NL * 8 * 4);
     take(&p.d_feat_cnt, (size_t)NL * 4);
-    take(&p.d_logit, (size_t)NL * 4);
     take(&p.d_leafscan, (size_t)(NL + 1) * 4);
-    take(&p.d_lstat, (size_t)NL * 6 * 8);
-    take(&p.d_box_emax, (size_t)B * 4);
-    take(&p.d_cand_list, (size_t)NL * 4);
     take(&p.d_row_box, (size_t)NL * 4);
     take(&p.d_row_feat, (size_t)NL * 8 * 4);
-    take(&p.d_drop, (size_t)n);
     take(&p.d_leafflag, (size_t)(NL + 1) * 4);
     return (off + 255) & ~(size_t)255;
 }
@@ -283,9 +279,9 @@ void free_plan(Plan *p)
                     p->ops.m2m, p->ops.l2l, p->ops.m2l, p->ops.lat_unit, p->ops.shell_unit, p->ops.m2l_hi,
                     p->ops.m2l_lo, p->d_xyzf, p->d_bnd, p->box.level, p->box.ax, p->box.ay, p->box.az,
                     p->box.parent, p->box.child, p->box.coll, p->box.start, p->box.end, p->d_ws_own,
-                    p->d_sel_params, p->d_pleaf, p->d_pleaf_of_box, p->d_pinfo, p->d_pinfo2, p->d_pcoll,
+                    p->d_sel_params, p->d_pleaf, p->d_pinfo, p->d_pinfo2,
                     p->d_cell, p->ops.grid_g, p->ops.grid_gt, p->ops.near_tab, p->d_sticky, p->ops.l2l_comp,
-                    p->d_boxmap, p->d_tmask};
+                    p->d_boxmap, p->d_tmask, p->d_leaf_pos, p->d_tile_leaves};
     // events and streams first, then the memory the work on them used
     if (p->events_ready)
         for (auto &set : p->ring)
@@ -484,25 +480,40 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
         }
         p.n_pleaf = (int32_t)leaves.size();
         up(&p.d_pleaf, leaves);
-        std::vector<int32_t> of_box(FT.level.size(), -1);
-        for (size_t i = 0; i < leaves.size(); ++i) of_box[leaves[i]] = (int32_t)i;
-        up(&p.d_pleaf_of_box, of_box);
         // the selector's per-leaf look-ups in one record each (no chains of dependent loads)
         {
             std::vector<int4> info(leaves.size()), info2(leaves.size());
-            std::vector<int32_t> pc(leaves.size() * 27);
             for (size_t i = 0; i < leaves.size(); ++i) {
                 const int32_t f = leaves[i];
                 info[i] = make_int4(f, FT.start[f], FT.end[f], 0);
                 info2[i] = make_int4(FT.ax[f], FT.ay[f], FT.az[f], FT.level[f]);
-                for (int d = 0; d < 27; ++d) {
-                    const int32_t C = FT.coll[(size_t)f * 27 + d];
-                    pc[i * 27 + d] = C < 0 ? -1 : (of_box[C] >= 0 ? C : -2 - C);
-                }
             }
             upload(p, reinterpret_cast<void **>(&p.d_pinfo), info);
             upload(p, reinterpret_cast<void **>(&p.d_pinfo2), info2);
-            up(&p.d_pcoll, pc);
+        }
+        // the plan leaves by first point, and per selection tile the range of them overlapping it
+        {
+            std::vector<int32_t> order(leaves.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+            std::sort(order.begin(), order.end(),
+                      [&](int32_t a, int32_t b) { return FT.start[leaves[a]] < FT.start[leaves[b]]; });
+            std::vector<int4> pos(order.size());
+            for (size_t j = 0; j < order.size(); ++j) {
+                const int32_t f = leaves[order[j]];
+                pos[j] = make_int4(FT.start[f], FT.end[f], order[j], 0);
+            }
+            const int64_t ntile = (n + kSelTilePoints - 1) / kSelTilePoints;
+            std::vector<int2> tl((size_t)std::max<int64_t>(ntile, 1), make_int2(0, 0));
+            size_t j = 0;
+            for (int64_t tI = 0; tI < ntile; ++tI) {
+                const int64_t t0 = tI * kSelTilePoints, t1 = std::min<int64_t>(n, t0 + kSelTilePoints);
+                while (j < pos.size() && pos[j].y <= t0) ++j;  // leaves ending before the tile
+                size_t e = j;
+                while (e < pos.size() && pos[e].x < t1) ++e;
+                tl[(size_t)tI] = make_int2((int32_t)j, (int32_t)e);
+            }
+            upload(p, reinterpret_cast<void **>(&p.d_leaf_pos), pos);
+            upload(p, reinterpret_cast<void **>(&p.d_tile_leaves), tl);
         }
         p.h_pleaf = std::move(leaves);
         // boxes by level and coordinates, for the composite translations
@@ -863,14 +874,14 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     const bool learned = p.selector == PH_SEL_LEARNED && !threshold_run;
     p.cur_I = I;  // the target kernels read the own-cell term's intensity from it
     mark(0, s);
+    // |E| is read where a field rule needs it, and by the learned selector's features
+    const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
+    const float *Eu = (need_e || learned) ? absE : nullptr;
     // the first kernel clears the call's scalars and advances the call number
-    if (learned) selector_reduce(p, I, absE, p.d_gen, s);  // the maxima come with the per-leaf statistics
-    else launch_reduce_max(I, p.precision == PH_FP64, absE, absE != nullptr, p.n, p.d_sc, p.d_gen, p.d_sticky,
-                           p.d_scan_tmp, s);
+    launch_reduce_max(p, I, Eu, p.d_gen, s);
     mark(1, s);
-    if (learned) selector_decide(p, I, absE, s);
-    mark(2, s);
-    launch_select(p, I, absE, S_out, s, learned ? p.d_drop : nullptr, threshold_run ? p.fallback_rel : -1.0);
+    mark(2, s);  // the learned decisions are made inside the selection pass
+    launch_select(p, I, Eu, S_out, s, learned, threshold_run ? p.fallback_rel : -1.0);
     mark(3, s);
     if (p.method == PH_METHOD_DIRECT) {
         for (int k = 4; k <= 7; ++k) mark(k, s);

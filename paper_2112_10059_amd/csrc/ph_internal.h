@@ -65,7 +65,9 @@ struct CallScalars {
     int32_t gen;                        // number of the call (never 0): V/X target tags
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t emax_key;                  // |E| bits << 32 | ~caller index of the largest |E|
-    double emax_xyz[3];                 // that point's position (learned selector calls)
+    double emax_xyz[3];                 // that point's position
+    uint64_t imax_key;                  // I bits (as FP32) << 32 | ~caller index of the largest I
+    double imax_xyz[3];                 // that point's position
     double check_rel;                   // validated calls: rel-L2 of learned vs threshold result
     // algorithmic work of the call (integer counters, order independent)
     unsigned long long work[12];        // p2p pairs, l2p evals, m2p evals, p2m evals,
@@ -152,7 +154,9 @@ struct OperatorsDev {
     void *l2l_comp = nullptr;
 };
 
-constexpr int kLeafPartials = 2048;  // per-workgroup maxima of the selector's statistics pass (at most)
+constexpr int kLeafPartials = 2048;  // scan space the selector's row compaction may use
+constexpr int kSelTilePoints = 4096;  // sorted points per workgroup of the selection pass
+constexpr size_t kRedBytes = 256 * 24;  // maxima partials: 256 x (max I, |E| key, I key)
 constexpr int kCompMaxDepth = 6;  // composite translations for trees of at most this depth
 
 constexpr int kNearTabMaxR = 7;     // table for leaves of at most 4^3 cells
@@ -202,22 +206,18 @@ struct Plan {
     double fallback_rel = 1e-4;     // threshold rule of the learned selector's fallback
     bool validate = false;          // learned calls also run the threshold rule and compare
     double validate_tol = 1e-3;     // ... falling back when the relative L2 difference exceeds this
-    uint8_t *d_drop = nullptr;      // per sorted point of a candidate leaf: 1 if the leaf was dropped
     uint32_t *d_leafflag = nullptr; // per plan leaf: 1 if it holds a candidate source
     int32_t n_pleaf = 0;            // leaves of the plan's tree over all points
     int32_t *d_pleaf = nullptr;     // their box ids in box order
     std::vector<int32_t> h_pleaf;   // host copy
-    int32_t *d_pleaf_of_box = nullptr; // per box: its plan-leaf index, -1 for split boxes
     int4 *d_pinfo = nullptr;           // per plan leaf: box, first point, end, 0
     int4 *d_pinfo2 = nullptr;          // per plan leaf: anchor x, y, z, level
-    int32_t *d_pcoll = nullptr;        // per plan leaf, 27: colleague box C if a plan leaf,
-                                       // -2 - C if split, -1 if none
     uint32_t *d_leafscan = nullptr; // per plan leaf: candidate flag, scanned by the row compaction
-    double *d_lstat = nullptr;      // per plan leaf: max I, sum |E|, sum |E|^2, max |E|
-    float *d_box_emax = nullptr;    // per box (plan leaves only): max |E|
-    int32_t *d_cand_list = nullptr; // plan-leaf indices of the candidate leaves (any order)
     int32_t *d_row_box = nullptr;   // compacted rows (training entry points): plan-leaf box ids
     float *d_row_feat = nullptr;    // and their features
+    int2 *d_tile_leaves = nullptr;  // per selection tile (4096 sorted points): its plan leaves in d_leaf_pos
+    int4 *d_leaf_pos = nullptr;     // plan leaves by first point: (first, end, plan-leaf index, 0)
+    double *d_red = nullptr;        // partials of the call's maxima (kRedBytes)
 
     // plan-time device arrays
     uint64_t *d_key = nullptr;      // sorted Morton keys (n)
@@ -252,7 +252,6 @@ struct Plan {
     void *d_u = nullptr;            // box_cap x n_lam downward check potentials
     float *d_feat = nullptr;        // learned selector features per plan leaf (n_pleaf x 8)
     int32_t *d_feat_cnt = nullptr;  // candidate sources per plan leaf
-    float *d_logit = nullptr;       // logits per plan leaf
     float *d_sel_params = nullptr;  // device copy of the selector weights
     // per-phase timing: a ring of event sets, one set per recorded call
     static constexpr int kRing = 32;
@@ -350,15 +349,18 @@ void launch_gather_sorted(const double *xyz, const double *w, const int32_t *per
 // selection (k_select.hip)
 // Clears the call's scalars; with gen, also advances the call number there and stores it in sc
 void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s);
-// maxima of I and |E| (partials, then one workgroup); with gen the first kernel also starts the
-// call (clears the scalars, advances the call number)
-void launch_reduce_max(const void *I, bool fp64, const float *E, bool need_e, int64_t n,
-                       CallScalars *sc, int32_t *gen, int32_t *sticky, void *tmp /* >= 16 KiB */, hipStream_t s);
-void launch_reduce_max_final(const double *partial, const uint64_t *partial_key, int nb, CallScalars *sc,
-                             int32_t *sticky, hipStream_t s);  // partials: up to 1024 blocks
-// selection flags, their scan (kept in d_flag for the tree build) and the compaction
-// src_rel >= 0 replaces the plan's source rule for this pass (the threshold run of a validated call)
-void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, const uint8_t *drop,
+// partials of the call's maxima of I and |E| and of the order keys of the largest of each into
+// d_red (at most 256 blocks); with gen the kernel also starts the call (clears the scalars,
+// advances the call number).  The selection pass reduces the partials in every workgroup.
+int reduce_blocks(int64_t n);
+void launch_reduce_max(const Plan &p, const void *I, const float *E, int32_t *gen, hipStream_t s);
+// the training entry points' reduction of those partials into the scalars (the selection pass
+// does it itself on the evaluation path)
+void launch_maxima_store(const Plan &p, bool has_e, hipStream_t s);
+// selection flags (with the learned decisions on the plan leaves when learned), their scan (kept
+// in d_flag for the tree build) and the compaction.  src_rel >= 0 replaces the plan's source rule
+// for this pass (the threshold run of a validated call).
+void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, bool learned,
                    double src_rel = -1.0);
 // validated learned call: S_out (learned) against S_ref (threshold rule); S_ref replaces S_out
 // and the call is marked fallen back when their relative L2 difference exceeds tol
@@ -395,10 +397,9 @@ void fmm_near(Plan &p, hipStream_t s);  // near field (P2P) of the targets of le
 void run_direct(Plan &p, void *S_out, hipStream_t s);
 
 // learned selector (k_mlp.hip)
-// maxima + per-leaf statistics; with gen its kernel also starts the call (see launch_reduce_max)
-void selector_reduce(Plan &p, const void *I, const float *E, int32_t *gen, hipStream_t s);
-void selector_features(Plan &p, const void *I, const float *E, hipStream_t s);  // rows, features (compacted)
-void selector_decide(Plan &p, const void *I, const float *E, hipStream_t s);    // features, network -> d_drop
+// training entry points: the call's maxima, then the rows (candidate plan leaves in box order) and
+// their features, compacted into d_row_box / d_row_feat (resets the call's scalars)
+void selector_features(Plan &p, const void *I, const float *E, hipStream_t s);
 void launch_mlp_forward(const float *params, const float *X, int64_t m, const int32_t *m_dev, float *logits,
                         int bf16, hipStream_t s);
 void launch_mlp_backward(const float *params, const float *X, const float *y, float pos_weight,

@@ -1,26 +1,28 @@
 """Train the learned leaf selector on synthetic streamer fields with the library's own GPU kernels.
 
-The selector decides, per source leaf of the first-pass tree, whether the leaf's sources enter
-the photoionization sum (adaptive source selection of Sec. 3 of the paper, made per leaf by
-a network instead of a fixed relative threshold on I).
+The selector decides, per leaf of the plan's tree that holds sources of the threshold rule
+(Sec. 3 eq. (18): I >= base_src_rel I_max), whether the leaf's sources enter the
+photoionization sum: it can only remove whole leaves from the rule's source set, which also
+removes their boxes from the near field and the multipole passes.
 
 Recipe:
   * fields: the seeded streamer generator (head + channel on the uniform grid); seeds
     [0, n_train) train, [n_train, n_train + n_cal) calibrate the decision threshold;
-  * rows: the plan leaves holding candidate sources (I >= base_src_rel I_max), with their
-    features (ph_selector_features);
-  * per row b its field S_b at every active target (ph_selector_fields, in chunks of targets)
-    and the Gram matrix G[b, b'] = <S_b, S_b'>; S = sum_b S_b is the candidates' field.  All
-    S_b are non-negative, and dropping a set D of rows changes S by exactly
-    sqrt(sum_{b, b' in D} G[b, b']) in L2;
-  * labels: rows in increasing order of ||S_b|| are dropped while that change stays within
-    label_budget ||S|| (1 = keep);
+  * references per field: S (every point a source) and S_rule (the rule's sources) from the
+    plain FP64 FMM; S_0 = S - S_rule is what the rule itself leaves out;
+  * rows: the plan leaves holding the rule's sources, with their features
+    (ph_selector_features); per row b its field S_b at every target (ph_selector_fields, in
+    chunks of targets), the Gram matrix G[b, b'] = <S_b, S_b'> and c[b] = <S_0, S_b>.  All
+    fields are non-negative, and dropping a set D of rows makes the method error exactly
+    ||S_0 + sum_D S_b|| (squared: ||S_0||^2 + 2 sum_D c + sum_{D x D} G);
+  * labels: rows are dropped one at a time, always the one that raises that error the least,
+    while it stays within label_budget ||S|| (1 = keep);
   * network 8 -> 64 -> 64 -> 1 (exact-erf GELU), BCE with logits, positive weight
     n_drop / n_keep, Adam; features standardised on the training rows and the standardisation
     folded into the first layer, so inference takes raw features;
-  * decision threshold: the largest logit threshold at which the change of S caused by the
-    dropped rows stays within gate_budget ||S|| on every calibration field, with the BF16
-    logits that the evaluation path computes.
+  * decision threshold: the largest logit threshold at which the method error of the dropped
+    rows stays within gate_budget ||S|| on every calibration field, with the BF16 logits that
+    the evaluation path computes.
 
 Output: a text file (header lines with the metadata, then the 4801 parameters in the C ABI's
 layout, one per line) read by ``load_selector``.
@@ -45,24 +47,32 @@ NPARAM = B.MLP_NPARAM
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_c2.txt")
 
 
-def keep_labels(G: np.ndarray, s_norm: float, budget: float) -> np.ndarray:
-    """1 = keep.  Rows in increasing order of sqrt(G[b, b]) are dropped while the norm of the
-    dropped rows' summed field stays <= budget * s_norm (G: Gram matrix of the row fields)."""
+def keep_labels(G: np.ndarray, c: np.ndarray, d0: float, s_norm: float, budget: float) -> np.ndarray:
+    """1 = keep.  Rows are dropped one at a time, always the one whose drop raises the squared
+    error d0 + 2 sum_D c + sum_{D x D} G the least (ties: lowest index), while the error stays
+    <= budget * s_norm (the running sums make each step O(rows))."""
     G = np.asarray(G, dtype=np.float64)
-    d = np.diag(G)
-    order = np.argsort(np.sqrt(np.maximum(d, 0.0)), kind="stable")
-    acc = np.zeros(G.shape[0])  # sum over the dropped rows of G[:, b]
-    e2 = 0.0
-    n_drop = 0
-    for b in order:
-        e2n = e2 + d[b] + 2.0 * acc[b]
-        if np.sqrt(e2n) > budget * s_norm:
+    c = np.asarray(c, dtype=np.float64)
+    m = G.shape[0]
+    diag = np.diag(G).copy()
+    acc = c.copy()  # <S_0 + S_D, S_b> for every row b
+    e2 = float(d0)
+    lim = (budget * s_norm) ** 2
+    dropped = np.zeros(m, dtype=bool)
+    while True:
+        rest = np.flatnonzero(~dropped)
+        if rest.size == 0:
             break
-        e2 = e2n
-        acc += G[:, b]
-        n_drop += 1
-    lab = np.ones(G.shape[0], dtype=np.float32)
-    lab[order[:n_drop]] = 0.0
+        inc = diag[rest] + 2.0 * acc[rest]
+        ok = e2 + inc <= lim
+        if not ok.any():
+            break
+        j = rest[np.flatnonzero(ok)[np.argmin(inc[ok])]]
+        e2 += diag[j] + 2.0 * acc[j]
+        acc += G[:, j]
+        dropped[j] = True
+    lab = np.ones(m, dtype=np.float32)
+    lab[dropped] = 0.0
     return lab
 
 
@@ -87,16 +97,19 @@ def fold_standardisation(p: np.ndarray, mu: np.ndarray, sd: np.ndarray) -> np.nd
 
 
 def calibrate_threshold(fields, gate_budget: float) -> float:
-    """Largest t such that on every field (z, G, s_norm) the rows with logit < t change S by
-    at most gate_budget * s_norm (exact, from the Gram matrix)."""
+    """Largest t such that on every field (z, G, c, d0, s_norm) the rows with logit < t leave a
+    method error of at most gate_budget * s_norm (exact, from G, c and d0)."""
     best = math.inf
-    for z, G, s_norm in fields:
+    for z, G, c, d0, s_norm in fields:
         order = np.argsort(z, kind="stable")
-        acc = np.zeros(G.shape[0])
-        e2 = 0.0
+        acc = np.asarray(c, dtype=np.float64).copy()
+        e2 = float(d0)
+        lim = (gate_budget * s_norm) ** 2
+        if e2 > lim:
+            return -math.inf  # the rule alone is over the budget: keep every row
         for b in order:
             e2n = e2 + G[b, b] + 2.0 * acc[b]
-            if np.sqrt(e2n) > gate_budget * s_norm:
+            if e2n > lim:
                 # rows strictly below z[b] are dropped: they are the prefix before b
                 best = min(best, float(z[b]))
                 break
@@ -123,19 +136,19 @@ def load_selector(path: str | None = None):
     return w, meta
 
 
-def field_rows(plan, I, E, targets, torch, chunk: int = 65536):
-    """Features (rows x 8), Gram matrix of the row fields over the targets, and ||S||."""
+def field_rows(plan, I, E, targets, S0, torch, chunk: int = 65536):
+    """Features (rows x 8), Gram matrix G of the row fields over the targets, c = <S_0, S_b>."""
     F = B.selector_features(plan, I, E)
     m = F.shape[0]
     G = torch.zeros((m, m), dtype=torch.float64, device="cuda")
-    s2 = 0.0
+    c = torch.zeros(m, dtype=torch.float64, device="cuda")
     buf = torch.empty((max(m, 1), chunk), dtype=torch.float32, device="cuda")
     for t0 in range(0, targets.numel(), chunk):
         tc = targets[t0:t0 + chunk]
         Fc = B.selector_fields(plan, I, tc, m, ld=chunk, out=buf).double()
         G += Fc @ Fc.T
-        s2 += float((Fc.sum(dim=0) ** 2).sum())
-    return F.cpu().numpy(), G.cpu().numpy(), math.sqrt(s2)
+        c += Fc @ S0[t0:t0 + chunk]
+    return F.cpu().numpy(), G.cpu().numpy(), c.cpu().numpy()
 
 
 def main(argv=None):
@@ -144,9 +157,9 @@ def main(argv=None):
     ap.add_argument("--n-train", type=int, default=180)
     ap.add_argument("--n-cal", type=int, default=20)
     ap.add_argument("--n-axis", type=int, default=128)
-    ap.add_argument("--base-src-rel", type=float, default=1e-7)
-    ap.add_argument("--label-budget", type=float, default=5e-4)
-    ap.add_argument("--gate-budget", type=float, default=8e-4)
+    ap.add_argument("--base-src-rel", type=float, default=1e-4)
+    ap.add_argument("--label-budget", type=float, default=8e-4)
+    ap.add_argument("--gate-budget", type=float, default=8.5e-4)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -163,23 +176,34 @@ def main(argv=None):
     lo, hi = wl0.domain
     thr = dict(wl0.thresholds)
     thr["src_rel"] = a.base_src_rel
-    plan = B.Plan(wl0.xyz, wl0.gas, thr, h=wl0.h, w=wl0.w, cube_lo=(lo, lo, lo), cube_size=hi - lo)
-    rows, grams = [], []
+    geo = dict(h=wl0.h, w=wl0.w, cube_lo=(lo, lo, lo), cube_size=hi - lo)
+    plan = B.Plan(wl0.xyz, wl0.gas, thr, **geo)
+    p_all = B.Plan(wl0.xyz, wl0.gas, dict(src_rel=0.0), precision="fp64", **geo)
+    p_rule = B.Plan(wl0.xyz, wl0.gas, dict(src_rel=a.base_src_rel), precision="fp64", **geo)
+    rows, cals = [], []
     for s in range(a.n_train + a.n_cal):
         wl = wl0 if s == 0 else gen.config2(seed=s, n_axis=a.n_axis)
         I = torch.tensor(wl.I.astype(np.float32), device="cuda")
         E = torch.tensor(wl.E.astype(np.float32), device="cuda")
         plan.evaluate(I, E)
         # the call's own target set, in caller order
-        targets = np.sort(plan.debug_fetch("perm")[plan.debug_fetch("tgt")]).astype(np.int32)
-        F, G, s_norm = field_rows(plan, I, E, torch.tensor(targets, device="cuda"), torch)
-        y = keep_labels(G, s_norm, a.label_budget)
+        targets = np.sort(plan.debug_fetch("perm")[plan.debug_fetch("tgt")]).astype(np.int64)
+        I64 = torch.tensor(wl.I.astype(np.float32).astype(np.float64), device="cuda")
+        S_all = p_all.evaluate(I64)
+        S0 = (S_all - p_rule.evaluate(I64))[torch.tensor(targets, device="cuda")]
+        s_norm = float(torch.linalg.norm(S_all[torch.tensor(targets, device="cuda")]))
+        d0 = float(S0 @ S0)
+        F, G, c = field_rows(plan, I, E, torch.tensor(targets.astype(np.int32), device="cuda"), S0, torch)
+        y = keep_labels(G, c, d0, s_norm, a.label_budget)
         rows.append((F, y))
         if s >= a.n_train:
-            grams.append((G, s_norm))
+            cals.append((G, c, d0, s_norm))
         if s % 20 == 0 or s + 1 == a.n_train + a.n_cal:
-            print(f"field {s}: {F.shape[0]} rows, keep {int(y.sum())} ({time.time() - t0:.0f} s)", flush=True)
+            print(f"field {s}: {F.shape[0]} rows, keep {int(y.sum())}, rule error {math.sqrt(d0) / s_norm:.3e} "
+                  f"({time.time() - t0:.0f} s)", flush=True)
     plan.close()
+    p_all.close()
+    p_rule.close()
 
     Xtr = np.concatenate([r[0] for r in rows[:a.n_train]]).astype(np.float64)
     ytr = np.concatenate([r[1] for r in rows[:a.n_train]]).astype(np.float32)
@@ -216,27 +240,27 @@ def main(argv=None):
     pf = fold_standardisation(p.cpu().numpy(), mu, sd)
     wdev = torch.tensor(pf, device="cuda")
     cal, agree = [], []
-    for (F, y), (G, s_norm) in zip(rows[a.n_train:], grams):
+    for (F, y), (G, c, d0, s_norm) in zip(rows[a.n_train:], cals):
         z = B.mlp_forward(wdev, torch.tensor(F, device="cuda"), bf16=True).cpu().numpy().astype(np.float64)
-        cal.append((z, G, s_norm))
+        cal.append((z, G, c, d0, s_norm))
         agree.append(y)
     tau = calibrate_threshold(cal, a.gate_budget)
     if not math.isfinite(tau):
-        tau = 1e30
+        tau = 1e30 if tau > 0 else -1e30
     kept, change, agreement = [], [], []
-    for (z, G, s_norm), y in zip(cal, agree):
+    for (z, G, c, d0, s_norm), y in zip(cal, agree):
         d = z < tau
         kept.append(float(np.mean(~d)))
-        change.append(float(np.sqrt(G[np.ix_(d, d)].sum()) / s_norm))
+        change.append(float(np.sqrt(d0 + 2.0 * c[d].sum() + G[np.ix_(d, d)].sum()) / s_norm))
         agreement.append(float(np.mean((~d) == (y > 0.5))))
     meta = dict(threshold=tau, base_src_rel=a.base_src_rel, label_budget=a.label_budget,
                 gate_budget=a.gate_budget, n_train=a.n_train, n_cal=a.n_cal, n_axis=a.n_axis,
                 epochs=a.epochs, batch=a.batch, lr=a.lr, seed=a.seed, pos_weight=pos_weight,
                 feature_mean=mu.tolist(), feature_std=sd.tolist(),
-                cal_kept_row_fraction=float(np.mean(kept)), cal_change_max=float(max(change)),
+                cal_kept_row_fraction=float(np.mean(kept)), cal_error_max=float(max(change)),
                 cal_label_agreement=float(np.mean(agreement)))
     print("calibration:", json.dumps({k: meta[k] for k in ("threshold", "cal_kept_row_fraction",
-                                                             "cal_change_max", "cal_label_agreement")}),
+                                                             "cal_error_max", "cal_label_agreement")}),
           flush=True)
     with open(a.out, "w") as f:
         f.write("# learned leaf selector: 8 -> 64 -> 64 -> 1 GELU network, parameters in the C ABI layout\n")

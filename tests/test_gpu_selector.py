@@ -117,21 +117,18 @@ def test_selector_features_match_numpy(gpu_lib):
     Es = E32[perm].astype(np.float64)
     Is = I32[perm].astype(np.float64)
     xE = wl.xyz[int(np.argmax(E32))]  # first in caller order among ties
+    xI = wl.xyz[int(np.argmax(I32))]
     ref = np.zeros_like(F)
     for r, (b, (st, en)) in enumerate(zip(ids, rng)):
         lev, ax, ay, az = (int(v) for v in full[b, :4])
-        Iv = Is[st:en]
-        Iv = Iv[Iv >= src_rel * Imax]
+        Iall = Is[st:en]
+        Iv = Iall[Iall >= src_rel * Imax]
         side = cube / 2 ** lev
         ctr = lo + (np.array([ax, ay, az]) + 0.5) * side
         e = Es[st:en] / Emax
-        nb = [[ax + dx, ay + dy, az + dz] for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
-              if 0 <= ax + dx < 2 ** lev and 0 <= ay + dy < 2 ** lev and 0 <= az + dz < 2 ** lev]
-        cs, ce = _ranges(keys, lev, nb)
-        emx_nb = max(Es[a:b].max() / Emax for a, b in zip(cs, ce) if b > a)
         ref[r] = [math.log10(Iv.max() / Imax), math.log10(Iv.sum() * w_ref / (Imax * w_ref)),
-                  math.log2(side / w_ref ** (1 / 3)), math.log10(1 + np.linalg.norm(ctr - xE) / side),
-                  e.max(), e.mean(), e.std(), emx_nb]
+                  math.log10(Iv.size / Iall.size), math.log10(1 + np.linalg.norm(ctr - xI) / side),
+                  math.log10(1 + np.linalg.norm(ctr - xE) / side), e.max(), e.mean(), e.std()]
     assert np.allclose(F, ref, rtol=2e-5, atol=2e-5)
     plan.close()
 
@@ -209,8 +206,8 @@ def test_learned_nonfinite_logits_fall_back_to_threshold(gpu_lib):
     _say("learned fallback")
     tI, tE = _t(wl.I.astype(np.float32)), _t(wl.E.astype(np.float32))
     w = np.zeros(omlp.NPARAM, dtype=np.float32)
-    w[:512] = 1e30   # W1: every hidden unit saturates to +inf or -inf ...
-    w[576:4672] = 1e30
+    w[512:576] = 1e30    # b1: every first-layer unit at 1e30 whatever the features ...
+    w[576:4672] = 1e30   # W2: every second-layer unit overflows to +inf ...
     w[4736:4800] = np.where(np.arange(64) % 2 == 0, 1.0, -1.0).astype(np.float32)  # ... and inf - inf
     p1 = gpu_lib.Plan(wl.xyz, wl.gas, thr, leaf_capacity=32, selector="learned", selector_weights=w,
                       selector_fallback_rel=1e-4, **plan_kwargs(wl))

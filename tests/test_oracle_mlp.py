@@ -100,3 +100,44 @@ def test_gram_labels_brute_force_on_explicit_fields():
         if drop.size < m:
             nxt = order[:drop.size + 1]
             assert np.linalg.norm(F[nxt].sum(axis=0)) > budget * np.linalg.norm(S)
+
+
+def test_greedy_labels_orthogonal_fields_hand_case():
+    # disjoint supports, no field left out by the rule: the cheapest rows go first while the
+    # root sum of squares stays within the budget
+    c = np.array([3e-4, 1e-4, 0.5, 2e-4, 4e-4])
+    lab = mlp.greedy_keep_labels(np.diag(c ** 2), np.zeros(5), 0.0, 1.0, 4e-4)
+    assert lab.tolist() == [0, 0, 1, 0, 1]
+    # with a left-out field of norm 3e-4 that overlaps nothing, only 1e-4 and 2e-4 still fit
+    # (sqrt(9e-8 + 1e-8 + 4e-8) = 3.74e-4; adding 3e-4 gives 4.8e-4)
+    lab = mlp.greedy_keep_labels(np.diag(c ** 2), np.zeros(5), 9e-8, 1.0, 4e-4)
+    assert lab.tolist() == [1, 0, 1, 0, 1]
+    # the left-out field alone over the budget: nothing is dropped
+    assert mlp.greedy_keep_labels(np.diag(c ** 2), np.zeros(5), 1.0, 1.0, 4e-4).tolist() == [1] * 5
+
+
+def test_greedy_labels_brute_force_on_explicit_fields():
+    """From explicit non-negative fields: every greedy step is the cheapest, the final error is within
+    the budget, and no remaining row could be dropped too."""
+    rng = np.random.default_rng(8)
+    for trial in range(15):
+        m, nt = int(rng.integers(2, 14)), 40
+        F = rng.lognormal(-6, 2, size=(m, 1)) * rng.uniform(0, 1, size=(m, nt)) ** 3
+        F0 = rng.lognormal(-9, 1) * rng.uniform(0, 1, size=nt) ** 2
+        S = F.sum(axis=0) + F0
+        budget = float(rng.choice([1e-3, 1e-2, 1e-1]))
+        lab = mlp.greedy_keep_labels(F @ F.T, F @ F0, float(F0 @ F0), np.linalg.norm(S), budget)
+        drop = np.flatnonzero(lab == 0)
+        lim = budget * np.linalg.norm(S)
+        if drop.size:
+            assert np.linalg.norm(F0 + F[drop].sum(axis=0)) <= lim * (1 + 1e-12)
+        for b in np.flatnonzero(lab == 1):
+            assert np.linalg.norm(F0 + F[drop].sum(axis=0) + F[b]) > lim * (1 - 1e-12)
+        # replay: each step took the cheapest row among those that fit
+        taken = []
+        for _ in range(drop.size):
+            rest = [b for b in range(m) if b not in taken]
+            norms = [np.linalg.norm(F0 + F[taken + [b]].sum(axis=0)) for b in rest]
+            nxt = rest[int(np.argmin(norms))]
+            taken.append(nxt)
+        assert sorted(taken) == sorted(drop.tolist())

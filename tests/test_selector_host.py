@@ -11,17 +11,19 @@ def _fields(rng, m, nt=60):
     return rng.lognormal(-6, 2, size=(m, 1)) * rng.uniform(0, 1, size=(m, nt)) ** 3
 
 
-def test_keep_labels_match_oracle_gram_rule():
+def test_keep_labels_match_oracle_greedy_rule():
     rng = np.random.default_rng(0)
     for trial in range(40):
-        F = _fields(rng, int(rng.integers(1, 60)))
+        m = int(rng.integers(1, 40))
+        F = _fields(rng, m)
+        F0 = rng.lognormal(-9, 1) * rng.uniform(0, 1, size=F.shape[1]) ** 2
         if trial % 5 == 0:
-            F[: F.shape[0] // 3] = F[0]  # equal norms
-        G = F @ F.T
-        s_norm = float(np.linalg.norm(F.sum(axis=0)))
+            F[: m // 3] = F[0]  # equal fields
+        G, c, d0 = F @ F.T, F @ F0, float(F0 @ F0)
+        s_norm = float(np.linalg.norm(F.sum(axis=0) + F0))
         budget = float(rng.choice([0.0, 1e-3, 1e-2, 1e-1, 10.0]))
-        ours = ts.keep_labels(G, s_norm, budget)
-        ref = omlp.budgeted_keep_labels_gram(G, s_norm, budget)
+        ours = ts.keep_labels(G, c, d0, s_norm, budget)
+        ref = omlp.greedy_keep_labels(G, c, d0, s_norm, budget)
         assert np.array_equal(ours, ref.astype(np.float32))
 
 
@@ -41,20 +43,27 @@ def test_calibrated_threshold_keeps_every_field_within_budget():
     fields, raw = [], []
     for _ in range(12):
         F = _fields(rng, 80)
+        F0 = rng.lognormal(-9, 1) * rng.uniform(0, 1, size=F.shape[1]) ** 2
         z = rng.normal(size=80)
-        fields.append((z, F @ F.T, float(np.linalg.norm(F.sum(axis=0)))))
-        raw.append((z, F))
+        S = F.sum(axis=0) + F0
+        fields.append((z, F @ F.T, F @ F0, float(F0 @ F0), float(np.linalg.norm(S))))
+        raw.append((z, F, F0))
     budget = 2e-2
+
+    def err(z, F, F0, t):
+        return np.linalg.norm(F0 + F[z < t].sum(axis=0)) / np.linalg.norm(F.sum(axis=0) + F0)
+
     t = ts.calibrate_threshold(fields, budget)
     assert math.isfinite(t)
-    change = lambda z, F, t: np.linalg.norm(F[z < t].sum(axis=0)) / np.linalg.norm(F.sum(axis=0))
-    assert all(change(z, F, t) <= budget * (1 + 1e-12) for z, F in raw)
+    assert all(err(z, F, F0, t) <= budget * (1 + 1e-12) for z, F, F0 in raw)
     # the next larger logit breaks the budget on at least one field
-    above = min(z[z > t].min() for z, _ in raw if np.any(z > t))
-    assert any(change(z, F, above + 1e-12) > budget for z, F in raw)
-    # a field that never breaks the budget does not bind
+    above = min(z[z > t].min() for z, _, _ in raw if np.any(z > t))
+    assert any(err(z, F, F0, above + 1e-12) > budget for z, F, F0 in raw)
+    # a field that never breaks the budget does not bind; one whose left-out field alone breaks
+    # it keeps every row
     F = _fields(rng, 5)
-    assert ts.calibrate_threshold([(np.zeros(5), F @ F.T, 1e30)], 1e-3) == math.inf
+    assert ts.calibrate_threshold([(np.zeros(5), F @ F.T, np.zeros(5), 0.0, 1e30)], 1e-3) == math.inf
+    assert ts.calibrate_threshold([(np.zeros(5), F @ F.T, np.zeros(5), 1.0, 1.0)], 1e-3) == -math.inf
 
 
 def test_weights_file_round_trip(tmp_path):
