@@ -235,8 +235,10 @@ ph_status ph_plan_set_graph(ph_plan *plan, int enable);
 /*
  * Per-phase device time.  ms_sum (host, PH_NPHASES doubles, nullable) receives the
  * summed hipEvent time of every call recorded since the previous query, per phase:
- *   0 maxima of I and |E|      1 learned selector (rows, features, network, drop mask)
- *   2 selection + compaction   3 octree        4 interaction lists
+ *   0 maxima of I and |E|
+ *   1 selection flags, one pass over the points (with the learned selector: its rows,
+ *     features, network and decisions, made inside that pass)
+ *   2 compaction of the selected points   3 octree        4 interaction lists
  *   5 upward pass (P2M, M2M)   6 downward pass (M2L, L2L, P2L; waits for the lists)
  *   7 far field at the targets (L2P, M2P, own cell) and the output (waits for 8)
  *   8 near field (P2P), or the whole direct sum

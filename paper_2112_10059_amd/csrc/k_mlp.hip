@@ -257,9 +257,9 @@ struct RowArgs {
     int32_t *cnt;
 };
 
-// One thread per plan leaf (box order): statistics in point order (the same function as the
-// evaluation path's), and for a candidate leaf its features; flag (and flag2, the compaction's
-// copy) 1 for a candidate leaf, else 0.
+// One wave per plan leaf (box order): its statistics (the same function as the evaluation
+// path's), and for a candidate leaf its features; flag (and flag2, the compaction's copy) 1 for
+// a candidate leaf, else 0.
 template <class T>
 __global__ __launch_bounds__(256) void leaf_rows_kernel(RowArgs a, const T *__restrict__ I, const float *__restrict__ E)
 {
@@ -271,8 +271,9 @@ __global__ __launch_bounds__(256) void leaf_rows_kernel(RowArgs a, const T *__re
         r.xi[d] = a.sc->imax_xyz[d];
         r.xe[d] = a.sc->emax_xyz[d];
     }
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && a.flag2) a.flag2[a.n_pleaf] = 0;
+    const int lane = threadIdx.x & 63;
+    const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (i == 0 && lane == 0 && a.flag2) a.flag2[a.n_pleaf] = 0;
     if (i >= a.n_pleaf) return;
     const int4 inf = a.pinfo[i], g = a.pinfo2[i];
     auto fetch = [&](int32_t k, double &v, double &e) {
@@ -280,17 +281,23 @@ __global__ __launch_bounds__(256) void leaf_rows_kernel(RowArgs a, const T *__re
         v = (double)I[o];
         e = E ? (double)E[o] : 0.0;
     };
-    const mlp::LeafStats s = mlp::leaf_stats_seq(fetch, a.w, r.w_ref, inf.y, inf.z, a.src_rel, r.imax);
+    const mlp::LeafStats s = mlp::leaf_stats_wave(fetch, a.w, r.w_ref, inf.y, inf.z, a.src_rel, r.imax, lane);
     const bool cand = s.n_c > 0.0;
     if (cand) {
         float fe[PH_MLP_NIN];
         mlp::leaf_features(s, r, g.w, g.x, g.y, g.z, fe);
+        if (lane < PH_MLP_NIN) {
+            float f = fe[0];
 #pragma unroll
-        for (int q = 0; q < PH_MLP_NIN; ++q) a.feats[(size_t)i * PH_MLP_NIN + q] = fe[q];
+            for (int q = 1; q < PH_MLP_NIN; ++q) f = lane == q ? fe[q] : f;
+            a.feats[(size_t)i * PH_MLP_NIN + lane] = f;
+        }
     }
-    a.flag[i] = cand ? 1u : 0u;
-    if (a.flag2) a.flag2[i] = cand ? 1u : 0u;
-    a.cnt[i] = (int32_t)s.n_c;
+    if (lane == 0) {
+        a.flag[i] = cand ? 1u : 0u;
+        if (a.flag2) a.flag2[i] = cand ? 1u : 0u;
+        a.cnt[i] = (int32_t)s.n_c;
+    }
 }
 
 // Row compaction for the training entry points: rows in box order, with their features.
@@ -416,7 +423,7 @@ void selector_features(Plan &p, const void *I, const float *E, hipStream_t s)
     a.flag = p.d_leafflag;
     a.flag2 = p.d_leafscan;
     a.cnt = p.d_feat_cnt;
-    const unsigned g = (unsigned)((p.n_pleaf + 255) / 256);
+    const unsigned g = (unsigned)((p.n_pleaf + 3) / 4);  // a wave per plan leaf
     if (p.precision == PH_FP64) leaf_rows_kernel<double><<<g, 256, 0, s>>>(a, (const double *)I, E);
     else leaf_rows_kernel<float><<<g, 256, 0, s>>>(a, (const float *)I, E);
     exclusive_scan_u32(p.d_leafscan, p.n_pleaf + 1, p.d_scan_tmp, reinterpret_cast<uint32_t *>(&p.d_sc->n_srcleaf), s);

@@ -37,30 +37,35 @@ __device__ __forceinline__ float q(float x)
 }
 
 // Inference, one wave per row: lane i owns hidden unit i of both layers.  The first two
-// weight matrices are staged transposed in LDS so that the 64 lanes read consecutive words;
-// the hidden activations of layer 1 are broadcast lane by lane, and the output layer is a
-// fixed butterfly sum over the wave.  Every inference (the evaluation path and the
-// standalone forward call) runs mlp_row, so their logits agree bit for bit.
+// weight matrices are staged in LDS as groups of four consecutive inputs per hidden unit
+// (w[(k / 4) NH + i][k % 4] is weight (i, k)), so a lane reads four weights in one 16-byte
+// load and the 64 lanes read consecutive words.  The hidden activations of layer 1 are
+// broadcast lane by lane through scalar registers, and the output layer is a fixed butterfly
+// sum over the wave.  Every inference (the evaluation path and the standalone forward call)
+// runs mlp_row, so their logits agree bit for bit; every sum runs over its inputs in order.
 struct MlpLds {
-    float w1t[NIN * NH], w2t[NH * NH], b1[NH], b2[NH], w3[NH], b3;
+    float4 w1[NIN / 4 * NH], w2[NH / 4 * NH];
+    float b1[NH], b2[NH], w3[NH], b3;
 };
+static_assert(NIN % 4 == 0 && NH % 4 == 0, "weights are staged four inputs at a time");
 
 template <bool BF16>
 __device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
 {
-    // walk the parameters in order (consecutive threads, consecutive addresses) and transpose
-    // on the LDS side; eight loads per thread in flight
-    // before their stores (one round trip per batch, not one per element).  Weight (o, i) of a
-    // layer with NI inputs sits at o NI + i in the parameters and at i NH + o in LDS.
+    // walk the parameters in order (consecutive threads, consecutive addresses) and regroup
+    // on the LDS side; eight loads per thread in flight before their stores (one round trip
+    // per batch, not one per element).  Weight (o, i) of a layer with NI inputs sits at
+    // o NI + i in the parameters.
     constexpr int kB = 8;
+    float *w1 = reinterpret_cast<float *>(L.w1), *w2 = reinterpret_cast<float *>(L.w2);
     for (int t0 = threadIdx.x; t0 < NH * NIN; t0 += kB * blockDim.x) {
         float v[kB];
 #pragma unroll
         for (int b = 0; b < kB; ++b) v[b] = params[OFF_W1 + min(t0 + b * (int)blockDim.x, NH * NIN - 1)];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            const int u = t0 + b * (int)blockDim.x;
-            if (u < NH * NIN) L.w1t[(u % NIN) * NH + u / NIN] = q<BF16>(v[b]);
+            const int u = t0 + b * (int)blockDim.x, o = u / NIN, i = u % NIN;
+            if (u < NH * NIN) w1[((i >> 2) * NH + o) * 4 + (i & 3)] = q<BF16>(v[b]);
         }
     }
     for (int t0 = threadIdx.x; t0 < NH * NH; t0 += kB * blockDim.x) {
@@ -69,8 +74,8 @@ __device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
         for (int b = 0; b < kB; ++b) v[b] = params[OFF_W2 + min(t0 + b * (int)blockDim.x, NH * NH - 1)];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            const int u = t0 + b * (int)blockDim.x;
-            if (u < NH * NH) L.w2t[(u % NH) * NH + u / NH] = q<BF16>(v[b]);
+            const int u = t0 + b * (int)blockDim.x, o = u / NH, i = u % NH;
+            if (u < NH * NH) w2[((i >> 2) * NH + o) * 4 + (i & 3)] = q<BF16>(v[b]);
         }
     }
     if (threadIdx.x < NH) {
@@ -81,17 +86,35 @@ __device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
     if (threadIdx.x == 0) L.b3 = q<BF16>(params[OFF_B3]);
 }
 
+// value of lane j (uniform j) in every lane
+__device__ __forceinline__ float lane_bcast(float v, int j)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
 // x: the row's 8 inputs, the same values in every lane.  Returns the logit in every lane.
 template <bool BF16>
 __device__ __forceinline__ float mlp_row(const float (&x)[NIN], const MlpLds &L, int lane)
 {
     float a = L.b1[lane];
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) a += L.w1t[k * NH + lane] * q<BF16>(x[k]);
+    for (int k4 = 0; k4 < NIN / 4; ++k4) {
+        const float4 wq = L.w1[k4 * NH + lane];
+        a += wq.x * q<BF16>(x[4 * k4 + 0]);
+        a += wq.y * q<BF16>(x[4 * k4 + 1]);
+        a += wq.z * q<BF16>(x[4 * k4 + 2]);
+        a += wq.w * q<BF16>(x[4 * k4 + 3]);
+    }
     const float h1 = q<BF16>(gelu(a));
     float a2 = L.b2[lane];
-#pragma unroll 16
-    for (int j = 0; j < NH; ++j) a2 += L.w2t[j * NH + lane] * __shfl(h1, j);
+#pragma unroll 4
+    for (int j4 = 0; j4 < NH / 4; ++j4) {
+        const float4 wq = L.w2[j4 * NH + lane];
+        a2 += wq.x * lane_bcast(h1, 4 * j4 + 0);
+        a2 += wq.y * lane_bcast(h1, 4 * j4 + 1);
+        a2 += wq.z * lane_bcast(h1, 4 * j4 + 2);
+        a2 += wq.w * lane_bcast(h1, 4 * j4 + 3);
+    }
     float z = L.w3[lane] * q<BF16>(gelu(a2));
     for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
     return z + L.b3;
@@ -117,21 +140,22 @@ __device__ __forceinline__ bool candidate(double v, double src_rel, double imax)
     return (src_rel <= 0.0) || (v >= src_rel * imax);
 }
 
-// Statistics of one plan leaf (sorted points [st, en)) by one thread, in point order: over the
-// candidates (the plan's source rule) the largest I, the sum of w I and their count; over all
-// points the largest, the sum and the sum of squares of |E|.  fetch(k, v, e) gives I and |E| of
-// sorted point k.  One thread per leaf needs no cross-lane reductions, and the fixed order makes
-// the sums the same wherever the values come from.
+// Statistics of one plan leaf (sorted points [st, en)) by one wave: over the candidates (the
+// plan's source rule) the largest I, the sum of w I and their count; over all points the
+// largest, the sum and the sum of squares of |E|.  fetch(k, v, e) gives I and |E| of sorted
+// point k.  Lane l takes points st + l, st + l + 64, ... in order, and the lanes are combined
+// by a fixed butterfly, which leaves the same bits in every lane; so the statistics do not
+// depend on where the values come from, and every caller of this function agrees bit for bit.
 struct LeafStats {
     double imax_c, swi_c, n_c, emax, es, es2, n;
 };
 
 template <class F>
-__device__ __forceinline__ LeafStats leaf_stats_seq(F &&fetch, const double *__restrict__ w, double w_ref, int32_t st,
-                                                    int32_t en, double src_rel, double imax)
+__device__ __forceinline__ LeafStats leaf_stats_wave(F &&fetch, const double *__restrict__ w, double w_ref,
+                                                     int32_t st, int32_t en, double src_rel, double imax, int lane)
 {
     LeafStats s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, (double)(en - st)};
-    for (int32_t k = st; k < en; ++k) {
+    for (int32_t k = st + lane; k < en; k += 64) {
         double v, e;
         fetch(k, v, e);
         if (candidate(v, src_rel, imax)) {
@@ -143,6 +167,12 @@ __device__ __forceinline__ LeafStats leaf_stats_seq(F &&fetch, const double *__r
         s.es += e;
         s.es2 += e * e;
     }
+    s.imax_c = wave_max(s.imax_c);
+    s.swi_c = wave_sum(s.swi_c);
+    s.n_c = wave_sum(s.n_c);
+    s.emax = wave_max(s.emax);
+    s.es = wave_sum(s.es);
+    s.es2 = wave_sum(s.es2);
     return s;
 }
 

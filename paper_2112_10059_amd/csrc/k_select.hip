@@ -251,17 +251,19 @@ struct LearnArgs {
     int count;                   // count rows and candidates into the scalars (calls with statistics)
 };
 
-constexpr int kLearnBatch = 64;  // leaves examined per round (at most 4 candidate leaves per wave)
+constexpr int kLearnBatch = 64;  // leaves examined per round
 
 template <class T>
 struct TileLds {
     T I[kSelTile];
     float E[kSelTile];
-    uint64_t cand[kSelWaves * kSelStrips];  // candidate bit per point, a word per strip
+    uint64_t cand[kSelTile / 64];  // candidate bit per point, a word per 64 points
     uint8_t state[kSelTile];
     mlp::MlpLds net;
+    int4 rowpos[kLearnBatch];      // the round's candidate leaves: (first, end, plan-leaf index, 0)
+    int4 rowgeo[kLearnBatch];      // and their anchor x, y, z and level
+    mlp::LeafStats rowstat[kLearnBatch];
     float rowf[kLearnBatch][PH_MLP_NIN];
-    int32_t rowleaf[kLearnBatch];
     int32_t nrow;
 };
 
@@ -279,22 +281,28 @@ __device__ __forceinline__ bool any_cand(const TileLds<T> &S, int a, int b)
     return false;
 }
 
+// Per round of up to kLearnBatch leaves: (1) a thread per leaf finds the candidate leaves and
+// records them as rows; (2) a wave per row takes the leaf's statistics, a lane per point;
+// (3) a lane per row computes the features (FP64 logarithms, once for all rows of the round);
+// (4) a wave per row runs the network and writes the decision into the tile's point states.
+// pre: the first round's leaf records, loaded by the first threads with the tile's values.
 template <class T>
 __device__ void learned_decisions(const T *__restrict__ I, const float *__restrict__ E,
                                   const int32_t *__restrict__ perm, int64_t n, const SelectParams &sp,
                                   const Maxima &mx, const int32_t *__restrict__ iperm, const double *__restrict__ xyz,
-                                  const LearnArgs &la, CallScalars *__restrict__ sc, TileLds<T> &S)
+                                  const LearnArgs &la, CallScalars *__restrict__ sc, TileLds<T> &S, int2 range,
+                                  int4 pre, bool anycand)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
     const int64_t t0 = (int64_t)blockIdx.x * kSelTile, t1 = min(n, t0 + kSelTile);
-    const int2 range = la.tile_leaves[blockIdx.x];
-    bool staged = false;
+    // a tile holding a candidate stages the weights at once (its rows need them in any case)
+    bool staged = anycand;
+    if (anycand) mlp::stage_weights<true>(la.params, S.net);
     for (int32_t b0 = range.x; b0 < range.y; b0 += kLearnBatch) {
-        // the candidate leaves among the next leaves, compacted into the round's rows
         if (threadIdx.x == 0) S.nrow = 0;
         __syncthreads();
         for (int32_t li = b0 + (int32_t)threadIdx.x; li < min(range.y, b0 + kLearnBatch); li += blockDim.x) {
-            const int4 lp = la.leaf_pos[li];
+            const int4 lp = (b0 == range.x && li - b0 < (int32_t)blockDim.x) ? pre : la.leaf_pos[li];
             bool c;
             if (lp.x >= t0 && lp.y <= t1) {
                 c = any_cand(S, (int)(lp.x - t0), (int)(lp.y - t0));
@@ -302,35 +310,24 @@ __device__ void learned_decisions(const T *__restrict__ I, const float *__restri
                 c = false;
                 for (int32_t k = lp.x; k < lp.y && !c; ++k) c = src_rule((double)I[perm[k]], sp.src_rel, mx.imax);
             }
-            if (c) S.rowleaf[atomicAdd(&S.nrow, 1)] = li;
-            else if (lp.x >= t0) la.leafflag[lp.z] = 0u;
+            if (c) {
+                const int r = atomicAdd(&S.nrow, 1);
+                S.rowpos[r] = lp;
+                S.rowgeo[r] = la.pinfo2[lp.z];
+            } else if (lp.x >= t0) {
+                la.leafflag[lp.z] = 0u;
+            }
         }
         __syncthreads();
         const int nrow = S.nrow;
         if (nrow == 0) continue;
-        // statistics and features, a wave per candidate leaf
-        mlp::FeatureRefs r;
-        r.imax = mx.imax;
-        r.emax = mx.emax;
-        r.w_ref = la.w_ref;
-        r.lo[0] = la.lo0;
-        r.lo[1] = la.lo1;
-        r.lo[2] = la.lo2;
-        r.cube = la.cube;
-        r.efeat = E && r.emax > 0.0;
-        for (int d = 0; d < 3; ++d) r.xi[d] = r.xe[d] = 0.0;
-        if (mx.imax > 0.0) {
-            const int64_t k = key_point(mx.ikey, iperm);
-            for (int d = 0; d < 3; ++d) r.xi[d] = xyz[3 * k + d];
+        if (!staged) {
+            mlp::stage_weights<true>(la.params, S.net);
+            staged = true;
         }
-        if (r.efeat) {
-            const int64_t k = key_point(mx.ekey, iperm);
-            for (int d = 0; d < 3; ++d) r.xe[d] = xyz[3 * k + d];
-        }
-        // statistics and features, a thread of wave 0 per candidate leaf
-        if (wv == 0 && lane < nrow) {
-            const int j = lane;
-            const int4 lp = la.leaf_pos[S.rowleaf[j]];
+        // statistics, a wave per row
+        for (int j = wv; j < nrow; j += nw) {
+            const int4 lp = S.rowpos[j];
             auto fetch = [&](int32_t k, double &v, double &e) {
                 if (k >= t0 && k < t1) {
                     v = (double)S.I[k - t0];
@@ -341,34 +338,56 @@ __device__ void learned_decisions(const T *__restrict__ I, const float *__restri
                     e = E ? (double)E[o] : 0.0;
                 }
             };
-            const mlp::LeafStats s = mlp::leaf_stats_seq(fetch, la.w, la.w_ref, lp.x, lp.y, sp.src_rel, r.imax);
-            const int4 g = la.pinfo2[lp.z];
+            const mlp::LeafStats st = mlp::leaf_stats_wave(fetch, la.w, la.w_ref, lp.x, lp.y, sp.src_rel, mx.imax, lane);
+            if (lane == 0) S.rowstat[j] = st;
+        }
+        __syncthreads();
+        // features, a lane per row
+        if ((int)threadIdx.x < nrow) {
+            const int j = threadIdx.x;
+            mlp::FeatureRefs r;
+            r.imax = mx.imax;
+            r.emax = mx.emax;
+            r.w_ref = la.w_ref;
+            r.lo[0] = la.lo0;
+            r.lo[1] = la.lo1;
+            r.lo[2] = la.lo2;
+            r.cube = la.cube;
+            r.efeat = E && r.emax > 0.0;
+            for (int d = 0; d < 3; ++d) r.xi[d] = r.xe[d] = 0.0;
+            if (mx.imax > 0.0) {
+                const int64_t k = key_point(mx.ikey, iperm);
+                for (int d = 0; d < 3; ++d) r.xi[d] = xyz[3 * k + d];
+            }
+            if (r.efeat) {
+                const int64_t k = key_point(mx.ekey, iperm);
+                for (int d = 0; d < 3; ++d) r.xe[d] = xyz[3 * k + d];
+            }
+            const mlp::LeafStats st = S.rowstat[j];
+            const int4 lp = S.rowpos[j], g = S.rowgeo[j];
             float fe[PH_MLP_NIN];
-            mlp::leaf_features(s, r, g.w, g.x, g.y, g.z, fe);
+            mlp::leaf_features(st, r, g.w, g.x, g.y, g.z, fe);
 #pragma unroll
             for (int q = 0; q < PH_MLP_NIN; ++q) S.rowf[j][q] = fe[q];
             if (lp.x >= t0) {
 #pragma unroll
                 for (int q = 0; q < PH_MLP_NIN; ++q) la.feats[(size_t)lp.z * PH_MLP_NIN + q] = fe[q];
                 la.leafflag[lp.z] = 1u;
-                la.featcnt[lp.z] = (int32_t)s.n_c;
+                la.featcnt[lp.z] = (int32_t)st.n_c;
                 if (la.count) {  // calls that report statistics: the rows and their candidates
-                    atomicAdd(&sc->n_src_base, (int32_t)s.n_c);
+                    atomicAdd(&sc->n_src_base, (int32_t)st.n_c);
                     atomicAdd(&sc->n_srcleaf, 1);
                 }
             }
         }
-        if (!staged) {
-            mlp::stage_weights<true>(la.params, S.net);
-            staged = true;
-        }
         __syncthreads();
-        for (int j = wv; j < nrow; j += kSelWaves) {
+        // the network, a wave per row
+        for (int j = wv; j < nrow; j += nw) {
             float fe[PH_MLP_NIN];
 #pragma unroll
             for (int q = 0; q < PH_MLP_NIN; ++q) fe[q] = S.rowf[j][q];
             const float z = mlp::mlp_row<true>(fe, S.net, lane);
-            const int4 lp = la.leaf_pos[S.rowleaf[j]];
+            const int4 lp = S.rowpos[j];
             const uint8_t st = !isfinite(z) ? 2 : (z >= la.threshold ? 0 : 1);
             if (st == 2 && lp.x >= t0 && lane == 0) atomicOr(&sc->fallback, 1);
             const int64_t a0 = max((int64_t)lp.x, t0), a1 = min((int64_t)lp.y, t1);
@@ -378,30 +397,43 @@ __device__ void learned_decisions(const T *__restrict__ I, const float *__restri
     }
 }
 
+// The learned variant runs the tile with half the waves (eight strips each): the network's
+// registers then leave room for two workgroups per CU, and the whole grid is resident at once.
+template <bool LEARNED>
+constexpr int sel_waves() { return LEARNED ? kSelWaves / 2 : kSelWaves; }
+
 template <class T, bool LEARNED>
-__global__ __launch_bounds__(64 * kSelWaves, LEARNED ? 4 : 8) void select_tiles_kernel(
+__global__ __launch_bounds__(64 * sel_waves<LEARNED>(), LEARNED ? 4 : 8) void select_tiles_kernel(
     const T *__restrict__ I, const float *__restrict__ E, const int32_t *__restrict__ perm, int64_t n,
     SelectParams sp, CallScalars *__restrict__ sc, const double *__restrict__ red, int red_nb, int32_t *sticky,
     const int32_t *__restrict__ iperm, const double *__restrict__ xyz, const uint8_t *__restrict__ tmask,
     uint8_t *__restrict__ sel, T *__restrict__ S_out, uint64_t *__restrict__ partial, LearnArgs la)
 {
-    __shared__ uint64_t wsum[kSelWaves];
+    constexpr int NW = sel_waves<LEARNED>(), NS = kSelTile / (64 * NW), SPAN = 64 * NS;
+    __shared__ uint64_t wsum[NW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile0 = (int64_t)blockIdx.x * kSelTile;
-    const int64_t base = tile0 + (int64_t)w * kSelSpan;
+    const int64_t base = tile0 + (int64_t)w * SPAN;
     // the tile's values first (they do not depend on the maxima), then the maxima from the partials
-    int32_t o[kSelStrips];
-    T v[kSelStrips];
-    float e[kSelStrips];
-    uint8_t tm[kSelStrips];
+    int32_t o[NS];
+    T v[NS];
+    float e[NS];
+    uint8_t tm[NS];
+    int2 lrange = make_int2(0, 0);
+    if constexpr (LEARNED) lrange = la.tile_leaves[blockIdx.x];
 #pragma unroll
-    for (int st = 0; st < kSelStrips; ++st) {
+    for (int st = 0; st < NS; ++st) {
         const int64_t k = base + st * 64 + lane;
         o[st] = k < n ? perm[k] : -1;
         tm[st] = (tmask && k < n) ? tmask[k] : 1;
     }
+    // the learned variant's first leaf records, in flight with the tile's values
+    int4 lpre = make_int4(0, 0, 0, 0);
+    if constexpr (LEARNED) {
+        if ((int)threadIdx.x < lrange.y - lrange.x) lpre = la.leaf_pos[lrange.x + threadIdx.x];
+    }
 #pragma unroll
-    for (int st = 0; st < kSelStrips; ++st) {
+    for (int st = 0; st < NS; ++st) {
         v[st] = o[st] >= 0 ? I[o[st]] : T(0);
         e[st] = (E && o[st] >= 0) ? E[o[st]] : 0.0f;
     }
@@ -410,7 +442,7 @@ __global__ __launch_bounds__(64 * kSelWaves, LEARNED ? 4 : 8) void select_tiles_
     uint64_t acc = 0;
     if constexpr (!LEARNED) {
 #pragma unroll
-        for (int st = 0; st < kSelStrips; ++st) {
+        for (int st = 0; st < NS; ++st) {
             const int64_t k = base + st * 64 + lane;
             if (k < n) {
                 const bool src = src_rule((double)v[st], sp.src_rel, imax);
@@ -423,22 +455,24 @@ __global__ __launch_bounds__(64 * kSelWaves, LEARNED ? 4 : 8) void select_tiles_
         }
     } else {
         __shared__ TileLds<T> S;
+        bool anyc = false;
         // stage the tile's values, one candidate word per strip
 #pragma unroll
-        for (int st = 0; st < kSelStrips; ++st) {
+        for (int st = 0; st < NS; ++st) {
             const int64_t k = base + st * 64 + lane;
             const int q = (int)(k - tile0);
             S.I[q] = v[st];
             S.E[q] = e[st];
             S.state[q] = 0;
             const uint64_t cw = __ballot(k < n && src_rule((double)v[st], sp.src_rel, imax));
-            if (lane == 0) S.cand[w * kSelStrips + st] = cw;
+            if (lane == 0) S.cand[w * NS + st] = cw;
+            anyc = anyc || cw != 0ull;
         }
-        __syncthreads();
-        learned_decisions(I, E, perm, n, sp, mx, iperm, xyz, la, sc, S);
+        const bool anycand = __syncthreads_or(anyc ? 1 : 0) != 0;
+        learned_decisions(I, E, perm, n, sp, mx, iperm, xyz, la, sc, S, lrange, lpre, anycand);
         // the points again from LDS (nothing of the staging loop stays live across the decisions)
 #pragma unroll
-        for (int st = 0; st < kSelStrips; ++st) {
+        for (int st = 0; st < NS; ++st) {
             const int64_t k = base + st * 64 + lane;
             if (k < n) {
                 const int q = (int)(k - tile0);
@@ -460,7 +494,7 @@ __global__ __launch_bounds__(64 * kSelWaves, LEARNED ? 4 : 8) void select_tiles_
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t t = 0;
-        for (int q = 0; q < kSelWaves; ++q) t += wsum[q];
+        for (int q = 0; q < NW; ++q) t += wsum[q];
         partial[blockIdx.x] = t;
     }
 }
@@ -630,7 +664,7 @@ static SelectParams params_of(const Plan &p, double src_rel)
 }
 
 void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, bool learned,
-                   double src_rel)
+                   double src_rel, hipEvent_t after_tiles)
 {
     if (p.n <= 0) return;
     const int64_t nb = (p.n + kSelTile - 1) / kSelTile;
@@ -654,7 +688,7 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
         la.featcnt = p.d_feat_cnt;
         la.count = p.count_work ? 1 : 0;
     }
-    const unsigned g = (unsigned)nb, bs = 64 * kSelWaves;
+    const unsigned g = (unsigned)nb, bs = 64 * (learned ? sel_waves<true>() : sel_waves<false>());
     const int rnb = reduce_blocks(p.n);
     if (p.precision == PH_FP64) {
         if (learned)
@@ -670,6 +704,7 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
             select_tiles_kernel<float, false><<<g, bs, 0, s>>>((const float *)I, E, p.d_perm, p.n, sp, p.d_sc, p.d_red, rnb, p.d_sticky, p.d_iperm, p.d_xyz, p.d_tmask,
                                                                p.d_sel, (float *)S_out, partial, la);
     }
+    if (after_tiles) PH_HIP(hipEventRecord(after_tiles, s));
     // up to 2048 tiles the compaction adds up the earlier tiles' sums itself; beyond, one
     // workgroup scans them first
     const int tile_sums = nb <= 2048 ? 1 : 0;

@@ -834,7 +834,7 @@ static void fetch_scalars(Plan &p, hipStream_t s)
 }
 
 // Phase boundaries recorded per call (events 0..9): 0 start, 1 maxima reduced,
-// 2 learned selector done, 3 selection and compaction done, 4 tree done, 5 lists done,
+// 2 selection flags (and learned decisions) done, 3 compaction done, 4 tree done, 5 lists done,
 // 6 upward done, 7 downward done, 8 far field at the targets done, 9 near field (or
 // direct sum) done.
 // Event k of a slot: 0..7 on the caller's stream (start, then the ends of reduce, selector,
@@ -880,8 +880,9 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     // the first kernel clears the call's scalars and advances the call number
     launch_reduce_max(p, I, Eu, p.d_gen, s);
     mark(1, s);
-    mark(2, s);  // the learned decisions are made inside the selection pass
-    launch_select(p, I, Eu, S_out, s, learned, threshold_run ? p.fallback_rel : -1.0);
+    // event 2 closes the tile pass (flags, and the learned decisions made inside it)
+    launch_select(p, I, Eu, S_out, s, learned, threshold_run ? p.fallback_rel : -1.0,
+                  timed ? p.ring[slot][2] : nullptr);
     mark(3, s);
     if (p.method == PH_METHOD_DIRECT) {
         for (int k = 4; k <= 7; ++k) mark(k, s);

@@ -361,7 +361,7 @@ void launch_maxima_store(const Plan &p, bool has_e, hipStream_t s);
 // in d_flag for the tree build) and the compaction.  src_rel >= 0 replaces the plan's source rule
 // for this pass (the threshold run of a validated call).
 void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, bool learned,
-                   double src_rel = -1.0);
+                   double src_rel, hipEvent_t after_tiles = nullptr);
 // validated learned call: S_out (learned) against S_ref (threshold rule); S_ref replaces S_out
 // and the call is marked fallen back when their relative L2 difference exceeds tol
 void launch_validate(const Plan &p, void *S_out, const void *S_ref, double tol, hipStream_t s);
