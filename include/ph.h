@@ -158,10 +158,13 @@ const char *ph_last_error(void);
 void ph_options_default(ph_options *opt);
 
 /*
- * Builds a plan over a fixed point set: validates every argument on the host
- * (no device call happens before validation passes), copies the points to the
- * device, computes 63-bit Morton keys and radix-sorts them, and precomputes
- * the per-level FMM operators in FP64 on the host.
+ * Builds a plan over a fixed point set for the discretised integral of Sec. 2.4 (eq. (15):
+ * weights w_j, the own-cell term on grids) and its fast multipole evaluation (eqs. (16)-(17):
+ * an octree whose near and far parts are summed directly and through equivalent densities):
+ * validates every argument on the host (no device call happens before validation passes),
+ * copies the points to the device, computes 63-bit Morton keys and radix-sorts them, builds
+ * the octree over all points, and precomputes the per-level FMM operators of the gas
+ * (Sec. 2.1, eq. (3)) in FP64 on the host.
  * Errors: PH_EINVAL (bad argument), PH_ENOMEM, PH_EDEVICE, PH_EUNSUPPORTED.
  * Synchronous.  *out is set only on success.
  */
@@ -225,6 +228,22 @@ ph_status ph_evaluate_ws(ph_plan *plan, const void *I, const float *absE, void *
  * call on the plan is still executing on another thread's stream.
  */
 ph_status ph_plan_set_targets(ph_plan *plan, const uint8_t *mask, int64_t n);
+
+/*
+ * Moves the plan to another gas (Sec. 2.1, eq. (3); the pressure study of Sec. 4.2): the
+ * constants a = chi_min p_O2, b = chi_max p_O2 and P, the own-cell coefficient (unless the
+ * plan was created with a fixed self_coeff) and every operator are rebuilt; the point order,
+ * the octree and the per-call buffers are kept.  The kernel depends on the pressure only
+ * through a r and b r, so the far-field operators of a box of half-width hw depend on a hw
+ * and b hw alone, up to powers of hw: the plan keeps every level it has built, and a level
+ * whose a hw and b hw it has seen before (for instance after halving or doubling the
+ * pressure, when level l takes the operators of level l +- 1) is rescaled from the cache
+ * instead of being built, bit for bit equal to a fresh build.  *levels_reused (nullable)
+ * receives how many levels came from the cache.  Results of later calls equal those of a
+ * plan created with this gas, bit for bit.  Waits for the device; must not run while a call
+ * on the plan is still executing.  Errors: PH_EINVAL (bad gas), PH_EDEVICE.
+ */
+ph_status ph_plan_set_gas(ph_plan *plan, const ph_gas *gas, int *levels_reused);
 
 /*
  * Graph replay of ph_evaluate: not available in this library.  enable = 0 returns

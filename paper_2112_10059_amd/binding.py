@@ -70,7 +70,7 @@ EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
             "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_fields",
             "ph_plan_set_graph", "ph_mlp_backward_noalloc", "ph_evaluate_workspace_bytes", "ph_evaluate_ws",
-            "ph_plan_set_targets"]
+            "ph_plan_set_targets", "ph_plan_set_gas"]
 
 _lib = None
 
@@ -115,6 +115,8 @@ def load(path: Optional[str] = None):
     lib.ph_evaluate_ws.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(PhStats)]
     lib.ph_plan_set_targets.restype = ctypes.c_int
     lib.ph_plan_set_targets.argtypes = [vp, vp, ctypes.c_int64]
+    lib.ph_plan_set_gas.restype = ctypes.c_int
+    lib.ph_plan_set_gas.argtypes = [vp, ctypes.POINTER(PhGas), ctypes.POINTER(ctypes.c_int)]
     lib.ph_plan_set_graph.restype = ctypes.c_int
     lib.ph_plan_set_graph.argtypes = [vp, ctypes.c_int]
     lib.ph_plan_check.restype = ctypes.c_int
@@ -259,6 +261,14 @@ class Plan:
             return
         self._tmask = np.ascontiguousarray(np.asarray(mask, dtype=bool).astype(np.uint8).ravel())
         _check(_lib.ph_plan_set_targets(self._h, self._tmask.ctypes.data_as(ctypes.c_void_p), self._tmask.size))
+
+    def set_gas(self, gas: dict) -> int:
+        """Moves the plan to another gas (same points and tree); returns the number of far-field
+        levels taken from the plan's operator cache."""
+        g = make_gas(gas)
+        n = ctypes.c_int(0)
+        _check(_lib.ph_plan_set_gas(self._h, ctypes.byref(g), ctypes.byref(n)))
+        return n.value
 
     def set_graph(self, enable: bool = True):
         """Later evaluate() calls without stats run as one replayed HIP graph (per set of buffers)."""

@@ -21,8 +21,17 @@ thread_local std::string g_last_error;
 template <class T>
 void upload(Plan &p, void **dst, const std::vector<T> &src)
 {
-    *dst = dev_alloc(p, src.size() * sizeof(T));
-    PH_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    const size_t bytes = src.size() * sizeof(T);
+    if (*dst) {  // a rebuild for a new gas: same operator, same size
+        auto it = p.upload_bytes.find(dst);
+        if (it == p.upload_bytes.end() || it->second != bytes)
+            throw Error{PH_EDEVICE, "internal: rebuilt operator changed size"};
+        PH_HIP(hipMemcpy(*dst, src.data(), bytes, hipMemcpyHostToDevice));
+        return;
+    }
+    *dst = dev_alloc(p, bytes);
+    p.upload_bytes[dst] = bytes;
+    PH_HIP(hipMemcpy(*dst, src.data(), bytes, hipMemcpyHostToDevice));
 }
 
 // f(i) for i in [0, n) over up to 16 host threads
@@ -80,6 +89,21 @@ void split_bf16(const std::vector<double> &v, std::vector<uint16_t> &hi, std::ve
     }
 }
 
+// The gas parameters (Sec. 2.1, eq. (3)): positive pressures and 0 < chi_min < chi_max
+void validate_gas(const ph_gas *gas)
+{
+    auto bad = [](const char *m) { throw Error{PH_EINVAL, m}; };
+    auto finite = [](double v) { return std::isfinite(v); };
+    if (!gas) bad("gas is null");
+    if (!(gas->p_torr > 0) || !finite(gas->p_torr)) bad("gas.p_torr must be > 0");
+    if (!(gas->o2_fraction > 0) || !(gas->o2_fraction <= 1)) bad("gas.o2_fraction must be in (0, 1]");
+    if (!(gas->pq_torr >= 0) || !finite(gas->pq_torr)) bad("gas.pq_torr must be >= 0");
+    if (!(gas->xi_omega_over_alpha >= 0) || !finite(gas->xi_omega_over_alpha))
+        bad("gas.xi_omega_over_alpha must be >= 0");
+    if (!(gas->chi_min > 0) || !(gas->chi_max > gas->chi_min) || !finite(gas->chi_max))
+        bad("gas needs 0 < chi_min < chi_max");
+}
+
 // Validation happens entirely on the host, before any device call.
 void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr, const ph_options *opt)
 {
@@ -114,13 +138,7 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
     } else if (!finite(pts->cube_size)) {
         bad("points.cube_size must be finite");
     }
-    if (!(gas->p_torr > 0) || !finite(gas->p_torr)) bad("gas.p_torr must be > 0");
-    if (!(gas->o2_fraction > 0) || !(gas->o2_fraction <= 1)) bad("gas.o2_fraction must be in (0, 1]");
-    if (!(gas->pq_torr >= 0) || !finite(gas->pq_torr)) bad("gas.pq_torr must be >= 0");
-    if (!(gas->xi_omega_over_alpha >= 0) || !finite(gas->xi_omega_over_alpha))
-        bad("gas.xi_omega_over_alpha must be >= 0");
-    if (!(gas->chi_min > 0) || !(gas->chi_max > gas->chi_min) || !finite(gas->chi_max))
-        bad("gas needs 0 < chi_min < chi_max");
+    validate_gas(gas);
     if (!finite(thr->src_rel) || thr->src_rel < 0 || thr->src_rel > 1) bad("thresholds.src_rel must be in [0, 1]");
     if (!finite(thr->e_abs)) bad("thresholds.e_abs must be finite");
     if (!finite(thr->e_rel) || thr->e_rel > 1) bad("thresholds.e_rel must be <= 1 (negative = off)");
@@ -321,235 +339,26 @@ void dev_free(void *ptr)
     if (ptr) (void)hipFree(ptr);
 }
 
-static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
-                        const ph_options *opt)
+// Everything that depends on the gas (Sec. 2.1, eqs. (1)-(3)): the constants a, b, L and P,
+// the own-cell coefficient, and the far-field operators with the grid operators and the near
+// table.  Called at plan creation and again for each new gas of ph_plan_set_gas; operator
+// buffers keep their sizes (the tree and the order are fixed by the plan), so a rebuild
+// copies into them.  Levels whose a hw and b hw were built before come from the plan's cache.
+static void build_gas_state(Plan &p, const ph_gas *gas)
 {
-    p.n = pts->n;
-    PH_HIP(hipGetDevice(&p.device));
-    p.precision = opt->precision;
-    p.method = opt->method;
-    p.selector = opt->selector;
-    p.q = opt->order_q ? opt->order_q : (p.precision == PH_FP64 ? 6 : 4);
-    p.leaf_cap = opt->leaf_capacity ? opt->leaf_capacity : 64;
-    p.pinv_cut = opt->pinv_rel_cutoff > 0 ? opt->pinv_rel_cutoff : (p.precision == PH_FP64 ? 1e-15 : 1e-7);
-    p.thr = *thr;
-    p.workspace_cap = opt->workspace_cap_bytes;
-    p.h = pts->h;
     const double pO2 = gas->o2_fraction * gas->p_torr;
     p.gas.a = gas->chi_min * pO2;
     p.gas.b = gas->chi_max * pO2;
     p.gas.L = std::log(gas->chi_max / gas->chi_min);
     p.gas.P = gas->pq_torr / (gas->p_torr + gas->pq_torr) * gas->xi_omega_over_alpha;
-    p.c_self = std::isnan(pts->self_coeff) ? cube_self_integral(p.gas, pts->h) : pts->self_coeff;
-    p.uniform_w = pts->w == nullptr;
-    p.w_uniform = p.uniform_w ? pts->h * pts->h * pts->h : 0.0;
-    if (opt->selector == PH_SEL_LEARNED) {
-        p.validate = opt->validate != 0;
-        p.validate_tol = opt->tol > 0 ? opt->tol : (opt->tol == 0 && opt->validate ? 0.0 : 1e-3);
-        p.sel_weights.assign(opt->selector_weights, opt->selector_weights + PH_MLP_NPARAM);
-        p.sel_threshold = opt->selector_logit_threshold;
-        p.fallback_rel = opt->selector_fallback_rel > 0 ? opt->selector_fallback_rel : 1e-4;
-    }
-    // root cube
-    if (pts->cube_size > 0) {
-        for (int d = 0; d < 3; ++d) p.cube_lo[d] = pts->cube_lo[d];
-        p.cube_size = pts->cube_size;
-    } else {
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (int64_t i = 0; i < p.n; ++i)
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = std::min(lo[d], pts->xyz[3 * i + d]);
-                hi[d] = std::max(hi[d], pts->xyz[3 * i + d]);
-            }
-        double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
-        if (!(ext > 0)) ext = 1.0;
-        ext *= 1.0 + 1e-9;
-        for (int d = 0; d < 3; ++d) p.cube_lo[d] = lo[d] - 1e-12 * ext;
-        p.cube_size = ext * (1.0 + 2e-12);
-    }
-    // points to the device, keys, sort
-    const int64_t n = p.n;
-    double *d_xyz_in = (double *)dev_alloc(p, (size_t)n * 3 * 8);
-    double *d_w_in = nullptr;
-    PH_HIP(hipMemcpy(d_xyz_in, pts->xyz, (size_t)n * 3 * 8, hipMemcpyHostToDevice));
-    if (pts->w) {
-        d_w_in = (double *)dev_alloc(p, (size_t)n * 8);
-        PH_HIP(hipMemcpy(d_w_in, pts->w, (size_t)n * 8, hipMemcpyHostToDevice));
-    }
-    p.d_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
-    p.d_perm = (int32_t *)dev_alloc(p, (size_t)n * 4);
-    uint64_t *ktmp = (uint64_t *)dev_alloc(p, (size_t)n * 8);
-    int32_t *vtmp = (int32_t *)dev_alloc(p, (size_t)n * 4);
-    size_t hb = radix_sort_tmp_bytes(n);
-    uint32_t *htmp = (uint32_t *)dev_alloc(p, hb);
-    hipStream_t s = nullptr;
-    launch_morton_keys(d_xyz_in, n, p.cube_lo[0], p.cube_lo[1], p.cube_lo[2], p.cube_size, p.d_key, p.d_perm, s);
-    radix_sort_pairs(p.d_key, p.d_perm, ktmp, vtmp, n, htmp, hb, 3 * kMortonBits, s);
-    p.d_xyz = (double *)dev_alloc(p, (size_t)n * 3 * 8);
-    p.d_iperm = (int32_t *)dev_alloc(p, (size_t)n * 4);
-    if (d_w_in) p.d_w = (double *)dev_alloc(p, (size_t)n * 8);
-    launch_gather_sorted(d_xyz_in, d_w_in, p.d_perm, n, p.d_xyz, p.d_w, p.d_iperm, s);
-    if (p.precision != PH_FP64) {
-        p.d_xyzf = (float4 *)dev_alloc(p, (size_t)n * sizeof(float4));
-        launch_pack_xyzf(p.d_xyz, n, p.d_xyzf, s);
-    }
-    PH_HIP(hipStreamSynchronize(s));
-    dev_free(ktmp);
-    dev_free(vtmp);
-    dev_free(htmp);
-    dev_free(d_xyz_in);
-    dev_free(d_w_in);
-    p.bytes_allocated -= (size_t)n * 8 + (size_t)n * 4 + hb + (size_t)n * 24 + (d_w_in ? (size_t)n * 8 : 0);
-    // uniform grid aligned with the root cube: every point at a cell centre
-    if (!pts->w && pts->h > 0) {
-        const double Nf = p.cube_size / pts->h;
-        const long N = std::lround(Nf);
-        bool ok = N >= 1 && N <= 1024 && std::fabs(Nf - (double)N) < 1e-9 * (double)N;
-        std::vector<int32_t> cell(ok ? n : 0);
-        for (int64_t i = 0; ok && i < n; ++i) {
-            int32_t c = 0;
-            for (int d = 0; d < 3; ++d) {
-                const double f = (pts->xyz[3 * i + d] - p.cube_lo[d]) / pts->h - 0.5;
-                const long ci = std::lround(f);
-                if (std::fabs(f - (double)ci) > 1e-6 || ci < 0 || ci >= N) {
-                    ok = false;
-                    break;
-                }
-                c |= (int32_t)ci << (10 * d);
-            }
-            if (ok) cell[i] = c;
-        }
-        if (ok) {
-            std::vector<int32_t> perm(n), sorted(n);
-            PH_HIP(hipMemcpy(perm.data(), p.d_perm, (size_t)n * 4, hipMemcpyDeviceToHost));
-            for (int64_t k = 0; k < n; ++k) sorted[k] = cell[perm[k]];
-            p.d_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
-            PH_HIP(hipMemcpy(p.d_cell, sorted.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-            p.grid_mode = true;
-            p.grid_n = (int)N;
-        }
-    }
+    if (!p.self_coeff_given) p.c_self = cube_self_integral(p.gas, p.h);
     // on a grid the closest distinct pair is h apart: the guarded form is needed only if (b - a) h < 1/4
     p.near_guard = !(p.grid_mode && (p.gas.b - p.gas.a) * p.h >= 0.25);
-    // default order from measured error: the FP64 form reaches 1e-7 at q = 6 on uniform grids
-    // but needs q = 7 on clustered point clouds (1.0e-6 at q = 6, 2.6e-7 at q = 7)
-    if (!opt->order_q && p.precision == PH_FP64 && !p.grid_mode) p.q = 7;
-    // FP32 forms: the pseudo-inverses are regularised so that FP32 rounding is not amplified by
-    // their conditioning; on clustered clouds (boxes over many absorption lengths, and at low
-    // pressure few) 1e-4 sigma_max keeps the error near 1e-4 at 40 and 760 Torr, where 1e-7
-    // reaches 1.5e-3 at 40 Torr; uniform grids at 760 Torr are best at 1e-7 (5e-5)
-    if (opt->pinv_rel_cutoff <= 0 && p.precision != PH_FP64 && !p.grid_mode) p.pinv_cut = 1e-4;
-    // tree bound from the tree over all points
-    std::vector<uint64_t> hkeys(n);
-    PH_HIP(hipMemcpy(hkeys.data(), p.d_key, (size_t)n * 8, hipMemcpyDeviceToHost));
-    int depth_limit = opt->max_depth ? opt->max_depth : kMaxDepth;
-    FullTree FT;
-    build_full_tree(hkeys, p.leaf_cap, depth_limit, FT);
-    p.level_cap = FT.level_cap;
-    p.max_depth = (int)p.level_cap.size() - 1;
-    {
-        // the tree structure is fixed for the plan: upload it once
-        BoxArrays &bx = p.box;
-        auto up = [&](int32_t **dst, const std::vector<int32_t> &v) {
-            *dst = (int32_t *)dev_alloc(p, v.size() * 4);
-            PH_HIP(hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice));
-        };
-        up(&bx.level, FT.level);
-        up(&bx.ax, FT.ax);
-        up(&bx.ay, FT.ay);
-        up(&bx.az, FT.az);
-        up(&bx.start, FT.start);
-        up(&bx.end, FT.end);
-        // the points where the tree build reads the selection scan: box starts and ends
-        std::vector<uint8_t> bnd((size_t)n, 0);
-        for (size_t f = 0; f < FT.start.size(); ++f) {
-            if (FT.start[f] < n) bnd[FT.start[f]] = 1;
-            if (FT.end[f] < n) bnd[FT.end[f]] = 1;
-        }
-        p.d_bnd = (uint8_t *)dev_alloc(p, (size_t)n);
-        PH_HIP(hipMemcpy(p.d_bnd, bnd.data(), (size_t)n, hipMemcpyHostToDevice));
-        up(&bx.parent, FT.parent);
-        up(&bx.child, FT.child);
-        up(&bx.coll, FT.coll);
-        // leaves of the full tree (no child), in box order: the rows of the learned selector
-        std::vector<int32_t> leaves;
-        for (size_t f = 0; f < FT.level.size(); ++f) {
-            bool leaf = true;
-            for (int o = 0; o < 8 && leaf; ++o) leaf = FT.child[f * 8 + o] < 0;
-            if (leaf) leaves.push_back((int32_t)f);
-        }
-        p.n_pleaf = (int32_t)leaves.size();
-        up(&p.d_pleaf, leaves);
-        // the selector's per-leaf look-ups in one record each (no chains of dependent loads)
-        {
-            std::vector<int4> info(leaves.size()), info2(leaves.size());
-            for (size_t i = 0; i < leaves.size(); ++i) {
-                const int32_t f = leaves[i];
-                info[i] = make_int4(f, FT.start[f], FT.end[f], 0);
-                info2[i] = make_int4(FT.ax[f], FT.ay[f], FT.az[f], FT.level[f]);
-            }
-            upload(p, reinterpret_cast<void **>(&p.d_pinfo), info);
-            upload(p, reinterpret_cast<void **>(&p.d_pinfo2), info2);
-        }
-        // the plan leaves by first point, and per selection tile the range of them overlapping it
-        {
-            std::vector<int32_t> order(leaves.size());
-            for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-            std::sort(order.begin(), order.end(),
-                      [&](int32_t a, int32_t b) { return FT.start[leaves[a]] < FT.start[leaves[b]]; });
-            std::vector<int4> pos(order.size());
-            for (size_t j = 0; j < order.size(); ++j) {
-                const int32_t f = leaves[order[j]];
-                pos[j] = make_int4(FT.start[f], FT.end[f], order[j], 0);
-            }
-            const int64_t ntile = (n + kSelTilePoints - 1) / kSelTilePoints;
-            std::vector<int2> tl((size_t)std::max<int64_t>(ntile, 1), make_int2(0, 0));
-            size_t j = 0;
-            for (int64_t tI = 0; tI < ntile; ++tI) {
-                const int64_t t0 = tI * kSelTilePoints, t1 = std::min<int64_t>(n, t0 + kSelTilePoints);
-                while (j < pos.size() && pos[j].y <= t0) ++j;  // leaves ending before the tile
-                size_t e = j;
-                while (e < pos.size() && pos[e].x < t1) ++e;
-                tl[(size_t)tI] = make_int2((int32_t)j, (int32_t)e);
-            }
-            upload(p, reinterpret_cast<void **>(&p.d_leaf_pos), pos);
-            upload(p, reinterpret_cast<void **>(&p.d_tile_leaves), tl);
-        }
-        p.h_pleaf = std::move(leaves);
-        // boxes by level and coordinates, for the composite translations
-        const int D = (int)FT.level_cap.size() - 1;
-        if (D >= 3 && D <= kCompMaxDepth) {
-            std::vector<int32_t> map;
-            for (int l = 0; l <= D; ++l) {
-                p.boxmap_off[l] = (int64_t)map.size();
-                if (l < 2) continue;
-                const int64_t nside = (int64_t)1 << l;
-                map.resize(map.size() + (size_t)(nside * nside * nside), -1);
-            }
-            for (size_t f = 0; f < FT.level.size(); ++f) {
-                const int l = FT.level[f];
-                if (l < 2) continue;
-                const int64_t nside = (int64_t)1 << l;
-                map[(size_t)(p.boxmap_off[l] + ((int64_t)FT.ax[f] * nside + FT.ay[f]) * nside + FT.az[f])] = (int32_t)f;
-            }
-            up(&p.d_boxmap, map);
-        }
-    }
-    p.level_base.assign(p.level_cap.size() + 1, 0);
-    for (size_t l = 0; l < p.level_cap.size(); ++l) p.level_base[l + 1] = p.level_base[l] + p.level_cap[l];
-    p.box_cap = p.level_base.back();
-    p.hw.resize(p.max_depth + 1);
-    for (int l = 0; l <= p.max_depth; ++l) p.hw[l] = p.cube_size / std::ldexp(1.0, l + 1);
-    // far-field operators
-    for (int t = 0; t < kNumM2L; ++t) {  // the device offset->slot map must match the host table
-        int dx, dy, dz;
-        m2l_offset(t, dx, dy, dz);
-        if (m2l_slot(dx, dy, dz) != t || m2l_index(dx, dy, dz) != t)
-            throw Error{PH_EDEVICE, "internal: translation slot table mismatch"};
-    }
+    p.levels_reused = 0;
     if (p.method == PH_METHOD_FMM) {
         HostOperators H;
-        build_operators(p.gas, p.q, p.cube_size, std::max(p.max_depth, 2), p.pinv_cut, H);
+        build_operators(p.gas, p.q, p.cube_size, std::max(p.max_depth, 2), p.pinv_cut, H, &p.op_cache,
+                        &p.levels_reused);
         p.n_lam = H.n_lam;
         p.n_sig = H.n_sig;
         const int nl = p.n_lam, ns = p.n_sig, L = p.max_depth + 1;
@@ -738,6 +547,229 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
             }
         }
     }
+}
+
+static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
+                        const ph_options *opt)
+{
+    p.n = pts->n;
+    PH_HIP(hipGetDevice(&p.device));
+    p.precision = opt->precision;
+    p.method = opt->method;
+    p.selector = opt->selector;
+    p.q = opt->order_q ? opt->order_q : (p.precision == PH_FP64 ? 6 : 4);
+    p.leaf_cap = opt->leaf_capacity ? opt->leaf_capacity : 64;
+    p.pinv_cut = opt->pinv_rel_cutoff > 0 ? opt->pinv_rel_cutoff : (p.precision == PH_FP64 ? 1e-15 : 1e-7);
+    p.thr = *thr;
+    p.workspace_cap = opt->workspace_cap_bytes;
+    p.h = pts->h;
+    p.self_coeff_given = !std::isnan(pts->self_coeff);
+    p.c_self = pts->self_coeff;
+    p.uniform_w = pts->w == nullptr;
+    p.w_uniform = p.uniform_w ? pts->h * pts->h * pts->h : 0.0;
+    if (opt->selector == PH_SEL_LEARNED) {
+        p.validate = opt->validate != 0;
+        p.validate_tol = opt->tol > 0 ? opt->tol : (opt->tol == 0 && opt->validate ? 0.0 : 1e-3);
+        p.sel_weights.assign(opt->selector_weights, opt->selector_weights + PH_MLP_NPARAM);
+        p.sel_threshold = opt->selector_logit_threshold;
+        p.fallback_rel = opt->selector_fallback_rel > 0 ? opt->selector_fallback_rel : 1e-4;
+    }
+    // root cube
+    if (pts->cube_size > 0) {
+        for (int d = 0; d < 3; ++d) p.cube_lo[d] = pts->cube_lo[d];
+        p.cube_size = pts->cube_size;
+    } else {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t i = 0; i < p.n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], pts->xyz[3 * i + d]);
+                hi[d] = std::max(hi[d], pts->xyz[3 * i + d]);
+            }
+        double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
+        if (!(ext > 0)) ext = 1.0;
+        ext *= 1.0 + 1e-9;
+        for (int d = 0; d < 3; ++d) p.cube_lo[d] = lo[d] - 1e-12 * ext;
+        p.cube_size = ext * (1.0 + 2e-12);
+    }
+    // points to the device, keys, sort
+    const int64_t n = p.n;
+    double *d_xyz_in = (double *)dev_alloc(p, (size_t)n * 3 * 8);
+    double *d_w_in = nullptr;
+    PH_HIP(hipMemcpy(d_xyz_in, pts->xyz, (size_t)n * 3 * 8, hipMemcpyHostToDevice));
+    if (pts->w) {
+        d_w_in = (double *)dev_alloc(p, (size_t)n * 8);
+        PH_HIP(hipMemcpy(d_w_in, pts->w, (size_t)n * 8, hipMemcpyHostToDevice));
+    }
+    p.d_key = (uint64_t *)dev_alloc(p, (size_t)n * 8);
+    p.d_perm = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    uint64_t *ktmp = (uint64_t *)dev_alloc(p, (size_t)n * 8);
+    int32_t *vtmp = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    size_t hb = radix_sort_tmp_bytes(n);
+    uint32_t *htmp = (uint32_t *)dev_alloc(p, hb);
+    hipStream_t s = nullptr;
+    launch_morton_keys(d_xyz_in, n, p.cube_lo[0], p.cube_lo[1], p.cube_lo[2], p.cube_size, p.d_key, p.d_perm, s);
+    radix_sort_pairs(p.d_key, p.d_perm, ktmp, vtmp, n, htmp, hb, 3 * kMortonBits, s);
+    p.d_xyz = (double *)dev_alloc(p, (size_t)n * 3 * 8);
+    p.d_iperm = (int32_t *)dev_alloc(p, (size_t)n * 4);
+    if (d_w_in) p.d_w = (double *)dev_alloc(p, (size_t)n * 8);
+    launch_gather_sorted(d_xyz_in, d_w_in, p.d_perm, n, p.d_xyz, p.d_w, p.d_iperm, s);
+    if (p.precision != PH_FP64) {
+        p.d_xyzf = (float4 *)dev_alloc(p, (size_t)n * sizeof(float4));
+        launch_pack_xyzf(p.d_xyz, n, p.d_xyzf, s);
+    }
+    PH_HIP(hipStreamSynchronize(s));
+    dev_free(ktmp);
+    dev_free(vtmp);
+    dev_free(htmp);
+    dev_free(d_xyz_in);
+    dev_free(d_w_in);
+    p.bytes_allocated -= (size_t)n * 8 + (size_t)n * 4 + hb + (size_t)n * 24 + (d_w_in ? (size_t)n * 8 : 0);
+    // uniform grid aligned with the root cube: every point at a cell centre
+    if (!pts->w && pts->h > 0) {
+        const double Nf = p.cube_size / pts->h;
+        const long N = std::lround(Nf);
+        bool ok = N >= 1 && N <= 1024 && std::fabs(Nf - (double)N) < 1e-9 * (double)N;
+        std::vector<int32_t> cell(ok ? n : 0);
+        for (int64_t i = 0; ok && i < n; ++i) {
+            int32_t c = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double f = (pts->xyz[3 * i + d] - p.cube_lo[d]) / pts->h - 0.5;
+                const long ci = std::lround(f);
+                if (std::fabs(f - (double)ci) > 1e-6 || ci < 0 || ci >= N) {
+                    ok = false;
+                    break;
+                }
+                c |= (int32_t)ci << (10 * d);
+            }
+            if (ok) cell[i] = c;
+        }
+        if (ok) {
+            std::vector<int32_t> perm(n), sorted(n);
+            PH_HIP(hipMemcpy(perm.data(), p.d_perm, (size_t)n * 4, hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < n; ++k) sorted[k] = cell[perm[k]];
+            p.d_cell = (int32_t *)dev_alloc(p, (size_t)n * 4);
+            PH_HIP(hipMemcpy(p.d_cell, sorted.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+            p.grid_mode = true;
+            p.grid_n = (int)N;
+        }
+    }
+    // default order from measured error: the FP64 form reaches 1e-7 at q = 6 on uniform grids
+    // but needs q = 7 on clustered point clouds (1.0e-6 at q = 6, 2.6e-7 at q = 7)
+    if (!opt->order_q && p.precision == PH_FP64 && !p.grid_mode) p.q = 7;
+    // FP32 forms: the pseudo-inverses are regularised so that FP32 rounding is not amplified by
+    // their conditioning; on clustered clouds (boxes over many absorption lengths, and at low
+    // pressure few) 1e-4 sigma_max keeps the error near 1e-4 at 40 and 760 Torr, where 1e-7
+    // reaches 1.5e-3 at 40 Torr; uniform grids at 760 Torr are best at 1e-7 (5e-5)
+    if (opt->pinv_rel_cutoff <= 0 && p.precision != PH_FP64 && !p.grid_mode) p.pinv_cut = 1e-4;
+    // tree bound from the tree over all points
+    std::vector<uint64_t> hkeys(n);
+    PH_HIP(hipMemcpy(hkeys.data(), p.d_key, (size_t)n * 8, hipMemcpyDeviceToHost));
+    int depth_limit = opt->max_depth ? opt->max_depth : kMaxDepth;
+    FullTree FT;
+    build_full_tree(hkeys, p.leaf_cap, depth_limit, FT);
+    p.level_cap = FT.level_cap;
+    p.max_depth = (int)p.level_cap.size() - 1;
+    {
+        // the tree structure is fixed for the plan: upload it once
+        BoxArrays &bx = p.box;
+        auto up = [&](int32_t **dst, const std::vector<int32_t> &v) {
+            *dst = (int32_t *)dev_alloc(p, v.size() * 4);
+            PH_HIP(hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+        };
+        up(&bx.level, FT.level);
+        up(&bx.ax, FT.ax);
+        up(&bx.ay, FT.ay);
+        up(&bx.az, FT.az);
+        up(&bx.start, FT.start);
+        up(&bx.end, FT.end);
+        // the points where the tree build reads the selection scan: box starts and ends
+        std::vector<uint8_t> bnd((size_t)n, 0);
+        for (size_t f = 0; f < FT.start.size(); ++f) {
+            if (FT.start[f] < n) bnd[FT.start[f]] = 1;
+            if (FT.end[f] < n) bnd[FT.end[f]] = 1;
+        }
+        p.d_bnd = (uint8_t *)dev_alloc(p, (size_t)n);
+        PH_HIP(hipMemcpy(p.d_bnd, bnd.data(), (size_t)n, hipMemcpyHostToDevice));
+        up(&bx.parent, FT.parent);
+        up(&bx.child, FT.child);
+        up(&bx.coll, FT.coll);
+        // leaves of the full tree (no child), in box order: the rows of the learned selector
+        std::vector<int32_t> leaves;
+        for (size_t f = 0; f < FT.level.size(); ++f) {
+            bool leaf = true;
+            for (int o = 0; o < 8 && leaf; ++o) leaf = FT.child[f * 8 + o] < 0;
+            if (leaf) leaves.push_back((int32_t)f);
+        }
+        p.n_pleaf = (int32_t)leaves.size();
+        up(&p.d_pleaf, leaves);
+        // the selector's per-leaf look-ups in one record each (no chains of dependent loads)
+        {
+            std::vector<int4> info(leaves.size()), info2(leaves.size());
+            for (size_t i = 0; i < leaves.size(); ++i) {
+                const int32_t f = leaves[i];
+                info[i] = make_int4(f, FT.start[f], FT.end[f], 0);
+                info2[i] = make_int4(FT.ax[f], FT.ay[f], FT.az[f], FT.level[f]);
+            }
+            upload(p, reinterpret_cast<void **>(&p.d_pinfo), info);
+            upload(p, reinterpret_cast<void **>(&p.d_pinfo2), info2);
+        }
+        // the plan leaves by first point, and per selection tile the range of them overlapping it
+        {
+            std::vector<int32_t> order(leaves.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+            std::sort(order.begin(), order.end(),
+                      [&](int32_t a, int32_t b) { return FT.start[leaves[a]] < FT.start[leaves[b]]; });
+            std::vector<int4> pos(order.size());
+            for (size_t j = 0; j < order.size(); ++j) {
+                const int32_t f = leaves[order[j]];
+                pos[j] = make_int4(FT.start[f], FT.end[f], order[j], 0);
+            }
+            const int64_t ntile = (n + kSelTilePoints - 1) / kSelTilePoints;
+            std::vector<int2> tl((size_t)std::max<int64_t>(ntile, 1), make_int2(0, 0));
+            size_t j = 0;
+            for (int64_t tI = 0; tI < ntile; ++tI) {
+                const int64_t t0 = tI * kSelTilePoints, t1 = std::min<int64_t>(n, t0 + kSelTilePoints);
+                while (j < pos.size() && pos[j].y <= t0) ++j;  // leaves ending before the tile
+                size_t e = j;
+                while (e < pos.size() && pos[e].x < t1) ++e;
+                tl[(size_t)tI] = make_int2((int32_t)j, (int32_t)e);
+            }
+            upload(p, reinterpret_cast<void **>(&p.d_leaf_pos), pos);
+            upload(p, reinterpret_cast<void **>(&p.d_tile_leaves), tl);
+        }
+        p.h_pleaf = std::move(leaves);
+        // boxes by level and coordinates, for the composite translations
+        const int D = (int)FT.level_cap.size() - 1;
+        if (D >= 3 && D <= kCompMaxDepth) {
+            std::vector<int32_t> map;
+            for (int l = 0; l <= D; ++l) {
+                p.boxmap_off[l] = (int64_t)map.size();
+                if (l < 2) continue;
+                const int64_t nside = (int64_t)1 << l;
+                map.resize(map.size() + (size_t)(nside * nside * nside), -1);
+            }
+            for (size_t f = 0; f < FT.level.size(); ++f) {
+                const int l = FT.level[f];
+                if (l < 2) continue;
+                const int64_t nside = (int64_t)1 << l;
+                map[(size_t)(p.boxmap_off[l] + ((int64_t)FT.ax[f] * nside + FT.ay[f]) * nside + FT.az[f])] = (int32_t)f;
+            }
+            up(&p.d_boxmap, map);
+        }
+    }
+    p.level_base.assign(p.level_cap.size() + 1, 0);
+    for (size_t l = 0; l < p.level_cap.size(); ++l) p.level_base[l + 1] = p.level_base[l] + p.level_cap[l];
+    p.box_cap = p.level_base.back();
+    p.hw.resize(p.max_depth + 1);
+    for (int l = 0; l <= p.max_depth; ++l) p.hw[l] = p.cube_size / std::ldexp(1.0, l + 1);
+    // far-field operators
+    for (int t = 0; t < kNumM2L; ++t) {  // the device offset->slot map must match the host table
+        int dx, dy, dz;
+        m2l_offset(t, dx, dy, dz);
+        if (m2l_slot(dx, dy, dz) != t || m2l_index(dx, dy, dz) != t)
+            throw Error{PH_EDEVICE, "internal: translation slot table mismatch"};
+    }
+    build_gas_state(p, gas);
     alloc_workspace(p);
     // timing-only events: no system-scope fence, so a mark does not write back L2 (that
     // write-back would otherwise be charged to the next phase)
@@ -1053,6 +1085,25 @@ ph_status ph_plan_set_targets(ph_plan *plan, const uint8_t *mask, int64_t n)
         for (int64_t k = 0; k < p.n; ++k) sorted[k] = mask[perm[k]] ? 1 : 0;
         if (!p.d_tmask) p.d_tmask = (uint8_t *)dev_alloc(p, (size_t)p.n);
         PH_HIP(hipMemcpy(p.d_tmask, sorted.data(), (size_t)p.n, hipMemcpyHostToDevice));
+        return PH_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+ph_status ph_plan_set_gas(ph_plan *plan, const ph_gas *gas, int *levels_reused)
+{
+    g_last_error.clear();
+    if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    try {
+        validate_gas(gas);
+        std::lock_guard<std::mutex> lock(p.mu);
+        PH_HIP(hipSetDevice(p.device));
+        PH_HIP(hipDeviceSynchronize());  // no call still reads the old operators
+        build_gas_state(p, gas);
+        PH_HIP(hipDeviceSynchronize());
+        if (levels_reused) *levels_reused = p.levels_reused;
         return PH_OK;
     } catch (const Error &e) {
         return fail(e);

@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <mutex>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ph.h"
@@ -164,8 +166,31 @@ constexpr int kNearTabMax = 4800;   // entries kept in LDS
 
 constexpr int kGridMaxCells = 16;  // lattice operators for boxes of at most 16^3 cells
 
+// Far-field operators of one level in the units of the level at which they were built.  The
+// kernel depends on the pressure only through a r and b r (eq. (3)), so two levels with equal
+// a hw and b hw (hw the half-width; for instance level l at pressure 2p and level l - 1 at p)
+// have operators that differ by powers of hw only: with f = hw_built / hw (a power of two),
+// K and the M2L operators scale by f^3, the check-to-equivalent maps by f^-3, and M2M is
+// unchanged.  Scaling by a power of two is exact, so a rescaled level equals a fresh build bit
+// for bit.
+struct CachedLevel {
+    double hw = 0.0;
+    uint64_t stamp = 0;                  // last build that used it (the oldest is evicted first)
+    std::vector<double> uc2e, m2l, m2m;  // m2m empty when the level was built as the coarsest
+};
+struct OperatorCache {
+    std::map<std::tuple<double, double, double>, CachedLevel> levels;  // key (a hw, b hw, ln(chi_max/chi_min))
+    size_t bytes = 0;                     // host memory held by the cached levels
+    size_t max_bytes = (size_t)1 << 30;   // beyond this the least recently used levels are dropped
+    uint64_t clock = 0;                   // builds so far
+};
+
 struct Plan {
     // configuration
+    bool self_coeff_given = false;   // the caller fixed c_self (else it follows the gas)
+    int levels_reused = 0;           // far-field levels of the last operator build taken from the cache
+    OperatorCache op_cache;          // far-field operators by (a hw, b hw, L), over the plan's gases
+    std::map<void **, size_t> upload_bytes;  // sizes of the uploaded operator buffers
     int64_t n = 0;
     int device = 0;
     ph_precision precision = PH_FP32;
@@ -322,8 +347,10 @@ struct HostOperators {
     std::vector<std::vector<double>> m2l;                // per level: 316 x n_lam x n_lam (row-major)
 };
 
+// cache (nullable): levels found there are rescaled instead of built, and new levels are added;
+// *reused (nullable) counts the levels taken from the cache.
 void build_operators(const Gas &gas, int q, double root_size, int max_depth, double cut,
-                     HostOperators &out);
+                     HostOperators &out, OperatorCache *cache = nullptr, int *reused = nullptr);
 double cube_self_integral(const Gas &gas, double h);
 void build_near_table(const Gas &gas, double h, int R, int sx, int sy, int sz, int n, std::vector<double> &tab);
 void build_grid_operator(const Gas &gas, const HostOperators &H, int level, double hw, double h, int m,

@@ -18,6 +18,7 @@
 //   l2l_{l,c} = m2m_{l,c}^T                          parent check values -> child
 //   m2l_{l,t} = K(lattice_l, lattice_l + 2 h_l t)    316 well-separated offsets t
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <thread>
 #include <vector>
@@ -49,46 +50,112 @@ void parallel_for(int n, F &&f)
     for (auto &x : th) x.join();
 }
 
+// Threads that meet at a barrier between rounds (sense-reversing, spinning): the rounds of
+// the Jacobi sweeps below are short, so threads stay alive across them.
+class SpinBarrier {
+public:
+    explicit SpinBarrier(unsigned n) : n_(n) {}
+    void wait()
+    {
+        const unsigned gen = gen_.load(std::memory_order_acquire);
+        if (count_.fetch_add(1, std::memory_order_acq_rel) + 1 == n_) {
+            count_.store(0, std::memory_order_relaxed);
+            gen_.fetch_add(1, std::memory_order_acq_rel);
+        } else {
+            while (gen_.load(std::memory_order_acquire) == gen) std::this_thread::yield();
+        }
+    }
+
+private:
+    const unsigned n_;
+    std::atomic<unsigned> count_{0}, gen_{0};
+};
+
 // One-sided Jacobi SVD of the m x n matrix A (column-major, m >= n).
 // On exit A holds U * diag(s); s the singular values; V (n x n, column-major).
+// The columns are split into nb blocks (a fixed count, at most 32); each sweep runs the rounds
+// of a round-robin tournament over the blocks (circle method), and in a round every pair of
+// blocks rotates all pairs of its columns (in the first round also the pairs inside each of
+// its two blocks), in a fixed order.  The block pairs of a round are disjoint, so they run in
+// parallel, and no bit of the result depends on the number of threads.  A column pair is
+// rotated when it is not yet orthogonal to 1e-16 relative; the sweeps stop when no pair
+// exceeds 1e-15.
 void jacobi_svd(int m, int n, std::vector<double> &A, std::vector<double> &s, std::vector<double> &V)
 {
     V.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 80; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < n - 1; ++p) {
-            double *ap = &A[(size_t)p * m];
-            for (int q = p + 1; q < n; ++q) {
-                double *aq = &A[(size_t)q * m];
-                double al = 0, be = 0, ga = 0;
-                for (int i = 0; i < m; ++i) {
-                    al += ap[i] * ap[i];
-                    be += aq[i] * aq[i];
-                    ga += ap[i] * aq[i];
-                }
-                if (ga == 0.0) continue;
-                double rel = std::fabs(ga) / std::sqrt(al * be);
-                if (!(rel > 1e-16)) continue;
-                off = std::max(off, rel);
-                double zeta = (be - al) / (2.0 * ga);
-                double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-                double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
-                for (int i = 0; i < m; ++i) {
-                    double x = ap[i], y = aq[i];
-                    ap[i] = c * x - sn * y;
-                    aq[i] = sn * x + c * y;
-                }
-                double *vp = &V[(size_t)p * n], *vq = &V[(size_t)q * n];
-                for (int i = 0; i < n; ++i) {
-                    double x = vp[i], y = vq[i];
-                    vp[i] = c * x - sn * y;
-                    vq[i] = sn * x + c * y;
-                }
-            }
+    auto rotate_pair = [&](int p, int q) -> double {
+        double *ap = &A[(size_t)p * m], *aq = &A[(size_t)q * m];
+        double al = 0, be = 0, ga = 0;
+        for (int i = 0; i < m; ++i) {
+            al += ap[i] * ap[i];
+            be += aq[i] * aq[i];
+            ga += ap[i] * aq[i];
         }
-        if (off < 1e-15) break;
-    }
+        if (ga == 0.0) return 0.0;
+        const double rel = std::fabs(ga) / std::sqrt(al * be);
+        if (!(rel > 1e-16)) return 0.0;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < m; ++i) {
+            const double x = ap[i], y = aq[i];
+            ap[i] = c * x - sn * y;
+            aq[i] = sn * x + c * y;
+        }
+        double *vp = &V[(size_t)p * n], *vq = &V[(size_t)q * n];
+        for (int i = 0; i < n; ++i) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = c * x - sn * y;
+            vq[i] = sn * x + c * y;
+        }
+        return rel;
+    };
+    const int nb = std::max(2, std::min(32, n - (n & 1)));  // even block count
+    auto first = [&](int b) { return (int)((int64_t)b * n / nb); };
+    std::vector<int> pos(nb);
+    for (int i = 0; i < nb; ++i) pos[i] = i;
+    const int npair = nb / 2;
+    const unsigned nt = std::max(1u, std::min({16u, std::thread::hardware_concurrency(), (unsigned)npair}));
+    SpinBarrier bar(nt);
+    std::vector<double> off_t(nt, 0.0);
+    std::atomic<bool> done{false};
+    auto worker = [&](unsigned tid) {
+        for (int sweep = 0; sweep < 80; ++sweep) {
+            double off = 0.0;
+            for (int r = 0; r < nb - 1; ++r) {
+                for (int i = (int)tid; i < npair; i += (int)nt) {
+                    const int P = std::min(pos[i], pos[nb - 1 - i]), Q = std::max(pos[i], pos[nb - 1 - i]);
+                    if (r == 0)
+                        for (int B : {P, Q})
+                            for (int p = first(B); p < first(B + 1); ++p)
+                                for (int q = p + 1; q < first(B + 1); ++q) off = std::max(off, rotate_pair(p, q));
+                    for (int p = first(P); p < first(P + 1); ++p)
+                        for (int q = first(Q); q < first(Q + 1); ++q) off = std::max(off, rotate_pair(p, q));
+                }
+                bar.wait();
+                if (tid == 0) {  // next round: every position but the first moves one place
+                    const int last = pos[nb - 1];
+                    for (int i = nb - 1; i > 1; --i) pos[i] = pos[i - 1];
+                    pos[1] = last;
+                }
+                bar.wait();
+            }
+            off_t[tid] = off;
+            bar.wait();
+            if (tid == 0) {
+                double mx = 0.0;
+                for (double v : off_t) mx = std::max(mx, v);
+                done.store(mx < 1e-15, std::memory_order_relaxed);
+            }
+            bar.wait();
+            if (done.load(std::memory_order_relaxed)) break;
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(worker, t);
+    worker(0);
+    for (auto &x : th) x.join();
     s.resize(n);
     for (int j = 0; j < n; ++j) {
         double acc = 0;
@@ -173,7 +240,8 @@ void m2l_offset(int idx, int &dx, int &dy, int &dz)
     dx = dy = dz = 0;
 }
 
-void build_operators(const Gas &gas, int q, double root_size, int max_depth, double cut, HostOperators &out)
+void build_operators(const Gas &gas, int q, double root_size, int max_depth, double cut, HostOperators &out,
+                     OperatorCache *cache, int *reused)
 {
     const double kShellRadius = 3.5;
     out.q = q;
@@ -209,15 +277,50 @@ void build_operators(const Gas &gas, int q, double root_size, int max_depth, dou
     const double zero[3] = {0, 0, 0};
     std::vector<double> hwl(L);
     for (int l = 0; l < L; ++l) hwl[l] = root_size / std::ldexp(1.0, l + 1);
-    // check-to-equivalent pseudo-inverse per level
-    parallel_for(L, [&](int l) {
-        if (l < 2) return;
+    // levels found in the cache (same a hw and b hw): rescaled by the power of two between the
+    // half-widths, exactly
+    std::vector<const CachedLevel *> hit(L, nullptr);
+    std::vector<int> fexp(L, 0);  // f = 2^fexp = hw_built / hw
+    int n_hit = 0;
+    if (cache) {
+        for (int l = 2; l < L; ++l) {
+            auto it = cache->levels.find(std::make_tuple(gas.a * hwl[l], gas.b * hwl[l], gas.L));
+            if (it == cache->levels.end()) continue;
+            int ex = 0;
+            const double fr = std::frexp(it->second.hw / hwl[l], &ex);
+            if (fr != 0.5) continue;  // not a power of two (cannot happen within one root cube)
+            hit[l] = &it->second;
+            fexp[l] = ex - 1;
+            ++n_hit;
+        }
+    }
+    if (reused) *reused = n_hit;
+    auto scaled = [](const std::vector<double> &v, int ex) {
+        std::vector<double> o(v.size());
+        const size_t chunk = 1 << 16, nc = (v.size() + chunk - 1) / chunk;
+        parallel_for((int)nc, [&](int c) {
+            const size_t e = std::min(v.size(), (c + 1) * chunk);
+            for (size_t i = c * chunk; i < e; ++i) o[i] = std::ldexp(v[i], ex);
+        });
+        return o;
+    };
+    // check-to-equivalent pseudo-inverse per level (K scales by f^3, its pseudo-inverse by
+    // f^-3); one level after the other, each SVD on every thread
+    for (int l = 2; l < L; ++l) {
+        if (hit[l]) {
+            out.uc2e[l] = scaled(hit[l]->uc2e, -3 * fexp[l]);
+            continue;
+        }
         std::vector<double> Kmat;
         kernel_matrix(out.shell_unit, out.lat_unit, ns, nl, hwl[l], hwl[l], zero, gas, Kmat);
         out.uc2e[l] = pinv_rowmajor(ns, nl, Kmat, cut);
-    });
-    // child -> parent translations (child level l, parent level l-1 >= 2)
+    }
+    // child -> parent translations (child level l, parent level l-1 >= 2); dimensionless
     for (int l = 3; l < L; ++l) {
+        if (hit[l] && !hit[l]->m2m.empty()) {
+            out.m2m[l] = hit[l]->m2m;
+            continue;
+        }
         out.m2m[l].assign((size_t)8 * nl * nl, 0.0);
         parallel_for(8, [&](int c) {
             double off[3] = {(((c >> 2) & 1) ? 1.0 : -1.0) * hwl[l], (((c >> 1) & 1) ? 1.0 : -1.0) * hwl[l],
@@ -234,8 +337,12 @@ void build_operators(const Gas &gas, int q, double root_size, int max_depth, dou
                 }
         });
     }
-    // well-separated translations, pure kernel values between lattices
+    // well-separated translations, pure kernel values between lattices (scale by f^3)
     for (int l = 2; l < L; ++l) {
+        if (hit[l]) {
+            out.m2l[l] = scaled(hit[l]->m2l, 3 * fexp[l]);
+            continue;
+        }
         out.m2l[l].assign((size_t)kNumM2L * nl * nl, 0.0);
         parallel_for(kNumM2L, [&](int k) {
             int dx, dy, dz;
@@ -245,6 +352,41 @@ void build_operators(const Gas &gas, int q, double root_size, int max_depth, dou
             kernel_matrix(out.lat_unit, out.lat_unit, nl, nl, hwl[l], hwl[l], sh, gas, Kmat);
             std::copy(Kmat.begin(), Kmat.end(), out.m2l[l].begin() + (size_t)k * nl * nl);
         });
+    }
+    // new levels into the cache, in the units of this build; the levels this build used are
+    // the most recent, and the least recently used go first when the cache is full
+    if (cache) {
+        const uint64_t now = ++cache->clock;
+        auto level_bytes = [](const CachedLevel &c) { return 8 * (c.uc2e.size() + c.m2l.size() + c.m2m.size()); };
+        for (int l = 2; l < L; ++l) {
+            auto key = std::make_tuple(gas.a * hwl[l], gas.b * hwl[l], gas.L);
+            auto it = cache->levels.find(key);
+            if (it == cache->levels.end()) {
+                CachedLevel c;
+                c.hw = hwl[l];
+                c.uc2e = out.uc2e[l];
+                c.m2l = out.m2l[l];
+                c.m2m = out.m2m[l];
+                c.stamp = now;
+                cache->bytes += level_bytes(c);
+                cache->levels.emplace(key, std::move(c));
+            } else {
+                it->second.stamp = now;
+                if (it->second.m2m.empty() && !out.m2m[l].empty()) {
+                    // a level first built as the coarsest gains its child -> parent translations
+                    // (dimensionless, so no rescaling)
+                    it->second.m2m = out.m2m[l];
+                    cache->bytes += 8 * out.m2m[l].size();
+                }
+            }
+        }
+        while (cache->bytes > cache->max_bytes && !cache->levels.empty()) {
+            auto old = cache->levels.begin();
+            for (auto i = cache->levels.begin(); i != cache->levels.end(); ++i)
+                if (i->second.stamp < old->second.stamp) old = i;
+            cache->bytes -= level_bytes(old->second);
+            cache->levels.erase(old);
+        }
     }
 }
 

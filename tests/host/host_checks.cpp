@@ -115,6 +115,47 @@ static void check_operators()
     EXPECT(bad == 0, "316 well-separated offsets round-trip");
 }
 
+// Operators rescaled from the cache (another pressure, the same a hw and b hw at another level)
+// equal a fresh build bit for bit: the kernel scales by an exact power of two.
+static void check_operator_cache()
+{
+    auto at = [](double p_torr) {
+        ph::Gas g{};
+        g.a = 0.035 * (0.2 * p_torr);
+        g.b = 2.0 * (0.2 * p_torr);
+        g.L = std::log(2.0 / 0.035);
+        g.P = 30.0 / (p_torr + 30.0) * 0.06;
+        return g;
+    };
+    auto same = [](const std::vector<double> &x, const std::vector<double> &y) {
+        return x.size() == y.size() && (x.empty() || std::memcmp(x.data(), y.data(), x.size() * 8) == 0);
+    };
+    const int q = 3, depth = 5;
+    ph::OperatorCache cache;
+    ph::HostOperators H0, H1, F1, H2, F2;
+    int r0 = -1, r1 = -1, r2 = -1;
+    ph::build_operators(at(400.0), q, 1.0, depth, 1e-7, H0, &cache, &r0);
+    EXPECT(r0 == 0, "first build takes nothing from the cache");
+    ph::build_operators(at(800.0), q, 1.0, depth, 1e-7, H1, &cache, &r1);
+    ph::build_operators(at(800.0), q, 1.0, depth, 1e-7, F1);
+    EXPECT(r1 == depth - 2, "doubled pressure: every level but the coarsest from the cache");
+    ph::build_operators(at(200.0), q, 1.0, depth, 1e-7, H2, &cache, &r2);
+    ph::build_operators(at(200.0), q, 1.0, depth, 1e-7, F2);
+    EXPECT(r2 == depth - 2, "halved pressure: every level but the finest from the cache");
+    bool eq1 = true, eq2 = true;
+    for (int l = 2; l <= depth; ++l) {
+        eq1 = eq1 && same(H1.uc2e[l], F1.uc2e[l]) && same(H1.m2l[l], F1.m2l[l]) && same(H1.m2m[l], F1.m2m[l]);
+        eq2 = eq2 && same(H2.uc2e[l], F2.uc2e[l]) && same(H2.m2l[l], F2.m2l[l]) && same(H2.m2m[l], F2.m2m[l]);
+    }
+    EXPECT(eq1, "doubled pressure: rescaled operators equal a fresh build bit for bit");
+    EXPECT(eq2, "halved pressure: rescaled operators equal a fresh build bit for bit");
+    // a pressure ratio that is not a power of two shares nothing
+    int r3 = -1;
+    ph::HostOperators H3;
+    ph::build_operators(at(760.0), q, 1.0, depth, 1e-7, H3, &cache, &r3);
+    EXPECT(r3 == 0, "760 Torr after 200/400/800 Torr: no level in common");
+}
+
 static void check_full_tree()
 {
     std::mt19937_64 rng(7);
@@ -166,6 +207,7 @@ int main()
 {
     check_validation();
     check_own_cell();
+    check_operator_cache();
     check_operators();
     check_full_tree();
     check_clamp();
