@@ -100,7 +100,12 @@ typedef struct {
     double e_abs;           /* keep target i iff |E_i| >= e_abs (V/m); < 0 => rule off         */
     double e_applied;       /* keep target i iff |E_i| >= e_applied + e_rel (max|E| - e_applied) */
     double e_rel;           /*   ... < 0 => rule off.  Both rules off => every point a target   */
-    double r_s;             /* third strategy of Sec. 3; must be 0 in this library              */
+    double r_s;             /* third strategy of Sec. 3 (r_s skip), 0 = off: at a target of leaf B
+                               the sources of B's W list (near boxes not adjacent to B, Fig. of
+                               the near-field cross section) are left out when
+                               sum_A Q_A K(d_min(A, B)) < r_s * (the rest of S at the target),
+                               Q_A the weighted strength of box A; that changes S by at most
+                               r_s relative.  The paper's streamer runs use 1e-4 (Sec. 5)     */
 } ph_thresholds;
 
 typedef struct {
@@ -295,6 +300,8 @@ int64_t ph_plan_size(const ph_plan *plan);
  *   7 scale exponent e of the FP32 forms (int32, 1)
  *   8 learned-selector row features (float, rows x 8)
  *   9 learned-selector row boxes: plan-tree box ids (int32, rows)
+ *  10 third strategy (r_s > 0): per sorted point, 1 where the W list of its leaf was left
+ *     out (uint8, n; defined at the targets of leaves with a W list)
  */
 #define PH_BOX_FIELDS 10  /* level, ax, ay, az, src_first, src_count, tgt_first, tgt_count, parent, flags */
 ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, int64_t *n_out);

@@ -26,7 +26,7 @@ BOX_FIELDS = 10
 MLP_NIN, MLP_NHID = 8, 64
 MLP_NPARAM = 64 * 8 + 64 + 64 * 64 + 64 + 64 + 1
 DEBUG = {"keys": 0, "perm": 1, "src": 2, "tgt": 3, "boxes": 4, "level_start": 5, "c_self": 6,
-         "scale_exp": 7, "features": 8, "feature_boxes": 9}
+         "scale_exp": 7, "features": 8, "feature_boxes": 9, "rs_skip": 10}
 
 
 class PhPoints(ctypes.Structure):
@@ -291,7 +291,7 @@ class Plan:
         n = ctypes.c_int64()
         _check(_lib.ph_debug_fetch(self._h, code, None, 0, ctypes.byref(n)))
         dt = {0: np.uint64, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5: np.int32, 6: np.float64,
-              7: np.int32, 8: np.float32, 9: np.int32}[code]
+              7: np.int32, 8: np.float32, 9: np.int32, 10: np.uint8}[code]
         width = {4: BOX_FIELDS, 8: 8}.get(code, 1)
         buf = np.zeros(n.value * width, dtype=dt)
         _check(_lib.ph_debug_fetch(self._h, code, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes,

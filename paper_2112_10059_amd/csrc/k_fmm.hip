@@ -264,6 +264,66 @@ __device__ __forceinline__ void put_output(TO *__restrict__ S_out, int32_t o, do
     S_out[o] = (TO)(P * ldexp(tot, scale_exp));
 }
 
+// Third strategy of Sec. 3: an upper bound of the W-list sources' field anywhere in leaf b.
+// Box A of the W list (not adjacent to b) holds selected sources of total weighted strength
+// Q_A; their field at any point of b is at most Q_A K(d_min), d_min the smallest distance
+// between the two cubes, because K decreases with r.  Sum over A in FP64, in the units of the
+// scaled strengths (2^-e).  At a target of b the W list is left out when this bound is below
+// r_s times the rest of S there (far field, near field and own cell).
+template <class T>
+__device__ double w_list_bound(const FmmArgs<T> &a, int32_t b)
+{
+    const int lb = a.bx.level[b];
+    const double hb = a.lt.hw[lb];
+    const double cb0 = a.lo0 + (2.0 * a.bx.ax[b] + 1.0) * hb, cb1 = a.lo1 + (2.0 * a.bx.ay[b] + 1.0) * hb,
+                 cb2 = a.lo2 + (2.0 * a.bx.az[b] + 1.0) * hb;
+    double bound = 0.0;
+    for (uint32_t e = a.L.w_rng[b].x; e < a.L.w_rng[b].y; ++e) {
+        const int32_t A = a.L.w[e];
+        const double ha = a.lt.hw[a.bx.level[A]];
+        const double g0 = fmax(fabs(a.lo0 + (2.0 * a.bx.ax[A] + 1.0) * ha - cb0) - ha - hb, 0.0);
+        const double g1 = fmax(fabs(a.lo1 + (2.0 * a.bx.ay[A] + 1.0) * ha - cb1) - ha - hb, 0.0);
+        const double g2 = fmax(fabs(a.lo2 + (2.0 * a.bx.az[A] + 1.0) * ha - cb2) - ha - hb, 0.0);
+        const int32_t s0 = a.bx.s_first[A], s1 = s0 + a.bx.s_cnt[A];
+        double q = 0.0;
+        for (int32_t j = s0; j < s1; ++j) q += (double)a.s_dat[j].w;
+        const double d2 = g0 * g0 + g1 * g1 + g2 * g2;
+        if (q > 0.0) bound += d2 > 0.0 ? q * kernel_eval<false>(d2, a.kp64) : INFINITY;
+    }
+    return bound;
+}
+
+// true when the W list of a leaf with bound bnd is left out at a target whose other terms sum
+// to rest (scaled units); records the decision for the target (sorted point k)
+template <class T>
+__device__ __forceinline__ bool w_list_skipped(const FmmArgs<T> &a, double bnd, double rest, int32_t k)
+{
+    const bool skip = bnd < a.r_s * rest;
+    if (a.rs_flag) a.rs_flag[k] = skip ? 1 : 0;
+    return skip;
+}
+
+// The bounds of every target leaf with a W list (third strategy), before the far-field
+// kernels read them: the leaves of the per-level grid segments and of the shell list
+template <class T>
+__global__ __launch_bounds__(256) void w_bound_kernel(FmmArgs<T> a, double *__restrict__ bound)
+{
+    const int32_t stride = (int32_t)(gridDim.x * blockDim.x), t0 = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    for (int32_t i = t0; i < a.sc->n_far_b; i += stride) {
+        const int32_t b = a.L.far_b[i];
+        if (a.L.w_rng[b].y > a.L.w_rng[b].x) bound[b] = w_list_bound(a, b);
+    }
+#pragma unroll
+    for (int l = 0; l < kMaxDepth + 2; ++l) {
+        if (l > a.lt.depth) break;
+        const int32_t n = a.sc->n_far_a_lvl[l], base = a.lt.base[l];
+        for (int32_t i = t0; i < n; i += stride) {
+            const int4 en = a.L.far_a[base + i];
+            if (en.w & 2) bound[en.x] = w_list_bound(a, en.x);
+        }
+    }
+}
+
 // W list of target leaf b for the lanes' targets: artificial sources of smaller non-adjacent
 // boxes.  The wave holds the source box's densities in registers, lane li of slot k holding
 // phi[64 k + li], and broadcasts them lane by lane.
@@ -438,7 +498,9 @@ __device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, c
                       kz = ((cl >> 20) & 1023) - lorg[qq][2];
             far = Us[qq][(i * gm + j) * gm + kz];
         }
-        if (lw[qq]) {
+        const double rest = (double)far + tnr + own_term(a, sbit, ot, scale_exp);
+        const bool skip_w = lw[qq] && a.r_s > 0.0 && w_list_skipped(a, a.rs_bound[b], rest, kk);
+        if (lw[qq] && !skip_w) {
             // W list (rare on grids): the source boxes' lattice densities, one thread per target
             const V4<float> xx = point_xyz(a, kk);
             for (uint32_t e = a.L.w_rng[b].x; e < a.L.w_rng[b].y; ++e) {
@@ -455,7 +517,7 @@ __device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, c
                 }
             }
         }
-        const double tot = (double)far + tnr + own_term(a, sbit, ot, scale_exp);
+        const double tot = lw[qq] && !skip_w ? (double)far + tnr + own_term(a, sbit, ot, scale_exp) : rest;
         S_out[ot] = (TO)(a.P * ldexp(tot, scale_exp));
     };
 #pragma unroll
@@ -571,6 +633,7 @@ __device__ void far_grid_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const
             const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
             const bool near = a.L.u_rng[b].y > a.L.u_rng[b].x;
             const bool has_w = a.L.w_rng[b].y > a.L.w_rng[b].x;
+            const double bnd = (has_w && a.r_s > 0.0) ? a.rs_bound[b] : 0.0;
             if (a.work && lane == 0) {
                 unsigned long long near_src = 0;
                 for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
@@ -592,7 +655,12 @@ __device__ void far_grid_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const
                     const int r = act ? local_cell(a, a.pcell[k], b, gm) : 0;
                     far = staged ? grid_far<T, NK, true>(Gs, R, nl, r, uv) : grid_far<T, NK, false>(G, R, nl, r, uv);
                 }
-                if (has_w) far += w_list_far<T, NK>(a, b, x, act, lane);
+                bool skip_w = false;
+                if (has_w && a.r_s > 0.0 && act) {
+                    const double rest = (double)far + (near ? t_near[k] : 0.0) + own_term(a, sb, a.perm[k], scale_exp);
+                    skip_w = w_list_skipped(a, bnd, rest, k);
+                }
+                if (has_w) far += w_list_far<T, NK>(a, b, x, act && !skip_w, lane);
                 if (act) {
                     const int32_t o = a.perm[k];
                     put_output(S_out, o, a.P, (double)far + (near ? t_near[k] : 0.0) + own_term(a, sb, o, scale_exp),
@@ -645,6 +713,7 @@ __device__ void far_shell_body(const FmmArgs<T> &a, TO *__restrict__ S_out, cons
         const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0, tn = a.bx.t_cnt[b];
         const uint32_t u0 = a.L.u_rng[b].x, u1 = a.L.u_rng[b].y;
         const uint32_t w0 = a.L.w_rng[b].x, w1 = a.L.w_rng[b].y;
+        const double bnd = (w1 > w0 && a.r_s > 0.0) ? a.rs_bound[b] : 0.0;
         if (a.work && threadIdx.x == 0) {
             unsigned long long near_src = 0;
             for (uint32_t e = u0; e < u1; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
@@ -668,6 +737,11 @@ __device__ void far_shell_body(const FmmArgs<T> &a, TO *__restrict__ S_out, cons
                     const T dx = x.x - q.x, dy = x.y - q.y, dz = x.z - q.z;
                     far += kernel_eval<false>(dx * dx + dy * dy + dz * dz, a.kp) * q.w;
                 }
+            bool skip_w = false;
+            if (w1 > w0 && a.r_s > 0.0 && act) {
+                const double rest = (double)far + (u1 > u0 ? t_near[k] : 0.0) + own_term(a, sb, a.perm[k], scale_exp);
+                skip_w = w_list_skipped(a, bnd, rest, k);
+            }
             for (uint32_t e = w0; e < w1; ++e) {
                 const int32_t A = a.L.w[e];
                 const double hwa = a.lt.hw[a.bx.level[A]];
@@ -677,7 +751,7 @@ __device__ void far_shell_body(const FmmArgs<T> &a, TO *__restrict__ S_out, cons
                 __syncthreads();
                 for (int li = threadIdx.x; li < nl; li += blockDim.x) wphi[li] = a.phi[(size_t)A * nl + li];
                 __syncthreads();
-                if (act)
+                if (act && !skip_w)
                     for (int li = 0; li < nl; ++li) {
                         const T dx = x.x - (ax + ha * a.lat[3 * li]);
                         const T dy = x.y - (ay + ha * a.lat[3 * li + 1]);
@@ -968,6 +1042,8 @@ template <class T>
 void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
 {
     FmmArgs<T> a = make_args<T>(p);
+    // third strategy: the W lists' bounds first (the leaf kernels compare them per target)
+    if (p.thr.r_s > 0 && p.d_rs_bound) w_bound_kernel<T><<<256, 256, 0, s>>>(a, p.d_rs_bound);
     // upper bounds on the list lengths (the counts are on the device)
     const int64_t B = p.box_cap;
     if (p.grid_mode) {

@@ -52,6 +52,13 @@ struct FmmArgs {
     int k_pad;  // padded row length of the stacked translation operators
     double lo0, lo1, lo2;
     double P;
+    // third strategy of Sec. 3 (0 = off): the W list of a target leaf is left out at a target
+    // where its bound is below r_s times the rest of S there; rs_flag (per sorted point) records
+    // the targets of leaves with a W list at which that happened
+    double r_s;
+    uint8_t *rs_flag;
+    const double *rs_bound;  // per box: the bound of its W list (leaves with one)
+    KParams<double> kp64;    // the kernel in FP64, for the bound
 };
 
 template <class T>
@@ -160,6 +167,10 @@ inline FmmArgs<T> make_args(Plan &p)
     a.lo1 = p.cube_lo[1];
     a.lo2 = p.cube_lo[2];
     a.P = p.gas.P;
+    a.r_s = p.thr.r_s;
+    a.rs_flag = p.d_rs_flag;
+    a.rs_bound = p.d_rs_bound;
+    a.kp64 = make_kparams<double>(p.gas);
     return a;
 }
 

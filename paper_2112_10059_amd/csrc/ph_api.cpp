@@ -143,7 +143,7 @@ void validate(const ph_points *pts, const ph_gas *gas, const ph_thresholds *thr,
     if (!finite(thr->e_abs)) bad("thresholds.e_abs must be finite");
     if (!finite(thr->e_rel) || thr->e_rel > 1) bad("thresholds.e_rel must be <= 1 (negative = off)");
     if (!finite(thr->e_applied) || thr->e_applied < 0) bad("thresholds.e_applied must be >= 0");
-    if (thr->r_s != 0.0) throw Error{PH_EUNSUPPORTED, "thresholds.r_s (third strategy) must be 0"};
+    if (!std::isfinite(thr->r_s) || thr->r_s < 0) bad("thresholds.r_s (third strategy) must be finite and >= 0");
     if (opt->precision < PH_FP64 || opt->precision > PH_FP32_BF16SPLIT) bad("options.precision out of range");
     if (opt->method < PH_METHOD_FMM || opt->method > PH_METHOD_DIRECT) bad("options.method out of range");
     if (opt->selector < PH_SEL_THRESHOLD || opt->selector > PH_SEL_LEARNED) bad("options.selector out of range");
@@ -271,6 +271,10 @@ size_t layout_workspace(Plan &p, char *base, bool assign)
     take(&p.d_row_box, (size_t)NL * 4);
     take(&p.d_row_feat, (size_t)NL * 8 * 4);
     take(&p.d_leafflag, (size_t)(NL + 1) * 4);
+    if (p.thr.r_s > 0) {
+        take(&p.d_rs_flag, (size_t)n);
+        take(&p.d_rs_bound, (size_t)B * 8);
+    }
     return (off + 255) & ~(size_t)255;
 }
 
@@ -1247,6 +1251,15 @@ ph_status ph_debug_fetch(ph_plan *plan, int what, void *dst, int64_t cap_bytes, 
             const size_t total = what == 8 ? rf.size() * 4 : rb.size() * 4;
             size_t bytes = std::min<size_t>(total, cap_bytes > 0 ? (size_t)cap_bytes : 0);
             if (bytes && dst) std::memcpy(dst, what == 8 ? (const void *)rf.data() : (const void *)rb.data(), bytes);
+            break;
+        }
+        case 10: {
+            // third strategy: per sorted point, 1 where the W list was left out (targets of leaves
+            // with a W list; other entries are not defined)
+            if (!p.d_rs_flag) throw Error{PH_EINVAL, "the plan has no third-strategy flags (r_s = 0)"};
+            *n_out = p.n;
+            const size_t bytes = std::min<size_t>((size_t)p.n, cap_bytes > 0 ? (size_t)cap_bytes : 0);
+            if (bytes && dst) PH_HIP(hipMemcpy(dst, p.d_rs_flag, bytes, hipMemcpyDeviceToHost));
             break;
         }
         default: throw Error{PH_EINVAL, "unknown debug array"};

@@ -316,6 +316,8 @@ struct Plan {
     size_t ws_bytes = 0;
     // caller-supplied target set (sorted order, 1 = may be a target), or null for every point
     uint8_t *d_tmask = nullptr;
+    uint8_t *d_rs_flag = nullptr;   // per sorted point: the W list was left out there (r_s > 0)
+    double *d_rs_bound = nullptr;   // per box: bound of its W list's field (r_s > 0)
     size_t bytes_allocated = 0;
     size_t workspace_cap = 0;
 };

@@ -67,3 +67,68 @@ def plan_kwargs(wl: gen.Workload, **kw):
         args["self_coeff"] = 0.0
     args.update(kw)
     return args
+
+
+def _adjacent(A, B):
+    """Closed cubes of two octree boxes (level, ax, ay, az) touch or overlap (A != B)."""
+    la, lb = int(A[0]), int(B[0])
+    L = max(la, lb)
+    sa, sb = 1 << (L - la), 1 << (L - lb)
+    for d in range(1, 4):
+        a0, b0 = int(A[d]) * sa, int(B[d]) * sb
+        if a0 > b0 + sb or b0 > a0 + sa:
+            return False
+    return tuple(int(v) for v in A[:4]) != tuple(int(v) for v in B[:4])
+
+
+def w_lists(rows):
+    """W list of every target leaf of a tree from ``reference_tree``: the boxes with sources
+    that descend from a colleague of the leaf, are not adjacent to it, and whose parent is
+    (kernel-independent FMM lists, Sec. 2.4).  Returns {leaf row: [rows of its W boxes]}."""
+    key = {tuple(int(v) for v in r[:4]): i for i, r in enumerate(rows)}
+
+    def children(i):
+        l, ax, ay, az = (int(v) for v in rows[i][:4])
+        out = []
+        for o in range(8):
+            k = (l + 1, 2 * ax + ((o >> 2) & 1), 2 * ay + ((o >> 1) & 1), 2 * az + (o & 1))
+            if k in key:
+                out.append(key[k])
+        return out
+
+    res = {}
+    for b, r in enumerate(rows):
+        if not (r[8] == 1 and r[7] > 0):
+            continue
+        l, ax, ay, az = (int(v) for v in r[:4])
+        stack = []
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    k = (l, ax + dx, ay + dy, az + dz)
+                    if k in key and k != (l, ax, ay, az):
+                        stack.append(key[k])
+        W = []
+        while stack:
+            c = stack.pop()
+            if rows[c][8] == 1:
+                continue
+            for a in children(c):
+                if _adjacent(rows[a], r):
+                    stack.append(a)
+                elif rows[a][5] > 0:
+                    W.append(a)
+        if W:
+            res[b] = sorted(W)
+    return res
+
+
+def box_gap(A, B, lo, size):
+    """Smallest distance between the cubes of two octree boxes (cube [lo, lo + size]^3)."""
+    ha, hb = size / (1 << int(A[0])), size / (1 << int(B[0]))
+    g2 = 0.0
+    for d in range(1, 4):
+        a0, b0 = lo + int(A[d]) * ha, lo + int(B[d]) * hb
+        g = max(0.0, max(a0, b0) - min(a0 + ha, b0 + hb))
+        g2 += g * g
+    return float(np.sqrt(g2))

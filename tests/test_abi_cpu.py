@@ -81,10 +81,12 @@ def test_nonfinite_coordinates_rejected():
     assert ei.value.status == binding.PH_EINVAL
 
 
-def test_third_strategy_unsupported():
+@pytest.mark.parametrize("r_s", [-1e-4, float("nan"), float("inf")])
+def test_third_strategy_ratio_validated(r_s):
     with pytest.raises(binding.PhError) as ei:
-        _plan(r_s=1e-4)
-    assert ei.value.status == binding.PH_EUNSUPPORTED
+        _plan(r_s=r_s)
+    assert ei.value.status == binding.PH_EINVAL
+    assert "r_s" in str(ei.value)
 
 
 def test_null_arguments():

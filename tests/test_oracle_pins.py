@@ -450,3 +450,77 @@ def test_local_ball_error_hand_case():
     assert local_ball_error(S_num, S_ref, xyz, (0.0, 0.0, 0.0), 0.3) == pytest.approx((0.1 + 0.05 + 0.0) / 3, rel=1e-14)
     assert local_ball_error(S_num, S_ref, xyz, (0.0, 0.0, 0.0), 0.2) == pytest.approx(0.075, rel=1e-14)
     assert math.isnan(local_ball_error(S_num, S_ref, xyz, (5.0, 5.0, 5.0), 0.1))
+
+
+# ---------------------------------------------------------------- third strategy (r_s skip)
+
+def _third_case(seed=5):
+    """A small cloud: a cluster near the origin holds the targets' box, a few distant small
+    boxes hold the remaining (non-adjacent near) sources."""
+    rng = np.random.default_rng(seed)
+    near = rng.uniform(-0.01, 0.01, size=(40, 3))
+    far1 = np.array([0.05, 0.0, 0.0]) + rng.uniform(-0.002, 0.002, size=(6, 3))
+    far2 = np.array([0.0, -0.06, 0.01]) + rng.uniform(-0.002, 0.002, size=(5, 3))
+    xyz = np.vstack([near, far1, far2])
+    I = np.concatenate([rng.uniform(0.5, 2.0, 40), rng.uniform(0.1, 1.0, 6), rng.uniform(0.1, 1.0, 5)])
+    w = rng.uniform(1e-7, 3e-7, xyz.shape[0])
+    targets = np.arange(10)
+    # smallest distances between the cubes [-0.01, 0.01]^3 and the boxes of half-width 0.002
+    groups = [[(np.arange(40, 46), 0.048 - 0.01), (np.arange(46, 51), 0.058 - 0.01)]]
+    return xyz, I, w, targets, groups
+
+
+def test_third_strategy_limits():
+    """r_s = 0 keeps every source (the plain sum); r_s huge drops exactly the remaining boxes."""
+    from oracle.strategies import third_strategy
+    xyz, I, w, tg, groups = _third_case()
+    grp = np.zeros(tg.size, dtype=np.int64)
+    r0 = third_strategy(xyz, I, gen.GAS_760, tg, grp, groups, 0.0, w=w, use_numpy=True)
+    full = photoionization(xyz, I, gen.GAS_760, w=w, targets=tg, use_numpy=True).S_t
+    np.testing.assert_allclose(r0.S_t, full, rtol=1e-13)
+    assert not r0.skipped.any()
+    rinf = third_strategy(xyz, I, gen.GAS_760, tg, grp, groups, 1e30, w=w, use_numpy=True)
+    assert rinf.skipped.all()
+    keep = np.ones(xyz.shape[0], dtype=bool)
+    keep[40:] = False
+    np.testing.assert_allclose(rinf.S_t, photoionization(xyz, I, gen.GAS_760, w=w, targets=tg, smask=keep,
+                                                         use_numpy=True).S_t, rtol=1e-13)
+
+
+def test_third_strategy_bound_and_error():
+    """The bound (strength times K at the smallest box distance) is at or above the remaining
+    sources' field at every target, and a skip changes S by at most r_s relative."""
+    from oracle.strategies import third_strategy
+    xyz, I, w, tg, groups = _third_case(seed=11)
+    grp = np.zeros(tg.size, dtype=np.int64)
+    r = third_strategy(xyz, I, gen.GAS_760, tg, grp, groups, 0.0, w=w, use_numpy=True)
+    assert np.all(r.rest_t > 0) and np.all(r.rest_t <= r.bound_t)
+    ratio = r.bound_t / r.est_t
+    r_s = float(np.median(ratio))  # half of the targets skip
+    rs = third_strategy(xyz, I, gen.GAS_760, tg, grp, groups, r_s, w=w, use_numpy=True)
+    assert 0 < rs.skipped.sum() < tg.size
+    np.testing.assert_array_equal(rs.skipped, ratio < r_s)
+    full = r.S_t
+    assert np.all((full - rs.S_t) / full <= r_s)
+
+
+def test_third_strategy_hand_case():
+    """One target, one source in its own neighbourhood and one remaining source: the decision
+    flips where bound = r_s * est, with bound = w I K(d_min) written out by hand."""
+    from oracle.strategies import third_strategy
+    gc = gas_constants(gen.GAS_760)
+    xyz = np.array([[0.0, 0.0, 0.0], [0.01, 0.0, 0.0], [0.1, 0.0, 0.0]])
+    I = np.array([0.0, 3.0, 5.0])
+    w = np.array([1e-6, 2e-6, 4e-6])
+    dmin = 0.08
+    groups = [[(np.array([2]), dmin)]]
+    est = gc.P * 2e-6 * 3.0 * float(kernel_K(np.array([0.01]), gc)[0])
+    rest = gc.P * 4e-6 * 5.0 * float(kernel_K(np.array([0.1]), gc)[0])
+    bound = gc.P * 4e-6 * 5.0 * float(kernel_K(np.array([dmin]), gc)[0])
+    thr = bound / est
+    for r_s, skip in ((thr * 1.001, True), (thr * 0.999, False)):
+        r = third_strategy(xyz, I, gen.GAS_760, np.array([0]), np.array([0]), groups, r_s, w=w, use_numpy=True)
+        assert bool(r.skipped[0]) == skip
+        np.testing.assert_allclose(r.est_t[0], est, rtol=1e-14)
+        np.testing.assert_allclose(r.bound_t[0], bound, rtol=1e-14)
+        np.testing.assert_allclose(r.S_t[0], est if skip else est + rest, rtol=1e-14)
