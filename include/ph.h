@@ -202,6 +202,23 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
                       void *stream, ph_stats *stats);
 
 /*
+ * Another evaluation on the sets of the previous ph_evaluate on this plan (Sec. 5 evaluates S_ph
+ * twice per time step, on fields that change little between the two): the source and target
+ * sets, the learned decisions, the octree and every interaction list are those that call built
+ * on the plan's own workspace; only the source strengths are new.  It runs the compaction of
+ * the new I on the old flags (which also clears S_out at the points that are not targets and
+ * checks the selected sources' values), the upward and downward passes, the near field and
+ * the far field; the maxima pass, the selection pass, the tree and the list builds are left
+ * out, and so are the FP32 scale (2^-e from the previous call's maximum) and, on learned plans,
+ * the validation.  I and S_out as for ph_evaluate (absE is not read).  Errors as ph_evaluate,
+ * plus PH_EINVAL when no ph_evaluate has completed its launches on the plan since it was
+ * created or its target set was changed, PH_EUNSUPPORTED for the direct method.  Results equal
+ * a plan whose selection gave those sets: for an I whose sets and maximum are those of the
+ * previous call, bit for bit equal to ph_evaluate.
+ */
+ph_status ph_evaluate_same_sets(ph_plan *plan, const void *I, void *S_out, void *stream, ph_stats *stats);
+
+/*
  * Size in bytes of the per-call workspace of ph_evaluate_ws (0 for NULL).  Every per-call
  * array of the hot path lives in it: selection flags and compacted records, the per-call
  * tree and interaction lists, equivalent densities and check values, translation products,

@@ -70,7 +70,7 @@ EXPORTED = ["ph_status_string", "ph_last_error", "ph_options_default", "ph_plan_
             "ph_evaluate", "ph_plan_check", "ph_plan_size", "ph_debug_fetch", "ph_mlp_forward",
             "ph_mlp_backward", "ph_adam_step", "ph_selector_features", "ph_phase_times", "ph_selector_fields",
             "ph_plan_set_graph", "ph_mlp_backward_noalloc", "ph_evaluate_workspace_bytes", "ph_evaluate_ws",
-            "ph_plan_set_targets", "ph_plan_set_gas"]
+            "ph_plan_set_targets", "ph_plan_set_gas", "ph_evaluate_same_sets"]
 
 _lib = None
 
@@ -115,6 +115,8 @@ def load(path: Optional[str] = None):
     lib.ph_evaluate_ws.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(PhStats)]
     lib.ph_plan_set_targets.restype = ctypes.c_int
     lib.ph_plan_set_targets.argtypes = [vp, vp, ctypes.c_int64]
+    lib.ph_evaluate_same_sets.restype = ctypes.c_int
+    lib.ph_evaluate_same_sets.argtypes = [vp, vp, vp, vp, ctypes.POINTER(PhStats)]
     lib.ph_plan_set_gas.restype = ctypes.c_int
     lib.ph_plan_set_gas.argtypes = [vp, ctypes.POINTER(PhGas), ctypes.POINTER(ctypes.c_int)]
     lib.ph_plan_set_graph.restype = ctypes.c_int
@@ -233,14 +235,19 @@ class Plan:
         import torch
         return torch.zeros(self.workspace_bytes(), dtype=torch.uint8, device=device)
 
-    def evaluate(self, I, E=None, out=None, stream=None, stats: bool = False, workspace=None):
+    def evaluate(self, I, E=None, out=None, stream=None, stats: bool = False, workspace=None,
+                 same_sets: bool = False):
         """S_ph for device tensors I (dtype of the plan) and |E| (float32 or None); with a
-        workspace (from new_workspace) the call runs on it (ph_evaluate_ws)."""
+        workspace (from new_workspace) the call runs on it (ph_evaluate_ws); same_sets: on the
+        sets, tree and lists of the previous call (ph_evaluate_same_sets, E unused)."""
         import torch
         if out is None:
             out = torch.empty(self.n, dtype=self.dtype, device=I.device)
         st = PhStats() if stats else None
-        if workspace is None:
+        if same_sets:
+            _check(_lib.ph_evaluate_same_sets(self._h, _dptr(I), _dptr(out), _stream_ptr(stream),
+                                              ctypes.byref(st) if stats else None))
+        elif workspace is None:
             _check(_lib.ph_evaluate(self._h, _dptr(I), _dptr(E), _dptr(out), _stream_ptr(stream),
                                     ctypes.byref(st) if stats else None))
         else:

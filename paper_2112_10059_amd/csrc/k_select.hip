@@ -182,6 +182,17 @@ __device__ void store_maxima(const Maxima &m, CallScalars *sc, int32_t *sticky, 
     }
 }
 
+// First kernel of a call on the previous call's sets: the call's work counters, error bits and
+// validation figure start from zero; the sets, the tree, the lists and the call number stay.
+__global__ void reuse_begin_kernel(CallScalars *sc)
+{
+    for (int i = threadIdx.x; i < 12; i += blockDim.x) sc->work[i] = 0ull;
+    if (threadIdx.x == 0) {
+        sc->err = 0;
+        sc->check_rel = 0.0;
+    }
+}
+
 // The training entry points' step between the reduction and their own passes
 __global__ __launch_bounds__(256) void maxima_store_kernel(const double *__restrict__ red, int nb, CallScalars *sc,
                                                            int32_t *sticky, const int32_t *__restrict__ iperm,
@@ -512,7 +523,8 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     const uint8_t *__restrict__ sel, const uint8_t *__restrict__ bnd, const uint64_t *__restrict__ partial,
     int64_t nb, int tile_sums, int tgt_compact, uint64_t *__restrict__ scanned, int32_t *__restrict__ t_out,
     typename Vec4T<T>::type *__restrict__ s_dat, typename Vec4T<T>::type *__restrict__ t_dat,
-    const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell, int32_t *__restrict__ t_cell)
+    const int32_t *__restrict__ cell, int32_t *__restrict__ s_cell, int32_t *__restrict__ t_cell,
+    TI *__restrict__ S_zero, int32_t *sticky)
 {
     __shared__ uint64_t wsum[kSelWaves];
     constexpr int kStrips = kSelStrips;
@@ -578,11 +590,16 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
         const int64_t k = base + st * 64 + lane;
         if (k >= n) continue;
         if (bd[st]) scanned[k] = here;
+        // a call on the previous call's sets (S_zero set): the output at the points that are
+        // not targets is cleared here, as the selection pass would have done
+        if (S_zero && !(f[st] & 2u)) S_zero[perm[k]] = TI(0);
         // points that are only targets need nothing more unless targets are compacted
         if (!(tgt_compact ? f[st] : (f[st] & 1u))) continue;
         const uint32_t sp_lo = (uint32_t)(here & 0xffffffffu), sp_hi = (uint32_t)(here >> 32);
         const int32_t o = perm[k];
-        const double Iv = (double)I[o] * scale;
+        const TI Iraw = I[o];
+        if (S_zero && bad_value(Iraw)) flag_error(sc, sticky, 1);  // no maxima pass checked it
+        const double Iv = (double)Iraw * scale;
         T x, y, z;
         if constexpr (sizeof(C) == 8) {
             x = (T)xyz[3 * k];
@@ -668,7 +685,7 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
 {
     if (p.n <= 0) return;
     const int64_t nb = (p.n + kSelTile - 1) / kSelTile;
-    uint64_t *partial = (uint64_t *)p.d_scan_tmp;
+    uint64_t *partial = p.d_tile_sum;
     const SelectParams sp = params_of(p, src_rel);
     LearnArgs la{};
     if (learned) {
@@ -706,19 +723,33 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
     }
     if (after_tiles) PH_HIP(hipEventRecord(after_tiles, s));
     // up to 2048 tiles the compaction adds up the earlier tiles' sums itself; beyond, one
-    // workgroup scans them first
+    // workgroup scans them first (in place: a call on the same sets reads the scan)
+    if (nb > 2048) scan_tile_sums_u64(partial, nb, &p.d_sc->packed_total, s);
+    launch_compact(p, I, nullptr, s);
+}
+
+// The compaction pass over the flags of the last selection pass.  S_zero: a call on the
+// previous call's sets, whose output at the points that are not targets is cleared here.
+void launch_compact(const Plan &p, const void *I, void *S_zero, hipStream_t s)
+{
+    const int64_t nb = (p.n + kSelTile - 1) / kSelTile;
+    const uint64_t *partial = p.d_tile_sum;
     const int tile_sums = nb <= 2048 ? 1 : 0;
-    if (!tile_sums) scan_tile_sums_u64(partial, nb, &p.d_sc->packed_total, s);
     if (p.precision == PH_FP64)
         select_compact_kernel<double, double, double><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
             (const double *)I, p.d_perm, p.d_xyz, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
             partial, nb, tile_sums, p.method == PH_METHOD_DIRECT ? 1 : 0, p.d_flag, p.d_t_out, (double4 *)p.d_s_dat, (double4 *)p.d_t_dat,
-            p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
+            p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell, (double *)S_zero, p.d_sticky);
     else
         select_compact_kernel<float, float, float4><<<(unsigned)nb, 64 * kSelWaves, 0, s>>>(
             (const float *)I, p.d_perm, p.d_xyzf, p.d_w, p.w_uniform, p.c_self, p.n, p.d_sc, p.d_sel, p.d_bnd,
             partial, nb, tile_sums, p.method == PH_METHOD_DIRECT ? 1 : 0, p.d_flag, p.d_t_out, (float4 *)p.d_s_dat, (float4 *)p.d_t_dat,
-            p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell);
+            p.grid_mode ? p.d_cell : nullptr, p.d_s_cell, p.d_t_cell, (float *)S_zero, p.d_sticky);
+}
+
+void launch_reuse_begin(const Plan &p, hipStream_t s)
+{
+    reuse_begin_kernel<<<1, 64, 0, s>>>(p.d_sc);
 }
 
 // ---------------------------------------------------------------- validation of a learned call

@@ -230,6 +230,7 @@ size_t layout_workspace(Plan &p, char *base, bool assign)
     take(&p.d_flag, (size_t)n * sizeof(uint64_t));
     take(&p.d_sel, (size_t)n);
     take(&p.d_scan_tmp, p.scan_tmp_bytes);
+    take(&p.d_tile_sum, (size_t)((n + kSelTilePoints - 1) / kSelTilePoints) * 8);
     take(&p.d_red, kRedBytes);
     take(&p.d_t_out, (size_t)n * 4);
     take(&p.d_s_dat, (size_t)n * 4 * rs);
@@ -902,7 +903,7 @@ namespace {
 // plain threshold-rule evaluation (source rule fallback_rel, no network), the reference of a
 // validated call.
 void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s, bool timed, int slot,
-                  bool threshold_run = false)
+                  bool threshold_run = false, bool same_sets = false)
 {
     auto mark = [&](int k, hipStream_t on) {
         if (timed) PH_HIP(hipEventRecord(p.ring[slot][k], on));
@@ -913,13 +914,22 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     // |E| is read where a field rule needs it, and by the learned selector's features
     const bool need_e = p.thr.e_abs >= 0 || p.thr.e_rel >= 0;
     const float *Eu = (need_e || learned) ? absE : nullptr;
-    // the first kernel clears the call's scalars and advances the call number
-    launch_reduce_max(p, I, Eu, p.d_gen, s);
-    mark(1, s);
-    // event 2 closes the tile pass (flags, and the learned decisions made inside it)
-    launch_select(p, I, Eu, S_out, s, learned, threshold_run ? p.fallback_rel : -1.0,
-                  timed ? p.ring[slot][2] : nullptr);
-    mark(3, s);
+    if (same_sets) {
+        // the previous call's sets, tree and lists: new strengths compacted on the old flags
+        launch_reuse_begin(p, s);
+        mark(1, s);
+        mark(2, s);
+        launch_compact(p, I, S_out, s);
+        mark(3, s);
+    } else {
+        // the first kernel clears the call's scalars and advances the call number
+        launch_reduce_max(p, I, Eu, p.d_gen, s);
+        mark(1, s);
+        // event 2 closes the tile pass (flags, and the learned decisions made inside it)
+        launch_select(p, I, Eu, S_out, s, learned, threshold_run ? p.fallback_rel : -1.0,
+                      timed ? p.ring[slot][2] : nullptr);
+        mark(3, s);
+    }
     if (p.method == PH_METHOD_DIRECT) {
         for (int k = 4; k <= 7; ++k) mark(k, s);
         mark(8, s);
@@ -928,7 +938,7 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
         mark(10, s);
         return;
     }
-    build_tree(p, s);
+    if (!same_sets) build_tree(p, s);
     mark(4, s);
     // The lists and the near field run on the second stream, the V/X targets and the deepest
     // level's M2L products on the third, the upward pass and the rest of the downward pass here.
@@ -941,10 +951,10 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     PH_HIP(hipEventRecord(p.ev_fork, s));
     PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
     PH_HIP(hipStreamWaitEvent(p.side2, p.ev_fork, 0));
-    build_vtargets(p, p.side2);
+    if (!same_sets) build_vtargets(p, p.side2);
     if (!deep) PH_HIP(hipEventRecord(p.ev_vt, p.side2));
     mark(8, p.side);
-    build_lists(p, p.side);
+    if (!same_sets) build_lists(p, p.side);
     mark(9, p.side);
     fmm_near(p, p.side);
     mark(10, p.side);
@@ -970,7 +980,7 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
 }  // namespace
 
 static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s,
-                                 ph_stats *stats);
+                                 ph_stats *stats, bool same_sets = false);
 
 // One call on the plan's current workspace, with the arguments checked
 static ph_status evaluate_checked(ph_plan *plan, const void *I, const float *absE, void *S_out, void *stream,
@@ -985,7 +995,13 @@ static ph_status evaluate_checked(ph_plan *plan, const void *I, const float *abs
     if (use_ws && (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)))
         return fail(Error{PH_EINVAL, "workspace must be a 256-byte aligned device pointer"});
     std::lock_guard<std::mutex> lock(p.mu);
-    if (!use_ws) return evaluate_locked(p, I, absE, S_out, reinterpret_cast<hipStream_t>(stream), stats);
+    if (!use_ws) {
+        // the own workspace holds this call's sets once the call is enqueued
+        p.sets_ready = false;
+        const ph_status st = evaluate_locked(p, I, absE, S_out, reinterpret_cast<hipStream_t>(stream), stats);
+        p.sets_ready = (st == PH_OK || st == PH_EFALLBACK) && p.method == PH_METHOD_FMM;
+        return st;
+    }
     // the per-call arrays point into the caller's workspace for this call only
     struct Restore {
         Plan &p;
@@ -1001,6 +1017,19 @@ ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_o
     return evaluate_checked(plan, I, absE, S_out, stream, stats, nullptr, false);
 }
 
+ph_status ph_evaluate_same_sets(ph_plan *plan, const void *I, void *S_out, void *stream, ph_stats *stats)
+{
+    g_last_error.clear();
+    if (!plan) return fail(Error{PH_EINVAL, "plan is null"});
+    Plan &p = *reinterpret_cast<Plan *>(plan);
+    if (!I || !S_out) return fail(Error{PH_EINVAL, "I and S_out must be device pointers"});
+    if (p.method != PH_METHOD_FMM) return fail(Error{PH_EUNSUPPORTED, "calls on the previous sets need the FMM method"});
+    std::lock_guard<std::mutex> lock(p.mu);
+    if (!p.sets_ready)
+        return fail(Error{PH_EINVAL, "no earlier ph_evaluate on this plan's own workspace to take the sets from"});
+    return evaluate_locked(p, I, nullptr, S_out, reinterpret_cast<hipStream_t>(stream), stats, true);
+}
+
 size_t ph_evaluate_workspace_bytes(const ph_plan *plan)
 {
     return plan ? reinterpret_cast<const Plan *>(plan)->ws_bytes : 0;
@@ -1013,7 +1042,7 @@ ph_status ph_evaluate_ws(ph_plan *plan, const void *I, const float *absE, void *
 }
 
 static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void *S_out, hipStream_t s,
-                                 ph_stats *stats)
+                                 ph_stats *stats, bool same_sets)
 {
     const bool learned_plan = p.selector == PH_SEL_LEARNED;
     (void)learned_plan;
@@ -1027,7 +1056,7 @@ static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void
             p.ring_pos = (p.ring_pos + 1) % Plan::kRing;
         }
         const bool learned = p.selector == PH_SEL_LEARNED;
-        const bool validated = learned && p.validate;
+        const bool validated = learned && p.validate && !same_sets;
         if (validated) {
             // the plain FMM under the threshold rule first (into the workspace), then the
             // learned call, then the comparison that keeps one of the two
@@ -1035,7 +1064,7 @@ static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void
             enqueue_call(p, I, absE, S_out, s, timed, slot);
             launch_validate(p, S_out, p.d_sref, p.validate_tol, s);
         } else {
-            enqueue_call(p, I, absE, S_out, s, timed, slot);
+            enqueue_call(p, I, absE, S_out, s, timed, slot, false, same_sets);
         }
         PH_HIP(hipGetLastError());
         if (timed) p.ring_used[slot] = true;
@@ -1077,6 +1106,7 @@ ph_status ph_plan_set_targets(ph_plan *plan, const uint8_t *mask, int64_t n)
         std::lock_guard<std::mutex> lock(p.mu);
         PH_HIP(hipSetDevice(p.device));
         PH_HIP(hipDeviceSynchronize());  // no call still reads the old set
+        p.sets_ready = false;             // the next call selects again
         if (!mask) {
             dev_free(p.d_tmask);
             if (p.d_tmask) p.bytes_allocated -= (size_t)p.n;

@@ -317,6 +317,8 @@ struct Plan {
     // caller-supplied target set (sorted order, 1 = may be a target), or null for every point
     uint8_t *d_tmask = nullptr;
     uint8_t *d_rs_flag = nullptr;   // per sorted point: the W list was left out there (r_s > 0)
+    uint64_t *d_tile_sum = nullptr; // per selection tile: packed (sources | targets << 32) counts
+    bool sets_ready = false;        // the own workspace holds a call's sets, tree and lists
     double *d_rs_bound = nullptr;   // per box: bound of its W list's field (r_s > 0)
     size_t bytes_allocated = 0;
     size_t workspace_cap = 0;
@@ -391,6 +393,8 @@ void launch_maxima_store(const Plan &p, bool has_e, hipStream_t s);
 // for this pass (the threshold run of a validated call).
 void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hipStream_t s, bool learned,
                    double src_rel, hipEvent_t after_tiles = nullptr);
+void launch_compact(const Plan &p, const void *I, void *S_zero, hipStream_t s);
+void launch_reuse_begin(const Plan &p, hipStream_t s);
 // validated learned call: S_out (learned) against S_ref (threshold rule); S_ref replaces S_out
 // and the call is marked fallen back when their relative L2 difference exceeds tol
 void launch_validate(const Plan &p, void *S_out, const void *S_ref, double tol, hipStream_t s);
