@@ -191,12 +191,13 @@ void ph_plan_destroy(ph_plan *plan);
  *         interaction list overflowed its capacity (the lists are then cut, reads
  *         stay in bounds, S_out is not valid).  When NULL the call is fully
  *         asynchronous; its faults are reported by the next ph_plan_check().
- * The interaction lists and the near field run on a second stream the plan owns,
- * and the V/X target lists with the deepest level's M2L products on a third, both
- * forked from `stream` after the octree and joined back into it in the downward
- * pass (the third before the other levels' M2L products, the second before the
- * gathers), so before the far field (events, no host synchronisation): the call
- * stays ordered on `stream`.  Calls on one plan's own workspace must not overlap.
+ * The interaction lists and the near field run on a second stream, and the V/X
+ * target lists with the deepest level's M2L products on a third (both library-owned,
+ * shared by the plans of the device), both
+ * forked from `stream` after the octree and joined back into it (the third before
+ * the other levels' M2L products, the second's lists before the gathers and its near
+ * field before the far field; events, no host synchronisation): the call stays
+ * ordered on `stream`.  Calls on one plan's own workspace must not overlap.
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);
@@ -234,7 +235,9 @@ size_t ph_evaluate_workspace_bytes(const ph_plan *plan);
  * call number and the box tags that let the lists skip clearing.  It may be reused across
  * calls of the same plan only.  Calls with distinct workspaces may run concurrently on
  * different streams (their device work overlaps, except the list building and near field,
- * which share the plan's second and third streams and run one call after the other).
+ * which share the second and third streams and run one call after the other; those two
+ * streams belong to all plans of a device, so that several plans never hold more streams than
+ * the device has hardware queues).
  * Results are bit-identical to ph_evaluate.  Errors as ph_evaluate, plus PH_EINVAL for a
  * null or misaligned workspace.
  */

@@ -146,6 +146,20 @@ struct Mfma<double> {
 // Start of a call, by workgroup 0 of the call's first kernel (no other kernel of the call has
 // run yet, and no other workgroup of that kernel touches the scalars): clear the call's
 // scalars and, with gen, advance the call number kept on the device and store it in sc.
+// Append val to list for the lanes with pred: one atomic per wave, lanes in lane order.
+template <class V>
+__device__ __forceinline__ void wave_append(bool pred, V *__restrict__ list, int32_t *counter, V val)
+{
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
 __device__ __forceinline__ void begin_call(CallScalars *sc, int32_t *gen)
 {
     int32_t *w = reinterpret_cast<int32_t *>(sc);

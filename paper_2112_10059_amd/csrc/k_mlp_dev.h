@@ -86,6 +86,41 @@ __device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
     if (threadIdx.x == 0) L.b3 = q<BF16>(params[OFF_B3]);
 }
 
+// The same staging with every load of a thread in flight at once (KW blockDim >= NP):
+// parameter t + k blockDim goes to thread t, then to its LDS place with the rounding of
+// stage_weights (the LDS contents are identical)
+template <bool BF16, int KW>
+__device__ __forceinline__ void stage_weights_at_once(const float *__restrict__ params, MlpLds &L)
+{
+    float v[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int idx = (int)threadIdx.x + k * (int)blockDim.x;
+        v[k] = idx < NP ? params[idx] : 0.0f;
+    }
+    float *w1 = reinterpret_cast<float *>(L.w1), *w2 = reinterpret_cast<float *>(L.w2);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int idx = (int)threadIdx.x + k * (int)blockDim.x;
+        const float x = q<BF16>(v[k]);
+        if (idx < OFF_B1) {
+            const int o = idx / NIN, i = idx % NIN;
+            w1[((i >> 2) * NH + o) * 4 + (i & 3)] = x;
+        } else if (idx < OFF_W2) {
+            L.b1[idx - OFF_B1] = x;
+        } else if (idx < OFF_B2) {
+            const int u = idx - OFF_W2, o = u / NH, i = u % NH;
+            w2[((i >> 2) * NH + o) * 4 + (i & 3)] = x;
+        } else if (idx < OFF_W3) {
+            L.b2[idx - OFF_B2] = x;
+        } else if (idx < OFF_B3) {
+            L.w3[idx - OFF_W3] = x;
+        } else if (idx == OFF_B3) {
+            L.b3 = x;
+        }
+    }
+}
+
 // value of lane j (uniform j) in every lane
 __device__ __forceinline__ float lane_bcast(float v, int j)
 {
@@ -118,6 +153,50 @@ __device__ __forceinline__ float mlp_row(const float (&x)[NIN], const MlpLds &L,
     float z = L.w3[lane] * q<BF16>(gelu(a2));
     for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o);
     return z + L.b3;
+}
+
+// Up to four rows at once (x[r] for r < nr, every lane the same values): four independent
+// chains in flight, each row's operations in the order of mlp_row, so every logit equals
+// mlp_row's bit for bit.
+template <bool BF16>
+__device__ __forceinline__ void mlp_rows4(const float (&x)[4][NIN], const MlpLds &L, int lane, float (&z)[4])
+{
+    float a[4], h1[4], a2[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = L.b1[lane];
+#pragma unroll
+    for (int k4 = 0; k4 < NIN / 4; ++k4) {
+        const float4 wq = L.w1[k4 * NH + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a[r] += wq.x * q<BF16>(x[r][4 * k4 + 0]);
+            a[r] += wq.y * q<BF16>(x[r][4 * k4 + 1]);
+            a[r] += wq.z * q<BF16>(x[r][4 * k4 + 2]);
+            a[r] += wq.w * q<BF16>(x[r][4 * k4 + 3]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        h1[r] = q<BF16>(gelu(a[r]));
+        a2[r] = L.b2[lane];
+    }
+#pragma unroll 4
+    for (int j4 = 0; j4 < NH / 4; ++j4) {
+        const float4 wq = L.w2[j4 * NH + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a2[r] += wq.x * lane_bcast(h1[r], 4 * j4 + 0);
+            a2[r] += wq.y * lane_bcast(h1[r], 4 * j4 + 1);
+            a2[r] += wq.z * lane_bcast(h1[r], 4 * j4 + 2);
+            a2[r] += wq.w * lane_bcast(h1[r], 4 * j4 + 3);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float zz = L.w3[lane] * q<BF16>(gelu(a2[r]));
+        for (int o = 32; o > 0; o >>= 1) zz += __shfl_xor(zz, o);
+        z[r] = zz + L.b3;
+    }
 }
 
 // ---------------------------------------------------------------- per-leaf statistics and features

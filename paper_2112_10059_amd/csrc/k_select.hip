@@ -8,6 +8,8 @@
 // every octree box is a contiguous run in each list.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "k_common.h"
 #include "k_mlp_dev.h"
 
@@ -238,16 +240,15 @@ constexpr int kSelSpan = 64 * kSelStrips;  // points per wave in a tile
 constexpr int kSelTile = kSelWaves * kSelSpan;
 static_assert(kSelTile == kSelTilePoints, "the plan's tile table uses the same tile");
 
-// Learned decisions inside the selection pass.  The plan leaves are listed by first point
+// The learned selector, around the selection pass.  The plan leaves are listed by first point
 // (leaf_pos: first, end, plan-leaf index), and each tile knows the range of them that overlaps
-// it (tile_leaves).  The tile's I and |E| are staged in LDS with a candidate bit per point (the
-// plan's source rule); a leaf with no candidate needs nothing more.  For a candidate leaf a wave
-// takes its statistics (points outside the tile from memory), its features and the network's
-// BF16 logit: keep iff logit >= threshold; a non-finite logit keeps the leaf under the fallback
-// rule.  The decision becomes the state of the leaf's points in the tile (0 the plan's rule,
-// 1 dropped, 2 the fallback rule); a leaf that straddles two tiles is decided by both,
-// identically.  The tile whose range holds a leaf's first point records its flag, features and
-// counts for the inspection and training entry points.
+// it (tile_leaves).  The learned variant of the pass flags the sources by the plan's rule (the
+// candidates) as the plain pass does, and in addition lists every plan leaf that holds a
+// candidate (the rows), once, by the tile that holds the leaf's first point.  A second pass
+// (learned_decide_kernel) then takes the rows a wave each, all of them at once across the
+// device: statistics, features, the network's BF16 logit; keep iff logit >= threshold, else
+// the leaf's candidates lose their source flag; a non-finite logit puts the leaf under the
+// fallback rule.  The tile counts are corrected there, before the compaction reads them.
 struct LearnArgs {
     const int2 *tile_leaves;     // per tile: [first, end) in leaf_pos
     const int4 *leaf_pos;        // plan leaves by first point: (first, end, plan-leaf index, 0)
@@ -259,31 +260,15 @@ struct LearnArgs {
     float *feats;                // per plan leaf: its features (candidate leaves)
     uint32_t *leafflag;          // per plan leaf: 1 if it held a candidate in this call
     int32_t *featcnt;            // per plan leaf: candidates
+    int4 *rows;                  // the call's rows: (first, end, plan-leaf index, 0)
     int count;                   // count rows and candidates into the scalars (calls with statistics)
 };
 
-constexpr int kLearnBatch = 64;  // leaves examined per round
-
-template <class T>
-struct TileLds {
-    T I[kSelTile];
-    float E[kSelTile];
-    uint64_t cand[kSelTile / 64];  // candidate bit per point, a word per 64 points
-    uint8_t state[kSelTile];
-    mlp::MlpLds net;
-    int4 rowpos[kLearnBatch];      // the round's candidate leaves: (first, end, plan-leaf index, 0)
-    int4 rowgeo[kLearnBatch];      // and their anchor x, y, z and level
-    mlp::LeafStats rowstat[kLearnBatch];
-    float rowf[kLearnBatch][PH_MLP_NIN];
-    int32_t nrow;
-};
-
-// Is a candidate among the tile's points [a, b) (tile-relative)?
-template <class T>
-__device__ __forceinline__ bool any_cand(const TileLds<T> &S, int a, int b)
+// Is a candidate among the tile's points [a, b) (tile-relative)?  cand: a word per 64 points.
+__device__ __forceinline__ bool any_cand(const uint64_t *cand, int a, int b)
 {
     for (int q = a >> 6; q <= (b - 1) >> 6; ++q) {
-        uint64_t wq = S.cand[q];
+        uint64_t wq = cand[q];
         const int lo = q * 64;
         if (a > lo) wq &= ~0ull << (a - lo);
         if (b < lo + 64) wq &= (1ull << (b - lo)) - 1ull;
@@ -292,210 +277,74 @@ __device__ __forceinline__ bool any_cand(const TileLds<T> &S, int a, int b)
     return false;
 }
 
-// Per round of up to kLearnBatch leaves: (1) a thread per leaf finds the candidate leaves and
-// records them as rows; (2) a wave per row takes the leaf's statistics, a lane per point;
-// (3) a lane per row computes the features (FP64 logarithms, once for all rows of the round);
-// (4) a wave per row runs the network and writes the decision into the tile's point states.
-// pre: the first round's leaf records, loaded by the first threads with the tile's values.
-template <class T>
-__device__ void learned_decisions(const T *__restrict__ I, const float *__restrict__ E,
-                                  const int32_t *__restrict__ perm, int64_t n, const SelectParams &sp,
-                                  const Maxima &mx, const int32_t *__restrict__ iperm, const double *__restrict__ xyz,
-                                  const LearnArgs &la, CallScalars *__restrict__ sc, TileLds<T> &S, int2 range,
-                                  int4 pre, bool anycand)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
-    const int64_t t0 = (int64_t)blockIdx.x * kSelTile, t1 = min(n, t0 + kSelTile);
-    // a tile holding a candidate stages the weights at once (its rows need them in any case)
-    bool staged = anycand;
-    if (anycand) mlp::stage_weights<true>(la.params, S.net);
-    for (int32_t b0 = range.x; b0 < range.y; b0 += kLearnBatch) {
-        if (threadIdx.x == 0) S.nrow = 0;
-        __syncthreads();
-        for (int32_t li = b0 + (int32_t)threadIdx.x; li < min(range.y, b0 + kLearnBatch); li += blockDim.x) {
-            const int4 lp = (b0 == range.x && li - b0 < (int32_t)blockDim.x) ? pre : la.leaf_pos[li];
-            bool c;
-            if (lp.x >= t0 && lp.y <= t1) {
-                c = any_cand(S, (int)(lp.x - t0), (int)(lp.y - t0));
-            } else {  // a leaf that leaves the tile: its points from memory
-                c = false;
-                for (int32_t k = lp.x; k < lp.y && !c; ++k) c = src_rule((double)I[perm[k]], sp.src_rel, mx.imax);
-            }
-            if (c) {
-                const int r = atomicAdd(&S.nrow, 1);
-                S.rowpos[r] = lp;
-                S.rowgeo[r] = la.pinfo2[lp.z];
-            } else if (lp.x >= t0) {
-                la.leafflag[lp.z] = 0u;
-            }
-        }
-        __syncthreads();
-        const int nrow = S.nrow;
-        if (nrow == 0) continue;
-        if (!staged) {
-            mlp::stage_weights<true>(la.params, S.net);
-            staged = true;
-        }
-        // statistics, a wave per row
-        for (int j = wv; j < nrow; j += nw) {
-            const int4 lp = S.rowpos[j];
-            auto fetch = [&](int32_t k, double &v, double &e) {
-                if (k >= t0 && k < t1) {
-                    v = (double)S.I[k - t0];
-                    e = (double)S.E[k - t0];
-                } else {
-                    const int32_t o = perm[k];
-                    v = (double)I[o];
-                    e = E ? (double)E[o] : 0.0;
-                }
-            };
-            const mlp::LeafStats st = mlp::leaf_stats_wave(fetch, la.w, la.w_ref, lp.x, lp.y, sp.src_rel, mx.imax, lane);
-            if (lane == 0) S.rowstat[j] = st;
-        }
-        __syncthreads();
-        // features, a lane per row
-        if ((int)threadIdx.x < nrow) {
-            const int j = threadIdx.x;
-            mlp::FeatureRefs r;
-            r.imax = mx.imax;
-            r.emax = mx.emax;
-            r.w_ref = la.w_ref;
-            r.lo[0] = la.lo0;
-            r.lo[1] = la.lo1;
-            r.lo[2] = la.lo2;
-            r.cube = la.cube;
-            r.efeat = E && r.emax > 0.0;
-            for (int d = 0; d < 3; ++d) r.xi[d] = r.xe[d] = 0.0;
-            if (mx.imax > 0.0) {
-                const int64_t k = key_point(mx.ikey, iperm);
-                for (int d = 0; d < 3; ++d) r.xi[d] = xyz[3 * k + d];
-            }
-            if (r.efeat) {
-                const int64_t k = key_point(mx.ekey, iperm);
-                for (int d = 0; d < 3; ++d) r.xe[d] = xyz[3 * k + d];
-            }
-            const mlp::LeafStats st = S.rowstat[j];
-            const int4 lp = S.rowpos[j], g = S.rowgeo[j];
-            float fe[PH_MLP_NIN];
-            mlp::leaf_features(st, r, g.w, g.x, g.y, g.z, fe);
-#pragma unroll
-            for (int q = 0; q < PH_MLP_NIN; ++q) S.rowf[j][q] = fe[q];
-            if (lp.x >= t0) {
-#pragma unroll
-                for (int q = 0; q < PH_MLP_NIN; ++q) la.feats[(size_t)lp.z * PH_MLP_NIN + q] = fe[q];
-                la.leafflag[lp.z] = 1u;
-                la.featcnt[lp.z] = (int32_t)st.n_c;
-                if (la.count) {  // calls that report statistics: the rows and their candidates
-                    atomicAdd(&sc->n_src_base, (int32_t)st.n_c);
-                    atomicAdd(&sc->n_srcleaf, 1);
-                }
-            }
-        }
-        __syncthreads();
-        // the network, a wave per row
-        for (int j = wv; j < nrow; j += nw) {
-            float fe[PH_MLP_NIN];
-#pragma unroll
-            for (int q = 0; q < PH_MLP_NIN; ++q) fe[q] = S.rowf[j][q];
-            const float z = mlp::mlp_row<true>(fe, S.net, lane);
-            const int4 lp = S.rowpos[j];
-            const uint8_t st = !isfinite(z) ? 2 : (z >= la.threshold ? 0 : 1);
-            if (st == 2 && lp.x >= t0 && lane == 0) atomicOr(&sc->fallback, 1);
-            const int64_t a0 = max((int64_t)lp.x, t0), a1 = min((int64_t)lp.y, t1);
-            for (int64_t k = a0 + lane; k < a1; k += 64) S.state[k - t0] = st;
-        }
-        __syncthreads();
-    }
-}
-
-// The learned variant runs the tile with half the waves (eight strips each): the network's
-// registers then leave room for two workgroups per CU, and the whole grid is resident at once.
-template <bool LEARNED>
-constexpr int sel_waves() { return LEARNED ? kSelWaves / 2 : kSelWaves; }
-
 template <class T, bool LEARNED>
-__global__ __launch_bounds__(64 * sel_waves<LEARNED>(), LEARNED ? 4 : 8) void select_tiles_kernel(
+__global__ __launch_bounds__(64 * kSelWaves, 8) void select_tiles_kernel(
     const T *__restrict__ I, const float *__restrict__ E, const int32_t *__restrict__ perm, int64_t n,
     SelectParams sp, CallScalars *__restrict__ sc, const double *__restrict__ red, int red_nb, int32_t *sticky,
     const int32_t *__restrict__ iperm, const double *__restrict__ xyz, const uint8_t *__restrict__ tmask,
     uint8_t *__restrict__ sel, T *__restrict__ S_out, uint64_t *__restrict__ partial, LearnArgs la)
 {
-    constexpr int NW = sel_waves<LEARNED>(), NS = kSelTile / (64 * NW), SPAN = 64 * NS;
-    __shared__ uint64_t wsum[NW];
+    __shared__ uint64_t wsum[kSelWaves];
+    __shared__ uint64_t cand[LEARNED ? kSelTile / 64 : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile0 = (int64_t)blockIdx.x * kSelTile;
-    const int64_t base = tile0 + (int64_t)w * SPAN;
+    const int64_t base = tile0 + (int64_t)w * kSelSpan;
     // the tile's values first (they do not depend on the maxima), then the maxima from the partials
-    int32_t o[NS];
-    T v[NS];
-    float e[NS];
-    uint8_t tm[NS];
+    int32_t o[kSelStrips];
+    T v[kSelStrips];
+    float e[kSelStrips];
+    uint8_t tm[kSelStrips];
     int2 lrange = make_int2(0, 0);
     if constexpr (LEARNED) lrange = la.tile_leaves[blockIdx.x];
 #pragma unroll
-    for (int st = 0; st < NS; ++st) {
+    for (int st = 0; st < kSelStrips; ++st) {
         const int64_t k = base + st * 64 + lane;
         o[st] = k < n ? perm[k] : -1;
         tm[st] = (tmask && k < n) ? tmask[k] : 1;
     }
-    // the learned variant's first leaf records, in flight with the tile's values
+    // the learned variant's leaf records, in flight with the tile's values
     int4 lpre = make_int4(0, 0, 0, 0);
     if constexpr (LEARNED) {
         if ((int)threadIdx.x < lrange.y - lrange.x) lpre = la.leaf_pos[lrange.x + threadIdx.x];
     }
 #pragma unroll
-    for (int st = 0; st < NS; ++st) {
+    for (int st = 0; st < kSelStrips; ++st) {
         v[st] = o[st] >= 0 ? I[o[st]] : T(0);
         e[st] = (E && o[st] >= 0) ? E[o[st]] : 0.0f;
     }
     const Maxima mx = block_maxima(red, red_nb);
     const double imax = mx.imax, emax = mx.emax;
     uint64_t acc = 0;
-    if constexpr (!LEARNED) {
 #pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int64_t k = base + st * 64 + lane;
-            if (k < n) {
-                const bool src = src_rule((double)v[st], sp.src_rel, imax);
-                const bool tgt = tgt_rule(sp, e[st], E != nullptr, emax, tm[st]);
-                const uint32_t f = (src ? 1u : 0u) | (tgt ? 2u : 0u);
-                sel[k] = (uint8_t)f;
-                if (!tgt) S_out[o[st]] = T(0);
-                acc += packed_of(f);
-            }
+    for (int st = 0; st < kSelStrips; ++st) {
+        const int64_t k = base + st * 64 + lane;
+        const bool src = k < n && src_rule((double)v[st], sp.src_rel, imax);
+        if constexpr (LEARNED) {
+            const uint64_t cw = __ballot(src);
+            if (lane == 0) cand[w * kSelStrips + st] = cw;
         }
-    } else {
-        __shared__ TileLds<T> S;
-        bool anyc = false;
-        // stage the tile's values, one candidate word per strip
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int64_t k = base + st * 64 + lane;
-            const int q = (int)(k - tile0);
-            S.I[q] = v[st];
-            S.E[q] = e[st];
-            S.state[q] = 0;
-            const uint64_t cw = __ballot(k < n && src_rule((double)v[st], sp.src_rel, imax));
-            if (lane == 0) S.cand[w * NS + st] = cw;
-            anyc = anyc || cw != 0ull;
+        if (k < n) {
+            const bool tgt = tgt_rule(sp, e[st], E != nullptr, emax, tm[st]);
+            const uint32_t f = (src ? 1u : 0u) | (tgt ? 2u : 0u);
+            sel[k] = (uint8_t)f;
+            if (!tgt) S_out[o[st]] = T(0);
+            acc += packed_of(f);
         }
-        const bool anycand = __syncthreads_or(anyc ? 1 : 0) != 0;
-        learned_decisions(I, E, perm, n, sp, mx, iperm, xyz, la, sc, S, lrange, lpre, anycand);
-        // the points again from LDS (nothing of the staging loop stays live across the decisions)
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int64_t k = base + st * 64 + lane;
-            if (k < n) {
-                const int q = (int)(k - tile0);
-                const uint32_t state = S.state[q];
-                const bool src = state == 2u ? src_rule((double)S.I[q], sp.fallback_rel, imax)
-                                             : (state == 0u && ((S.cand[q >> 6] >> (q & 63)) & 1ull));
-                const bool tgt = tgt_rule(sp, S.E[q], E != nullptr, emax, tmask ? tmask[k] : 1);
-                const uint32_t f = (src ? 1u : 0u) | (tgt ? 2u : 0u);
-                sel[k] = (uint8_t)f;
-                if (!tgt) S_out[perm[k]] = T(0);
-                acc += packed_of(f);
+    }
+    if constexpr (LEARNED) {
+        // the rows: leaves whose first point is in this tile and that hold a candidate
+        __syncthreads();
+        const int64_t t1 = min(n, tile0 + kSelTile);
+        for (int32_t li = lrange.x + (int32_t)threadIdx.x; li < lrange.y; li += (int32_t)blockDim.x) {
+            const int4 lp = li - lrange.x < (int32_t)blockDim.x ? lpre : la.leaf_pos[li];
+            bool c = false;
+            if (lp.x >= tile0) {
+                c = any_cand(cand, (int)(lp.x - tile0), (int)(min((int64_t)lp.y, t1) - tile0));
+                // a leaf that runs into the next tile: the rest of its points from memory
+                for (int32_t k = (int32_t)t1; k < lp.y && !c; ++k) c = src_rule((double)I[perm[k]], sp.src_rel, imax);
+                la.leafflag[lp.z] = c ? 1u : 0u;
             }
+            wave_append(c, la.rows, &sc->n_rows, lp);
         }
     }
     // workgroup 0 publishes the maxima for the later kernels (after its own points)
@@ -505,8 +354,120 @@ __global__ __launch_bounds__(64 * sel_waves<LEARNED>(), LEARNED ? 4 : 8) void se
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t t = 0;
-        for (int q = 0; q < NW; ++q) t += wsum[q];
+        for (int q = 0; q < kSelWaves; ++q) t += wsum[q];
         partial[blockIdx.x] = t;
+    }
+}
+
+// The decisions on the rows, a wave per row over the whole device (the rows of a call are few
+// and independent).  The leaf's statistics read I and |E| through the permutation, with the
+// same function as the training entry points, so the features are those the network was
+// trained on, bit for bit; the logit is mlp_row's.  A dropped leaf's candidates lose their
+// source flag, a leaf under the fallback rule gets the flags of that rule, and the tiles'
+// source counts follow (one atomic per tile the leaf touches).
+constexpr int kDecideWaves = 4;
+
+template <class T>
+__global__ __launch_bounds__(64 * kDecideWaves) void learned_decide_kernel(
+    const T *__restrict__ I, const float *__restrict__ E, const int32_t *__restrict__ perm, SelectParams sp,
+    CallScalars *__restrict__ sc, LearnArgs la, uint8_t *__restrict__ sel, uint64_t *__restrict__ partial)
+{
+    __shared__ mlp::MlpLds net;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t nrows = sc->n_rows;
+    if ((int32_t)blockIdx.x * kDecideWaves >= nrows) return;  // the whole workgroup: no row for it
+    // the wave's first row: its record, geometry and the values of its first 64 points, loaded
+    // before the weights so that both are in flight together
+    int32_t row = (int32_t)blockIdx.x * kDecideWaves + wv;
+    int4 lp = make_int4(0, 0, 0, 0), g = make_int4(0, 0, 0, 0);
+    double pv = 0.0, pe = 0.0;
+    if (row < nrows) {
+        lp = la.rows[row];
+        g = la.pinfo2[lp.z];
+        const int32_t k = lp.x + lane;
+        if (k < lp.y) {
+            const int32_t o = perm[k];
+            pv = (double)I[o];
+            pe = E ? (double)E[o] : 0.0;
+        }
+    }
+    constexpr int kW = (PH_MLP_NPARAM + 64 * kDecideWaves - 1) / (64 * kDecideWaves);
+    mlp::stage_weights_at_once<true, kW>(la.params, net);
+    mlp::FeatureRefs r;
+    r.imax = sc->imax;
+    r.emax = sc->emax;
+    r.w_ref = la.w_ref;
+    r.lo[0] = la.lo0;
+    r.lo[1] = la.lo1;
+    r.lo[2] = la.lo2;
+    r.cube = la.cube;
+    r.efeat = E && r.emax > 0.0;
+    for (int d = 0; d < 3; ++d) {
+        r.xi[d] = sc->imax_xyz[d];
+        r.xe[d] = sc->emax_xyz[d];
+    }
+    __syncthreads();
+    bool first = true;
+    for (; row < nrows; row += (int32_t)gridDim.x * kDecideWaves) {
+        if (!first) {
+            lp = la.rows[row];
+            g = la.pinfo2[lp.z];
+        }
+        const bool pre = first;
+        first = false;
+        auto fetch = [&](int32_t k, double &v, double &e) {
+            if (pre && k < lp.x + 64) {  // this lane's prefetched point
+                v = pv;
+                e = pe;
+                return;
+            }
+            const int32_t o = perm[k];
+            v = (double)I[o];
+            e = E ? (double)E[o] : 0.0;
+        };
+        const mlp::LeafStats st = mlp::leaf_stats_wave(fetch, la.w, la.w_ref, lp.x, lp.y, sp.src_rel, r.imax, lane);
+        float fe[PH_MLP_NIN];
+        mlp::leaf_features(st, r, g.w, g.x, g.y, g.z, fe);
+        if (lane < PH_MLP_NIN) {
+            float f = fe[0];
+#pragma unroll
+            for (int q = 1; q < PH_MLP_NIN; ++q) f = lane == q ? fe[q] : f;
+            la.feats[(size_t)lp.z * PH_MLP_NIN + lane] = f;
+        }
+        if (lane == 0) {
+            la.featcnt[lp.z] = (int32_t)st.n_c;
+            if (la.count) {  // calls that report statistics: the rows and their candidates
+                atomicAdd(&sc->n_src_base, (int32_t)st.n_c);
+                atomicAdd(&sc->n_srcleaf, 1);
+            }
+        }
+        const float z = mlp::mlp_row<true>(fe, net, lane);
+        if (isfinite(z) && z >= la.threshold) continue;  // kept: the flags stand
+        const bool fb = !isfinite(z);
+        if (fb && lane == 0) atomicOr(&sc->fallback, 1);
+        // new source flags on the leaf's points; the change of each tile's count (a leaf touches
+        // at most two tiles: it holds fewer points than a tile)
+        const int64_t tA = (int64_t)lp.x / kSelTile;
+        int32_t dA = 0, dB = 0;
+        for (int32_t k = lp.x + lane; k < lp.y; k += 64) {
+            const uint32_t f = sel[k];
+            const uint32_t was = f & 1u;
+            const uint32_t now = fb ? (src_rule((double)I[perm[k]], sp.fallback_rel, r.imax) ? 1u : 0u) : 0u;
+            if (was == now) continue;
+            sel[k] = (uint8_t)((f & ~1u) | now);
+            const int32_t d = (int32_t)now - (int32_t)was;
+            if ((int64_t)k / kSelTile == tA) dA += d;
+            else dB += d;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            dA += __shfl_xor(dA, off);
+            dB += __shfl_xor(dB, off);
+        }
+        if (lane == 0) {
+            // the count sits in the low word of the packed value, which stays >= 0
+            if (dA) atomicAdd((unsigned long long *)&partial[tA], (unsigned long long)(int64_t)dA);
+            if (dB) atomicAdd((unsigned long long *)&partial[tA + 1], (unsigned long long)(int64_t)dB);
+        }
     }
 }
 
@@ -703,9 +664,10 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
         la.feats = p.d_feat;
         la.leafflag = p.d_leafflag;
         la.featcnt = p.d_feat_cnt;
+        la.rows = p.d_rows;
         la.count = p.count_work ? 1 : 0;
     }
-    const unsigned g = (unsigned)nb, bs = 64 * (learned ? sel_waves<true>() : sel_waves<false>());
+    const unsigned g = (unsigned)nb, bs = 64 * kSelWaves;
     const int rnb = reduce_blocks(p.n);
     if (p.precision == PH_FP64) {
         if (learned)
@@ -720,6 +682,16 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
         else
             select_tiles_kernel<float, false><<<g, bs, 0, s>>>((const float *)I, E, p.d_perm, p.n, sp, p.d_sc, p.d_red, rnb, p.d_sticky, p.d_iperm, p.d_xyz, p.d_tmask,
                                                                p.d_sel, (float *)S_out, partial, la);
+    }
+    if (learned) {
+        // the rows' decisions: a wave per row; workgroups beyond the call's rows return at once
+        const unsigned gd = (unsigned)std::max<int64_t>(1, std::min<int64_t>((p.n_pleaf + kDecideWaves - 1) / kDecideWaves, 1024));
+        if (p.precision == PH_FP64)
+            learned_decide_kernel<double><<<gd, 64 * kDecideWaves, 0, s>>>((const double *)I, E, p.d_perm, sp, p.d_sc, la,
+                                                                          p.d_sel, partial);
+        else
+            learned_decide_kernel<float><<<gd, 64 * kDecideWaves, 0, s>>>((const float *)I, E, p.d_perm, sp, p.d_sc, la,
+                                                                         p.d_sel, partial);
     }
     if (after_tiles) PH_HIP(hipEventRecord(after_tiles, s));
     // up to 2048 tiles the compaction adds up the earlier tiles' sums itself; beyond, one

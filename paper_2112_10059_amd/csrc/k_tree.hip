@@ -34,20 +34,6 @@ struct LevelInfo {
     int32_t depth;                 // deepest level
 };
 
-// Append val to list for the lanes with pred: one atomic per wave, lanes in lane order.
-template <class V>
-__device__ __forceinline__ void wave_append(bool pred, V *__restrict__ list, int32_t *counter, V val)
-{
-    const uint64_t m = __ballot(pred);
-    if (m == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
-    base = __shfl(base, leader);
-    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
-}
-
 // Slot of each lane with pred in a list whose length is *counter: one atomic per wave, lanes in
 // lane order; -1 for the other lanes.
 __device__ __forceinline__ int32_t wave_slot(bool pred, int32_t *counter)

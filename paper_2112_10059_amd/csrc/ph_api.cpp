@@ -269,6 +269,7 @@ size_t layout_workspace(Plan &p, char *base, bool assign)
     take(&p.d_feat, (size_t)NL * 8 * 4);
     take(&p.d_feat_cnt, (size_t)NL * 4);
     take(&p.d_leafscan, (size_t)(NL + 1) * 4);
+    take(&p.d_rows, (size_t)NL * sizeof(int4));
     take(&p.d_row_box, (size_t)NL * 4);
     take(&p.d_row_feat, (size_t)NL * 8 * 4);
     take(&p.d_leafflag, (size_t)(NL + 1) * 4);
@@ -294,6 +295,48 @@ void alloc_workspace(Plan &p)
         PH_HIP(hipMemcpy(p.d_sel_params, p.sel_weights.data(), PH_MLP_NPARAM * 4, hipMemcpyHostToDevice));
 }
 
+// The second and third streams of the plans on one device, shared by them all (default
+// priority).  A process with several plans would otherwise hold more streams than the device
+// has hardware queues, and streams that share a queue run one after the other.  Calls on
+// different plans enqueue their work on these streams one call at a time (side_mu).
+struct SideStreams {
+    hipStream_t side = nullptr, side2 = nullptr;
+    int refs = 0;
+    std::mutex enqueue;  // held while a call enqueues its work
+};
+static std::mutex g_side_mu;
+static std::map<int, SideStreams> g_side;
+
+static SideStreams &acquire_side_streams(int device)
+{
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    SideStreams &ss = g_side[device];
+    if (ss.refs == 0) {
+        PH_HIP(hipStreamCreateWithFlags(&ss.side, hipStreamNonBlocking));
+        PH_HIP(hipStreamCreateWithFlags(&ss.side2, hipStreamNonBlocking));
+    }
+    ++ss.refs;
+    return ss;
+}
+
+static void release_side_streams(int device)
+{
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    auto it = g_side.find(device);
+    if (it == g_side.end()) return;
+    if (--it->second.refs == 0) {
+        (void)hipStreamDestroy(it->second.side);
+        (void)hipStreamDestroy(it->second.side2);
+        g_side.erase(it);
+    }
+}
+
+std::mutex &side_enqueue_mutex(int device)
+{
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    return g_side[device].enqueue;
+}
+
 void free_plan(Plan *p)
 {
     if (!p) return;
@@ -309,10 +352,9 @@ void free_plan(Plan *p)
     if (p->events_ready)
         for (auto &set : p->ring)
             for (auto &e : set) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_vt, p->ev_p2m, p->ev_m2l})
+    for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_lists, p->ev_vt, p->ev_p2m, p->ev_m2l})
         if (e) (void)hipEventDestroy(e);
-    if (p->side) (void)hipStreamDestroy(p->side);
-    if (p->side2) (void)hipStreamDestroy(p->side2);
+    if (p->side) release_side_streams(p->device);
     for (void *q : ptrs) dev_free(q);
     delete p;
 }
@@ -781,16 +823,20 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     for (auto &set : p.ring)
         for (auto &e : set) PH_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     p.events_ready = true;
-    // second and third streams (default priority) and their ordering events.  The events order
+    // second and third streams (shared by the device's plans) and their ordering events.  The events order
     // kernels of one device only: every kernel's completion already makes its writes visible to
     // later kernels on the device, so a record needs no system-scope fence (host visibility)
     constexpr unsigned kSyncEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
-    PH_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
-    PH_HIP(hipStreamCreateWithFlags(&p.side2, hipStreamNonBlocking));
+    {
+        SideStreams &ss = acquire_side_streams(p.device);
+        p.side = ss.side;
+        p.side2 = ss.side2;
+    }
     PH_HIP(hipEventCreateWithFlags(&p.ev_p2m, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_m2l, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_fork, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_join, kSyncEventFlags));
+    PH_HIP(hipEventCreateWithFlags(&p.ev_lists, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_vt, kSyncEventFlags));
 }
 
@@ -942,13 +988,16 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(4, s);
     // The lists and the near field run on the second stream, the V/X targets and the deepest
     // level's M2L products on the third, the upward pass and the rest of the downward pass here.
-    // A wait on an event still pending costs the host about as much as several launches, so
-    // each stream's last event covers what precedes it there: the M2L levels here wait for the
-    // deepest level's products (which follow the V/X targets), the gathers for the near field
-    // (which follows the lists), and the far-field kernels, which combine both fields into the
-    // output, come after the gathers.
+    // A wait on an event still pending costs the host several launches' time, so each wait
+    // stands for everything before its event on that stream: the M2L levels here wait for the
+    // deepest level's products (which follow the V/X targets), the gathers for the lists (the
+    // near field runs on beside the gathers and the L2L step), and the far-field kernels, which
+    // add the near field into the output, for the near field.  The leaf densities are enqueued
+    // here before the other streams' work, so that the host reaches them early.
     const bool deep = p.y_all_levels && p.max_depth >= 2;
     PH_HIP(hipEventRecord(p.ev_fork, s));
+    fmm_p2m(p, s);
+    if (deep) PH_HIP(hipEventRecord(p.ev_p2m, s));
     PH_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
     PH_HIP(hipStreamWaitEvent(p.side2, p.ev_fork, 0));
     if (!same_sets) build_vtargets(p, p.side2);
@@ -956,22 +1005,22 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(8, p.side);
     if (!same_sets) build_lists(p, p.side);
     mark(9, p.side);
+    PH_HIP(hipEventRecord(p.ev_lists, p.side));
     fmm_near(p, p.side);
     mark(10, p.side);
     PH_HIP(hipEventRecord(p.ev_join, p.side));
-    // the leaf densities, then the deepest level's M2L products on the third stream while the
-    // M2M chain runs here
-    fmm_p2m(p, s);
+    // the deepest level's M2L products on the third stream (after the leaf densities) while
+    // the M2M chain runs here
     if (deep) {
-        PH_HIP(hipEventRecord(p.ev_p2m, s));
         PH_HIP(hipStreamWaitEvent(p.side2, p.ev_p2m, 0));
         fmm_m2l_deepest(p, p.side2);
         PH_HIP(hipEventRecord(p.ev_m2l, p.side2));
     }
     fmm_m2m(p, s);
     mark(5, s);
-    fmm_downward(p, s, deep ? p.ev_m2l : p.ev_vt, p.ev_join);
+    fmm_downward(p, s, deep ? p.ev_m2l : p.ev_vt, p.ev_lists);
     mark(6, s);
+    PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));  // the near field, added by the far-field kernels
     // far field at the targets (every leaf kernel here, after the gathers and so after the near field)
     fmm_leaf(p, S_out, s, s);
     mark(7, s);
@@ -1057,6 +1106,8 @@ static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void
         }
         const bool learned = p.selector == PH_SEL_LEARNED;
         const bool validated = learned && p.validate && !same_sets;
+        // the side streams are shared with the other plans of the device: one call's work at a time
+        std::lock_guard<std::mutex> side_lock(side_enqueue_mutex(p.device));
         if (validated) {
             // the plain FMM under the threshold rule first (into the workspace), then the
             // learned call, then the comparison that keeps one of the two

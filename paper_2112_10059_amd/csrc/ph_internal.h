@@ -64,6 +64,7 @@ struct CallScalars {
     int32_t fallback;                   // learned selector fell back to the threshold rule
     int32_t n_srcleaf;                  // selector rows: plan leaves holding candidate sources
     int32_t n_src_base;                 // candidate sources of the learned decisions (kept + dropped)
+    int32_t n_rows;                     // learned selector: rows listed by the selection pass
     int32_t gen;                        // number of the call (never 0): V/X target tags
     uint64_t packed_total;              // selected (sources | targets << 32)
     uint64_t emax_key;                  // |E| bits << 32 | ~caller index of the largest |E|
@@ -238,6 +239,7 @@ struct Plan {
     int4 *d_pinfo = nullptr;           // per plan leaf: box, first point, end, 0
     int4 *d_pinfo2 = nullptr;          // per plan leaf: anchor x, y, z, level
     uint32_t *d_leafscan = nullptr; // per plan leaf: candidate flag, scanned by the row compaction
+    int4 *d_rows = nullptr;         // learned selector: the call's rows (first, end, plan leaf, 0)
     int32_t *d_row_box = nullptr;   // compacted rows (training entry points): plan-leaf box ids
     float *d_row_feat = nullptr;    // and their features
     int2 *d_tile_leaves = nullptr;  // per selection tile (4096 sorted points): its plan leaves in d_leaf_pos
@@ -291,12 +293,12 @@ struct Plan {
     bool events_ready = false;
     // the interaction lists and the near field run on a second stream, the V/X targets, offset
     // masks and deepest level's M2L products on a third, both forked from the caller's stream
-    // after the tree (ev_fork); the gathers wait for the near field (ev_join, after the lists),
-    // the other levels' M2L products for the deepest level's (ev_m2l, after the offset masks;
-    // ev_vt when that level runs with the others)
+    // after the tree (ev_fork); the gathers wait for the lists (ev_lists), the far field for
+    // the near field (ev_join), the other levels' M2L products for the deepest level's (ev_m2l,
+    // after the offset masks; ev_vt when that level runs with the others)
     hipStream_t side = nullptr;
     hipStream_t side2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_lists = nullptr;
     hipEvent_t ev_vt = nullptr;                     // V/X targets and M2L offset masks known
     hipEvent_t ev_p2m = nullptr, ev_m2l = nullptr;  // leaf densities known (main); deepest M2L done
     // check values of the leaves of levels >= 3 in one launch from the level-local parts of their
