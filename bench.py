@@ -12,9 +12,9 @@ and the scatter to caller order, with I and |E| already resident in HBM.
 
 The printed JSON line carries targets/s (null unless the relative L2 error on
 sampled targets is within 1e-3 against the FP64 oracle, both on the same source
-set and against all sources), the roofline of the selection pass (the largest
-kernel of a call: one launch, timed by hipEvents on its stream inside the timed
-region), the FP64 oracle timed on the host cores on a bounded sample, the
+set and against all sources), the roofline of the M2L products (the kernel with
+the largest time per call: two launches, timed by hipEvents on their streams
+inside the timed region), the FP64 oracle timed on the host cores on a bounded sample, the
 paper's threshold rule (tau_s = 1e-4) on the same field, and the plain FP64 FMM
 (all points sources and targets, no adaptivity) on the same grid for the
 speed-up ratio.
@@ -149,6 +149,22 @@ def main():
     log(f"learned fp32: {ms:.4f} ms/step ({host['launch']}), {value:.4e} targets/s; host enqueue "
         f"{host['enqueue_ms_per_call']:.4f} ms/call; phases {phases}")
     roof = roofline(phases, st, wl.n)
+    # the second evaluation of a time step on the same sets (tree and lists of the call before)
+    out2 = torch.empty(wl.n, dtype=torch.float32, device=dev)
+    plan.evaluate(I, E, out=out2)
+    for _ in range(args.warmup):
+        plan.evaluate(I, out=out2, same_sets=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.evaluate(I, out=out2, same_sets=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_same = e0.elapsed_time(e1) / args.steps
+    same_sets = {"ms_per_step": ms_same, "targets_per_s": n_tgt / (ms_same * 1e-3),
+                 "bitwise_equal_to_full_call": bool(torch.equal(out2.view(torch.int32), S.view(torch.int32)))}
+    log(f"same sets: {same_sets}")
     perm = plan.debug_fetch("perm")
     smask = np.zeros(wl.n, dtype=bool)
     smask[perm[plan.debug_fetch("src")]] = True
@@ -257,6 +273,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "threshold_fp32": threshold,
+        "same_sets_fp32": same_sets,
         "plain_fp64_fmm": plain,
     }
     print(json.dumps(line), flush=True)
@@ -292,50 +309,63 @@ def tiles_work(st, n):
             "flops": 9.3e3 * float(st.get("n_leaves", 0))}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "select_tiles_streamer128_fp32_learned_traffic.txt")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "m2l_pipe_streamer128_fp32_learned_counters.txt")
 
 
-def tiles_kernel_source_hash():
-    """SHA-256 of the selection pass's source: k_select.hip up to the compaction pass, the
-    selector's device header and k_common.h."""
+def m2l_kernel_source_hash():
+    """SHA-256 of the M2L product's source: the pipelined kernel and its helpers in k_m2l.hip
+    (everything before the composite L2L kernel) and k_common.h."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2112_10059_amd", "csrc")
-    text = open(os.path.join(csrc, "k_select.hip")).read()
-    h = hashlib.sha256(text[:text.index("// Pass two:")].encode())
-    for f in ("k_mlp_dev.h", "k_common.h"):
-        h.update(open(os.path.join(csrc, f)).read().encode())
+    text = open(os.path.join(csrc, "k_m2l.hip")).read()
+    h = hashlib.sha256(text[:text.index("// Check values of the target leaves of levels 3")].encode())
+    h.update(open(os.path.join(csrc, "k_common.h")).read().encode())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the selection pass from the committed counter summary, or None
-    when that summary is missing or was taken on a different version of the kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_counters():
+    """Per call of the M2L product launches, from the committed counter summary: HBM bytes
+    (FETCH_SIZE + WRITE_SIZE, calibrated) and executed matrix-core FLOPs, or None when that
+    summary is missing or was taken on a different version of the kernels."""
+    if not os.path.exists(COUNTER_FILE):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(COUNTER_FILE):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != tiles_kernel_source_hash():
+    if vals.get("source_sha256") != m2l_kernel_source_hash():
         return None
-    return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    return {"traffic": float(vals["fetch_bytes_per_call"]) + float(vals["write_bytes_per_call"]),
+            "executed_flops": float(vals["mfma_flops_per_call"])}
 
 
 def roofline(phases, st, n):
-    """Roofline of the selection pass (flags of every point with the learned decisions made
-    inside it), the largest kernel of a learned call.
+    """Roofline of the M2L products (the two launches per call: the deepest level on the third
+    stream, the other levels on the caller's), the kernel with the largest time per call.
 
-    Its phase holds exactly one launch on the caller's stream, so the per-call event time of
-    that phase is the kernel's average duration over the recorded calls.
+    Algorithmic work: 2 n_lam^2 FLOPs per V-list pair (work counter m2l_pairs), the products the
+    method needs; the launches also run the unused offsets of a 64-box column tile that some
+    box of the tile needs (executed_flops, from the matrix-core counters).  Time: the phase
+    events bracket exactly those two launches on their streams, summed per call over the
+    recorded calls.  The selection pass (HBM-bound) is reported beside it.
     """
+    nl = 64  # q = 4
+    flops = 2.0 * nl * nl * float(st["work"]["m2l_pairs"])
+    sec = phases["m2l"] * 1e-3
+    tf = flops / sec / 1e12
+    r = {"bound": "mfma", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS}
+    mc = measured_counters()
+    r.update({"traffic": mc["traffic"] if mc else None,
+              "kernel": "m2l_pipe_kernel (M2L products of every level, FP32 matrix cores; two launches per call)",
+              "avg_ms": phases["m2l"], "algorithmic_flops": flops,
+              "executed_flops": mc["executed_flops"] if mc else None})
     tw = tiles_work(st, n)
-    sec = phases["flags"] * 1e-3
-    gb = tw["bytes"] / sec / 1e9
-    r = {"bound": "hbm", "achieved": gb, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gb / PEAK_HBM_GBS}
-    r.update({"traffic": measured_traffic(),
-              "kernel": "select_tiles_kernel<float, true> (source/target flags of every point, learned leaf decisions)",
-              "avg_ms": phases["flags"], "algorithmic_bytes": tw["bytes"], "algorithmic_flops": tw["flops"]})
+    gb = tw["bytes"] / (phases["flags"] * 1e-3) / 1e9
+    r["selection_pass"] = {"bound": "hbm", "achieved": gb, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": gb / PEAK_HBM_GBS, "avg_ms": phases["flags"],
+                           "algorithmic_bytes": tw["bytes"],
+                           "kernel": "select_tiles_kernel (flags of every point; learned: with the rows list)"}
     return r
 
 

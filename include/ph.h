@@ -280,12 +280,15 @@ ph_status ph_plan_set_graph(ph_plan *plan, int enable);
  * Per-phase device time.  ms_sum (host, PH_NPHASES doubles, nullable) receives the
  * summed hipEvent time of every call recorded since the previous query, per phase:
  *   0 maxima of I and |E|
- *   1 selection flags, one pass over the points (with the learned selector: its rows,
- *     features, network and decisions, made inside that pass)
- *   2 compaction of the selected points   3 octree        4 interaction lists
+ *   1 selection flags, one pass over the points (with the learned selector, the list
+ *     of its rows too)
+ *   2 the learned selector's decisions (learned plans) and the compaction of the
+ *     selected points                     3 octree        4 interaction lists
  *   5 upward pass (P2M, M2M)   6 downward pass (M2L, L2L, P2L; waits for the lists)
  *   7 far field at the targets (L2P, M2P, own cell) and the output (waits for 8)
  *   8 near field (P2P), or the whole direct sum
+ *   9 the M2L product launches alone (the deepest level's on the third stream plus the
+ *     others' on the caller's; their events bracket just those launches)
  * Phases 4 and 8 run on the plan's second stream beside phases 5-7, so their
  * times overlap those; the V/X target lists and the deepest level's M2L products
  * run on a third stream (not timed apart: their time shows in phases 5 and 6).

@@ -281,7 +281,7 @@ class Plan:
         """Later evaluate() calls without stats run as one replayed HIP graph (per set of buffers)."""
         _check(_lib.ph_plan_set_graph(self._h, 1 if enable else 0))
 
-    PHASES = ("reduce", "flags", "compact", "tree", "lists", "upward", "downward", "leaf", "near")
+    PHASES = ("reduce", "flags", "compact", "tree", "lists", "upward", "downward", "leaf", "near", "m2l")
 
     def phase_times(self, record: int = -1):
         """Summed per-phase device ms since the last query, and the number of calls."""

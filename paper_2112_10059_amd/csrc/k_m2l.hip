@@ -809,7 +809,8 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
 }
 
 template <class T>
-void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready)
+void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready, hipEvent_t m2l_begin,
+                    hipEvent_t m2l_end)
 {
     FmmArgs<T> a = make_args<T>(p);
     const int nl = p.n_lam;
@@ -829,7 +830,12 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lis
                                    (int64_t)l * M * p.k_pad, p.y_lvl_col[l], p.m2l_tile_base[l]};
             tiles += (p.level_cap[l] + kTile - 1) / kTile;
         }
+        if (m2l_begin) PH_HIP(hipEventRecord(m2l_begin, s));
         m2l_product<T>(p, sg, tiles, s);
+        if (m2l_end) PH_HIP(hipEventRecord(m2l_end, s));
+    } else if (m2l_begin) {
+        PH_HIP(hipEventRecord(m2l_begin, s));
+        PH_HIP(hipEventRecord(m2l_end, s));
     }
     PH_HIP(hipStreamWaitEvent(s, lists_ready, 0));  // the gathers read the X and V/X target lists
     // level-local parts (V and X lists) of every level: no dependence between levels
@@ -952,10 +958,11 @@ bool fmm_m2l_deepest(Plan &p, hipStream_t s)
     return true;
 }
 
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready)
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready, hipEvent_t m2l_begin,
+                  hipEvent_t m2l_end)
 {
-    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, m2l_ready, lists_ready);
-    else fmm_downward_t<float>(p, s, m2l_ready, lists_ready);
+    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, m2l_ready, lists_ready, m2l_begin, m2l_end);
+    else fmm_downward_t<float>(p, s, m2l_ready, lists_ready, m2l_begin, m2l_end);
 }
 
 void fmm_m2m_level(Plan &p, int l, hipStream_t s)

@@ -683,6 +683,7 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
             select_tiles_kernel<float, false><<<g, bs, 0, s>>>((const float *)I, E, p.d_perm, p.n, sp, p.d_sc, p.d_red, rnb, p.d_sticky, p.d_iperm, p.d_xyz, p.d_tmask,
                                                                p.d_sel, (float *)S_out, partial, la);
     }
+    if (after_tiles) PH_HIP(hipEventRecord(after_tiles, s));
     if (learned) {
         // the rows' decisions: a wave per row; workgroups beyond the call's rows return at once
         const unsigned gd = (unsigned)std::max<int64_t>(1, std::min<int64_t>((p.n_pleaf + kDecideWaves - 1) / kDecideWaves, 1024));
@@ -693,7 +694,6 @@ void launch_select(const Plan &p, const void *I, const float *E, void *S_out, hi
             learned_decide_kernel<float><<<gd, 64 * kDecideWaves, 0, s>>>((const float *)I, E, p.d_perm, sp, p.d_sc, la,
                                                                          p.d_sel, partial);
     }
-    if (after_tiles) PH_HIP(hipEventRecord(after_tiles, s));
     // up to 2048 tiles the compaction adds up the earlier tiles' sums itself; beyond, one
     // workgroup scans them first (in place: a call on the same sets reads the scan)
     if (nb > 2048) scan_tile_sums_u64(partial, nb, &p.d_sc->packed_total, s);

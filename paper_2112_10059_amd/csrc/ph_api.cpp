@@ -917,7 +917,7 @@ static void fetch_scalars(Plan &p, hipStream_t s)
 }
 
 // Phase boundaries recorded per call (events 0..9): 0 start, 1 maxima reduced,
-// 2 selection flags (and learned decisions) done, 3 compaction done, 4 tree done, 5 lists done,
+// 2 selection flags done, 3 learned decisions and compaction done, 4 tree done, 5 lists done,
 // 6 upward done, 7 downward done, 8 far field at the targets done, 9 near field (or
 // direct sum) done.
 // Event k of a slot: 0..7 on the caller's stream (start, then the ends of reduce, selector,
@@ -928,6 +928,12 @@ static float phase_ms(Plan &p, int slot, int k)
     static const int from[9] = {0, 1, 2, 3, 8, 4, 5, 6, 9};
     static const int to[9] = {1, 2, 3, 4, 9, 5, 6, 7, 10};
     float ms = 0;
+    if (k == 9) {  // the M2L product launches: the deepest level's (third stream) and the others'
+        float a = 0, b = 0;
+        PH_HIP(hipEventElapsedTime(&a, p.ring[slot][11], p.ring[slot][12]));
+        PH_HIP(hipEventElapsedTime(&b, p.ring[slot][13], p.ring[slot][14]));
+        return a + b;
+    }
     PH_HIP(hipEventElapsedTime(&ms, p.ring[slot][from[k]], p.ring[slot][to[k]]));
     return ms;
 }
@@ -937,7 +943,7 @@ static void harvest_slot(Plan &p, int slot)
     if (!p.ring_used[slot]) return;
     PH_HIP(hipEventSynchronize(p.ring[slot][7]));
     PH_HIP(hipEventSynchronize(p.ring[slot][10]));
-    for (int k = 0; k < 9; ++k) p.phase_sum[k] += phase_ms(p, slot, k);
+    for (int k = 0; k < 10; ++k) p.phase_sum[k] += phase_ms(p, slot, k);
     p.phase_calls += 1;
     p.ring_used[slot] = false;
 }
@@ -971,7 +977,7 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
         // the first kernel clears the call's scalars and advances the call number
         launch_reduce_max(p, I, Eu, p.d_gen, s);
         mark(1, s);
-        // event 2 closes the tile pass (flags, and the learned decisions made inside it)
+        // event 2 closes the tile pass (flags, and the learned selector's rows)
         launch_select(p, I, Eu, S_out, s, learned, threshold_run ? p.fallback_rel : -1.0,
                       timed ? p.ring[slot][2] : nullptr);
         mark(3, s);
@@ -982,6 +988,7 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
         mark(9, s);
         run_direct(p, S_out, s);
         mark(10, s);
+        for (int k = 11; k <= 14; ++k) mark(k, s);
         return;
     }
     if (!same_sets) build_tree(p, s);
@@ -1013,12 +1020,18 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     // the M2M chain runs here
     if (deep) {
         PH_HIP(hipStreamWaitEvent(p.side2, p.ev_p2m, 0));
+        mark(11, p.side2);
         fmm_m2l_deepest(p, p.side2);
+        mark(12, p.side2);
         PH_HIP(hipEventRecord(p.ev_m2l, p.side2));
+    } else {
+        mark(11, p.side2);
+        mark(12, p.side2);
     }
     fmm_m2m(p, s);
     mark(5, s);
-    fmm_downward(p, s, deep ? p.ev_m2l : p.ev_vt, p.ev_lists);
+    fmm_downward(p, s, deep ? p.ev_m2l : p.ev_vt, p.ev_lists, timed ? p.ring[slot][13] : nullptr,
+                 timed ? p.ring[slot][14] : nullptr);
     mark(6, s);
     PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));  // the near field, added by the far-field kernels
     // far field at the targets (every leaf kernel here, after the gathers and so after the near field)
@@ -1137,7 +1150,7 @@ static ph_status evaluate_locked(Plan &p, const void *I, const float *absE, void
                 (learned && !p.h_sc.fallback) ? (int64_t)p.h_sc.n_src_base - p.h_sc.n_src : 0;
             stats->n_leaves = learned ? p.h_sc.n_srcleaf : 0;
             for (int k = 0; k < 12; ++k) stats->work[k] = (int64_t)p.h_sc.work[k];
-            for (int k = 0; k < 9; ++k) stats->t_ms[k] = phase_ms(p, slot, k);
+            for (int k = 0; k < 10; ++k) stats->t_ms[k] = phase_ms(p, slot, k);
             stats->check_rel_l2 = validated ? p.h_sc.check_rel : -1.0;
         }
         if (stats && stats->fell_back) return PH_EFALLBACK;
@@ -1212,7 +1225,7 @@ ph_status ph_phase_times(ph_plan *plan, int record, double *ms_sum, int64_t *n_c
         PH_HIP(hipSetDevice(p.device));
         for (int k = 0; k < Plan::kRing; ++k) harvest_slot(p, k);
         if (ms_sum)
-            for (int k = 0; k < PH_NPHASES; ++k) ms_sum[k] = k < 9 ? p.phase_sum[k] : 0.0;
+            for (int k = 0; k < PH_NPHASES; ++k) ms_sum[k] = k < 10 ? p.phase_sum[k] : 0.0;
         if (n_calls) *n_calls = p.phase_calls;
         for (double &v : p.phase_sum) v = 0.0;
         p.phase_calls = 0;

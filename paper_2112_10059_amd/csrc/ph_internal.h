@@ -283,7 +283,7 @@ struct Plan {
     // per-phase timing: a ring of event sets, one set per recorded call
     static constexpr int kRing = 32;
     // marks 0..7 on the caller's stream, 8..10 on the plan's second stream (lists, near field)
-    static constexpr int kMarks = 11;
+    static constexpr int kMarks = 15;  // 11..14: around the M2L product launches (third, main stream)
     hipEvent_t ring[kRing][kMarks] = {};
     bool ring_used[kRing] = {};
     int ring_pos = 0;
@@ -419,7 +419,8 @@ void fmm_m2m(Plan &p, hipStream_t s);  // ... and the M2M chain
 bool fmm_m2l_deepest(Plan &p, hipStream_t s);
 // waits for m2l_ready (the offset masks, and the deepest level's M2L products when they run on
 // another stream) before the M2L products and for lists_ready before the gathers
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready);
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready,
+                  hipEvent_t m2l_begin = nullptr, hipEvent_t m2l_end = nullptr);
 void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
 // far field at targets (L2P, M2P, own cell) + output: the matrix-core kernel on s, the other
