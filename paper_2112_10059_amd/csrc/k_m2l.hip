@@ -530,8 +530,9 @@ __global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArg
 // dropped lo * lo term is below 2^-16 of the product.
 // Operand layout of v_mfma_f32_16x16x16_bf16: A lane l holds A[l%16][4 (l/16) + v],
 // B lane l holds B[4 (l/16) + v][l%16] (v = 0..3); D as for the FP32 form.
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-constexpr int kPadB = 4;  // LDS row padding (bfloat16 elements; rows stay 8-byte aligned)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kPadB = 8;  // LDS row padding (bfloat16 elements; rows stay 16-byte aligned)
+static_assert(kTK % 32 == 0 && ((kTK + kPadB) * 2) % 16 == 0, "whole 16x16x32 steps, 16-byte aligned LDS rows");
 
 __device__ __forceinline__ uint16_t bf16_rne(float x)
 {
@@ -589,25 +590,27 @@ __global__ __launch_bounds__(256) void tgemm_m2l_bf16s_kernel(const uint16_t *__
                 Bl[n][k] = gm < M ? Ol[(size_t)gm * kp + gk] : (uint16_t)0;
             }
             __syncthreads();
+            // v_mfma_f32_16x16x32_bf16: lane l holds row l % 16, k = 8 (l / 16) .. + 7 of A and
+            // the same of B (column l % 16); three products per step (hi hi, hi lo, lo hi)
 #pragma unroll
-            for (int ks = 0; ks < kTK; ks += 16) {
-                const int kk = ks + 4 * (lane >> 4);
-                bf16x4 ah[2], al[2], bh[2], bl[2];
+            for (int ks = 0; ks < kTK; ks += 32) {
+                const int kk = ks + 8 * (lane >> 4);
+                bf16x8 ah[2], al[2], bh[2], bl[2];
                 for (int i = 0; i < 2; ++i) {
                     const int n = wn * 32 + i * 16 + (lane & 15);
-                    ah[i] = *reinterpret_cast<const bf16x4 *>(&Ah[n][kk]);
-                    al[i] = *reinterpret_cast<const bf16x4 *>(&Al[n][kk]);
+                    ah[i] = *reinterpret_cast<const bf16x8 *>(&Ah[n][kk]);
+                    al[i] = *reinterpret_cast<const bf16x8 *>(&Al[n][kk]);
                 }
                 for (int j = 0; j < 2; ++j) {
                     const int m = wm * 32 + j * 16 + (lane & 15);
-                    bh[j] = *reinterpret_cast<const bf16x4 *>(&Bh[m][kk]);
-                    bl[j] = *reinterpret_cast<const bf16x4 *>(&Bl[m][kk]);
+                    bh[j] = *reinterpret_cast<const bf16x8 *>(&Bh[m][kk]);
+                    bl[j] = *reinterpret_cast<const bf16x8 *>(&Bl[m][kk]);
                 }
                 for (int i = 0; i < 2; ++i)
                     for (int j = 0; j < 2; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                     }
             }
         }

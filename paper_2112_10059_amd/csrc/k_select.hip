@@ -38,7 +38,7 @@ __global__ void reset_scalars_kernel(CallScalars *sc, int32_t *gen)
 // order among ties).  The consumers reduce the few partials themselves: maxima do not depend on
 // the order of reduction, and no two blocks write one address.
 constexpr int kRedUnroll = 8;
-constexpr int kRedBlocks = 256;
+constexpr int kRedBlocks = 1024;
 
 template <class T>
 __global__ __launch_bounds__(256) void reduce_max_kernel(const T *__restrict__ I, const float *__restrict__ E,
@@ -499,6 +499,15 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     }
     // the tile's offset: partial holds the tile sums (tile_sums: each workgroup adds up those of
     // the earlier tiles, and workgroup 0 all of them for the totals) or their exclusive scan
+    // the tile's flags and box-boundary marks first (they do not depend on the offset)
+    const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)wv * kSelSpan;
+    uint32_t f[kStrips], bd[kStrips];
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) {
+        const int64_t k = base + st * 64 + lane;
+        f[st] = k < n ? sel[k] : 0u;
+        bd[st] = k < n ? bnd[k] : 0u;
+    }
     uint64_t tile_off;
     if (tile_sums) {
         const int64_t upto = blockIdx.x == 0 ? nb : blockIdx.x;
@@ -526,15 +535,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->scale_exp = e;
     const double scale = ldexp(1.0, -e);
-    const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)wv * kSelSpan;
-    uint32_t f[kStrips], bd[kStrips];  // flags and box-boundary marks, loaded together
     uint64_t acc = 0;
-#pragma unroll
-    for (int st = 0; st < kStrips; ++st) {
-        const int64_t k = base + st * 64 + lane;
-        f[st] = k < n ? sel[k] : 0u;
-        bd[st] = k < n ? bnd[k] : 0u;
-    }
 #pragma unroll
     for (int st = 0; st < kStrips; ++st) acc += packed_of(f[st]);
     acc = lane_value(wave_inclusive(acc, lane), 63);
@@ -617,6 +618,7 @@ void launch_reset_scalars(CallScalars *sc, int32_t *gen, hipStream_t s)
 
 
 int reduce_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (n + 2047) / 2048)); }
+static_assert(kRedBytes == (size_t)kRedBlocks * 24, "partials buffer sized for the reduction's blocks");
 
 void launch_reduce_max(const Plan &p, const void *I, const float *E, int32_t *gen, hipStream_t s)
 {

@@ -159,7 +159,7 @@ struct OperatorsDev {
 
 constexpr int kLeafPartials = 2048;  // scan space the selector's row compaction may use
 constexpr int kSelTilePoints = 4096;  // sorted points per workgroup of the selection pass
-constexpr size_t kRedBytes = 256 * 24;  // maxima partials: 256 x (max I, |E| key, I key)
+constexpr size_t kRedBytes = 1024 * 24;  // maxima partials: 1024 x (max I, |E| key, I key)
 constexpr int kCompMaxDepth = 6;  // composite translations for trees of at most this depth
 
 constexpr int kNearTabMaxR = 7;     // table for leaves of at most 4^3 cells
