@@ -236,6 +236,17 @@ __device__ __forceinline__ T shfl_up_t(T v, int d)
     }
 }
 
+// Workgroups are handed to the eight XCDs in turn (workgroup b to XCD b mod 8), and each XCD
+// has its own L2.  This maps workgroup b of nb to a logical index such that every XCD takes
+// one contiguous range of them (a bijection on [0, nb)): work items that share cache lines
+// (neighbouring tiles of sorted points, whose grid rows interleave) then meet in one L2
+// instead of each XCD fetching, or writing back, its own copy of the line.
+__device__ __forceinline__ int32_t xcd_contiguous(uint32_t b, uint32_t nb)
+{
+    const uint32_t x = b & 7u, q = nb >> 3, r = nb & 7u;
+    return (int32_t)(x * q + min(x, r) + (b >> 3));
+}
+
 template <class T>
 __device__ __forceinline__ T lane_value(T v, int l)
 {

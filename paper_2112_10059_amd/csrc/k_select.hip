@@ -287,7 +287,9 @@ __global__ __launch_bounds__(64 * kSelWaves, 8) void select_tiles_kernel(
     __shared__ uint64_t wsum[kSelWaves];
     __shared__ uint64_t cand[LEARNED ? kSelTile / 64 : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t tile0 = (int64_t)blockIdx.x * kSelTile;
+    // the tile: consecutive tiles on one XCD (their points' rows share cache lines)
+    const int64_t bt = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t tile0 = bt * kSelTile;
     const int64_t base = tile0 + (int64_t)w * kSelSpan;
     // the tile's values first (they do not depend on the maxima), then the maxima from the partials
     int32_t o[kSelStrips];
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(64 * kSelWaves, 8) void select_tiles_kernel(
     float e[kSelStrips];
     uint8_t tm[kSelStrips];
     int2 lrange = make_int2(0, 0);
-    if constexpr (LEARNED) lrange = la.tile_leaves[blockIdx.x];
+    if constexpr (LEARNED) lrange = la.tile_leaves[bt];
 #pragma unroll
     for (int st = 0; st < kSelStrips; ++st) {
         const int64_t k = base + st * 64 + lane;
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(64 * kSelWaves, 8) void select_tiles_kernel(
     if (threadIdx.x == 0) {
         uint64_t t = 0;
         for (int q = 0; q < kSelWaves; ++q) t += wsum[q];
-        partial[blockIdx.x] = t;
+        partial[bt] = t;
     }
 }
 
