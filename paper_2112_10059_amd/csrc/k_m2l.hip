@@ -526,10 +526,10 @@ __global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArg
 // every operand x is taken as hi + lo with hi = bf16(x), lo = bf16(x - hi) (the operator's
 // parts precomputed in FP64, the densities split while staged), and
 //   Y = Phi^T (Op_hi + Op_lo)^T ~ Phi_hi Op_hi + Phi_hi Op_lo + Phi_lo Op_hi
-// runs as three v_mfma_f32_16x16x16_bf16 per 16-deep k step with FP32 accumulation; the
+// runs as three v_mfma_f32_16x16x32_bf16 per 32-deep k step with FP32 accumulation; the
 // dropped lo * lo term is below 2^-16 of the product.
-// Operand layout of v_mfma_f32_16x16x16_bf16: A lane l holds A[l%16][4 (l/16) + v],
-// B lane l holds B[4 (l/16) + v][l%16] (v = 0..3); D as for the FP32 form.
+// Operand layout of v_mfma_f32_16x16x32_bf16: A lane l holds A[l%16][8 (l/16) + v],
+// B lane l holds B[8 (l/16) + v][l%16] (v = 0..7); D as for the FP32 form.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kPadB = 8;  // LDS row padding (bfloat16 elements; rows stay 16-byte aligned)
 static_assert(kTK % 32 == 0 && ((kTK + kPadB) * 2) % 16 == 0, "whole 16x16x32 steps, 16-byte aligned LDS rows");
@@ -647,7 +647,7 @@ template <class T, int NK>
 __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLevels gl, const T *__restrict__ Y0,
                                                          int M, int32_t r0, int32_t ccap, int init, int with_x)
 {
-    __shared__ int32_t cds[64];  // a slice's translations
+    __shared__ int32_t cds[kVSlots];  // the box's translations, in candidate order
     const int lane = threadIdx.x & 63;
     const int nl = a.n_lam;
     const int gen = a.sc->gen;  // this call's tag of the V-list slots
@@ -712,6 +712,10 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
             ve[q] = j < kVSlots ? vs[j] : 0ull;
         }
         const uint64_t below = (1ull << lane) - 1ull;
+        // the box's translations compacted in candidate order (all slices first, so that the
+        // reads below run across slice boundaries), then read kB at a time (loads issued
+        // together, added in order)
+        int n = 0;
 #pragma unroll
         for (int q = 0; q < (kVSlots + 63) / 64; ++q) {
             int32_t code = -1;  // rank * 316 + slot, chunk-relative
@@ -720,32 +724,29 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
                 const int32_t rk = full / kNumM2L - r0;
                 if (rk >= 0 && rk < ncols) code = rk * kNumM2L + full % kNumM2L;
             }
-            // the slice's translations compacted in candidate order, then read kB at a time
-            // (loads issued together, added in order)
             const uint64_t mask = __ballot(code >= 0);
-            const int n = __popcll(mask);
-            n_m2l += n;
-            wave_lds_sync();  // the previous slice's codes have been read
-            if (code >= 0) cds[__popcll(mask & below)] = code;
-            wave_lds_sync();
-            constexpr int kB = sizeof(T) == 4 ? 16 : 8;
-            for (int u0 = 0; u0 < n; u0 += kB) {
+            if (code >= 0) cds[n + __popcll(mask & below)] = code;
+            n += __popcll(mask);
+        }
+        n_m2l += n;
+        wave_lds_sync();
+        constexpr int kB = sizeof(T) == 4 ? 32 : 8;
+        for (int u0 = 0; u0 < n; u0 += kB) {
 #pragma unroll
-                for (int k = 0; k < NK; ++k) {
-                    if (k >= nk) break;
-                    const int li = lane + 64 * k;
-                    T v[kB];
+            for (int k = 0; k < NK; ++k) {
+                if (k >= nk) break;
+                const int li = lane + 64 * k;
+                T v[kB];
 #pragma unroll
-                    for (int u = 0; u < kB; ++u) {
-                        const int32_t c = u0 + u < n ? cds[u0 + u] : 0;
-                        v[u] = (u0 + u < n && li < nl)
-                                   ? Y[(size_t)(c / kNumM2L) * M + (size_t)(c % kNumM2L) * nl + li]
-                                   : T(0);
-                    }
-#pragma unroll
-                    for (int u = 0; u < kB; ++u)
-                        if (u0 + u < n && li < nl) acc[k] += v[u];
+                for (int u = 0; u < kB; ++u) {
+                    const int32_t c = u0 + u < n ? cds[u0 + u] : 0;
+                    v[u] = (u0 + u < n && li < nl)
+                               ? Y[(size_t)(c / kNumM2L) * M + (size_t)(c % kNumM2L) * nl + li]
+                               : T(0);
                 }
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    if (u0 + u < n && li < nl) acc[k] += v[u];
             }
         }
 #pragma unroll
