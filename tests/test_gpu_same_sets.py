@@ -98,8 +98,11 @@ def test_same_sets_learned_and_speed(gpu_lib):
     plan.evaluate(I, E, out=out1)
     plan.evaluate(I, out=out2, same_sets=True)
     assert np.array_equal(out1.cpu().numpy().view(np.uint32), out2.cpu().numpy().view(np.uint32))
-    full = _ms(lambda: plan.evaluate(I, E, out=out1), torch)
-    same = _ms(lambda: plan.evaluate(I, out=out2, same_sets=True), torch)
+    # the fastest of three runs each, in turn (a transient stall of the device says nothing)
+    full, same = float("inf"), float("inf")
+    for _ in range(3):
+        full = min(full, _ms(lambda: plan.evaluate(I, E, out=out1), torch))
+        same = min(same, _ms(lambda: plan.evaluate(I, out=out2, same_sets=True), torch))
     _say(f"  full call {full:.4f} ms, call on the previous sets {same:.4f} ms")
     assert same < full
     plan.close()
