@@ -195,9 +195,8 @@ void ph_plan_destroy(ph_plan *plan);
  * target lists with the deepest level's M2L products on a third (both library-owned,
  * shared by the plans of the device), both
  * forked from `stream` after the octree and joined back into it (the third before
- * the other levels' M2L products, the second's lists before the gathers and its near
- * field before the far field; events, no host synchronisation): the call stays
- * ordered on `stream`.  Calls on one plan's own workspace must not overlap.
+ * the other levels' M2L products, the second, lists and near field, before the
+ * gathers; events, no host synchronisation): the call stays ordered on `stream`.  Calls on one plan's own workspace must not overlap.
  */
 ph_status ph_evaluate(ph_plan *plan, const void *I, const float *absE, void *S_out,
                       void *stream, ph_stats *stats);

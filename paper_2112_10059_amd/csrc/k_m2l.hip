@@ -813,7 +813,7 @@ void m2l_product(Plan &p, const GemmSegs &sg, int64_t col_tiles, hipStream_t s)
 }
 
 template <class T>
-void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready, hipEvent_t m2l_begin,
+void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t side_ready, hipEvent_t m2l_begin,
                     hipEvent_t m2l_end)
 {
     FmmArgs<T> a = make_args<T>(p);
@@ -841,7 +841,7 @@ void fmm_downward_t(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lis
         PH_HIP(hipEventRecord(m2l_begin, s));
         PH_HIP(hipEventRecord(m2l_end, s));
     }
-    PH_HIP(hipStreamWaitEvent(s, lists_ready, 0));  // the gathers read the X and V/X target lists
+    PH_HIP(hipStreamWaitEvent(s, side_ready, 0));  // the gathers read the X lists (built before it)
     // level-local parts (V and X lists) of every level: no dependence between levels
     int64_t gcap = 0;
     for (int l = 2; l <= D; ++l) gcap += p.level_cap[l];
@@ -962,11 +962,11 @@ bool fmm_m2l_deepest(Plan &p, hipStream_t s)
     return true;
 }
 
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready, hipEvent_t m2l_begin,
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t side_ready, hipEvent_t m2l_begin,
                   hipEvent_t m2l_end)
 {
-    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, m2l_ready, lists_ready, m2l_begin, m2l_end);
-    else fmm_downward_t<float>(p, s, m2l_ready, lists_ready, m2l_begin, m2l_end);
+    if (p.precision == PH_FP64) fmm_downward_t<double>(p, s, m2l_ready, side_ready, m2l_begin, m2l_end);
+    else fmm_downward_t<float>(p, s, m2l_ready, side_ready, m2l_begin, m2l_end);
 }
 
 void fmm_m2m_level(Plan &p, int l, hipStream_t s)

@@ -352,7 +352,7 @@ void free_plan(Plan *p)
     if (p->events_ready)
         for (auto &set : p->ring)
             for (auto &e : set) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_lists, p->ev_vt, p->ev_p2m, p->ev_m2l})
+    for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_vt, p->ev_p2m, p->ev_m2l})
         if (e) (void)hipEventDestroy(e);
     if (p->side) release_side_streams(p->device);
     for (void *q : ptrs) dev_free(q);
@@ -836,7 +836,6 @@ static void create_plan(Plan &p, const ph_points *pts, const ph_gas *gas, const 
     PH_HIP(hipEventCreateWithFlags(&p.ev_m2l, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_fork, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_join, kSyncEventFlags));
-    PH_HIP(hipEventCreateWithFlags(&p.ev_lists, kSyncEventFlags));
     PH_HIP(hipEventCreateWithFlags(&p.ev_vt, kSyncEventFlags));
 }
 
@@ -995,12 +994,17 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(4, s);
     // The lists and the near field run on the second stream, the V/X targets and the deepest
     // level's M2L products on the third, the upward pass and the rest of the downward pass here.
-    // A wait on an event still pending costs the host several launches' time, so each wait
-    // stands for everything before its event on that stream: the M2L levels here wait for the
-    // deepest level's products (which follow the V/X targets), the gathers for the lists (the
-    // near field runs on beside the gathers and the L2L step), and the far-field kernels, which
-    // add the near field into the output, for the near field.  The leaf densities are enqueued
-    // here before the other streams' work, so that the host reaches them early.
+    // Every event record or wait costs the host time and leaves the stream idle for several
+    // microseconds (measured: 5-9 us between two kernels, even for an event that completed long
+    // before), so each wait stands for everything before its event on that stream: the M2L
+    // levels here wait for the deepest level's products (which follow the V/X targets), and the
+    // gathers for the near field (which follows the lists), which also orders the far-field
+    // kernels after it (they add the near field into the output).  On the 128^3 grid the lists
+    // and the near field end about when the coarser levels' M2L products do, so the gathers
+    // lose little.  The leaf densities are enqueued here before the other streams' work, so
+    // that the host reaches them early; enqueued before the fork they would delay the third
+    // stream's chain (V/X targets, deepest M2L products), which sets when the coarser M2L
+    // products can start (measured: 9 us more per call).
     const bool deep = p.y_all_levels && p.max_depth >= 2;
     PH_HIP(hipEventRecord(p.ev_fork, s));
     fmm_p2m(p, s);
@@ -1012,7 +1016,6 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     mark(8, p.side);
     if (!same_sets) build_lists(p, p.side);
     mark(9, p.side);
-    PH_HIP(hipEventRecord(p.ev_lists, p.side));
     fmm_near(p, p.side);
     mark(10, p.side);
     PH_HIP(hipEventRecord(p.ev_join, p.side));
@@ -1030,10 +1033,9 @@ void enqueue_call(Plan &p, const void *I, const float *absE, void *S_out, hipStr
     }
     fmm_m2m(p, s);
     mark(5, s);
-    fmm_downward(p, s, deep ? p.ev_m2l : p.ev_vt, p.ev_lists, timed ? p.ring[slot][13] : nullptr,
+    fmm_downward(p, s, deep ? p.ev_m2l : p.ev_vt, p.ev_join, timed ? p.ring[slot][13] : nullptr,
                  timed ? p.ring[slot][14] : nullptr);
     mark(6, s);
-    PH_HIP(hipStreamWaitEvent(s, p.ev_join, 0));  // the near field, added by the far-field kernels
     // far field at the targets (every leaf kernel here, after the gathers and so after the near field)
     fmm_leaf(p, S_out, s, s);
     mark(7, s);

@@ -293,12 +293,12 @@ struct Plan {
     bool events_ready = false;
     // the interaction lists and the near field run on a second stream, the V/X targets, offset
     // masks and deepest level's M2L products on a third, both forked from the caller's stream
-    // after the tree (ev_fork); the gathers wait for the lists (ev_lists), the far field for
-    // the near field (ev_join), the other levels' M2L products for the deepest level's (ev_m2l,
-    // after the offset masks; ev_vt when that level runs with the others)
+    // after the tree (ev_fork); the gathers (and so the far field) wait for the near field
+    // (ev_join, after the lists), the other levels' M2L products for the deepest level's
+    // (ev_m2l, after the offset masks; ev_vt when that level runs with the others)
     hipStream_t side = nullptr;
     hipStream_t side2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_lists = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_vt = nullptr;                     // V/X targets and M2L offset masks known
     hipEvent_t ev_p2m = nullptr, ev_m2l = nullptr;  // leaf densities known (main); deepest M2L done
     // check values of the leaves of levels >= 3 in one launch from the level-local parts of their
@@ -418,8 +418,8 @@ void fmm_m2m(Plan &p, hipStream_t s);  // ... and the M2M chain
 // false if this plan computes that level with the others (then nothing is launched)
 bool fmm_m2l_deepest(Plan &p, hipStream_t s);
 // waits for m2l_ready (the offset masks, and the deepest level's M2L products when they run on
-// another stream) before the M2L products and for lists_ready before the gathers
-void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t lists_ready,
+// another stream) before the M2L products and for side_ready (the lists and the near field) before the gathers
+void fmm_downward(Plan &p, hipStream_t s, hipEvent_t m2l_ready, hipEvent_t side_ready,
                   hipEvent_t m2l_begin = nullptr, hipEvent_t m2l_end = nullptr);
 void fmm_m2m_level(Plan &p, int level, hipStream_t s);  // parents at level, children at level + 1
 constexpr int kGemmK = 32;  // K chunk of the translation GEMM
