@@ -14,7 +14,9 @@ The printed JSON line carries targets/s (null unless the relative L2 error on
 sampled targets is within 1e-3 against the FP64 oracle, both on the same source
 set and against all sources), the roofline of the M2L products (the kernel with
 the largest time per call: two launches, timed by hipEvents on their streams
-inside the timed region), the FP64 oracle timed on the host cores on a bounded sample, the
+inside the timed region), the GPU time per call with every call queued before the
+first one runs (behind a sleep kernel: no host gap; equal to the back-to-back time
+when the calls are GPU-bound), the FP64 oracle timed on the host cores on a bounded sample, the
 paper's threshold rule (tau_s = 1e-4) on the same field, and the plain FP64 FMM
 (all points sources and targets, no adaptivity) on the same grid for the
 speed-up ratio.
@@ -88,6 +90,17 @@ def time_steps(plan, I, E, steps, warmup, torch, host=None):
     if host is not None:
         host["launch"] = "eager"
         host["enqueue_ms_per_call"] = (h1 - h0) * 1e3 / steps
+        # the same calls all queued before the first one runs (behind a sleep kernel on the
+        # caller's stream, about 20 ms per 20 calls against 3 ms of enqueueing): the device-side
+        # time of a call with no host gap; equal to ms when the calls are GPU-bound
+        torch.cuda._sleep(50_000_000 * (steps // 20 + 1))
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        q0.record()
+        for _ in range(steps):
+            plan.evaluate(I, E, out=out)
+        q1.record()
+        torch.cuda.synchronize()
+        host["queued_gpu_ms_per_call"] = q0.elapsed_time(q1) / steps
     plan.phase_times(record=1)  # discard, start recording
     for _ in range(steps):
         plan.evaluate(I, E, out=out)
@@ -147,7 +160,8 @@ def main():
     n_tgt = st["n_tgt"]
     value = n_tgt / (ms * 1e-3)
     log(f"learned fp32: {ms:.4f} ms/step ({host['launch']}), {value:.4e} targets/s; host enqueue "
-        f"{host['enqueue_ms_per_call']:.4f} ms/call; phases {phases}")
+        f"{host['enqueue_ms_per_call']:.4f} ms/call; queued on the GPU {host['queued_gpu_ms_per_call']:.4f} ms/call; "
+        f"phases {phases}")
     roof = roofline(phases, st, wl.n)
     # the second evaluation of a time step on the same sets (tree and lists of the call before)
     out2 = torch.empty(wl.n, dtype=torch.float32, device=dev)
@@ -172,10 +186,11 @@ def main():
     # ---------------- the paper's threshold rule (tau_s = 1e-4) on the same field, for comparison
     plan_t = binding.Plan(wl.xyz, wl.gas, wl.thresholds, precision=args.precision, order_q=args.order_q, **common)
     _, st_t = plan_t.evaluate(I, E, stats=True)
-    S_t, ms_t, phases_t = time_steps(plan_t, I, E, args.steps, args.warmup, torch)
+    host_t = {}
+    S_t, ms_t, phases_t = time_steps(plan_t, I, E, args.steps, args.warmup, torch, host=host_t)
     plan_t.close()
     threshold = {"targets_per_s": n_tgt / (ms_t * 1e-3), "ms_per_step": ms_t, "n_src": st_t["n_src"],
-                 "phases_ms": phases_t}
+                 "gpu_ms_per_call_queued": host_t["queued_gpu_ms_per_call"], "phases_ms": phases_t}
     log(f"threshold fp32: {threshold}")
 
     # ---------------- parity on sampled targets: same source set, and all sources (method error)
@@ -252,6 +267,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms,
         "host_enqueue_ms_per_call": host["enqueue_ms_per_call"],
+        "gpu_ms_per_call_queued": host["queued_gpu_ms_per_call"],
         "launch": host["launch"],
         "higher_is_better": True,
         "scaling": "weak",
