@@ -452,38 +452,53 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
         const int32_t P = bx.parent[S];
         const int sx = bx.ax[S], sy = bx.ay[S], sz = bx.az[S];
         if (lane < kUseWords) use[wv][lane] = 0u;
-        int32_t Qd = -1;
-        if (lane < 27) {
-            const int32_t Q = bx.coll[(size_t)P * 27 + lane];
-            if (Q >= 0 && (bx.flags[Q] & (kBoxExists | kBoxLeaf)) == kBoxExists) Qd = Q;
-        }
+        // the parent's colleagues; the children of those not split in this call have no
+        // targets (every box outside the call's tree has zero counts), so the count test
+        // below also stands for the colleague's own status
+        const int32_t Qd = lane < 27 ? bx.coll[(size_t)P * 27 + lane] : -1;
         const uint64_t qmask = __ballot(Qd >= 0);
         const int nc = 8 * __popcll(qmask);
         __builtin_amdgcn_wave_barrier();
-        for (int f0 = 0; f0 < nc; f0 += 64) {
-            const int f = f0 + lane;
+        // the candidates (8 children per colleague, up to 216): every child index, then every
+        // child's target count and position, each batch of loads issued together
+        constexpr int kC = (27 * 8 + 63) / 64;
+        int32_t Bc[kC], dq[kC];
+#pragma unroll
+        for (int u = 0; u < kC; ++u) {
+            const int f = 64 * u + lane;
             uint64_t m = qmask;
             for (int j = f < nc ? (f >> 3) : 0; j > 0; --j) m &= m - 1;
             const int d = m ? __ffsll((long long)m) - 1 : 0;
             const int32_t Q = __shfl(Qd, d);
-            int32_t B = -1;
+            dq[u] = d;
+            Bc[u] = f < nc ? bx.child[(size_t)Q * 8 + (f & 7)] : -1;
+        }
+        int32_t tc[kC], bxc[kC], byc[kC], bzc[kC];
+#pragma unroll
+        for (int u = 0; u < kC; ++u) {
+            const int32_t B = Bc[u];
+            tc[u] = B >= 0 ? bx.t_cnt[B] : 0;
+            bxc[u] = B >= 0 ? bx.ax[B] : 0;
+            byc[u] = B >= 0 ? bx.ay[B] : 0;
+            bzc[u] = B >= 0 ? bx.az[B] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kC; ++u) {
+            const int32_t B = Bc[u];
             bool fresh = false;
-            if (f < nc) {
-                B = bx.child[(size_t)Q * 8 + (f & 7)];
-                if (B >= 0 && bx.t_cnt[B] > 0) {
-                    const int dx = sx - bx.ax[B], dy = sy - bx.ay[B], dz = sz - bx.az[B];
-                    const bool near = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-                    if (!near) {
-                        const int slot = m2l_slot(dx, dy, dz);
-                        atomicOr(&use[wv][slot >> 5], 1u << (slot & 31));
-                        // B's V-list entry for S: candidate slot 8 c + o, c the index of S's parent
-                        // among B's parent's colleagues (the mirror of Q's index d among P's), o
-                        // S's octant
-                        const int o = ((sx & 1) << 2) | ((sy & 1) << 1) | (sz & 1);
-                        L.vslot[(size_t)B * kVSlots + (26 - d) * 8 + o] =
-                            ((uint64_t)(uint32_t)gen << 32) | (uint32_t)(r * kNumM2L + slot);
-                        fresh = level >= 3 && atomicExch(&L.vt_tag[B], gen) != gen;
-                    }
+            if (B >= 0 && tc[u] > 0) {
+                const int dx = sx - bxc[u], dy = sy - byc[u], dz = sz - bzc[u];
+                const bool near = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+                if (!near) {
+                    const int slot = m2l_slot(dx, dy, dz);
+                    atomicOr(&use[wv][slot >> 5], 1u << (slot & 31));
+                    // B's V-list entry for S: candidate slot 8 c + o, c the index of S's parent
+                    // among B's parent's colleagues (the mirror of Q's index d among P's), o
+                    // S's octant
+                    const int o = ((sx & 1) << 2) | ((sy & 1) << 1) | (sz & 1);
+                    L.vslot[(size_t)B * kVSlots + (26 - dq[u]) * 8 + o] =
+                        ((uint64_t)(uint32_t)gen << 32) | (uint32_t)(r * kNumM2L + slot);
+                    fresh = level >= 3 && atomicExch(&L.vt_tag[B], gen) != gen;
                 }
             }
             wave_append(fresh, L.vt + li.base[level], &sc->n_vt_lvl[level], B);
