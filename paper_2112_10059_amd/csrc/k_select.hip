@@ -502,14 +502,18 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     // the tile's offset: partial holds the tile sums (tile_sums: each workgroup adds up those of
     // the earlier tiles, and workgroup 0 all of them for the totals) or their exclusive scan
     // the tile's flags and box-boundary marks first (they do not depend on the offset)
+    // (lanes past the end read the last point, so that the loads need no branch and go out together)
     const int64_t base = (int64_t)blockIdx.x * kSelTile + (int64_t)wv * kSelSpan;
     uint32_t f[kStrips], bd[kStrips];
 #pragma unroll
     for (int st = 0; st < kStrips; ++st) {
-        const int64_t k = base + st * 64 + lane;
-        f[st] = k < n ? sel[k] : 0u;
-        bd[st] = k < n ? bnd[k] : 0u;
+        const int64_t k = min(base + st * 64 + lane, n - 1);
+        f[st] = sel[k];
+        bd[st] = bnd[k];
     }
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st)
+        if (base + st * 64 + lane >= n) f[st] = bd[st] = 0u;
     uint64_t tile_off;
     if (tile_sums) {
         const int64_t upto = blockIdx.x == 0 ? nb : blockIdx.x;
@@ -545,56 +549,75 @@ __global__ __launch_bounds__(64 * kSelWaves) void select_compact_kernel(
     __syncthreads();
     uint64_t carry = tile_off;
     for (int q = 0; q < wv; ++q) carry += wsum[q];
+    uint64_t here[kStrips];
+    bool wr[kStrips], any = false;
 #pragma unroll
     for (int st = 0; st < kStrips; ++st) {
         const uint64_t v = packed_of(f[st]);
         const uint64_t incl = wave_inclusive(v, lane);
-        const uint64_t here = carry + incl - v;
+        here[st] = carry + incl - v;
         carry += lane_value(incl, 63);
         const int64_t k = base + st * 64 + lane;
+        // points that are only targets need nothing more unless targets are compacted
+        wr[st] = k < n && (tgt_compact ? f[st] != 0u : (f[st] & 1u) != 0u);
+        any = any || wr[st];
         if (k >= n) continue;
-        if (bd[st]) scanned[k] = here;
+        if (bd[st]) scanned[k] = here[st];
         // a call on the previous call's sets (S_zero set): the output at the points that are
         // not targets is cleared here, as the selection pass would have done
         if (S_zero && !(f[st] & 2u)) S_zero[perm[k]] = TI(0);
-        // points that are only targets need nothing more unless targets are compacted
-        if (!(tgt_compact ? f[st] : (f[st] & 1u))) continue;
-        const uint32_t sp_lo = (uint32_t)(here & 0xffffffffu), sp_hi = (uint32_t)(here >> 32);
-        const int32_t o = perm[k];
-        const TI Iraw = I[o];
-        if (S_zero && bad_value(Iraw)) flag_error(sc, sticky, 1);  // no maxima pass checked it
-        const double Iv = (double)Iraw * scale;
-        T x, y, z;
+    }
+    // the written points' data for all strips in two batches of loads (the permutation and
+    // the point's record, then I through the permutation), in the waves that write any
+    if (!__ballot(any)) return;
+    int32_t o[kStrips], ce[kStrips];
+    T x[kStrips], y[kStrips], z[kStrips];
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) {
+        const int64_t k = min(base + st * 64 + lane, n - 1);
+        o[st] = perm[k];
+        ce[st] = cell ? cell[k] : 0;
         if constexpr (sizeof(C) == 8) {
-            x = (T)xyz[3 * k];
-            y = (T)xyz[3 * k + 1];
-            z = (T)xyz[3 * k + 2];
+            x[st] = (T)xyz[3 * k];
+            y[st] = (T)xyz[3 * k + 1];
+            z[st] = (T)xyz[3 * k + 2];
         } else {
             const C q = xyz[k];
-            x = q.x;
-            y = q.y;
-            z = q.z;
+            x[st] = q.x;
+            y[st] = q.y;
+            z[st] = q.z;
         }
+    }
+    TI Iraw[kStrips];
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) Iraw[st] = I[o[st]];
+#pragma unroll
+    for (int st = 0; st < kStrips; ++st) {
+        if (!wr[st]) continue;
+        const int64_t k = base + st * 64 + lane;
+        const uint32_t sp_lo = (uint32_t)(here[st] & 0xffffffffu), sp_hi = (uint32_t)(here[st] >> 32);
+        if (S_zero && bad_value(Iraw[st])) flag_error(sc, sticky, 1);  // no maxima pass checked it
+        const double Iv = (double)Iraw[st] * scale;
         const bool is_src = f[st] & 1u;
         if (is_src) {
             const double wk = w ? w[k] : w_uniform;
             typename Vec4T<T>::type d;
-            d.x = (T)x;
-            d.y = (T)y;
-            d.z = (T)z;
+            d.x = x[st];
+            d.y = y[st];
+            d.z = z[st];
             d.w = (T)(wk * Iv);
             s_dat[sp_lo] = d;
-            if (cell) s_cell[sp_lo] = cell[k];
+            if (cell) s_cell[sp_lo] = ce[st];
         }
         if ((f[st] & 2u) && tgt_compact) {
-            t_out[sp_hi] = o;
+            t_out[sp_hi] = o[st];
             typename Vec4T<T>::type d;
-            d.x = (T)x;
-            d.y = (T)y;
-            d.z = (T)z;
+            d.x = x[st];
+            d.y = y[st];
+            d.z = z[st];
             d.w = is_src ? (T)(c_self * Iv) : T(0);
             t_dat[sp_hi] = d;
-            if (cell) t_cell[sp_hi] = cell[k];
+            if (cell) t_cell[sp_hi] = ce[st];
         }
     }
 }
