@@ -178,11 +178,15 @@ __global__ __launch_bounds__(kUpThreads) void p2m_kernel(FmmArgs<T> a, int depth
     for (int64_t i = u_zero + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < u_end;
          i += (int64_t)gridDim.x * blockDim.x)
         a.u[i] = T(0);
+    static_assert(kMaxDepth + 2 <= 64, "a lane per level");
+    // the call's per-level counts, lane l holding level l's (read once, picked by readlane)
+    const int lane = threadIdx.x & 63;
+    const int32_t src_l = lane < kMaxDepth + 2 ? a.sc->lvl_src[lane] : 0;
     for (int32_t idx = blockIdx.x;; idx += gridDim.x) {
         int level = -1;
         int32_t r = idx;
         for (int l = 2; l <= depth; ++l) {
-            const int32_t c = a.sc->lvl_src[l];
+            const int32_t c = __builtin_amdgcn_readlane(src_l, l);
             if (r < c) {
                 level = l;
                 break;

@@ -450,12 +450,19 @@ __global__ __launch_bounds__(256) void l2l_comp_kernel(FmmArgs<float> a, CompArg
         // a box of level >= 3 holds a level-local part only if the gather wrote one this call
         // (a V/X target: tagged with the call number); the others count as zero, so their
         // check values need no clearing.  Every box of level 2 is written.
+        // (all read unconditionally, box 0 standing in for an absent box: a short-circuit test
+        // would make each read a round trip of its own)
         const int gen = a.sc->gen;
-        const bool v = B >= 0 && (a.bx.flags[B] & kBoxLeaf) && a.bx.t_cnt[B] > 0;
-        const bool vo = B >= 0 && a.L.vt_tag[B] == gen;
+        const int32_t Bc = max(B, 0);
+        const int32_t fl = a.bx.flags[Bc], tc = a.bx.t_cnt[Bc], tg = a.L.vt_tag[Bc];
+        int32_t tga[kCompMaxDepth];
+#pragma unroll
+        for (int l = 2; l < kCompMaxDepth; ++l) tga[l] = a.L.vt_tag[max(an[l], 0)];
+        const bool v = B >= 0 && (fl & kBoxLeaf) && tc > 0;
+        const bool vo = B >= 0 && tg == gen;
         bool va[kCompMaxDepth];
 #pragma unroll
-        for (int l = 2; l < kCompMaxDepth; ++l) va[l] = l == 2 || (an[l] >= 0 && a.L.vt_tag[an[l]] == gen);
+        for (int l = 2; l < kCompMaxDepth; ++l) va[l] = l == 2 || (an[l] >= 0 && tga[l] == gen);
         leafb[t] = v ? B : -1;
         lown[t] = v && vo;
 #pragma unroll
@@ -652,11 +659,16 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
     const int nl = a.n_lam;
     const int gen = a.sc->gen;  // this call's tag of the V-list slots
     constexpr int nk = NK;  // lattice values per lane: n_lam <= 64 NK
+    static_assert(kMaxDepth + 2 <= 64, "a lane per level");
+    // the call's per-level counts, lane l holding level l's (read once, picked by readlane)
+    const int32_t cnt_l = (lane >= gl.lo && lane <= gl.hi)
+                              ? (lane == 2 ? a.sc->lvl_count[2] : a.sc->n_vt_lvl[lane]) : 0;
+    const int32_t src_l = lane < kMaxDepth + 2 ? a.sc->lvl_src[lane] : 0;
     for (int32_t idx = blockIdx.x;; idx += gridDim.x) {
         int level = -1;
         int32_t i = idx;
         for (int l = gl.lo; l <= gl.hi; ++l) {
-            const int32_t c = l == 2 ? a.sc->lvl_count[2] : a.sc->n_vt_lvl[l];
+            const int32_t c = __builtin_amdgcn_readlane(cnt_l, l);
             if (i < c) {
                 level = l;
                 break;
@@ -664,10 +676,23 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
             i -= c;
         }
         if (level < 0) break;
-        const int32_t ncols = min(ccap, a.sc->lvl_src[level] - r0);
+        const int32_t ncols = min(ccap, __builtin_amdgcn_readlane(src_l, level) - r0);
         if (!with_x && ncols <= 0) continue;  // nothing of this level in the chunk
         const int32_t b = level == 2 ? a.lt.base[2] + i : a.L.vt[a.lt.base[level] + i];
-        if (a.bx.t_cnt[b] == 0) continue;
+        // the box's target count, X range and V-list slots (the children of the parent's
+        // colleagues, in candidate order, filled by this call's V-target pass), loaded together
+        // (no branch on them before their use: a box without targets only writes nothing)
+        const int32_t tcnt = a.bx.t_cnt[b];
+        const uint2 xrng = a.L.x_rng[b];
+        const uint64_t *__restrict__ vs = a.L.vslot + (size_t)b * kVSlots;
+        uint64_t ve[(kVSlots + 63) / 64];
+#pragma unroll
+        for (int q = 0; q < (kVSlots + 63) / 64; ++q) ve[q] = vs[min(64 * q + lane, kVSlots - 1)];
+        const bool live = tcnt != 0;
+#pragma unroll
+        for (int q = 0; q < (kVSlots + 63) / 64; ++q)
+            if (64 * q + lane >= kVSlots || !live) ve[q] = 0ull;
+        const uint2 xr = (with_x && live) ? xrng : make_uint2(0u, 0u);
         int64_t yrow = 0;  // constant indices only (no private copy of the argument block)
 #pragma unroll
         for (int l = 0; l < kMaxDepth + 2; ++l)
@@ -678,7 +703,7 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
         unsigned long long n_m2l = 0, n_p2l = 0;
         if (with_x) {
             // X list: sources of coarser leaves straight onto the check points
-            const uint32_t x0 = a.L.x_rng[b].x, x1 = a.L.x_rng[b].y;
+            const uint32_t x0 = xr.x, x1 = xr.y;
             if (x1 > x0) {
                 const double hw = a.lt.hw[level];
                 T cx, cy, cz;
@@ -702,15 +727,7 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
                 }
             }
         }
-        // V list: the box's candidate slots (the children of the parent's colleagues, in
-        // candidate order), filled by this call's V-target pass, read in one sweep
-        const uint64_t *__restrict__ vs = a.L.vslot + (size_t)b * kVSlots;
-        uint64_t ve[(kVSlots + 63) / 64];
-#pragma unroll
-        for (int q = 0; q < (kVSlots + 63) / 64; ++q) {
-            const int j = 64 * q + lane;
-            ve[q] = j < kVSlots ? vs[j] : 0ull;
-        }
+        // V list: the box's candidate slots, read above in one sweep
         const uint64_t below = (1ull << lane) - 1ull;
         // the box's translations compacted in candidate order (all slices first, so that the
         // reads below run across slice boundaries), then read kB at a time (loads issued
@@ -752,7 +769,7 @@ __global__ __launch_bounds__(64) void down_gather_kernel(FmmArgs<T> a, GatherLev
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int li = lane + 64 * k;
-            if (k < nk && li < nl) {
+            if (live && k < nk && li < nl) {
                 const size_t o = (size_t)b * nl + li;
                 a.u[o] = init ? acc[k] : a.u[o] + acc[k];
             }

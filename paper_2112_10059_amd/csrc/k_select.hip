@@ -298,11 +298,16 @@ __global__ __launch_bounds__(64 * kSelWaves, 8) void select_tiles_kernel(
     uint8_t tm[kSelStrips];
     int2 lrange = make_int2(0, 0);
     if constexpr (LEARNED) lrange = la.tile_leaves[bt];
+    // (lanes past the end read the last point, so that the loads need no per-lane branch, each
+    // of which would cost a round trip of its own, and go out together; the flags below test k)
 #pragma unroll
-    for (int st = 0; st < kSelStrips; ++st) {
-        const int64_t k = base + st * 64 + lane;
-        o[st] = k < n ? perm[k] : -1;
-        tm[st] = (tmask && k < n) ? tmask[k] : 1;
+    for (int st = 0; st < kSelStrips; ++st) o[st] = perm[min(base + st * 64 + lane, n - 1)];
+    if (tmask) {
+#pragma unroll
+        for (int st = 0; st < kSelStrips; ++st) tm[st] = tmask[min(base + st * 64 + lane, n - 1)];
+    } else {
+#pragma unroll
+        for (int st = 0; st < kSelStrips; ++st) tm[st] = 1;
     }
     // the learned variant's leaf records, in flight with the tile's values
     int4 lpre = make_int4(0, 0, 0, 0);
@@ -310,9 +315,13 @@ __global__ __launch_bounds__(64 * kSelWaves, 8) void select_tiles_kernel(
         if ((int)threadIdx.x < lrange.y - lrange.x) lpre = la.leaf_pos[lrange.x + threadIdx.x];
     }
 #pragma unroll
-    for (int st = 0; st < kSelStrips; ++st) {
-        v[st] = o[st] >= 0 ? I[o[st]] : T(0);
-        e[st] = (E && o[st] >= 0) ? E[o[st]] : 0.0f;
+    for (int st = 0; st < kSelStrips; ++st) v[st] = I[o[st]];
+    if (E) {
+#pragma unroll
+        for (int st = 0; st < kSelStrips; ++st) e[st] = E[o[st]];
+    } else {
+#pragma unroll
+        for (int st = 0; st < kSelStrips; ++st) e[st] = 0.0f;
     }
     const Maxima mx = block_maxima(red, red_nb);
     const double imax = mx.imax, emax = mx.emax;

@@ -54,7 +54,10 @@ __device__ __forceinline__ int32_t wave_slot(bool pred, int32_t *counter)
 __device__ __forceinline__ uint64_t scan_at(const uint64_t *__restrict__ scanned, int32_t k, int64_t n,
                                             uint64_t total)
 {
-    return k < n ? scanned[k] : total;
+    // (the load is unconditional, at the last point past the end, so that it needs no branch
+    // and goes out with the caller's other loads)
+    const uint64_t v = scanned[k < n ? k : n - 1];
+    return k < n ? v : total;
 }
 
 __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int leaf_cap, int max_depth,
@@ -70,20 +73,22 @@ __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int
         for (int l = 0; l <= li.depth; ++l) sc->lvl_count[l] = li.cap[l];
         for (int l = 0; l <= li.depth + 1; ++l) sc->lvl_start[l] = li.base[l];
     }
-    const int32_t st = bx.start[f], en = bx.end[f];
+    // the box's and its parent's ranges and their scanned counts, each set of loads together
+    const int32_t st = bx.start[f], en = bx.end[f], par = bx.parent[f], lev = bx.level[f];
+    const int32_t pc = par >= 0 ? par : f;
+    const int32_t pst = bx.start[pc], pen = bx.end[pc];
     const uint64_t a = scan_at(scanned, st, n, total), b = scan_at(scanned, en, n, total);
+    const uint64_t pa = scan_at(scanned, pst, n, total), pb = scan_at(scanned, pen, n, total);
     const int32_t s0 = (int32_t)(a & 0xffffffffu), t0 = (int32_t)(a >> 32);
     const int32_t sn = (int32_t)(b & 0xffffffffu) - s0, tn = (int32_t)(b >> 32) - t0;
-    const int32_t par = bx.parent[f];
     bool exists = true;
     if (par >= 0) {
-        const uint64_t pa = scan_at(scanned, bx.start[par], n, total), pb = scan_at(scanned, bx.end[par], n, total);
         const int32_t psn = (int32_t)(pb & 0xffffffffu) - (int32_t)(pa & 0xffffffffu);
         const int32_t ptn = (int32_t)(pb >> 32) - (int32_t)(pa >> 32);
         exists = (sn + tn > 0) && (max(psn, ptn) > leaf_cap);
     }
     // split in the plan's tree iff it holds more than leaf_cap points above the depth limit
-    const bool split = exists && (en - st > leaf_cap) && (bx.level[f] < max_depth) && (max(sn, tn) > leaf_cap);
+    const bool split = exists && (en - st > leaf_cap) && (lev < max_depth) && (max(sn, tn) > leaf_cap);
     if (mine) {
         bx.s_first[f] = exists ? s0 : 0;
         bx.s_cnt[f] = exists ? sn : 0;
@@ -96,7 +101,6 @@ __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int
     // come from atomic appends (a wave rarely spans two levels): the order of the boxes within
     // a level enters no result, only the layout of the per-level products.
     const bool has_src = mine && exists && sn > 0, is_tpar = mine && split && tn > 0;
-    const int lev = bx.level[f];
     int32_t srank = -1, trank = -1;
     uint64_t pending = __ballot(has_src || is_tpar);
     while (pending) {
@@ -116,7 +120,7 @@ __global__ void tree_status_kernel(BoxArrays bx, LevelInfo li, int32_t nbox, int
         if (trank >= 0) bx.tpar_box[li.base[lev] + trank] = f;
     }
     // lowest level holding a leaf with sources, as max of (depth + 1 - level), one atomic per wave
-    int v = (mine && exists && !split && sn > 0) ? (li.depth + 1 - bx.level[f]) : 0;
+    int v = (mine && exists && !split && sn > 0) ? (li.depth + 1 - lev) : 0;
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
     if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(&sc->min_leafsrc_level, v);
 }
@@ -436,11 +440,14 @@ __global__ __launch_bounds__(256) void vtarget_kernel(BoxArrays bx, LevelInfo li
     const int gen = sc->gen;
     __shared__ uint32_t use[4][kUseWords];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    static_assert(kMaxDepth + 2 <= 64, "a lane per level");
+    // the call's per-level counts, lane l holding level l's (read once, picked by readlane)
+    const int32_t src_l = lane < kMaxDepth + 2 ? sc->lvl_src[lane] : 0;
     for (int32_t idx = blockIdx.x * 4 + wv;; idx += gridDim.x * 4) {
         int level = -1;
         int32_t r = idx;
         for (int l = 2; l <= li.depth; ++l) {
-            const int32_t c = sc->lvl_src[l];
+            const int32_t c = __builtin_amdgcn_readlane(src_l, l);
             if (r < c) {
                 level = l;
                 break;
