@@ -838,7 +838,17 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
     extern __shared__ __align__(16) float ntab[];  // the near-field kernel table, when present
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t n = a.sc->n_near;
-    if ((int32_t)blockIdx.x >= n) return;  // the whole workgroup
+    // the workgroup's leaves: each XCD (workgroup b runs on XCD b mod 8) takes one contiguous run
+    // of the list, so that neighbouring leaves, whose U lists share their sources, read them
+    // through one L2 (with fewer than 8 workgroups: every gridDim-th leaf)
+    const uint32_t G = gridDim.x, xcd = blockIdx.x & 7u;
+    int32_t idx0 = (int32_t)blockIdx.x, idx1 = n, step = (int32_t)G;
+    if (G >= 8) {
+        idx0 = (int32_t)((int64_t)n * xcd / 8) + (int32_t)(blockIdx.x >> 3);
+        idx1 = (int32_t)((int64_t)n * (xcd + 1) / 8);
+        step = (int32_t)((G >> 3) + (xcd < (G & 7u) ? 1u : 0u));
+    }
+    if (idx0 >= idx1) return;  // the whole workgroup
     // uniform grids (FP32): between two leaves of the table's level the kernel is read from the
     // table at the integer cell offset instead of being evaluated
     const bool tab = sizeof(T) == 4 && a.near_tab != nullptr;
@@ -856,7 +866,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void near_kernel(FmmArgs<T> a, dou
         }
     }
     bool staged = !tab;
-    for (int32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
+    for (int32_t idx = idx0; idx < idx1; idx += step) {
         const int32_t b = a.L.near_leaves[idx];
         const uint32_t u0 = a.L.u_rng[b].x, u1 = a.L.u_rng[b].y;
         const int32_t p0 = a.bx.start[b], np = a.bx.end[b] - p0;
