@@ -51,7 +51,7 @@ typedef enum {
     PH_ENOMEM = 2,        /* device or host allocation failed, or the workspace cap was hit   */
     PH_EDEVICE = 3,       /* a HIP runtime call failed                                        */
     PH_ENUMERIC = 4,      /* a non-finite or negative source value was seen on the device     */
-    PH_EUNSUPPORTED = 5,  /* a valid request this build does not implement                    */
+    PH_EUNSUPPORTED = 5,  /* a valid request the library does not implement                   */
     PH_EFALLBACK = 6      /* informational: the learned selector fell back to the threshold rule;
                              the output is valid                                              */
 } ph_status;

@@ -353,8 +353,8 @@ void build_operators(const Gas &gas, int q, double root_size, int max_depth, dou
             std::copy(Kmat.begin(), Kmat.end(), out.m2l[l].begin() + (size_t)k * nl * nl);
         });
     }
-    // new levels into the cache, in the units of this build; the levels this build used are
-    // the most recent, and the least recently used go first when the cache is full
+    // new levels into the cache, in the units of this operator set; the levels this call used
+    // are the most recent, and the least recently used go first when the cache is full
     if (cache) {
         const uint64_t now = ++cache->clock;
         auto level_bytes = [](const CachedLevel &c) { return 8 * (c.uc2e.size() + c.m2l.size() + c.m2m.size()); };
