@@ -164,6 +164,32 @@ def test_fmm_fp32_c2_small_adaptive(gpu_lib):
     plan.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("fp64", 1e-6)])
+def test_fmm_threshold_c2_full_size(gpu_lib, precision, tol):
+    """The benchmark's workload at its full size (128^3 streamer grid, seed 1000, the rule
+    tau_s = 1e-4 of Sec. 3 eq. (18), targets |E| >= 3e6 V/m): the selected counts equal the
+    oracle's masks, and S at sampled targets (3000 uniform, and up to 2000 within 1 mm of the
+    head) matches the oracle over the same source set, at the bar of the precision."""
+    import torch
+    wl = gen.config2(seed=1000, n_axis=128)
+    _say(f"threshold rule, 128^3, {precision}")
+    plan = gpu_lib.Plan(wl.xyz, wl.gas, wl.thresholds, precision=precision, **plan_kwargs(wl))
+    I = wl.I.astype(np.float32) if precision == "fp32" else wl.I.astype(np.float64)
+    E32 = wl.E.astype(np.float32)
+    S, st = plan.evaluate(_tensor(I, torch.float32 if precision == "fp32" else torch.float64),
+                          _tensor(E32, torch.float32), stats=True)
+    S = S.double().cpu().numpy()
+    smask = source_mask(I.astype(np.float64), wl.thresholds["src_rel"])
+    tmask = target_mask(E32.astype(np.float64), wl.thresholds.get("e_abs", -1.0))
+    assert st["n_src"] == int(smask.sum()) and st["n_tgt"] == int(tmask.sum())
+    tg = gen.sample_targets(np.flatnonzero(tmask), wl.xyz, wl.head, k=3000, seed=11, head_cap=2000)
+    ref = photoionization(wl.xyz, I.astype(np.float64), wl.gas, h=wl.h, smask=smask, targets=tg)
+    err = rel_l2(S[tg], ref.S_t)
+    _say(f"  rel-L2 on {tg.size} targets: {err:.3e}")
+    assert err <= tol
+    plan.close()
+
+
 def test_fmm_fp64_all_sources_c2_small(gpu_lib):
     """Plain FP64 FMM (every point a source and a target) on a 32^3 streamer grid: <= 1e-6."""
     import torch
