@@ -341,6 +341,25 @@ def test_selection_rules():
     assert target_mask(None) is None
 
 
+def test_p10_threshold_error_rises_with_the_cut():
+    """Sec. 3 eq. (18) and Tables T6-T9, as a sanity pin (the paper's error measure, its G and its
+    reference data cannot be reproduced, so its percentages are not a parity target): the
+    kernel is positive and I >= 0, so a larger cut tau_s leaves out more positive terms at every
+    target.  The error of the thresholded sum against all sources is therefore zero with no cut
+    and rises monotonically with the cut, and the thresholded S never exceeds the full S."""
+    wl = gen.config2(seed=1000, n_axis=24)
+    tg = np.arange(0, wl.n, 7)
+    full = photoionization(wl.xyz, wl.I, wl.gas, h=wl.h, targets=tg).S_t
+    none = photoionization(wl.xyz, wl.I, wl.gas, h=wl.h, smask=source_mask(wl.I, 0.0), targets=tg).S_t
+    assert np.array_equal(none, full)
+    errs = []
+    for tau in (1e-6, 1e-5, 1e-4, 1e-3, 1e-2):
+        part = photoionization(wl.xyz, wl.I, wl.gas, h=wl.h, smask=source_mask(wl.I, tau), targets=tg).S_t
+        assert np.all(part <= full * (1 + 1e-12))
+        errs.append(rel_l2(part, full))
+    assert all(b >= a for a, b in zip(errs, errs[1:])) and errs[-1] > 10 * errs[0] > 0
+
+
 # ---------------------------------------------------------------- point clouds: w_j weights, no own-cell term
 
 def _cloud_brute(xyz, w, I, smask, tgt, gc):
