@@ -17,7 +17,8 @@ the largest time per call: two launches, timed by hipEvents on their streams
 inside the timed region), the GPU time per call with every call queued before the
 first one runs (behind a sleep kernel: no host gap; equal to the back-to-back time
 when the calls are GPU-bound), the FP64 oracle timed on the host cores on a bounded sample, the
-paper's threshold rule (tau_s = 1e-4) on the same field, and the plain FP64 FMM
+paper's threshold rule (tau_s = 1e-4) on the same field, the relative field rule of Sec. 5 for
+the targets (fewer targets than the literal rule), and the plain FP64 FMM
 (all points sources and targets, no adaptivity) on the same grid for the
 speed-up ratio.
 """
@@ -193,6 +194,18 @@ def main():
                  "gpu_ms_per_call_queued": host_t["queued_gpu_ms_per_call"], "phases_ms": phases_t}
     log(f"threshold fp32: {threshold}")
 
+    # ---------------- the paper's relative field rule of Sec. 5 for the targets (|E| >= E_app +
+    # eps (|E|_max - E_app), the background field E_app = 5e6 V/m, eps = 0.5 %), the source rule
+    # tau_s = 1e-4: fewer targets than the literal rule, which keeps every point of this field
+    thr_r = dict(wl.thresholds, e_abs=-1.0, e_applied=5e6, e_rel=0.005)
+    plan_r = binding.Plan(wl.xyz, wl.gas, thr_r, precision=args.precision, order_q=args.order_q, **common)
+    _, st_r = plan_r.evaluate(I, E, stats=True)
+    S_r, ms_r, phases_r = time_steps(plan_r, I, E, args.steps, args.warmup, torch)
+    plan_r.close()
+    relative = {"targets_per_s": st_r["n_tgt"] / (ms_r * 1e-3), "ms_per_step": ms_r, "n_src": st_r["n_src"],
+                "n_tgt": st_r["n_tgt"], "e_applied": 5e6, "e_rel": 0.005, "phases_ms": phases_r}
+    log(f"relative field rule fp32: {relative}")
+
     # ---------------- parity on sampled targets: same source set, and all sources (method error)
     from oracle import photoionization, rel_l2
     S_host = S.double().cpu().numpy()
@@ -211,6 +224,15 @@ def main():
     method_err = rel_l2(S_host[msample], r_all.S_t)
     method_err_t = rel_l2(St_host[msample], r_all.S_t)
     threshold["method_rel_l2_sampled"] = method_err_t
+    # the relative rule's targets against the oracle over the same (rule) sources
+    from oracle import source_mask as o_source_mask, target_mask as o_target_mask
+    rt = o_target_mask(E32.astype(np.float64), -1.0, 5e6, 0.005)
+    rsample = gen.sample_targets(np.flatnonzero(rt), wl.xyz, wl.head, k=2000, seed=5, head_cap=1000)
+    r_r = photoionization(wl.xyz, I32.astype(np.float64), wl.gas, h=wl.h,
+                          smask=o_source_mask(I32.astype(np.float64), wl.thresholds["src_rel"]), targets=rsample)
+    relative["rel_l2_sampled"] = rel_l2(S_r.double().cpu().numpy()[rsample], r_r.S_t)
+    relative["n_tgt_oracle_mask"] = int(rt.sum())
+    log(f"relative rule parity (sampled {rsample.size} targets): rel-L2 = {relative['rel_l2_sampled']:.3e}")
     log(f"method error vs all sources (sampled {msample.size}): learned {method_err:.3e}, threshold {method_err_t:.3e}")
     cpu = None
     if not args.skip_cpu:
@@ -289,6 +311,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "threshold_fp32": threshold,
+        "relative_field_rule_fp32": relative,
         "same_sets_fp32": same_sets,
         "plain_fp64_fmm": plain,
     }
