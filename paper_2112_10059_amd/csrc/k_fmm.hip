@@ -557,14 +557,54 @@ __device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, c
     }
 }
 
-// Far field of the target leaves whose level has a grid operator (uniform grids).  Each
-// workgroup takes up to kFarLeaves leaves of one level (the list's per-level segments), stages
-// that level's operator G_l (n_lam x m^3) in LDS once, and gives one wave per leaf:
+// Far field of the target leaves whose level has a grid operator (uniform grids).  A workgroup
+// takes up to kFarLeaves leaves of one level (the list's per-level segments), stages that
+// level's operator G_l (n_lam x m^3) in LDS once, and gives one wave per leaf:
 // far(t) = sum_li G_l[li][cell(t)] u[li], with the leaf's u in registers (lane li of slot k
 // holds u[64 k + li]) broadcast lane by lane, plus the W list, the near field of leaves with a
-// U list (computed beforehand) and the own-cell term, which gives the output.
+// U list (computed beforehand) and the own-cell term, which gives the output.  Leaves of more
+// than 64 points (m^3 > 64: coarse leaves, where a target rule leaves few targets in a box) are
+// shared out instead: a workgroup takes one leaf and a group of four of its 64-point chunks, a
+// chunk per wave, so that a few coarse leaves do not hold the whole launch one wave each.
 constexpr int kFarLeaves = 4;      // leaves per workgroup: one per wave, all in flight at once
 constexpr int kGridStage = 8192;   // operator entries staged in LDS (larger operators stay in L2)
+
+// 64-point chunks of a leaf of a level with m cells per axis, and groups of four of them
+__host__ __device__ __forceinline__ int far_chunks(int m) { return m > 0 ? (m * m * m + 63) / 64 : 1; }
+__host__ __device__ __forceinline__ int far_groups(int m) { return (far_chunks(m) + 3) / 4; }
+
+// This workgroup's level and its slice of that level's far_a segment for the wave kernel: up to
+// kFarLeaves leaves from the first (group -1), or, on levels whose leaves span several chunks,
+// the leaf first and its chunk group; false if the workgroup has no slice.
+template <class T>
+__device__ __forceinline__ bool far_slice_w(const FmmArgs<T> &a, uint32_t mask, int32_t slice, int &level,
+                                            int32_t &first, int &group)
+{
+    int32_t cnt[kMaxDepth + 2];
+#pragma unroll
+    for (int l = 0; l < kMaxDepth + 2; ++l) cnt[l] = a.sc->n_far_a_lvl[l];  // loads issued together
+    int32_t acc = 0;
+#pragma unroll
+    for (int l = 0; l < kMaxDepth + 2; ++l) {
+        if (l > a.lt.depth || !((mask >> l) & 1u)) continue;
+        const int gm = l >= 2 ? a.grid_m[l] : 0;
+        const int gr = far_chunks(gm) > 1 ? far_groups(gm) : 0;
+        const int32_t nb = gr > 0 ? cnt[l] * gr : (cnt[l] + kFarLeaves - 1) / kFarLeaves;
+        if (slice < acc + nb) {
+            level = l;
+            if (gr > 0) {
+                first = (slice - acc) / gr;
+                group = (slice - acc) % gr;
+            } else {
+                first = (slice - acc) * kFarLeaves;
+                group = -1;
+            }
+            return true;
+        }
+        acc += nb;
+    }
+    return false;
+}
 
 template <class T, int NK, bool LDSG>
 __device__ __forceinline__ T grid_far(const T *__restrict__ G, int R, int nl, int r, const T (&uv)[NK])
@@ -588,11 +628,13 @@ __device__ void far_grid_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const
     // slices of the per-level leaf lists, grid-stride (a small grid costs little when the lists
     // are empty)
     for (int32_t slice = bid;; slice += nblk) {
-        int level;
+        int level, group;
         int32_t first;
-        if (!far_slice(a.sc, a.lt.depth, level_mask, kFarLeaves, slice, level, first)) return;  // the whole workgroup
+        if (!far_slice_w(a, level_mask, slice, level, first, group)) return;  // the whole workgroup
         if (slice != bid) __syncthreads();  // the previous slice is done with Gs
-        const int32_t cnt = min(kFarLeaves, a.sc->n_far_a_lvl[level] - first);
+        // group < 0: up to kFarLeaves leaves, a wave each, every chunk; else the leaf first, the
+        // chunk 4 group + w of it for wave w
+        const int32_t cnt = group < 0 ? min(kFarLeaves, a.sc->n_far_a_lvl[level] - first) : 1;
         const int nl = a.n_lam;
         const int gm = level >= 2 ? level_pick(a.grid_m, level) : 0;
         const int R = gm * gm * gm;
@@ -628,7 +670,7 @@ __device__ void far_grid_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const
             __syncthreads();
         }
         const int scale_exp = a.sc->scale_exp;
-        for (int32_t q = w; q < cnt; q += 4) {
+        for (int32_t q = group < 0 ? w : 0; q < cnt; q += 4) {
             const int32_t b = a.L.far_a[level_pick(a.lt.base, level) + first + q].x;
             T uv[NK];
 #pragma unroll
@@ -638,7 +680,7 @@ __device__ void far_grid_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const
             const bool near = a.L.u_rng[b].y > a.L.u_rng[b].x;
             const bool has_w = a.L.w_rng[b].y > a.L.w_rng[b].x;
             const double bnd = (has_w && a.r_s > 0.0) ? a.rs_bound[b] : 0.0;
-            if (a.work && lane == 0) {
+            if (a.work && lane == 0 && (group < 0 || (group == 0 && w == 0))) {  // once per leaf
                 unsigned long long near_src = 0;
                 for (uint32_t e = a.L.u_rng[b].x; e < a.L.u_rng[b].y; ++e) near_src += a.bx.s_cnt[a.L.u[e]];
                 atomicAdd(&a.work[0], near_src * tn);
@@ -646,8 +688,11 @@ __device__ void far_grid_body(const FmmArgs<T> &a, TO *__restrict__ S_out, const
                 if (gm > 0) atomicAdd(&a.work[8], (unsigned long long)tn * nl);
                 if (has_w) atomicAdd(&a.work[2], (unsigned long long)(a.L.w_rng[b].y - a.L.w_rng[b].x) * nl * tn);
             }
-            // the leaf's points in sorted order, the targets among them flagged
-            for (int tb = 0; tb < np; tb += 64) {
+            // the leaf's points in sorted order, the targets among them flagged: every chunk, or
+            // chunk 4 group + w and those a whole round of the leaf's groups later (none when a
+            // leaf holds at most m^3 points)
+            const int tb0 = group < 0 ? 0 : 64 * (4 * group + w), tstep = group < 0 ? 64 : 256 * far_groups(gm);
+            for (int tb = tb0; tb < np; tb += tstep) {
                 const int32_t k = p0 + tb + lane;
                 const uint32_t sb = tb + lane < np ? a.sel[k] : 0u;
                 const bool act = (sb & 2u) != 0;
@@ -1072,7 +1117,11 @@ void fmm_leaf_t(Plan &p, void *S_out, hipStream_t s, hipStream_t s_aux)
         int64_t gm_blocks = 0, gw_blocks = 0;
         for (int l = 0; l <= p.max_depth; ++l) {
             if ((mfma_levels >> l) & 1u) gm_blocks += (p.level_cap[l] + kFarMLeaves - 1) / kFarMLeaves;
-            if ((wave_levels >> l) & 1u) gw_blocks += (p.level_cap[l] + kFarLeaves - 1) / kFarLeaves;
+            if ((wave_levels >> l) & 1u) {
+                const int gm = l >= 2 ? p.grid_m[l] : 0;
+                gw_blocks += far_chunks(gm) > 1 ? p.level_cap[l] * far_groups(gm)
+                                                : (p.level_cap[l] + kFarLeaves - 1) / kFarLeaves;
+            }
         }
         if (!std::is_same<T, float>::value) gm_blocks = 0;
         // LDS for the largest wave-kernel level operator that fits the staging cap
