@@ -86,18 +86,21 @@ __device__ void stage_weights(const float *__restrict__ params, MlpLds &L)
     if (threadIdx.x == 0) L.b3 = q<BF16>(params[OFF_B3]);
 }
 
-// The same staging with every load of a thread in flight at once (KW blockDim >= NP):
-// parameter t + k blockDim goes to thread t, then to its LDS place with the rounding of
-// stage_weights (the LDS contents are identical)
-template <bool BF16, int KW>
-__device__ __forceinline__ void stage_weights_at_once(const float *__restrict__ params, MlpLds &L)
+// The same staging with every load of a thread in flight at once (KW blockDim >= NP), in two
+// halves so that a kernel can issue the loads early and place the values later: parameter
+// t + k blockDim goes to thread t (indices past the end read the last parameter: no per-lane
+// branch, which would make each load wait on its own), then to its LDS place with the
+// rounding of stage_weights (the LDS contents are identical)
+template <int KW>
+__device__ __forceinline__ void load_weights(const float *__restrict__ params, float (&v)[KW])
 {
-    float v[KW];
 #pragma unroll
-    for (int k = 0; k < KW; ++k) {
-        const int idx = (int)threadIdx.x + k * (int)blockDim.x;
-        v[k] = idx < NP ? params[idx] : 0.0f;
-    }
+    for (int k = 0; k < KW; ++k) v[k] = params[min((int)threadIdx.x + k * (int)blockDim.x, NP - 1)];
+}
+
+template <bool BF16, int KW>
+__device__ __forceinline__ void store_weights(const float (&v)[KW], MlpLds &L)
+{
     float *w1 = reinterpret_cast<float *>(L.w1), *w2 = reinterpret_cast<float *>(L.w2);
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
@@ -119,6 +122,14 @@ __device__ __forceinline__ void stage_weights_at_once(const float *__restrict__ 
             L.b3 = x;
         }
     }
+}
+
+template <bool BF16, int KW>
+__device__ __forceinline__ void stage_weights_at_once(const float *__restrict__ params, MlpLds &L)
+{
+    float v[KW];
+    load_weights<KW>(params, v);
+    store_weights<BF16, KW>(v, L);
 }
 
 // value of lane j (uniform j) in every lane

@@ -387,23 +387,23 @@ __global__ __launch_bounds__(64 * kDecideWaves) void learned_decide_kernel(
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int32_t nrows = sc->n_rows;
     if ((int32_t)blockIdx.x * kDecideWaves >= nrows) return;  // the whole workgroup: no row for it
-    // the wave's first row: its record, geometry and the values of its first 64 points, loaded
-    // before the weights so that both are in flight together
+    // the wave's first row: its record, then its geometry and the permutation of its first 64
+    // points, then their values, with the network's weights in flight behind the record (a
+    // wave past the rows, or a lane past its leaf, reads the last row or point: every load is
+    // unconditional, so that none waits on its own, and the values go unused)
     int32_t row = (int32_t)blockIdx.x * kDecideWaves + wv;
-    int4 lp = make_int4(0, 0, 0, 0), g = make_int4(0, 0, 0, 0);
-    double pv = 0.0, pe = 0.0;
-    if (row < nrows) {
-        lp = la.rows[row];
-        g = la.pinfo2[lp.z];
-        const int32_t k = lp.x + lane;
-        if (k < lp.y) {
-            const int32_t o = perm[k];
-            pv = (double)I[o];
-            pe = E ? (double)E[o] : 0.0;
-        }
-    }
+    int4 lp = la.rows[min(row, nrows - 1)];
     constexpr int kW = (PH_MLP_NPARAM + 64 * kDecideWaves - 1) / (64 * kDecideWaves);
-    mlp::stage_weights_at_once<true, kW>(la.params, net);
+    float wts[kW];
+    mlp::load_weights<kW>(la.params, wts);
+    int4 g = la.pinfo2[lp.z];
+    double pv, pe = 0.0;
+    {
+        const int32_t o = perm[min(lp.x + lane, lp.y - 1)];
+        pv = (double)I[o];
+        if (E) pe = (double)E[o];
+    }
+    mlp::store_weights<true, kW>(wts, net);
     mlp::FeatureRefs r;
     r.imax = sc->imax;
     r.emax = sc->emax;
