@@ -391,19 +391,8 @@ __global__ __launch_bounds__(64 * kDecideWaves) void learned_decide_kernel(
     // points, then their values, with the network's weights in flight behind the record (a
     // wave past the rows, or a lane past its leaf, reads the last row or point: every load is
     // unconditional, so that none waits on its own, and the values go unused)
-    int32_t row = (int32_t)blockIdx.x * kDecideWaves + wv;
-    int4 lp = la.rows[min(row, nrows - 1)];
-    constexpr int kW = (PH_MLP_NPARAM + 64 * kDecideWaves - 1) / (64 * kDecideWaves);
-    float wts[kW];
-    mlp::load_weights<kW>(la.params, wts);
-    int4 g = la.pinfo2[lp.z];
-    double pv, pe = 0.0;
-    {
-        const int32_t o = perm[min(lp.x + lane, lp.y - 1)];
-        pv = (double)I[o];
-        if (E) pe = (double)E[o];
-    }
-    mlp::store_weights<true, kW>(wts, net);
+    // the call's maxima and their positions first: the kernel also writes the scalars, so these
+    // are vector loads, and issued here they share the first round trip
     mlp::FeatureRefs r;
     r.imax = sc->imax;
     r.emax = sc->emax;
@@ -417,6 +406,19 @@ __global__ __launch_bounds__(64 * kDecideWaves) void learned_decide_kernel(
         r.xi[d] = sc->imax_xyz[d];
         r.xe[d] = sc->emax_xyz[d];
     }
+    int32_t row = (int32_t)blockIdx.x * kDecideWaves + wv;
+    int4 lp = la.rows[min(row, nrows - 1)];
+    constexpr int kW = (PH_MLP_NPARAM + 64 * kDecideWaves - 1) / (64 * kDecideWaves);
+    float wts[kW];
+    mlp::load_weights<kW>(la.params, wts);
+    int4 g = la.pinfo2[lp.z];
+    double pv, pe = 0.0;
+    {
+        const int32_t o = perm[min(lp.x + lane, lp.y - 1)];
+        pv = (double)I[o];
+        if (E) pe = (double)E[o];
+    }
+    mlp::store_weights<true, kW>(wts, net);
     __syncthreads();
     bool first = true;
     for (; row < nrows; row += (int32_t)gridDim.x * kDecideWaves) {
