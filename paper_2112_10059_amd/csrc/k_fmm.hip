@@ -446,9 +446,10 @@ __device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, c
     const int32_t *__restrict__ pcell = a.pcell;
     const int32_t *__restrict__ perm = a.perm;
     const uint8_t *__restrict__ sel = a.sel;
+    // per point only what the product's registers leave room for (the sorted position is
+    // recomputed from the leaf, the flags ride in the top bits of the cell, the near-field sum
+    // is read after the product): held across it, more would spill to scratch memory
     int32_t q[kU], k[kU], cell[kU], out[kU];
-    uint32_t sb[kU];
-    double tnear[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const int32_t f = u * 256 + t;
@@ -476,10 +477,9 @@ __device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, c
 #pragma unroll
     for (int u = 0; u < kU; ++u)
         if (q[u] >= 0) {
-            sb[u] = sel[k[u]];
-            cell[u] = gm > 0 ? pcell[k[u]] : 0;
+            // cells pack three 10-bit coordinates: the two flag bits go above them
+            cell[u] = (gm > 0 ? pcell[k[u]] : 0) | ((int32_t)sel[k[u]] << 30);
             out[u] = perm[k[u]];
-            tnear[u] = lnear[q[u]] ? t_near[k[u]] : 0.0;
         }
 #pragma unroll
     for (int r = 0; r < kUR; ++r) Us[(t + 256 * r) >> 6][(t + 256 * r) & 63] = uv[r];
@@ -494,6 +494,7 @@ __device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, c
     __syncthreads();
     const int scale_exp = a.sc->scale_exp;
     auto finish = [&](int qq, int32_t cl, int32_t ot, int32_t kk, uint32_t sbit, double tnr) {
+        cl &= 0x3fffffff;
         if (!(sbit & 2u)) return;  // not a target (its output was cleared at selection)
         const int32_t b = lbox[qq];
         float far = 0.0f;
@@ -524,9 +525,16 @@ __device__ void far_mfma_body(const FmmArgs<float> &a, TO *__restrict__ S_out, c
         const double tot = lw[qq] && !skip_w ? (double)far + tnr + own_term(a, sbit, ot, scale_exp) : rest;
         S_out[ot] = (TO)(a.P * ldexp(tot, scale_exp));
     };
+    double tnear[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int32_t kk = q[u] >= 0 ? lt0[q[u]] + (u * 256 + t - loff[q[u]]) : 0;
+        tnear[u] = (q[u] >= 0 && lnear[q[u]]) ? t_near[kk] : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-        if (q[u] >= 0) finish(q[u], cell[u], out[u], k[u], sb[u], tnear[u]);
+        if (q[u] >= 0)
+            finish(q[u], cell[u], out[u], lt0[q[u]] + (u * 256 + t - loff[q[u]]), (uint32_t)cell[u] >> 30, tnear[u]);
     // points beyond the first kU x 256 (leaves of levels without an operator may hold more)
     for (int32_t f = kU * 256 + t; f < total; f += 256) {
         int lo = 0, hi = cnt - 1;
